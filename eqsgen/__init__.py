@@ -1,0 +1,40 @@
+"""Seeded synthetic inputs for the EQS explicit-RKC hot path.
+
+This package builds input data only: tetrahedral meshes of the unit cube,
+material tables and per-tet material ids, Dirichlet node sets with their drive
+functions, and seeded random states. It holds none of the method's arithmetic
+(no element matrices, no solves, no time stepping), so both the CPU oracle and
+the HIP library can consume its output without sharing any method code.
+
+The workloads mirror the paper's field-grading setting (Sec. V: a microvaristor
+coating with field-dependent conductivity inside a polymer insulator) on cube
+meshes, because the paper's insulator model is not available.
+"""
+
+from .mesh import kuhn_cube_mesh, permute_nodes, shuffle_tets
+from .cases import (
+    Case,
+    make_case,
+    layered_case,
+    case_c0,
+    case_c1,
+    case_c2,
+    case_batch,
+    random_state,
+    CASE_NAMES,
+)
+
+__all__ = [
+    "Case",
+    "kuhn_cube_mesh",
+    "permute_nodes",
+    "shuffle_tets",
+    "make_case",
+    "layered_case",
+    "case_c0",
+    "case_c1",
+    "case_c2",
+    "case_batch",
+    "random_state",
+    "CASE_NAMES",
+]
