@@ -1,0 +1,214 @@
+#!/usr/bin/env python
+"""RKC stages/s of the explicit EQS hot path on one MI355X.
+
+Workload (default "c2"): the unit cube meshed with 128^3 sub-cubes split into
+6 P1 tets each (2,146,689 nodes, 12,582,912 tets, 2,113,407 free DOF),
+grounded at z = 0, driven by sin(2 pi 50 t) at z = 1, with seeded spherical
+microvaristor inclusions (5 % of the volume, kappa = 1e-10 (1 + (|E|/0.5)^alpha),
+alpha ~ U[8, 14], eps_r ~ U[8, 15]) in an eps_r = 4, kappa = 1e-12 host.
+Each RKC(16) step runs 16 stages; a stage is one fused element pass
+(K(x)x + Dirichlet RHS), one AMG-preconditioned CG solve of M to rel-res 1e-8
+(FP64 CG, FP32 AMG hierarchy and V-cycle), and one RKC combination.
+
+Prints ONE JSON line (rank 0). `value` = stages/s of the timed steps with all
+inputs resident in HBM. The plain FP64 path (FP64 hierarchy) is timed over a
+shorter window beside it, and the FP64 CPU oracle is timed on one stage of the
+same workload (cpu_baseline).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+METRIC = "RKC stages/s at 2.1M DOF (rel-res 1e-8), HBM GB/s; mixed+learned vs FP64"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def element_bytes(info):
+    # per tet: 4 int32 node ids + uint16 material id; per node: xyz (24 B),
+    # potential read (8 B), output write (8 B) -- each array touched once
+    return info["n_tets"] * (16 + 2) + info["n_nodes"] * (24 + 8 + 8)
+
+
+def spmv_bytes(info, nnz):
+    # CG product q = M z + beta q, p = z + beta p on the free DOF:
+    # values (8 B) + column ids (4 B) per nonzero, slice offsets, z read,
+    # p and q read + written
+    n = info["n_free"]
+    return 12 * nnz + 4 * (n // 64 + 1) + 8 * n + 32 * n
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def run_gpu(case, precision, steps, warmup, rtol, profile_classes=()):
+    import torch
+
+    from paper_1612_09447_amd import Context
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.perf_counter()
+    ctx = Context(0, stream)
+    info = ctx.setup_case(case, precision=precision)
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] setup {precision}: {setup_s:.1f}s levels={info['level_rows']} nnz_M={info['nnz_M']}")
+    x = torch.zeros(case.n_nodes, dtype=torch.float64, device=dev)
+    tau, s = case.tau, case.s
+    n = 0
+    for _ in range(warmup):
+        ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
+        n += 1
+    if profile_classes:
+        ctx.profile_enable(profile_classes)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    iters = []
+    for k in range(steps):
+        st = ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
+        iters.append(st["total_iters"] / st["stages"])
+        n += 1
+        if (k + 1) % max(1, steps // 5) == 0:
+            log(f"[bench] {precision} step {k + 1}/{steps} mean CG it/stage {sum(iters) / len(iters):.2f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    prof = {c: ctx.profile_read(c) for c in profile_classes}
+    ctx.profile_enable(())
+    xn = x.cpu().numpy()
+    ctx.close()
+    return dict(elapsed=elapsed, stages=steps * s, iters=iters, info=info, prof=prof, setup_s=setup_s, x=xn)
+
+
+def cpu_baseline(case):
+    """The oracle, as it stands, on one stage of the workload (single thread)."""
+    import numpy as np
+
+    from oracle.eqs import EqsOracle
+
+    t0 = time.perf_counter()
+    orc = EqsOracle(case, solve_rtol=case.rtol)
+    log(f"[bench] oracle setup {time.perf_counter() - t0:.1f}s")
+    t1 = time.perf_counter()
+    orc.F(0.0, np.zeros(orc.n_free))  # one stage: K(x)x over all tets + one SGS-PCG solve of M
+    dt = time.perf_counter() - t1
+    log(f"[bench] oracle stage {dt:.1f}s ({orc.last_iters} SGS-PCG iterations)")
+    return dict(value=1.0 / dt, unit="stages/s", cores=1, kind="oracle",
+                sample=f"stage 0 of step 0 (t=0, phi=0): one element pass over {case.n_tets} tets + one "
+                       f"SGS-PCG solve of M to rel-res {case.rtol:g} from a zero start "
+                       f"({orc.last_iters} iterations), {dt:.1f} s on 1 of {os.cpu_count()} cores "
+                       f"({cpu_model()})")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40, help="timed RKC steps")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
+    ap.add_argument("--n", type=int, default=None, help="override the mesh resolution (testing)")
+    ap.add_argument("--plain-steps", type=int, default=10, help="timed steps of the plain FP64 path (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not built)"}))
+        sys.exit(2)
+
+    import eqsgen
+
+    t0 = time.perf_counter()
+    case = eqsgen.make_case(args.workload, n=args.n)
+    log(f"[bench] workload {args.workload}: n={case.n} nodes={case.n_nodes} tets={case.n_tets} "
+        f"({time.perf_counter() - t0:.1f}s to generate)")
+    prec = "fp32" if case.precision == "fp32" else "fp64"
+    from paper_1612_09447_amd import EQS_PREC_FP32, EQS_PREC_FP64
+
+    main_prec = EQS_PREC_FP32 if prec == "fp32" else EQS_PREC_FP64
+    classes = ("element", "spmv_M", "presmooth0", "postsmooth0", "vcycle", "cg_update", "rkc_combine")
+    r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, profile_classes=classes)
+    stages_per_s = r["stages"] / r["elapsed"]
+    info = r["info"]
+    prof = r["prof"]
+
+    # roofline of the dominant single kernel class (by summed time)
+    per_class_bytes = {
+        "element": element_bytes(info),
+        "spmv_M": spmv_bytes(info, info["nnz_M"]),
+    }
+    dominant = max(per_class_bytes, key=lambda k: prof[k]["total_ms"])
+    avg_s = prof[dominant]["avg_ms"] * 1e-3
+    achieved = per_class_bytes[dominant] / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": {"element": "k_kx<true>", "spmv_M": "k_pcg_spmv"}[dominant],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": per_class_bytes[dominant], "avg_launch_us": round(avg_s * 1e6, 2)}
+    breakdown = {k: {"launches": v["launches"], "avg_us": round(v["avg_ms"] * 1e3, 2),
+                     "share_of_timed": round(v["total_ms"] * 1e-3 / r["elapsed"], 4)} for k, v in prof.items()}
+
+    plain = None
+    if args.plain_steps > 0 and main_prec != EQS_PREC_FP64:
+        p = run_gpu(case, EQS_PREC_FP64, args.plain_steps, args.warmup, case.rtol)
+        plain = {"stages_per_s": round(p["stages"] / p["elapsed"], 2),
+                 "mean_cg_iters_per_stage": round(sum(p["iters"]) / len(p["iters"]), 2),
+                 "steps": args.plain_steps}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(case)
+        cpu["value"] = round(cpu["value"], 6)
+
+    out = {
+        "metric": METRIC,
+        "value": round(stages_per_s, 2),
+        "unit": "stages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r["elapsed"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: unit cube, {case.n}^3 sub-cubes x 6 P1 tets ({case.n_tets} tets, "
+                        f"{info['n_free']} free DOF), seeded varistor inclusions, RKC s={case.s}, "
+                        f"tau={case.tau:g}, CG rel-res {case.rtol:g}",
+            "precision": "FP64 CG + K(x)x, FP32 AMG V-cycle" if main_prec == EQS_PREC_FP32 else "FP64",
+            "start_vector": "previous stage solution",
+            "mean_cg_iters_per_stage": round(sum(r["iters"]) / len(r["iters"]), 2),
+            "amg_levels": info["level_rows"],
+            "nnz_M": info["nnz_M"],
+            "setup_s": round(r["setup_s"], 1),
+        },
+        "roofline": roofline,
+        "kernel_breakdown": breakdown,
+        "fp64_plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

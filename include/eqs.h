@@ -1,0 +1,232 @@
+/*
+ * eqs.h - C ABI of the MI355X (gfx950) explicit-RKC library for nonlinear
+ * electro-quasistatic (EQS) fields.
+ *
+ * Method: C. Richter, S. Schoeps, M. Clemens, "GPU Accelerated Explicit Time
+ * Integration Methods for Electro-Quasistatic Fields" (arXiv 1612.09447).
+ *   Sec. II, eq. (1): div(kappa(|grad phi|) grad phi) + div(eps grad dphi/dt) = 0.
+ *   Sec. II, eq. (2): after P1 finite elements, M dx/dt + K(x)x = b, with M the
+ *     constant permittivity Laplacian, K(x) the field-dependent conductivity
+ *     matrix and b the inhomogeneous Dirichlet contribution.
+ *   Sec. II: explicit Runge-Kutta-Chebyshev (RKC, its ref. [9]) time stepping,
+ *     where every stage needs one solve with the constant M (a multiple
+ *     right-hand-side problem whose preconditioner is built once).
+ *   Sec. III: K(x)x is formed element by element and added straight into the
+ *     right-hand side; the matrix K(x) is never assembled.
+ *   Sec. II/V: M is solved by conjugate gradients with an algebraic multigrid
+ *     preconditioner.
+ *
+ * Conventions for every call:
+ *   - Return value: EQS_OK (0) or a negative EQS_ERR_* code; the thread-local
+ *     message of the last failure is eqs_last_error(). No C++ exception ever
+ *     crosses this interface.
+ *   - Host arrays passed to eqs_set_* are copied; the caller keeps ownership
+ *     and may free them after the call returns.
+ *   - Device pointers (suffix _dev) must be device memory on the context's
+ *     device, 8-byte aligned, and are only borrowed for the duration of the
+ *     call. All device work is enqueued on the context's stream; calls return
+ *     after that work has completed (the library synchronises its stream), so
+ *     results are ready for any stream afterwards.
+ *   - Node ids are 0-based int32. "Free" nodes are the nodes not listed in
+ *     eqs_set_dirichlet; vectors over free nodes (length n_free) list them in
+ *     increasing node id. Vectors over all nodes (length n_nodes) are in node
+ *     id order.
+ *   - Units are SI: metres, volts, seconds, S/m; eps = eps0 * eps_r with
+ *     eps0 = 8.8541878128e-12 F/m.
+ *   - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef EQS_H
+#define EQS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define EQS_OK 0
+#define EQS_ERR_INVALID_ARG (-1)   /* bad pointer, size, id, or degenerate tet */
+#define EQS_ERR_STATE (-2)         /* call out of order (see eqs_build_preconditioner) */
+#define EQS_ERR_HIP (-3)           /* HIP runtime error */
+#define EQS_ERR_NOT_CONVERGED (-4) /* maxit reached; results and stats still written */
+#define EQS_ERR_BREAKDOWN (-5)     /* CG breakdown: p.Mp <= 0 or non-finite scalar */
+#define EQS_ERR_NONFINITE (-6)     /* NaN/Inf in an input */
+#define EQS_ERR_ALLOC (-7)         /* device or host allocation failed */
+
+#define EQS_MAX_DRIVES 8 /* distinct drive functions per context */
+
+enum { EQS_PREC_FP64 = 0, EQS_PREC_FP32 = 1 };
+
+typedef struct eqs_ctx eqs_ctx;
+
+/* Material law (Sec. I and eq. (1)): permittivity eps0*eps_r; conductivity
+ * kappa0 * (1 + (|E|/e_s)^alpha) if nonlinear != 0 (a microvaristor-type
+ * power law switching near the field e_s), else the constant kappa0.
+ * Requires eps_r > 0, kappa0 >= 0, and for nonlinear materials e_s > 0,
+ * alpha >= 0. */
+typedef struct eqs_material {
+    double eps_r;
+    double kappa0;
+    double e_s;
+    double alpha;
+    int32_t nonlinear;
+    int32_t reserved; /* set to 0 */
+} eqs_material;
+
+/* Dirichlet drive g(t) = amp * sin(2 pi freq t + phase) (amp = 0: ground;
+ * freq = 0, phase = pi/2: constant amp). Its time derivative enters b of
+ * eq. (2). */
+typedef struct eqs_drive {
+    double amp;
+    double freq;
+    double phase;
+} eqs_drive;
+
+/* Smoothed-aggregation AMG parameters for the preconditioner of M (the
+ * paper's solver is AMG-preconditioned CG, Sec. I and Sec. V; the algebraic
+ * multigrid variant is this library's choice). Zero-initialised fields take
+ * the defaults in brackets. */
+typedef struct eqs_amg_params {
+    int32_t precision;  /* EQS_PREC_FP64 or EQS_PREC_FP32 storage and V-cycle [FP64] */
+    int32_t coarse_max; /* coarsen until at most this many unknowns, <= 4096 [512] */
+    int32_t max_levels; /* including the coarsest, 2..16 [12] */
+    int32_t flexible;   /* 1: Polak-Ribiere beta (needed with FP32), 0: standard [= precision] */
+    double theta;       /* strength threshold |a_ij| >= theta sqrt(a_ii a_jj) [0.08] */
+    double jacobi_weight; /* damped-Jacobi weight times 1/rho(D^-1 A) [4/3] */
+    double smooth_weight; /* prolongator-smoothing weight times 1/rho(D^-1 A) [4/3] */
+} eqs_amg_params;
+
+typedef struct eqs_solve_stats {
+    int32_t iters;  /* CG iterations */
+    int32_t status; /* EQS_OK, EQS_ERR_NOT_CONVERGED or EQS_ERR_BREAKDOWN */
+    double relres;  /* true |rhs - M y| / |rhs| at exit (0 if rhs = 0) */
+} eqs_solve_stats;
+
+typedef struct eqs_step_stats {
+    int32_t stages;        /* s */
+    int32_t total_iters;   /* CG iterations summed over the stages */
+    int32_t max_iters;     /* largest per-stage count */
+    int32_t min_iters;     /* smallest per-stage count */
+    int32_t not_converged; /* stages whose solve hit maxit */
+    int32_t reserved;
+    double max_relres;     /* largest per-stage true relative residual */
+} eqs_step_stats;
+
+typedef struct eqs_info {
+    int64_t n_nodes;
+    int64_t n_tets;
+    int64_t n_free;
+    int64_t nnz_M;        /* nonzeros of M restricted to the free nodes */
+    int32_t n_levels;     /* AMG levels including the coarsest (0 before build) */
+    int32_t precision;
+    int64_t level_rows[16];
+    int64_t level_nnz[16];
+    int64_t device_bytes; /* device memory held by the context */
+} eqs_info;
+
+/* Create a context on HIP device `device` whose work goes to `hip_stream`
+ * (a hipStream_t; NULL = the null stream). *out receives the context. */
+int eqs_create(eqs_ctx **out, int device, void *hip_stream);
+
+/* Release the context and all device memory it holds. NULL is accepted. */
+int eqs_destroy(eqs_ctx *ctx);
+
+/* Tetrahedral P1 mesh (the "FEM data" handed to the GPU, Sec. III).
+ * xyz: n_nodes x 3 doubles (x, y, z per node); tets: n_tets x 4 node ids.
+ * Every tet needs a nonzero volume (either orientation); a flat tet gives
+ * EQS_ERR_INVALID_ARG. Resets materials, Dirichlet data and the preconditioner. */
+int eqs_set_mesh(eqs_ctx *ctx, int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tets);
+
+/* Material table (n_mat entries) and the material id of every tet
+ * (tet_mat[n_tets], 0 <= id < n_mat <= 65535): the "nonlinear material
+ * parameters" of Sec. III. Invalidates the preconditioner. */
+int eqs_set_materials(eqs_ctx *ctx, int32_t n_mat, const eqs_material *mats, const int32_t *tet_mat);
+
+/* Dirichlet nodes and their drives (eq. (1) is well posed with Dirichlet
+ * data, Sec. II): node nodes[k] follows drives[drive_id[k]]. Nodes must be
+ * distinct; 1 <= n_drive <= EQS_MAX_DRIVES; at least one node must stay
+ * free. All other boundary parts are natural (zero normal current).
+ * Invalidates the preconditioner. */
+int eqs_set_dirichlet(eqs_ctx *ctx, int64_t n_d, const int32_t *nodes, const int32_t *drive_id,
+                      int32_t n_drive, const eqs_drive *drives);
+
+/* Assemble M on the free nodes (eq. (2)), build the AMG hierarchy once for
+ * all stages and steps (Sec. II: the constant M makes the solves a multiple
+ * right-hand-side problem), and upload mesh, materials and hierarchy to the
+ * device. Needs mesh, materials and Dirichlet data, else EQS_ERR_STATE.
+ * p may be NULL for the defaults. */
+int eqs_build_preconditioner(eqs_ctx *ctx, const eqs_amg_params *p);
+
+/* Sizes and hierarchy statistics. */
+int eqs_query(const eqs_ctx *ctx, eqs_info *info);
+
+/* y = K(x_bar) x_bar on all nodes (Sec. III, element-by-element product),
+ * where x_bar equals x_dev on free nodes and g(t) on Dirichlet nodes
+ * (the Dirichlet entries of x_dev are ignored). x_dev, y_dev: n_nodes
+ * doubles, may not alias. */
+int eqs_apply_K(eqs_ctx *ctx, double t, const double *x_dev, double *y_dev);
+
+/* Stage right-hand side r = b(t) - [K(x_bar) x_bar]_free with
+ * b(t) = -M_{free,D} g'(t) (eq. (2) with the Dirichlet nodes D eliminated)
+ * and x_bar = (y_free_dev, g(t)). Both vectors have n_free doubles. */
+int eqs_stage_rhs(eqs_ctx *ctx, double t, const double *y_free_dev, double *r_dev);
+
+/* y = M_free x (the constant matrix of eq. (2) on the free nodes). */
+int eqs_apply_M(eqs_ctx *ctx, const double *x_dev, double *y_dev);
+
+/* z = B r: one AMG V-cycle applied to r (the preconditioner built by
+ * eqs_build_preconditioner; linear and symmetric positive definite). */
+int eqs_apply_preconditioner(eqs_ctx *ctx, const double *r_dev, double *z_dev);
+
+/* Solve M_free y = rhs by AMG-preconditioned CG (Sec. II, Sec. V) until the
+ * true relative residual |rhs - M y| / |rhs| <= rtol. y_dev holds the start
+ * vector on entry (Sec. IV: a good start vector cuts iterations; an exact one
+ * needs none) and the solution on exit. Returns EQS_ERR_NOT_CONVERGED after
+ * maxit iterations (y and stats still written) or EQS_ERR_BREAKDOWN.
+ * st may be NULL. */
+int eqs_solve_M(eqs_ctx *ctx, const double *rhs_dev, double *y_dev, double rtol, int32_t maxit,
+                eqs_solve_stats *st);
+
+/* One RKC step (Sec. II, its ref. [9]: s stages, second order, damping 2/13)
+ * from time t to t + dt for M dx/dt + K(x)x = b. x_dev (n_nodes doubles) holds
+ * x(t) on entry (Dirichlet entries ignored) and x(t + dt) on exit, with the
+ * Dirichlet entries set to g(t + dt). Every stage j evaluates
+ * F_j = M^{-1}(b(t + c_j dt) - K(x_bar_j) x_bar_j) with one fused element pass
+ * and one preconditioned CG solve to rtol, started from the previous stage's
+ * F. Requires 2 <= s <= 256. Returns EQS_ERR_NOT_CONVERGED if any stage's
+ * solve hit maxit (the step is still completed); st may be NULL. */
+int eqs_rkc_step(eqs_ctx *ctx, double t, double dt, int32_t s, double *x_dev, double rtol, int32_t maxit,
+                 eqs_step_stats *st);
+
+/* ---- per-kernel timing ------------------------------------------------
+ * When enabled, the library records a pair of HIP events on the context's
+ * stream around every launch of the selected kernel classes; durations are
+ * summed at read time. Classes: */
+enum {
+    EQS_KCLASS_ELEMENT = 0,     /* fused element pass: K(x)x / stage right-hand side */
+    EQS_KCLASS_SPMV_M = 1,      /* CG product q = M z + beta q (FP64 SpMV on M) */
+    EQS_KCLASS_PRESMOOTH0 = 2,  /* finest-level Jacobi pre-smoothing + residual */
+    EQS_KCLASS_POSTSMOOTH0 = 3, /* finest-level Jacobi post-smoothing (+ r.z) */
+    EQS_KCLASS_VCYCLE = 4,      /* one whole V-cycle */
+    EQS_KCLASS_CG_UPDATE = 5,   /* x += alpha p, r -= alpha q (+ |r|^2) */
+    EQS_KCLASS_RKC_COMBINE = 6, /* RKC stage combination */
+    EQS_KCLASS_COUNT = 7
+};
+
+/* Enable timing of the classes whose bits are set in class_mask (bit k =
+ * class k); 0 disables. Resets all counters. */
+int eqs_profile_enable(eqs_ctx *ctx, uint32_t class_mask);
+
+/* Launch count and summed duration (milliseconds) of one class since the last
+ * eqs_profile_enable. Synchronises the context's stream. */
+int eqs_profile_read(eqs_ctx *ctx, int32_t kclass, int64_t *launches, double *total_ms);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *eqs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EQS_H */

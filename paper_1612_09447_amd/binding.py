@@ -1,0 +1,281 @@
+"""ctypes binding of the C ABI in ``include/eqs.h`` (argument marshalling only).
+
+Every numerical step runs in the HIP library ``libeqs.so``; this module only
+converts arguments. Device vectors are passed as torch CUDA (HIP) tensors of
+dtype float64 (their ``data_ptr()`` is handed to the library) or as raw
+integer device addresses. If the library is missing the import fails loudly:
+there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeqs.so")
+
+EQS_OK = 0
+EQS_ERR_INVALID_ARG = -1
+EQS_ERR_STATE = -2
+EQS_ERR_HIP = -3
+EQS_ERR_NOT_CONVERGED = -4
+EQS_ERR_BREAKDOWN = -5
+EQS_ERR_NONFINITE = -6
+EQS_ERR_ALLOC = -7
+EQS_MAX_DRIVES = 8
+EQS_PREC_FP64 = 0
+EQS_PREC_FP32 = 1
+
+ERROR_NAMES = {
+    EQS_ERR_INVALID_ARG: "EQS_ERR_INVALID_ARG",
+    EQS_ERR_STATE: "EQS_ERR_STATE",
+    EQS_ERR_HIP: "EQS_ERR_HIP",
+    EQS_ERR_NOT_CONVERGED: "EQS_ERR_NOT_CONVERGED",
+    EQS_ERR_BREAKDOWN: "EQS_ERR_BREAKDOWN",
+    EQS_ERR_NONFINITE: "EQS_ERR_NONFINITE",
+    EQS_ERR_ALLOC: "EQS_ERR_ALLOC",
+}
+
+
+class eqs_material(C.Structure):
+    _fields_ = [("eps_r", C.c_double), ("kappa0", C.c_double), ("e_s", C.c_double), ("alpha", C.c_double),
+                ("nonlinear", C.c_int32), ("reserved", C.c_int32)]
+
+
+class eqs_drive(C.Structure):
+    _fields_ = [("amp", C.c_double), ("freq", C.c_double), ("phase", C.c_double)]
+
+
+class eqs_amg_params(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
+                ("flexible", C.c_int32), ("theta", C.c_double), ("jacobi_weight", C.c_double),
+                ("smooth_weight", C.c_double)]
+
+
+class eqs_solve_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double)]
+
+
+class eqs_step_stats(C.Structure):
+    _fields_ = [("stages", C.c_int32), ("total_iters", C.c_int32), ("max_iters", C.c_int32),
+                ("min_iters", C.c_int32), ("not_converged", C.c_int32), ("reserved", C.c_int32),
+                ("max_relres", C.c_double)]
+
+
+class eqs_info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("n_free", C.c_int64), ("nnz_M", C.c_int64),
+                ("n_levels", C.c_int32), ("precision", C.c_int32), ("level_rows", C.c_int64 * 16),
+                ("level_nnz", C.c_int64 * 16), ("device_bytes", C.c_int64)]
+
+
+_P = C.c_void_p
+_SIGNATURES = {
+    "eqs_create": ([C.POINTER(_P), C.c_int, _P], C.c_int),
+    "eqs_destroy": ([_P], C.c_int),
+    "eqs_set_mesh": ([_P, C.c_int64, _P, C.c_int64, _P], C.c_int),
+    "eqs_set_materials": ([_P, C.c_int32, _P, _P], C.c_int),
+    "eqs_set_dirichlet": ([_P, C.c_int64, _P, _P, C.c_int32, _P], C.c_int),
+    "eqs_build_preconditioner": ([_P, _P], C.c_int),
+    "eqs_query": ([_P, _P], C.c_int),
+    "eqs_apply_K": ([_P, C.c_double, _P, _P], C.c_int),
+    "eqs_stage_rhs": ([_P, C.c_double, _P, _P], C.c_int),
+    "eqs_apply_M": ([_P, _P, _P], C.c_int),
+    "eqs_apply_preconditioner": ([_P, _P, _P], C.c_int),
+    "eqs_solve_M": ([_P, _P, _P, C.c_double, C.c_int32, _P], C.c_int),
+    "eqs_rkc_step": ([_P, C.c_double, C.c_double, C.c_int32, _P, C.c_double, C.c_int32, _P], C.c_int),
+    "eqs_profile_enable": ([_P, C.c_uint32], C.c_int),
+    "eqs_profile_read": ([_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
+    "eqs_last_error": ([], C.c_char_p),
+}
+
+KCLASS = {
+    "element": 0,
+    "spmv_M": 1,
+    "presmooth0": 2,
+    "postsmooth0": 3,
+    "vcycle": 4,
+    "cg_update": 5,
+    "rkc_combine": 6,
+}
+
+_lib = None
+
+
+def lib():
+    """Load ``libeqs.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library {LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'` (no CPU fallback exists)"
+            )
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+class EqsError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().eqs_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {ERROR_NAMES.get(code, code)}: {msg}")
+
+
+def _check(code, where, ok=(EQS_OK,)):
+    if code not in ok:
+        raise EqsError(code, where)
+    return code
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(_P)
+
+
+def _dev(t):
+    """Device address of a torch tensor (float64, contiguous) or an int address."""
+    if isinstance(t, int):
+        return _P(t)
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor on the GPU or an integer device address")
+    if t.device.type != "cuda":
+        raise ValueError("device vectors must live on the GPU")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("device vectors must be contiguous float64")
+    return _P(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return _P(stream)
+    return _P(stream.cuda_stream)
+
+
+class Context:
+    """One EQS instance on one device (wraps ``eqs_ctx``)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._h = _P()
+        _check(lib().eqs_create(C.byref(self._h), device, _stream_handle(stream)), "eqs_create")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().eqs_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- set-up ----------------------------------------------------------
+    def set_mesh(self, xyz, tets):
+        xyz, pxyz = _host(xyz, np.float64)
+        tets, ptets = _host(tets, np.int32)
+        _check(lib().eqs_set_mesh(self._h, xyz.shape[0], pxyz, tets.shape[0], ptets), "eqs_set_mesh")
+
+    def set_materials(self, eps_r, kappa0, e_s, alpha, nonlinear, tet_mat):
+        n = len(eps_r)
+        arr = (eqs_material * n)()
+        for m in range(n):
+            arr[m] = eqs_material(float(eps_r[m]), float(kappa0[m]), float(e_s[m]), float(alpha[m]),
+                                  int(nonlinear[m]), 0)
+        tm, ptm = _host(tet_mat, np.int32)
+        _check(lib().eqs_set_materials(self._h, n, C.cast(arr, _P), ptm), "eqs_set_materials")
+
+    def set_dirichlet(self, nodes, drive_id, amp, freq, phase):
+        nodes, pn = _host(nodes, np.int32)
+        did, pd = _host(drive_id, np.int32)
+        n_drive = len(amp)
+        arr = (eqs_drive * n_drive)()
+        for k in range(n_drive):
+            arr[k] = eqs_drive(float(amp[k]), float(freq[k]), float(phase[k]))
+        _check(lib().eqs_set_dirichlet(self._h, nodes.shape[0], pn, pd, n_drive, C.cast(arr, _P)),
+               "eqs_set_dirichlet")
+
+    def build_preconditioner(self, precision=EQS_PREC_FP64, **kw):
+        p = eqs_amg_params()
+        p.precision = precision
+        for k, v in kw.items():
+            setattr(p, k, v)
+        _check(lib().eqs_build_preconditioner(self._h, C.byref(p)), "eqs_build_preconditioner")
+
+    def setup_case(self, case, precision=None, **amg):
+        """Hand a ``eqsgen.Case`` to the library (mesh, materials, Dirichlet, AMG)."""
+        self.set_mesh(case.xyz, case.tets)
+        self.set_materials(case.eps_r, case.kappa0, case.e_s, case.alpha, case.nonlinear, case.tet_mat)
+        self.set_dirichlet(case.dir_nodes, case.dir_drive, case.amp, case.freq, case.phase)
+        if precision is None:
+            precision = EQS_PREC_FP32 if case.precision == "fp32" else EQS_PREC_FP64
+        self.build_preconditioner(precision, **amg)
+        return self.info()
+
+    def info(self) -> dict:
+        o = eqs_info()
+        _check(lib().eqs_query(self._h, C.byref(o)), "eqs_query")
+        L = o.n_levels
+        return dict(n_nodes=o.n_nodes, n_tets=o.n_tets, n_free=o.n_free, nnz_M=o.nnz_M, n_levels=L,
+                    precision=o.precision, level_rows=list(o.level_rows[:L]), level_nnz=list(o.level_nnz[:L]),
+                    device_bytes=o.device_bytes)
+
+    # ---- per-kernel timing -----------------------------------------------
+    def profile_enable(self, classes=()):
+        """Time every launch of the named kernel classes with HIP events (resets counters)."""
+        mask = 0
+        for k in classes:
+            mask |= 1 << KCLASS[k]
+        _check(lib().eqs_profile_enable(self._h, mask), "eqs_profile_enable")
+
+    def profile_read(self, kclass):
+        n = C.c_int64()
+        ms = C.c_double()
+        _check(lib().eqs_profile_read(self._h, KCLASS[kclass], C.byref(n), C.byref(ms)), "eqs_profile_read")
+        return dict(launches=n.value, total_ms=ms.value, avg_ms=ms.value / n.value if n.value else 0.0)
+
+    # ---- hot path --------------------------------------------------------
+    def apply_K(self, t, x, y):
+        _check(lib().eqs_apply_K(self._h, float(t), _dev(x), _dev(y)), "eqs_apply_K")
+
+    def stage_rhs(self, t, y_free, r):
+        _check(lib().eqs_stage_rhs(self._h, float(t), _dev(y_free), _dev(r)), "eqs_stage_rhs")
+
+    def apply_M(self, x, y):
+        _check(lib().eqs_apply_M(self._h, _dev(x), _dev(y)), "eqs_apply_M")
+
+    def apply_preconditioner(self, r, z):
+        _check(lib().eqs_apply_preconditioner(self._h, _dev(r), _dev(z)), "eqs_apply_preconditioner")
+
+    def solve_M(self, rhs, y, rtol, maxit=1000, allow_not_converged=False):
+        st = eqs_solve_stats()
+        ok = (EQS_OK, EQS_ERR_NOT_CONVERGED) if allow_not_converged else (EQS_OK,)
+        rc = lib().eqs_solve_M(self._h, _dev(rhs), _dev(y), float(rtol), int(maxit), C.byref(st))
+        _check(rc, "eqs_solve_M", ok)
+        return dict(iters=st.iters, status=st.status, relres=st.relres, rc=rc)
+
+    def rkc_step(self, t, dt, s, x, rtol, maxit=1000, allow_not_converged=False):
+        st = eqs_step_stats()
+        ok = (EQS_OK, EQS_ERR_NOT_CONVERGED) if allow_not_converged else (EQS_OK,)
+        rc = lib().eqs_rkc_step(self._h, float(t), float(dt), int(s), _dev(x), float(rtol), int(maxit), C.byref(st))
+        _check(rc, "eqs_rkc_step", ok)
+        return dict(stages=st.stages, total_iters=st.total_iters, max_iters=st.max_iters, min_iters=st.min_iters,
+                    not_converged=st.not_converged, max_relres=st.max_relres, rc=rc)

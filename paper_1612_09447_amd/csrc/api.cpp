@@ -1,0 +1,327 @@
+// C ABI entry points (declared in include/eqs.h). Every call validates its
+// arguments, runs under a catch-all so that no exception crosses the ABI, and
+// records a thread-local message on failure.
+#include <cmath>
+#include <new>
+#include <set>
+
+#include "eqs_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const eqs::Error& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return EQS_ERR_ALLOC;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return EQS_ERR_INVALID_ARG;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return EQS_ERR_INVALID_ARG;
+    }
+}
+
+using eqs::fail;
+
+void need(bool cond, const char* msg) {
+    if (!cond) fail(EQS_ERR_INVALID_ARG, msg);
+}
+
+void bind_device(const eqs_ctx* c) { EQS_HIP(hipSetDevice(c->device)); }
+
+void need_built(const eqs_ctx* c) {
+    if (!c->built) fail(EQS_ERR_STATE, "eqs_build_preconditioner has not been called since the last set-up change");
+}
+
+int result_code(int rc, const char* what) {
+    if (rc == EQS_ERR_NOT_CONVERGED) g_last_error = std::string(what) + ": iteration limit reached";
+    else if (rc == EQS_ERR_BREAKDOWN) g_last_error = std::string(what) + ": CG breakdown";
+    return rc;
+}
+
+}  // namespace
+
+namespace eqs {
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace eqs
+
+extern "C" {
+
+const char* eqs_last_error(void) { return g_last_error.c_str(); }
+
+int eqs_create(eqs_ctx** out, int device, void* hip_stream) {
+    return guarded([&] {
+        need(out != nullptr, "out is NULL");
+        *out = nullptr;
+        int n = 0;
+        EQS_HIP(hipGetDeviceCount(&n));
+        need(device >= 0 && device < n, "device id out of range");
+        EQS_HIP(hipSetDevice(device));
+        eqs_ctx* c = new eqs_ctx();
+        c->device = device;
+        c->stream = (hipStream_t)hip_stream;
+        *out = c;
+        return EQS_OK;
+    });
+}
+
+int eqs_destroy(eqs_ctx* ctx) {
+    return guarded([&] {
+        if (!ctx) return EQS_OK;
+        (void)hipSetDevice(ctx->device);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        else (void)hipDeviceSynchronize();
+        eqs::free_device(ctx);
+        eqs::prof_release(ctx);
+        delete ctx;
+        return EQS_OK;
+    });
+}
+
+int eqs_set_mesh(eqs_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        need(n_nodes >= 4 && n_nodes < INT32_MAX, "n_nodes must be in [4, 2^31)");
+        need(n_tets >= 1 && n_tets < INT32_MAX, "n_tets must be in [1, 2^31)");
+        need(xyz != nullptr && tets != nullptr, "xyz or tets is NULL");
+        bind_device(c);
+        eqs::free_device(c);
+        c->n_nodes = n_nodes;
+        c->n_tets = n_tets;
+        c->xyz.assign(xyz, xyz + 3 * n_nodes);
+        c->tets.assign(tets, tets + 4 * n_tets);
+        for (int64_t k = 0; k < 4 * n_tets; ++k)
+            need(tets[k] >= 0 && tets[k] < n_nodes, "tet node id out of range");
+        c->have_mesh = true;
+        c->have_mat = c->have_dir = false;
+        c->mats.clear();
+        c->tet_mat.clear();
+        c->dir_nodes.clear();
+        c->dir_drive.clear();
+        c->drives.clear();
+        return EQS_OK;
+    });
+}
+
+int eqs_set_materials(eqs_ctx* c, int32_t n_mat, const eqs_material* mats, const int32_t* tet_mat) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        if (!c->have_mesh) fail(EQS_ERR_STATE, "eqs_set_mesh must come first");
+        need(n_mat >= 1 && n_mat <= 65535, "n_mat must be in [1, 65535]");
+        need(mats != nullptr && tet_mat != nullptr, "mats or tet_mat is NULL");
+        for (int32_t m = 0; m < n_mat; ++m) {
+            const eqs_material& s = mats[m];
+            if (!std::isfinite(s.eps_r) || !std::isfinite(s.kappa0) || !std::isfinite(s.e_s) || !std::isfinite(s.alpha))
+                fail(EQS_ERR_NONFINITE, "non-finite material parameter");
+            need(s.eps_r > 0, "eps_r must be > 0");
+            need(s.kappa0 >= 0, "kappa0 must be >= 0");
+            if (s.nonlinear) need(s.e_s > 0 && s.alpha >= 0, "nonlinear material needs e_s > 0 and alpha >= 0");
+        }
+        for (int64_t e = 0; e < c->n_tets; ++e) need(tet_mat[e] >= 0 && tet_mat[e] < n_mat, "tet material id out of range");
+        eqs::free_device(c);
+        c->mats.assign(mats, mats + n_mat);
+        c->tet_mat.assign(tet_mat, tet_mat + c->n_tets);
+        c->have_mat = true;
+        return EQS_OK;
+    });
+}
+
+int eqs_set_dirichlet(eqs_ctx* c, int64_t n_d, const int32_t* nodes, const int32_t* drive_id, int32_t n_drive,
+                      const eqs_drive* drives) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        if (!c->have_mesh) fail(EQS_ERR_STATE, "eqs_set_mesh must come first");
+        need(n_d >= 1 && n_d < c->n_nodes, "need 1 <= n_d < n_nodes (at least one free node)");
+        need(n_drive >= 1 && n_drive <= EQS_MAX_DRIVES, "n_drive must be in [1, EQS_MAX_DRIVES]");
+        need(nodes && drive_id && drives, "NULL Dirichlet array");
+        std::vector<char> seen(c->n_nodes, 0);
+        for (int64_t k = 0; k < n_d; ++k) {
+            need(nodes[k] >= 0 && nodes[k] < c->n_nodes, "Dirichlet node id out of range");
+            need(!seen[nodes[k]], "Dirichlet node listed twice");
+            seen[nodes[k]] = 1;
+            need(drive_id[k] >= 0 && drive_id[k] < n_drive, "drive id out of range");
+        }
+        for (int32_t k = 0; k < n_drive; ++k)
+            if (!std::isfinite(drives[k].amp) || !std::isfinite(drives[k].freq) || !std::isfinite(drives[k].phase))
+                fail(EQS_ERR_NONFINITE, "non-finite drive parameter");
+        eqs::free_device(c);
+        c->dir_nodes.assign(nodes, nodes + n_d);
+        c->dir_drive.assign(drive_id, drive_id + n_d);
+        c->drives.assign(drives, drives + n_drive);
+        c->have_dir = true;
+        return EQS_OK;
+    });
+}
+
+int eqs_build_preconditioner(eqs_ctx* c, const eqs_amg_params* p) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        if (!(c->have_mesh && c->have_mat && c->have_dir))
+            fail(EQS_ERR_STATE, "mesh, materials and Dirichlet data must be set first");
+        eqs_amg_params a{};
+        if (p) a = *p;
+        need(a.precision == EQS_PREC_FP64 || a.precision == EQS_PREC_FP32, "precision must be FP64 or FP32");
+        if (a.coarse_max == 0) a.coarse_max = 512;
+        if (a.max_levels == 0) a.max_levels = 12;
+        if (a.theta == 0) a.theta = 0.08;
+        if (a.jacobi_weight == 0) a.jacobi_weight = 4.0 / 3.0;
+        if (a.smooth_weight == 0) a.smooth_weight = 4.0 / 3.0;
+        if (!p || p->flexible == 0) a.flexible = (a.precision == EQS_PREC_FP32) ? 1 : 0;
+        need(a.coarse_max >= 1 && a.coarse_max <= 4096, "coarse_max must be in [1, 4096]");
+        need(a.max_levels >= 1 && a.max_levels <= 16, "max_levels must be in [1, 16]");
+        need(a.theta >= 0 && a.theta < 1, "theta must be in [0, 1)");
+        need(a.jacobi_weight > 0 && a.jacobi_weight < 2 && a.smooth_weight > 0 && a.smooth_weight < 2,
+             "weights must be in (0, 2)");
+        bind_device(c);
+        eqs::free_device(c);
+        c->amg = a;
+        eqs::validate_and_order(c);
+        eqs::upload(c);
+        EQS_HIP(hipDeviceSynchronize());
+        c->built = true;
+        return EQS_OK;
+    });
+}
+
+int eqs_query(const eqs_ctx* c, eqs_info* info) {
+    return guarded([&] {
+        need(c != nullptr && info != nullptr, "NULL argument");
+        eqs_info o{};
+        o.n_nodes = c->n_nodes;
+        o.n_tets = c->n_tets;
+        o.n_free = c->built ? c->n_free : 0;
+        o.nnz_M = c->nnz_M;
+        o.precision = c->amg.precision;
+        if (c->built) {
+            if (c->amg.precision == EQS_PREC_FP32) {
+                o.n_levels = (int32_t)c->h32.lv.size();
+                for (size_t l = 0; l < c->h32.lv.size() && l < 16; ++l) {
+                    o.level_rows[l] = c->h32.lv[l].n;
+                    o.level_nnz[l] = c->h32.lv[l].A.stored;
+                }
+            } else {
+                o.n_levels = (int32_t)c->h64.lv.size();
+                for (size_t l = 0; l < c->h64.lv.size() && l < 16; ++l) {
+                    o.level_rows[l] = c->h64.lv[l].n;
+                    o.level_nnz[l] = c->h64.lv[l].A.stored;
+                }
+            }
+        }
+        o.device_bytes = c->device_bytes;
+        *info = o;
+        return EQS_OK;
+    });
+}
+
+int eqs_apply_K(eqs_ctx* c, double t, const double* x_dev, double* y_dev) {
+    return guarded([&] {
+        need(c != nullptr && x_dev != nullptr && y_dev != nullptr, "NULL argument");
+        need(x_dev != y_dev, "x and y must not alias");
+        need(std::isfinite(t), "t must be finite");
+        need_built(c);
+        bind_device(c);
+        hipStream_t s = c->stream;
+        eqs::launch_gather(s, x_dev, c->d_int_to_user, c->d_tmpN, c->n_free);
+        eqs::launch_kx(s, false, c, c->d_tmpN, eqs::drive_values(c, t), c->d_tmpN2);
+        eqs::launch_scatter(s, c->d_tmpN2, c->d_int_to_user, y_dev, c->n_nodes);
+        EQS_HIP(hipGetLastError());
+        EQS_HIP(hipStreamSynchronize(s));
+        return EQS_OK;
+    });
+}
+
+int eqs_stage_rhs(eqs_ctx* c, double t, const double* y_free_dev, double* r_dev) {
+    return guarded([&] {
+        need(c != nullptr && y_free_dev != nullptr && r_dev != nullptr, "NULL argument");
+        need(y_free_dev != r_dev, "y and r must not alias");
+        need(std::isfinite(t), "t must be finite");
+        need_built(c);
+        bind_device(c);
+        eqs::launch_kx(c->stream, true, c, y_free_dev, eqs::drive_values(c, t), r_dev);
+        EQS_HIP(hipGetLastError());
+        EQS_HIP(hipStreamSynchronize(c->stream));
+        return EQS_OK;
+    });
+}
+
+int eqs_apply_M(eqs_ctx* c, const double* x_dev, double* y_dev) {
+    return guarded([&] {
+        need(c != nullptr && x_dev != nullptr && y_dev != nullptr, "NULL argument");
+        need(x_dev != y_dev, "x and y must not alias");
+        need_built(c);
+        bind_device(c);
+        eqs::launch_spmv64(c->stream, c->M, x_dev, y_dev);
+        EQS_HIP(hipGetLastError());
+        EQS_HIP(hipStreamSynchronize(c->stream));
+        return EQS_OK;
+    });
+}
+
+int eqs_apply_preconditioner(eqs_ctx* c, const double* r_dev, double* z_dev) {
+    return guarded([&] {
+        need(c != nullptr && r_dev != nullptr && z_dev != nullptr, "NULL argument");
+        need(r_dev != z_dev, "r and z must not alias");
+        need_built(c);
+        bind_device(c);
+        eqs::apply_preconditioner(c, r_dev, z_dev);
+        return EQS_OK;
+    });
+}
+
+int eqs_solve_M(eqs_ctx* c, const double* rhs_dev, double* y_dev, double rtol, int32_t maxit, eqs_solve_stats* st) {
+    return guarded([&] {
+        need(c != nullptr && rhs_dev != nullptr && y_dev != nullptr, "NULL argument");
+        need(rhs_dev != y_dev, "rhs and y must not alias");
+        need(std::isfinite(rtol) && rtol >= 0, "rtol must be finite and >= 0");
+        need(maxit >= 0, "maxit must be >= 0");
+        need_built(c);
+        bind_device(c);
+        return result_code(eqs::solve_M(c, rhs_dev, y_dev, rtol, maxit, st), "eqs_solve_M");
+    });
+}
+
+int eqs_rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_dev, double rtol, int32_t maxit,
+                 eqs_step_stats* st) {
+    return guarded([&] {
+        need(c != nullptr && x_dev != nullptr, "NULL argument");
+        need(std::isfinite(t) && std::isfinite(dt) && dt > 0, "t must be finite and dt > 0");
+        need(s >= 2 && s <= 256, "s must be in [2, 256]");
+        need(std::isfinite(rtol) && rtol >= 0, "rtol must be finite and >= 0");
+        need(maxit >= 0, "maxit must be >= 0");
+        need_built(c);
+        bind_device(c);
+        return result_code(eqs::rkc_step(c, t, dt, s, x_dev, rtol, maxit, st), "eqs_rkc_step");
+    });
+}
+
+int eqs_profile_enable_impl(eqs_ctx* c, uint32_t mask);
+int eqs_profile_read_impl(eqs_ctx* c, int32_t cls, int64_t* launches, double* total_ms);
+
+int eqs_profile_enable(eqs_ctx* c, uint32_t class_mask) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        bind_device(c);
+        return eqs_profile_enable_impl(c, class_mask);
+    });
+}
+
+int eqs_profile_read(eqs_ctx* c, int32_t kclass, int64_t* launches, double* total_ms) {
+    return guarded([&] {
+        need(c != nullptr && launches != nullptr && total_ms != nullptr, "NULL argument");
+        need(kclass >= 0 && kclass < EQS_KCLASS_COUNT, "kernel class out of range");
+        bind_device(c);
+        return eqs_profile_read_impl(c, kclass, launches, total_ms);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+// Internal declarations of the EQS explicit-RKC library (gfx950).
+//
+// Layout in device memory (internal node order: the free nodes in increasing
+// user id, then the Dirichlet nodes in increasing user id):
+//   conn   int4   [n_tets]      internal node ids of each tet
+//   tmat   uint16 [n_tets]      material id of each tet
+//   xyz    double4[n_nodes]     x, y, z, 0 (one 32-byte record per node)
+//   mats   MatDev [n_mat]       eps (absolute), kappa0, 1/e_s, alpha, flags
+//   ddrive int32  [n_dir]       drive id of Dirichlet node n_free + k
+//   M      SELL-64 FP64         M restricted to the free nodes
+//   AMG    per level: SELL-64 A_l, P_l, R_l = P_l^T (FP64 or FP32), 1/diag,
+//          work vectors; a dense inverse at the coarsest level
+//
+// SELL-64: rows are cut into slices of 64 consecutive rows (one wavefront);
+// slice s stores width_s = max row length of its rows, column-major: entry k
+// of row 64 s + l sits at sptr[s] + 64 k + l. Short rows are padded with a
+// zero value and an in-range column.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "eqs.h"
+
+namespace eqs {
+
+constexpr int kSlice = 64;   // SELL slice height = wavefront size
+constexpr int kBlock = 256;  // threads per block for streaming kernels
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string msg;
+};
+void set_error(const std::string& msg);
+#define EQS_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::eqs::Error{EQS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+// ----------------------------------------------------------- host matrices
+template <typename T>
+struct Csr {
+    int32_t n_rows = 0, n_cols = 0;
+    std::vector<int32_t> ptr, col;
+    std::vector<T> val;
+    int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
+};
+
+// --------------------------------------------------------- device matrices
+template <typename T>
+struct Sell {
+    int32_t n_rows = 0, n_cols = 0, n_slices = 0;
+    int64_t stored = 0;         // padded entries
+    int32_t* sptr = nullptr;    // [n_slices + 1]
+    int32_t* col = nullptr;     // [stored]
+    T* val = nullptr;           // [stored]
+};
+
+struct MatDev {
+    double eps;      // eps0 * eps_r
+    double kappa0;
+    double inv_es;   // 1 / e_s
+    double alpha;
+    int32_t nonlinear;
+    int32_t ialpha;  // alpha as an integer in [0, 64] when exact, else -1
+};
+
+struct DriveVals {
+    double g[EQS_MAX_DRIVES];   // g_k(t)
+    double gd[EQS_MAX_DRIVES];  // g_k'(t)
+};
+
+// PCG scalars kept on the device so that the iteration needs no host values.
+struct PcgScalars {
+    double bb;       // |rhs|^2
+    double rr;       // |r|^2
+    double rho;      // r.z of the current iteration
+    double rho_old;  // r.z of the previous iteration
+    double beta;
+    double alpha;
+    double tol2;     // (rtol |rhs|)^2
+    double relres;
+    int32_t it;
+    int32_t maxit;
+    int32_t done;    // 1 once converged, out of iterations or broken down
+    int32_t status;  // EQS_OK / EQS_ERR_NOT_CONVERGED / EQS_ERR_BREAKDOWN
+    int32_t fresh;   // 1: next beta is 0 (first iteration or restart)
+    int32_t flexible;
+};
+
+template <typename T>
+struct Level {
+    int32_t n = 0;
+    Sell<T> A, P, R;   // P, R unused on the coarsest level
+    T* dinv = nullptr;
+    double omega = 0;  // damped Jacobi weight
+    T *b = nullptr, *x = nullptr, *xs = nullptr, *res = nullptr;
+    T* dense_inv = nullptr;  // coarsest level only: n x n, column-major
+};
+
+template <typename T>
+struct Hierarchy {
+    std::vector<Level<T>> lv;
+};
+
+// ------------------------------------------------------------------ context
+}  // namespace eqs
+
+struct eqs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    // inputs (host copies)
+    int64_t n_nodes = 0, n_tets = 0;
+    std::vector<double> xyz;
+    std::vector<int32_t> tets;
+    std::vector<eqs_material> mats;
+    std::vector<int32_t> tet_mat;
+    std::vector<int32_t> dir_nodes, dir_drive;
+    std::vector<eqs_drive> drives;
+    bool have_mesh = false, have_mat = false, have_dir = false, built = false;
+
+    // derived ordering
+    int64_t n_free = 0, n_dir = 0;
+    std::vector<int32_t> int_to_user;  // [n_nodes]
+    eqs_amg_params amg{};
+    int64_t nnz_M = 0;
+
+    // device: mesh + materials
+    int4* d_conn = nullptr;
+    uint16_t* d_tmat = nullptr;
+    double4* d_xyz = nullptr;
+    eqs::MatDev* d_mats = nullptr;
+    int32_t* d_ddrive = nullptr;
+    int32_t* d_int_to_user = nullptr;
+
+    // device: M and the hierarchy
+    eqs::Sell<double> M;
+    eqs::Hierarchy<double> h64;
+    eqs::Hierarchy<float> h32;
+
+    // device: work vectors (n_free doubles each)
+    double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr;
+    double *d_Y0 = nullptr, *d_Ya = nullptr, *d_Yb = nullptr, *d_F0 = nullptr, *d_F = nullptr;
+    double *d_rhs = nullptr, *d_tmpN = nullptr, *d_tmpN2 = nullptr;  // tmpN*: n_nodes
+    bool have_Flast = false;
+    double* d_partials = nullptr;  // 4 * max_blocks doubles
+    int64_t max_blocks = 0;
+    eqs::PcgScalars* d_scal = nullptr;
+    eqs::PcgScalars* h_scal = nullptr;  // pinned host mirror written by the finalisers
+    eqs::PcgScalars* d_hscal = nullptr; // its device-side address
+    hipEvent_t ev[2] = {nullptr, nullptr};
+
+    int64_t device_bytes = 0;
+    std::vector<void*> allocations;
+
+    // per-kernel-class timing (HIP event pairs around launches)
+    uint32_t prof_mask = 0;
+    std::vector<hipEvent_t> prof_ev[EQS_KCLASS_COUNT];
+    int64_t prof_used[EQS_KCLASS_COUNT] = {};
+};
+
+namespace eqs {
+
+// ------------------------------------------------------- host-side setup
+void validate_and_order(eqs_ctx* c);
+Csr<double> assemble_M_free(const eqs_ctx* c);
+struct AmgHost {
+    std::vector<Csr<double>> A, P, R;
+    std::vector<double> omega;
+    std::vector<double> coarse_inv;  // dense inverse of A.back(), column-major
+};
+AmgHost build_sa_amg(const Csr<double>& M, const eqs_amg_params& p);
+void rkc_coefficients(int s, std::vector<double>& mu, std::vector<double>& nu, std::vector<double>& mut,
+                      std::vector<double>& gmt, std::vector<double>& c);
+
+// device upload
+void* dev_alloc(eqs_ctx* c, size_t bytes);
+void upload(eqs_ctx* c);
+void free_device(eqs_ctx* c);
+template <typename T>
+Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A);
+
+DriveVals drive_values(const eqs_ctx* c, double t);
+
+// -------------------------------------------------------- kernel launchers
+void launch_fill(hipStream_t s, double* p, double v, int64_t n);
+void launch_gather(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n);
+void launch_scatter(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n);
+void launch_finish_state(hipStream_t s, const double* yfree, const int32_t* int_to_user, const int32_t* ddrive,
+                         DriveVals dv, double* x_user, int64_t n_free, int64_t n_nodes);
+void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, DriveVals dv, double* out);
+void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);
+void launch_rkc_first(hipStream_t s, double* out, const double* Y0, const double* F0, double a, int64_t n);
+void launch_rkc_combine(hipStream_t s, double* out, const double* Y0, const double* Yjm1, const double* Yjm2,
+                        const double* Fjm1, const double* F0, double c0, double c1, double c2, double c3,
+                        double c4, int64_t n);
+void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double* y);
+
+// PCG pieces (all scalar state on the device in PcgScalars)
+void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int32_t maxit, double rtol,
+              int flexible);
+void pcg_restart(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x);
+void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int precision);
+void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x);
+
+template <typename T>
+void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double* z, double* part_rz,
+            const PcgScalars* scal);
+
+// per-kernel timing (profile.cpp)
+void prof_begin(eqs_ctx* c, int cls, hipStream_t s);
+void prof_end(eqs_ctx* c, int cls, hipStream_t s);
+void prof_release(eqs_ctx* c);
+
+// drivers (solver.cpp)
+int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st);
+int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double rtol, int32_t maxit,
+             eqs_step_stats* st);
+void apply_preconditioner(eqs_ctx* c, const double* r, double* z);
+
+}  // namespace eqs

@@ -1,0 +1,665 @@
+// gfx950 kernels of the EQS explicit-RKC hot path.
+//
+//  * k_kx: fused element pass (Sec. III): per tetrahedron the barycentric
+//    gradients are formed from the four vertex coordinates, the constant field
+//    E = -grad(phi) gives kappa(|E|), and the element matrix times the local
+//    potentials is added straight into the output (K(x)x, or the stage
+//    right-hand side b(t) - K(x)x with b folded in element by element).
+//  * SELL-64 sparse products with fused epilogues for CG on M and for the
+//    smoothed-aggregation V-cycle (damped Jacobi, restriction, prolongation,
+//    dense coarsest solve).
+//  * CG vector updates with block partial sums; one-block finalisers turn the
+//    partials into the CG scalars, kept in device memory.
+//  * RKC stage combination (the paper's ref. [9]).
+#include "eqs_internal.h"
+
+namespace eqs {
+
+// ----------------------------------------------------------- reductions
+// Sum over a 256-thread block in a fixed order (wavefront tree, then the four
+// wavefront sums in index order); the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    return r;
+}
+
+// Sum of partials[0..n) by one block, in a fixed order; valid in thread 0.
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int64_t n, double* sh) {
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+    return block_sum(v, sh);
+}
+
+// ------------------------------------------------------------- simple ops
+__global__ void k_fill(double* __restrict__ p, double v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+// dst[i] = src[idx[i]]
+__global__ void k_gather(const double* __restrict__ src, const int32_t* __restrict__ idx, double* __restrict__ dst,
+                         int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+// dst[idx[i]] = src[i]
+__global__ void k_scatter(const double* __restrict__ src, const int32_t* __restrict__ idx, double* __restrict__ dst,
+                          int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[idx[i]] = src[i];
+}
+
+// x_user = (yfree on free nodes, g(t) on Dirichlet nodes), in user order.
+__global__ void k_finish_state(const double* __restrict__ yfree, const int32_t* __restrict__ int_to_user,
+                               const int32_t* __restrict__ ddrive, DriveVals dv, double* __restrict__ x_user,
+                               int64_t n_free, int64_t n_nodes) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    x_user[int_to_user[i]] = (i < n_free) ? yfree[i] : dv.g[ddrive[i - n_free]];
+}
+
+static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+void launch_fill(hipStream_t s, double* p, double v, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
+}
+void launch_copy(hipStream_t s, double* d, const double* src, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(kBlock), 0, s, d, src, n);
+}
+void launch_gather(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kBlock), 0, s, src, idx, dst, n);
+}
+void launch_scatter(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(kBlock), 0, s, src, idx, dst, n);
+}
+void launch_finish_state(hipStream_t s, const double* yfree, const int32_t* int_to_user, const int32_t* ddrive,
+                         DriveVals dv, double* x_user, int64_t n_free, int64_t n_nodes) {
+    hipLaunchKernelGGL(k_finish_state, dim3(grid_for(n_nodes)), dim3(kBlock), 0, s, yfree, int_to_user, ddrive, dv,
+                       x_user, n_free, n_nodes);
+}
+
+// ------------------------------------------------------ fused element pass
+__device__ __forceinline__ double ipow(double x, int n) {
+    double r = 1.0;
+    while (n) {
+        if (n & 1) r *= x;
+        x *= x;
+        n >>= 1;
+    }
+    return r;
+}
+
+// One thread per tetrahedron. With edges e_k = p_k - p_0 and cofactor rows
+// c_1 = e2 x e3, c_2 = e3 x e1, c_3 = e1 x e2, c_0 = -(c_1 + c_2 + c_3),
+// det = e1 . c_1: the barycentric gradients are c_a / det, so
+//   w = sum_k c_k (u_k - u_0) = det * grad(phi),   |E| = |w| / |det|,
+//   (A_e u)_a = |T| g_a . grad(phi) = c_a . w / (6 |det|).
+// RHS mode adds eps * A_e g' for the Dirichlet vertices (b(t) = -M_ID g'(t),
+// folded element by element) and writes -(...) for free vertices only.
+template <bool RHS>
+__global__ __launch_bounds__(256) void k_kx(int64_t n_tets, const int4* __restrict__ conn,
+                                             const uint16_t* __restrict__ tmat, const double4* __restrict__ xyz,
+                                             const MatDev* __restrict__ mats, const double* __restrict__ yfree,
+                                             int32_t n_free, const int32_t* __restrict__ ddrive, DriveVals dv,
+                                             double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_tets) return;
+    const int4 v = conn[e];
+    const MatDev m = mats[tmat[e]];
+    const double4 p0 = xyz[v.x], p1 = xyz[v.y], p2 = xyz[v.z], p3 = xyz[v.w];
+
+    bool bnd = false;
+    double u[4], r[4] = {0.0, 0.0, 0.0, 0.0};
+    const int id[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (id[a] < n_free) {
+            u[a] = yfree[id[a]];
+        } else {
+            const int d = ddrive[id[a] - n_free];
+            u[a] = dv.g[d];
+            r[a] = dv.gd[d];
+            bnd = true;
+        }
+    }
+    const double e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
+    const double e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
+    const double e3x = p3.x - p0.x, e3y = p3.y - p0.y, e3z = p3.z - p0.z;
+    const double c1x = e2y * e3z - e2z * e3y, c1y = e2z * e3x - e2x * e3z, c1z = e2x * e3y - e2y * e3x;
+    const double c2x = e3y * e1z - e3z * e1y, c2y = e3z * e1x - e3x * e1z, c2z = e3x * e1y - e3y * e1x;
+    const double c3x = e1y * e2z - e1z * e2y, c3y = e1z * e2x - e1x * e2z, c3z = e1x * e2y - e1y * e2x;
+    const double det = e1x * c1x + e1y * c1y + e1z * c1z;
+    const double adet = fabs(det);
+
+    const double d1 = u[1] - u[0], d2 = u[2] - u[0], d3 = u[3] - u[0];
+    double wx = c1x * d1 + c2x * d2 + c3x * d3;
+    double wy = c1y * d1 + c2y * d2 + c3y * d3;
+    double wz = c1z * d1 + c2z * d2 + c3z * d3;
+
+    double kappa = m.kappa0;
+    if (m.nonlinear) {
+        const double ratio = sqrt(wx * wx + wy * wy + wz * wz) / adet * m.inv_es;
+        const double pw = (m.ialpha >= 0) ? ipow(ratio, m.ialpha) : pow(ratio, m.alpha);
+        kappa *= 1.0 + pw;
+    }
+    wx *= kappa;
+    wy *= kappa;
+    wz *= kappa;
+    if (RHS && bnd) {
+        const double q1 = r[1] - r[0], q2 = r[2] - r[0], q3 = r[3] - r[0];
+        wx += m.eps * (c1x * q1 + c2x * q2 + c3x * q3);
+        wy += m.eps * (c1y * q1 + c2y * q2 + c3y * q3);
+        wz += m.eps * (c1z * q1 + c2z * q2 + c3z * q3);
+    }
+    const double sc = 1.0 / (6.0 * adet);
+    double y[4];
+    y[1] = (c1x * wx + c1y * wy + c1z * wz) * sc;
+    y[2] = (c2x * wx + c2y * wy + c2z * wz) * sc;
+    y[3] = (c3x * wx + c3y * wy + c3z * wz) * sc;
+    y[0] = -(y[1] + y[2] + y[3]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (RHS) {
+            if (id[a] < n_free) unsafeAtomicAdd(&out[id[a]], -y[a]);
+        } else {
+            unsafeAtomicAdd(&out[id[a]], y[a]);
+        }
+    }
+}
+
+void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, DriveVals dv, double* out) {
+    const int64_t nout = rhs_mode ? c->n_free : c->n_nodes;
+    launch_fill(s, out, 0.0, nout);
+    if (c->n_tets == 0) return;
+    dim3 g(grid_for(c->n_tets)), b(kBlock);
+    prof_begin(c, EQS_KCLASS_ELEMENT, s);
+    if (rhs_mode)
+        hipLaunchKernelGGL(k_kx<true>, g, b, 0, s, c->n_tets, c->d_conn, c->d_tmat, c->d_xyz, c->d_mats, yfree,
+                           (int32_t)c->n_free, c->d_ddrive, dv, out);
+    else
+        hipLaunchKernelGGL(k_kx<false>, g, b, 0, s, c->n_tets, c->d_conn, c->d_tmat, c->d_xyz, c->d_mats, yfree,
+                           (int32_t)c->n_free, c->d_ddrive, dv, out);
+    prof_end(c, EQS_KCLASS_ELEMENT, s);
+}
+
+// ------------------------------------------------------------- SELL-64
+template <typename T>
+struct SellView {
+    const int32_t* __restrict__ sptr;
+    const int32_t* __restrict__ col;
+    const T* __restrict__ val;
+    int32_t n_rows, n_slices;
+};
+template <typename T>
+static SellView<T> view(const Sell<T>& A) {
+    return SellView<T>{A.sptr, A.col, A.val, A.n_rows, A.n_slices};
+}
+
+// Row `row` of A times x (rows past n_rows but inside the last slice read padding).
+template <typename T, typename TX>
+__device__ __forceinline__ T sell_row(const SellView<T>& A, int32_t row, const TX* __restrict__ x) {
+    const int32_t s = row >> 6, l = row & 63;
+    const int32_t beg = A.sptr[s];
+    const int32_t w = (A.sptr[s + 1] - beg) >> 6;
+    const int32_t* cp = A.col + beg + l;
+    const T* vp = A.val + beg + l;
+    T acc = T(0);
+    for (int32_t k = 0; k < w; ++k) acc += vp[(int64_t)k * 64] * (T)x[cp[(int64_t)k * 64]];
+    return acc;
+}
+
+template <typename T>
+static unsigned sell_grid(const Sell<T>& A) {
+    return (unsigned)(((int64_t)A.n_slices * kSlice + kBlock - 1) / kBlock);
+}
+
+// y = A x  or  y += A x
+template <typename T>
+__global__ __launch_bounds__(256) void k_sell_mv(SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
+                                                  const PcgScalars* __restrict__ scal) {
+    if (scal && scal->done) return;
+    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= A.n_slices * 64) return;
+    const T v = sell_row(A, row, x);
+    if (row < A.n_rows) y[row] = acc ? y[row] + v : v;
+}
+
+__global__ __launch_bounds__(256) void k_spmv64(SellView<double> A, const double* __restrict__ x,
+                                                 double* __restrict__ y) {
+    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= A.n_slices * 64) return;
+    const double v = sell_row(A, row, x);
+    if (row < A.n_rows) y[row] = v;
+}
+
+void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double* y) {
+    if (A.n_rows > 0) hipLaunchKernelGGL(k_spmv64, dim3(sell_grid(A)), dim3(kBlock), 0, s, view(A), x, y);
+}
+
+// ------------------------------------------------------------ V-cycle
+// Pre-smoothing from a zero guess fused with the residual:
+//   x = omega D^{-1} b,   res = b - A x = b - A (omega D^{-1} b).
+template <typename T, typename TB>
+__global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> A, const T* __restrict__ dinv, T omega,
+                                                        const TB* __restrict__ b, T* __restrict__ x,
+                                                        T* __restrict__ res, const PcgScalars* __restrict__ scal) {
+    if (scal && scal->done) return;
+    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= A.n_slices * 64) return;
+    const int32_t s = row >> 6, l = row & 63;
+    const int32_t beg = A.sptr[s];
+    const int32_t w = (A.sptr[s + 1] - beg) >> 6;
+    const int32_t* cp = A.col + beg + l;
+    const T* vp = A.val + beg + l;
+    T acc = T(0);
+    for (int32_t k = 0; k < w; ++k) {
+        const int32_t j = cp[(int64_t)k * 64];
+        acc += vp[(int64_t)k * 64] * (dinv[j] * (T)b[j]);
+    }
+    if (row < A.n_rows) {
+        const T bi = (T)b[row];
+        x[row] = omega * dinv[row] * bi;
+        res[row] = bi - omega * acc;
+    }
+}
+
+// Post-smoothing: out = x + omega D^{-1} (b - A x). At the finest level the
+// output is CG's z (FP64) and the block partials of r.z and r.z_old (the
+// Polak-Ribiere numerator) are produced; z_old is read before it is overwritten.
+template <typename T, typename TB, typename TO, bool DOT>
+__global__ __launch_bounds__(256) void k_postsmooth(SellView<T> A, const T* __restrict__ dinv, T omega,
+                                                     const TB* __restrict__ b, const T* __restrict__ x,
+                                                     TO* __restrict__ out, double* __restrict__ part_rz,
+                                                     double* __restrict__ part_rzold, int64_t part_stride,
+                                                     const PcgScalars* __restrict__ scal) {
+    __shared__ double sh[4];
+    if (scal && scal->done) return;
+    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    double rz = 0.0, rzo = 0.0;
+    if (row < A.n_slices * 64) {
+        const T ax = sell_row(A, row, x);
+        if (row < A.n_rows) {
+            const T v = x[row] + omega * dinv[row] * ((T)b[row] - ax);
+            if (DOT) {
+                const double ri = (double)b[row];
+                rzo = ri * (double)out[row];
+                rz = ri * (double)v;
+            }
+            out[row] = (TO)v;
+        }
+    }
+    if (DOT) {
+        const double s1 = block_sum(rz, sh);
+        const double s2 = block_sum(rzo, sh);
+        if (threadIdx.x == 0) {
+            part_rz[blockIdx.x] = s1;
+            part_rzold[blockIdx.x] = s2;
+        }
+    }
+    (void)part_stride;
+}
+
+// Coarsest level: x = A^{-1} b with the dense inverse (column-major, symmetric).
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const T* __restrict__ b,
+                                                 T* __restrict__ x, int32_t n, const PcgScalars* __restrict__ scal) {
+    if (scal && scal->done) return;
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T acc = T(0);
+    for (int32_t k = 0; k < n; ++k) acc += inv[(int64_t)k * n + i] * b[k];
+    x[i] = acc;
+}
+
+// Single-level hierarchy: z = A^{-1} r with the same r.z partials as k_postsmooth.
+template <typename T, bool DOT>
+__global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv, const double* __restrict__ r,
+                                                        double* __restrict__ z, int32_t n, double* __restrict__ part_rz,
+                                                        double* __restrict__ part_rzold,
+                                                        const PcgScalars* __restrict__ scal) {
+    __shared__ double sh[4];
+    if (scal && scal->done) return;
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    double rz = 0.0, rzo = 0.0;
+    if (i < n) {
+        T acc = T(0);
+        for (int32_t k = 0; k < n; ++k) acc += inv[(int64_t)k * n + i] * (T)r[k];
+        if (DOT) {
+            rzo = r[i] * z[i];
+            rz = r[i] * (double)acc;
+        }
+        z[i] = (double)acc;
+    }
+    if (DOT) {
+        const double s1 = block_sum(rz, sh);
+        const double s2 = block_sum(rzo, sh);
+        if (threadIdx.x == 0) {
+            part_rz[blockIdx.x] = s1;
+            part_rzold[blockIdx.x] = s2;
+        }
+    }
+}
+
+// V(1,1) cycle z = B r. r and z are FP64 (CG's vectors); the hierarchy is T.
+template <typename T>
+void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double* z, double* part_rz,
+            const PcgScalars* scal) {
+    const int L = (int)h.lv.size();
+    dim3 b(kBlock);
+    double* part_rzold = part_rz ? part_rz + c->max_blocks : nullptr;
+    if (L == 1) {
+        // the matrix is small enough for its dense inverse: z = A^{-1} r
+        Level<T>& lv = h.lv[0];
+        if (part_rz)
+            hipLaunchKernelGGL((k_dense_precond<T, true>), dim3(grid_for(lv.n)), b, 0, s, (const T*)lv.dense_inv, r, z,
+                               lv.n, part_rz, part_rzold, scal);
+        else
+            hipLaunchKernelGGL((k_dense_precond<T, false>), dim3(grid_for(lv.n)), b, 0, s, (const T*)lv.dense_inv, r,
+                               z, lv.n, part_rz, part_rzold, scal);
+        return;
+    }
+    // descend
+    for (int l = 0; l < L - 1; ++l) {
+        Level<T>& lv = h.lv[l];
+        if (l == 0) {
+            prof_begin(c, EQS_KCLASS_PRESMOOTH0, s);
+            hipLaunchKernelGGL((k_presmooth_res<T, double>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A), lv.dinv,
+                               (T)lv.omega, r, lv.x, lv.res, scal);
+            prof_end(c, EQS_KCLASS_PRESMOOTH0, s);
+        } else
+            hipLaunchKernelGGL((k_presmooth_res<T, T>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A), lv.dinv,
+                               (T)lv.omega, (const T*)lv.b, lv.x, lv.res, scal);
+        hipLaunchKernelGGL(k_sell_mv<T>, dim3(sell_grid(lv.R)), b, 0, s, view(lv.R), (const T*)lv.res,
+                           h.lv[l + 1].b, 0, scal);
+    }
+    {
+        Level<T>& lc = h.lv[L - 1];
+        hipLaunchKernelGGL(k_coarse<T>, dim3(grid_for(lc.n)), b, 0, s, (const T*)lc.dense_inv, (const T*)lc.b, lc.x,
+                           lc.n, scal);
+    }
+    // ascend
+    for (int l = L - 2; l >= 0; --l) {
+        Level<T>& lv = h.lv[l];
+        const T* xc = (l + 1 == L - 1) ? h.lv[l + 1].x : h.lv[l + 1].xs;
+        hipLaunchKernelGGL(k_sell_mv<T>, dim3(sell_grid(lv.P)), b, 0, s, view(lv.P), xc, lv.x, 1, scal);
+        if (l > 0) {
+            hipLaunchKernelGGL((k_postsmooth<T, T, T, false>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A), lv.dinv,
+                               (T)lv.omega, (const T*)lv.b, (const T*)lv.x, lv.xs, (double*)nullptr,
+                               (double*)nullptr, (int64_t)0, scal);
+        } else if (part_rz) {
+            prof_begin(c, EQS_KCLASS_POSTSMOOTH0, s);
+            hipLaunchKernelGGL((k_postsmooth<T, double, double, true>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A),
+                               lv.dinv, (T)lv.omega, r, (const T*)lv.x, z, part_rz, part_rzold, c->max_blocks,
+                               scal);
+            prof_end(c, EQS_KCLASS_POSTSMOOTH0, s);
+        } else {
+            hipLaunchKernelGGL((k_postsmooth<T, double, double, false>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A),
+                               lv.dinv, (T)lv.omega, r, (const T*)lv.x, z, (double*)nullptr, (double*)nullptr,
+                               (int64_t)0, scal);
+        }
+    }
+}
+
+template void vcycle<double>(hipStream_t, eqs_ctx*, Hierarchy<double>&, const double*, double*, double*,
+                             const PcgScalars*);
+template void vcycle<float>(hipStream_t, eqs_ctx*, Hierarchy<float>&, const double*, double*, double*,
+                            const PcgScalars*);
+
+// ------------------------------------------------------------------ CG
+// r = rhs - M x; partials of |r|^2 and |rhs|^2.
+__global__ __launch_bounds__(256) void k_pcg_residual(SellView<double> M, const double* __restrict__ rhs,
+                                                       const double* __restrict__ x, double* __restrict__ r,
+                                                       double* __restrict__ part_rr, double* __restrict__ part_bb) {
+    __shared__ double sh[4];
+    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0, bb = 0.0;
+    if (row < M.n_slices * 64) {
+        const double mx = sell_row(M, row, x);
+        if (row < M.n_rows) {
+            const double bi = rhs[row];
+            const double ri = bi - mx;
+            r[row] = ri;
+            rr = ri * ri;
+            bb = bi * bi;
+        }
+    }
+    const double s1 = block_sum(rr, sh);
+    const double s2 = block_sum(bb, sh);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = s1;
+        part_bb[blockIdx.x] = s2;
+    }
+}
+
+// q = M z + beta q, p = z + beta p (so q = M p without a second pass); partials of p.q.
+__global__ __launch_bounds__(256) void k_pcg_spmv(SellView<double> M, const double* __restrict__ z,
+                                                   double* __restrict__ p, double* __restrict__ q,
+                                                   double* __restrict__ part_pq, const PcgScalars* __restrict__ scal) {
+    __shared__ double sh[4];
+    if (scal->done) return;
+    const double beta = scal->beta;
+    const int fresh = scal->fresh;
+    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    double pq = 0.0;
+    if (row < M.n_slices * 64) {
+        const double mz = sell_row(M, row, z);
+        if (row < M.n_rows) {
+            double pi, qi;
+            if (fresh) {
+                pi = z[row];
+                qi = mz;
+            } else {
+                pi = z[row] + beta * p[row];
+                qi = mz + beta * q[row];
+            }
+            p[row] = pi;
+            q[row] = qi;
+            pq = pi * qi;
+        }
+    }
+    const double s1 = block_sum(pq, sh);
+    if (threadIdx.x == 0) part_pq[blockIdx.x] = s1;
+}
+
+// x += alpha p, r -= alpha q; partials of |r|^2.
+__global__ __launch_bounds__(256) void k_pcg_update(double* __restrict__ x, double* __restrict__ r,
+                                                     const double* __restrict__ p, const double* __restrict__ q,
+                                                     int64_t n, double* __restrict__ part_rr,
+                                                     const PcgScalars* __restrict__ scal) {
+    __shared__ double sh[4];
+    if (scal->done) return;
+    const double alpha = scal->alpha;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0;
+    if (i < n) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        rr = ri * ri;
+    }
+    const double s1 = block_sum(rr, sh);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = s1;
+}
+
+// mode 0: start of a solve (it = 0); mode 1: restart from the true residual
+// (iteration count kept). Sets done when |r| <= rtol |rhs|, rhs = 0 or the
+// iteration budget is spent. The scalars are mirrored to host memory.
+__global__ void k_fin_start(PcgScalars* __restrict__ s, PcgScalars* __restrict__ host, const double* __restrict__ prr,
+                            const double* __restrict__ pbb, int64_t nb, double rtol, int32_t maxit, int32_t flexible,
+                            int32_t mode) {
+    __shared__ double sh[4];
+    const double rr = reduce_partials(prr, nb, sh);
+    const double bb = reduce_partials(pbb, nb, sh);
+    if (threadIdx.x != 0) return;
+    PcgScalars v = *s;
+    if (mode == 0) {
+        v = PcgScalars{};
+        v.maxit = maxit;
+        v.flexible = flexible;
+        v.tol2 = rtol * rtol * bb;
+    }
+    v.bb = bb;
+    v.rr = rr;
+    v.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    v.fresh = 1;
+    v.beta = 0.0;
+    v.status = EQS_OK;
+    v.done = 0;
+    if (bb == 0.0 || rr <= v.tol2) {
+        v.done = 1;
+    } else if (v.it >= v.maxit) {
+        v.done = 1;
+        v.status = EQS_ERR_NOT_CONVERGED;
+    } else if (!isfinite(rr) || !isfinite(bb)) {
+        v.done = 1;
+        v.status = EQS_ERR_BREAKDOWN;
+    }
+    *s = v;
+    *host = v;
+}
+
+// beta from r.z (Polak-Ribiere with r.z_old when flexible).
+__global__ void k_fin_beta(PcgScalars* __restrict__ s, const double* __restrict__ prz,
+                           const double* __restrict__ przold, int64_t nb) {
+    __shared__ double sh[4];
+    if (s->done) return;
+    const double rz = reduce_partials(prz, nb, sh);
+    const double rzo = reduce_partials(przold, nb, sh);
+    if (threadIdx.x != 0) return;
+    if (!(rz > 0.0) || !isfinite(rz)) {
+        s->done = 1;
+        s->status = EQS_ERR_BREAKDOWN;
+        return;
+    }
+    if (s->fresh) s->beta = 0.0;
+    else s->beta = s->flexible ? (rz - rzo) / s->rho : rz / s->rho;
+    s->rho = rz;
+}
+
+__global__ void k_fin_alpha(PcgScalars* __restrict__ s, const double* __restrict__ ppq, int64_t nb) {
+    __shared__ double sh[4];
+    if (s->done) return;
+    const double pq = reduce_partials(ppq, nb, sh);
+    if (threadIdx.x != 0) return;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        s->done = 1;
+        s->status = EQS_ERR_BREAKDOWN;
+        return;
+    }
+    s->alpha = s->rho / pq;
+    s->fresh = 0;
+}
+
+__global__ void k_fin_conv(PcgScalars* __restrict__ s, PcgScalars* __restrict__ host, const double* __restrict__ prr,
+                           int64_t nb) {
+    __shared__ double sh[4];
+    if (s->done) {
+        if (threadIdx.x == 0) host->done = 1;
+        return;
+    }
+    const double rr = reduce_partials(prr, nb, sh);
+    if (threadIdx.x != 0) return;
+    PcgScalars v = *s;
+    v.rr = rr;
+    v.relres = sqrt(rr / v.bb);
+    v.it += 1;
+    if (rr <= v.tol2) {
+        v.done = 1;
+    } else if (v.it >= v.maxit) {
+        v.done = 1;
+        v.status = EQS_ERR_NOT_CONVERGED;
+    } else if (!isfinite(rr)) {
+        v.done = 1;
+        v.status = EQS_ERR_BREAKDOWN;
+    }
+    *s = v;
+    *host = v;
+}
+
+static PcgScalars* host_mirror(eqs_ctx* c) { return c->d_hscal; }
+
+void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int32_t maxit, double rtol,
+              int flexible) {
+    const int64_t nb = sell_grid(c->M);
+    double* P = c->d_partials;
+    hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), rhs, x, c->d_r, P,
+                       P + c->max_blocks);
+    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kBlock), 0, s, c->d_scal, host_mirror(c), P, P + c->max_blocks,
+                       nb, rtol, maxit, flexible, 0);
+}
+
+void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x) {
+    const int64_t nb = sell_grid(c->M);
+    double* P = c->d_partials;
+    hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), rhs, x, c->d_r, P,
+                       P + c->max_blocks);
+    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kBlock), 0, s, c->d_scal, host_mirror(c), P, P + c->max_blocks,
+                       nb, 0.0, 0, 0, 1);
+}
+
+void pcg_restart(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x) { pcg_true_residual(s, c, rhs, x); }
+
+void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int precision) {
+    (void)rhs;
+    const int64_t nbM = sell_grid(c->M);
+    const int64_t nbV = (c->n_free + kBlock - 1) / kBlock;
+    double* P = c->d_partials;
+    const int64_t mb = c->max_blocks;
+    // z = B r, with partials of r.z (P) and r.z_old (P + mb)
+    prof_begin(c, EQS_KCLASS_VCYCLE, s);
+    if (precision == EQS_PREC_FP32) vcycle<float>(s, c, c->h32, c->d_r, c->d_z, P, c->d_scal);
+    else vcycle<double>(s, c, c->h64, c->d_r, c->d_z, P, c->d_scal);
+    prof_end(c, EQS_KCLASS_VCYCLE, s);
+    const int64_t nbz = nbV;  // the finest-level kernel that wrote the r.z partials has one block per 256 rows
+    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kBlock), 0, s, c->d_scal, P, P + mb, nbz);
+    prof_begin(c, EQS_KCLASS_SPMV_M, s);
+    hipLaunchKernelGGL(k_pcg_spmv, dim3(nbM), dim3(kBlock), 0, s, view(c->M), c->d_z, c->d_p, c->d_q, P + 2 * mb,
+                       c->d_scal);
+    prof_end(c, EQS_KCLASS_SPMV_M, s);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kBlock), 0, s, c->d_scal, P + 2 * mb, nbM);
+    prof_begin(c, EQS_KCLASS_CG_UPDATE, s);
+    hipLaunchKernelGGL(k_pcg_update, dim3(nbV), dim3(kBlock), 0, s, x, c->d_r, c->d_p, c->d_q, c->n_free,
+                       P + 3 * mb, c->d_scal);
+    prof_end(c, EQS_KCLASS_CG_UPDATE, s);
+    hipLaunchKernelGGL(k_fin_conv, dim3(1), dim3(kBlock), 0, s, c->d_scal, host_mirror(c), P + 3 * mb, nbV);
+}
+
+// ------------------------------------------------------------------ RKC
+__global__ void k_rkc_first(double* __restrict__ out, const double* __restrict__ Y0, const double* __restrict__ F0,
+                            double a, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = Y0[i] + a * F0[i];
+}
+
+// out may alias Yjm2 (each element is read before it is written).
+__global__ void k_rkc_combine(double* out, const double* __restrict__ Y0, const double* __restrict__ Yjm1,
+                              const double* Yjm2, const double* __restrict__ Fjm1, const double* __restrict__ F0,
+                              double c0, double c1, double c2, double c3, double c4, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = c0 * Y0[i] + c1 * Yjm1[i] + c2 * Yjm2[i] + c3 * Fjm1[i] + c4 * F0[i];
+}
+
+void launch_rkc_first(hipStream_t s, double* out, const double* Y0, const double* F0, double a, int64_t n) {
+    hipLaunchKernelGGL(k_rkc_first, dim3(grid_for(n)), dim3(kBlock), 0, s, out, Y0, F0, a, n);
+}
+
+void launch_rkc_combine(hipStream_t s, double* out, const double* Y0, const double* Yjm1, const double* Yjm2,
+                        const double* Fjm1, const double* F0, double c0, double c1, double c2, double c3,
+                        double c4, int64_t n) {
+    hipLaunchKernelGGL(k_rkc_combine, dim3(grid_for(n)), dim3(kBlock), 0, s, out, Y0, Yjm1, Yjm2, Fjm1, F0, c0, c1,
+                       c2, c3, c4, n);
+}
+
+}  // namespace eqs

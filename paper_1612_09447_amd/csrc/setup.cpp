@@ -1,0 +1,632 @@
+// Host-side, once-per-context setup: input validation and node ordering,
+// assembly of the constant permittivity matrix M on the free nodes (eq. (2)),
+// the smoothed-aggregation AMG hierarchy that preconditions every M-solve
+// (built once: Sec. II, the constant M turns the stage solves into a multiple
+// right-hand-side problem), RKC coefficients (ref. [9] of the paper) and the
+// upload of everything to device memory in SELL-64 form.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "eqs_internal.h"
+
+namespace eqs {
+
+static constexpr double kEps0 = 8.8541878128e-12;  // F/m
+
+// Edge vectors from p0 and their cross products: for a tet with edges
+// e1, e2, e3 from p0, the rows of J^{-1} (J = [e1 e2 e3]) are
+// (e2 x e3, e3 x e1, e1 x e2) / det with det = e1 . (e2 x e3); so the
+// barycentric gradients are g_k = c_k / det and g_0 = -(g_1 + g_2 + g_3).
+static double tet_cofactors(const double* p0, const double* p1, const double* p2, const double* p3,
+                            double c[4][3]) {
+    double e1[3], e2[3], e3[3];
+    for (int d = 0; d < 3; ++d) {
+        e1[d] = p1[d] - p0[d];
+        e2[d] = p2[d] - p0[d];
+        e3[d] = p3[d] - p0[d];
+    }
+    auto cross = [](const double* a, const double* b, double* o) {
+        o[0] = a[1] * b[2] - a[2] * b[1];
+        o[1] = a[2] * b[0] - a[0] * b[2];
+        o[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    cross(e2, e3, c[1]);
+    cross(e3, e1, c[2]);
+    cross(e1, e2, c[3]);
+    for (int d = 0; d < 3; ++d) c[0][d] = -(c[1][d] + c[2][d] + c[3][d]);
+    return e1[0] * c[1][0] + e1[1] * c[1][1] + e1[2] * c[1][2];
+}
+
+// ------------------------------------------------------------ validation
+void validate_and_order(eqs_ctx* c) {
+    const int64_t N = c->n_nodes;
+    for (int64_t i = 0; i < 3 * N; ++i)
+        if (!std::isfinite(c->xyz[i])) fail(EQS_ERR_NONFINITE, "non-finite node coordinate");
+    for (int64_t e = 0; e < c->n_tets; ++e) {
+        const int32_t* v = &c->tets[4 * e];
+        for (int a = 0; a < 4; ++a)
+            if (v[a] < 0 || v[a] >= N) fail(EQS_ERR_INVALID_ARG, "tet " + std::to_string(e) + " has a node id out of range");
+        double cf[4][3];
+        double det = tet_cofactors(&c->xyz[3 * (int64_t)v[0]], &c->xyz[3 * (int64_t)v[1]], &c->xyz[3 * (int64_t)v[2]],
+                                   &c->xyz[3 * (int64_t)v[3]], cf);
+        if (!(std::fabs(det) > 0) || !std::isfinite(det))
+            fail(EQS_ERR_INVALID_ARG, "tet " + std::to_string(e) + " has zero volume");
+    }
+    std::vector<char> is_dir(N, 0);
+    for (size_t k = 0; k < c->dir_nodes.size(); ++k) is_dir[c->dir_nodes[k]] = 1;
+    c->n_dir = (int64_t)c->dir_nodes.size();
+    c->n_free = N - c->n_dir;
+    c->int_to_user.resize(N);
+    int64_t f = 0, d = c->n_free;
+    for (int64_t i = 0; i < N; ++i) {
+        if (is_dir[i]) c->int_to_user[d++] = (int32_t)i;
+        else c->int_to_user[f++] = (int32_t)i;
+    }
+}
+
+// ----------------------------------------------------------- assembly of M
+// Off-diagonal entries whose magnitude is at roundoff level against the
+// diagonal, |a_ij| <= 1e-14 sqrt(a_ii a_jj), are dropped. On meshes built from
+// right-angled (Kuhn) tets the P1 Laplacian has exact zeros on the face and
+// body diagonals of every cube, i.e. about half of the structural entries.
+static Csr<double> drop_zeros(const Csr<double>& A) {
+    std::vector<double> d(A.n_rows, 0.0);
+    for (int32_t i = 0; i < A.n_rows; ++i)
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (A.col[k] == i) d[i] = A.val[k];
+    Csr<double> B;
+    B.n_rows = A.n_rows;
+    B.n_cols = A.n_cols;
+    B.ptr.assign(A.n_rows + 1, 0);
+    B.col.reserve(A.nnz());
+    B.val.reserve(A.nnz());
+    for (int32_t i = 0; i < A.n_rows; ++i) {
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            const int32_t j = A.col[k];
+            if (j != i && std::fabs(A.val[k]) <= 1e-14 * std::sqrt(std::fabs(d[i] * d[j]))) continue;
+            B.col.push_back(j);
+            B.val.push_back(A.val[k]);
+        }
+        B.ptr[i + 1] = (int32_t)B.col.size();
+    }
+    return B;
+}
+
+Csr<double> assemble_M_free(const eqs_ctx* c) {
+    const int64_t N = c->n_nodes, T = c->n_tets, NF = c->n_free;
+    std::vector<int32_t> u2i(N);
+    for (int64_t i = 0; i < N; ++i) u2i[c->int_to_user[i]] = (int32_t)i;
+
+    // node -> incident tets
+    std::vector<int64_t> nt_ptr(N + 1, 0);
+    for (int64_t e = 0; e < 4 * T; ++e) nt_ptr[u2i[c->tets[e]] + 1]++;
+    for (int64_t i = 0; i < N; ++i) nt_ptr[i + 1] += nt_ptr[i];
+    std::vector<int32_t> nt(nt_ptr[N]);
+    {
+        std::vector<int64_t> fill(nt_ptr.begin(), nt_ptr.end() - 1);
+        for (int64_t e = 0; e < T; ++e)
+            for (int a = 0; a < 4; ++a) nt[fill[u2i[c->tets[4 * e + a]]]++] = (int32_t)e;
+    }
+
+    // row patterns: free neighbours through incident tets
+    Csr<double> M;
+    M.n_rows = M.n_cols = (int32_t)NF;
+    M.ptr.assign(NF + 1, 0);
+    std::vector<int32_t> buf;
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t pos = 0;
+        for (int64_t i = 0; i < NF; ++i) {
+            buf.clear();
+            for (int64_t k = nt_ptr[i]; k < nt_ptr[i + 1]; ++k) {
+                const int32_t* v = &c->tets[4 * (int64_t)nt[k]];
+                for (int a = 0; a < 4; ++a) {
+                    int32_t j = u2i[v[a]];
+                    if (j < NF) buf.push_back(j);
+                }
+            }
+            std::sort(buf.begin(), buf.end());
+            buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+            if (pass == 0) {
+                pos += (int64_t)buf.size();
+                if (pos > INT32_MAX) fail(EQS_ERR_INVALID_ARG, "M has more than 2^31 nonzeros");
+                M.ptr[i + 1] = (int32_t)pos;
+            } else {
+                std::copy(buf.begin(), buf.end(), M.col.begin() + M.ptr[i]);
+            }
+        }
+        if (pass == 0) {
+            M.col.resize(M.ptr[NF]);
+            M.val.assign(M.ptr[NF], 0.0);
+        }
+    }
+
+    // values: element matrices eps_e |T| g_a . g_b = eps_e c_a . c_b / (6 |det|)
+    for (int64_t e = 0; e < T; ++e) {
+        const int32_t* vu = &c->tets[4 * e];
+        int32_t v[4];
+        for (int a = 0; a < 4; ++a) v[a] = u2i[vu[a]];
+        double cf[4][3];
+        double det = tet_cofactors(&c->xyz[3 * (int64_t)vu[0]], &c->xyz[3 * (int64_t)vu[1]], &c->xyz[3 * (int64_t)vu[2]],
+                                   &c->xyz[3 * (int64_t)vu[3]], cf);
+        const double w = kEps0 * c->mats[c->tet_mat[e]].eps_r / (6.0 * std::fabs(det));
+        for (int a = 0; a < 4; ++a) {
+            if (v[a] >= NF) continue;
+            const int32_t* cb = &M.col[M.ptr[v[a]]];
+            const int32_t* ce = &M.col[M.ptr[v[a] + 1]];
+            for (int b = 0; b < 4; ++b) {
+                if (v[b] >= NF) continue;
+                const int32_t* it = std::lower_bound(cb, ce, v[b]);
+                M.val[it - M.col.data()] += w * (cf[a][0] * cf[b][0] + cf[a][1] * cf[b][1] + cf[a][2] * cf[b][2]);
+            }
+        }
+    }
+    return drop_zeros(M);
+}
+
+// ------------------------------------------------------ sparse host algebra
+static Csr<double> transpose(const Csr<double>& A) {
+    Csr<double> T;
+    T.n_rows = A.n_cols;
+    T.n_cols = A.n_rows;
+    T.ptr.assign(T.n_rows + 1, 0);
+    for (int32_t k = 0; k < (int32_t)A.nnz(); ++k) T.ptr[A.col[k] + 1]++;
+    for (int32_t i = 0; i < T.n_rows; ++i) T.ptr[i + 1] += T.ptr[i];
+    T.col.resize(A.nnz());
+    T.val.resize(A.nnz());
+    std::vector<int32_t> fill(T.ptr.begin(), T.ptr.end() - 1);
+    for (int32_t i = 0; i < A.n_rows; ++i)
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            int32_t p = fill[A.col[k]]++;
+            T.col[p] = i;
+            T.val[p] = A.val[k];
+        }
+    return T;
+}
+
+// C = A B, row by row with a dense accumulator (columns sorted per row).
+static Csr<double> spgemm(const Csr<double>& A, const Csr<double>& B) {
+    Csr<double> C;
+    C.n_rows = A.n_rows;
+    C.n_cols = B.n_cols;
+    C.ptr.assign(C.n_rows + 1, 0);
+    std::vector<double> acc(B.n_cols, 0.0);
+    std::vector<int32_t> mark(B.n_cols, -1), cols;
+    for (int32_t i = 0; i < A.n_rows; ++i) {
+        cols.clear();
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            const int32_t r = A.col[k];
+            const double a = A.val[k];
+            for (int32_t m = B.ptr[r]; m < B.ptr[r + 1]; ++m) {
+                const int32_t j = B.col[m];
+                if (mark[j] != i) {
+                    mark[j] = i;
+                    acc[j] = 0.0;
+                    cols.push_back(j);
+                }
+                acc[j] += a * B.val[m];
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        if ((int64_t)C.col.size() + (int64_t)cols.size() > INT32_MAX) fail(EQS_ERR_INVALID_ARG, "AMG product too large");
+        for (int32_t j : cols) {
+            C.col.push_back(j);
+            C.val.push_back(acc[j]);
+        }
+        C.ptr[i + 1] = (int32_t)C.col.size();
+    }
+    return C;
+}
+
+static std::vector<double> diagonal(const Csr<double>& A) {
+    std::vector<double> d(A.n_rows, 0.0);
+    for (int32_t i = 0; i < A.n_rows; ++i)
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (A.col[k] == i) d[i] = A.val[k];
+    return d;
+}
+
+// Spectral radius of D^{-1} A: power iteration (deterministic start), with a
+// 5 % margin, capped by the Gershgorin bound max_i sum_j |a_ij| / a_ii.
+static double spectral_radius_DinvA(const Csr<double>& A, const std::vector<double>& d) {
+    const int32_t n = A.n_rows;
+    double gersh = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += std::fabs(A.val[k]);
+        gersh = std::max(gersh, s / d[i]);
+    }
+    std::vector<double> x(n), y(n);
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    for (int32_t i = 0; i < n; ++i) {
+        st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+        x[i] = 0.5 + (double)(st >> 11) * (1.0 / 9007199254740992.0);
+    }
+    double lam = 0.0;
+    for (int it = 0; it < 15; ++it) {
+        double nx = 0.0, ny = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
+            y[i] = s / d[i];
+            ny += y[i] * y[i];
+            nx += x[i] * x[i];
+        }
+        lam = std::sqrt(ny / nx);
+        double inv = 1.0 / std::sqrt(ny);
+        for (int32_t i = 0; i < n; ++i) x[i] = y[i] * inv;
+    }
+    return std::min(gersh, 1.05 * lam);
+}
+
+// Greedy aggregation on the strength graph: (1) a node whose strong
+// neighbours are all unassigned seeds an aggregate with them; (2) leftover
+// nodes join the seeded aggregate they are most strongly tied to; (3) what is
+// still unassigned forms aggregates with its unassigned strong neighbours.
+static int32_t aggregate(const Csr<double>& A, const std::vector<double>& d, double theta,
+                         std::vector<int32_t>& agg) {
+    const int32_t n = A.n_rows;
+    std::vector<char> strong(A.nnz(), 0);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            int32_t j = A.col[k];
+            if (j != i && std::fabs(A.val[k]) >= theta * std::sqrt(std::fabs(d[i] * d[j]))) strong[k] = 1;
+        }
+    agg.assign(n, -1);
+    int32_t na = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (agg[i] != -1) continue;
+        bool free_nbhd = true, any = false;
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (strong[k]) {
+                any = true;
+                if (agg[A.col[k]] != -1) { free_nbhd = false; break; }
+            }
+        if (!any || !free_nbhd) continue;
+        agg[i] = na;
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (strong[k]) agg[A.col[k]] = na;
+        ++na;
+    }
+    std::vector<int32_t> seeded = agg;
+    for (int32_t i = 0; i < n; ++i) {
+        if (agg[i] != -1) continue;
+        double best = -1.0;
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (strong[k] && seeded[A.col[k]] != -1 && std::fabs(A.val[k]) > best) {
+                best = std::fabs(A.val[k]);
+                agg[i] = seeded[A.col[k]];
+            }
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        if (agg[i] != -1) continue;
+        agg[i] = na;
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (strong[k] && agg[A.col[k]] == -1) agg[A.col[k]] = na;
+        ++na;
+    }
+    return na;
+}
+
+// Dense inverse of a small SPD matrix via Cholesky (column-major output).
+static std::vector<double> dense_spd_inverse(const Csr<double>& A) {
+    const int32_t n = A.n_rows;
+    std::vector<double> L((size_t)n * n, 0.0);  // row-major lower factor
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) L[(size_t)i * n + A.col[k]] = A.val[k];
+    for (int32_t j = 0; j < n; ++j) {
+        double s = L[(size_t)j * n + j];
+        for (int32_t k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(s > 0)) fail(EQS_ERR_INVALID_ARG, "coarsest AMG matrix is not positive definite");
+        const double ljj = std::sqrt(s);
+        L[(size_t)j * n + j] = ljj;
+        for (int32_t i = j + 1; i < n; ++i) {
+            double t = L[(size_t)i * n + j];
+            for (int32_t k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    std::vector<double> inv((size_t)n * n, 0.0), col(n);
+    for (int32_t c = 0; c < n; ++c) {
+        // solve L y = e_c, then L^T x = y
+        for (int32_t i = 0; i < n; ++i) {
+            double t = (i == c) ? 1.0 : 0.0;
+            for (int32_t k = 0; k < i; ++k) t -= L[(size_t)i * n + k] * col[k];
+            col[i] = t / L[(size_t)i * n + i];
+        }
+        for (int32_t i = n - 1; i >= 0; --i) {
+            double t = col[i];
+            for (int32_t k = i + 1; k < n; ++k) t -= L[(size_t)k * n + i] * col[k];
+            col[i] = t / L[(size_t)i * n + i];
+        }
+        for (int32_t i = 0; i < n; ++i) inv[(size_t)c * n + i] = col[i];
+    }
+    return inv;
+}
+
+AmgHost build_sa_amg(const Csr<double>& M, const eqs_amg_params& p) {
+    AmgHost h;
+    Csr<double> A = M;
+    for (;;) {
+        const int32_t n = A.n_rows;
+        const bool last = n <= p.coarse_max || (int32_t)h.A.size() + 1 >= p.max_levels;
+        std::vector<double> d = diagonal(A);
+        for (int32_t i = 0; i < n; ++i)
+            if (!(d[i] > 0)) fail(EQS_ERR_INVALID_ARG, "matrix has a non-positive diagonal entry");
+        if (last) {
+            if (n > 4096) fail(EQS_ERR_INVALID_ARG, "AMG coarsening stalled above 4096 unknowns");
+            h.coarse_inv = dense_spd_inverse(A);
+            h.omega.push_back(0.0);
+            h.A.push_back(std::move(A));
+            break;
+        }
+        const double rho = spectral_radius_DinvA(A, d);
+        std::vector<int32_t> agg;
+        // strength threshold halves from level to level (Vanek, Mandel, Brezina 1996)
+        const double theta_l = p.theta * std::ldexp(1.0, -(int)h.A.size());
+        const int32_t nc = aggregate(A, d, theta_l, agg);
+        if (nc >= n) fail(EQS_ERR_INVALID_ARG, "AMG aggregation did not coarsen");
+
+        // tentative prolongator: column per aggregate, normalised
+        std::vector<int32_t> size(nc, 0);
+        for (int32_t i = 0; i < n; ++i) size[agg[i]]++;
+        std::vector<double> w(nc);
+        for (int32_t a = 0; a < nc; ++a) w[a] = 1.0 / std::sqrt((double)size[a]);
+
+        // P = P_tent - (smooth_weight / rho) D^{-1} A P_tent
+        const double sw = p.smooth_weight / rho;
+        Csr<double> P;
+        P.n_rows = n;
+        P.n_cols = nc;
+        P.ptr.assign(n + 1, 0);
+        std::vector<int32_t> cols;
+        std::vector<double> acc(nc, 0.0);
+        std::vector<int32_t> mark(nc, -1);
+        for (int32_t i = 0; i < n; ++i) {
+            cols.clear();
+            auto add = [&](int32_t a, double v) {
+                if (mark[a] != i) { mark[a] = i; acc[a] = 0.0; cols.push_back(a); }
+                acc[a] += v;
+            };
+            add(agg[i], w[agg[i]]);
+            for (int32_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                int32_t j = A.col[k];
+                add(agg[j], -sw * A.val[k] / d[i] * w[agg[j]]);
+            }
+            std::sort(cols.begin(), cols.end());
+            for (int32_t a : cols) {
+                P.col.push_back(a);
+                P.val.push_back(acc[a]);
+            }
+            P.ptr[i + 1] = (int32_t)P.col.size();
+        }
+        Csr<double> R = transpose(P);
+        Csr<double> AP = spgemm(A, P);
+        Csr<double> Ac = spgemm(R, AP);
+        h.omega.push_back(p.jacobi_weight / rho);
+        h.A.push_back(std::move(A));
+        h.P.push_back(std::move(P));
+        h.R.push_back(std::move(R));
+        A = std::move(Ac);
+    }
+    return h;
+}
+
+// ---------------------------------------------------------------- RKC(s)
+// Coefficients of the s-stage second-order RKC method (ref. [9]: Sommeijer,
+// Shampine, Verwer), damping 2/13. Index j = 0..s; mu, nu, mut (mu~), gmt
+// (gamma~) are used for j >= 2 (mut also for j = 1); c are the stage times.
+void rkc_coefficients(int s, std::vector<double>& mu, std::vector<double>& nu, std::vector<double>& mut,
+                      std::vector<double>& gmt, std::vector<double>& c) {
+    const double w0 = 1.0 + (2.0 / 13.0) / ((double)s * s);
+    std::vector<double> T(s + 1), T1(s + 1), T2(s + 1);  // Chebyshev T_j and derivatives at w0
+    T[0] = 1.0; T1[0] = 0.0; T2[0] = 0.0;
+    T[1] = w0;  T1[1] = 1.0; T2[1] = 0.0;
+    for (int j = 2; j <= s; ++j) {
+        T[j] = 2.0 * w0 * T[j - 1] - T[j - 2];
+        T1[j] = 2.0 * T[j - 1] + 2.0 * w0 * T1[j - 1] - T1[j - 2];
+        T2[j] = 4.0 * T1[j - 1] + 2.0 * w0 * T2[j - 1] - T2[j - 2];
+    }
+    const double w1 = T1[s] / T2[s];
+    std::vector<double> b(s + 1), a(s + 1);
+    for (int j = 2; j <= s; ++j) b[j] = T2[j] / (T1[j] * T1[j]);
+    b[0] = b[1] = b[2];
+    for (int j = 0; j <= s; ++j) a[j] = 1.0 - b[j] * T[j];
+    mu.assign(s + 1, 0.0); nu.assign(s + 1, 0.0); mut.assign(s + 1, 0.0); gmt.assign(s + 1, 0.0); c.assign(s + 1, 0.0);
+    mut[1] = b[1] * w1;
+    c[1] = mut[1];
+    for (int j = 2; j <= s; ++j) {
+        mu[j] = 2.0 * b[j] * w0 / b[j - 1];
+        nu[j] = -b[j] / b[j - 2];
+        mut[j] = 2.0 * b[j] * w1 / b[j - 1];
+        gmt[j] = -a[j - 1] * mut[j];
+        c[j] = w1 * T2[j] / T1[j];
+    }
+}
+
+// ------------------------------------------------------------------ upload
+void* dev_alloc(eqs_ctx* c, size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) fail(EQS_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+    c->allocations.push_back(p);
+    c->device_bytes += (int64_t)bytes;
+    return p;
+}
+
+template <typename T>
+static T* upload_vec(eqs_ctx* c, const std::vector<T>& v) {
+    T* d = (T*)dev_alloc(c, v.size() * sizeof(T));
+    if (!v.empty()) EQS_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+
+template <typename T>
+Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A) {
+    Sell<T> S;
+    S.n_rows = A.n_rows;
+    S.n_cols = A.n_cols;
+    S.n_slices = (A.n_rows + kSlice - 1) / kSlice;
+    std::vector<int32_t> sptr(S.n_slices + 1, 0);
+    for (int32_t s = 0; s < S.n_slices; ++s) {
+        int32_t w = 0;
+        for (int32_t r = s * kSlice; r < std::min(A.n_rows, (s + 1) * kSlice); ++r)
+            w = std::max(w, A.ptr[r + 1] - A.ptr[r]);
+        int64_t next = (int64_t)sptr[s] + (int64_t)w * kSlice;
+        if (next > INT32_MAX) fail(EQS_ERR_INVALID_ARG, "matrix too large for SELL offsets");
+        sptr[s + 1] = (int32_t)next;
+    }
+    S.stored = sptr[S.n_slices];
+    std::vector<int32_t> col(S.stored, 0);
+    std::vector<T> val(S.stored, T(0));
+    for (int32_t s = 0; s < S.n_slices; ++s) {
+        const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
+        for (int32_t l = 0; l < kSlice; ++l) {
+            const int32_t r = s * kSlice + l;
+            int32_t pad_col = 0;
+            int32_t len = 0;
+            if (r < A.n_rows) {
+                len = A.ptr[r + 1] - A.ptr[r];
+                for (int32_t k = 0; k < len; ++k) {
+                    col[sptr[s] + (int64_t)k * kSlice + l] = A.col[A.ptr[r] + k];
+                    val[sptr[s] + (int64_t)k * kSlice + l] = (T)A.val[A.ptr[r] + k];
+                }
+                if (len > 0) pad_col = A.col[A.ptr[r] + len - 1];
+            }
+            for (int32_t k = len; k < w; ++k) col[sptr[s] + (int64_t)k * kSlice + l] = pad_col;
+        }
+    }
+    S.sptr = upload_vec(c, sptr);
+    S.col = upload_vec(c, col);
+    S.val = upload_vec(c, val);
+    return S;
+}
+
+template Sell<double> to_sell<double>(eqs_ctx*, const Csr<double>&);
+template Sell<float> to_sell<float>(eqs_ctx*, const Csr<double>&);
+
+template <typename T>
+static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, const double* level0_M_vals_hint) {
+    (void)level0_M_vals_hint;
+    const size_t L = ah.A.size();
+    h.lv.resize(L);
+    for (size_t l = 0; l < L; ++l) {
+        Level<T>& lv = h.lv[l];
+        lv.n = ah.A[l].n_rows;
+        lv.A = to_sell<T>(c, ah.A[l]);
+        std::vector<double> d = diagonal(ah.A[l]);
+        std::vector<T> dinv(lv.n);
+        for (int32_t i = 0; i < lv.n; ++i) dinv[i] = (T)(1.0 / d[i]);
+        lv.dinv = upload_vec(c, dinv);
+        lv.omega = ah.omega[l];
+        lv.b = (T*)dev_alloc(c, sizeof(T) * lv.n);
+        lv.x = (T*)dev_alloc(c, sizeof(T) * lv.n);
+        lv.xs = (T*)dev_alloc(c, sizeof(T) * lv.n);
+        lv.res = (T*)dev_alloc(c, sizeof(T) * lv.n);
+        if (l + 1 < L) {
+            lv.P = to_sell<T>(c, ah.P[l]);
+            lv.R = to_sell<T>(c, ah.R[l]);
+        } else {
+            std::vector<T> inv(ah.coarse_inv.size());
+            for (size_t k = 0; k < inv.size(); ++k) inv[k] = (T)ah.coarse_inv[k];
+            lv.dense_inv = upload_vec(c, inv);
+        }
+    }
+}
+
+void upload(eqs_ctx* c) {
+    const int64_t N = c->n_nodes, T = c->n_tets, NF = c->n_free;
+    std::vector<int32_t> u2i(N);
+    for (int64_t i = 0; i < N; ++i) u2i[c->int_to_user[i]] = (int32_t)i;
+
+    std::vector<int4> conn(T);
+    for (int64_t e = 0; e < T; ++e) {
+        const int32_t* v = &c->tets[4 * e];
+        conn[e] = make_int4(u2i[v[0]], u2i[v[1]], u2i[v[2]], u2i[v[3]]);
+    }
+    std::vector<uint16_t> tm(T);
+    for (int64_t e = 0; e < T; ++e) tm[e] = (uint16_t)c->tet_mat[e];
+    std::vector<double4> xyz(N);
+    for (int64_t i = 0; i < N; ++i) {
+        const double* p = &c->xyz[3 * (int64_t)c->int_to_user[i]];
+        xyz[i] = make_double4(p[0], p[1], p[2], 0.0);
+    }
+    std::vector<MatDev> md(c->mats.size());
+    for (size_t m = 0; m < c->mats.size(); ++m) {
+        const eqs_material& s = c->mats[m];
+        md[m].eps = kEps0 * s.eps_r;
+        md[m].kappa0 = s.kappa0;
+        md[m].inv_es = s.nonlinear ? 1.0 / s.e_s : 0.0;
+        md[m].alpha = s.alpha;
+        md[m].nonlinear = s.nonlinear ? 1 : 0;
+        md[m].ialpha = (s.alpha == std::floor(s.alpha) && s.alpha >= 0 && s.alpha <= 64) ? (int32_t)s.alpha : -1;
+    }
+    std::vector<int32_t> dd(c->n_dir);
+    {
+        std::vector<int32_t> drive_of(N, -1);
+        for (size_t k = 0; k < c->dir_nodes.size(); ++k) drive_of[c->dir_nodes[k]] = c->dir_drive[k];
+        for (int64_t k = 0; k < c->n_dir; ++k) dd[k] = drive_of[c->int_to_user[NF + k]];
+    }
+    c->d_conn = upload_vec(c, conn);
+    c->d_tmat = upload_vec(c, tm);
+    c->d_xyz = upload_vec(c, xyz);
+    c->d_mats = upload_vec(c, md);
+    c->d_ddrive = upload_vec(c, dd);
+    c->d_int_to_user = upload_vec(c, c->int_to_user);
+
+    Csr<double> M = assemble_M_free(c);
+    c->nnz_M = M.nnz();
+    c->M = to_sell<double>(c, M);
+    AmgHost ah = build_sa_amg(M, c->amg);
+    if (c->amg.precision == EQS_PREC_FP32) upload_hierarchy<float>(c, ah, c->h32, nullptr);
+    else upload_hierarchy<double>(c, ah, c->h64, nullptr);
+
+    auto vec = [&](int64_t n) { return (double*)dev_alloc(c, sizeof(double) * (size_t)n); };
+    c->d_r = vec(NF); c->d_z = vec(NF); c->d_p = vec(NF); c->d_q = vec(NF);
+    c->d_Y0 = vec(NF); c->d_Ya = vec(NF); c->d_Yb = vec(NF); c->d_F0 = vec(NF); c->d_F = vec(NF);
+    c->d_rhs = vec(NF); c->d_tmpN = vec(N); c->d_tmpN2 = vec(N);
+    c->max_blocks = (std::max<int64_t>(N, T) + kBlock - 1) / kBlock + 1;
+    c->d_partials = vec(4 * c->max_blocks);
+    c->d_scal = (PcgScalars*)dev_alloc(c, sizeof(PcgScalars));
+    EQS_HIP(hipHostMalloc((void**)&c->h_scal, 2 * sizeof(PcgScalars), hipHostMallocMapped));
+    EQS_HIP(hipHostGetDevicePointer((void**)&c->d_hscal, c->h_scal, 0));
+    EQS_HIP(hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming));
+    EQS_HIP(hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming));
+    c->have_Flast = false;
+}
+
+void free_device(eqs_ctx* c) {
+    for (void* p : c->allocations) (void)hipFree(p);
+    c->allocations.clear();
+    c->device_bytes = 0;
+    if (c->h_scal) { (void)hipHostFree(c->h_scal); c->h_scal = nullptr; c->d_hscal = nullptr; }
+    for (auto& e : c->ev)
+        if (e) { (void)hipEventDestroy(e); e = nullptr; }
+    c->M = Sell<double>{};
+    c->h64.lv.clear();
+    c->h32.lv.clear();
+    c->d_conn = nullptr; c->d_tmat = nullptr; c->d_xyz = nullptr; c->d_mats = nullptr;
+    c->d_ddrive = nullptr; c->d_int_to_user = nullptr;
+    c->d_r = c->d_z = c->d_p = c->d_q = nullptr;
+    c->d_Y0 = c->d_Ya = c->d_Yb = c->d_F0 = c->d_F = nullptr;
+    c->d_rhs = c->d_tmpN = c->d_tmpN2 = nullptr;
+    c->d_partials = nullptr;
+    c->d_scal = nullptr;
+    c->built = false;
+    c->have_Flast = false;
+}
+
+DriveVals drive_values(const eqs_ctx* c, double t) {
+    DriveVals dv{};
+    for (size_t k = 0; k < c->drives.size(); ++k) {
+        const eqs_drive& d = c->drives[k];
+        const double w = 2.0 * M_PI * d.freq;
+        dv.g[k] = d.amp * std::sin(w * t + d.phase);
+        dv.gd[k] = w * d.amp * std::cos(w * t + d.phase);
+    }
+    return dv;
+}
+
+}  // namespace eqs

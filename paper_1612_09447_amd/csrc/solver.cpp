@@ -1,0 +1,151 @@
+// Host drivers of the hot path: AMG-preconditioned CG on the constant M
+// (Sec. II and Sec. V of the paper; the preconditioner is built once), and
+// the RKC step (Sec. II, ref. [9]) whose every stage is one fused element
+// pass (Sec. III) plus one M-solve.
+//
+// CG keeps all scalars on the device. The host enqueues iteration k+1 before
+// it waits for iteration k, and reads only a "done" flag that the
+// convergence finaliser writes to pinned host memory, so the GPU never idles
+// between iterations; once done, further kernels exit at entry.
+#include <algorithm>
+#include <cmath>
+
+#include "eqs_internal.h"
+
+namespace eqs {
+
+static PcgScalars read_scalars(eqs_ctx* c) {
+    const volatile PcgScalars* h = c->h_scal;
+    PcgScalars v;
+    v.bb = h->bb; v.rr = h->rr; v.rho = h->rho; v.rho_old = h->rho_old; v.beta = h->beta; v.alpha = h->alpha;
+    v.tol2 = h->tol2; v.relres = h->relres; v.it = h->it; v.maxit = h->maxit; v.done = h->done;
+    v.status = h->status; v.fresh = h->fresh; v.flexible = h->flexible;
+    return v;
+}
+
+static void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(EQS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st) {
+    hipStream_t s = c->stream;
+    const int prec = c->amg.precision;
+    pcg_init(s, c, rhs, y, maxit, rtol, c->amg.flexible);
+    check_launch();
+    EQS_HIP(hipStreamSynchronize(s));
+    PcgScalars v = read_scalars(c);
+    if (v.bb == 0.0) {
+        launch_fill(s, y, 0.0, c->n_free);
+        EQS_HIP(hipStreamSynchronize(s));
+        if (st) *st = eqs_solve_stats{0, EQS_OK, 0.0};
+        return EQS_OK;
+    }
+    int restarts = 0;
+    while (!v.done) {
+        // iterate until the device reports done, keeping one iteration queued ahead
+        for (int64_t k = 0;; ++k) {
+            pcg_iteration(s, c, rhs, y, prec);
+            EQS_HIP(hipEventRecord(c->ev[k & 1], s));
+            if (k >= 1) {
+                EQS_HIP(hipEventSynchronize(c->ev[(k - 1) & 1]));
+                if (((volatile PcgScalars*)c->h_scal)->done) break;
+            }
+            if (k > (int64_t)maxit + 2) break;  // the device stops itself at maxit
+        }
+        check_launch();
+        EQS_HIP(hipStreamSynchronize(s));
+        v = read_scalars(c);
+        if (v.status == EQS_ERR_BREAKDOWN) break;
+        // converged on the recursive residual (or out of iterations): check the
+        // true residual; if it disagrees, CG restarts from it
+        pcg_true_residual(s, c, rhs, y);
+        check_launch();
+        EQS_HIP(hipStreamSynchronize(s));
+        v = read_scalars(c);
+        if (++restarts > 4 && !v.done) {
+            v.status = EQS_ERR_NOT_CONVERGED;
+            break;
+        }
+    }
+    if (v.status == EQS_ERR_BREAKDOWN) {
+        const int it = v.it;
+        pcg_true_residual(s, c, rhs, y);
+        EQS_HIP(hipStreamSynchronize(s));
+        v = read_scalars(c);
+        v.it = it;
+        v.status = EQS_ERR_BREAKDOWN;
+    }
+    if (st) *st = eqs_solve_stats{v.it, v.status, v.relres};
+    return v.status;
+}
+
+void apply_preconditioner(eqs_ctx* c, const double* r, double* z) {
+    if (c->amg.precision == EQS_PREC_FP32) vcycle<float>(c->stream, c, c->h32, r, z, nullptr, nullptr);
+    else vcycle<double>(c->stream, c, c->h64, r, z, nullptr, nullptr);
+    check_launch();
+    EQS_HIP(hipStreamSynchronize(c->stream));
+}
+
+int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double rtol, int32_t maxit,
+             eqs_step_stats* st) {
+    std::vector<double> mu, nu, mut, gmt, cc;
+    rkc_coefficients(s, mu, nu, mut, gmt, cc);
+    hipStream_t q = c->stream;
+    const int64_t NF = c->n_free;
+
+    launch_gather(q, x_user, c->d_int_to_user, c->d_Y0, NF);
+    if (!c->have_Flast) launch_fill(q, c->d_F, 0.0, NF);
+
+    eqs_step_stats S{};
+    S.stages = s;
+    S.min_iters = INT32_MAX;
+    int rc = EQS_OK;
+    const double* Ycur = c->d_Y0;
+    const double* Yprev = c->d_Y0;
+    for (int j = 0; j < s; ++j) {
+        const double tj = t + cc[j] * dt;
+        launch_kx(q, true, c, Ycur, drive_values(c, tj), c->d_rhs);
+        check_launch();
+        // F_j = M^{-1} r_j, started from F_{j-1} (held in d_F)
+        eqs_solve_stats ss{};
+        const int src = solve_M(c, c->d_rhs, c->d_F, rtol, maxit, &ss);
+        S.total_iters += ss.iters;
+        S.max_iters = std::max(S.max_iters, ss.iters);
+        S.min_iters = std::min(S.min_iters, ss.iters);
+        S.max_relres = std::max(S.max_relres, ss.relres);
+        if (src == EQS_ERR_NOT_CONVERGED) {
+            S.not_converged++;
+            rc = EQS_ERR_NOT_CONVERGED;
+        } else if (src != EQS_OK) {
+            if (st) *st = S;
+            c->have_Flast = false;
+            return src;
+        }
+        if (j == 0) launch_copy(q, c->d_F0, c->d_F, NF);
+        double* out;
+        prof_begin(c, EQS_KCLASS_RKC_COMBINE, q);
+        if (j == 0) {
+            out = c->d_Ya;
+            launch_rkc_first(q, out, c->d_Y0, c->d_F0, mut[1] * dt, NF);
+        } else {
+            out = (Ycur == c->d_Ya) ? c->d_Yb : c->d_Ya;  // for j >= 2 this buffer holds Y_{j-1}
+            const int k = j + 1;
+            launch_rkc_combine(q, out, c->d_Y0, Ycur, Yprev, c->d_F, c->d_F0, 1.0 - mu[k] - nu[k], mu[k], nu[k],
+                               mut[k] * dt, gmt[k] * dt, NF);
+        }
+        prof_end(c, EQS_KCLASS_RKC_COMBINE, q);
+        check_launch();
+        Yprev = Ycur;
+        Ycur = out;
+    }
+    launch_finish_state(q, Ycur, c->d_int_to_user, c->d_ddrive, drive_values(c, t + dt), x_user, NF, c->n_nodes);
+    check_launch();
+    EQS_HIP(hipStreamSynchronize(q));
+    c->have_Flast = true;
+    if (S.min_iters == INT32_MAX) S.min_iters = 0;
+    if (st) *st = S;
+    return rc;
+}
+
+}  // namespace eqs

@@ -1,0 +1,109 @@
+"""The C ABI without a GPU: symbols, struct layouts, error paths (CPU only)."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1612_09447_amd as pkg
+from paper_1612_09447_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eqs.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(eqs_[a-zA-Z_0-9]+)\s*\(", src)))
+
+
+def test_library_is_built():
+    assert os.path.exists(binding.LIB_PATH), "run __graft_entry__.build() first"
+
+
+def test_every_declared_symbol_is_exported():
+    names = header_functions()
+    assert len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r"\bT (eqs_\w+)", out.stdout))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    # and the binding declares a signature for each of them
+    assert set(names) == set(binding._SIGNATURES)
+    L = pkg.lib()
+    for n in names:
+        assert getattr(L, n) is not None
+
+
+STRUCTS = {
+    "eqs_material": ["eps_r", "kappa0", "e_s", "alpha", "nonlinear", "reserved"],
+    "eqs_drive": ["amp", "freq", "phase"],
+    "eqs_amg_params": ["precision", "coarse_max", "max_levels", "flexible", "theta", "jacobi_weight",
+                       "smooth_weight"],
+    "eqs_solve_stats": ["iters", "status", "relres"],
+    "eqs_step_stats": ["stages", "total_iters", "max_iters", "min_iters", "not_converged", "reserved",
+                       "max_relres"],
+    "eqs_info": ["n_nodes", "n_tets", "n_free", "nnz_M", "n_levels", "precision", "level_rows", "level_nnz",
+                 "device_bytes"],
+}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    prog = ['#include <stdio.h>', '#include <stddef.h>', '#include "eqs.h"', "int main(void){"]
+    for s, fields in STRUCTS.items():
+        prog.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for f in fields:
+            prog.append(f'printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    prog.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(prog))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    for s, fields in STRUCTS.items():
+        cls = getattr(binding, s)
+        assert int(out[s]) == C.sizeof(cls), s
+        for f in fields:
+            assert int(out[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
+
+
+def test_constants_match_header():
+    src = open(HEADER).read()
+    for name in ["EQS_OK", "EQS_ERR_INVALID_ARG", "EQS_ERR_STATE", "EQS_ERR_HIP", "EQS_ERR_NOT_CONVERGED",
+                 "EQS_ERR_BREAKDOWN", "EQS_ERR_NONFINITE", "EQS_ERR_ALLOC", "EQS_MAX_DRIVES"]:
+        m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, src)
+        assert m and int(m.group(1)) == getattr(binding, name), name
+
+
+def _no_gpu():
+    try:
+        import torch
+
+        return not torch.cuda.is_available()
+    except Exception:
+        return True
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="checks the no-device error path")
+def test_error_paths_without_device():
+    L = pkg.lib()
+    h = C.c_void_p()
+    assert L.eqs_create(C.byref(h), 0, None) == binding.EQS_ERR_HIP
+    assert L.eqs_last_error()  # a message is recorded
+    assert L.eqs_create(None, 0, None) == binding.EQS_ERR_INVALID_ARG
+    assert b"NULL" in L.eqs_last_error()
+    assert L.eqs_destroy(None) == binding.EQS_OK
+    assert L.eqs_last_error() == b""
+    with pytest.raises(pkg.EqsError) as ei:
+        pkg.Context(0)
+    assert ei.value.code == binding.EQS_ERR_HIP
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", "/nonexistent/libeqs.so")
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        binding.lib()

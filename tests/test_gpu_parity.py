@@ -1,0 +1,263 @@
+"""GPU parity: every entry point of the C ABI against the FP64 CPU oracle.
+
+Sizes are small enough for the oracle's dense solves (several SELL slices and
+256-thread blocks, ragged tails), plus the workload shapes of the slab (c0)
+and inclusion (c1/c2) recipes. Tolerances (floating point, FP64 path):
+  * element pass and SpMV: |gpu - oracle|_inf <= 1e-12 |oracle|_inf (rounding
+    order of the atomics and of the two element formulas);
+  * trajectories: max_n |x_n - x_n^ref| / max_n |x_n^ref| <= 1e-9 with CG at
+    rel-res 1e-12 (plain FP64) and <= 1e-8 with the FP32 preconditioner.
+"""
+
+import numpy as np
+import pytest
+
+import eqsgen
+from oracle import fem
+from oracle.eqs import EqsOracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1612_09447_amd import (  # noqa: E402
+    EQS_ERR_INVALID_ARG,
+    EQS_ERR_NOT_CONVERGED,
+    EQS_ERR_STATE,
+    EQS_PREC_FP32,
+    EQS_PREC_FP64,
+    Context,
+    EqsError,
+)
+
+DEV = torch.device("cuda:0")
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def ctx_for(case, precision=None, **amg):
+    c = Context(0, torch.cuda.current_stream(DEV))
+    c.setup_case(case, precision=precision, **amg)
+    return c
+
+
+def inclusion_case(n, seed=1):
+    c = eqsgen.case_c1(n=n, seed=seed)
+    return c
+
+
+def relinf(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ------------------------------------------------------------ element pass
+@pytest.mark.parametrize("maker", [lambda: eqsgen.case_c0(8), lambda: inclusion_case(12), lambda: inclusion_case(7, 3)])
+def test_apply_K_matches_oracle(maker):
+    case = maker()
+    print(f"[apply_K] case {case.name} n={case.n} tets={case.n_tets}", flush=True)
+    with ctx_for(case) as c:
+        for seed, scale in [(1, 0.05), (2, 1.0), (3, 4.0)]:
+            x = eqsgen.random_state(case.n_nodes, seed, scale)
+            t = 0.0031 * seed
+            y = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+            c.apply_K(t, T(x), y)
+            o = EqsOracle(case)
+            xbar = o.embed(x[o.free], t)
+            ref = fem.apply_K(case, xbar)
+            assert relinf(N(y), ref) <= 1e-12, (seed, relinf(N(y), ref))
+
+
+def test_apply_K_relies_on_connectivity_only():
+    case = inclusion_case(9, 5)
+    x = eqsgen.random_state(case.n_nodes, 7, 2.0)
+    xyz2, tets2, dn2, perm = eqsgen.permute_nodes(case.xyz, case.tets, case.dir_nodes, seed=11)
+    case2 = eqsgen.make_case("c1", n=9, seed=5)
+    case2.xyz, case2.tets, case2.dir_nodes = xyz2, tets2, dn2
+    case2.tets, case2.tet_mat, _ = eqsgen.shuffle_tets(case2.tets, case2.tet_mat, seed=12)
+    x2 = np.empty_like(x)
+    x2[perm] = x
+    with ctx_for(case) as c1, ctx_for(case2) as c2:
+        y1 = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+        y2 = torch.zeros_like(y1)
+        c1.apply_K(0.002, T(x), y1)
+        c2.apply_K(0.002, T(x2), y2)
+        assert relinf(N(y2)[perm], N(y1)) <= 1e-12
+
+
+def test_stage_rhs_matches_oracle():
+    case = inclusion_case(12)
+    o = EqsOracle(case)
+    with ctx_for(case) as c:
+        for t in [0.0, 0.0013, 0.0047]:
+            Y = eqsgen.random_state(case.n_nodes, 4, 0.7)[o.free]
+            r = torch.zeros(o.n_free, dtype=torch.float64, device=DEV)
+            c.stage_rhs(t, T(Y), r)
+            ref = o.stage_rhs(t, Y)
+            assert relinf(N(r), ref) <= 1e-12, t
+
+
+def test_apply_M_matches_oracle():
+    case = inclusion_case(13, 2)
+    o = EqsOracle(case)
+    with ctx_for(case) as c:
+        info = c.info()
+        assert info["n_free"] == o.n_free and info["nnz_M"] == o.M_II.nnz
+        x = np.random.default_rng(0).normal(size=o.n_free)
+        y = torch.zeros(o.n_free, dtype=torch.float64, device=DEV)
+        c.apply_M(T(x), y)
+        assert relinf(N(y), o.M_II @ x) <= 1e-13
+
+
+# ---------------------------------------------------------- preconditioner
+@pytest.mark.parametrize("prec,tol", [(EQS_PREC_FP64, 1e-12), (EQS_PREC_FP32, 2e-5)])
+def test_preconditioner_symmetric_positive(prec, tol):
+    case = inclusion_case(14, 4)
+    with ctx_for(case, precision=prec) as c:
+        info = c.info()
+        assert info["n_levels"] >= 2, info
+        n = info["n_free"]
+        rng = np.random.default_rng(1)
+        X, Y = rng.normal(size=n), rng.normal(size=n)
+        bx = torch.zeros(n, dtype=torch.float64, device=DEV)
+        by = torch.zeros_like(bx)
+        c.apply_preconditioner(T(X), bx)
+        c.apply_preconditioner(T(Y), by)
+        bx, by = N(bx), N(by)
+        assert abs(bx @ Y - X @ by) <= tol * np.linalg.norm(bx) * np.linalg.norm(Y)
+        assert bx @ X > 0 and by @ Y > 0
+        # V-cycle is a contraction in the energy norm: I - B M has spectral radius < 1
+        o = EqsOracle(case)
+        e = rng.normal(size=n)
+        for _ in range(3):
+            be = torch.zeros(n, dtype=torch.float64, device=DEV)
+            c.apply_preconditioner(T(o.M_II @ e), be)
+            e_new = e - N(be)
+            ratio = np.sqrt(e_new @ (o.M_II @ e_new)) / np.sqrt(e @ (o.M_II @ e))
+            assert ratio < 0.9, ratio
+            e = e_new
+
+
+# ------------------------------------------------------------------ solve
+@pytest.mark.parametrize("prec", [EQS_PREC_FP64, EQS_PREC_FP32])
+def test_solve_M_matches_dense(prec):
+    case = inclusion_case(12, 6)
+    o = EqsOracle(case)
+    rng = np.random.default_rng(3)
+    rhs = rng.normal(size=o.n_free)
+    ref = o.solve(rhs)
+    with ctx_for(case, precision=prec) as c:
+        y = torch.zeros(o.n_free, dtype=torch.float64, device=DEV)
+        st = c.solve_M(T(rhs), y, rtol=1e-11, maxit=300)
+        print(f"[solve_M] prec={prec} iters={st['iters']} relres={st['relres']:.2e}", flush=True)
+        got = N(y)
+        true_rr = np.linalg.norm(rhs - o.M_II @ got) / np.linalg.norm(rhs)
+        assert st["relres"] <= 1e-11 and true_rr <= 1.5e-11
+        assert abs(st["relres"] - true_rr) <= 1e-12
+        assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(ref)
+        assert st["iters"] < 60
+
+
+def test_solve_M_edge_cases():
+    case = inclusion_case(10, 2)
+    o = EqsOracle(case)
+    rng = np.random.default_rng(4)
+    with ctx_for(case) as c:
+        n = o.n_free
+        # exact start vector: no iterations (Sec. IV: an accurate start vector needs none)
+        rhs = rng.normal(size=n)
+        y = T(o.solve(rhs))
+        st = c.solve_M(T(rhs), y, rtol=1e-10)
+        assert st["iters"] == 0
+        # zero right-hand side: zero solution whatever the start
+        y = T(rng.normal(size=n))
+        st = c.solve_M(T(np.zeros(n)), y, rtol=1e-10)
+        assert st["iters"] == 0 and not N(y).any()
+        # iteration limit is reported, results still written
+        y = torch.zeros(n, dtype=torch.float64, device=DEV)
+        st = c.solve_M(T(rhs), y, rtol=1e-14, maxit=2, allow_not_converged=True)
+        assert st["rc"] == EQS_ERR_NOT_CONVERGED and st["iters"] == 2 and st["relres"] < 1
+        # a garbage start (scaled by 1e30) still converges
+        y = T(1e30 * rng.normal(size=n))
+        st = c.solve_M(T(rhs), y, rtol=1e-10, maxit=400)
+        assert np.linalg.norm(rhs - o.M_II @ N(y)) <= 2e-10 * np.linalg.norm(rhs)
+
+
+def test_call_order_and_argument_errors():
+    case = inclusion_case(5, 2)
+    c = Context(0, torch.cuda.current_stream(DEV))
+    x = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+    with pytest.raises(EqsError) as e:
+        c.apply_K(0.0, x, torch.zeros_like(x))
+    assert e.value.code == EQS_ERR_STATE
+    with pytest.raises(EqsError) as e:
+        c.set_materials(case.eps_r, case.kappa0, case.e_s, case.alpha, case.nonlinear, case.tet_mat)
+    assert e.value.code == EQS_ERR_STATE
+    c.set_mesh(case.xyz, case.tets)
+    bad = case.tets.copy()
+    bad[3] = [0, 1, 2, 0]
+    with pytest.raises(EqsError) as e:
+        c.set_mesh(case.xyz, np.where(bad < 0, 0, bad) * 0 + 10 ** 7)
+    assert e.value.code == EQS_ERR_INVALID_ARG
+    c.set_mesh(case.xyz, bad)
+    c.set_materials(case.eps_r, case.kappa0, case.e_s, case.alpha, case.nonlinear, case.tet_mat)
+    c.set_dirichlet(case.dir_nodes, case.dir_drive, case.amp, case.freq, case.phase)
+    with pytest.raises(EqsError) as e:  # flat tet found at build time
+        c.build_preconditioner()
+    assert e.value.code == EQS_ERR_INVALID_ARG and "zero volume" in str(e.value)
+    c.close()
+
+
+# ------------------------------------------------------------ RKC steps
+def trajectory_error(case, steps, rtol, precision=None, **amg):
+    o = EqsOracle(case)
+    ref = o.rkc_trajectory(np.zeros(o.n_free), 0.0, case.tau, case.s, steps)
+    with ctx_for(case, precision=precision, **amg) as c:
+        x = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+        worst, iters = 0.0, []
+        for n in range(steps):
+            st = c.rkc_step(n * case.tau, case.tau, case.s, x, rtol=rtol, maxit=500)
+            iters.append(st["total_iters"] / st["stages"])
+            got = N(x)
+            worst = max(worst, np.linalg.norm(got[o.free] - ref[n + 1]))
+            # Dirichlet entries hold g(t_{n+1})
+            g = o.g((n + 1) * case.tau)
+            assert np.abs(got[o.dir_nodes] - g).max() <= 1e-15 * max(1.0, np.abs(g).max())
+    scale = max(np.linalg.norm(r) for r in ref)
+    return worst / scale, float(np.mean(iters))
+
+
+def test_rkc_c0_full_trajectory_plain_fp64():
+    """c0: n = 8, slab, 200 RKC(8) steps at the recipe tolerance 1e-10."""
+    case = eqsgen.case_c0(8)
+    err, it = trajectory_error(case, case.steps, case.rtol)
+    print(f"[rkc c0] err={err:.3e} mean CG iters/stage={it:.2f}", flush=True)
+    assert err <= 1e-9
+
+
+def test_rkc_strongly_nonlinear_slab():
+    case = eqsgen.case_c0(8)
+    case.amp[1] = 3.2
+    err, it = trajectory_error(case, 60, 1e-12)
+    print(f"[rkc c0 strong] err={err:.3e} iters={it:.2f}", flush=True)
+    assert err <= 1e-9
+
+
+def test_rkc_inclusions_plain_and_mixed():
+    case = inclusion_case(12, 1)
+    case.s = 12
+    err64, it64 = trajectory_error(case, 6, 1e-12, EQS_PREC_FP64)
+    err32, it32 = trajectory_error(case, 6, 1e-10, EQS_PREC_FP32)
+    print(f"[rkc incl] fp64 err={err64:.3e} it={it64:.2f}; fp32-AMG err={err32:.3e} it={it32:.2f}", flush=True)
+    assert err64 <= 1e-9
+    assert err32 <= 1e-8
+
+
+def test_rkc_single_level_hierarchy():
+    case = eqsgen.case_c0(4)  # 75 free nodes: the dense coarse solve is the preconditioner
+    err, it = trajectory_error(case, 5, 1e-12)
+    assert err <= 1e-9 and it <= 2
