@@ -106,7 +106,12 @@ def test_apply_M_matches_oracle():
     o = EqsOracle(case)
     with ctx_for(case) as c:
         info = c.info()
-        assert info["n_free"] == o.n_free and info["nnz_M"] == o.M_II.nnz
+        # the library stores only entries above roundoff (Kuhn tets give exact
+        # zeros on face and body diagonals); the oracle keeps the structural pattern
+        A = o.M_II.tocoo()
+        d = o.M_II.diagonal()
+        keep = (A.row == A.col) | (np.abs(A.data) > 1e-14 * np.sqrt(np.abs(d[A.row] * d[A.col])))
+        assert info["n_free"] == o.n_free and info["nnz_M"] == int(keep.sum())
         x = np.random.default_rng(0).normal(size=o.n_free)
         y = torch.zeros(o.n_free, dtype=torch.float64, device=DEV)
         c.apply_M(T(x), y)
@@ -226,7 +231,8 @@ def trajectory_error(case, steps, rtol, precision=None, **amg):
             worst = max(worst, np.linalg.norm(got[o.free] - ref[n + 1]))
             # Dirichlet entries hold g(t_{n+1})
             g = o.g((n + 1) * case.tau)
-            assert np.abs(got[o.dir_nodes] - g).max() <= 1e-15 * max(1.0, np.abs(g).max())
+            dg = float(np.abs(got[o.dir_nodes] - g).max())
+            assert dg <= 1e-13 * max(1.0, float(np.abs(g).max())), dg  # same sine, rounded in another order
     scale = max(np.linalg.norm(r) for r in ref)
     return worst / scale, float(np.mean(iters))
 
