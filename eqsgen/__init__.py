@@ -21,6 +21,7 @@ from .cases import (
     case_c2,
     case_batch,
     random_state,
+    mlp_init,
     CASE_NAMES,
 )
 
@@ -36,5 +37,6 @@ __all__ = [
     "case_c2",
     "case_batch",
     "random_state",
+    "mlp_init",
     "CASE_NAMES",
 ]

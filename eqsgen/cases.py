@@ -237,3 +237,16 @@ def random_state(n_nodes: int, seed: int, scale: float = 1.0) -> np.ndarray:
     """Seeded random potentials on all nodes, uniform in [-scale, scale]."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-scale, scale, size=n_nodes)
+
+
+def mlp_init(seed: int = 4, layers=(32, 64, 64, 16)):
+    """Seeded Xavier-uniform initial weights (zero biases) of the start-vector
+    network, float32: {W1, b1, W2, b2, W3, b3}, W_l of shape [out, in]."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for l in range(len(layers) - 1):
+        fan_in, fan_out = layers[l], layers[l + 1]
+        bound = np.sqrt(6.0 / (fan_in + fan_out))
+        out[f"W{l + 1}"] = rng.uniform(-bound, bound, size=(fan_out, fan_in)).astype(np.float32)
+        out[f"b{l + 1}"] = np.zeros(fan_out, dtype=np.float32)
+    return out
