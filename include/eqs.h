@@ -104,13 +104,16 @@ typedef struct eqs_solve_stats {
 } eqs_solve_stats;
 
 typedef struct eqs_step_stats {
-    int32_t stages;        /* s */
-    int32_t total_iters;   /* CG iterations summed over the stages */
-    int32_t max_iters;     /* largest per-stage count */
-    int32_t min_iters;     /* smallest per-stage count */
-    int32_t not_converged; /* stages whose solve hit maxit */
+    int32_t stages;          /* s */
+    int32_t total_iters;     /* CG iterations summed over the stages */
+    int32_t max_iters;       /* largest per-stage count */
+    int32_t min_iters;       /* smallest per-stage count */
+    int32_t not_converged;   /* stages whose solve hit maxit */
+    int32_t guess_used;      /* stages whose CG started from the estimator's vector */
+    int32_t guess_fallbacks; /* stages where the guard kept the previous solution instead */
     int32_t reserved;
-    double max_relres;     /* largest per-stage true relative residual */
+    double max_relres;       /* largest per-stage true relative residual */
+    double train_loss;       /* last minibatch loss of the start-vector network (0 if none) */
 } eqs_step_stats;
 
 typedef struct eqs_info {
@@ -198,6 +201,62 @@ int eqs_solve_M(eqs_ctx *ctx, const double *rhs_dev, double *y_dev, double rtol,
  * solve hit maxit (the step is still completed); st may be NULL. */
 int eqs_rkc_step(eqs_ctx *ctx, double t, double dt, int32_t s, double *x_dev, double rtol, int32_t maxit,
                  eqs_step_stats *st);
+
+/* ---- start vectors (Sec. IV) ------------------------------------------
+ * The stage solves of one run form a multiple right-hand-side problem with the
+ * constant M, so earlier solutions predict the next one (Sec. IV). Kinds:
+ *   EQS_GUESS_PREVIOUS  the previous stage's solution (default)
+ *   EQS_GUESS_ZERO      zero
+ *   EQS_GUESS_GALERKIN  eq. (5) on the POD basis V of the last `window` stage
+ *                       solutions: V (V^T M V)^{-1} V^T r (the reduced matrix
+ *                       comes for free because M s_k = r_k for every stored
+ *                       solution s_k)
+ *   EQS_GUESS_MLP       the coefficients on the same basis come from the
+ *                       start-vector network (eqs_mlp below), fed with the
+ *                       POD coefficients of the latest solution and of the
+ *                       stage right-hand side; the network is trained online
+ *                       on the GPU from (features, V^T F_j) pairs of the run.
+ * For GALERKIN and MLP a guard compares |r - M x0| of the candidate with that
+ * of the previous solution and keeps the better one; CG to rtol always follows,
+ * so the start vector never changes the result beyond the solve tolerance. */
+enum { EQS_GUESS_PREVIOUS = 0, EQS_GUESS_ZERO = 1, EQS_GUESS_GALERKIN = 2, EQS_GUESS_MLP = 3 };
+
+#define EQS_MLP_NPARAM 7312 /* W1[64][32] b1[64] W2[64][64] b2[64] W3[16][64] b3[16], float */
+
+typedef struct eqs_guess_params {
+    int32_t kind;      /* EQS_GUESS_* */
+    int32_t window;    /* POD window of stage solutions, 2..16 [16] */
+    int32_t capacity;  /* replay-buffer pairs kept for training, <= 100000 [2000] */
+    int32_t warmup;    /* pairs collected before the network's vector is used [256] */
+    int32_t batch;     /* minibatch per stage, 1..64 [64] */
+    int32_t bf16;      /* 1: BF16 matmul operands, FP32 accumulation; 0: FP32 [1] */
+    int32_t guard;     /* 1: residual guard against the previous solution [1] */
+    int32_t reserved;
+    double lr;         /* Adam learning rate [1e-3] */
+    uint64_t seed;     /* minibatch sampling: SplitMix64 stream from this seed */
+    const float *init; /* EQS_MLP_NPARAM initial parameters (host, copied); required for MLP */
+} eqs_guess_params;
+
+/* Select the start vector of every stage solve of eqs_rkc_step. Resets the
+ * snapshot window, the replay buffer and (for MLP) the network. */
+int eqs_set_guess(eqs_ctx *ctx, const eqs_guess_params *p);
+
+/* ---- the start-vector network on its own ------------------------------
+ * Multilayer perceptron 32 -> 64 -> 64 -> 16, SiLU hidden activations,
+ * linear output, mean-squared-error loss, Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8). One workgroup runs a minibatch (batch <= 64 for training).
+ * Device arrays are row-major float: x[batch][32], y/t[batch][16]. */
+typedef struct eqs_mlp eqs_mlp;
+
+int eqs_mlp_create(eqs_mlp **out, int device, void *hip_stream, const float *params, int32_t bf16, double lr);
+int eqs_mlp_destroy(eqs_mlp *net);
+int eqs_mlp_forward(eqs_mlp *net, const float *x_dev, float *y_dev, int32_t batch);
+/* One training step on the batch: loss, gradients, Adam update. *loss (host,
+ * may be NULL) receives the batch loss before the update. */
+int eqs_mlp_train_step(eqs_mlp *net, const float *x_dev, const float *t_dev, int32_t batch, float *loss);
+/* Copy the FP32 master parameters and/or the last gradients to the host
+ * (either pointer may be NULL; EQS_MLP_NPARAM floats each). */
+int eqs_mlp_get(eqs_mlp *net, float *params_host, float *grad_host);
 
 /* ---- per-kernel timing ------------------------------------------------
  * When enabled, the library records a pair of HIP events on the context's

@@ -9,6 +9,12 @@ and streams.
 from .binding import (  # noqa: F401
     Context,
     EqsError,
+    Mlp,
+    EQS_GUESS_GALERKIN,
+    EQS_GUESS_MLP,
+    EQS_GUESS_PREVIOUS,
+    EQS_GUESS_ZERO,
+    EQS_MLP_NPARAM,
     EQS_OK,
     EQS_ERR_INVALID_ARG,
     EQS_ERR_STATE,

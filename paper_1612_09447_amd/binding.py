@@ -61,8 +61,24 @@ class eqs_solve_stats(C.Structure):
 
 class eqs_step_stats(C.Structure):
     _fields_ = [("stages", C.c_int32), ("total_iters", C.c_int32), ("max_iters", C.c_int32),
-                ("min_iters", C.c_int32), ("not_converged", C.c_int32), ("reserved", C.c_int32),
-                ("max_relres", C.c_double)]
+                ("min_iters", C.c_int32), ("not_converged", C.c_int32), ("guess_used", C.c_int32),
+                ("guess_fallbacks", C.c_int32), ("reserved", C.c_int32), ("max_relres", C.c_double),
+                ("train_loss", C.c_double)]
+
+
+class eqs_guess_params(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("window", C.c_int32), ("capacity", C.c_int32), ("warmup", C.c_int32),
+                ("batch", C.c_int32), ("bf16", C.c_int32), ("guard", C.c_int32), ("reserved", C.c_int32),
+                ("lr", C.c_double), ("seed", C.c_uint64), ("init", C.c_void_p)]
+
+
+EQS_GUESS_PREVIOUS = 0
+EQS_GUESS_ZERO = 1
+EQS_GUESS_GALERKIN = 2
+EQS_GUESS_MLP = 3
+EQS_MLP_NPARAM = 7312
+GUESS_KINDS = {"previous": EQS_GUESS_PREVIOUS, "zero": EQS_GUESS_ZERO, "galerkin": EQS_GUESS_GALERKIN,
+               "mlp": EQS_GUESS_MLP}
 
 
 class eqs_info(C.Structure):
@@ -86,6 +102,12 @@ _SIGNATURES = {
     "eqs_apply_preconditioner": ([_P, _P, _P], C.c_int),
     "eqs_solve_M": ([_P, _P, _P, C.c_double, C.c_int32, _P], C.c_int),
     "eqs_rkc_step": ([_P, C.c_double, C.c_double, C.c_int32, _P, C.c_double, C.c_int32, _P], C.c_int),
+    "eqs_set_guess": ([_P, _P], C.c_int),
+    "eqs_mlp_create": ([C.POINTER(_P), C.c_int, _P, _P, C.c_int32, C.c_double], C.c_int),
+    "eqs_mlp_destroy": ([_P], C.c_int),
+    "eqs_mlp_forward": ([_P, _P, _P, C.c_int32], C.c_int),
+    "eqs_mlp_train_step": ([_P, _P, _P, C.c_int32, C.POINTER(C.c_float)], C.c_int),
+    "eqs_mlp_get": ([_P, _P, _P], C.c_int),
     "eqs_profile_enable": ([_P, C.c_uint32], C.c_int),
     "eqs_profile_read": ([_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
     "eqs_last_error": ([], C.c_char_p),
@@ -140,8 +162,8 @@ def _host(a, dtype):
     return a, a.ctypes.data_as(_P)
 
 
-def _dev(t):
-    """Device address of a torch tensor (float64, contiguous) or an int address."""
+def _dev(t, dtype="float64"):
+    """Device address of a torch tensor (contiguous, given dtype) or an int address."""
     if isinstance(t, int):
         return _P(t)
     import torch
@@ -150,8 +172,8 @@ def _dev(t):
         raise TypeError("expected a torch tensor on the GPU or an integer device address")
     if t.device.type != "cuda":
         raise ValueError("device vectors must live on the GPU")
-    if t.dtype != torch.float64 or not t.is_contiguous():
-        raise ValueError("device vectors must be contiguous float64")
+    if t.dtype != getattr(torch, dtype) or not t.is_contiguous():
+        raise ValueError(f"device vectors must be contiguous {dtype}")
     return _P(t.data_ptr())
 
 
@@ -278,4 +300,78 @@ class Context:
         rc = lib().eqs_rkc_step(self._h, float(t), float(dt), int(s), _dev(x), float(rtol), int(maxit), C.byref(st))
         _check(rc, "eqs_rkc_step", ok)
         return dict(stages=st.stages, total_iters=st.total_iters, max_iters=st.max_iters, min_iters=st.min_iters,
-                    not_converged=st.not_converged, max_relres=st.max_relres, rc=rc)
+                    not_converged=st.not_converged, guess_used=st.guess_used, guess_fallbacks=st.guess_fallbacks,
+                    max_relres=st.max_relres, train_loss=st.train_loss, rc=rc)
+
+    def set_guess(self, kind="previous", init=None, **kw):
+        """Select the stage start vector: previous, zero, galerkin (eq. (5)) or mlp."""
+        p = eqs_guess_params()
+        p.kind = GUESS_KINDS[kind] if isinstance(kind, str) else int(kind)
+        p.bf16 = 1
+        p.guard = 1
+        p.warmup = 256
+        for k, v in kw.items():
+            setattr(p, k, v)
+        keep = None
+        if init is not None:
+            keep = _flat_params(init)
+            p.init = keep.ctypes.data_as(_P)
+        _check(lib().eqs_set_guess(self._h, C.byref(p)), "eqs_set_guess")
+
+
+def _flat_params(params):
+    """Concatenate {W1, b1, W2, b2, W3, b3} (or an already flat array) into float32."""
+    if isinstance(params, dict):
+        arr = np.concatenate([np.asarray(params[k], np.float32).reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+    else:
+        arr = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    if arr.size != EQS_MLP_NPARAM:
+        raise ValueError(f"expected {EQS_MLP_NPARAM} parameters, got {arr.size}")
+    return np.ascontiguousarray(arr)
+
+
+def unflatten_params(flat):
+    flat = np.asarray(flat)
+    out, o = {}, 0
+    for k, shp in (("W1", (64, 32)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (16, 64)), ("b3", (16,))):
+        n = int(np.prod(shp))
+        out[k] = flat[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+class Mlp:
+    """The start-vector network on its own (eqs_mlp_*): forward, train step, parameters."""
+
+    def __init__(self, params, bf16=True, lr=1e-3, device=0, stream=None):
+        self._h = _P()
+        flat = _flat_params(params)
+        _check(lib().eqs_mlp_create(C.byref(self._h), device, _stream_handle(stream), flat.ctypes.data_as(_P),
+                                    1 if bf16 else 0, float(lr)), "eqs_mlp_create")
+
+    def close(self):
+        if self._h:
+            lib().eqs_mlp_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, x, y):
+        _check(lib().eqs_mlp_forward(self._h, _dev(x, "float32"), _dev(y, "float32"), int(x.shape[0])),
+               "eqs_mlp_forward")
+
+    def train_step(self, x, t):
+        loss = C.c_float()
+        _check(lib().eqs_mlp_train_step(self._h, _dev(x, "float32"), _dev(t, "float32"), int(x.shape[0]),
+                                        C.byref(loss)), "eqs_mlp_train_step")
+        return float(loss.value)
+
+    def get(self):
+        p = np.zeros(EQS_MLP_NPARAM, np.float32)
+        g = np.zeros(EQS_MLP_NPARAM, np.float32)
+        _check(lib().eqs_mlp_get(self._h, p.ctypes.data_as(_P), g.ctypes.data_as(_P)), "eqs_mlp_get")
+        return unflatten_params(p), unflatten_params(g)

@@ -83,6 +83,7 @@ int eqs_destroy(eqs_ctx* ctx) {
         else (void)hipDeviceSynchronize();
         eqs::free_device(ctx);
         eqs::prof_release(ctx);
+        eqs::guess_release(ctx);
         delete ctx;
         return EQS_OK;
     });
@@ -301,6 +302,87 @@ int eqs_rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_dev, doub
         need_built(c);
         bind_device(c);
         return result_code(eqs::rkc_step(c, t, dt, s, x_dev, rtol, maxit, st), "eqs_rkc_step");
+    });
+}
+
+int eqs_set_guess(eqs_ctx* c, const eqs_guess_params* p) {
+    return guarded([&] {
+        need(c != nullptr && p != nullptr, "NULL argument");
+        eqs_guess_params a = *p;
+        need(a.kind >= EQS_GUESS_PREVIOUS && a.kind <= EQS_GUESS_MLP, "unknown guess kind");
+        if (a.window == 0) a.window = 16;
+        if (a.capacity == 0) a.capacity = 2000;
+        if (a.batch == 0) a.batch = 64;
+        if (a.lr == 0) a.lr = 1e-3;
+        need(a.window >= 2 && a.window <= 16, "window must be in [2, 16]");
+        need(a.capacity >= 1 && a.capacity <= 100000, "capacity must be in [1, 100000]");
+        need(a.warmup >= 0, "warmup must be >= 0");
+        need(a.batch >= 1 && a.batch <= 64, "batch must be in [1, 64]");
+        need(std::isfinite(a.lr) && a.lr > 0, "lr must be > 0");
+        bind_device(c);
+        c->guess.init.clear();
+        if (a.kind == EQS_GUESS_MLP) {
+            need(a.init != nullptr, "the MLP guess needs initial parameters");
+            for (int i = 0; i < EQS_MLP_NPARAM; ++i)
+                if (!std::isfinite(a.init[i])) fail(EQS_ERR_NONFINITE, "non-finite network parameter");
+            c->guess.init.assign(a.init, a.init + EQS_MLP_NPARAM);
+        }
+        a.init = nullptr;
+        eqs::guess_configure(c, a);
+        return EQS_OK;
+    });
+}
+
+int eqs_mlp_create(eqs_mlp** out, int device, void* hip_stream, const float* params, int32_t bf16, double lr) {
+    return guarded([&] {
+        need(out != nullptr && params != nullptr, "NULL argument");
+        *out = nullptr;
+        need(std::isfinite(lr) && lr > 0, "lr must be > 0");
+        for (int i = 0; i < EQS_MLP_NPARAM; ++i)
+            if (!std::isfinite(params[i])) fail(EQS_ERR_NONFINITE, "non-finite network parameter");
+        int n = 0;
+        EQS_HIP(hipGetDeviceCount(&n));
+        need(device >= 0 && device < n, "device id out of range");
+        EQS_HIP(hipSetDevice(device));
+        *out = eqs::mlp_create(device, (hipStream_t)hip_stream, params, bf16, lr);
+        return EQS_OK;
+    });
+}
+
+int eqs_mlp_destroy(eqs_mlp* net) {
+    return guarded([&] {
+        eqs::mlp_destroy(net);
+        return EQS_OK;
+    });
+}
+
+int eqs_mlp_forward(eqs_mlp* net, const float* x_dev, float* y_dev, int32_t batch) {
+    return guarded([&] {
+        need(net && x_dev && y_dev, "NULL argument");
+        need(batch >= 1, "batch must be >= 1");
+        eqs::mlp_forward(net, x_dev, y_dev, batch);
+        EQS_HIP(hipGetLastError());
+        return EQS_OK;
+    });
+}
+
+int eqs_mlp_train_step(eqs_mlp* net, const float* x_dev, const float* t_dev, int32_t batch, float* loss) {
+    return guarded([&] {
+        need(net && x_dev && t_dev, "NULL argument");
+        need(batch >= 1 && batch <= 64, "batch must be in [1, 64]");
+        eqs::mlp_train(net, x_dev, t_dev, batch);
+        EQS_HIP(hipGetLastError());
+        const float l = eqs::mlp_last_loss(net);
+        if (loss) *loss = l;
+        return EQS_OK;
+    });
+}
+
+int eqs_mlp_get(eqs_mlp* net, float* params_host, float* grad_host) {
+    return guarded([&] {
+        need(net != nullptr, "NULL argument");
+        eqs::mlp_get(net, params_host, grad_host);
+        return EQS_OK;
     });
 }
 

@@ -110,6 +110,42 @@ struct Hierarchy {
     std::vector<Level<T>> lv;
 };
 
+// Start-vector estimator state (guess.hip).
+}  // namespace eqs
+struct eqs_mlp;
+namespace eqs {
+struct GuessState {
+    eqs_guess_params p{};
+    std::vector<float> init;          // network initial parameters
+    // window of stage solutions (device) and its Gram / energy matrices (host)
+    double* d_S = nullptr;            // [16][n_free]
+    double* d_rprev = nullptr;        // r_{j-1}
+    double* d_x0 = nullptr;
+    double* d_alpha = nullptr;        // [16]
+    double* d_dots = nullptr;
+    double* d_part = nullptr;
+    float *d_bx = nullptr, *d_bt = nullptr;  // minibatch staging
+    float* h_stage = nullptr;         // pinned
+    bool dev_ready = false;
+    int count = 0, oldest = 0;
+    std::vector<double> G, H, rdots;  // 16 x 16, 16 x 16, 16
+    bool have_prev = false;
+    // pending training pair of the current stage
+    bool have_pending = false;
+    float pend_x[32];
+    double pend_scale = 1.0;
+    std::vector<int> pend_slot;
+    std::vector<double> pend_B;
+    int pend_m = 0;
+    // replay buffer (host) and network
+    std::vector<float> rx, rt;
+    int rcount = 0, rhead = 0;
+    uint64_t counter = 0;
+    eqs_mlp* net = nullptr;
+    bool trained = false;
+    double last_loss = 0.0;
+};
+
 // ------------------------------------------------------------------ context
 }  // namespace eqs
 
@@ -160,6 +196,9 @@ struct eqs_ctx {
 
     int64_t device_bytes = 0;
     std::vector<void*> allocations;
+
+    // start vectors
+    eqs::GuessState guess;
 
     // per-kernel-class timing (HIP event pairs around launches)
     uint32_t prof_mask = 0;
@@ -214,6 +253,26 @@ void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const doubl
 template <typename T>
 void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double* z, double* part_rz,
             const PcgScalars* scal);
+
+// start-vector network (mlp.hip)
+}  // namespace eqs
+struct eqs_mlp;
+namespace eqs {
+eqs_mlp* mlp_create(int device, hipStream_t stream, const float* params, int bf16, double lr);
+void mlp_destroy(eqs_mlp* n);
+void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B);
+void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B);
+float mlp_last_loss(eqs_mlp* n);
+void mlp_get(eqs_mlp* n, float* params, float* grad);
+void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, double* alpha);
+
+// start vectors (guess.hip)
+void guess_configure(eqs_ctx* c, const eqs_guess_params& p);
+void guess_release(eqs_ctx* c);
+void guess_reset(eqs_ctx* c);
+int guess_stage(eqs_ctx* c);
+void guess_after_solve(eqs_ctx* c);
+double guess_last_loss(eqs_ctx* c);
 
 // per-kernel timing (profile.cpp)
 void prof_begin(eqs_ctx* c, int cls, hipStream_t s);

@@ -1,0 +1,475 @@
+// Start vectors for the stage solves (Sec. IV of the paper).
+//
+// The solutions F_j of successive stages solve M F_j = r_j with the same M, so
+// a window S of the last W stage solutions spans good start vectors. Sec. IV
+// builds them by a reduced solve on an orthonormal or POD basis V of S
+// (eq. (5): x0 = V (V^T M V)^{-1} V^T r). Here the POD basis comes from the
+// W x W Gram matrix G = S^T S, and V^T M V needs no extra products because
+// M s_k = r_k for every stored solution: H = S^T M S has entries r_a . s_b.
+//
+// Per stage j (after the element pass wrote r_j) one fused pass reads the
+// window S (before F_{j-1} joins it), u = F_{j-1}, v = r_j and w = r_{j-1}
+// and returns S^T u, S^T v, u.u, u.v, u.w. The host then
+//   * completes the training pair of stage j-1 (target V_{j-1}^T F_{j-1}),
+//   * moves F_{j-1} into the window (G and H gain a row),
+//   * forms V from G's eigenvectors, the features (V^T F_{j-1}, V^T r_j),
+//     and the coefficients of the start vector: by eq. (5) (GALERKIN) or by
+//     the network (MLP, inference on the GPU), x0 = S alpha (one pass),
+//   * lets a guard compare |r_j - M x0| with |r_j - M F_{j-1}|.
+// The network then takes one Adam step on a minibatch of stored pairs.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "eqs_internal.h"
+
+namespace eqs {
+
+constexpr int kMaxWin = 16;
+constexpr int kNDots = 2 * kMaxWin + 3;
+constexpr int kDotGrid = 1024;
+
+// ------------------------------------------------------------- kernels
+template <int NQ>
+__device__ __forceinline__ void block_sums_store(double (&v)[NQ], double* __restrict__ part, int64_t stride) {
+    __shared__ double sh[NQ][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[q][wid] = x;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NQ; q += blockDim.x) part[q * stride + blockIdx.x] = ((sh[q][0] + sh[q][1]) + sh[q][2]) + sh[q][3];
+}
+
+// S^T u, S^T v for the first nslot slots, and u.u, u.v, u.w.
+__global__ __launch_bounds__(256) void k_window_dots(const double* __restrict__ S, int64_t ld, int nslot,
+                                                      const double* __restrict__ u, const double* __restrict__ v,
+                                                      const double* __restrict__ w, int64_t n,
+                                                      double* __restrict__ part) {
+    double acc[kNDots];
+#pragma unroll
+    for (int q = 0; q < kNDots; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double ui = u[i], vi = v[i];
+#pragma unroll
+        for (int k = 0; k < kMaxWin; ++k) {
+            if (k < nslot) {
+                const double sk = S[k * ld + i];
+                acc[2 * k] += sk * ui;
+                acc[2 * k + 1] += sk * vi;
+            }
+        }
+        acc[2 * kMaxWin] += ui * ui;
+        acc[2 * kMaxWin + 1] += ui * vi;
+        acc[2 * kMaxWin + 2] += ui * w[i];
+    }
+    block_sums_store<kNDots>(acc, part, kDotGrid);
+}
+
+// out[q] = sum of part[q][0..nb) in a fixed order (one block per value).
+__global__ void k_sum_rows(const double* __restrict__ part, int64_t stride, int nb, double* __restrict__ out) {
+    __shared__ double sh[4];
+    double x = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) x += part[blockIdx.x * stride + i];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// x0 = sum_k alpha_k S_k
+__global__ __launch_bounds__(256) void k_window_prolong(const double* __restrict__ S, int64_t ld, int nslot,
+                                                         const double* __restrict__ alpha, double* __restrict__ x0,
+                                                         int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < nslot; ++k) acc += alpha[k] * S[k * ld + i];
+    x0[i] = acc;
+}
+
+// |r - M a|^2 and |r - M b|^2 (partials), M in SELL-64.
+__global__ __launch_bounds__(256) void k_two_residuals(const int32_t* __restrict__ sptr, const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val, int32_t n_rows, int32_t n_slices,
+                                                        const double* __restrict__ r, const double* __restrict__ a,
+                                                        const double* __restrict__ b, double* __restrict__ part,
+                                                        int64_t stride) {
+    double acc[2] = {0.0, 0.0};
+    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row < n_slices * 64) {
+        const int32_t s = row >> 6, l = row & 63;
+        const int32_t beg = sptr[s], wd = (sptr[s + 1] - beg) >> 6;
+        double ma = 0.0, mb = 0.0;
+        for (int32_t k = 0; k < wd; ++k) {
+            const int32_t j = col[beg + (int64_t)k * 64 + l];
+            const double m = val[beg + (int64_t)k * 64 + l];
+            ma += m * a[j];
+            mb += m * b[j];
+        }
+        if (row < n_rows) {
+            const double da = r[row] - ma, db = r[row] - mb;
+            acc[0] = da * da;
+            acc[1] = db * db;
+        }
+    }
+    block_sums_store<2>(acc, part, stride);
+}
+
+// ---------------------------------------------------------- host algebra
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major):
+// A = Q diag(lam) Q^T; columns of Q are the eigenvectors.
+static void jacobi_eigen(int n, std::vector<double> A, std::vector<double>& lam, std::vector<double>& Q) {
+    Q.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) (i == j ? diag : off) += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        if (off <= 1e-30 * diag) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; ++k) {  // A <- A J (columns p, q)
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = cs * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // A <- J^T A (rows p, q)
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = cs * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; ++k) {  // Q <- Q J
+                    const double qkp = Q[(size_t)k * n + p], qkq = Q[(size_t)k * n + q];
+                    Q[(size_t)k * n + p] = cs * qkp - sn * qkq;
+                    Q[(size_t)k * n + q] = sn * qkp + cs * qkq;
+                }
+            }
+    }
+    lam.resize(n);
+    for (int i = 0; i < n; ++i) lam[i] = A[(size_t)i * n + i];
+}
+
+// Solve the small dense system K c = b (Gaussian elimination, partial pivoting).
+static bool dense_solve(int n, std::vector<double> K, std::vector<double>& b) {
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(K[(size_t)r * n + c]) > std::fabs(K[(size_t)p * n + c])) p = r;
+        if (!(std::fabs(K[(size_t)p * n + c]) > 0)) return false;
+        if (p != c) {
+            for (int k = 0; k < n; ++k) std::swap(K[(size_t)p * n + k], K[(size_t)c * n + k]);
+            std::swap(b[p], b[c]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = K[(size_t)r * n + c] / K[(size_t)c * n + c];
+            for (int k = c; k < n; ++k) K[(size_t)r * n + k] -= f * K[(size_t)c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < n; ++k) s -= K[(size_t)r * n + k] * b[k];
+        b[r] = s / K[(size_t)r * n + r];
+    }
+    return true;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): minibatch indices from a counter.
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// ------------------------------------------------------------ guess state
+void guess_release(eqs_ctx* c) {
+    GuessState& g = c->guess;
+    if (g.net) mlp_destroy(g.net);
+    g.net = nullptr;
+    if (g.h_stage) (void)hipHostFree(g.h_stage);
+    g.h_stage = nullptr;
+    g.dev_ready = false;
+}
+
+void guess_reset(eqs_ctx* c) {
+    GuessState& g = c->guess;
+    g.count = 0;
+    g.oldest = 0;
+    g.have_prev = false;
+    g.have_pending = false;
+    g.rcount = 0;
+    g.rhead = 0;
+    g.counter = 0;
+    g.last_loss = 0.0;
+    std::fill(g.G.begin(), g.G.end(), 0.0);
+    std::fill(g.H.begin(), g.H.end(), 0.0);
+}
+
+void guess_configure(eqs_ctx* c, const eqs_guess_params& p) {
+    GuessState& g = c->guess;
+    guess_release(c);
+    g.p = p;
+    g.G.assign(kMaxWin * kMaxWin, 0.0);
+    g.H.assign(kMaxWin * kMaxWin, 0.0);
+    g.rdots.assign(kMaxWin, 0.0);
+    g.rx.assign((size_t)p.capacity * 32, 0.0f);
+    g.rt.assign((size_t)p.capacity * 16, 0.0f);
+    guess_reset(c);
+    if (p.kind == EQS_GUESS_MLP) g.net = mlp_create(c->device, c->stream, g.init.data(), p.bf16, p.lr);
+    EQS_HIP(hipHostMalloc((void**)&g.h_stage, sizeof(float) * 64 * 48 + sizeof(double) * 64, hipHostMallocDefault));
+}
+
+void guess_alloc_device(eqs_ctx* c) {
+    GuessState& g = c->guess;
+    const int64_t NF = c->n_free;
+    g.d_S = (double*)dev_alloc(c, sizeof(double) * (size_t)kMaxWin * NF);
+    g.d_rprev = (double*)dev_alloc(c, sizeof(double) * NF);
+    g.d_x0 = (double*)dev_alloc(c, sizeof(double) * NF);
+    g.d_alpha = (double*)dev_alloc(c, sizeof(double) * kMaxWin);
+    g.d_dots = (double*)dev_alloc(c, sizeof(double) * 64);
+    g.d_part = (double*)dev_alloc(c, sizeof(double) * kNDots * kDotGrid);
+    g.d_bx = (float*)dev_alloc(c, sizeof(float) * 64 * 32);
+    g.d_bt = (float*)dev_alloc(c, sizeof(float) * 64 * 16);
+    g.dev_ready = true;
+}
+
+// Basis from the Gram matrix of the current window (slots in age order).
+struct Basis {
+    int m = 0;                 // kept directions
+    std::vector<int> slot;     // window slots (age order, newest first)
+    std::vector<double> B;     // [count x m]: V = S_slots B  (B = Q diag(1/sigma))
+    std::vector<double> sigma; // kept singular values
+};
+
+static Basis window_basis(const GuessState& g) {
+    Basis b;
+    const int n = g.count;
+    const int W = g.p.window;
+    for (int k = 0; k < n; ++k) b.slot.push_back((g.oldest + n - 1 - k + W) % W);  // newest first
+    std::vector<double> A((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = g.G[b.slot[i] * kMaxWin + b.slot[j]];
+    std::vector<double> lam, Q;
+    jacobi_eigen(n, A, lam, Q);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return lam[x] > lam[y]; });
+    const double smax = std::sqrt(std::max(lam[order[0]], 0.0));
+    for (int k = 0; k < n; ++k) {
+        const double sg = std::sqrt(std::max(lam[order[k]], 0.0));
+        if (!(sg > 1e-7 * smax)) break;
+        b.sigma.push_back(sg);
+    }
+    b.m = (int)b.sigma.size();
+    b.B.assign((size_t)n * b.m, 0.0);
+    for (int k = 0; k < b.m; ++k) {
+        // sign: the newest snapshot (row 0) has a nonnegative coordinate
+        const double sgn = Q[(size_t)0 * n + order[k]] < 0 ? -1.0 : 1.0;
+        for (int i = 0; i < n; ++i) b.B[(size_t)i * b.m + k] = sgn * Q[(size_t)i * n + order[k]] / b.sigma[k];
+    }
+    return b;
+}
+
+// V^T y for y given by its dots with the window slots (d[slot]).
+static std::vector<double> project(const Basis& b, const double* dslot) {
+    std::vector<double> out(b.m, 0.0);
+    for (int k = 0; k < b.m; ++k)
+        for (int i = 0; i < (int)b.slot.size(); ++i) out[k] += b.B[(size_t)i * b.m + k] * dslot[b.slot[i]];
+    return out;
+}
+
+static double norm(const std::vector<double>& v) {
+    double s = 0.0;
+    for (double x : v) s += x * x;
+    return std::sqrt(s);
+}
+
+// One stage's start vector. Called after the element pass wrote r_j into
+// c->d_rhs and before the solve; d_F holds F_{j-1} (if have_prev). On return
+// d_F holds the chosen start vector. Returns 1 if the estimator's vector was
+// used, -1 if the guard kept F_{j-1}, 0 if no estimate was available.
+int guess_stage(eqs_ctx* c) {
+    GuessState& g = c->guess;
+    hipStream_t s = c->stream;
+    const int64_t NF = c->n_free;
+    if (!g.dev_ready) guess_alloc_device(c);
+    int used = 0;
+    if (!g.have_prev) return 0;  // nothing known yet: d_F (zero or last run's) stays
+
+    // fused pass over the window (F_{j-1} still pending) with u = F_{j-1}, v = r_j, w = r_{j-1}
+    const int n_old = g.count;
+    const unsigned grid = (unsigned)std::min<int64_t>(kDotGrid, (NF + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_window_dots, dim3(grid), dim3(kBlock), 0, s, g.d_S, NF, n_old, c->d_F, c->d_rhs,
+                       g.d_rprev, NF, g.d_part);
+    hipLaunchKernelGGL(k_sum_rows, dim3(kNDots), dim3(kBlock), 0, s, g.d_part, (int64_t)kDotGrid, (int)grid,
+                       g.d_dots);
+    double dots[kNDots];
+    EQS_HIP(hipMemcpyAsync(dots, g.d_dots, sizeof dots, hipMemcpyDeviceToHost, s));
+    EQS_HIP(hipStreamSynchronize(s));
+    double Su[kMaxWin], Sv[kMaxWin];
+    for (int k = 0; k < kMaxWin; ++k) {
+        Su[k] = k < n_old ? dots[2 * k] : 0.0;
+        Sv[k] = k < n_old ? dots[2 * k + 1] : 0.0;
+    }
+    const double uu = dots[2 * kMaxWin], uv = dots[2 * kMaxWin + 1], uw = dots[2 * kMaxWin + 2];
+
+    // (1) training pair of the previous stage: target V_{j-1}^T F_{j-1}
+    if (g.have_pending && g.p.kind == EQS_GUESS_MLP) {
+        std::vector<double> tcoef(16, 0.0);
+        for (int k = 0; k < g.pend_m; ++k) {
+            double a = 0.0;
+            for (int i = 0; i < (int)g.pend_slot.size(); ++i) a += g.pend_B[(size_t)i * g.pend_m + k] * Su[g.pend_slot[i]];
+            tcoef[k] = a / g.pend_scale;
+        }
+        const int slot = g.rhead;
+        for (int q = 0; q < 32; ++q) g.rx[(size_t)slot * 32 + q] = g.pend_x[q];
+        for (int q = 0; q < 16; ++q) g.rt[(size_t)slot * 16 + q] = (float)tcoef[q];
+        g.rhead = (g.rhead + 1) % g.p.capacity;
+        g.rcount = std::min(g.rcount + 1, g.p.capacity);
+    }
+    g.have_pending = false;
+
+    // (2) F_{j-1} joins the window (evicting the oldest when full)
+    const int W = g.p.window;  // physical slots 0..W-1 fill in order, then rotate
+    int e;
+    if (g.count < W) {
+        e = (g.oldest + g.count) % W;
+        g.count++;
+    } else {
+        e = g.oldest;
+        g.oldest = (g.oldest + 1) % W;
+    }
+    // slots 0..n_old-1 are the physical slots in use before the insertion
+    for (int b = 0; b < n_old; ++b) {
+        if (b == e) continue;
+        g.G[e * kMaxWin + b] = g.G[b * kMaxWin + e] = Su[b];
+        g.H[e * kMaxWin + b] = g.H[b * kMaxWin + e] = g.rdots[b];  // r_{j-1} . s_b = s_b^T M F_{j-1}
+    }
+    g.G[e * kMaxWin + e] = uu;
+    g.H[e * kMaxWin + e] = uw;
+    launch_copy(s, g.d_S + (int64_t)e * NF, c->d_F, NF);
+    // r_j against the new window, kept for the next insertion
+    for (int b = 0; b < kMaxWin; ++b) g.rdots[b] = (b == e) ? uv : (b < n_old ? Sv[b] : 0.0);
+
+    if (g.count < 2) return 0;
+
+    // (3) basis, features and coefficients
+    Basis B = window_basis(g);
+    std::vector<double> a = project(B, &g.G[e * kMaxWin]);  // V^T F_{j-1}
+    std::vector<double> bh = project(B, g.rdots.data());     // V^T r_j
+    std::vector<double> coef;                                // on V
+    bool have = false;
+    if (g.p.kind == EQS_GUESS_GALERKIN) {
+        // (V^T M V) c = V^T r with V^T M V = B^T H B
+        const int n = (int)B.slot.size(), m = B.m;
+        std::vector<double> K((size_t)m * m, 0.0);
+        for (int p = 0; p < m; ++p)
+            for (int q = 0; q < m; ++q) {
+                double acc = 0.0;
+                for (int i = 0; i < n; ++i)
+                    for (int k = 0; k < n; ++k)
+                        acc += B.B[(size_t)i * m + p] * g.H[B.slot[i] * kMaxWin + B.slot[k]] * B.B[(size_t)k * m + q];
+                K[(size_t)p * m + q] = acc;
+            }
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) K[(size_t)p * m + q] = K[(size_t)q * m + p] = 0.5 * (K[(size_t)p * m + q] + K[(size_t)q * m + p]);
+        coef = bh;
+        have = dense_solve(m, K, coef);
+        if (have) {
+            std::vector<double> alpha(kMaxWin, 0.0);
+            for (int i = 0; i < n; ++i) {
+                double acc = 0.0;
+                for (int k = 0; k < m; ++k) acc += B.B[(size_t)i * m + k] * coef[k];
+                alpha[B.slot[i]] = acc;
+            }
+            EQS_HIP(hipMemcpyAsync(g.d_alpha, alpha.data(), sizeof(double) * kMaxWin, hipMemcpyHostToDevice, s));
+            EQS_HIP(hipStreamSynchronize(s));
+        }
+    } else if (g.p.kind == EQS_GUESS_MLP) {
+        const double sa = norm(a), sb = norm(bh);
+        float x[32];
+        for (int k = 0; k < 16; ++k) {
+            x[k] = (k < B.m && sa > 0) ? (float)(a[k] / sa) : 0.0f;
+            x[16 + k] = (k < B.m && sb > 0) ? (float)(bh[k] / sb) : 0.0f;
+        }
+        // pending pair for this stage: target V_j^T F_j / |V_j^T F_{j-1}| once F_j is known
+        std::memcpy(g.pend_x, x, sizeof x);
+        g.pend_scale = sa > 0 ? sa : 1.0;
+        g.pend_slot = B.slot;
+        g.pend_B = B.B;
+        g.pend_m = B.m;
+        g.have_pending = true;
+        if (g.rcount >= g.p.warmup && sa > 0) {
+            // alpha_slot = sum_k B[i][k] * sa * y_k  ->  P[slot][k]; slots past count stay 0
+            double P[16 * 16];
+            std::fill(P, P + 256, 0.0);
+            for (int i = 0; i < (int)B.slot.size(); ++i)
+                for (int k = 0; k < B.m; ++k) P[B.slot[i] * 16 + k] = B.B[(size_t)i * B.m + k] * sa;
+            mlp_forward_coeffs(g.net, x, P, g.d_alpha);
+            have = true;
+        }
+    }
+
+    if (have) {
+        hipLaunchKernelGGL(k_window_prolong, dim3((unsigned)((NF + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g.d_S,
+                           NF, g.count, g.d_alpha, g.d_x0, NF);
+        bool take = true;
+        if (g.p.guard) {
+            const int64_t nb = (c->M.n_slices * 64 + kBlock - 1) / kBlock;
+            hipLaunchKernelGGL(k_two_residuals, dim3((unsigned)nb), dim3(kBlock), 0, s, c->M.sptr, c->M.col, c->M.val,
+                               c->M.n_rows, c->M.n_slices, c->d_rhs, g.d_x0, c->d_F, c->d_partials, c->max_blocks);
+            hipLaunchKernelGGL(k_sum_rows, dim3(2), dim3(kBlock), 0, s, c->d_partials, c->max_blocks, (int)nb,
+                               g.d_dots);
+            double rr[2];
+            EQS_HIP(hipMemcpyAsync(rr, g.d_dots, sizeof rr, hipMemcpyDeviceToHost, s));
+            EQS_HIP(hipStreamSynchronize(s));
+            take = std::isfinite(rr[0]) && rr[0] <= rr[1];
+        }
+        if (take) {
+            launch_copy(s, c->d_F, g.d_x0, NF);
+            used = 1;
+        } else {
+            used = -1;
+        }
+    }
+    return used;
+}
+
+// After the solve of stage j: remember r_j (the next pass needs it), mark F_j
+// pending, and train the network on one minibatch.
+void guess_after_solve(eqs_ctx* c) {
+    GuessState& g = c->guess;
+    std::swap(c->d_rhs, g.d_rprev);  // r_j is kept; the next element pass writes the other buffer
+    g.have_prev = true;
+    if (g.p.kind != EQS_GUESS_MLP || g.rcount == 0) return;
+    const int B = std::min(g.p.batch, g.rcount);
+    float* hx = g.h_stage;
+    float* ht = g.h_stage + 64 * 32;
+    for (int b = 0; b < B; ++b) {
+        const int idx = (int)(splitmix64(g.p.seed + g.counter++) % (uint64_t)g.rcount);
+        std::memcpy(hx + b * 32, &g.rx[(size_t)idx * 32], 32 * sizeof(float));
+        std::memcpy(ht + b * 16, &g.rt[(size_t)idx * 16], 16 * sizeof(float));
+    }
+    EQS_HIP(hipMemcpyAsync(g.d_bx, hx, sizeof(float) * B * 32, hipMemcpyHostToDevice, c->stream));
+    EQS_HIP(hipMemcpyAsync(g.d_bt, ht, sizeof(float) * B * 16, hipMemcpyHostToDevice, c->stream));
+    mlp_train(g.net, g.d_bx, g.d_bt, B);
+    g.trained = true;
+}
+
+double guess_last_loss(eqs_ctx* c) {
+    GuessState& g = c->guess;
+    if (!g.net || !g.trained) return 0.0;
+    return mlp_last_loss(g.net);
+}
+
+}  // namespace eqs

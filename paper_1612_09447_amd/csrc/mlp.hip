@@ -1,0 +1,340 @@
+// Start-vector network for the learned form: a multilayer perceptron
+// 32 -> 64 -> 64 -> 16 (SiLU hidden activations, linear output) trained online
+// with mean-squared error and Adam. Sec. IV of the paper builds CG start
+// vectors from a POD basis of earlier solutions; here the small reduced solve
+// is replaced by this learned map, and CG stays the judge of the result.
+//
+// One workgroup of 256 threads runs a whole minibatch (B <= 64): forward,
+// loss, backward and the Adam update, all in one launch with activations in
+// LDS (44 KiB) and weights in global memory (7312 parameters, L2-resident).
+// Matmul operands are rounded to bfloat16 (round to nearest even) in BF16
+// mode, products accumulate in FP32; master weights, gradients and Adam
+// moments are FP32. Every sum runs in a fixed order, so results are
+// deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "eqs_internal.h"
+
+namespace eqs {
+
+constexpr int kIn = 32, kH = 64, kOut = 16, kMaxB = 64;
+constexpr int oW1 = 0, oB1 = oW1 + kH * kIn, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH,
+              oB3 = oW3 + kOut * kH, kNParam = oB3 + kOut;
+static_assert(kNParam == 7312, "parameter layout");
+
+__device__ __forceinline__ float bf16_round(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return x;  // inf / nan unchanged
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    return __uint_as_float(u);
+}
+
+template <bool BF16>
+__device__ __forceinline__ float q(float x) {
+    return BF16 ? bf16_round(x) : x;
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+    const float s = 1.0f / (1.0f + expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+struct MlpState {
+    float lr, beta1, beta2, eps;
+    int32_t step;  // Adam steps taken
+    float loss;    // loss of the last training batch
+};
+
+// wq: matmul copies of the weights (bf16-rounded in BF16 mode); master: FP32.
+template <bool TRAIN, bool BF16>
+__global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ x, const float* __restrict__ tgt, float* __restrict__ y,
+                                             int32_t B, float* __restrict__ master, float* __restrict__ wq,
+                                             float* __restrict__ grad, float* __restrict__ m1, float* __restrict__ m2,
+                                             MlpState* __restrict__ st) {
+    __shared__ float sx[kMaxB * kIn];
+    __shared__ float sh1[kMaxB * kH];
+    __shared__ float sh2[kMaxB * kH];
+    __shared__ float sy[kMaxB * kOut];
+    __shared__ float sred[256];
+    const int tid = threadIdx.x;
+
+    for (int i = tid; i < B * kIn; i += 256) sx[i] = x[i];
+    __syncthreads();
+    // h1 = W1 x + b1
+    for (int i = tid; i < B * kH; i += 256) {
+        const int b = i / kH, o = i % kH;
+        float acc = 0.0f;
+        for (int k = 0; k < kIn; ++k) acc += wq[oW1 + o * kIn + k] * q<BF16>(sx[b * kIn + k]);
+        sh1[i] = acc + master[oB1 + o];
+    }
+    __syncthreads();
+    // h2 = W2 silu(h1) + b2
+    for (int i = tid; i < B * kH; i += 256) {
+        const int b = i / kH, o = i % kH;
+        float acc = 0.0f;
+        for (int k = 0; k < kH; ++k) acc += wq[oW2 + o * kH + k] * q<BF16>(silu(sh1[b * kH + k]));
+        sh2[i] = acc + master[oB2 + o];
+    }
+    __syncthreads();
+    // y = W3 silu(h2) + b3
+    for (int i = tid; i < B * kOut; i += 256) {
+        const int b = i / kOut, o = i % kOut;
+        float acc = 0.0f;
+        for (int k = 0; k < kH; ++k) acc += wq[oW3 + o * kH + k] * q<BF16>(silu(sh2[b * kH + k]));
+        sy[i] = acc + master[oB3 + o];
+    }
+    __syncthreads();
+    if (!TRAIN) {
+        for (int i = tid; i < B * kOut; i += 256) y[i] = sy[i];
+        return;
+    }
+
+    // loss and dy = 2 (y - t) / (B * 16), in place of y
+    float part = 0.0f;
+    const float inv = 1.0f / (float)(B * kOut);
+    for (int i = tid; i < B * kOut; i += 256) {
+        const float d = sy[i] - tgt[i];
+        part += d * d;
+    }
+    sred[tid] = part;
+    __syncthreads();
+    for (int i = tid; i < B * kOut; i += 256) sy[i] = 2.0f * (sy[i] - tgt[i]) * inv;
+    if (tid == 0) {
+        float s = 0.0f;
+        for (int k = 0; k < 256; ++k) s += sred[k];
+        st->loss = s * inv;
+    }
+    __syncthreads();
+
+    // layer 3: gW3 = dy^T a2, gb3 = sum_b dy
+    for (int i = tid; i < kOut * kH; i += 256) {
+        const int o = i / kH, k = i % kH;
+        float acc = 0.0f;
+        for (int b = 0; b < B; ++b) acc += q<BF16>(sy[b * kOut + o]) * q<BF16>(silu(sh2[b * kH + k]));
+        grad[oW3 + i] = acc;
+    }
+    for (int o = tid; o < kOut; o += 256) {
+        float acc = 0.0f;
+        for (int b = 0; b < B; ++b) acc += sy[b * kOut + o];
+        grad[oB3 + o] = acc;
+    }
+    __syncthreads();
+    // dh2 = (dy W3) * silu'(h2), written over h2 (each thread reads its own h2 first)
+    for (int i = tid; i < B * kH; i += 256) {
+        const int b = i / kH, k = i % kH;
+        float acc = 0.0f;
+        for (int o = 0; o < kOut; ++o) acc += q<BF16>(sy[b * kOut + o]) * wq[oW3 + o * kH + k];
+        sh2[i] = acc * silu_grad(sh2[i]);
+    }
+    __syncthreads();
+    // layer 2: gW2 = dh2^T a1, gb2 = sum_b dh2
+    for (int i = tid; i < kH * kH; i += 256) {
+        const int o = i / kH, k = i % kH;
+        float acc = 0.0f;
+        for (int b = 0; b < B; ++b) acc += q<BF16>(sh2[b * kH + o]) * q<BF16>(silu(sh1[b * kH + k]));
+        grad[oW2 + i] = acc;
+    }
+    for (int o = tid; o < kH; o += 256) {
+        float acc = 0.0f;
+        for (int b = 0; b < B; ++b) acc += sh2[b * kH + o];
+        grad[oB2 + o] = acc;
+    }
+    __syncthreads();
+    // dh1 = (dh2 W2) * silu'(h1), over h1
+    for (int i = tid; i < B * kH; i += 256) {
+        const int b = i / kH, k = i % kH;
+        float acc = 0.0f;
+        for (int o = 0; o < kH; ++o) acc += q<BF16>(sh2[b * kH + o]) * wq[oW2 + o * kH + k];
+        sh1[i] = acc * silu_grad(sh1[i]);
+    }
+    __syncthreads();
+    // layer 1: gW1 = dh1^T x, gb1 = sum_b dh1
+    for (int i = tid; i < kH * kIn; i += 256) {
+        const int o = i / kIn, k = i % kIn;
+        float acc = 0.0f;
+        for (int b = 0; b < B; ++b) acc += q<BF16>(sh1[b * kH + o]) * q<BF16>(sx[b * kIn + k]);
+        grad[oW1 + i] = acc;
+    }
+    for (int o = tid; o < kH; o += 256) {
+        float acc = 0.0f;
+        for (int b = 0; b < B; ++b) acc += sh1[b * kH + o];
+        grad[oB1 + o] = acc;
+    }
+    __syncthreads();
+
+    // Adam (Kingma & Ba): bias-corrected first and second moments
+    const int t = st->step + 1;
+    const float bc1 = 1.0f - powf(st->beta1, (float)t);
+    const float bc2 = 1.0f - powf(st->beta2, (float)t);
+    for (int i = tid; i < kNParam; i += 256) {
+        const float g = grad[i];
+        const float a = st->beta1 * m1[i] + (1.0f - st->beta1) * g;
+        const float v = st->beta2 * m2[i] + (1.0f - st->beta2) * g * g;
+        m1[i] = a;
+        m2[i] = v;
+        const float w = master[i] - st->lr * (a / bc1) / (sqrtf(v / bc2) + st->eps);
+        master[i] = w;
+        wq[i] = q<BF16>(w);
+    }
+    __syncthreads();
+    if (tid == 0) st->step = t;
+}
+
+// Inference for one feature vector, followed by the map from the network's
+// 16 outputs to the 16 snapshot coefficients of the start vector:
+// alpha = P y (P carries the POD basis change and the output scale).
+struct MlpIn {
+    float x[kIn];
+    double P[kOut * kOut];
+};
+
+template <bool BF16>
+__global__ __launch_bounds__(64) void k_mlp_alpha(MlpIn in, const float* __restrict__ master,
+                                                   const float* __restrict__ wq, double* __restrict__ alpha) {
+    __shared__ float a1[kH], a2[kH], yv[kOut];
+    const int tid = threadIdx.x;
+    {
+        float acc = 0.0f;
+        for (int k = 0; k < kIn; ++k) acc += wq[oW1 + tid * kIn + k] * q<BF16>(in.x[k]);
+        a1[tid] = silu(acc + master[oB1 + tid]);
+    }
+    __syncthreads();
+    {
+        float acc = 0.0f;
+        for (int k = 0; k < kH; ++k) acc += wq[oW2 + tid * kH + k] * q<BF16>(a1[k]);
+        a2[tid] = silu(acc + master[oB2 + tid]);
+    }
+    __syncthreads();
+    if (tid < kOut) {
+        float acc = 0.0f;
+        for (int k = 0; k < kH; ++k) acc += wq[oW3 + tid * kH + k] * q<BF16>(a2[k]);
+        yv[tid] = acc + master[oB3 + tid];
+    }
+    __syncthreads();
+    if (tid < kOut) {
+        double acc = 0.0;
+        for (int k = 0; k < kOut; ++k) acc += in.P[tid * kOut + k] * (double)yv[k];
+        alpha[tid] = acc;
+    }
+}
+
+}  // namespace eqs
+
+struct eqs_mlp {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int bf16 = 1;
+    float *master = nullptr, *wq = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
+    eqs::MlpState* st = nullptr;
+};
+
+namespace eqs {
+
+static void mlp_launch(eqs_mlp* n, bool train, const float* x, const float* t, float* y, int32_t B) {
+    dim3 g(1), b(256);
+    if (train) {
+        if (n->bf16)
+            hipLaunchKernelGGL((k_mlp<true, true>), g, b, 0, n->stream, x, t, y, B, n->master, n->wq, n->grad, n->m1,
+                               n->m2, n->st);
+        else
+            hipLaunchKernelGGL((k_mlp<true, false>), g, b, 0, n->stream, x, t, y, B, n->master, n->wq, n->grad, n->m1,
+                               n->m2, n->st);
+    } else {
+        if (n->bf16)
+            hipLaunchKernelGGL((k_mlp<false, true>), g, b, 0, n->stream, x, t, y, B, n->master, n->wq, n->grad,
+                               n->m1, n->m2, n->st);
+        else
+            hipLaunchKernelGGL((k_mlp<false, false>), g, b, 0, n->stream, x, t, y, B, n->master, n->wq, n->grad,
+                               n->m1, n->m2, n->st);
+    }
+}
+
+static float host_bf16(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return x;
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    float r;
+    std::memcpy(&r, &u, 4);
+    return r;
+}
+
+eqs_mlp* mlp_create(int device, hipStream_t stream, const float* params, int bf16, double lr) {
+    eqs_mlp* n = new eqs_mlp();
+    n->device = device;
+    n->stream = stream;
+    n->bf16 = bf16 ? 1 : 0;
+    const size_t bytes = sizeof(float) * kNParam;
+    auto alloc = [&](float** p) { EQS_HIP(hipMalloc((void**)p, bytes)); };
+    try {
+        alloc(&n->master);
+        alloc(&n->wq);
+        alloc(&n->grad);
+        alloc(&n->m1);
+        alloc(&n->m2);
+        EQS_HIP(hipMalloc((void**)&n->st, sizeof(MlpState)));
+        std::vector<float> w(params, params + kNParam), wq(kNParam);
+        for (int i = 0; i < kNParam; ++i) wq[i] = n->bf16 ? host_bf16(w[i]) : w[i];
+        std::vector<float> zero(kNParam, 0.0f);
+        EQS_HIP(hipMemcpy(n->master, w.data(), bytes, hipMemcpyHostToDevice));
+        EQS_HIP(hipMemcpy(n->wq, wq.data(), bytes, hipMemcpyHostToDevice));
+        EQS_HIP(hipMemcpy(n->grad, zero.data(), bytes, hipMemcpyHostToDevice));
+        EQS_HIP(hipMemcpy(n->m1, zero.data(), bytes, hipMemcpyHostToDevice));
+        EQS_HIP(hipMemcpy(n->m2, zero.data(), bytes, hipMemcpyHostToDevice));
+        MlpState s{(float)lr, 0.9f, 0.999f, 1e-8f, 0, 0.0f};
+        EQS_HIP(hipMemcpy(n->st, &s, sizeof s, hipMemcpyHostToDevice));
+    } catch (...) {
+        mlp_destroy(n);
+        throw;
+    }
+    return n;
+}
+
+void mlp_destroy(eqs_mlp* n) {
+    if (!n) return;
+    for (float* p : {n->master, n->wq, n->grad, n->m1, n->m2})
+        if (p) (void)hipFree(p);
+    if (n->st) (void)hipFree(n->st);
+    delete n;
+}
+
+void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B) {
+    for (int32_t b0 = 0; b0 < B; b0 += kMaxB) {
+        const int32_t nb = std::min<int32_t>(kMaxB, B - b0);
+        mlp_launch(n, false, x + (int64_t)b0 * kIn, nullptr, y + (int64_t)b0 * kOut, nb);
+    }
+}
+
+void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B) { mlp_launch(n, true, x, t, nullptr, B); }
+
+void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, double* alpha) {
+    MlpIn in;
+    std::memcpy(in.x, x, sizeof in.x);
+    std::memcpy(in.P, P, sizeof in.P);
+    if (n->bf16)
+        hipLaunchKernelGGL(k_mlp_alpha<true>, dim3(1), dim3(64), 0, n->stream, in, n->master, n->wq, alpha);
+    else
+        hipLaunchKernelGGL(k_mlp_alpha<false>, dim3(1), dim3(64), 0, n->stream, in, n->master, n->wq, alpha);
+}
+
+void mlp_get(eqs_mlp* n, float* params, float* grad) {
+    if (params) EQS_HIP(hipMemcpyAsync(params, n->master, sizeof(float) * kNParam, hipMemcpyDeviceToHost, n->stream));
+    if (grad) EQS_HIP(hipMemcpyAsync(grad, n->grad, sizeof(float) * kNParam, hipMemcpyDeviceToHost, n->stream));
+    EQS_HIP(hipStreamSynchronize(n->stream));
+}
+
+float mlp_last_loss(eqs_mlp* n) {
+    MlpState s;
+    EQS_HIP(hipMemcpyAsync(&s, n->st, sizeof s, hipMemcpyDeviceToHost, n->stream));
+    EQS_HIP(hipStreamSynchronize(n->stream));
+    return s.loss;
+}
+
+}  // namespace eqs

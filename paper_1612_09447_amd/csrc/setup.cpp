@@ -616,6 +616,10 @@ void free_device(eqs_ctx* c) {
     c->d_scal = nullptr;
     c->built = false;
     c->have_Flast = false;
+    c->guess.dev_ready = false;
+    c->guess.d_S = c->guess.d_rprev = c->guess.d_x0 = c->guess.d_alpha = c->guess.d_dots = c->guess.d_part = nullptr;
+    c->guess.d_bx = c->guess.d_bt = nullptr;
+    if (!c->guess.G.empty()) guess_reset(c);
 }
 
 DriveVals drive_values(const eqs_ctx* c, double t) {

@@ -107,9 +107,19 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
         const double tj = t + cc[j] * dt;
         launch_kx(q, true, c, Ycur, drive_values(c, tj), c->d_rhs);
         check_launch();
-        // F_j = M^{-1} r_j, started from F_{j-1} (held in d_F)
+        // start vector: F_{j-1} (held in d_F), zero, or an estimator's vector
+        const int kind = c->guess.p.kind;
+        if (kind == EQS_GUESS_ZERO) {
+            launch_fill(q, c->d_F, 0.0, NF);
+        } else if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP) {
+            const int u = guess_stage(c);
+            if (u > 0) S.guess_used++;
+            else if (u < 0) S.guess_fallbacks++;
+        }
+        // F_j = M^{-1} r_j
         eqs_solve_stats ss{};
         const int src = solve_M(c, c->d_rhs, c->d_F, rtol, maxit, &ss);
+        if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP) guess_after_solve(c);
         S.total_iters += ss.iters;
         S.max_iters = std::max(S.max_iters, ss.iters);
         S.min_iters = std::min(S.min_iters, ss.iters);
@@ -144,6 +154,7 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
     EQS_HIP(hipStreamSynchronize(q));
     c->have_Flast = true;
     if (S.min_iters == INT32_MAX) S.min_iters = 0;
+    if (c->guess.p.kind == EQS_GUESS_MLP) S.train_loss = guess_last_loss(c);
     if (st) *st = S;
     return rc;
 }

@@ -44,8 +44,10 @@ STRUCTS = {
     "eqs_amg_params": ["precision", "coarse_max", "max_levels", "flexible", "theta", "jacobi_weight",
                        "smooth_weight"],
     "eqs_solve_stats": ["iters", "status", "relres"],
-    "eqs_step_stats": ["stages", "total_iters", "max_iters", "min_iters", "not_converged", "reserved",
-                       "max_relres"],
+    "eqs_step_stats": ["stages", "total_iters", "max_iters", "min_iters", "not_converged", "guess_used",
+                       "guess_fallbacks", "reserved", "max_relres", "train_loss"],
+    "eqs_guess_params": ["kind", "window", "capacity", "warmup", "batch", "bf16", "guard", "reserved", "lr", "seed",
+                         "init"],
     "eqs_info": ["n_nodes", "n_tets", "n_free", "nnz_M", "n_levels", "precision", "level_rows", "level_nnz",
                  "device_bytes"],
 }
@@ -73,7 +75,7 @@ def test_struct_layouts_match_header(tmp_path):
 def test_constants_match_header():
     src = open(HEADER).read()
     for name in ["EQS_OK", "EQS_ERR_INVALID_ARG", "EQS_ERR_STATE", "EQS_ERR_HIP", "EQS_ERR_NOT_CONVERGED",
-                 "EQS_ERR_BREAKDOWN", "EQS_ERR_NONFINITE", "EQS_ERR_ALLOC", "EQS_MAX_DRIVES"]:
+                 "EQS_ERR_BREAKDOWN", "EQS_ERR_NONFINITE", "EQS_ERR_ALLOC", "EQS_MAX_DRIVES", "EQS_MLP_NPARAM"]:
         m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, src)
         assert m and int(m.group(1)) == getattr(binding, name), name
 

@@ -1,0 +1,126 @@
+"""Learned form on the GPU: the start-vector network's kernels against the FP64
+oracle (forward, gradients, Adam), and the Galerkin (eq. (5)) and network start
+vectors inside the RKC stage loop, where CG to the tolerance stays the judge.
+
+Tolerances (SURVEY L-2): FP32 operands 1e-5 relative, BF16 operands 2e-2
+relative (normwise per tensor), against the FP64 reference.
+"""
+
+import numpy as np
+import pytest
+
+import eqsgen
+from oracle import mlp as omlp
+from oracle.eqs import EqsOracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1612_09447_amd import EQS_PREC_FP64, Context, Mlp  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def F32(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=DEV)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def params64(p):
+    return {k: np.asarray(v, np.float64) for k, v in p.items()}
+
+
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-5), (True, 2e-2)])
+def test_mlp_forward_matches_oracle(bf16, tol):
+    p = eqsgen.mlp_init(4)
+    net = Mlp(p, bf16=bf16, stream=torch.cuda.current_stream(DEV))
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(100, 32)).astype(np.float32)  # two chunks of <= 64
+    y = torch.zeros((100, 16), dtype=torch.float32, device=DEV)
+    net.forward(F32(x), y)
+    ref, _ = omlp.forward(params64(p), x.astype(np.float64))
+    assert rel(y.cpu().numpy(), ref) <= tol
+    net.close()
+
+
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-5), (True, 2e-2)])
+def test_mlp_train_step_gradients_and_adam(bf16, tol):
+    p = eqsgen.mlp_init(5)
+    net = Mlp(p, bf16=bf16, lr=1e-3, stream=torch.cuda.current_stream(DEV))
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(64, 32)).astype(np.float32)
+    t = rng.normal(size=(64, 16)).astype(np.float32)
+    loss = net.train_step(F32(x), F32(t))
+    L, g = omlp.backward(params64(p), x.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - L) <= tol * L
+    p_after, g_gpu = net.get()
+    for k in omlp.NAMES:
+        assert rel(g_gpu[k], g[k]) <= tol, (k, rel(g_gpu[k], g[k]))
+    # Adam's first step moves each weight by lr * sign(g) (where g is not tiny)
+    q = params64(p)
+    st = omlp.adam_state(q)
+    omlp.adam_step(q, g, st, lr=1e-3)
+    for k in omlp.NAMES:
+        big = np.abs(g[k]) > 1e-2 * np.abs(g[k]).max()
+        np.testing.assert_allclose(np.asarray(p_after[k], np.float64)[big], q[k][big], rtol=0, atol=1e-6)
+    net.close()
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_mlp_learns_a_linear_map(bf16):
+    p = eqsgen.mlp_init(6)
+    net = Mlp(p, bf16=bf16, lr=1e-3, stream=torch.cuda.current_stream(DEV))
+    rng = np.random.default_rng(2)
+    A = rng.normal(size=(16, 32)) / 6
+    X = rng.normal(size=(512, 32)).astype(np.float32)
+    Y = (X @ A.T).astype(np.float32)
+    Xd, Yd = F32(X), F32(Y)
+    first = net.train_step(Xd[:64], Yd[:64])
+    for it in range(1, 400):
+        b = rng.choice(512, 64, replace=False)
+        last = net.train_step(Xd[b], Yd[b])
+    assert last < 0.05 * first, (first, last)
+    net.close()
+
+
+def run_kind(case, kind, steps, rtol, **kw):
+    o = EqsOracle(case)
+    with Context(0, torch.cuda.current_stream(DEV)) as c:
+        c.setup_case(case, precision=EQS_PREC_FP64)
+        if kind == "mlp":
+            c.set_guess("mlp", init=eqsgen.mlp_init(4), **kw)
+        else:
+            c.set_guess(kind, **kw)
+        x = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+        traj, stats = [], []
+        for n in range(steps):
+            st = c.rkc_step(n * case.tau, case.tau, case.s, x, rtol=rtol, maxit=500)
+            stats.append(st)
+            traj.append(x.cpu().numpy()[o.free].copy())
+    return traj, stats, o
+
+
+def test_start_vector_kinds_keep_the_result_and_galerkin_beats_previous():
+    case = eqsgen.case_c1(n=12, seed=1)
+    case.s = 12
+    steps = 8
+    o = EqsOracle(case)
+    ref = o.rkc_trajectory(np.zeros(o.n_free), 0.0, case.tau, case.s, steps)[1:]
+    scale = max(np.linalg.norm(r) for r in ref)
+    iters = {}
+    for kind in ("previous", "zero", "galerkin", "mlp"):
+        kw = dict(warmup=16) if kind == "mlp" else {}
+        traj, stats, _ = run_kind(case, kind, steps, 1e-12, **kw)
+        err = max(np.linalg.norm(a - b) for a, b in zip(traj, ref)) / scale
+        iters[kind] = sum(s["total_iters"] for s in stats)
+        used = sum(s["guess_used"] for s in stats)
+        fb = sum(s["guess_fallbacks"] for s in stats)
+        print(f"[guess] {kind}: CG iterations {iters[kind]}, used {used}, fallbacks {fb}, err {err:.2e}, "
+              f"loss {stats[-1]['train_loss']:.3e}", flush=True)
+        assert err <= 1e-9, (kind, err)
+        if kind in ("galerkin", "mlp"):
+            assert used + fb > 0
+    assert iters["galerkin"] < iters["previous"] < iters["zero"]
