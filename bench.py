@@ -38,9 +38,11 @@ def log(*a):
 
 
 def element_bytes(info):
-    # per tet: 4 int32 node ids + uint16 material id; per node: xyz (24 B),
-    # potential read (8 B), output write (8 B) -- each array touched once
-    return info["n_tets"] * (16 + 2) + info["n_nodes"] * (24 + 8 + 8)
+    # per tet: its packed record (4 x 12-bit block-local vertex ids + 16-bit
+    # material, 8 B); per node: xyz (24 B), potential read (8 B), output write
+    # (8 B) -- each array touched once (block node lists and re-reads of nodes
+    # shared between blocks are overhead, not counted)
+    return info["n_tets"] * 8 + info["n_nodes"] * (24 + 8 + 8)
 
 
 def spmv_bytes(info, nnz):
@@ -61,9 +63,18 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def run_gpu(case, precision, steps, warmup, rtol, profile_classes=()):
+SINGLE_KERNEL_CLASSES = ("element", "spmv_M", "presmooth0", "postsmooth0", "cg_update", "rkc_combine")
+ALL_CLASSES = SINGLE_KERNEL_CLASSES + ("vcycle",)
+KERNEL_NAMES = {"element": "k_kx<true>", "spmv_M": "k_pcg_spmv", "presmooth0": "k_presmooth_res (finest)",
+                "postsmooth0": "k_postsmooth (finest)", "cg_update": "k_pcg_update", "rkc_combine": "k_rkc_combine"}
+
+
+def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"):
+    """Time `steps` RKC steps (uninstrumented), then `prof_steps` more with every
+    kernel class timed by HIP events on the context's stream."""
     import torch
 
+    import eqsgen
     from paper_1612_09447_amd import Context
 
     dev = torch.device("cuda:0")
@@ -71,32 +82,47 @@ def run_gpu(case, precision, steps, warmup, rtol, profile_classes=()):
     t0 = time.perf_counter()
     ctx = Context(0, stream)
     info = ctx.setup_case(case, precision=precision)
+    if guess == "mlp":
+        ctx.set_guess("mlp", init=eqsgen.mlp_init(4))
+    elif guess != "previous":
+        ctx.set_guess(guess)
     setup_s = time.perf_counter() - t0
-    log(f"[bench] setup {precision}: {setup_s:.1f}s levels={info['level_rows']} nnz_M={info['nnz_M']}")
+    log(f"[bench] setup precision={precision} guess={guess}: {setup_s:.1f}s\n" + ctx.describe())
     x = torch.zeros(case.n_nodes, dtype=torch.float64, device=dev)
     tau, s = case.tau, case.s
     n = 0
     for _ in range(warmup):
         ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
         n += 1
-    if profile_classes:
-        ctx.profile_enable(profile_classes)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    iters = []
+    iters, used, fallbacks = [], 0, 0
     for k in range(steps):
         st = ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
         iters.append(st["total_iters"] / st["stages"])
+        used += st["guess_used"]
+        fallbacks += st["guess_fallbacks"]
         n += 1
         if (k + 1) % max(1, steps // 5) == 0:
-            log(f"[bench] {precision} step {k + 1}/{steps} mean CG it/stage {sum(iters) / len(iters):.2f}")
+            log(f"[bench] {precision}/{guess} step {k + 1}/{steps} mean CG it/stage {sum(iters) / len(iters):.2f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
-    prof = {c: ctx.profile_read(c) for c in profile_classes}
-    ctx.profile_enable(())
+    prof, prof_elapsed = {}, 0.0
+    if prof_steps > 0:
+        ctx.profile_enable(ALL_CLASSES)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(prof_steps):
+            ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
+            n += 1
+        torch.cuda.synchronize()
+        prof_elapsed = time.perf_counter() - t2
+        prof = {c: ctx.profile_read(c) for c in ALL_CLASSES}
+        ctx.profile_enable(())
     xn = x.cpu().numpy()
     ctx.close()
-    return dict(elapsed=elapsed, stages=steps * s, iters=iters, info=info, prof=prof, setup_s=setup_s, x=xn)
+    return dict(elapsed=elapsed, stages=steps * s, iters=iters, info=info, prof=prof, prof_elapsed=prof_elapsed,
+                prof_stages=prof_steps * s, setup_s=setup_s, x=xn, used=used, fallbacks=fallbacks)
 
 
 def cpu_baseline(case):
@@ -128,8 +154,12 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the mesh resolution (testing)")
     ap.add_argument("--plain-steps", type=int, default=10, help="timed steps of the plain FP64 path (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prof-steps", type=int, default=3, help="instrumented steps after the timed ones")
+    ap.add_argument("--guess", default="previous", choices=["previous", "zero", "galerkin", "mlp"])
+    ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
     args = ap.parse_args()
 
+    os.environ["EQS_USE_GRAPHS"] = "1" if args.graphs else "0"
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not built)"}))
@@ -145,13 +175,12 @@ def main():
     from paper_1612_09447_amd import EQS_PREC_FP32, EQS_PREC_FP64
 
     main_prec = EQS_PREC_FP32 if prec == "fp32" else EQS_PREC_FP64
-    classes = ("element", "spmv_M", "presmooth0", "postsmooth0", "vcycle", "cg_update", "rkc_combine")
-    r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, profile_classes=classes)
+    r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess)
     stages_per_s = r["stages"] / r["elapsed"]
     info = r["info"]
     prof = r["prof"]
 
-    # roofline of the dominant single kernel class (by summed time)
+    # roofline of the dominant single kernel (largest summed time in the instrumented window)
     per_class_bytes = {
         "element": element_bytes(info),
         "spmv_M": spmv_bytes(info, info["nnz_M"]),
@@ -159,12 +188,15 @@ def main():
     dominant = max(per_class_bytes, key=lambda k: prof[k]["total_ms"])
     avg_s = prof[dominant]["avg_ms"] * 1e-3
     achieved = per_class_bytes[dominant] / avg_s / 1e9
-    roofline = {"bound": "hbm", "kernel": {"element": "k_kx<true>", "spmv_M": "k_pcg_spmv"}[dominant],
+    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dominant],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": per_class_bytes[dominant], "avg_launch_us": round(avg_s * 1e6, 2)}
+                "bytes_per_launch": per_class_bytes[dominant], "avg_launch_us": round(avg_s * 1e6, 2),
+                "timing": f"HIP events around every launch on the context stream, {args.prof_steps} instrumented "
+                          f"steps following the timed ones"}
     breakdown = {k: {"launches": v["launches"], "avg_us": round(v["avg_ms"] * 1e3, 2),
-                     "share_of_timed": round(v["total_ms"] * 1e-3 / r["elapsed"], 4)} for k, v in prof.items()}
+                     "share_of_instrumented": round(v["total_ms"] * 1e-3 / r["prof_elapsed"], 4)}
+                 for k, v in prof.items()}
 
     plain = None
     if args.plain_steps > 0 and main_prec != EQS_PREC_FP64:
@@ -196,7 +228,10 @@ def main():
                         f"{info['n_free']} free DOF), seeded varistor inclusions, RKC s={case.s}, "
                         f"tau={case.tau:g}, CG rel-res {case.rtol:g}",
             "precision": "FP64 CG + K(x)x, FP32 AMG V-cycle" if main_prec == EQS_PREC_FP32 else "FP64",
-            "start_vector": "previous stage solution",
+            "start_vector": args.guess,
+            "guess_used": r["used"],
+            "guess_fallbacks": r["fallbacks"],
+            "graphs": bool(args.graphs),
             "mean_cg_iters_per_stage": round(sum(r["iters"]) / len(r["iters"]), 2),
             "amg_levels": info["level_rows"],
             "nnz_M": info["nnz_M"],

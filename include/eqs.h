@@ -281,6 +281,11 @@ int eqs_profile_enable(eqs_ctx *ctx, uint32_t class_mask);
  * eqs_profile_enable. Synchronises the context's stream. */
 int eqs_profile_read(eqs_ctx *ctx, int32_t kclass, int64_t *launches, double *total_ms);
 
+/* Text description of the built context (hierarchy sizes, the layout the
+ * autotuner chose for every AMG operator): NUL-terminated, truncated to cap
+ * bytes; *needed (may be NULL) receives the full length + 1. */
+int eqs_describe(const eqs_ctx *ctx, char *buf, int64_t cap, int64_t *needed);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *eqs_last_error(void);
 

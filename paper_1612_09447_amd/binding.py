@@ -110,6 +110,7 @@ _SIGNATURES = {
     "eqs_mlp_get": ([_P, _P, _P], C.c_int),
     "eqs_profile_enable": ([_P, C.c_uint32], C.c_int),
     "eqs_profile_read": ([_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
+    "eqs_describe": ([_P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "eqs_last_error": ([], C.c_char_p),
 }
 
@@ -259,6 +260,13 @@ class Context:
         return dict(n_nodes=o.n_nodes, n_tets=o.n_tets, n_free=o.n_free, nnz_M=o.nnz_M, n_levels=L,
                     precision=o.precision, level_rows=list(o.level_rows[:L]), level_nnz=list(o.level_nnz[:L]),
                     device_bytes=o.device_bytes)
+
+    def describe(self) -> str:
+        need = C.c_int64()
+        _check(lib().eqs_describe(self._h, None, 0, C.byref(need)), "eqs_describe")
+        buf = C.create_string_buffer(need.value)
+        _check(lib().eqs_describe(self._h, buf, need.value, None), "eqs_describe")
+        return buf.value.decode()
 
     # ---- per-kernel timing -----------------------------------------------
     def profile_enable(self, classes=()):

@@ -1,7 +1,11 @@
 // C ABI entry points (declared in include/eqs.h). Every call validates its
 // arguments, runs under a catch-all so that no exception crosses the ABI, and
 // records a thread-local message on failure.
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <new>
 #include <set>
 
@@ -70,6 +74,10 @@ int eqs_create(eqs_ctx** out, int device, void* hip_stream) {
         eqs_ctx* c = new eqs_ctx();
         c->device = device;
         c->stream = (hipStream_t)hip_stream;
+        const char* g = std::getenv("EQS_USE_GRAPHS");  // "0" replays CG iterations as plain launches
+        c->use_graphs = !(g && g[0] == '0');
+        const char* at = std::getenv("EQS_AUTOTUNE");  // "0" keeps the rule-based operator layouts
+        c->autotune = !(at && at[0] == '0');
         *out = c;
         return EQS_OK;
     });
@@ -208,13 +216,13 @@ int eqs_query(const eqs_ctx* c, eqs_info* info) {
                 o.n_levels = (int32_t)c->h32.lv.size();
                 for (size_t l = 0; l < c->h32.lv.size() && l < 16; ++l) {
                     o.level_rows[l] = c->h32.lv[l].n;
-                    o.level_nnz[l] = c->h32.lv[l].A.stored;
+                    o.level_nnz[l] = c->h32.lv[l].A.nnz;
                 }
             } else {
                 o.n_levels = (int32_t)c->h64.lv.size();
                 for (size_t l = 0; l < c->h64.lv.size() && l < 16; ++l) {
                     o.level_rows[l] = c->h64.lv[l].n;
-                    o.level_nnz[l] = c->h64.lv[l].A.stored;
+                    o.level_nnz[l] = c->h64.lv[l].A.nnz;
                 }
             }
         }
@@ -382,6 +390,29 @@ int eqs_mlp_get(eqs_mlp* net, float* params_host, float* grad_host) {
     return guarded([&] {
         need(net != nullptr, "NULL argument");
         eqs::mlp_get(net, params_host, grad_host);
+        return EQS_OK;
+    });
+}
+
+int eqs_describe(const eqs_ctx* c, char* buf, int64_t cap, int64_t* needed) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        std::string d;
+        char line[200];
+        std::snprintf(line, sizeof line, "nodes %lld tets %lld free %lld nnz(M) %lld precision %s built %d\n",
+                      (long long)c->n_nodes, (long long)c->n_tets, (long long)c->n_free, (long long)c->nnz_M,
+                      c->amg.precision == EQS_PREC_FP32 ? "fp32" : "fp64", (int)c->built);
+        d += line;
+        std::snprintf(line, sizeof line, "element blocks %lld, max nodes per block %d, graphs %d, autotune %d\n",
+                      (long long)c->n_blocks, c->max_block_nodes, (int)c->use_graphs, (int)c->autotune);
+        d += line;
+        d += c->tune_log;
+        if (needed) *needed = (int64_t)d.size() + 1;
+        if (buf && cap > 0) {
+            const size_t n = std::min<size_t>((size_t)cap - 1, d.size());
+            std::memcpy(buf, d.data(), n);
+            buf[n] = 0;
+        }
         return EQS_OK;
     });
 }

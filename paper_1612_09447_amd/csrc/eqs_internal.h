@@ -28,6 +28,7 @@
 namespace eqs {
 
 constexpr int kSlice = 64;   // SELL slice height = wavefront size
+constexpr int kTetBlock = 256;  // tets per element-pass workgroup
 constexpr int kBlock = 256;  // threads per block for streaming kernels
 
 // ---------------------------------------------------------------- errors
@@ -61,6 +62,23 @@ struct Sell {
     int32_t* sptr = nullptr;    // [n_slices + 1]
     int32_t* col = nullptr;     // [stored]
     T* val = nullptr;           // [stored]
+};
+
+// A hierarchy operator in one of two layouts, chosen per matrix from its
+// mean row length: SELL-64 (one lane per row) for short rows, or CSR with
+// `lanes` lanes per row (a power of two <= 64) whose partial sums are combined
+// by cross-lane shuffles, for long rows (coarse AMG operators).
+enum { FMT_SELL = 0, FMT_CSR = 1 };
+template <typename T>
+struct SpMat {
+    int fmt = FMT_SELL;
+    int lanes = 1;
+    Sell<T> sell;
+    int32_t n_rows = 0, n_cols = 0;
+    int32_t* rowptr = nullptr;  // CSR
+    int32_t* col = nullptr;
+    T* val = nullptr;
+    int64_t nnz = 0;
 };
 
 struct MatDev {
@@ -98,7 +116,7 @@ struct PcgScalars {
 template <typename T>
 struct Level {
     int32_t n = 0;
-    Sell<T> A, P, R;   // P, R unused on the coarsest level
+    SpMat<T> A, P, R;  // P, R unused on the coarsest level
     T* dinv = nullptr;
     double omega = 0;  // damped Jacobi weight
     T *b = nullptr, *x = nullptr, *xs = nullptr, *res = nullptr;
@@ -169,9 +187,15 @@ struct eqs_ctx {
     eqs_amg_params amg{};
     int64_t nnz_M = 0;
 
-    // device: mesh + materials
-    int4* d_conn = nullptr;
-    uint16_t* d_tmat = nullptr;
+    // device: mesh + materials. Tets are processed in blocks of kTetBlock
+    // (Morton order of centroids); block b lists its distinct nodes in
+    // d_bnodes[d_boff[b] .. d_boff[b+1]) and every tet packs the 12-bit
+    // block-local ids of its vertices and its 16-bit material id in 64 bits.
+    uint64_t* d_tpack = nullptr;
+    int32_t* d_bnodes = nullptr;
+    int32_t* d_boff = nullptr;
+    int64_t n_blocks = 0;
+    int32_t max_block_nodes = 0;
     double4* d_xyz = nullptr;
     eqs::MatDev* d_mats = nullptr;
     int32_t* d_ddrive = nullptr;
@@ -195,10 +219,18 @@ struct eqs_ctx {
     hipEvent_t ev[2] = {nullptr, nullptr};
 
     int64_t device_bytes = 0;
-    std::vector<void*> allocations;
+    std::vector<std::pair<void*, size_t>> allocations;
+    bool autotune = true;  // time the candidate layouts of every AMG operator at build time
+    std::string tune_log;  // chosen layouts, one line per operator
 
     // start vectors
     eqs::GuessState guess;
+
+    // the CG iteration body captured once as a HIP graph (x is baked in)
+    bool use_graphs = true;
+    hipGraphExec_t iter_exec = nullptr;
+    const double* iter_x = nullptr;
+    int iter_prec = -1;
 
     // per-kernel-class timing (HIP event pairs around launches)
     uint32_t prof_mask = 0;
@@ -222,10 +254,16 @@ void rkc_coefficients(int s, std::vector<double>& mu, std::vector<double>& nu, s
 
 // device upload
 void* dev_alloc(eqs_ctx* c, size_t bytes);
+void dev_free(eqs_ctx* c, void* p);
+template <typename T>
+double time_mv(eqs_ctx* c, const SpMat<T>& A, const T* x, T* y, int reps);
 void upload(eqs_ctx* c);
+void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i);
 void free_device(eqs_ctx* c);
 template <typename T>
 Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A);
+template <typename T>
+SpMat<T> to_spmat(eqs_ctx* c, const Csr<double>& A);
 
 DriveVals drive_values(const eqs_ctx* c, double t);
 
@@ -284,5 +322,6 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
 int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double rtol, int32_t maxit,
              eqs_step_stats* st);
 void apply_preconditioner(eqs_ctx* c, const double* r, double* z);
+void release_graphs(eqs_ctx* c);
 
 }  // namespace eqs

@@ -11,6 +11,8 @@
 //  * CG vector updates with block partial sums; one-block finalisers turn the
 //    partials into the CG scalars, kept in device memory.
 //  * RKC stage combination (the paper's ref. [9]).
+#include <algorithm>
+
 #include "eqs_internal.h"
 
 namespace eqs {
@@ -29,11 +31,21 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
-// Sum of partials[0..n) by one block, in a fixed order; valid in thread 0.
+// Sum of partials[0..n) by one block of kFin threads, in a fixed order; valid
+// in thread 0. sh must hold kFin / 64 doubles.
+constexpr int kFin = 1024;
 __device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int64_t n, double* sh) {
     double v = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
-    return block_sum(v, sh);
+    for (int64_t i = threadIdx.x; i < n; i += kFin) v += part[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kFin / 64; ++w) r += sh[w];
+    return r;
 }
 
 // ------------------------------------------------------------- simple ops
@@ -101,81 +113,104 @@ __device__ __forceinline__ double ipow(double x, int n) {
     return r;
 }
 
-// One thread per tetrahedron. With edges e_k = p_k - p_0 and cofactor rows
-// c_1 = e2 x e3, c_2 = e3 x e1, c_3 = e1 x e2, c_0 = -(c_1 + c_2 + c_3),
-// det = e1 . c_1: the barycentric gradients are c_a / det, so
-//   w = sum_k c_k (u_k - u_0) = det * grad(phi),   |E| = |w| / |det|,
-//   (A_e u)_a = |T| g_a . grad(phi) = c_a . w / (6 |det|).
-// RHS mode adds eps * A_e g' for the Dirichlet vertices (b(t) = -M_ID g'(t),
-// folded element by element) and writes -(...) for free vertices only.
+// Fused element pass over blocks of kTetBlock tets (one workgroup each).
+// 1. The block's distinct nodes are staged in LDS: coordinates, potential
+//    (free: y[id]; Dirichlet: g(t) of its drive) and drive rate g'(t).
+// 2. One thread per tet: with edges e_k = p_k - p_0 and cofactor rows
+//    c_1 = e2 x e3, c_2 = e3 x e1, c_3 = e1 x e2, c_0 = -(c_1 + c_2 + c_3),
+//    det = e1 . c_1, the barycentric gradients are c_a / det, so
+//      w = sum_k c_k (u_k - u_0) = det * grad(phi),  |E| = |w| / |det|,
+//      (A_e u)_a = |T| g_a . grad(phi) = c_a . w / (6 |det|).
+//    kappa(|E|) scales w; RHS mode adds eps * A_e g' (b(t) = -M_ID g'(t),
+//    folded in element by element). Contributions go to an LDS accumulator.
+// 3. One global atomic per block node (RHS mode: free nodes only, negated).
 template <bool RHS>
-__global__ __launch_bounds__(256) void k_kx(int64_t n_tets, const int4* __restrict__ conn,
-                                             const uint16_t* __restrict__ tmat, const double4* __restrict__ xyz,
-                                             const MatDev* __restrict__ mats, const double* __restrict__ yfree,
-                                             int32_t n_free, const int32_t* __restrict__ ddrive, DriveVals dv,
-                                             double* __restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_tets) return;
-    const int4 v = conn[e];
-    const MatDev m = mats[tmat[e]];
-    const double4 p0 = xyz[v.x], p1 = xyz[v.y], p2 = xyz[v.z], p3 = xyz[v.w];
-
-    bool bnd = false;
-    double u[4], r[4] = {0.0, 0.0, 0.0, 0.0};
-    const int id[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        if (id[a] < n_free) {
-            u[a] = yfree[id[a]];
+__global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, const uint64_t* __restrict__ tpack,
+                                                   const int32_t* __restrict__ boff,
+                                                   const int32_t* __restrict__ bnodes,
+                                                   const double4* __restrict__ xyz, const MatDev* __restrict__ mats,
+                                                   const double* __restrict__ yfree, int32_t n_free,
+                                                   const int32_t* __restrict__ ddrive, DriveVals dv,
+                                                   double* __restrict__ out) {
+    extern __shared__ double lds[];
+    const int32_t b = blockIdx.x;
+    const int32_t off = boff[b];
+    const int32_t nn = boff[b + 1] - off;
+    double4* P = reinterpret_cast<double4*>(lds);  // x, y, z, potential
+    double* R = lds + 4 * (size_t)nn;              // drive rate (0 for free nodes)
+    double* Acc = R + nn;
+    for (int k = threadIdx.x; k < nn; k += kTetBlock) {
+        const int32_t id = bnodes[off + k];
+        double4 p = xyz[id];
+        double rate = 0.0;
+        if (id < n_free) {
+            p.w = yfree[id];
         } else {
-            const int d = ddrive[id[a] - n_free];
-            u[a] = dv.g[d];
-            r[a] = dv.gd[d];
-            bnd = true;
+            const int d = ddrive[id - n_free];
+            p.w = dv.g[d];
+            rate = dv.gd[d];
         }
+        P[k] = p;
+        R[k] = rate;
+        Acc[k] = 0.0;
     }
-    const double e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
-    const double e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
-    const double e3x = p3.x - p0.x, e3y = p3.y - p0.y, e3z = p3.z - p0.z;
-    const double c1x = e2y * e3z - e2z * e3y, c1y = e2z * e3x - e2x * e3z, c1z = e2x * e3y - e2y * e3x;
-    const double c2x = e3y * e1z - e3z * e1y, c2y = e3z * e1x - e3x * e1z, c2z = e3x * e1y - e3y * e1x;
-    const double c3x = e1y * e2z - e1z * e2y, c3y = e1z * e2x - e1x * e2z, c3z = e1x * e2y - e1y * e2x;
-    const double det = e1x * c1x + e1y * c1y + e1z * c1z;
-    const double adet = fabs(det);
+    __syncthreads();
 
-    const double d1 = u[1] - u[0], d2 = u[2] - u[0], d3 = u[3] - u[0];
-    double wx = c1x * d1 + c2x * d2 + c3x * d3;
-    double wy = c1y * d1 + c2y * d2 + c3y * d3;
-    double wz = c1z * d1 + c2z * d2 + c3z * d3;
-
-    double kappa = m.kappa0;
-    if (m.nonlinear) {
-        const double ratio = sqrt(wx * wx + wy * wy + wz * wz) / adet * m.inv_es;
-        const double pw = (m.ialpha >= 0) ? ipow(ratio, m.ialpha) : pow(ratio, m.alpha);
-        kappa *= 1.0 + pw;
-    }
-    wx *= kappa;
-    wy *= kappa;
-    wz *= kappa;
-    if (RHS && bnd) {
-        const double q1 = r[1] - r[0], q2 = r[2] - r[0], q3 = r[3] - r[0];
-        wx += m.eps * (c1x * q1 + c2x * q2 + c3x * q3);
-        wy += m.eps * (c1y * q1 + c2y * q2 + c3y * q3);
-        wz += m.eps * (c1z * q1 + c2z * q2 + c3z * q3);
-    }
-    const double sc = 1.0 / (6.0 * adet);
-    double y[4];
-    y[1] = (c1x * wx + c1y * wy + c1z * wz) * sc;
-    y[2] = (c2x * wx + c2y * wy + c2z * wz) * sc;
-    y[3] = (c3x * wx + c3y * wy + c3z * wz) * sc;
-    y[0] = -(y[1] + y[2] + y[3]);
+    const int64_t e = (int64_t)b * kTetBlock + threadIdx.x;
+    if (e < n_tets) {
+        const uint64_t w = tpack[e];
+        const MatDev m = mats[(uint32_t)(w & 0xffffu)];
+        int l[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+        for (int a = 0; a < 4; ++a) l[a] = (int)((w >> (16 + 12 * a)) & 0xfffu);
+        const double4 p0 = P[l[0]], p1 = P[l[1]], p2 = P[l[2]], p3 = P[l[3]];
+        const double e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
+        const double e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
+        const double e3x = p3.x - p0.x, e3y = p3.y - p0.y, e3z = p3.z - p0.z;
+        const double c1x = e2y * e3z - e2z * e3y, c1y = e2z * e3x - e2x * e3z, c1z = e2x * e3y - e2y * e3x;
+        const double c2x = e3y * e1z - e3z * e1y, c2y = e3z * e1x - e3x * e1z, c2z = e3x * e1y - e3y * e1x;
+        const double c3x = e1y * e2z - e1z * e2y, c3y = e1z * e2x - e1x * e2z, c3z = e1x * e2y - e1y * e2x;
+        const double det = e1x * c1x + e1y * c1y + e1z * c1z;
+        const double adet = fabs(det);
+
+        const double d1 = p1.w - p0.w, d2 = p2.w - p0.w, d3 = p3.w - p0.w;
+        double wx = c1x * d1 + c2x * d2 + c3x * d3;
+        double wy = c1y * d1 + c2y * d2 + c3y * d3;
+        double wz = c1z * d1 + c2z * d2 + c3z * d3;
+
+        double kappa = m.kappa0;
+        if (m.nonlinear) {
+            const double ratio = sqrt(wx * wx + wy * wy + wz * wz) / adet * m.inv_es;
+            const double pw = (m.ialpha >= 0) ? ipow(ratio, m.ialpha) : pow(ratio, m.alpha);
+            kappa *= 1.0 + pw;
+        }
+        wx *= kappa;
+        wy *= kappa;
+        wz *= kappa;
         if (RHS) {
-            if (id[a] < n_free) unsafeAtomicAdd(&out[id[a]], -y[a]);
-        } else {
-            unsafeAtomicAdd(&out[id[a]], y[a]);
+            const double r0 = R[l[0]], r1 = R[l[1]], r2 = R[l[2]], r3 = R[l[3]];
+            if (r0 != 0.0 || r1 != 0.0 || r2 != 0.0 || r3 != 0.0) {
+                const double q1 = r1 - r0, q2 = r2 - r0, q3 = r3 - r0;
+                wx += m.eps * (c1x * q1 + c2x * q2 + c3x * q3);
+                wy += m.eps * (c1y * q1 + c2y * q2 + c3y * q3);
+                wz += m.eps * (c1z * q1 + c2z * q2 + c3z * q3);
+            }
         }
+        const double sc = (RHS ? -1.0 : 1.0) / (6.0 * adet);
+        const double y1 = (c1x * wx + c1y * wy + c1z * wz) * sc;
+        const double y2 = (c2x * wx + c2y * wy + c2z * wz) * sc;
+        const double y3 = (c3x * wx + c3y * wy + c3z * wz) * sc;
+        const double y0 = -(y1 + y2 + y3);
+        unsafeAtomicAdd(&Acc[l[0]], y0);
+        unsafeAtomicAdd(&Acc[l[1]], y1);
+        unsafeAtomicAdd(&Acc[l[2]], y2);
+        unsafeAtomicAdd(&Acc[l[3]], y3);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nn; k += kTetBlock) {
+        const int32_t id = bnodes[off + k];
+        if (RHS && id >= n_free) continue;
+        unsafeAtomicAdd(&out[id], Acc[k]);
     }
 }
 
@@ -183,14 +218,15 @@ void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, Dr
     const int64_t nout = rhs_mode ? c->n_free : c->n_nodes;
     launch_fill(s, out, 0.0, nout);
     if (c->n_tets == 0) return;
-    dim3 g(grid_for(c->n_tets)), b(kBlock);
+    dim3 g((unsigned)c->n_blocks), b(kTetBlock);
+    const size_t lds = sizeof(double) * 6 * (size_t)c->max_block_nodes;
     prof_begin(c, EQS_KCLASS_ELEMENT, s);
     if (rhs_mode)
-        hipLaunchKernelGGL(k_kx<true>, g, b, 0, s, c->n_tets, c->d_conn, c->d_tmat, c->d_xyz, c->d_mats, yfree,
-                           (int32_t)c->n_free, c->d_ddrive, dv, out);
+        hipLaunchKernelGGL(k_kx<true>, g, b, lds, s, c->n_tets, c->d_tpack, c->d_boff, c->d_bnodes, c->d_xyz,
+                           c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, dv, out);
     else
-        hipLaunchKernelGGL(k_kx<false>, g, b, 0, s, c->n_tets, c->d_conn, c->d_tmat, c->d_xyz, c->d_mats, yfree,
-                           (int32_t)c->n_free, c->d_ddrive, dv, out);
+        hipLaunchKernelGGL(k_kx<false>, g, b, lds, s, c->n_tets, c->d_tpack, c->d_boff, c->d_bnodes, c->d_xyz,
+                           c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, dv, out);
     prof_end(c, EQS_KCLASS_ELEMENT, s);
 }
 
@@ -282,7 +318,7 @@ template <typename T, typename TB, typename TO, bool DOT>
 __global__ __launch_bounds__(256) void k_postsmooth(SellView<T> A, const T* __restrict__ dinv, T omega,
                                                      const TB* __restrict__ b, const T* __restrict__ x,
                                                      TO* __restrict__ out, double* __restrict__ part_rz,
-                                                     double* __restrict__ part_rzold, int64_t part_stride,
+                                                     double* __restrict__ part_rzold,
                                                      const PcgScalars* __restrict__ scal) {
     __shared__ double sh[4];
     if (scal && scal->done) return;
@@ -308,19 +344,186 @@ __global__ __launch_bounds__(256) void k_postsmooth(SellView<T> A, const T* __re
             part_rzold[blockIdx.x] = s2;
         }
     }
-    (void)part_stride;
 }
 
-// Coarsest level: x = A^{-1} b with the dense inverse (column-major, symmetric).
+// ---- CSR with L lanes per row (long rows of coarse operators) ----------
+template <typename T>
+struct CsrView {
+    const int32_t* __restrict__ rp;
+    const int32_t* __restrict__ col;
+    const T* __restrict__ val;
+    int32_t n_rows;
+};
+template <typename T>
+static CsrView<T> cview(const SpMat<T>& A) {
+    return CsrView<T>{A.rowptr, A.col, A.val, A.n_rows};
+}
+
+template <int L, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
+    return v;
+}
+
+// Row sum of A (lanes of one group split the row), with x_j given by f(j).
+template <int L, typename T, typename F>
+__device__ __forceinline__ T csr_row(const CsrView<T>& A, int32_t row, int lane, F f) {
+    T acc = T(0);
+    for (int32_t k = A.rp[row] + lane; k < A.rp[row + 1]; k += L) acc += A.val[k] * f(A.col[k]);
+    return group_sum<L>(acc);
+}
+
+template <int L, typename T>
+__global__ __launch_bounds__(256) void k_csr_mv(CsrView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
+                                                 const PcgScalars* __restrict__ scal) {
+    if (scal && scal->done) return;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t row = (int32_t)(g / L);
+    const int lane = (int)(g % L);
+    if (row >= A.n_rows) return;  // whole groups leave together
+    const T v = csr_row<L>(A, row, lane, [&](int32_t j) { return x[j]; });
+    if (lane == 0) y[row] = acc ? y[row] + v : v;
+}
+
+template <int L, typename T, typename TB>
+__global__ __launch_bounds__(256) void k_csr_presmooth_res(CsrView<T> A, const T* __restrict__ dinv, T omega,
+                                                            const TB* __restrict__ b, T* __restrict__ x,
+                                                            T* __restrict__ res, const PcgScalars* __restrict__ scal) {
+    if (scal && scal->done) return;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t row = (int32_t)(g / L);
+    const int lane = (int)(g % L);
+    if (row >= A.n_rows) return;
+    const T acc = csr_row<L>(A, row, lane, [&](int32_t j) { return dinv[j] * (T)b[j]; });
+    if (lane == 0) {
+        const T bi = (T)b[row];
+        x[row] = omega * dinv[row] * bi;
+        res[row] = bi - omega * acc;
+    }
+}
+
+template <int L, typename T, typename TB, typename TO, bool DOT>
+__global__ __launch_bounds__(256) void k_csr_postsmooth(CsrView<T> A, const T* __restrict__ dinv, T omega,
+                                                         const TB* __restrict__ b, const T* __restrict__ x,
+                                                         TO* __restrict__ out, double* __restrict__ part_rz,
+                                                         double* __restrict__ part_rzold,
+                                                         const PcgScalars* __restrict__ scal) {
+    __shared__ double sh[4];
+    if (scal && scal->done) return;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t row = (int32_t)(g / L);
+    const int lane = (int)(g % L);
+    double rz = 0.0, rzo = 0.0;
+    if (row < A.n_rows) {
+        const T ax = csr_row<L>(A, row, lane, [&](int32_t j) { return x[j]; });
+        if (lane == 0) {
+            const T v = x[row] + omega * dinv[row] * ((T)b[row] - ax);
+            if (DOT) {
+                const double ri = (double)b[row];
+                rzo = ri * (double)out[row];
+                rz = ri * (double)v;
+            }
+            out[row] = (TO)v;
+        }
+    }
+    if (DOT) {
+        const double s1 = block_sum(rz, sh);
+        const double s2 = block_sum(rzo, sh);
+        if (threadIdx.x == 0) {
+            part_rz[blockIdx.x] = s1;
+            part_rzold[blockIdx.x] = s2;
+        }
+    }
+}
+
+template <typename T>
+static unsigned csr_grid(const SpMat<T>& A) {
+    return (unsigned)(((int64_t)A.n_rows * A.lanes + kBlock - 1) / kBlock);
+}
+
+#define EQS_LANES_SWITCH(Lvar, CALL) \
+    switch (Lvar) {                  \
+        case 2: { constexpr int L_ = 2; CALL; } break;   \
+        case 4: { constexpr int L_ = 4; CALL; } break;   \
+        case 8: { constexpr int L_ = 8; CALL; } break;   \
+        case 16: { constexpr int L_ = 16; CALL; } break; \
+        case 32: { constexpr int L_ = 32; CALL; } break; \
+        default: { constexpr int L_ = 64; CALL; } break; \
+    }
+
+template <typename T>
+static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int acc, const PcgScalars* scal) {
+    if (A.fmt == FMT_SELL) {
+        hipLaunchKernelGGL(k_sell_mv<T>, dim3(sell_grid(A.sell)), dim3(kBlock), 0, s, view(A.sell), x, y, acc, scal);
+    } else {
+        EQS_LANES_SWITCH(A.lanes, hipLaunchKernelGGL((k_csr_mv<L_, T>), dim3(csr_grid(A)), dim3(kBlock), 0, s,
+                                                     cview(A), x, y, acc, scal));
+    }
+}
+
+template <typename T, typename TB>
+static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, const PcgScalars* scal) {
+    if (lv.A.fmt == FMT_SELL) {
+        hipLaunchKernelGGL((k_presmooth_res<T, TB>), dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s, view(lv.A.sell),
+                           (const T*)lv.dinv, (T)lv.omega, b, lv.x, lv.res, scal);
+    } else {
+        EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_presmooth_res<L_, T, TB>), dim3(csr_grid(lv.A)),
+                                                        dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
+                                                        (T)lv.omega, b, lv.x, lv.res, scal));
+    }
+}
+
+template <typename T, typename TB, typename TO, bool DOT>
+static void launch_postsmooth(hipStream_t s, const Level<T>& lv, const TB* b, const T* x, TO* out, double* prz,
+                              double* przo, const PcgScalars* scal) {
+    if (lv.A.fmt == FMT_SELL) {
+        hipLaunchKernelGGL((k_postsmooth<T, TB, TO, DOT>), dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
+                           view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, b, x, out, prz, przo, scal);
+    } else {
+        EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_postsmooth<L_, T, TB, TO, DOT>), dim3(csr_grid(lv.A)),
+                                                        dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
+                                                        (T)lv.omega, b, x, out, prz, przo, scal));
+    }
+}
+
+template <typename T>
+double time_mv(eqs_ctx* c, const SpMat<T>& A, const T* x, T* y, int reps) {
+    hipEvent_t e0, e1;
+    EQS_HIP(hipEventCreate(&e0));
+    EQS_HIP(hipEventCreate(&e1));
+    std::vector<float> ms;
+    for (int r = 0; r < reps + 2; ++r) {
+        EQS_HIP(hipEventRecord(e0, c->stream));
+        launch_mv<T>(c->stream, A, x, y, 0, nullptr);
+        EQS_HIP(hipEventRecord(e1, c->stream));
+        EQS_HIP(hipEventSynchronize(e1));
+        float t = 0.0f;
+        EQS_HIP(hipEventElapsedTime(&t, e0, e1));
+        if (r >= 2) ms.push_back(t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::sort(ms.begin(), ms.end());
+    return ms[ms.size() / 2];
+}
+template double time_mv<double>(eqs_ctx*, const SpMat<double>&, const double*, double*, int);
+template double time_mv<float>(eqs_ctx*, const SpMat<float>&, const float*, float*, int);
+
+// Coarsest level: x = A^{-1} b with the dense inverse. The inverse is
+// symmetric, so row i is stored contiguously (column i); one wavefront per row
+// splits the dot product over its 64 lanes.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const T* __restrict__ b,
                                                  T* __restrict__ x, int32_t n, const PcgScalars* __restrict__ scal) {
     if (scal && scal->done) return;
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (i >= n) return;
     T acc = T(0);
-    for (int32_t k = 0; k < n; ++k) acc += inv[(int64_t)k * n + i] * b[k];
-    x[i] = acc;
+    for (int32_t k = lane; k < n; k += 64) acc += inv[(int64_t)i * n + k] * b[k];
+    acc = group_sum<64>(acc);
+    if (lane == 0) x[i] = acc;
 }
 
 // Single-level hierarchy: z = A^{-1} r with the same r.z partials as k_postsmooth.
@@ -352,6 +555,16 @@ __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv
     }
 }
 
+// Number of blocks of the finest-level kernel that writes the r.z partials.
+template <typename T>
+int64_t finest_blocks(const Hierarchy<T>& h) {
+    const Level<T>& lv = h.lv[0];
+    if (h.lv.size() == 1) return grid_for(lv.n);
+    return lv.A.fmt == FMT_SELL ? (int64_t)sell_grid(lv.A.sell) : (int64_t)csr_grid(lv.A);
+}
+template int64_t finest_blocks<double>(const Hierarchy<double>&);
+template int64_t finest_blocks<float>(const Hierarchy<float>&);
+
 // V(1,1) cycle z = B r. r and z are FP64 (CG's vectors); the hierarchy is T.
 template <typename T>
 void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double* z, double* part_rz,
@@ -375,39 +588,31 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         Level<T>& lv = h.lv[l];
         if (l == 0) {
             prof_begin(c, EQS_KCLASS_PRESMOOTH0, s);
-            hipLaunchKernelGGL((k_presmooth_res<T, double>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A), lv.dinv,
-                               (T)lv.omega, r, lv.x, lv.res, scal);
+            launch_presmooth<T, double>(s, lv, r, scal);
             prof_end(c, EQS_KCLASS_PRESMOOTH0, s);
-        } else
-            hipLaunchKernelGGL((k_presmooth_res<T, T>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A), lv.dinv,
-                               (T)lv.omega, (const T*)lv.b, lv.x, lv.res, scal);
-        hipLaunchKernelGGL(k_sell_mv<T>, dim3(sell_grid(lv.R)), b, 0, s, view(lv.R), (const T*)lv.res,
-                           h.lv[l + 1].b, 0, scal);
+        } else {
+            launch_presmooth<T, T>(s, lv, (const T*)lv.b, scal);
+        }
+        launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, scal);
     }
     {
         Level<T>& lc = h.lv[L - 1];
-        hipLaunchKernelGGL(k_coarse<T>, dim3(grid_for(lc.n)), b, 0, s, (const T*)lc.dense_inv, (const T*)lc.b, lc.x,
-                           lc.n, scal);
+        hipLaunchKernelGGL(k_coarse<T>, dim3(grid_for((int64_t)lc.n * 64)), b, 0, s, (const T*)lc.dense_inv,
+                           (const T*)lc.b, lc.x, lc.n, scal);
     }
     // ascend
     for (int l = L - 2; l >= 0; --l) {
         Level<T>& lv = h.lv[l];
         const T* xc = (l + 1 == L - 1) ? h.lv[l + 1].x : h.lv[l + 1].xs;
-        hipLaunchKernelGGL(k_sell_mv<T>, dim3(sell_grid(lv.P)), b, 0, s, view(lv.P), xc, lv.x, 1, scal);
+        launch_mv<T>(s, lv.P, xc, lv.x, 1, scal);
         if (l > 0) {
-            hipLaunchKernelGGL((k_postsmooth<T, T, T, false>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A), lv.dinv,
-                               (T)lv.omega, (const T*)lv.b, (const T*)lv.x, lv.xs, (double*)nullptr,
-                               (double*)nullptr, (int64_t)0, scal);
+            launch_postsmooth<T, T, T, false>(s, lv, (const T*)lv.b, (const T*)lv.x, lv.xs, nullptr, nullptr, scal);
         } else if (part_rz) {
             prof_begin(c, EQS_KCLASS_POSTSMOOTH0, s);
-            hipLaunchKernelGGL((k_postsmooth<T, double, double, true>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A),
-                               lv.dinv, (T)lv.omega, r, (const T*)lv.x, z, part_rz, part_rzold, c->max_blocks,
-                               scal);
+            launch_postsmooth<T, double, double, true>(s, lv, r, (const T*)lv.x, z, part_rz, part_rzold, scal);
             prof_end(c, EQS_KCLASS_POSTSMOOTH0, s);
         } else {
-            hipLaunchKernelGGL((k_postsmooth<T, double, double, false>), dim3(sell_grid(lv.A)), b, 0, s, view(lv.A),
-                               lv.dinv, (T)lv.omega, r, (const T*)lv.x, z, (double*)nullptr, (double*)nullptr,
-                               (int64_t)0, scal);
+            launch_postsmooth<T, double, double, false>(s, lv, r, (const T*)lv.x, z, nullptr, nullptr, scal);
         }
     }
 }
@@ -496,10 +701,10 @@ __global__ __launch_bounds__(256) void k_pcg_update(double* __restrict__ x, doub
 // mode 0: start of a solve (it = 0); mode 1: restart from the true residual
 // (iteration count kept). Sets done when |r| <= rtol |rhs|, rhs = 0 or the
 // iteration budget is spent. The scalars are mirrored to host memory.
-__global__ void k_fin_start(PcgScalars* __restrict__ s, PcgScalars* __restrict__ host, const double* __restrict__ prr,
+__global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, PcgScalars* __restrict__ host, const double* __restrict__ prr,
                             const double* __restrict__ pbb, int64_t nb, double rtol, int32_t maxit, int32_t flexible,
                             int32_t mode) {
-    __shared__ double sh[4];
+    __shared__ double sh[kFin / 64];
     const double rr = reduce_partials(prr, nb, sh);
     const double bb = reduce_partials(pbb, nb, sh);
     if (threadIdx.x != 0) return;
@@ -531,9 +736,9 @@ __global__ void k_fin_start(PcgScalars* __restrict__ s, PcgScalars* __restrict__
 }
 
 // beta from r.z (Polak-Ribiere with r.z_old when flexible).
-__global__ void k_fin_beta(PcgScalars* __restrict__ s, const double* __restrict__ prz,
+__global__ __launch_bounds__(kFin) void k_fin_beta(PcgScalars* __restrict__ s, const double* __restrict__ prz,
                            const double* __restrict__ przold, int64_t nb) {
-    __shared__ double sh[4];
+    __shared__ double sh[kFin / 64];
     if (s->done) return;
     const double rz = reduce_partials(prz, nb, sh);
     const double rzo = reduce_partials(przold, nb, sh);
@@ -548,8 +753,8 @@ __global__ void k_fin_beta(PcgScalars* __restrict__ s, const double* __restrict_
     s->rho = rz;
 }
 
-__global__ void k_fin_alpha(PcgScalars* __restrict__ s, const double* __restrict__ ppq, int64_t nb) {
-    __shared__ double sh[4];
+__global__ __launch_bounds__(kFin) void k_fin_alpha(PcgScalars* __restrict__ s, const double* __restrict__ ppq, int64_t nb) {
+    __shared__ double sh[kFin / 64];
     if (s->done) return;
     const double pq = reduce_partials(ppq, nb, sh);
     if (threadIdx.x != 0) return;
@@ -562,9 +767,9 @@ __global__ void k_fin_alpha(PcgScalars* __restrict__ s, const double* __restrict
     s->fresh = 0;
 }
 
-__global__ void k_fin_conv(PcgScalars* __restrict__ s, PcgScalars* __restrict__ host, const double* __restrict__ prr,
+__global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, PcgScalars* __restrict__ host, const double* __restrict__ prr,
                            int64_t nb) {
-    __shared__ double sh[4];
+    __shared__ double sh[kFin / 64];
     if (s->done) {
         if (threadIdx.x == 0) host->done = 1;
         return;
@@ -596,7 +801,7 @@ void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int
     double* P = c->d_partials;
     hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), rhs, x, c->d_r, P,
                        P + c->max_blocks);
-    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kBlock), 0, s, c->d_scal, host_mirror(c), P, P + c->max_blocks,
+    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, host_mirror(c), P, P + c->max_blocks,
                        nb, rtol, maxit, flexible, 0);
 }
 
@@ -605,7 +810,7 @@ void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const doubl
     double* P = c->d_partials;
     hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), rhs, x, c->d_r, P,
                        P + c->max_blocks);
-    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kBlock), 0, s, c->d_scal, host_mirror(c), P, P + c->max_blocks,
+    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, host_mirror(c), P, P + c->max_blocks,
                        nb, 0.0, 0, 0, 1);
 }
 
@@ -622,18 +827,18 @@ void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int 
     if (precision == EQS_PREC_FP32) vcycle<float>(s, c, c->h32, c->d_r, c->d_z, P, c->d_scal);
     else vcycle<double>(s, c, c->h64, c->d_r, c->d_z, P, c->d_scal);
     prof_end(c, EQS_KCLASS_VCYCLE, s);
-    const int64_t nbz = nbV;  // the finest-level kernel that wrote the r.z partials has one block per 256 rows
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kBlock), 0, s, c->d_scal, P, P + mb, nbz);
+    const int64_t nbz = precision == EQS_PREC_FP32 ? finest_blocks(c->h32) : finest_blocks(c->h64);
+    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFin), 0, s, c->d_scal, P, P + mb, nbz);
     prof_begin(c, EQS_KCLASS_SPMV_M, s);
     hipLaunchKernelGGL(k_pcg_spmv, dim3(nbM), dim3(kBlock), 0, s, view(c->M), c->d_z, c->d_p, c->d_q, P + 2 * mb,
                        c->d_scal);
     prof_end(c, EQS_KCLASS_SPMV_M, s);
-    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kBlock), 0, s, c->d_scal, P + 2 * mb, nbM);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFin), 0, s, c->d_scal, P + 2 * mb, nbM);
     prof_begin(c, EQS_KCLASS_CG_UPDATE, s);
     hipLaunchKernelGGL(k_pcg_update, dim3(nbV), dim3(kBlock), 0, s, x, c->d_r, c->d_p, c->d_q, c->n_free,
                        P + 3 * mb, c->d_scal);
     prof_end(c, EQS_KCLASS_CG_UPDATE, s);
-    hipLaunchKernelGGL(k_fin_conv, dim3(1), dim3(kBlock), 0, s, c->d_scal, host_mirror(c), P + 3 * mb, nbV);
+    hipLaunchKernelGGL(k_fin_conv, dim3(1), dim3(kFin), 0, s, c->d_scal, host_mirror(c), P + 3 * mb, nbV);
 }
 
 // ------------------------------------------------------------------ RKC

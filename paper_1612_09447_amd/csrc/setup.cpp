@@ -6,6 +6,7 @@
 // upload of everything to device memory in SELL-64 form.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 
@@ -451,9 +452,20 @@ void* dev_alloc(eqs_ctx* c, size_t bytes) {
     if (bytes == 0) bytes = 8;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) fail(EQS_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
-    c->allocations.push_back(p);
+    c->allocations.push_back({p, bytes});
     c->device_bytes += (int64_t)bytes;
     return p;
+}
+
+void dev_free(eqs_ctx* c, void* p) {
+    if (!p) return;
+    for (size_t k = 0; k < c->allocations.size(); ++k)
+        if (c->allocations[k].first == p) {
+            (void)hipFree(p);
+            c->device_bytes -= (int64_t)c->allocations[k].second;
+            c->allocations.erase(c->allocations.begin() + k);
+            return;
+        }
 }
 
 template <typename T>
@@ -507,6 +519,103 @@ Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A) {
 template Sell<double> to_sell<double>(eqs_ctx*, const Csr<double>&);
 template Sell<float> to_sell<float>(eqs_ctx*, const Csr<double>&);
 
+// Layout choice: rows of up to 16 entries go one lane per row (SELL-64);
+// longer rows get L = 2^ceil(log2(mean/2)) lanes (2 <= L <= 64), so each lane
+// sums about two entries per pass and a wavefront covers 64/L rows.
+template <typename T>
+SpMat<T> to_spmat(eqs_ctx* c, const Csr<double>& A) {
+    SpMat<T> S;
+    S.n_rows = A.n_rows;
+    S.n_cols = A.n_cols;
+    S.nnz = A.nnz();
+    const double mean = A.n_rows ? (double)A.nnz() / A.n_rows : 0.0;
+    if (mean <= 16.0) {
+        S.fmt = FMT_SELL;
+        S.sell = to_sell<T>(c, A);
+        return S;
+    }
+    S.fmt = FMT_CSR;
+    int L = 2;
+    while (L < 64 && L < mean / 2.0) L *= 2;
+    S.lanes = L;
+    std::vector<T> v(A.val.size());
+    for (size_t k = 0; k < v.size(); ++k) v[k] = (T)A.val[k];
+    S.rowptr = upload_vec(c, A.ptr);
+    S.col = upload_vec(c, A.col);
+    S.val = upload_vec(c, v);
+    return S;
+}
+template SpMat<double> to_spmat<double>(eqs_ctx*, const Csr<double>&);
+template SpMat<float> to_spmat<float>(eqs_ctx*, const Csr<double>&);
+
+template <typename T>
+static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
+    dev_free(c, S.sell.sptr);
+    dev_free(c, S.sell.col);
+    dev_free(c, S.sell.val);
+    dev_free(c, S.rowptr);
+    dev_free(c, S.col);
+    dev_free(c, S.val);
+    S = SpMat<T>{};
+}
+
+// Autotuner: upload the operator in every candidate layout (SELL-64, CSR with
+// L = 2..64 lanes per row up to about twice the mean row length), time y = A x
+// with HIP events on the context's stream (median of 5 after 2 warm-ups) and
+// keep the fastest.
+template <typename T>
+static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what) {
+    if (!c->autotune || A.n_rows == 0) return to_spmat<T>(c, A);
+    const double mean = (double)A.nnz() / A.n_rows;
+    T* x = (T*)dev_alloc(c, sizeof(T) * std::max<int32_t>(A.n_cols, 1));
+    T* y = (T*)dev_alloc(c, sizeof(T) * std::max<int32_t>(A.n_rows, 1));
+    {
+        std::vector<T> ones(std::max<int32_t>(A.n_cols, 1), T(1));
+        EQS_HIP(hipMemcpy(x, ones.data(), sizeof(T) * ones.size(), hipMemcpyHostToDevice));
+    }
+    SpMat<T> best;
+    double best_ms = 1e300;
+    std::string best_name;
+    auto consider = [&](SpMat<T> cand, const std::string& name) {
+        const double ms = time_mv<T>(c, cand, x, y, 5);
+        if (ms < best_ms) {
+            if (best.n_rows || best.nnz) free_spmat(c, best);
+            best = cand;
+            best_ms = ms;
+            best_name = name;
+        } else {
+            free_spmat(c, cand);
+        }
+    };
+    {
+        SpMat<T> S;
+        S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
+        S.fmt = FMT_SELL;
+        S.sell = to_sell<T>(c, A);
+        consider(S, "sell64");
+    }
+    for (int L = 2; L <= 64; L *= 2) {
+        if (L > 2 && L / 2 > 2.0 * mean) break;
+        SpMat<T> S;
+        S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
+        S.fmt = FMT_CSR;
+        S.lanes = L;
+        std::vector<T> v(A.val.size());
+        for (size_t k = 0; k < v.size(); ++k) v[k] = (T)A.val[k];
+        S.rowptr = upload_vec(c, A.ptr);
+        S.col = upload_vec(c, A.col);
+        S.val = upload_vec(c, v);
+        consider(S, "csr" + std::to_string(L));
+    }
+    dev_free(c, x);
+    dev_free(c, y);
+    char line[160];
+    std::snprintf(line, sizeof line, "%s: %d x %d, %.1f nnz/row -> %s (%.1f us)\n", what, A.n_rows, A.n_cols, mean,
+                  best_name.c_str(), best_ms * 1e3);
+    c->tune_log += line;
+    return best;
+}
+
 template <typename T>
 static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, const double* level0_M_vals_hint) {
     (void)level0_M_vals_hint;
@@ -515,7 +624,7 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
     for (size_t l = 0; l < L; ++l) {
         Level<T>& lv = h.lv[l];
         lv.n = ah.A[l].n_rows;
-        lv.A = to_sell<T>(c, ah.A[l]);
+        lv.A = tuned_spmat<T>(c, ah.A[l], ("A" + std::to_string(l)).c_str());
         std::vector<double> d = diagonal(ah.A[l]);
         std::vector<T> dinv(lv.n);
         for (int32_t i = 0; i < lv.n; ++i) dinv[i] = (T)(1.0 / d[i]);
@@ -526,8 +635,8 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
         lv.xs = (T*)dev_alloc(c, sizeof(T) * lv.n);
         lv.res = (T*)dev_alloc(c, sizeof(T) * lv.n);
         if (l + 1 < L) {
-            lv.P = to_sell<T>(c, ah.P[l]);
-            lv.R = to_sell<T>(c, ah.R[l]);
+            lv.P = tuned_spmat<T>(c, ah.P[l], ("P" + std::to_string(l)).c_str());
+            lv.R = tuned_spmat<T>(c, ah.R[l], ("R" + std::to_string(l)).c_str());
         } else {
             std::vector<T> inv(ah.coarse_inv.size());
             for (size_t k = 0; k < inv.size(); ++k) inv[k] = (T)ah.coarse_inv[k];
@@ -536,18 +645,83 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
     }
 }
 
+// Morton key of a point quantised to 21 bits per axis inside the box [lo, hi].
+static uint64_t morton3(const double* p, const double* lo, const double* inv_ext) {
+    uint64_t key = 0;
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        double f = (p[d] - lo[d]) * inv_ext[d];
+        f = std::min(std::max(f, 0.0), 1.0);
+        q[d] = (uint32_t)(f * 2097151.0);
+    }
+    for (int bit = 20; bit >= 0; --bit)
+        for (int d = 0; d < 3; ++d) key = (key << 1) | ((q[d] >> bit) & 1u);
+    return key;
+}
+
+// Element blocks for the fused element pass: tets sorted by the Morton key of
+// their centroid, cut into blocks of kTetBlock; per block the sorted distinct
+// internal node ids, and per tet 4 x 12-bit block-local vertex ids | material.
+void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i) {
+    const int64_t T = c->n_tets;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < c->n_nodes; ++i)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], c->xyz[3 * i + d]);
+            hi[d] = std::max(hi[d], c->xyz[3 * i + d]);
+        }
+    double inv_ext[3];
+    for (int d = 0; d < 3; ++d) inv_ext[d] = hi[d] > lo[d] ? 1.0 / (hi[d] - lo[d]) : 0.0;
+    std::vector<std::pair<uint64_t, int32_t>> key(T);
+    for (int64_t e = 0; e < T; ++e) {
+        double cen[3] = {0, 0, 0};
+        for (int a = 0; a < 4; ++a)
+            for (int d = 0; d < 3; ++d) cen[d] += 0.25 * c->xyz[3 * (int64_t)c->tets[4 * e + a] + d];
+        key[e] = {morton3(cen, lo, inv_ext), (int32_t)e};
+    }
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint64_t, int32_t>& x, const std::pair<uint64_t, int32_t>& y) { return x.first < y.first; });
+    const int64_t nb = (T + kTetBlock - 1) / kTetBlock;
+    std::vector<uint64_t> pack(T);
+    std::vector<int32_t> boff(nb + 1, 0), bnodes;
+    bnodes.reserve((size_t)T);
+    std::vector<int32_t> ids;
+    int32_t maxn = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t e0 = b * kTetBlock, e1 = std::min<int64_t>(T, e0 + kTetBlock);
+        ids.clear();
+        for (int64_t k = e0; k < e1; ++k)
+            for (int a = 0; a < 4; ++a) ids.push_back(u2i[c->tets[4 * (int64_t)key[k].second + a]]);
+        std::sort(ids.begin(), ids.end());
+        ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+        if (ids.size() > 4095) fail(EQS_ERR_INVALID_ARG, "element block with more than 4095 nodes");
+        maxn = std::max<int32_t>(maxn, (int32_t)ids.size());
+        for (int64_t k = e0; k < e1; ++k) {
+            const int32_t e = key[k].second;
+            uint64_t w = (uint64_t)(uint16_t)c->tet_mat[e];
+            for (int a = 0; a < 4; ++a) {
+                const int32_t loc = (int32_t)(std::lower_bound(ids.begin(), ids.end(), u2i[c->tets[4 * (int64_t)e + a]]) - ids.begin());
+                w |= (uint64_t)loc << (16 + 12 * a);
+            }
+            pack[k] = w;
+        }
+        bnodes.insert(bnodes.end(), ids.begin(), ids.end());
+        if (bnodes.size() > (size_t)INT32_MAX) fail(EQS_ERR_INVALID_ARG, "too many block nodes");
+        boff[b + 1] = (int32_t)bnodes.size();
+    }
+    c->n_blocks = nb;
+    c->max_block_nodes = maxn;
+    c->d_tpack = upload_vec(c, pack);
+    c->d_bnodes = upload_vec(c, bnodes);
+    c->d_boff = upload_vec(c, boff);
+}
+
 void upload(eqs_ctx* c) {
     const int64_t N = c->n_nodes, T = c->n_tets, NF = c->n_free;
     std::vector<int32_t> u2i(N);
     for (int64_t i = 0; i < N; ++i) u2i[c->int_to_user[i]] = (int32_t)i;
 
-    std::vector<int4> conn(T);
-    for (int64_t e = 0; e < T; ++e) {
-        const int32_t* v = &c->tets[4 * e];
-        conn[e] = make_int4(u2i[v[0]], u2i[v[1]], u2i[v[2]], u2i[v[3]]);
-    }
-    std::vector<uint16_t> tm(T);
-    for (int64_t e = 0; e < T; ++e) tm[e] = (uint16_t)c->tet_mat[e];
+    build_element_blocks(c, u2i);
     std::vector<double4> xyz(N);
     for (int64_t i = 0; i < N; ++i) {
         const double* p = &c->xyz[3 * (int64_t)c->int_to_user[i]];
@@ -569,13 +743,12 @@ void upload(eqs_ctx* c) {
         for (size_t k = 0; k < c->dir_nodes.size(); ++k) drive_of[c->dir_nodes[k]] = c->dir_drive[k];
         for (int64_t k = 0; k < c->n_dir; ++k) dd[k] = drive_of[c->int_to_user[NF + k]];
     }
-    c->d_conn = upload_vec(c, conn);
-    c->d_tmat = upload_vec(c, tm);
     c->d_xyz = upload_vec(c, xyz);
     c->d_mats = upload_vec(c, md);
     c->d_ddrive = upload_vec(c, dd);
     c->d_int_to_user = upload_vec(c, c->int_to_user);
 
+    c->tune_log.clear();
     Csr<double> M = assemble_M_free(c);
     c->nnz_M = M.nnz();
     c->M = to_sell<double>(c, M);
@@ -598,7 +771,8 @@ void upload(eqs_ctx* c) {
 }
 
 void free_device(eqs_ctx* c) {
-    for (void* p : c->allocations) (void)hipFree(p);
+    release_graphs(c);
+    for (auto& a : c->allocations) (void)hipFree(a.first);
     c->allocations.clear();
     c->device_bytes = 0;
     if (c->h_scal) { (void)hipHostFree(c->h_scal); c->h_scal = nullptr; c->d_hscal = nullptr; }
@@ -607,7 +781,8 @@ void free_device(eqs_ctx* c) {
     c->M = Sell<double>{};
     c->h64.lv.clear();
     c->h32.lv.clear();
-    c->d_conn = nullptr; c->d_tmat = nullptr; c->d_xyz = nullptr; c->d_mats = nullptr;
+    c->d_tpack = nullptr; c->d_bnodes = nullptr; c->d_boff = nullptr; c->n_blocks = 0; c->max_block_nodes = 0;
+    c->d_xyz = nullptr; c->d_mats = nullptr;
     c->d_ddrive = nullptr; c->d_int_to_user = nullptr;
     c->d_r = c->d_z = c->d_p = c->d_q = nullptr;
     c->d_Y0 = c->d_Ya = c->d_Yb = c->d_F0 = c->d_F = nullptr;

@@ -28,6 +28,43 @@ static void check_launch() {
     if (e != hipSuccess) fail(EQS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
+// The kernels of one CG iteration take every scalar from device memory, so a
+// single captured graph replays any iteration of any solve into the same x.
+// Graphs are skipped on the null stream and while kernels of the iteration
+// are being timed individually.
+static void run_iteration(eqs_ctx* c, double* x, int prec) {
+    const uint32_t iter_classes = (1u << EQS_KCLASS_SPMV_M) | (1u << EQS_KCLASS_PRESMOOTH0) |
+                                  (1u << EQS_KCLASS_POSTSMOOTH0) | (1u << EQS_KCLASS_VCYCLE) |
+                                  (1u << EQS_KCLASS_CG_UPDATE);
+    if (!c->use_graphs || c->stream == nullptr || (c->prof_mask & iter_classes)) {
+        pcg_iteration(c->stream, c, nullptr, x, prec);
+        return;
+    }
+    if (c->iter_exec == nullptr || c->iter_x != x || c->iter_prec != prec) {
+        if (c->iter_exec) {
+            (void)hipGraphExecDestroy(c->iter_exec);
+            c->iter_exec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        EQS_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        pcg_iteration(c->stream, c, nullptr, x, prec);
+        EQS_HIP(hipStreamEndCapture(c->stream, &g));
+        hipError_t e = hipGraphInstantiate(&c->iter_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) fail(EQS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        c->iter_x = x;
+        c->iter_prec = prec;
+    }
+    EQS_HIP(hipGraphLaunch(c->iter_exec, c->stream));
+}
+
+void release_graphs(eqs_ctx* c) {
+    if (c->iter_exec) (void)hipGraphExecDestroy(c->iter_exec);
+    c->iter_exec = nullptr;
+    c->iter_x = nullptr;
+    c->iter_prec = -1;
+}
+
 int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st) {
     hipStream_t s = c->stream;
     const int prec = c->amg.precision;
@@ -45,7 +82,7 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
     while (!v.done) {
         // iterate until the device reports done, keeping one iteration queued ahead
         for (int64_t k = 0;; ++k) {
-            pcg_iteration(s, c, rhs, y, prec);
+            run_iteration(c, y, prec);
             EQS_HIP(hipEventRecord(c->ev[k & 1], s));
             if (k >= 1) {
                 EQS_HIP(hipEventSynchronize(c->ev[(k - 1) & 1]));
