@@ -69,7 +69,7 @@ KERNEL_NAMES = {"element": "k_kx<true>", "spmv_M": "k_pcg_spmv", "presmooth0": "
                 "postsmooth0": "k_postsmooth (finest)", "cg_update": "k_pcg_update", "rkc_combine": "k_rkc_combine"}
 
 
-def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"):
+def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous", flexible=0):
     """Time `steps` RKC steps (uninstrumented), then `prof_steps` more with every
     kernel class timed by HIP events on the context's stream."""
     import torch
@@ -81,7 +81,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
     stream = torch.cuda.current_stream(dev)
     t0 = time.perf_counter()
     ctx = Context(0, stream)
-    info = ctx.setup_case(case, precision=precision)
+    info = ctx.setup_case(case, precision=precision, flexible=flexible)
     if guess == "mlp":
         ctx.set_guess("mlp", init=eqsgen.mlp_init(4))
     elif guess != "previous":
@@ -157,6 +157,7 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=3, help="instrumented steps after the timed ones")
     ap.add_argument("--guess", default="previous", choices=["previous", "zero", "galerkin", "mlp"])
     ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
+    ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     args = ap.parse_args()
 
     os.environ["EQS_USE_GRAPHS"] = "1" if args.graphs else "0"
@@ -175,7 +176,8 @@ def main():
     from paper_1612_09447_amd import EQS_PREC_FP32, EQS_PREC_FP64
 
     main_prec = EQS_PREC_FP32 if prec == "fp32" else EQS_PREC_FP64
-    r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess)
+    r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess,
+                flexible=args.flexible)
     stages_per_s = r["stages"] / r["elapsed"]
     info = r["info"]
     prof = r["prof"]

@@ -91,7 +91,7 @@ typedef struct eqs_amg_params {
     int32_t precision;  /* EQS_PREC_FP64 or EQS_PREC_FP32 storage and V-cycle [FP64] */
     int32_t coarse_max; /* coarsen until at most this many unknowns, <= 4096 [512] */
     int32_t max_levels; /* including the coarsest, 2..16 [12] */
-    int32_t flexible;   /* 1: Polak-Ribiere beta (needed with FP32), 0: standard [= precision] */
+    int32_t flexible;   /* CG beta: 1 Polak-Ribiere (flexible), 2 Fletcher-Reeves; 0 = PR with FP32, FR with FP64 */
     double theta;       /* strength threshold |a_ij| >= theta sqrt(a_ii a_jj) [0.08] */
     double jacobi_weight; /* damped-Jacobi weight times 1/rho(D^-1 A) [4/3] */
     double smooth_weight; /* prolongator-smoothing weight times 1/rho(D^-1 A) [4/3] */

@@ -185,7 +185,9 @@ int eqs_build_preconditioner(eqs_ctx* c, const eqs_amg_params* p) {
         if (a.theta == 0) a.theta = 0.08;
         if (a.jacobi_weight == 0) a.jacobi_weight = 4.0 / 3.0;
         if (a.smooth_weight == 0) a.smooth_weight = 4.0 / 3.0;
-        if (!p || p->flexible == 0) a.flexible = (a.precision == EQS_PREC_FP32) ? 1 : 0;
+        need(a.flexible >= 0 && a.flexible <= 2, "flexible must be 0, 1 or 2");
+        if (a.flexible == 0) a.flexible = (a.precision == EQS_PREC_FP32) ? 1 : 2;
+        a.flexible = (a.flexible == 1) ? 1 : 0;  // stored as: 1 Polak-Ribiere, 0 Fletcher-Reeves
         need(a.coarse_max >= 1 && a.coarse_max <= 4096, "coarse_max must be in [1, 4096]");
         need(a.max_levels >= 1 && a.max_levels <= 16, "max_levels must be in [1, 16]");
         need(a.theta >= 0 && a.theta < 1, "theta must be in [0, 1)");

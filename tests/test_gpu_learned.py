@@ -97,7 +97,10 @@ def run_kind(case, kind, steps, rtol, **kw):
         x = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
         traj, stats = [], []
         for n in range(steps):
-            st = c.rkc_step(n * case.tau, case.tau, case.s, x, rtol=rtol, maxit=500)
+            st = c.rkc_step(n * case.tau, case.tau, case.s, x, rtol=rtol, maxit=500, allow_not_converged=True)
+            if st["not_converged"]:
+                print(f"[guess] {kind} step {n}: {st}", flush=True)
+            assert st["not_converged"] == 0, (kind, n, st)
             stats.append(st)
             traj.append(x.cpu().numpy()[o.free].copy())
     return traj, stats, o
@@ -113,7 +116,7 @@ def test_start_vector_kinds_keep_the_result_and_galerkin_beats_previous():
     iters = {}
     for kind in ("previous", "zero", "galerkin", "mlp"):
         kw = dict(warmup=16) if kind == "mlp" else {}
-        traj, stats, _ = run_kind(case, kind, steps, 1e-12, **kw)
+        traj, stats, _ = run_kind(case, kind, steps, 1e-11, **kw)
         err = max(np.linalg.norm(a - b) for a, b in zip(traj, ref)) / scale
         iters[kind] = sum(s["total_iters"] for s in stats)
         used = sum(s["guess_used"] for s in stats)
