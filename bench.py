@@ -125,6 +125,47 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
                 prof_stages=prof_steps * s, setup_s=setup_s, x=xn, used=used, fallbacks=fallbacks)
 
 
+def run_batched(steps, warmup):
+    """The batched workload: 64 independent instances (n in {16..48}^3) packed
+    into one context, RKC(8) steps of all of them together."""
+    import torch
+
+    import eqsgen
+    from paper_1612_09447_amd import EQS_PREC_FP32, Batch, Context
+
+    t0 = time.perf_counter()
+    cases = eqsgen.case_batch()
+    stream = torch.cuda.current_stream(torch.device("cuda:0"))
+    inputs = []
+    for c in cases:
+        ctx = Context(0, stream)
+        ctx.set_inputs(c)
+        inputs.append(ctx)
+    b = Batch(inputs, precision=EQS_PREC_FP32, stream=stream)
+    for ctx in inputs:
+        ctx.close()
+    setup_s = time.perf_counter() - t0
+    dof = sum((c.n + 1) ** 2 * (c.n - 1) for c in cases)
+    log(f"[bench] batched: {len(cases)} instances, {dof} free DOF, {sum(c.n_tets for c in cases)} tets, "
+        f"setup {setup_s:.1f}s")
+    xs = [torch.zeros(c.n_nodes, dtype=torch.float64, device="cuda:0") for c in cases]
+    tau, s, rtol = cases[0].tau, cases[0].s, cases[0].rtol
+    if warmup:
+        b.rkc_steps(warmup, 0.0, tau, s, xs, rtol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = b.rkc_steps(steps, warmup * tau, tau, s, xs, rtol)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    b.close()
+    stages = steps * s * len(cases)
+    return {"instances": len(cases), "free_dof": dof, "steps": steps, "s": s,
+            "stages_per_s_aggregate": round(stages / el, 1), "dof_stages_per_s": round(dof * steps * s / el, 1),
+            "cg_iters_per_instance_stage": {"min": round(float(res["iters"].min()) / (steps * s), 2),
+                                            "max": round(float(res["iters"].max()) / (steps * s), 2)},
+            "precision": "FP64 CG + K(x)x, FP32 AMG", "setup_s": round(setup_s, 1)}
+
+
 def cpu_baseline(case):
     """The oracle, as it stands, on one stage of the workload (single thread)."""
     import numpy as np
@@ -158,6 +199,7 @@ def main():
     ap.add_argument("--guess", default="previous", choices=["previous", "zero", "galerkin", "mlp"])
     ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
+    ap.add_argument("--c3-steps", type=int, default=0, help="also time the 64-instance batched workload")
     args = ap.parse_args()
 
     os.environ["EQS_USE_GRAPHS"] = "1" if args.graphs else "0"
@@ -207,6 +249,8 @@ def main():
                  "mean_cg_iters_per_stage": round(sum(p["iters"]) / len(p["iters"]), 2),
                  "steps": args.plain_steps}
 
+    batched = run_batched(args.c3_steps, 1) if args.c3_steps > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(case)
@@ -242,6 +286,7 @@ def main():
         "roofline": roofline,
         "kernel_breakdown": breakdown,
         "fp64_plain": plain,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

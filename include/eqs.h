@@ -54,7 +54,7 @@ extern "C" {
 #define EQS_ERR_NONFINITE (-6)     /* NaN/Inf in an input */
 #define EQS_ERR_ALLOC (-7)         /* device or host allocation failed */
 
-#define EQS_MAX_DRIVES 8 /* distinct drive functions per context */
+#define EQS_MAX_DRIVES 65536 /* distinct drive functions per context */
 
 enum { EQS_PREC_FP64 = 0, EQS_PREC_FP32 = 1 };
 
@@ -201,6 +201,40 @@ int eqs_solve_M(eqs_ctx *ctx, const double *rhs_dev, double *y_dev, double rtol,
  * solve hit maxit (the step is still completed); st may be NULL. */
 int eqs_rkc_step(eqs_ctx *ctx, double t, double dt, int32_t s, double *x_dev, double rtol, int32_t maxit,
                  eqs_step_stats *st);
+
+/* ---- batches of independent instances ---------------------------------
+ * A context can hold several independent EQS problems at once (the batched
+ * form): their meshes are concatenated (node ids of instance i in
+ * [node_off[i], node_off[i+1]), its tets in [tet_off[i], tet_off[i+1])), and
+ * materials and Dirichlet data are given for the concatenation as usual. The
+ * element pass, the sparse products and the AMG hierarchy then act on all
+ * instances at once (block-diagonal operators; aggregation never joins rows of
+ * different instances), while every instance keeps its own CG scalars and its
+ * own convergence test to rtol, so finished instances stop updating while the
+ * others iterate. All instances share t, dt and s of eqs_rkc_step. Each
+ * instance needs at least one Dirichlet node and, when n_inst > 1, at least
+ * 256 free nodes. Call after eqs_set_mesh; invalidates the preconditioner. */
+int eqs_set_instances(eqs_ctx *ctx, int32_t n_inst, const int64_t *node_off, const int64_t *tet_off);
+
+/* Per-instance results of the last eqs_rkc_step or eqs_solve_M: CG iterations
+ * (summed over the stages) and the largest final relative residual. Arrays of
+ * n_inst entries (either may be NULL). */
+int eqs_instance_stats(const eqs_ctx *ctx, int32_t n_inst, int64_t *iters, double *relres);
+
+/* Convenience form: pack n contexts that hold mesh, materials and Dirichlet
+ * data (same device; their own preconditioners are not needed) into one
+ * batched context on `device`/`hip_stream`, built with p (NULL: defaults). */
+typedef struct eqs_batch eqs_batch;
+int eqs_batch_create(eqs_batch **out, int32_t n, eqs_ctx *const *ctxs, int device, void *hip_stream,
+                     const eqs_amg_params *p);
+int eqs_batch_destroy(eqs_batch *b);
+/* nsteps RKC(s) steps of every instance from t0 with step dt; x_dev[i] holds
+ * instance i's n_nodes potentials (in/out, as eqs_rkc_step). st (may be NULL)
+ * receives the batch's aggregated stats of the last step; per-instance
+ * iterations through eqs_batch_instance_stats. */
+int eqs_batch_rkc_steps(eqs_batch *b, int32_t nsteps, double t0, double dt, int32_t s, double *const *x_dev,
+                        double rtol, int32_t maxit, eqs_step_stats *st);
+int eqs_batch_instance_stats(const eqs_batch *b, int64_t *iters, double *relres);
 
 /* ---- start vectors (Sec. IV) ------------------------------------------
  * The stage solves of one run form a multiple right-hand-side problem with the

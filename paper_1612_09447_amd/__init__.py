@@ -7,6 +7,7 @@ and streams.
 """
 
 from .binding import (  # noqa: F401
+    Batch,
     Context,
     EqsError,
     Mlp,

@@ -25,7 +25,7 @@ EQS_ERR_NOT_CONVERGED = -4
 EQS_ERR_BREAKDOWN = -5
 EQS_ERR_NONFINITE = -6
 EQS_ERR_ALLOC = -7
-EQS_MAX_DRIVES = 8
+EQS_MAX_DRIVES = 65536
 EQS_PREC_FP64 = 0
 EQS_PREC_FP32 = 1
 
@@ -103,6 +103,13 @@ _SIGNATURES = {
     "eqs_solve_M": ([_P, _P, _P, C.c_double, C.c_int32, _P], C.c_int),
     "eqs_rkc_step": ([_P, C.c_double, C.c_double, C.c_int32, _P, C.c_double, C.c_int32, _P], C.c_int),
     "eqs_set_guess": ([_P, _P], C.c_int),
+    "eqs_set_instances": ([_P, C.c_int32, _P, _P], C.c_int),
+    "eqs_instance_stats": ([_P, C.c_int32, _P, _P], C.c_int),
+    "eqs_batch_create": ([C.POINTER(_P), C.c_int32, _P, C.c_int, _P, _P], C.c_int),
+    "eqs_batch_destroy": ([_P], C.c_int),
+    "eqs_batch_rkc_steps": ([_P, C.c_int32, C.c_double, C.c_double, C.c_int32, _P, C.c_double, C.c_int32, _P],
+                            C.c_int),
+    "eqs_batch_instance_stats": ([_P, _P, _P], C.c_int),
     "eqs_mlp_create": ([C.POINTER(_P), C.c_int, _P, _P, C.c_int32, C.c_double], C.c_int),
     "eqs_mlp_destroy": ([_P], C.c_int),
     "eqs_mlp_forward": ([_P, _P, _P, C.c_int32], C.c_int),
@@ -253,6 +260,25 @@ class Context:
         self.build_preconditioner(precision, **amg)
         return self.info()
 
+    def set_instances(self, node_off, tet_off):
+        """Declare the mesh a concatenation of independent instances (batched form)."""
+        no, pno = _host(node_off, np.int64)
+        to, pto = _host(tet_off, np.int64)
+        _check(lib().eqs_set_instances(self._h, no.size - 1, pno, pto), "eqs_set_instances")
+
+    def instance_stats(self, n_inst):
+        it = np.zeros(n_inst, np.int64)
+        rr = np.zeros(n_inst)
+        _check(lib().eqs_instance_stats(self._h, n_inst, it.ctypes.data_as(_P), rr.ctypes.data_as(_P)),
+               "eqs_instance_stats")
+        return it, rr
+
+    def set_inputs(self, case):
+        """Mesh, materials and Dirichlet data of a ``eqsgen.Case`` (no build)."""
+        self.set_mesh(case.xyz, case.tets)
+        self.set_materials(case.eps_r, case.kappa0, case.e_s, case.alpha, case.nonlinear, case.tet_mat)
+        self.set_dirichlet(case.dir_nodes, case.dir_drive, case.amp, case.freq, case.phase)
+
     def info(self) -> dict:
         o = eqs_info()
         _check(lib().eqs_query(self._h, C.byref(o)), "eqs_query")
@@ -383,3 +409,40 @@ class Mlp:
         g = np.zeros(EQS_MLP_NPARAM, np.float32)
         _check(lib().eqs_mlp_get(self._h, p.ctypes.data_as(_P), g.ctypes.data_as(_P)), "eqs_mlp_get")
         return unflatten_params(p), unflatten_params(g)
+
+
+class Batch:
+    """Independent instances advanced together (eqs_batch_*)."""
+
+    def __init__(self, contexts, precision=EQS_PREC_FP64, device=0, stream=None, **amg):
+        self._h = _P()
+        self.n = len(contexts)
+        arr = (_P * self.n)(*[c._h for c in contexts])
+        p = eqs_amg_params()
+        p.precision = precision
+        for k, v in amg.items():
+            setattr(p, k, v)
+        _check(lib().eqs_batch_create(C.byref(self._h), self.n, C.cast(arr, _P), device, _stream_handle(stream),
+                                      C.byref(p)), "eqs_batch_create")
+
+    def close(self):
+        if self._h:
+            lib().eqs_batch_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rkc_steps(self, nsteps, t0, dt, s, xs, rtol, maxit=1000):
+        ptrs = (_P * self.n)(*[_dev(x) for x in xs])
+        st = eqs_step_stats()
+        _check(lib().eqs_batch_rkc_steps(self._h, int(nsteps), float(t0), float(dt), int(s), C.cast(ptrs, _P),
+                                         float(rtol), int(maxit), C.byref(st)), "eqs_batch_rkc_steps")
+        it = np.zeros(self.n, np.int64)
+        rr = np.zeros(self.n)
+        _check(lib().eqs_batch_instance_stats(self._h, it.ctypes.data_as(_P), rr.ctypes.data_as(_P)),
+               "eqs_batch_instance_stats")
+        return dict(iters=it, relres=rr, last_step_total_iters=st.total_iters)

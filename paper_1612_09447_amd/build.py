@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libeqs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "setup.cpp", "solver.cpp", "profile.cpp", "kernels.hip", "mlp.hip", "guess.hip"]
+SOURCES = ["api.cpp", "setup.cpp", "solver.cpp", "profile.cpp", "kernels.hip", "mlp.hip", "guess.hip", "batch.cpp"]
 
 COMMON = [
     "-O3",

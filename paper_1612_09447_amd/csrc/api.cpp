@@ -112,6 +112,8 @@ int eqs_set_mesh(eqs_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets,
         for (int64_t k = 0; k < 4 * n_tets; ++k)
             need(tets[k] >= 0 && tets[k] < n_nodes, "tet node id out of range");
         c->have_mesh = true;
+        c->inst_node_off.clear();
+        c->inst_tet_off.clear();
         c->have_mat = c->have_dir = false;
         c->mats.clear();
         c->tet_mat.clear();
@@ -243,7 +245,7 @@ int eqs_apply_K(eqs_ctx* c, double t, const double* x_dev, double* y_dev) {
         bind_device(c);
         hipStream_t s = c->stream;
         eqs::launch_gather(s, x_dev, c->d_int_to_user, c->d_tmpN, c->n_free);
-        eqs::launch_kx(s, false, c, c->d_tmpN, eqs::drive_values(c, t), c->d_tmpN2);
+        eqs::launch_kx(s, false, c, c->d_tmpN, t, c->d_tmpN2);
         eqs::launch_scatter(s, c->d_tmpN2, c->d_int_to_user, y_dev, c->n_nodes);
         EQS_HIP(hipGetLastError());
         EQS_HIP(hipStreamSynchronize(s));
@@ -258,7 +260,7 @@ int eqs_stage_rhs(eqs_ctx* c, double t, const double* y_free_dev, double* r_dev)
         need(std::isfinite(t), "t must be finite");
         need_built(c);
         bind_device(c);
-        eqs::launch_kx(c->stream, true, c, y_free_dev, eqs::drive_values(c, t), r_dev);
+        eqs::launch_kx(c->stream, true, c, y_free_dev, t, r_dev);
         EQS_HIP(hipGetLastError());
         EQS_HIP(hipStreamSynchronize(c->stream));
         return EQS_OK;
@@ -297,6 +299,8 @@ int eqs_solve_M(eqs_ctx* c, const double* rhs_dev, double* y_dev, double rtol, i
         need(maxit >= 0, "maxit must be >= 0");
         need_built(c);
         bind_device(c);
+        std::fill(c->inst_iters.begin(), c->inst_iters.end(), 0);
+        std::fill(c->inst_relres.begin(), c->inst_relres.end(), 0.0);
         return result_code(eqs::solve_M(c, rhs_dev, y_dev, rtol, maxit, st), "eqs_solve_M");
     });
 }
@@ -312,6 +316,38 @@ int eqs_rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_dev, doub
         need_built(c);
         bind_device(c);
         return result_code(eqs::rkc_step(c, t, dt, s, x_dev, rtol, maxit, st), "eqs_rkc_step");
+    });
+}
+
+int eqs_set_instances(eqs_ctx* c, int32_t n_inst, const int64_t* node_off, const int64_t* tet_off) {
+    return guarded([&] {
+        need(c != nullptr && node_off != nullptr && tet_off != nullptr, "NULL argument");
+        if (!c->have_mesh) fail(EQS_ERR_STATE, "eqs_set_mesh must come first");
+        need(n_inst >= 1, "n_inst must be >= 1");
+        need(node_off[0] == 0 && node_off[n_inst] == c->n_nodes, "node offsets must run from 0 to n_nodes");
+        need(tet_off[0] == 0 && tet_off[n_inst] == c->n_tets, "tet offsets must run from 0 to n_tets");
+        for (int32_t i = 0; i < n_inst; ++i)
+            need(node_off[i + 1] > node_off[i] && tet_off[i + 1] > tet_off[i], "every instance needs nodes and tets");
+        if (n_inst > 1 && c->guess.p.kind >= EQS_GUESS_GALERKIN)
+            fail(EQS_ERR_STATE, "Galerkin and network start vectors need a single instance");
+        bind_device(c);
+        eqs::free_device(c);
+        c->inst_node_off.assign(node_off, node_off + n_inst + 1);
+        c->inst_tet_off.assign(tet_off, tet_off + n_inst + 1);
+        return EQS_OK;
+    });
+}
+
+int eqs_instance_stats(const eqs_ctx* c, int32_t n_inst, int64_t* iters, double* relres) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        if (!c->built) fail(EQS_ERR_STATE, "context not built");
+        need(n_inst == (int32_t)c->n_inst, "n_inst does not match the context");
+        for (int32_t i = 0; i < n_inst; ++i) {
+            if (iters) iters[i] = c->inst_iters[i];
+            if (relres) relres[i] = c->inst_relres[i];
+        }
+        return EQS_OK;
     });
 }
 
@@ -338,6 +374,8 @@ int eqs_set_guess(eqs_ctx* c, const eqs_guess_params* p) {
             c->guess.init.assign(a.init, a.init + EQS_MLP_NPARAM);
         }
         a.init = nullptr;
+        if (a.kind >= EQS_GUESS_GALERKIN && c->inst_node_off.size() > 2)
+            fail(EQS_ERR_STATE, "Galerkin and network start vectors need a single instance");
         eqs::guess_configure(c, a);
         return EQS_OK;
     });

@@ -90,9 +90,10 @@ struct MatDev {
     int32_t ialpha;  // alpha as an integer in [0, 64] when exact, else -1
 };
 
-struct DriveVals {
-    double g[EQS_MAX_DRIVES];   // g_k(t)
-    double gd[EQS_MAX_DRIVES];  // g_k'(t)
+// Drive k: g_k(t) = amp sin(w t + phase), g_k'(t) = w amp cos(w t + phase),
+// w = 2 pi freq; evaluated on the device at the stage time.
+struct DriveDev {
+    double w, amp, phase, pad;
 };
 
 // PCG scalars kept on the device so that the iteration needs no host values.
@@ -111,6 +112,17 @@ struct PcgScalars {
     int32_t status;  // EQS_OK / EQS_ERR_NOT_CONVERGED / EQS_ERR_BREAKDOWN
     int32_t fresh;   // 1: next beta is 0 (first iteration or restart)
     int32_t flexible;
+};
+
+// Summary of all instances' CG states (written by the finalisers).
+struct PcgSummary {
+    int32_t all_done;
+    int32_t n_active;
+    int32_t n_breakdown;
+    int32_t n_notconv;
+    int32_t n_zero_rhs;
+    int32_t max_it;
+    double max_relres;
 };
 
 template <typename T>
@@ -199,6 +211,7 @@ struct eqs_ctx {
     double4* d_xyz = nullptr;
     eqs::MatDev* d_mats = nullptr;
     int32_t* d_ddrive = nullptr;
+    eqs::DriveDev* d_drives = nullptr;
     int32_t* d_int_to_user = nullptr;
 
     // device: M and the hierarchy
@@ -213,9 +226,21 @@ struct eqs_ctx {
     bool have_Flast = false;
     double* d_partials = nullptr;  // 4 * max_blocks doubles
     int64_t max_blocks = 0;
-    eqs::PcgScalars* d_scal = nullptr;
-    eqs::PcgScalars* h_scal = nullptr;  // pinned host mirror written by the finalisers
-    eqs::PcgScalars* d_hscal = nullptr; // its device-side address
+    // independent instances (a batch): contiguous node, tet and free-row ranges
+    int64_t n_inst = 1;
+    std::vector<int64_t> inst_node_off, inst_tet_off;  // user-level offsets [n_inst + 1]
+    std::vector<int32_t> inst_row_off;                  // free rows [n_inst + 1]
+    int32_t* d_inst_row = nullptr;
+    int32_t* d_blk_inst = nullptr;  // instance of the first row of every 256-row block
+    std::vector<int64_t> inst_iters;  // CG iterations per instance over the last rkc_step / solve
+    std::vector<double> inst_relres;  // largest final relative residual per instance over the same
+
+    eqs::PcgScalars* d_scal = nullptr;   // [n_inst]
+    eqs::PcgSummary* d_sum = nullptr;
+    eqs::PcgScalars* h_scal = nullptr;   // pinned host mirror of d_scal, written by the finalisers
+    eqs::PcgScalars* d_hscal = nullptr;  // its device-side address
+    eqs::PcgSummary* h_sum = nullptr;    // pinned host mirror of the summary
+    eqs::PcgSummary* d_hsum = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
 
     int64_t device_bytes = 0;
@@ -265,15 +290,13 @@ Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A);
 template <typename T>
 SpMat<T> to_spmat(eqs_ctx* c, const Csr<double>& A);
 
-DriveVals drive_values(const eqs_ctx* c, double t);
 
 // -------------------------------------------------------- kernel launchers
 void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_gather(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n);
 void launch_scatter(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n);
-void launch_finish_state(hipStream_t s, const double* yfree, const int32_t* int_to_user, const int32_t* ddrive,
-                         DriveVals dv, double* x_user, int64_t n_free, int64_t n_nodes);
-void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, DriveVals dv, double* out);
+void launch_finish_state(eqs_ctx* c, const double* yfree, double t, double* x_user);
+void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);
 void launch_rkc_first(hipStream_t s, double* out, const double* Y0, const double* F0, double a, int64_t n);
 void launch_rkc_combine(hipStream_t s, double* out, const double* Y0, const double* Yjm1, const double* Yjm2,
@@ -281,16 +304,16 @@ void launch_rkc_combine(hipStream_t s, double* out, const double* Y0, const doub
                         double c4, int64_t n);
 void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double* y);
 
-// PCG pieces (all scalar state on the device in PcgScalars)
+// PCG pieces (all scalar state on the device, one PcgScalars per instance)
 void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int32_t maxit, double rtol,
               int flexible);
-void pcg_restart(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x);
 void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int precision);
 void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x);
+void pcg_zero_rhs_rows(hipStream_t s, eqs_ctx* c, double* x);
 
 template <typename T>
 void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double* z, double* part_rz,
-            const PcgScalars* scal);
+            double* part_rzold, const int32_t* stop);
 
 // start-vector network (mlp.hip)
 }  // namespace eqs

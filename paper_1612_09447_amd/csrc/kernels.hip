@@ -48,6 +48,46 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
     return r;
 }
 
+// ---------------------------------------------------- instances (batches)
+// Independent instances occupy contiguous ranges of free rows. Every
+// 256-row block of the finest level holds rows of at most two instances (each
+// instance has >= 256 rows when there is more than one), so a block writes a
+// pair of partial sums: [2b] for the instance of its first row, [2b+1] for the
+// next instance (0 if the block lies in one instance).
+struct InstMap {
+    const int32_t* __restrict__ row_off;   // [n_inst + 1] first row of every instance
+    const int32_t* __restrict__ blk_inst;  // [blocks] instance of each block's first row
+    int32_t n_inst;
+};
+
+__device__ __forceinline__ void block_instances(const InstMap& m, int32_t& lo, int32_t& bound) {
+    lo = m.blk_inst[blockIdx.x];
+    bound = m.row_off[lo + 1];
+}
+
+// Thread 0 stores the block's pair of sums of v (split by `second`).
+__device__ __forceinline__ void store_pair(double* __restrict__ part, double v, bool second, double* sh) {
+    const double a = block_sum(second ? 0.0 : v, sh);
+    const double b = block_sum(second ? v : 0.0, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// Sum of instance i's partials by one wavefront, in a fixed order; valid in all lanes.
+__device__ __forceinline__ double inst_sum(const double* __restrict__ part, const InstMap& m, int32_t i) {
+    const int32_t r0 = m.row_off[i], r1 = m.row_off[i + 1];
+    double v = 0.0;
+    if (r1 > r0) {
+        const int32_t b0 = r0 >> 8, b1 = (r1 - 1) >> 8;
+        for (int32_t b = b0 + (int32_t)(threadIdx.x & 63); b <= b1; b += 64)
+            v += (m.blk_inst[b] == i) ? part[2 * b] : part[2 * b + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // ------------------------------------------------------------- simple ops
 __global__ void k_fill(double* __restrict__ p, double v, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -75,11 +115,18 @@ __global__ void k_scatter(const double* __restrict__ src, const int32_t* __restr
 
 // x_user = (yfree on free nodes, g(t) on Dirichlet nodes), in user order.
 __global__ void k_finish_state(const double* __restrict__ yfree, const int32_t* __restrict__ int_to_user,
-                               const int32_t* __restrict__ ddrive, DriveVals dv, double* __restrict__ x_user,
-                               int64_t n_free, int64_t n_nodes) {
+                               const int32_t* __restrict__ ddrive, const DriveDev* __restrict__ drives, double t,
+                               double* __restrict__ x_user, int64_t n_free, int64_t n_nodes) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_nodes) return;
-    x_user[int_to_user[i]] = (i < n_free) ? yfree[i] : dv.g[ddrive[i - n_free]];
+    double v;
+    if (i < n_free) {
+        v = yfree[i];
+    } else {
+        const DriveDev d = drives[ddrive[i - n_free]];
+        v = d.amp * sin(d.w * t + d.phase);
+    }
+    x_user[int_to_user[i]] = v;
 }
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -96,10 +143,9 @@ void launch_gather(hipStream_t s, const double* src, const int32_t* idx, double*
 void launch_scatter(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n) {
     if (n > 0) hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(kBlock), 0, s, src, idx, dst, n);
 }
-void launch_finish_state(hipStream_t s, const double* yfree, const int32_t* int_to_user, const int32_t* ddrive,
-                         DriveVals dv, double* x_user, int64_t n_free, int64_t n_nodes) {
-    hipLaunchKernelGGL(k_finish_state, dim3(grid_for(n_nodes)), dim3(kBlock), 0, s, yfree, int_to_user, ddrive, dv,
-                       x_user, n_free, n_nodes);
+void launch_finish_state(eqs_ctx* c, const double* yfree, double t, double* x_user) {
+    hipLaunchKernelGGL(k_finish_state, dim3(grid_for(c->n_nodes)), dim3(kBlock), 0, c->stream, yfree,
+                       c->d_int_to_user, c->d_ddrive, c->d_drives, t, x_user, c->n_free, c->n_nodes);
 }
 
 // ------------------------------------------------------ fused element pass
@@ -130,7 +176,8 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, const uint64_t
                                                    const int32_t* __restrict__ bnodes,
                                                    const double4* __restrict__ xyz, const MatDev* __restrict__ mats,
                                                    const double* __restrict__ yfree, int32_t n_free,
-                                                   const int32_t* __restrict__ ddrive, DriveVals dv,
+                                                   const int32_t* __restrict__ ddrive,
+                                                   const DriveDev* __restrict__ drives, double t,
                                                    double* __restrict__ out) {
     extern __shared__ double lds[];
     const int32_t b = blockIdx.x;
@@ -146,9 +193,10 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, const uint64_t
         if (id < n_free) {
             p.w = yfree[id];
         } else {
-            const int d = ddrive[id - n_free];
-            p.w = dv.g[d];
-            rate = dv.gd[d];
+            const DriveDev d = drives[ddrive[id - n_free]];
+            const double ph = d.w * t + d.phase;
+            p.w = d.amp * sin(ph);
+            rate = d.w * d.amp * cos(ph);
         }
         P[k] = p;
         R[k] = rate;
@@ -214,7 +262,7 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, const uint64_t
     }
 }
 
-void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, DriveVals dv, double* out) {
+void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out) {
     const int64_t nout = rhs_mode ? c->n_free : c->n_nodes;
     launch_fill(s, out, 0.0, nout);
     if (c->n_tets == 0) return;
@@ -223,10 +271,10 @@ void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, Dr
     prof_begin(c, EQS_KCLASS_ELEMENT, s);
     if (rhs_mode)
         hipLaunchKernelGGL(k_kx<true>, g, b, lds, s, c->n_tets, c->d_tpack, c->d_boff, c->d_bnodes, c->d_xyz,
-                           c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, dv, out);
+                           c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out);
     else
         hipLaunchKernelGGL(k_kx<false>, g, b, lds, s, c->n_tets, c->d_tpack, c->d_boff, c->d_bnodes, c->d_xyz,
-                           c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, dv, out);
+                           c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out);
     prof_end(c, EQS_KCLASS_ELEMENT, s);
 }
 
@@ -264,8 +312,8 @@ static unsigned sell_grid(const Sell<T>& A) {
 // y = A x  or  y += A x
 template <typename T>
 __global__ __launch_bounds__(256) void k_sell_mv(SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
-                                                  const PcgScalars* __restrict__ scal) {
-    if (scal && scal->done) return;
+                                                  const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= A.n_slices * 64) return;
     const T v = sell_row(A, row, x);
@@ -290,8 +338,8 @@ void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double
 template <typename T, typename TB>
 __global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> A, const T* __restrict__ dinv, T omega,
                                                         const TB* __restrict__ b, T* __restrict__ x,
-                                                        T* __restrict__ res, const PcgScalars* __restrict__ scal) {
-    if (scal && scal->done) return;
+                                                        T* __restrict__ res, const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= A.n_slices * 64) return;
     const int32_t s = row >> 6, l = row & 63;
@@ -313,15 +361,16 @@ __global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> A, const T* _
 
 // Post-smoothing: out = x + omega D^{-1} (b - A x). At the finest level the
 // output is CG's z (FP64) and the block partials of r.z and r.z_old (the
-// Polak-Ribiere numerator) are produced; z_old is read before it is overwritten.
+// Polak-Ribiere numerator) are produced per instance (pair layout, see
+// InstMap); z_old is read before it is overwritten.
 template <typename T, typename TB, typename TO, bool DOT>
 __global__ __launch_bounds__(256) void k_postsmooth(SellView<T> A, const T* __restrict__ dinv, T omega,
                                                      const TB* __restrict__ b, const T* __restrict__ x,
-                                                     TO* __restrict__ out, double* __restrict__ part_rz,
+                                                     TO* __restrict__ out, InstMap m, double* __restrict__ part_rz,
                                                      double* __restrict__ part_rzold,
-                                                     const PcgScalars* __restrict__ scal) {
+                                                     const int32_t* __restrict__ stop) {
     __shared__ double sh[4];
-    if (scal && scal->done) return;
+    if (stop && *stop) return;
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     double rz = 0.0, rzo = 0.0;
     if (row < A.n_slices * 64) {
@@ -337,12 +386,10 @@ __global__ __launch_bounds__(256) void k_postsmooth(SellView<T> A, const T* __re
         }
     }
     if (DOT) {
-        const double s1 = block_sum(rz, sh);
-        const double s2 = block_sum(rzo, sh);
-        if (threadIdx.x == 0) {
-            part_rz[blockIdx.x] = s1;
-            part_rzold[blockIdx.x] = s2;
-        }
+        int32_t lo, bound;
+        block_instances(m, lo, bound);
+        store_pair(part_rz, rz, row >= bound, sh);
+        store_pair(part_rzold, rzo, row >= bound, sh);
     }
 }
 
@@ -376,8 +423,8 @@ __device__ __forceinline__ T csr_row(const CsrView<T>& A, int32_t row, int lane,
 
 template <int L, typename T>
 __global__ __launch_bounds__(256) void k_csr_mv(CsrView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
-                                                 const PcgScalars* __restrict__ scal) {
-    if (scal && scal->done) return;
+                                                 const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
@@ -389,8 +436,8 @@ __global__ __launch_bounds__(256) void k_csr_mv(CsrView<T> A, const T* __restric
 template <int L, typename T, typename TB>
 __global__ __launch_bounds__(256) void k_csr_presmooth_res(CsrView<T> A, const T* __restrict__ dinv, T omega,
                                                             const TB* __restrict__ b, T* __restrict__ x,
-                                                            T* __restrict__ res, const PcgScalars* __restrict__ scal) {
-    if (scal && scal->done) return;
+                                                            T* __restrict__ res, const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
@@ -403,38 +450,17 @@ __global__ __launch_bounds__(256) void k_csr_presmooth_res(CsrView<T> A, const T
     }
 }
 
-template <int L, typename T, typename TB, typename TO, bool DOT>
+template <int L, typename T, typename TB, typename TO>
 __global__ __launch_bounds__(256) void k_csr_postsmooth(CsrView<T> A, const T* __restrict__ dinv, T omega,
                                                          const TB* __restrict__ b, const T* __restrict__ x,
-                                                         TO* __restrict__ out, double* __restrict__ part_rz,
-                                                         double* __restrict__ part_rzold,
-                                                         const PcgScalars* __restrict__ scal) {
-    __shared__ double sh[4];
-    if (scal && scal->done) return;
+                                                         TO* __restrict__ out, const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
-    double rz = 0.0, rzo = 0.0;
-    if (row < A.n_rows) {
-        const T ax = csr_row<L>(A, row, lane, [&](int32_t j) { return x[j]; });
-        if (lane == 0) {
-            const T v = x[row] + omega * dinv[row] * ((T)b[row] - ax);
-            if (DOT) {
-                const double ri = (double)b[row];
-                rzo = ri * (double)out[row];
-                rz = ri * (double)v;
-            }
-            out[row] = (TO)v;
-        }
-    }
-    if (DOT) {
-        const double s1 = block_sum(rz, sh);
-        const double s2 = block_sum(rzo, sh);
-        if (threadIdx.x == 0) {
-            part_rz[blockIdx.x] = s1;
-            part_rzold[blockIdx.x] = s2;
-        }
-    }
+    if (row >= A.n_rows) return;
+    const T ax = csr_row<L>(A, row, lane, [&](int32_t j) { return x[j]; });
+    if (lane == 0) out[row] = (TO)(x[row] + omega * dinv[row] * ((T)b[row] - ax));
 }
 
 template <typename T>
@@ -453,37 +479,38 @@ static unsigned csr_grid(const SpMat<T>& A) {
     }
 
 template <typename T>
-static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int acc, const PcgScalars* scal) {
+static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int acc, const int32_t* stop) {
     if (A.fmt == FMT_SELL) {
-        hipLaunchKernelGGL(k_sell_mv<T>, dim3(sell_grid(A.sell)), dim3(kBlock), 0, s, view(A.sell), x, y, acc, scal);
+        hipLaunchKernelGGL(k_sell_mv<T>, dim3(sell_grid(A.sell)), dim3(kBlock), 0, s, view(A.sell), x, y, acc, stop);
     } else {
         EQS_LANES_SWITCH(A.lanes, hipLaunchKernelGGL((k_csr_mv<L_, T>), dim3(csr_grid(A)), dim3(kBlock), 0, s,
-                                                     cview(A), x, y, acc, scal));
+                                                     cview(A), x, y, acc, stop));
     }
 }
 
 template <typename T, typename TB>
-static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, const PcgScalars* scal) {
+static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, const int32_t* stop) {
     if (lv.A.fmt == FMT_SELL) {
         hipLaunchKernelGGL((k_presmooth_res<T, TB>), dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s, view(lv.A.sell),
-                           (const T*)lv.dinv, (T)lv.omega, b, lv.x, lv.res, scal);
+                           (const T*)lv.dinv, (T)lv.omega, b, lv.x, lv.res, stop);
     } else {
         EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_presmooth_res<L_, T, TB>), dim3(csr_grid(lv.A)),
                                                         dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
-                                                        (T)lv.omega, b, lv.x, lv.res, scal));
+                                                        (T)lv.omega, b, lv.x, lv.res, stop));
     }
 }
 
-template <typename T, typename TB, typename TO, bool DOT>
-static void launch_postsmooth(hipStream_t s, const Level<T>& lv, const TB* b, const T* x, TO* out, double* prz,
-                              double* przo, const PcgScalars* scal) {
+// Post-smoothing of a coarse level (no dot products).
+template <typename T>
+static void launch_postsmooth(hipStream_t s, const Level<T>& lv, const T* b, const T* x, T* out, const int32_t* stop) {
     if (lv.A.fmt == FMT_SELL) {
-        hipLaunchKernelGGL((k_postsmooth<T, TB, TO, DOT>), dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
-                           view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, b, x, out, prz, przo, scal);
+        hipLaunchKernelGGL((k_postsmooth<T, T, T, false>), dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
+                           view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, b, x, out, InstMap{}, nullptr, nullptr,
+                           stop);
     } else {
-        EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_postsmooth<L_, T, TB, TO, DOT>), dim3(csr_grid(lv.A)),
+        EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_postsmooth<L_, T, T, T>), dim3(csr_grid(lv.A)),
                                                         dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
-                                                        (T)lv.omega, b, x, out, prz, przo, scal));
+                                                        (T)lv.omega, b, x, out, stop));
     }
 }
 
@@ -515,8 +542,8 @@ template double time_mv<float>(eqs_ctx*, const SpMat<float>&, const float*, floa
 // splits the dot product over its 64 lanes.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const T* __restrict__ b,
-                                                 T* __restrict__ x, int32_t n, const PcgScalars* __restrict__ scal) {
-    if (scal && scal->done) return;
+                                                 T* __restrict__ x, int32_t n, const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
     const int32_t i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (i >= n) return;
@@ -529,11 +556,11 @@ __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const
 // Single-level hierarchy: z = A^{-1} r with the same r.z partials as k_postsmooth.
 template <typename T, bool DOT>
 __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv, const double* __restrict__ r,
-                                                        double* __restrict__ z, int32_t n, double* __restrict__ part_rz,
-                                                        double* __restrict__ part_rzold,
-                                                        const PcgScalars* __restrict__ scal) {
+                                                        double* __restrict__ z, int32_t n, InstMap m,
+                                                        double* __restrict__ part_rz, double* __restrict__ part_rzold,
+                                                        const int32_t* __restrict__ stop) {
     __shared__ double sh[4];
-    if (scal && scal->done) return;
+    if (stop && *stop) return;
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     double rz = 0.0, rzo = 0.0;
     if (i < n) {
@@ -546,41 +573,32 @@ __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv
         z[i] = (double)acc;
     }
     if (DOT) {
-        const double s1 = block_sum(rz, sh);
-        const double s2 = block_sum(rzo, sh);
-        if (threadIdx.x == 0) {
-            part_rz[blockIdx.x] = s1;
-            part_rzold[blockIdx.x] = s2;
-        }
+        int32_t lo, bound;
+        block_instances(m, lo, bound);
+        store_pair(part_rz, rz, i >= bound, sh);
+        store_pair(part_rzold, rzo, i >= bound, sh);
     }
 }
 
-// Number of blocks of the finest-level kernel that writes the r.z partials.
-template <typename T>
-int64_t finest_blocks(const Hierarchy<T>& h) {
-    const Level<T>& lv = h.lv[0];
-    if (h.lv.size() == 1) return grid_for(lv.n);
-    return lv.A.fmt == FMT_SELL ? (int64_t)sell_grid(lv.A.sell) : (int64_t)csr_grid(lv.A);
-}
-template int64_t finest_blocks<double>(const Hierarchy<double>&);
-template int64_t finest_blocks<float>(const Hierarchy<float>&);
+static InstMap inst_map(const eqs_ctx* c) { return InstMap{c->d_inst_row, c->d_blk_inst, (int32_t)c->n_inst}; }
 
 // V(1,1) cycle z = B r. r and z are FP64 (CG's vectors); the hierarchy is T.
+// With part_rz the finest post-smoothing also writes the r.z and r.z_old
+// partials (pair layout); `stop` (may be NULL) ends every kernel at entry.
 template <typename T>
 void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double* z, double* part_rz,
-            const PcgScalars* scal) {
+            double* part_rzold, const int32_t* stop) {
     const int L = (int)h.lv.size();
     dim3 b(kBlock);
-    double* part_rzold = part_rz ? part_rz + c->max_blocks : nullptr;
     if (L == 1) {
         // the matrix is small enough for its dense inverse: z = A^{-1} r
         Level<T>& lv = h.lv[0];
         if (part_rz)
             hipLaunchKernelGGL((k_dense_precond<T, true>), dim3(grid_for(lv.n)), b, 0, s, (const T*)lv.dense_inv, r, z,
-                               lv.n, part_rz, part_rzold, scal);
+                               lv.n, inst_map(c), part_rz, part_rzold, stop);
         else
             hipLaunchKernelGGL((k_dense_precond<T, false>), dim3(grid_for(lv.n)), b, 0, s, (const T*)lv.dense_inv, r,
-                               z, lv.n, part_rz, part_rzold, scal);
+                               z, lv.n, inst_map(c), part_rz, part_rzold, stop);
         return;
     }
     // descend
@@ -588,43 +606,53 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         Level<T>& lv = h.lv[l];
         if (l == 0) {
             prof_begin(c, EQS_KCLASS_PRESMOOTH0, s);
-            launch_presmooth<T, double>(s, lv, r, scal);
+            launch_presmooth<T, double>(s, lv, r, stop);
             prof_end(c, EQS_KCLASS_PRESMOOTH0, s);
         } else {
-            launch_presmooth<T, T>(s, lv, (const T*)lv.b, scal);
+            launch_presmooth<T, T>(s, lv, (const T*)lv.b, stop);
         }
-        launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, scal);
+        launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, stop);
     }
     {
         Level<T>& lc = h.lv[L - 1];
         hipLaunchKernelGGL(k_coarse<T>, dim3(grid_for((int64_t)lc.n * 64)), b, 0, s, (const T*)lc.dense_inv,
-                           (const T*)lc.b, lc.x, lc.n, scal);
+                           (const T*)lc.b, lc.x, lc.n, stop);
     }
     // ascend
     for (int l = L - 2; l >= 0; --l) {
         Level<T>& lv = h.lv[l];
         const T* xc = (l + 1 == L - 1) ? h.lv[l + 1].x : h.lv[l + 1].xs;
-        launch_mv<T>(s, lv.P, xc, lv.x, 1, scal);
+        launch_mv<T>(s, lv.P, xc, lv.x, 1, stop);
         if (l > 0) {
-            launch_postsmooth<T, T, T, false>(s, lv, (const T*)lv.b, (const T*)lv.x, lv.xs, nullptr, nullptr, scal);
-        } else if (part_rz) {
-            prof_begin(c, EQS_KCLASS_POSTSMOOTH0, s);
-            launch_postsmooth<T, double, double, true>(s, lv, r, (const T*)lv.x, z, part_rz, part_rzold, scal);
-            prof_end(c, EQS_KCLASS_POSTSMOOTH0, s);
+            launch_postsmooth<T>(s, lv, (const T*)lv.b, (const T*)lv.x, lv.xs, stop);
         } else {
-            launch_postsmooth<T, double, double, false>(s, lv, r, (const T*)lv.x, z, nullptr, nullptr, scal);
+            // the finest operator is always SELL-64 (see tuned_spmat)
+            prof_begin(c, EQS_KCLASS_POSTSMOOTH0, s);
+            if (part_rz)
+                hipLaunchKernelGGL((k_postsmooth<T, double, double, true>), dim3(sell_grid(lv.A.sell)), b, 0, s,
+                                   view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, r, (const T*)lv.x, z, inst_map(c),
+                                   part_rz, part_rzold, stop);
+            else
+                hipLaunchKernelGGL((k_postsmooth<T, double, double, false>), dim3(sell_grid(lv.A.sell)), b, 0, s,
+                                   view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, r, (const T*)lv.x, z, InstMap{},
+                                   nullptr, nullptr, stop);
+            prof_end(c, EQS_KCLASS_POSTSMOOTH0, s);
         }
     }
 }
 
-template void vcycle<double>(hipStream_t, eqs_ctx*, Hierarchy<double>&, const double*, double*, double*,
-                             const PcgScalars*);
-template void vcycle<float>(hipStream_t, eqs_ctx*, Hierarchy<float>&, const double*, double*, double*,
-                            const PcgScalars*);
+template void vcycle<double>(hipStream_t, eqs_ctx*, Hierarchy<double>&, const double*, double*, double*, double*,
+                             const int32_t*);
+template void vcycle<float>(hipStream_t, eqs_ctx*, Hierarchy<float>&, const double*, double*, double*, double*,
+                            const int32_t*);
 
 // ------------------------------------------------------------------ CG
-// r = rhs - M x; partials of |r|^2 and |rhs|^2.
-__global__ __launch_bounds__(256) void k_pcg_residual(SellView<double> M, const double* __restrict__ rhs,
+// Every instance runs its own CG (own scalars, own convergence test); the
+// sparse products and the V-cycle act on all instances at once (block-diagonal
+// operators). Rows of an instance that is done are left untouched.
+
+// r = rhs - M x; pair partials of |r|^2 and |rhs|^2.
+__global__ __launch_bounds__(256) void k_pcg_residual(SellView<double> M, InstMap m, const double* __restrict__ rhs,
                                                        const double* __restrict__ x, double* __restrict__ r,
                                                        double* __restrict__ part_rr, double* __restrict__ part_bb) {
     __shared__ double sh[4];
@@ -640,205 +668,256 @@ __global__ __launch_bounds__(256) void k_pcg_residual(SellView<double> M, const 
             bb = bi * bi;
         }
     }
-    const double s1 = block_sum(rr, sh);
-    const double s2 = block_sum(bb, sh);
-    if (threadIdx.x == 0) {
-        part_rr[blockIdx.x] = s1;
-        part_bb[blockIdx.x] = s2;
-    }
+    int32_t lo, bound;
+    block_instances(m, lo, bound);
+    store_pair(part_rr, rr, row >= bound, sh);
+    store_pair(part_bb, bb, row >= bound, sh);
 }
 
-// q = M z + beta q, p = z + beta p (so q = M p without a second pass); partials of p.q.
-__global__ __launch_bounds__(256) void k_pcg_spmv(SellView<double> M, const double* __restrict__ z,
+// q = M z + beta q, p = z + beta p (so q = M p without a second pass); pair partials of p.q.
+__global__ __launch_bounds__(256) void k_pcg_spmv(SellView<double> M, InstMap m, const double* __restrict__ z,
                                                    double* __restrict__ p, double* __restrict__ q,
-                                                   double* __restrict__ part_pq, const PcgScalars* __restrict__ scal) {
+                                                   double* __restrict__ part_pq, const PcgScalars* __restrict__ scal,
+                                                   const int32_t* __restrict__ stop) {
     __shared__ double sh[4];
-    if (scal->done) return;
-    const double beta = scal->beta;
-    const int fresh = scal->fresh;
+    if (*stop) return;
+    int32_t lo, bound;
+    block_instances(m, lo, bound);
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool second = row >= bound;
+    const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
     double pq = 0.0;
     if (row < M.n_slices * 64) {
         const double mz = sell_row(M, row, z);
-        if (row < M.n_rows) {
+        if (row < M.n_rows && !S.done) {
             double pi, qi;
-            if (fresh) {
+            if (S.fresh) {
                 pi = z[row];
                 qi = mz;
             } else {
-                pi = z[row] + beta * p[row];
-                qi = mz + beta * q[row];
+                pi = z[row] + S.beta * p[row];
+                qi = mz + S.beta * q[row];
             }
             p[row] = pi;
             q[row] = qi;
             pq = pi * qi;
         }
     }
-    const double s1 = block_sum(pq, sh);
-    if (threadIdx.x == 0) part_pq[blockIdx.x] = s1;
+    store_pair(part_pq, pq, second, sh);
 }
 
-// x += alpha p, r -= alpha q; partials of |r|^2.
-__global__ __launch_bounds__(256) void k_pcg_update(double* __restrict__ x, double* __restrict__ r,
+// x += alpha p, r -= alpha q; pair partials of |r|^2.
+__global__ __launch_bounds__(256) void k_pcg_update(InstMap m, double* __restrict__ x, double* __restrict__ r,
                                                      const double* __restrict__ p, const double* __restrict__ q,
                                                      int64_t n, double* __restrict__ part_rr,
-                                                     const PcgScalars* __restrict__ scal) {
+                                                     const PcgScalars* __restrict__ scal,
+                                                     const int32_t* __restrict__ stop) {
     __shared__ double sh[4];
-    if (scal->done) return;
-    const double alpha = scal->alpha;
+    if (*stop) return;
+    int32_t lo, bound;
+    block_instances(m, lo, bound);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool second = i >= bound;
+    const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
     double rr = 0.0;
-    if (i < n) {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
+    if (i < n && !S.done) {
+        x[i] += S.alpha * p[i];
+        const double ri = r[i] - S.alpha * q[i];
         r[i] = ri;
         rr = ri * ri;
     }
-    const double s1 = block_sum(rr, sh);
-    if (threadIdx.x == 0) part_rr[blockIdx.x] = s1;
+    store_pair(part_rr, rr, second, sh);
+}
+
+// x = 0 on the rows of instances whose right-hand side is zero.
+__global__ void k_zero_rhs_rows(InstMap m, double* __restrict__ x, int64_t n, const PcgScalars* __restrict__ scal) {
+    int32_t lo, bound;
+    block_instances(m, lo, bound);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && scal[min(i >= bound ? lo + 1 : lo, m.n_inst - 1)].bb == 0.0) x[i] = 0.0;
+}
+
+// Summary over the instances, by thread 0, mirrored with all scalars to the host.
+__device__ void summarise(const PcgScalars* __restrict__ s, int32_t n, PcgSummary* __restrict__ sum,
+                          PcgSummary* __restrict__ host_sum, PcgScalars* __restrict__ host) {
+    PcgSummary v{};
+    v.all_done = 1;
+    for (int32_t i = 0; i < n; ++i) {
+        const PcgScalars& x = s[i];
+        if (!x.done) {
+            v.all_done = 0;
+            v.n_active++;
+        }
+        if (x.status == EQS_ERR_BREAKDOWN) v.n_breakdown++;
+        if (x.status == EQS_ERR_NOT_CONVERGED) v.n_notconv++;
+        if (x.bb == 0.0) v.n_zero_rhs++;
+        v.max_it = max(v.max_it, x.it);
+        v.max_relres = fmax(v.max_relres, x.relres);
+        host[i] = x;
+    }
+    *sum = v;
+    *host_sum = v;
 }
 
 // mode 0: start of a solve (it = 0); mode 1: restart from the true residual
-// (iteration count kept). Sets done when |r| <= rtol |rhs|, rhs = 0 or the
-// iteration budget is spent. The scalars are mirrored to host memory.
-__global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, PcgScalars* __restrict__ host, const double* __restrict__ prr,
-                            const double* __restrict__ pbb, int64_t nb, double rtol, int32_t maxit, int32_t flexible,
-                            int32_t mode) {
-    __shared__ double sh[kFin / 64];
-    const double rr = reduce_partials(prr, nb, sh);
-    const double bb = reduce_partials(pbb, nb, sh);
-    if (threadIdx.x != 0) return;
-    PcgScalars v = *s;
-    if (mode == 0) {
-        v = PcgScalars{};
-        v.maxit = maxit;
-        v.flexible = flexible;
-        v.tol2 = rtol * rtol * bb;
+// (iteration count kept; broken-down instances stay so). An instance is done
+// when |r| <= rtol |rhs|, rhs = 0, or its iteration budget is spent.
+__global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, InstMap m, const double* __restrict__ prr,
+                                                     const double* __restrict__ pbb, double rtol, int32_t maxit,
+                                                     int32_t flexible, int32_t mode, PcgSummary* __restrict__ sum,
+                                                     PcgSummary* __restrict__ host_sum,
+                                                     PcgScalars* __restrict__ host) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int32_t i = wave; i < m.n_inst; i += kFin / 64) {
+        const double rr = inst_sum(prr, m, i);
+        const double bb = inst_sum(pbb, m, i);
+        if (lane != 0) continue;
+        PcgScalars v = s[i];
+        if (mode == 0) {
+            v = PcgScalars{};
+            v.maxit = maxit;
+            v.flexible = flexible;
+            v.tol2 = rtol * rtol * bb;
+        } else if (v.status == EQS_ERR_BREAKDOWN) {
+            continue;
+        }
+        v.bb = bb;
+        v.rr = rr;
+        v.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+        v.fresh = 1;
+        v.beta = 0.0;
+        v.status = EQS_OK;
+        v.done = 0;
+        if (bb == 0.0 || rr <= v.tol2) {
+            v.done = 1;
+        } else if (!isfinite(rr) || !isfinite(bb)) {
+            v.done = 1;
+            v.status = EQS_ERR_BREAKDOWN;
+        } else if (v.it >= v.maxit) {
+            v.done = 1;
+            v.status = EQS_ERR_NOT_CONVERGED;
+        }
+        s[i] = v;
     }
-    v.bb = bb;
-    v.rr = rr;
-    v.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-    v.fresh = 1;
-    v.beta = 0.0;
-    v.status = EQS_OK;
-    v.done = 0;
-    if (bb == 0.0 || rr <= v.tol2) {
-        v.done = 1;
-    } else if (v.it >= v.maxit) {
-        v.done = 1;
-        v.status = EQS_ERR_NOT_CONVERGED;
-    } else if (!isfinite(rr) || !isfinite(bb)) {
-        v.done = 1;
-        v.status = EQS_ERR_BREAKDOWN;
-    }
-    *s = v;
-    *host = v;
+    __syncthreads();
+    if (threadIdx.x == 0) summarise(s, m.n_inst, sum, host_sum, host);
 }
 
 // beta from r.z (Polak-Ribiere with r.z_old when flexible).
-__global__ __launch_bounds__(kFin) void k_fin_beta(PcgScalars* __restrict__ s, const double* __restrict__ prz,
-                           const double* __restrict__ przold, int64_t nb) {
-    __shared__ double sh[kFin / 64];
-    if (s->done) return;
-    const double rz = reduce_partials(prz, nb, sh);
-    const double rzo = reduce_partials(przold, nb, sh);
-    if (threadIdx.x != 0) return;
-    if (!(rz > 0.0) || !isfinite(rz)) {
-        s->done = 1;
-        s->status = EQS_ERR_BREAKDOWN;
-        return;
+__global__ __launch_bounds__(kFin) void k_fin_beta(PcgScalars* __restrict__ s, InstMap m,
+                                                    const double* __restrict__ prz, const double* __restrict__ przold,
+                                                    const int32_t* __restrict__ stop) {
+    if (*stop) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int32_t i = wave; i < m.n_inst; i += kFin / 64) {
+        if (s[i].done) continue;
+        const double rz = inst_sum(prz, m, i);
+        const double rzo = inst_sum(przold, m, i);
+        if (lane != 0) continue;
+        PcgScalars& v = s[i];
+        if (!(rz > 0.0) || !isfinite(rz)) {
+            v.done = 1;
+            v.status = EQS_ERR_BREAKDOWN;
+            continue;
+        }
+        if (v.fresh) v.beta = 0.0;
+        else v.beta = v.flexible ? (rz - rzo) / v.rho : rz / v.rho;
+        v.rho = rz;
     }
-    if (s->fresh) s->beta = 0.0;
-    else s->beta = s->flexible ? (rz - rzo) / s->rho : rz / s->rho;
-    s->rho = rz;
 }
 
-__global__ __launch_bounds__(kFin) void k_fin_alpha(PcgScalars* __restrict__ s, const double* __restrict__ ppq, int64_t nb) {
-    __shared__ double sh[kFin / 64];
-    if (s->done) return;
-    const double pq = reduce_partials(ppq, nb, sh);
-    if (threadIdx.x != 0) return;
-    if (!(pq > 0.0) || !isfinite(pq)) {
-        s->done = 1;
-        s->status = EQS_ERR_BREAKDOWN;
-        return;
+__global__ __launch_bounds__(kFin) void k_fin_alpha(PcgScalars* __restrict__ s, InstMap m,
+                                                     const double* __restrict__ ppq, const int32_t* __restrict__ stop) {
+    if (*stop) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int32_t i = wave; i < m.n_inst; i += kFin / 64) {
+        if (s[i].done) continue;
+        const double pq = inst_sum(ppq, m, i);
+        if (lane != 0) continue;
+        PcgScalars& v = s[i];
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            v.done = 1;
+            v.status = EQS_ERR_BREAKDOWN;
+            continue;
+        }
+        v.alpha = v.rho / pq;
+        v.fresh = 0;
     }
-    s->alpha = s->rho / pq;
-    s->fresh = 0;
 }
 
-__global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, PcgScalars* __restrict__ host, const double* __restrict__ prr,
-                           int64_t nb) {
-    __shared__ double sh[kFin / 64];
-    if (s->done) {
-        if (threadIdx.x == 0) host->done = 1;
-        return;
+__global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, InstMap m,
+                                                    const double* __restrict__ prr, PcgSummary* __restrict__ sum,
+                                                    PcgSummary* __restrict__ host_sum, PcgScalars* __restrict__ host) {
+    if (sum->all_done) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int32_t i = wave; i < m.n_inst; i += kFin / 64) {
+        if (s[i].done) continue;
+        const double rr = inst_sum(prr, m, i);
+        if (lane != 0) continue;
+        PcgScalars& v = s[i];
+        v.rr = rr;
+        v.relres = sqrt(rr / v.bb);
+        v.it += 1;
+        if (rr <= v.tol2) {
+            v.done = 1;
+        } else if (!isfinite(rr)) {
+            v.done = 1;
+            v.status = EQS_ERR_BREAKDOWN;
+        } else if (v.it >= v.maxit) {
+            v.done = 1;
+            v.status = EQS_ERR_NOT_CONVERGED;
+        }
     }
-    const double rr = reduce_partials(prr, nb, sh);
-    if (threadIdx.x != 0) return;
-    PcgScalars v = *s;
-    v.rr = rr;
-    v.relres = sqrt(rr / v.bb);
-    v.it += 1;
-    if (rr <= v.tol2) {
-        v.done = 1;
-    } else if (v.it >= v.maxit) {
-        v.done = 1;
-        v.status = EQS_ERR_NOT_CONVERGED;
-    } else if (!isfinite(rr)) {
-        v.done = 1;
-        v.status = EQS_ERR_BREAKDOWN;
-    }
-    *s = v;
-    *host = v;
+    __syncthreads();
+    if (threadIdx.x == 0) summarise(s, m.n_inst, sum, host_sum, host);
 }
 
-static PcgScalars* host_mirror(eqs_ctx* c) { return c->d_hscal; }
+static double* part(eqs_ctx* c, int q) { return c->d_partials + (int64_t)q * 2 * c->max_blocks; }
 
 void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int32_t maxit, double rtol,
               int flexible) {
     const int64_t nb = sell_grid(c->M);
-    double* P = c->d_partials;
-    hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), rhs, x, c->d_r, P,
-                       P + c->max_blocks);
-    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, host_mirror(c), P, P + c->max_blocks,
-                       nb, rtol, maxit, flexible, 0);
+    hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
+                       part(c, 0), part(c, 1));
+    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), rtol,
+                       maxit, flexible, 0, c->d_sum, c->d_hsum, c->d_hscal);
 }
 
 void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x) {
     const int64_t nb = sell_grid(c->M);
-    double* P = c->d_partials;
-    hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), rhs, x, c->d_r, P,
-                       P + c->max_blocks);
-    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, host_mirror(c), P, P + c->max_blocks,
-                       nb, 0.0, 0, 0, 1);
+    hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
+                       part(c, 0), part(c, 1));
+    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), 0.0, 0,
+                       0, 1, c->d_sum, c->d_hsum, c->d_hscal);
 }
 
-void pcg_restart(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x) { pcg_true_residual(s, c, rhs, x); }
+void pcg_zero_rhs_rows(hipStream_t s, eqs_ctx* c, double* x) {
+    hipLaunchKernelGGL(k_zero_rhs_rows, dim3(grid_for(c->n_free)), dim3(kBlock), 0, s, inst_map(c), x, c->n_free,
+                       c->d_scal);
+}
 
 void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int precision) {
     (void)rhs;
     const int64_t nbM = sell_grid(c->M);
-    const int64_t nbV = (c->n_free + kBlock - 1) / kBlock;
-    double* P = c->d_partials;
-    const int64_t mb = c->max_blocks;
-    // z = B r, with partials of r.z (P) and r.z_old (P + mb)
+    const int64_t nbV = grid_for(c->n_free);
+    const int32_t* stop = &c->d_sum->all_done;
+    // z = B r, with pair partials of r.z (part 0) and r.z_old (part 1)
     prof_begin(c, EQS_KCLASS_VCYCLE, s);
-    if (precision == EQS_PREC_FP32) vcycle<float>(s, c, c->h32, c->d_r, c->d_z, P, c->d_scal);
-    else vcycle<double>(s, c, c->h64, c->d_r, c->d_z, P, c->d_scal);
+    if (precision == EQS_PREC_FP32) vcycle<float>(s, c, c->h32, c->d_r, c->d_z, part(c, 0), part(c, 1), stop);
+    else vcycle<double>(s, c, c->h64, c->d_r, c->d_z, part(c, 0), part(c, 1), stop);
     prof_end(c, EQS_KCLASS_VCYCLE, s);
-    const int64_t nbz = precision == EQS_PREC_FP32 ? finest_blocks(c->h32) : finest_blocks(c->h64);
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFin), 0, s, c->d_scal, P, P + mb, nbz);
+    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), stop);
     prof_begin(c, EQS_KCLASS_SPMV_M, s);
-    hipLaunchKernelGGL(k_pcg_spmv, dim3(nbM), dim3(kBlock), 0, s, view(c->M), c->d_z, c->d_p, c->d_q, P + 2 * mb,
-                       c->d_scal);
+    hipLaunchKernelGGL(k_pcg_spmv, dim3(nbM), dim3(kBlock), 0, s, view(c->M), inst_map(c), c->d_z, c->d_p, c->d_q,
+                       part(c, 2), c->d_scal, stop);
     prof_end(c, EQS_KCLASS_SPMV_M, s);
-    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFin), 0, s, c->d_scal, P + 2 * mb, nbM);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 2), stop);
     prof_begin(c, EQS_KCLASS_CG_UPDATE, s);
-    hipLaunchKernelGGL(k_pcg_update, dim3(nbV), dim3(kBlock), 0, s, x, c->d_r, c->d_p, c->d_q, c->n_free,
-                       P + 3 * mb, c->d_scal);
+    hipLaunchKernelGGL(k_pcg_update, dim3(nbV), dim3(kBlock), 0, s, inst_map(c), x, c->d_r, c->d_p, c->d_q,
+                       c->n_free, part(c, 3), c->d_scal, stop);
     prof_end(c, EQS_KCLASS_CG_UPDATE, s);
-    hipLaunchKernelGGL(k_fin_conv, dim3(1), dim3(kFin), 0, s, c->d_scal, host_mirror(c), P + 3 * mb, nbV);
+    hipLaunchKernelGGL(k_fin_conv, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 3), c->d_sum,
+                       c->d_hsum, c->d_hscal);
 }
 
 // ------------------------------------------------------------------ RKC

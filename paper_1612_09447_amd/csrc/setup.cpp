@@ -65,6 +65,32 @@ void validate_and_order(eqs_ctx* c) {
         if (is_dir[i]) c->int_to_user[d++] = (int32_t)i;
         else c->int_to_user[f++] = (int32_t)i;
     }
+    // instances: free rows of instance i are the free nodes of its node range,
+    // contiguous because free nodes keep increasing user ids
+    if (c->inst_node_off.empty()) {
+        c->inst_node_off = {0, N};
+        c->inst_tet_off = {0, c->n_tets};
+    }
+    c->n_inst = (int64_t)c->inst_node_off.size() - 1;
+    c->inst_row_off.assign(c->n_inst + 1, 0);
+    for (int64_t i = 0; i < c->n_inst; ++i) {
+        int64_t nf = 0, nd = 0;
+        for (int64_t v = c->inst_node_off[i]; v < c->inst_node_off[i + 1]; ++v) (is_dir[v] ? nd : nf)++;
+        if (nd == 0) fail(EQS_ERR_INVALID_ARG, "instance " + std::to_string(i) + " has no Dirichlet node");
+        if (nf == 0) fail(EQS_ERR_INVALID_ARG, "instance " + std::to_string(i) + " has no free node");
+        if (c->n_inst > 1 && nf < 256)
+            fail(EQS_ERR_INVALID_ARG, "instance " + std::to_string(i) + " has fewer than 256 free nodes");
+        c->inst_row_off[i + 1] = c->inst_row_off[i] + (int32_t)nf;
+    }
+    for (int64_t i = 0; i < c->n_inst; ++i)
+        for (int64_t e = c->inst_tet_off[i]; e < c->inst_tet_off[i + 1]; ++e)
+            for (int a = 0; a < 4; ++a) {
+                const int32_t v = c->tets[4 * e + a];
+                if (v < c->inst_node_off[i] || v >= c->inst_node_off[i + 1])
+                    fail(EQS_ERR_INVALID_ARG, "tet " + std::to_string(e) + " uses a node of another instance");
+            }
+    c->inst_iters.assign(c->n_inst, 0);
+    c->inst_relres.assign(c->n_inst, 0.0);
 }
 
 // ----------------------------------------------------------- assembly of M
@@ -307,6 +333,13 @@ static int32_t aggregate(const Csr<double>& A, const std::vector<double>& d, dou
             if (strong[k] && agg[A.col[k]] == -1) agg[A.col[k]] = na;
         ++na;
     }
+    // number aggregates in the order of their first row, so coarse rows follow
+    // fine rows (locality, and instances stay contiguous at every level)
+    std::vector<int32_t> renum(na, -1);
+    int32_t next = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (renum[agg[i]] < 0) renum[agg[i]] = next++;
+    for (int32_t i = 0; i < n; ++i) agg[i] = renum[agg[i]];
     return na;
 }
 
@@ -564,7 +597,15 @@ static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
 // with HIP events on the context's stream (median of 5 after 2 warm-ups) and
 // keep the fastest.
 template <typename T>
-static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what) {
+static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, bool sell_only = false) {
+    if (sell_only) {  // the finest operator: its post-smoothing kernel writes per-block CG partials
+        SpMat<T> S;
+        S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
+        S.fmt = FMT_SELL;
+        S.sell = to_sell<T>(c, A);
+        c->tune_log += std::string(what) + ": sell64 (finest level)\n";
+        return S;
+    }
     if (!c->autotune || A.n_rows == 0) return to_spmat<T>(c, A);
     const double mean = (double)A.nnz() / A.n_rows;
     T* x = (T*)dev_alloc(c, sizeof(T) * std::max<int32_t>(A.n_cols, 1));
@@ -624,7 +665,7 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
     for (size_t l = 0; l < L; ++l) {
         Level<T>& lv = h.lv[l];
         lv.n = ah.A[l].n_rows;
-        lv.A = tuned_spmat<T>(c, ah.A[l], ("A" + std::to_string(l)).c_str());
+        lv.A = tuned_spmat<T>(c, ah.A[l], ("A" + std::to_string(l)).c_str(), l == 0);
         std::vector<double> d = diagonal(ah.A[l]);
         std::vector<T> dinv(lv.n);
         for (int32_t i = 0; i < lv.n; ++i) dinv[i] = (T)(1.0 / d[i]);
@@ -673,14 +714,21 @@ void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i) {
     double inv_ext[3];
     for (int d = 0; d < 3; ++d) inv_ext[d] = hi[d] > lo[d] ? 1.0 / (hi[d] - lo[d]) : 0.0;
     std::vector<std::pair<uint64_t, int32_t>> key(T);
+    std::vector<int32_t> tinst(T, 0);
+    for (int64_t i = 0; i < c->n_inst; ++i)
+        for (int64_t e = c->inst_tet_off[i]; e < c->inst_tet_off[i + 1]; ++e) tinst[e] = (int32_t)i;
     for (int64_t e = 0; e < T; ++e) {
         double cen[3] = {0, 0, 0};
         for (int a = 0; a < 4; ++a)
             for (int d = 0; d < 3; ++d) cen[d] += 0.25 * c->xyz[3 * (int64_t)c->tets[4 * e + a] + d];
         key[e] = {morton3(cen, lo, inv_ext), (int32_t)e};
     }
+    // instance first (blocks then never mix instances, whose meshes may overlap in space)
     std::stable_sort(key.begin(), key.end(),
-                     [](const std::pair<uint64_t, int32_t>& x, const std::pair<uint64_t, int32_t>& y) { return x.first < y.first; });
+                     [&](const std::pair<uint64_t, int32_t>& x, const std::pair<uint64_t, int32_t>& y) {
+                         if (tinst[x.second] != tinst[y.second]) return tinst[x.second] < tinst[y.second];
+                         return x.first < y.first;
+                     });
     const int64_t nb = (T + kTetBlock - 1) / kTetBlock;
     std::vector<uint64_t> pack(T);
     std::vector<int32_t> boff(nb + 1, 0), bnodes;
@@ -746,6 +794,12 @@ void upload(eqs_ctx* c) {
     c->d_xyz = upload_vec(c, xyz);
     c->d_mats = upload_vec(c, md);
     c->d_ddrive = upload_vec(c, dd);
+    {
+        std::vector<DriveDev> dr(c->drives.size());
+        for (size_t k = 0; k < dr.size(); ++k)
+            dr[k] = DriveDev{2.0 * M_PI * c->drives[k].freq, c->drives[k].amp, c->drives[k].phase, 0.0};
+        c->d_drives = upload_vec(c, dr);
+    }
     c->d_int_to_user = upload_vec(c, c->int_to_user);
 
     c->tune_log.clear();
@@ -761,10 +815,25 @@ void upload(eqs_ctx* c) {
     c->d_Y0 = vec(NF); c->d_Ya = vec(NF); c->d_Yb = vec(NF); c->d_F0 = vec(NF); c->d_F = vec(NF);
     c->d_rhs = vec(NF); c->d_tmpN = vec(N); c->d_tmpN2 = vec(N);
     c->max_blocks = (std::max<int64_t>(N, T) + kBlock - 1) / kBlock + 1;
-    c->d_partials = vec(4 * c->max_blocks);
-    c->d_scal = (PcgScalars*)dev_alloc(c, sizeof(PcgScalars));
-    EQS_HIP(hipHostMalloc((void**)&c->h_scal, 2 * sizeof(PcgScalars), hipHostMallocMapped));
+    c->d_partials = vec(8 * c->max_blocks);
+    c->d_scal = (PcgScalars*)dev_alloc(c, sizeof(PcgScalars) * (size_t)c->n_inst);
+    c->d_sum = (PcgSummary*)dev_alloc(c, sizeof(PcgSummary));
+    EQS_HIP(hipMemset(c->d_sum, 0, sizeof(PcgSummary)));
+    EQS_HIP(hipHostMalloc((void**)&c->h_scal, sizeof(PcgScalars) * (size_t)c->n_inst, hipHostMallocMapped));
     EQS_HIP(hipHostGetDevicePointer((void**)&c->d_hscal, c->h_scal, 0));
+    EQS_HIP(hipHostMalloc((void**)&c->h_sum, sizeof(PcgSummary), hipHostMallocMapped));
+    EQS_HIP(hipHostGetDevicePointer((void**)&c->d_hsum, c->h_sum, 0));
+    c->d_inst_row = upload_vec(c, c->inst_row_off);
+    {
+        const int64_t nb = (NF + kBlock - 1) / kBlock;
+        std::vector<int32_t> bi(std::max<int64_t>(nb, 1), 0);
+        int32_t i = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            while (i + 1 < c->n_inst && c->inst_row_off[i + 1] <= b * kBlock) ++i;
+            bi[b] = i;
+        }
+        c->d_blk_inst = upload_vec(c, bi);
+    }
     EQS_HIP(hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming));
     EQS_HIP(hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming));
     c->have_Flast = false;
@@ -776,6 +845,8 @@ void free_device(eqs_ctx* c) {
     c->allocations.clear();
     c->device_bytes = 0;
     if (c->h_scal) { (void)hipHostFree(c->h_scal); c->h_scal = nullptr; c->d_hscal = nullptr; }
+    if (c->h_sum) { (void)hipHostFree(c->h_sum); c->h_sum = nullptr; c->d_hsum = nullptr; }
+    c->d_sum = nullptr; c->d_inst_row = nullptr; c->d_blk_inst = nullptr;
     for (auto& e : c->ev)
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
     c->M = Sell<double>{};
@@ -783,7 +854,7 @@ void free_device(eqs_ctx* c) {
     c->h32.lv.clear();
     c->d_tpack = nullptr; c->d_bnodes = nullptr; c->d_boff = nullptr; c->n_blocks = 0; c->max_block_nodes = 0;
     c->d_xyz = nullptr; c->d_mats = nullptr;
-    c->d_ddrive = nullptr; c->d_int_to_user = nullptr;
+    c->d_ddrive = nullptr; c->d_int_to_user = nullptr; c->d_drives = nullptr;
     c->d_r = c->d_z = c->d_p = c->d_q = nullptr;
     c->d_Y0 = c->d_Ya = c->d_Yb = c->d_F0 = c->d_F = nullptr;
     c->d_rhs = c->d_tmpN = c->d_tmpN2 = nullptr;
@@ -795,17 +866,6 @@ void free_device(eqs_ctx* c) {
     c->guess.d_S = c->guess.d_rprev = c->guess.d_x0 = c->guess.d_alpha = c->guess.d_dots = c->guess.d_part = nullptr;
     c->guess.d_bx = c->guess.d_bt = nullptr;
     if (!c->guess.G.empty()) guess_reset(c);
-}
-
-DriveVals drive_values(const eqs_ctx* c, double t) {
-    DriveVals dv{};
-    for (size_t k = 0; k < c->drives.size(); ++k) {
-        const eqs_drive& d = c->drives[k];
-        const double w = 2.0 * M_PI * d.freq;
-        dv.g[k] = d.amp * std::sin(w * t + d.phase);
-        dv.gd[k] = w * d.amp * std::cos(w * t + d.phase);
-    }
-    return dv;
 }
 
 }  // namespace eqs

@@ -14,12 +14,11 @@
 
 namespace eqs {
 
-static PcgScalars read_scalars(eqs_ctx* c) {
-    const volatile PcgScalars* h = c->h_scal;
-    PcgScalars v;
-    v.bb = h->bb; v.rr = h->rr; v.rho = h->rho; v.rho_old = h->rho_old; v.beta = h->beta; v.alpha = h->alpha;
-    v.tol2 = h->tol2; v.relres = h->relres; v.it = h->it; v.maxit = h->maxit; v.done = h->done;
-    v.status = h->status; v.fresh = h->fresh; v.flexible = h->flexible;
+static PcgSummary read_summary(eqs_ctx* c) {
+    const volatile PcgSummary* h = c->h_sum;
+    PcgSummary v;
+    v.all_done = h->all_done; v.n_active = h->n_active; v.n_breakdown = h->n_breakdown; v.n_notconv = h->n_notconv;
+    v.n_zero_rhs = h->n_zero_rhs; v.max_it = h->max_it; v.max_relres = h->max_relres;
     return v;
 }
 
@@ -65,61 +64,56 @@ void release_graphs(eqs_ctx* c) {
     c->iter_prec = -1;
 }
 
+// Solve M y = rhs for every instance to its own rel-res rtol. The host
+// enqueues iteration k+1 before it waits for iteration k and reads only the
+// "all done" flag of the pinned summary. When every instance has converged on
+// its recursive residual, the true residuals are checked; instances that
+// disagree restart from them. Aggregated stats: max iterations, worst status,
+// max relres; per-instance results are in c->inst_iters / c->inst_relres.
 int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st) {
     hipStream_t s = c->stream;
     const int prec = c->amg.precision;
     pcg_init(s, c, rhs, y, maxit, rtol, c->amg.flexible);
     check_launch();
     EQS_HIP(hipStreamSynchronize(s));
-    PcgScalars v = read_scalars(c);
-    if (v.bb == 0.0) {
-        launch_fill(s, y, 0.0, c->n_free);
-        EQS_HIP(hipStreamSynchronize(s));
-        if (st) *st = eqs_solve_stats{0, EQS_OK, 0.0};
-        return EQS_OK;
-    }
+    PcgSummary v = read_summary(c);
+    if (v.n_zero_rhs > 0) pcg_zero_rhs_rows(s, c, y);
     int restarts = 0;
-    while (!v.done) {
-        // iterate until the device reports done, keeping one iteration queued ahead
+    while (!v.all_done) {
         for (int64_t k = 0;; ++k) {
             run_iteration(c, y, prec);
             EQS_HIP(hipEventRecord(c->ev[k & 1], s));
             if (k >= 1) {
                 EQS_HIP(hipEventSynchronize(c->ev[(k - 1) & 1]));
-                if (((volatile PcgScalars*)c->h_scal)->done) break;
+                if (((volatile PcgSummary*)c->h_sum)->all_done) break;
             }
             if (k > (int64_t)maxit + 2) break;  // the device stops itself at maxit
         }
         check_launch();
         EQS_HIP(hipStreamSynchronize(s));
-        v = read_scalars(c);
-        if (v.status == EQS_ERR_BREAKDOWN) break;
-        // converged on the recursive residual (or out of iterations): check the
-        // true residual; if it disagrees, CG restarts from it
+        // every instance is done on its recursive residual (or out of iterations,
+        // or broken down): check the true residuals; disagreeing ones restart
         pcg_true_residual(s, c, rhs, y);
         check_launch();
         EQS_HIP(hipStreamSynchronize(s));
-        v = read_scalars(c);
-        if (++restarts > 4 && !v.done) {
-            v.status = EQS_ERR_NOT_CONVERGED;
-            break;
-        }
+        v = read_summary(c);
+        if (++restarts > 4) break;
     }
-    if (v.status == EQS_ERR_BREAKDOWN) {
-        const int it = v.it;
-        pcg_true_residual(s, c, rhs, y);
-        EQS_HIP(hipStreamSynchronize(s));
-        v = read_scalars(c);
-        v.it = it;
-        v.status = EQS_ERR_BREAKDOWN;
+    int status = EQS_OK;
+    if (v.n_notconv > 0 || !v.all_done) status = EQS_ERR_NOT_CONVERGED;
+    if (v.n_breakdown > 0) status = EQS_ERR_BREAKDOWN;
+    for (int64_t i = 0; i < c->n_inst; ++i) {
+        const volatile PcgScalars& x = c->h_scal[i];
+        c->inst_iters[i] += x.it;
+        c->inst_relres[i] = std::max(c->inst_relres[i], (double)x.relres);
     }
-    if (st) *st = eqs_solve_stats{v.it, v.status, v.relres};
-    return v.status;
+    if (st) *st = eqs_solve_stats{v.max_it, status, v.max_relres};
+    return status;
 }
 
 void apply_preconditioner(eqs_ctx* c, const double* r, double* z) {
-    if (c->amg.precision == EQS_PREC_FP32) vcycle<float>(c->stream, c, c->h32, r, z, nullptr, nullptr);
-    else vcycle<double>(c->stream, c, c->h64, r, z, nullptr, nullptr);
+    if (c->amg.precision == EQS_PREC_FP32) vcycle<float>(c->stream, c, c->h32, r, z, nullptr, nullptr, nullptr);
+    else vcycle<double>(c->stream, c, c->h64, r, z, nullptr, nullptr, nullptr);
     check_launch();
     EQS_HIP(hipStreamSynchronize(c->stream));
 }
@@ -134,6 +128,8 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
     launch_gather(q, x_user, c->d_int_to_user, c->d_Y0, NF);
     if (!c->have_Flast) launch_fill(q, c->d_F, 0.0, NF);
 
+    std::fill(c->inst_iters.begin(), c->inst_iters.end(), 0);
+    std::fill(c->inst_relres.begin(), c->inst_relres.end(), 0.0);
     eqs_step_stats S{};
     S.stages = s;
     S.min_iters = INT32_MAX;
@@ -142,7 +138,7 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
     const double* Yprev = c->d_Y0;
     for (int j = 0; j < s; ++j) {
         const double tj = t + cc[j] * dt;
-        launch_kx(q, true, c, Ycur, drive_values(c, tj), c->d_rhs);
+        launch_kx(q, true, c, Ycur, tj, c->d_rhs);
         check_launch();
         // start vector: F_{j-1} (held in d_F), zero, or an estimator's vector
         const int kind = c->guess.p.kind;
@@ -186,7 +182,7 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
         Yprev = Ycur;
         Ycur = out;
     }
-    launch_finish_state(q, Ycur, c->d_int_to_user, c->d_ddrive, drive_values(c, t + dt), x_user, NF, c->n_nodes);
+    launch_finish_state(c, Ycur, t + dt, x_user);
     check_launch();
     EQS_HIP(hipStreamSynchronize(q));
     c->have_Flast = true;
