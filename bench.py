@@ -53,6 +53,31 @@ def spmv_bytes(info, nnz):
     return 12 * nnz + 4 * (n // 64 + 1) + 8 * n + 32 * n
 
 
+def copy_probe(mib=512, reps=20):
+    """Bandwidth of a plain device-to-device copy (torch's copy kernel) of
+    `mib` MiB: the measured streaming ceiling beside the nominal peak, and the
+    reference launch that scales the HBM byte counters."""
+    import torch
+
+    src = torch.empty(mib << 17, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for r in range(reps + 2):
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        ev[1].synchronize()
+        if r >= 2:
+            times.append(ev[0].elapsed_time(ev[1]) * 1e-3)
+    times.sort()
+    nbytes = 2 * src.numel() * 8
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch": nbytes, "median_us": round(times[len(times) // 2] * 1e6, 2),
+            "GB/s": round(nbytes / times[len(times) // 2] / 1e9, 1)}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -69,9 +94,33 @@ KERNEL_NAMES = {"element": "k_kx<true>", "spmv_M": "k_pcg_spmv", "presmooth0": "
                 "postsmooth0": "k_postsmooth (finest)", "cg_update": "k_pcg_update", "rkc_combine": "k_rkc_combine"}
 
 
-def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous", flexible=0):
+def timed_steps(ctx, x, n, steps, tau, s, rtol, label):
+    """Run `steps` RKC steps from step index n; returns (elapsed s, per-step
+    mean CG iterations per stage, guesses used, guard fallbacks)."""
+    import torch
+
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    iters, used, fallbacks = [], 0, 0
+    for k in range(steps):
+        st = ctx.rkc_step((n + k) * tau, tau, s, x, rtol=rtol, maxit=500)
+        iters.append(st["total_iters"] / st["stages"])
+        used += st["guess_used"]
+        fallbacks += st["guess_fallbacks"]
+        if (k + 1) % max(1, steps // 5) == 0:
+            log(f"[bench] {label} step {k + 1}/{steps} mean CG it/stage {sum(iters) / len(iters):.2f}")
+    torch.cuda.synchronize()
+    return time.perf_counter() - t1, iters, used, fallbacks
+
+
+def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous", flexible=0, learned_steps=0,
+            learned_warmup=20):
     """Time `steps` RKC steps (uninstrumented), then `prof_steps` more with every
-    kernel class timed by HIP events on the context's stream."""
+    kernel class timed by HIP events on the context's stream. With
+    learned_steps > 0 the same context then switches to the Galerkin and the
+    network start vectors and times that many steps of each (after
+    learned_warmup untimed steps that fill the snapshot window and the replay
+    buffer)."""
     import torch
 
     import eqsgen
@@ -94,19 +143,8 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
     for _ in range(warmup):
         ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
         n += 1
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    iters, used, fallbacks = [], 0, 0
-    for k in range(steps):
-        st = ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
-        iters.append(st["total_iters"] / st["stages"])
-        used += st["guess_used"]
-        fallbacks += st["guess_fallbacks"]
-        n += 1
-        if (k + 1) % max(1, steps // 5) == 0:
-            log(f"[bench] {precision}/{guess} step {k + 1}/{steps} mean CG it/stage {sum(iters) / len(iters):.2f}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t1
+    elapsed, iters, used, fallbacks = timed_steps(ctx, x, n, steps, tau, s, rtol, f"{precision}/{guess}")
+    n += steps
     prof, prof_elapsed = {}, 0.0
     if prof_steps > 0:
         ctx.profile_enable(ALL_CLASSES)
@@ -119,10 +157,31 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         prof_elapsed = time.perf_counter() - t2
         prof = {c: ctx.profile_read(c) for c in ALL_CLASSES}
         ctx.profile_enable(())
+    learned = {}
+    if learned_steps > 0:
+        # the reference leg: the plain start vector over the same window length
+        el, it, _, _ = timed_steps(ctx, x, n, learned_steps, tau, s, rtol, "previous")
+        n += learned_steps
+        learned["previous"] = {"stages_per_s": round(learned_steps * s / el, 2),
+                               "mean_cg_iters_per_stage": round(sum(it) / len(it), 2)}
+        for kind in ("zero", "galerkin", "mlp"):
+            if kind == "mlp":
+                ctx.set_guess("mlp", init=eqsgen.mlp_init(4))
+            else:
+                ctx.set_guess(kind)
+            wu = 1 if kind == "zero" else learned_warmup
+            timed_steps(ctx, x, n, wu, tau, s, rtol, f"{kind} warm-up")
+            n += wu
+            el, it, u, fb = timed_steps(ctx, x, n, learned_steps, tau, s, rtol, kind)
+            n += learned_steps
+            learned[kind] = {"stages_per_s": round(learned_steps * s / el, 2),
+                             "mean_cg_iters_per_stage": round(sum(it) / len(it), 2),
+                             "guess_used": u, "guard_fallbacks": fb, "warmup_steps": wu}
+        ctx.set_guess("previous")
     xn = x.cpu().numpy()
     ctx.close()
     return dict(elapsed=elapsed, stages=steps * s, iters=iters, info=info, prof=prof, prof_elapsed=prof_elapsed,
-                prof_stages=prof_steps * s, setup_s=setup_s, x=xn, used=used, fallbacks=fallbacks)
+                prof_stages=prof_steps * s, setup_s=setup_s, x=xn, used=used, fallbacks=fallbacks, learned=learned)
 
 
 def run_batched(steps, warmup):
@@ -200,6 +259,8 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     ap.add_argument("--c3-steps", type=int, default=0, help="also time the 64-instance batched workload")
+    ap.add_argument("--learned-steps", type=int, default=0,
+                    help="also time this many steps with each start vector (zero, Galerkin, network)")
     args = ap.parse_args()
 
     os.environ["EQS_USE_GRAPHS"] = "1" if args.graphs else "0"
@@ -218,8 +279,10 @@ def main():
     from paper_1612_09447_amd import EQS_PREC_FP32, EQS_PREC_FP64
 
     main_prec = EQS_PREC_FP32 if prec == "fp32" else EQS_PREC_FP64
+    copy = copy_probe()
+    log(f"[bench] copy probe: {copy}")
     r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess,
-                flexible=args.flexible)
+                flexible=args.flexible, learned_steps=args.learned_steps)
     stages_per_s = r["stages"] / r["elapsed"]
     info = r["info"]
     prof = r["prof"]
@@ -235,6 +298,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dominant],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac_of_copy": round(achieved / copy["GB/s"], 4),
                 "bytes_per_launch": per_class_bytes[dominant], "avg_launch_us": round(avg_s * 1e6, 2),
                 "timing": f"HIP events around every launch on the context stream, {args.prof_steps} instrumented "
                           f"steps following the timed ones"}
@@ -285,7 +349,9 @@ def main():
         },
         "roofline": roofline,
         "kernel_breakdown": breakdown,
+        "copy_probe": copy,
         "fp64_plain": plain,
+        "start_vectors": r["learned"] or None,
         "batched": batched,
         "cpu_baseline": cpu,
     }

@@ -78,6 +78,8 @@ int eqs_create(eqs_ctx** out, int device, void* hip_stream) {
         c->use_graphs = !(g && g[0] == '0');
         const char* at = std::getenv("EQS_AUTOTUNE");  // "0" keeps the rule-based operator layouts
         c->autotune = !(at && at[0] == '0');
+        const char* i16 = std::getenv("EQS_INDEX16");
+        c->index16 = !(i16 && i16[0] == '0');
         *out = c;
         return EQS_OK;
     });
@@ -443,8 +445,10 @@ int eqs_describe(const eqs_ctx* c, char* buf, int64_t cap, int64_t* needed) {
                       (long long)c->n_nodes, (long long)c->n_tets, (long long)c->n_free, (long long)c->nnz_M,
                       c->amg.precision == EQS_PREC_FP32 ? "fp32" : "fp64", (int)c->built);
         d += line;
-        std::snprintf(line, sizeof line, "element blocks %lld, max nodes per block %d, graphs %d, autotune %d\n",
-                      (long long)c->n_blocks, c->max_block_nodes, (int)c->use_graphs, (int)c->autotune);
+        std::snprintf(line, sizeof line,
+                      "element blocks %lld of %d tets, block nodes %lld (max %d), graphs %d, autotune %d\n",
+                      (long long)c->n_blocks, eqs::kTetBlock * c->tet_tpt, (long long)c->n_block_nodes,
+                      c->max_block_nodes, (int)c->use_graphs, (int)c->autotune);
         d += line;
         d += c->tune_log;
         if (needed) *needed = (int64_t)d.size() + 1;

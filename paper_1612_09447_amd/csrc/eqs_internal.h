@@ -28,7 +28,9 @@
 namespace eqs {
 
 constexpr int kSlice = 64;   // SELL slice height = wavefront size
-constexpr int kTetBlock = 256;  // tets per element-pass workgroup
+constexpr int kTetBlock = 256;  // threads per element-pass workgroup
+constexpr int kMaxTetsPerThread = 8;  // element blocks hold kTetBlock * tpt tets, tpt in {1, 2, 4, 8}
+constexpr int kMaxBlockNodes = 1360;  // distinct nodes per element block: 48 B of LDS each (<= 64 KiB)
 constexpr int kBlock = 256;  // threads per block for streaming kernels
 
 // ---------------------------------------------------------------- errors
@@ -60,7 +62,8 @@ struct Sell {
     int32_t n_rows = 0, n_cols = 0, n_slices = 0;
     int64_t stored = 0;         // padded entries
     int32_t* sptr = nullptr;    // [n_slices + 1]
-    int32_t* col = nullptr;     // [stored]
+    int32_t* col = nullptr;     // [stored] absolute column ids, or
+    int16_t* d16 = nullptr;     // [stored] column - row (when every entry is within 32767 rows)
     T* val = nullptr;           // [stored]
 };
 
@@ -199,16 +202,21 @@ struct eqs_ctx {
     eqs_amg_params amg{};
     int64_t nnz_M = 0;
 
-    // device: mesh + materials. Tets are processed in blocks of kTetBlock
-    // (Morton order of centroids); block b lists its distinct nodes in
-    // d_bnodes[d_boff[b] .. d_boff[b+1]) and every tet packs the 12-bit
-    // block-local ids of its vertices and its 16-bit material id in 64 bits.
+    // device: mesh + materials. Tets are processed in blocks of
+    // kTetBlock * tet_tpt tets (Morton order of centroids); block b lists its
+    // distinct nodes in d_bnodes[d_boff[b] .. d_boff[b+1]) and every tet packs
+    // the 12-bit block-local ids of its vertices and its 16-bit material id in
+    // 64 bits. Coordinates are stored per axis (d_cx, d_cy, d_cz).
     uint64_t* d_tpack = nullptr;
     int32_t* d_bnodes = nullptr;
     int32_t* d_boff = nullptr;
     int64_t n_blocks = 0;
     int32_t max_block_nodes = 0;
-    double4* d_xyz = nullptr;
+    int32_t tet_tpt = 0;        // tets per thread of the element pass
+    int64_t n_block_nodes = 0;  // entries of d_bnodes (nodes shared by blocks count once per block)
+    double* d_cx = nullptr;
+    double* d_cy = nullptr;
+    double* d_cz = nullptr;
     eqs::MatDev* d_mats = nullptr;
     int32_t* d_ddrive = nullptr;
     eqs::DriveDev* d_drives = nullptr;
@@ -245,6 +253,7 @@ struct eqs_ctx {
 
     int64_t device_bytes = 0;
     std::vector<std::pair<void*, size_t>> allocations;
+    bool index16 = true;   // 16-bit column offsets for SELL operators whose entries allow them
     bool autotune = true;  // time the candidate layouts of every AMG operator at build time
     std::string tune_log;  // chosen layouts, one line per operator
 
@@ -283,7 +292,7 @@ void dev_free(eqs_ctx* c, void* p);
 template <typename T>
 double time_mv(eqs_ctx* c, const SpMat<T>& A, const T* x, T* y, int reps);
 void upload(eqs_ctx* c);
-void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i);
+void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const double* yfree, double* out);
 void free_device(eqs_ctx* c);
 template <typename T>
 Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A);
@@ -297,6 +306,7 @@ void launch_gather(hipStream_t s, const double* src, const int32_t* idx, double*
 void launch_scatter(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n);
 void launch_finish_state(eqs_ctx* c, const double* yfree, double t, double* x_user);
 void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out);
+double time_kx(eqs_ctx* c, const double* yfree, double* out, int reps);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);
 void launch_rkc_first(hipStream_t s, double* out, const double* Y0, const double* F0, double a, int64_t n);
 void launch_rkc_combine(hipStream_t s, double* out, const double* Y0, const double* Yjm1, const double* Yjm2,

@@ -22,6 +22,7 @@
 #include <cstring>
 
 #include "eqs_internal.h"
+#include "sell.h"
 
 namespace eqs {
 
@@ -92,24 +93,14 @@ __global__ __launch_bounds__(256) void k_window_prolong(const double* __restrict
 }
 
 // |r - M a|^2 and |r - M b|^2 (partials), M in SELL-64.
-__global__ __launch_bounds__(256) void k_two_residuals(const int32_t* __restrict__ sptr, const int32_t* __restrict__ col,
-                                                        const double* __restrict__ val, int32_t n_rows, int32_t n_slices,
-                                                        const double* __restrict__ r, const double* __restrict__ a,
-                                                        const double* __restrict__ b, double* __restrict__ part,
-                                                        int64_t stride) {
+__global__ __launch_bounds__(256) void k_two_residuals(SellView<double> M, const double* __restrict__ r,
+                                                        const double* __restrict__ a, const double* __restrict__ b,
+                                                        double* __restrict__ part, int64_t stride) {
     double acc[2] = {0.0, 0.0};
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row < n_slices * 64) {
-        const int32_t s = row >> 6, l = row & 63;
-        const int32_t beg = sptr[s], wd = (sptr[s + 1] - beg) >> 6;
-        double ma = 0.0, mb = 0.0;
-        for (int32_t k = 0; k < wd; ++k) {
-            const int32_t j = col[beg + (int64_t)k * 64 + l];
-            const double m = val[beg + (int64_t)k * 64 + l];
-            ma += m * a[j];
-            mb += m * b[j];
-        }
-        if (row < n_rows) {
+    if (row < M.n_slices * 64) {
+        const double ma = sell_row(M, row, a), mb = sell_row(M, row, b);
+        if (row < M.n_rows) {
             const double da = r[row] - ma, db = r[row] - mb;
             acc[0] = da * da;
             acc[1] = db * db;
@@ -426,8 +417,8 @@ int guess_stage(eqs_ctx* c) {
         bool take = true;
         if (g.p.guard) {
             const int64_t nb = (c->M.n_slices * 64 + kBlock - 1) / kBlock;
-            hipLaunchKernelGGL(k_two_residuals, dim3((unsigned)nb), dim3(kBlock), 0, s, c->M.sptr, c->M.col, c->M.val,
-                               c->M.n_rows, c->M.n_slices, c->d_rhs, g.d_x0, c->d_F, c->d_partials, c->max_blocks);
+            hipLaunchKernelGGL(k_two_residuals, dim3((unsigned)nb), dim3(kBlock), 0, s, view(c->M), c->d_rhs, g.d_x0,
+                               c->d_F, c->d_partials, c->max_blocks);
             hipLaunchKernelGGL(k_sum_rows, dim3(2), dim3(kBlock), 0, s, c->d_partials, c->max_blocks, (int)nb,
                                g.d_dots);
             double rr[2];

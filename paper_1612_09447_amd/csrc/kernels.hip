@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "eqs_internal.h"
+#include "sell.h"
 
 namespace eqs {
 
@@ -159,10 +160,13 @@ __device__ __forceinline__ double ipow(double x, int n) {
     return r;
 }
 
-// Fused element pass over blocks of kTetBlock tets (one workgroup each).
+// Fused element pass over blocks of kTetBlock * TPT tets (one workgroup of
+// kTetBlock threads each; thread i handles tets i, i + kTetBlock, ...).
+// 0. The block's packed tet records are loaded first (they do not depend on
+//    the node staging, so their latency overlaps it).
 // 1. The block's distinct nodes are staged in LDS: coordinates, potential
 //    (free: y[id]; Dirichlet: g(t) of its drive) and drive rate g'(t).
-// 2. One thread per tet: with edges e_k = p_k - p_0 and cofactor rows
+// 2. Per tet: with edges e_k = p_k - p_0 and cofactor rows
 //    c_1 = e2 x e3, c_2 = e3 x e1, c_3 = e1 x e2, c_0 = -(c_1 + c_2 + c_3),
 //    det = e1 . c_1, the barycentric gradients are c_a / det, so
 //      w = sum_k c_k (u_k - u_0) = det * grad(phi),  |E| = |w| / |det|,
@@ -170,17 +174,32 @@ __device__ __forceinline__ double ipow(double x, int n) {
 //    kappa(|E|) scales w; RHS mode adds eps * A_e g' (b(t) = -M_ID g'(t),
 //    folded in element by element). Contributions go to an LDS accumulator.
 // 3. One global atomic per block node (RHS mode: free nodes only, negated).
-template <bool RHS>
-__global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, const uint64_t* __restrict__ tpack,
+// Workgroups are mapped so that each XCD (workgroups are dealt to the 8 XCDs
+// round-robin) walks a contiguous range of Morton-ordered blocks: nodes
+// shared by neighbouring blocks then meet in the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t nb) {
+    const int64_t q = nb >> 3, r = nb & 7, x = i & 7;
+    return x * q + (x < r ? x : r) + (i >> 3);
+}
+
+template <bool RHS, int TPT>
+__global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, int64_t n_blocks, const uint64_t* __restrict__ tpack,
                                                    const int32_t* __restrict__ boff,
-                                                   const int32_t* __restrict__ bnodes,
-                                                   const double4* __restrict__ xyz, const MatDev* __restrict__ mats,
+                                                   const int32_t* __restrict__ bnodes, const double* __restrict__ X,
+                                                   const double* __restrict__ Y, const double* __restrict__ Z,
+                                                   const MatDev* __restrict__ mats,
                                                    const double* __restrict__ yfree, int32_t n_free,
                                                    const int32_t* __restrict__ ddrive,
                                                    const DriveDev* __restrict__ drives, double t,
                                                    double* __restrict__ out) {
     extern __shared__ double lds[];
-    const int32_t b = blockIdx.x;
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    uint64_t rec[TPT];
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+        const int64_t e = b * (kTetBlock * TPT) + i * kTetBlock + threadIdx.x;
+        rec[i] = e < n_tets ? tpack[e] : ~0ull;
+    }
     const int32_t off = boff[b];
     const int32_t nn = boff[b + 1] - off;
     double4* P = reinterpret_cast<double4*>(lds);  // x, y, z, potential
@@ -188,7 +207,7 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, const uint64_t
     double* Acc = R + nn;
     for (int k = threadIdx.x; k < nn; k += kTetBlock) {
         const int32_t id = bnodes[off + k];
-        double4 p = xyz[id];
+        double4 p = make_double4(X[id], Y[id], Z[id], 0.0);
         double rate = 0.0;
         if (id < n_free) {
             p.w = yfree[id];
@@ -204,9 +223,10 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, const uint64_t
     }
     __syncthreads();
 
-    const int64_t e = (int64_t)b * kTetBlock + threadIdx.x;
-    if (e < n_tets) {
-        const uint64_t w = tpack[e];
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+        const uint64_t w = rec[i];
+        if (w == ~0ull) continue;
         const MatDev m = mats[(uint32_t)(w & 0xffffu)];
         int l[4];
 #pragma unroll
@@ -262,48 +282,54 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, const uint64_t
     }
 }
 
+template <bool RHS>
+static void launch_kx_t(hipStream_t s, const eqs_ctx* c, const double* yfree, double t, double* out) {
+    dim3 g((unsigned)c->n_blocks), b(kTetBlock);
+    const size_t lds = sizeof(double) * 6 * (size_t)c->max_block_nodes;
+#define EQS_KX(TPT_)                                                                                                  \
+    hipLaunchKernelGGL((k_kx<RHS, TPT_>), g, b, lds, s, c->n_tets, c->n_blocks, c->d_tpack, c->d_boff, c->d_bnodes, \
+                       c->d_cx, c->d_cy, c->d_cz, c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out)
+    switch (c->tet_tpt) {
+        case 1: EQS_KX(1); break;
+        case 2: EQS_KX(2); break;
+        case 4: EQS_KX(4); break;
+        case 8: EQS_KX(8); break;
+        default: fail(EQS_ERR_STATE, "element blocks not built");
+    }
+#undef EQS_KX
+}
+
 void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out) {
     const int64_t nout = rhs_mode ? c->n_free : c->n_nodes;
     launch_fill(s, out, 0.0, nout);
     if (c->n_tets == 0) return;
-    dim3 g((unsigned)c->n_blocks), b(kTetBlock);
-    const size_t lds = sizeof(double) * 6 * (size_t)c->max_block_nodes;
     prof_begin(c, EQS_KCLASS_ELEMENT, s);
-    if (rhs_mode)
-        hipLaunchKernelGGL(k_kx<true>, g, b, lds, s, c->n_tets, c->d_tpack, c->d_boff, c->d_bnodes, c->d_xyz,
-                           c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out);
-    else
-        hipLaunchKernelGGL(k_kx<false>, g, b, lds, s, c->n_tets, c->d_tpack, c->d_boff, c->d_bnodes, c->d_xyz,
-                           c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out);
+    if (rhs_mode) launch_kx_t<true>(s, c, yfree, t, out);
+    else launch_kx_t<false>(s, c, yfree, t, out);
     prof_end(c, EQS_KCLASS_ELEMENT, s);
 }
 
+double time_kx(eqs_ctx* c, const double* yfree, double* out, int reps) {
+    hipEvent_t e0, e1;
+    EQS_HIP(hipEventCreate(&e0));
+    EQS_HIP(hipEventCreate(&e1));
+    std::vector<float> ms;
+    for (int r = 0; r < reps + 2; ++r) {
+        EQS_HIP(hipEventRecord(e0, c->stream));
+        launch_kx_t<true>(c->stream, c, yfree, 0.0, out);
+        EQS_HIP(hipEventRecord(e1, c->stream));
+        EQS_HIP(hipEventSynchronize(e1));
+        float t = 0.0f;
+        EQS_HIP(hipEventElapsedTime(&t, e0, e1));
+        if (r >= 2) ms.push_back(t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::sort(ms.begin(), ms.end());
+    return ms[ms.size() / 2];
+}
+
 // ------------------------------------------------------------- SELL-64
-template <typename T>
-struct SellView {
-    const int32_t* __restrict__ sptr;
-    const int32_t* __restrict__ col;
-    const T* __restrict__ val;
-    int32_t n_rows, n_slices;
-};
-template <typename T>
-static SellView<T> view(const Sell<T>& A) {
-    return SellView<T>{A.sptr, A.col, A.val, A.n_rows, A.n_slices};
-}
-
-// Row `row` of A times x (rows past n_rows but inside the last slice read padding).
-template <typename T, typename TX>
-__device__ __forceinline__ T sell_row(const SellView<T>& A, int32_t row, const TX* __restrict__ x) {
-    const int32_t s = row >> 6, l = row & 63;
-    const int32_t beg = A.sptr[s];
-    const int32_t w = (A.sptr[s + 1] - beg) >> 6;
-    const int32_t* cp = A.col + beg + l;
-    const T* vp = A.val + beg + l;
-    T acc = T(0);
-    for (int32_t k = 0; k < w; ++k) acc += vp[(int64_t)k * 64] * (T)x[cp[(int64_t)k * 64]];
-    return acc;
-}
-
 template <typename T>
 static unsigned sell_grid(const Sell<T>& A) {
     return (unsigned)(((int64_t)A.n_slices * kSlice + kBlock - 1) / kBlock);
@@ -342,16 +368,7 @@ __global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> A, const T* _
     if (stop && *stop) return;
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= A.n_slices * 64) return;
-    const int32_t s = row >> 6, l = row & 63;
-    const int32_t beg = A.sptr[s];
-    const int32_t w = (A.sptr[s + 1] - beg) >> 6;
-    const int32_t* cp = A.col + beg + l;
-    const T* vp = A.val + beg + l;
-    T acc = T(0);
-    for (int32_t k = 0; k < w; ++k) {
-        const int32_t j = cp[(int64_t)k * 64];
-        acc += vp[(int64_t)k * 64] * (dinv[j] * (T)b[j]);
-    }
+    const T acc = sell_accum(A, row, [&](int32_t j) { return dinv[j] * (T)b[j]; });
     if (row < A.n_rows) {
         const T bi = (T)b[row];
         x[row] = omega * dinv[row] * bi;

@@ -1,0 +1,54 @@
+// SELL-64 rows on the device: slices of 64 rows (one wavefront), each stored
+// column-major with the slice's longest row, so lane l of a wavefront reads
+// entry k of row 64 s + l at sptr[s] + 64 k + l (unit stride across lanes).
+// Column ids are either absolute (col, 32-bit) or, when every stored entry
+// lies within 32767 rows of the diagonal, 16-bit offsets from the row (d16):
+// 6 instead of 8 bytes per FP32 entry, 10 instead of 12 per FP64 entry.
+// Padding entries carry value 0 and an in-range column.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "eqs_internal.h"
+
+namespace eqs {
+
+template <typename T>
+struct SellView {
+    const int32_t* __restrict__ sptr;
+    const int32_t* __restrict__ col;
+    const int16_t* __restrict__ d16;
+    const T* __restrict__ val;
+    int32_t n_rows, n_slices;
+};
+
+template <typename T>
+static inline SellView<T> view(const Sell<T>& A) {
+    return SellView<T>{A.sptr, A.col, A.d16, A.val, A.n_rows, A.n_slices};
+}
+
+// sum_k a_{row,k} f(col_k) over the stored entries of `row` (rows past n_rows
+// but inside the last slice see padding only).
+template <typename T, typename F>
+__device__ __forceinline__ T sell_accum(const SellView<T>& A, int32_t row, F f) {
+    const int32_t s = row >> 6, l = row & 63;
+    const int32_t beg = A.sptr[s];
+    const int32_t w = (A.sptr[s + 1] - beg) >> 6;
+    const T* vp = A.val + beg + l;
+    T acc = T(0);
+    if (A.d16) {
+        const int16_t* dp = A.d16 + beg + l;
+        for (int32_t k = 0; k < w; ++k) acc += vp[(int64_t)k * 64] * f(row + (int32_t)dp[(int64_t)k * 64]);
+    } else {
+        const int32_t* cp = A.col + beg + l;
+        for (int32_t k = 0; k < w; ++k) acc += vp[(int64_t)k * 64] * f(cp[(int64_t)k * 64]);
+    }
+    return acc;
+}
+
+template <typename T, typename TX>
+__device__ __forceinline__ T sell_row(const SellView<T>& A, int32_t row, const TX* __restrict__ x) {
+    return sell_accum(A, row, [&](int32_t j) { return (T)x[j]; });
+}
+
+}  // namespace eqs

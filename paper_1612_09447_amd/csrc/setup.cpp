@@ -543,8 +543,38 @@ Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A) {
             for (int32_t k = len; k < w; ++k) col[sptr[s] + (int64_t)k * kSlice + l] = pad_col;
         }
     }
+    // 16-bit offsets for square operators whose stored columns all lie within
+    // 32767 rows of their row (padding of rows past n_rows points at the last
+    // row, a valid column of a square matrix)
+    bool fits = c->index16 && A.n_rows == A.n_cols;
+    for (int32_t s = 0; s < S.n_slices && fits; ++s) {
+        const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
+        for (int32_t l = 0; l < kSlice && fits; ++l) {
+            const int32_t r = s * kSlice + l;
+            if (r >= A.n_rows) continue;
+            for (int32_t k = 0; k < w; ++k) {
+                const int64_t d = (int64_t)col[sptr[s] + (int64_t)k * kSlice + l] - r;
+                if (d < -32767 || d > 32767) { fits = false; break; }
+            }
+        }
+    }
     S.sptr = upload_vec(c, sptr);
-    S.col = upload_vec(c, col);
+    if (fits) {
+        std::vector<int16_t> d16(S.stored, 0);
+        for (int32_t s = 0; s < S.n_slices; ++s) {
+            const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
+            for (int32_t l = 0; l < kSlice; ++l) {
+                const int32_t r = s * kSlice + l;
+                for (int32_t k = 0; k < w; ++k) {
+                    const int64_t at = sptr[s] + (int64_t)k * kSlice + l;
+                    d16[at] = (int16_t)(r < A.n_rows ? col[at] - r : (A.n_rows - 1) - r);
+                }
+            }
+        }
+        S.d16 = upload_vec(c, d16);
+    } else {
+        S.col = upload_vec(c, col);
+    }
     S.val = upload_vec(c, val);
     return S;
 }
@@ -585,6 +615,7 @@ template <typename T>
 static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
     dev_free(c, S.sell.sptr);
     dev_free(c, S.sell.col);
+    dev_free(c, S.sell.d16);
     dev_free(c, S.sell.val);
     dev_free(c, S.rowptr);
     dev_free(c, S.col);
@@ -603,7 +634,8 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
         S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
         S.fmt = FMT_SELL;
         S.sell = to_sell<T>(c, A);
-        c->tune_log += std::string(what) + ": sell64 (finest level)\n";
+        c->tune_log += std::string(what) + ": sell64 (finest level), " +
+                       (S.sell.d16 ? "16-bit column offsets\n" : "32-bit columns\n");
         return S;
     }
     if (!c->autotune || A.n_rows == 0) return to_spmat<T>(c, A);
@@ -700,10 +732,17 @@ static uint64_t morton3(const double* p, const double* lo, const double* inv_ext
     return key;
 }
 
-// Element blocks for the fused element pass: tets sorted by the Morton key of
-// their centroid, cut into blocks of kTetBlock; per block the sorted distinct
-// internal node ids, and per tet 4 x 12-bit block-local vertex ids | material.
-void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i) {
+// Element blocks for the fused element pass: tets sorted by instance, then by
+// the Morton code of their centroid, cut into blocks of kTetBlock * tpt tets;
+// per block the sorted distinct internal node ids and, per tet, a 64-bit
+// record: 16-bit material, then the four 12-bit block-local vertex ids.
+struct ElementBlocks {
+    std::vector<uint64_t> pack;
+    std::vector<int32_t> boff, bnodes;
+    int32_t max_nodes = 0;
+};
+
+static std::vector<int32_t> morton_tet_order(const eqs_ctx* c) {
     const int64_t T = c->n_tets;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t i = 0; i < c->n_nodes; ++i)
@@ -729,39 +768,96 @@ void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i) {
                          if (tinst[x.second] != tinst[y.second]) return tinst[x.second] < tinst[y.second];
                          return x.first < y.first;
                      });
-    const int64_t nb = (T + kTetBlock - 1) / kTetBlock;
-    std::vector<uint64_t> pack(T);
-    std::vector<int32_t> boff(nb + 1, 0), bnodes;
-    bnodes.reserve((size_t)T);
+    std::vector<int32_t> order(T);
+    for (int64_t k = 0; k < T; ++k) order[k] = key[k].second;
+    return order;
+}
+
+static ElementBlocks element_blocks(const eqs_ctx* c, const std::vector<int32_t>& u2i,
+                                    const std::vector<int32_t>& order, int tpt) {
+    const int64_t T = c->n_tets, per = (int64_t)kTetBlock * tpt;
+    const int64_t nb = (T + per - 1) / per;
+    ElementBlocks eb;
+    eb.pack.resize(T);
+    eb.boff.assign(nb + 1, 0);
+    eb.bnodes.reserve((size_t)T);
     std::vector<int32_t> ids;
-    int32_t maxn = 0;
     for (int64_t b = 0; b < nb; ++b) {
-        const int64_t e0 = b * kTetBlock, e1 = std::min<int64_t>(T, e0 + kTetBlock);
+        const int64_t e0 = b * per, e1 = std::min<int64_t>(T, e0 + per);
         ids.clear();
         for (int64_t k = e0; k < e1; ++k)
-            for (int a = 0; a < 4; ++a) ids.push_back(u2i[c->tets[4 * (int64_t)key[k].second + a]]);
+            for (int a = 0; a < 4; ++a) ids.push_back(u2i[c->tets[4 * (int64_t)order[k] + a]]);
         std::sort(ids.begin(), ids.end());
         ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
-        if (ids.size() > 4095) fail(EQS_ERR_INVALID_ARG, "element block with more than 4095 nodes");
-        maxn = std::max<int32_t>(maxn, (int32_t)ids.size());
+        if (ids.size() > (size_t)kMaxBlockNodes) {  // local ids / LDS: the caller tries a smaller block
+            eb.max_nodes = INT32_MAX;
+            return eb;
+        }
+        eb.max_nodes = std::max<int32_t>(eb.max_nodes, (int32_t)ids.size());
         for (int64_t k = e0; k < e1; ++k) {
-            const int32_t e = key[k].second;
+            const int32_t e = order[k];
             uint64_t w = (uint64_t)(uint16_t)c->tet_mat[e];
             for (int a = 0; a < 4; ++a) {
                 const int32_t loc = (int32_t)(std::lower_bound(ids.begin(), ids.end(), u2i[c->tets[4 * (int64_t)e + a]]) - ids.begin());
                 w |= (uint64_t)loc << (16 + 12 * a);
             }
-            pack[k] = w;
+            eb.pack[k] = w;
         }
-        bnodes.insert(bnodes.end(), ids.begin(), ids.end());
-        if (bnodes.size() > (size_t)INT32_MAX) fail(EQS_ERR_INVALID_ARG, "too many block nodes");
-        boff[b + 1] = (int32_t)bnodes.size();
+        eb.bnodes.insert(eb.bnodes.end(), ids.begin(), ids.end());
+        if (eb.bnodes.size() > (size_t)INT32_MAX) fail(EQS_ERR_INVALID_ARG, "too many block nodes");
+        eb.boff[b + 1] = (int32_t)eb.bnodes.size();
     }
-    c->n_blocks = nb;
-    c->max_block_nodes = maxn;
-    c->d_tpack = upload_vec(c, pack);
-    c->d_bnodes = upload_vec(c, bnodes);
-    c->d_boff = upload_vec(c, boff);
+    return eb;
+}
+
+static void install_blocks(eqs_ctx* c, const ElementBlocks& eb, int tpt) {
+    if (c->d_tpack) { dev_free(c, c->d_tpack); dev_free(c, c->d_bnodes); dev_free(c, c->d_boff); }
+    c->n_blocks = (int64_t)eb.boff.size() - 1;
+    c->max_block_nodes = eb.max_nodes;
+    c->n_block_nodes = (int64_t)eb.bnodes.size();
+    c->tet_tpt = tpt;
+    c->d_tpack = upload_vec(c, eb.pack);
+    c->d_bnodes = upload_vec(c, eb.bnodes);
+    c->d_boff = upload_vec(c, eb.boff);
+}
+
+// Blocks of 256 tets per workgroup trade LDS reuse (each block re-reads the
+// nodes it shares with its neighbours) against parallelism; with autotuning
+// on, every block size that fits the 12-bit local ids is timed on the RHS
+// pass and the fastest kept (else 4 tets per thread).
+void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const double* yfree, double* out) {
+    const std::vector<int32_t> order = morton_tet_order(c);
+    const int fixed = 4;
+    if (!c->autotune || c->n_tets < 16 * (int64_t)kTetBlock * kMaxTetsPerThread) {
+        for (int tpt = fixed; tpt >= 1; tpt /= 2) {
+            ElementBlocks eb = element_blocks(c, u2i, order, tpt);
+            if (eb.max_nodes <= kMaxBlockNodes) {
+                install_blocks(c, eb, tpt);
+                c->tune_log += "element: " + std::to_string(kTetBlock * tpt) + " tets per block\n";
+                return;
+            }
+        }
+        fail(EQS_ERR_INVALID_ARG, "element block of 256 tets with more than " + std::to_string(kMaxBlockNodes) +
+                                      " distinct nodes");
+    }
+    int best_tpt = 0;
+    double best = 1e300;
+    std::string line = "element:";
+    for (int tpt = 1; tpt <= kMaxTetsPerThread; tpt *= 2) {
+        ElementBlocks eb = element_blocks(c, u2i, order, tpt);
+        if (eb.max_nodes > kMaxBlockNodes) break;
+        install_blocks(c, eb, tpt);
+        const double ms = time_kx(c, yfree, out, 5);
+        char buf[64];
+        std::snprintf(buf, sizeof buf, " %d:%.1fus", kTetBlock * tpt, 1e3 * ms);
+        line += buf;
+        if (ms < best) { best = ms; best_tpt = tpt; }
+    }
+    if (best_tpt == 0)
+        fail(EQS_ERR_INVALID_ARG, "element block of 256 tets with more than " + std::to_string(kMaxBlockNodes) +
+                                      " distinct nodes");
+    if (best_tpt != c->tet_tpt) install_blocks(c, element_blocks(c, u2i, order, best_tpt), best_tpt);
+    c->tune_log += line + " -> " + std::to_string(kTetBlock * best_tpt) + " tets per block\n";
 }
 
 void upload(eqs_ctx* c) {
@@ -769,11 +865,12 @@ void upload(eqs_ctx* c) {
     std::vector<int32_t> u2i(N);
     for (int64_t i = 0; i < N; ++i) u2i[c->int_to_user[i]] = (int32_t)i;
 
-    build_element_blocks(c, u2i);
-    std::vector<double4> xyz(N);
+    std::vector<double> px(N), py(N), pz(N);
     for (int64_t i = 0; i < N; ++i) {
         const double* p = &c->xyz[3 * (int64_t)c->int_to_user[i]];
-        xyz[i] = make_double4(p[0], p[1], p[2], 0.0);
+        px[i] = p[0];
+        py[i] = p[1];
+        pz[i] = p[2];
     }
     std::vector<MatDev> md(c->mats.size());
     for (size_t m = 0; m < c->mats.size(); ++m) {
@@ -791,7 +888,9 @@ void upload(eqs_ctx* c) {
         for (size_t k = 0; k < c->dir_nodes.size(); ++k) drive_of[c->dir_nodes[k]] = c->dir_drive[k];
         for (int64_t k = 0; k < c->n_dir; ++k) dd[k] = drive_of[c->int_to_user[NF + k]];
     }
-    c->d_xyz = upload_vec(c, xyz);
+    c->d_cx = upload_vec(c, px);
+    c->d_cy = upload_vec(c, py);
+    c->d_cz = upload_vec(c, pz);
     c->d_mats = upload_vec(c, md);
     c->d_ddrive = upload_vec(c, dd);
     {
@@ -806,6 +905,7 @@ void upload(eqs_ctx* c) {
     Csr<double> M = assemble_M_free(c);
     c->nnz_M = M.nnz();
     c->M = to_sell<double>(c, M);
+    c->tune_log += std::string("M: sell64, ") + (c->M.d16 ? "16-bit column offsets\n" : "32-bit columns\n");
     AmgHost ah = build_sa_amg(M, c->amg);
     if (c->amg.precision == EQS_PREC_FP32) upload_hierarchy<float>(c, ah, c->h32, nullptr);
     else upload_hierarchy<double>(c, ah, c->h64, nullptr);
@@ -834,6 +934,8 @@ void upload(eqs_ctx* c) {
         }
         c->d_blk_inst = upload_vec(c, bi);
     }
+    launch_fill(c->stream, c->d_Y0, 0.0, NF);
+    build_element_blocks(c, u2i, c->d_Y0, c->d_rhs);
     EQS_HIP(hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming));
     EQS_HIP(hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming));
     c->have_Flast = false;
@@ -852,8 +954,8 @@ void free_device(eqs_ctx* c) {
     c->M = Sell<double>{};
     c->h64.lv.clear();
     c->h32.lv.clear();
-    c->d_tpack = nullptr; c->d_bnodes = nullptr; c->d_boff = nullptr; c->n_blocks = 0; c->max_block_nodes = 0;
-    c->d_xyz = nullptr; c->d_mats = nullptr;
+    c->d_tpack = nullptr; c->d_bnodes = nullptr; c->d_boff = nullptr; c->n_blocks = 0; c->max_block_nodes = 0; c->n_block_nodes = 0;
+    c->d_cx = c->d_cy = c->d_cz = nullptr; c->d_mats = nullptr; c->tet_tpt = 0;
     c->d_ddrive = nullptr; c->d_int_to_user = nullptr; c->d_drives = nullptr;
     c->d_r = c->d_z = c->d_p = c->d_q = nullptr;
     c->d_Y0 = c->d_Ya = c->d_Yb = c->d_F0 = c->d_F = nullptr;
