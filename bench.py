@@ -38,17 +38,19 @@ def log(*a):
 
 
 def element_bytes(info):
-    # per tet: its packed record (4 x 12-bit block-local vertex ids + 16-bit
-    # material, 8 B); per node: xyz (24 B), potential read (8 B), output write
-    # (8 B) -- each array touched once (block node lists and re-reads of nodes
-    # shared between blocks are overhead, not counted)
-    return info["n_tets"] * 8 + info["n_nodes"] * (24 + 8 + 8)
+    # algorithmic bytes of one element pass: per tet its connectivity (4 x 4 B)
+    # and material id (4 B); per node its coordinates (24 B), potential (8 B)
+    # and result (8 B), each array touched once. The library's packed tet
+    # records need 8 B instead of 20; re-reads of nodes shared between element
+    # blocks and the block node lists are overhead, not counted.
+    return info["n_tets"] * 20 + info["n_nodes"] * (24 + 8 + 8)
 
 
 def spmv_bytes(info, nnz):
-    # CG product q = M z + beta q, p = z + beta p on the free DOF:
-    # values (8 B) + column ids (4 B) per nonzero, slice offsets, z read,
-    # p and q read + written
+    # CG product q = M z + beta q, p = z + beta p on the free DOF: value (8 B)
+    # and column id (4 B) per stored nonzero, slice offsets, z read, p and q
+    # read and written. With 16-bit column offsets the kernel reads 10 B per
+    # nonzero, not 12.
     n = info["n_free"]
     return 12 * nnz + 4 * (n // 64 + 1) + 8 * n + 32 * n
 
@@ -292,19 +294,21 @@ def main():
         "element": element_bytes(info),
         "spmv_M": spmv_bytes(info, info["nnz_M"]),
     }
-    dominant = max(per_class_bytes, key=lambda k: prof[k]["total_ms"])
-    avg_s = prof[dominant]["avg_ms"] * 1e-3
-    achieved = per_class_bytes[dominant] / avg_s / 1e9
-    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dominant],
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "frac_of_copy": round(achieved / copy["GB/s"], 4),
-                "bytes_per_launch": per_class_bytes[dominant], "avg_launch_us": round(avg_s * 1e6, 2),
-                "timing": f"HIP events around every launch on the context stream, {args.prof_steps} instrumented "
-                          f"steps following the timed ones"}
-    breakdown = {k: {"launches": v["launches"], "avg_us": round(v["avg_ms"] * 1e3, 2),
-                     "share_of_instrumented": round(v["total_ms"] * 1e-3 / r["prof_elapsed"], 4)}
-                 for k, v in prof.items()}
+    roofline, breakdown = None, None
+    if prof:
+        dominant = max(per_class_bytes, key=lambda k: prof[k]["total_ms"])
+        avg_s = prof[dominant]["avg_ms"] * 1e-3
+        achieved = per_class_bytes[dominant] / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dominant],
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac_of_copy": round(achieved / copy["GB/s"], 4),
+                    "bytes_per_launch": per_class_bytes[dominant], "avg_launch_us": round(avg_s * 1e6, 2),
+                    "timing": f"HIP events around every launch on the context stream, {args.prof_steps} "
+                              f"instrumented steps following the timed ones"}
+        breakdown = {k: {"launches": v["launches"], "avg_us": round(v["avg_ms"] * 1e3, 2),
+                         "share_of_instrumented": round(v["total_ms"] * 1e-3 / r["prof_elapsed"], 4)}
+                     for k, v in prof.items()}
 
     plain = None
     if args.plain_steps > 0 and main_prec != EQS_PREC_FP64:

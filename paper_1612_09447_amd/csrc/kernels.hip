@@ -76,17 +76,99 @@ __device__ __forceinline__ void store_pair(double* __restrict__ part, double v, 
     }
 }
 
-// Sum of instance i's partials by one wavefront, in a fixed order; valid in all lanes.
-__device__ __forceinline__ double inst_sum(const double* __restrict__ part, const InstMap& m, int32_t i) {
+// Blocks b0..b1 hold instance i's rows r0..r1-1. Every block after b0 starts
+// inside instance i, so its first partial is i's; block b0 starts inside i
+// only when r0 is a multiple of 256, else i's share is its second partial.
+__device__ __forceinline__ void inst_blocks(const InstMap& m, int32_t i, int32_t& b0, int32_t& b1, int32_t& head) {
     const int32_t r0 = m.row_off[i], r1 = m.row_off[i + 1];
-    double v = 0.0;
-    if (r1 > r0) {
-        const int32_t b0 = r0 >> 8, b1 = (r1 - 1) >> 8;
-        for (int32_t b = b0 + (int32_t)(threadIdx.x & 63); b <= b1; b += 64)
-            v += (m.blk_inst[b] == i) ? part[2 * b] : part[2 * b + 1];
+    if (r1 <= r0) {
+        b0 = 0;
+        b1 = -1;
+        head = 0;
+        return;
     }
+    b0 = r0 >> 8;
+    b1 = (r1 - 1) >> 8;
+    head = (r0 & 255) ? 1 : 0;
+}
+
+// Sum over blocks lo..hi (inclusive) of the first partial, by the 64 lanes of
+// one wavefront (the head block b0 is added by the caller); valid in all lanes.
+__device__ __forceinline__ double wave_range_sum(const double* __restrict__ part, int32_t lo, int32_t hi) {
+    const int lane = threadIdx.x & 63;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int32_t b = lo + lane;
+    for (; b + 192 <= hi; b += 256) {
+        v0 += part[2 * (int64_t)b];
+        v1 += part[2 * (int64_t)(b + 64)];
+        v2 += part[2 * (int64_t)(b + 128)];
+        v3 += part[2 * (int64_t)(b + 192)];
+    }
+    for (; b <= hi; b += 64) v0 += part[2 * (int64_t)b];
+    double v = (v0 + v1) + (v2 + v3);
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+constexpr int kFinWaves = kFin / 64;
+
+// Per-instance sums of NP pair-partial arrays, in a fixed order (the result
+// does not depend on timing). With at most kFinWaves instances every instance
+// gets kFinWaves / n_inst wavefronts, each summing an equal share of its
+// blocks; otherwise wavefronts take whole instances in turn. body(i, sums)
+// runs once per instance, in one thread. Must be reached by the whole block.
+template <int NP, typename F>
+__device__ __forceinline__ void for_each_instance_sum(const double* const (&parts)[NP], const InstMap& m, F body) {
+    __shared__ double sh[NP][kFinWaves];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (m.n_inst <= kFinWaves) {
+        const int wpi = kFinWaves / m.n_inst;
+        const int i = wave / wpi, sub = wave - i * wpi;
+        double v[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) v[p] = 0.0;
+        if (i < m.n_inst) {
+            int32_t b0, b1, head;
+            inst_blocks(m, i, b0, b1, head);
+            if (b1 >= b0) {
+                const int32_t first = b0 + 1, n = b1 - b0;  // blocks first..b1 read their first partial
+                const int32_t lo = first + (int32_t)(((int64_t)n * sub) / wpi);
+                const int32_t hi = first + (int32_t)(((int64_t)n * (sub + 1)) / wpi) - 1;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    v[p] = wave_range_sum(parts[p], lo, hi);
+                    if (sub == 0) v[p] += parts[p][2 * (int64_t)b0 + head];
+                }
+            }
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) sh[p][wave] = v[p];
+        __syncthreads();
+        if ((int32_t)threadIdx.x < m.n_inst) {
+            const int32_t k = threadIdx.x;
+            double sums[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                double t = 0.0;
+                for (int w = k * wpi; w < (k + 1) * wpi; ++w) t += sh[p][w];
+                sums[p] = t;
+            }
+            body(k, sums);
+        }
+    } else {
+        for (int32_t i = wave; i < m.n_inst; i += kFinWaves) {
+            int32_t b0, b1, head;
+            inst_blocks(m, i, b0, b1, head);
+            double sums[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                sums[p] = 0.0;
+                if (b1 >= b0) sums[p] = wave_range_sum(parts[p], b0 + 1, b1) + parts[p][2 * (int64_t)b0 + head];
+            }
+            if (lane == 0) body(i, sums);
+        }
+    }
 }
 
 // ------------------------------------------------------------- simple ops
@@ -433,8 +515,21 @@ __device__ __forceinline__ T group_sum(T v) {
 // Row sum of A (lanes of one group split the row), with x_j given by f(j).
 template <int L, typename T, typename F>
 __device__ __forceinline__ T csr_row(const CsrView<T>& A, int32_t row, int lane, F f) {
+    // each lane takes entries lane, lane + L, ... of the row, four at a time:
+    // positions past the row's end re-read its last entry and are dropped by a
+    // select, so the loads carry no branch; the lane's sum runs in entry order
     T acc = T(0);
-    for (int32_t k = A.rp[row] + lane; k < A.rp[row + 1]; k += L) acc += A.val[k] * f(A.col[k]);
+    const int32_t end = A.rp[row + 1];
+    for (int32_t k = A.rp[row] + lane; k < end; k += 4 * L) {
+        T t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t kk = min(k + u * L, end - 1);
+            t[u] = A.val[kk] * f(A.col[kk]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += (k + u * L < end) ? t[u] : T(0);
+    }
     return group_sum<L>(acc);
 }
 
@@ -754,26 +849,49 @@ __global__ void k_zero_rhs_rows(InstMap m, double* __restrict__ x, int64_t n, co
     if (i < n && scal[min(i >= bound ? lo + 1 : lo, m.n_inst - 1)].bb == 0.0) x[i] = 0.0;
 }
 
-// Summary over the instances, by thread 0, mirrored with all scalars to the host.
+// Summary over the instances, mirrored with all scalars to the host; every
+// thread of the block takes part (counts and maxima do not depend on order).
+// A NaN relative residual is reported as +inf.
 __device__ void summarise(const PcgScalars* __restrict__ s, int32_t n, PcgSummary* __restrict__ sum,
                           PcgSummary* __restrict__ host_sum, PcgScalars* __restrict__ host) {
-    PcgSummary v{};
-    v.all_done = 1;
-    for (int32_t i = 0; i < n; ++i) {
-        const PcgScalars& x = s[i];
-        if (!x.done) {
-            v.all_done = 0;
-            v.n_active++;
-        }
-        if (x.status == EQS_ERR_BREAKDOWN) v.n_breakdown++;
-        if (x.status == EQS_ERR_NOT_CONVERGED) v.n_notconv++;
-        if (x.bb == 0.0) v.n_zero_rhs++;
-        v.max_it = max(v.max_it, x.it);
-        v.max_relres = fmax(v.max_relres, x.relres);
-        host[i] = x;
+    __shared__ int32_t cnt[5];  // active, breakdown, not converged, zero rhs, max it
+    __shared__ unsigned long long max_rel;
+    if (threadIdx.x == 0) {
+        cnt[0] = cnt[1] = cnt[2] = cnt[3] = cnt[4] = 0;
+        max_rel = 0ull;
     }
-    *sum = v;
-    *host_sum = v;
+    __syncthreads();
+    int32_t act = 0, brk = 0, nc = 0, zr = 0, mit = 0;
+    double mr = 0.0;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const PcgScalars x = s[i];
+        host[i] = x;
+        act += x.done ? 0 : 1;
+        brk += x.status == EQS_ERR_BREAKDOWN;
+        nc += x.status == EQS_ERR_NOT_CONVERGED;
+        zr += x.bb == 0.0;
+        mit = max(mit, x.it);
+        mr = fmax(mr, isnan(x.relres) ? INFINITY : x.relres);
+    }
+    if (act) atomicAdd(&cnt[0], act);
+    if (brk) atomicAdd(&cnt[1], brk);
+    if (nc) atomicAdd(&cnt[2], nc);
+    if (zr) atomicAdd(&cnt[3], zr);
+    if (mit) atomicMax(&cnt[4], mit);
+    if (mr > 0.0) atomicMax(&max_rel, (unsigned long long)__double_as_longlong(mr));  // order of non-negative doubles
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        PcgSummary v{};
+        v.all_done = cnt[0] == 0;
+        v.n_active = cnt[0];
+        v.n_breakdown = cnt[1];
+        v.n_notconv = cnt[2];
+        v.n_zero_rhs = cnt[3];
+        v.max_it = cnt[4];
+        v.max_relres = __longlong_as_double((long long)max_rel);
+        *sum = v;
+        *host_sum = v;
+    }
 }
 
 // mode 0: start of a solve (it = 0); mode 1: restart from the true residual
@@ -784,40 +902,38 @@ __global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, 
                                                      int32_t flexible, int32_t mode, PcgSummary* __restrict__ sum,
                                                      PcgSummary* __restrict__ host_sum,
                                                      PcgScalars* __restrict__ host) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int32_t i = wave; i < m.n_inst; i += kFin / 64) {
-        const double rr = inst_sum(prr, m, i);
-        const double bb = inst_sum(pbb, m, i);
-        if (lane != 0) continue;
-        PcgScalars v = s[i];
+    const double* parts[2] = {prr, pbb};
+    for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
+        const double rr = v[0], bb = v[1];
+        PcgScalars x = s[i];
         if (mode == 0) {
-            v = PcgScalars{};
-            v.maxit = maxit;
-            v.flexible = flexible;
-            v.tol2 = rtol * rtol * bb;
-        } else if (v.status == EQS_ERR_BREAKDOWN) {
-            continue;
+            x = PcgScalars{};
+            x.maxit = maxit;
+            x.flexible = flexible;
+            x.tol2 = rtol * rtol * bb;
+        } else if (x.status == EQS_ERR_BREAKDOWN) {
+            return;
         }
-        v.bb = bb;
-        v.rr = rr;
-        v.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-        v.fresh = 1;
-        v.beta = 0.0;
-        v.status = EQS_OK;
-        v.done = 0;
-        if (bb == 0.0 || rr <= v.tol2) {
-            v.done = 1;
+        x.bb = bb;
+        x.rr = rr;
+        x.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+        x.fresh = 1;
+        x.beta = 0.0;
+        x.status = EQS_OK;
+        x.done = 0;
+        if (bb == 0.0 || rr <= x.tol2) {
+            x.done = 1;
         } else if (!isfinite(rr) || !isfinite(bb)) {
-            v.done = 1;
-            v.status = EQS_ERR_BREAKDOWN;
-        } else if (v.it >= v.maxit) {
-            v.done = 1;
-            v.status = EQS_ERR_NOT_CONVERGED;
+            x.done = 1;
+            x.status = EQS_ERR_BREAKDOWN;
+        } else if (x.it >= x.maxit) {
+            x.done = 1;
+            x.status = EQS_ERR_NOT_CONVERGED;
         }
-        s[i] = v;
-    }
+        s[i] = x;
+    });
     __syncthreads();
-    if (threadIdx.x == 0) summarise(s, m.n_inst, sum, host_sum, host);
+    summarise(s, m.n_inst, sum, host_sum, host);
 }
 
 // beta from r.z (Polak-Ribiere with r.z_old when flexible).
@@ -825,68 +941,64 @@ __global__ __launch_bounds__(kFin) void k_fin_beta(PcgScalars* __restrict__ s, I
                                                     const double* __restrict__ prz, const double* __restrict__ przold,
                                                     const int32_t* __restrict__ stop) {
     if (*stop) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int32_t i = wave; i < m.n_inst; i += kFin / 64) {
-        if (s[i].done) continue;
-        const double rz = inst_sum(prz, m, i);
-        const double rzo = inst_sum(przold, m, i);
-        if (lane != 0) continue;
-        PcgScalars& v = s[i];
+    const double* parts[2] = {prz, przold};
+    for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
+        PcgScalars& x = s[i];
+        if (x.done) return;
+        const double rz = v[0], rzo = v[1];
         if (!(rz > 0.0) || !isfinite(rz)) {
-            v.done = 1;
-            v.status = EQS_ERR_BREAKDOWN;
-            continue;
+            x.done = 1;
+            x.status = EQS_ERR_BREAKDOWN;
+            return;
         }
-        if (v.fresh) v.beta = 0.0;
-        else v.beta = v.flexible ? (rz - rzo) / v.rho : rz / v.rho;
-        v.rho = rz;
-    }
+        if (x.fresh) x.beta = 0.0;
+        else x.beta = x.flexible ? (rz - rzo) / x.rho : rz / x.rho;
+        x.rho = rz;
+    });
 }
 
 __global__ __launch_bounds__(kFin) void k_fin_alpha(PcgScalars* __restrict__ s, InstMap m,
                                                      const double* __restrict__ ppq, const int32_t* __restrict__ stop) {
     if (*stop) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int32_t i = wave; i < m.n_inst; i += kFin / 64) {
-        if (s[i].done) continue;
-        const double pq = inst_sum(ppq, m, i);
-        if (lane != 0) continue;
-        PcgScalars& v = s[i];
+    const double* parts[1] = {ppq};
+    for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
+        PcgScalars& x = s[i];
+        if (x.done) return;
+        const double pq = v[0];
         if (!(pq > 0.0) || !isfinite(pq)) {
-            v.done = 1;
-            v.status = EQS_ERR_BREAKDOWN;
-            continue;
+            x.done = 1;
+            x.status = EQS_ERR_BREAKDOWN;
+            return;
         }
-        v.alpha = v.rho / pq;
-        v.fresh = 0;
-    }
+        x.alpha = x.rho / pq;
+        x.fresh = 0;
+    });
 }
 
 __global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, InstMap m,
                                                     const double* __restrict__ prr, PcgSummary* __restrict__ sum,
                                                     PcgSummary* __restrict__ host_sum, PcgScalars* __restrict__ host) {
     if (sum->all_done) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int32_t i = wave; i < m.n_inst; i += kFin / 64) {
-        if (s[i].done) continue;
-        const double rr = inst_sum(prr, m, i);
-        if (lane != 0) continue;
-        PcgScalars& v = s[i];
-        v.rr = rr;
-        v.relres = sqrt(rr / v.bb);
-        v.it += 1;
-        if (rr <= v.tol2) {
-            v.done = 1;
+    const double* parts[1] = {prr};
+    for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
+        PcgScalars& x = s[i];
+        if (x.done) return;
+        const double rr = v[0];
+        x.rr = rr;
+        x.relres = sqrt(rr / x.bb);
+        x.it += 1;
+        if (rr <= x.tol2) {
+            x.done = 1;
         } else if (!isfinite(rr)) {
-            v.done = 1;
-            v.status = EQS_ERR_BREAKDOWN;
-        } else if (v.it >= v.maxit) {
-            v.done = 1;
-            v.status = EQS_ERR_NOT_CONVERGED;
+            x.done = 1;
+            x.status = EQS_ERR_BREAKDOWN;
+        } else if (x.it >= x.maxit) {
+            x.done = 1;
+            x.status = EQS_ERR_NOT_CONVERGED;
         }
-    }
+    });
     __syncthreads();
-    if (threadIdx.x == 0) summarise(s, m.n_inst, sum, host_sum, host);
+    summarise(s, m.n_inst, sum, host_sum, host);
 }
 
 static double* part(eqs_ctx* c, int q) { return c->d_partials + (int64_t)q * 2 * c->max_blocks; }

@@ -28,20 +28,42 @@ static inline SellView<T> view(const Sell<T>& A) {
 }
 
 // sum_k a_{row,k} f(col_k) over the stored entries of `row` (rows past n_rows
-// but inside the last slice see padding only).
+// but inside the last slice see padding only). Entries are taken in groups of
+// 8 whose loads carry no branch: positions past the row's width re-read its
+// last entry (a cache hit) and their terms are dropped by a select, so all
+// loads and gathers of a group are in flight together. The sum runs in k order.
 template <typename T, typename F>
 __device__ __forceinline__ T sell_accum(const SellView<T>& A, int32_t row, F f) {
     const int32_t s = row >> 6, l = row & 63;
     const int32_t beg = A.sptr[s];
-    const int32_t w = (A.sptr[s + 1] - beg) >> 6;
+    const int32_t w = (A.sptr[s + 1] - beg) >> 6;  // uniform across the wavefront
     const T* vp = A.val + beg + l;
     T acc = T(0);
-    if (A.d16) {
-        const int16_t* dp = A.d16 + beg + l;
-        for (int32_t k = 0; k < w; ++k) acc += vp[(int64_t)k * 64] * f(row + (int32_t)dp[(int64_t)k * 64]);
-    } else {
-        const int32_t* cp = A.col + beg + l;
-        for (int32_t k = 0; k < w; ++k) acc += vp[(int64_t)k * 64] * f(cp[(int64_t)k * 64]);
+    for (int32_t k0 = 0; k0 < w; k0 += 8) {
+        T v[8];
+        int32_t j[8];
+        if (A.d16) {
+            const int16_t* dp = A.d16 + beg + l;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t kk = (int64_t)min(k0 + u, w - 1) * 64;
+                v[u] = vp[kk];
+                j[u] = row + (int32_t)dp[kk];
+            }
+        } else {
+            const int32_t* cp = A.col + beg + l;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t kk = (int64_t)min(k0 + u, w - 1) * 64;
+                v[u] = vp[kk];
+                j[u] = cp[kk];
+            }
+        }
+        T t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = v[u] * f(j[u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (k0 + u < w) ? t[u] : T(0);
     }
     return acc;
 }
