@@ -161,24 +161,23 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         ctx.profile_enable(())
     learned = {}
     if learned_steps > 0:
-        # the reference leg: the plain start vector over the same window length
-        el, it, _, _ = timed_steps(ctx, x, n, learned_steps, tau, s, rtol, "previous")
-        n += learned_steps
-        learned["previous"] = {"stages_per_s": round(learned_steps * s / el, 2),
-                               "mean_cg_iters_per_stage": round(sum(it) / len(it), 2)}
-        for kind in ("zero", "galerkin", "mlp"):
+        # every start vector runs the same steps from the same state: warm-up
+        # steps (filling the snapshot window and the replay buffer), then the
+        # timed ones
+        x0 = x.clone()
+        for kind in ("previous", "zero", "galerkin", "mlp"):
+            x.copy_(x0)
             if kind == "mlp":
                 ctx.set_guess("mlp", init=eqsgen.mlp_init(4))
             else:
                 ctx.set_guess(kind)
-            wu = 1 if kind == "zero" else learned_warmup
-            timed_steps(ctx, x, n, wu, tau, s, rtol, f"{kind} warm-up")
-            n += wu
-            el, it, u, fb = timed_steps(ctx, x, n, learned_steps, tau, s, rtol, kind)
-            n += learned_steps
+            timed_steps(ctx, x, n, learned_warmup, tau, s, rtol, f"{kind} warm-up")
+            el, it, u, fb = timed_steps(ctx, x, n + learned_warmup, learned_steps, tau, s, rtol, kind)
             learned[kind] = {"stages_per_s": round(learned_steps * s / el, 2),
                              "mean_cg_iters_per_stage": round(sum(it) / len(it), 2),
-                             "guess_used": u, "guard_fallbacks": fb, "warmup_steps": wu}
+                             "guess_used": u, "guard_fallbacks": fb}
+        learned["window"] = {"first_step": n + learned_warmup, "steps": learned_steps,
+                             "warmup_steps": learned_warmup}
         ctx.set_guess("previous")
     xn = x.cpu().numpy()
     ctx.close()

@@ -167,6 +167,8 @@ struct GuessState {
     bool have_pending = false;
     float pend_x[32];
     double pend_scale = 1.0;
+    double pend_a[16];                // V^T F_{j-1} of the pending pair (its target is the change)
+    double sol_scale = 0.0;           // |V^T F| / |V^T r| of the first pair, then fixed
     std::vector<int> pend_slot;
     std::vector<double> pend_B;
     int pend_m = 0;
@@ -335,7 +337,7 @@ void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B);
 void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B);
 float mlp_last_loss(eqs_mlp* n);
 void mlp_get(eqs_mlp* n, float* params, float* grad);
-void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, double* alpha);
+void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, const double* bias, double* alpha);
 
 // start vectors (guess.hip)
 void guess_configure(eqs_ctx* c, const eqs_guess_params& p);

@@ -198,6 +198,7 @@ void guess_reset(eqs_ctx* c) {
     g.oldest = 0;
     g.have_prev = false;
     g.have_pending = false;
+    g.sol_scale = 0.0;
     g.rcount = 0;
     g.rhead = 0;
     g.counter = 0;
@@ -314,13 +315,13 @@ int guess_stage(eqs_ctx* c) {
     }
     const double uu = dots[2 * kMaxWin], uv = dots[2 * kMaxWin + 1], uw = dots[2 * kMaxWin + 2];
 
-    // (1) training pair of the previous stage: target V_{j-1}^T F_{j-1}
+    // (1) training pair of the previous stage: target V_{j-1}^T (F_{j-1} - F_{j-2})
     if (g.have_pending && g.p.kind == EQS_GUESS_MLP) {
         std::vector<double> tcoef(16, 0.0);
         for (int k = 0; k < g.pend_m; ++k) {
             double a = 0.0;
             for (int i = 0; i < (int)g.pend_slot.size(); ++i) a += g.pend_B[(size_t)i * g.pend_m + k] * Su[g.pend_slot[i]];
-            tcoef[k] = a / g.pend_scale;
+            tcoef[k] = (a - g.pend_a[k]) / g.pend_scale;
         }
         const int slot = g.rhead;
         for (int q = 0; q < 32; ++q) g.rx[(size_t)slot * 32 + q] = g.pend_x[q];
@@ -349,7 +350,10 @@ int guess_stage(eqs_ctx* c) {
     g.G[e * kMaxWin + e] = uu;
     g.H[e * kMaxWin + e] = uw;
     launch_copy(s, g.d_S + (int64_t)e * NF, c->d_F, NF);
-    // r_j against the new window, kept for the next insertion
+    // r_{j-1} against the new window (for the change of the RHS) and r_j,
+    // kept for the next insertion
+    double rprev[kMaxWin];
+    for (int b = 0; b < kMaxWin; ++b) rprev[b] = (b == e) ? uw : g.rdots[b];
     for (int b = 0; b < kMaxWin; ++b) g.rdots[b] = (b == e) ? uv : (b < n_old ? Sv[b] : 0.0);
 
     if (g.count < 2) return 0;
@@ -387,27 +391,42 @@ int guess_stage(eqs_ctx* c) {
             EQS_HIP(hipStreamSynchronize(s));
         }
     } else if (g.p.kind == EQS_GUESS_MLP) {
-        const double sa = norm(a), sb = norm(bh);
-        float x[32];
-        for (int k = 0; k < 16; ++k) {
-            x[k] = (k < B.m && sa > 0) ? (float)(a[k] / sa) : 0.0f;
-            x[16 + k] = (k < B.m && sb > 0) ? (float)(bh[k] / sb) : 0.0f;
-        }
-        // pending pair for this stage: target V_j^T F_j / |V_j^T F_{j-1}| once F_j is known
-        std::memcpy(g.pend_x, x, sizeof x);
-        g.pend_scale = sa > 0 ? sa : 1.0;
-        g.pend_slot = B.slot;
-        g.pend_B = B.B;
-        g.pend_m = B.m;
-        g.have_pending = true;
-        if (g.rcount >= g.p.warmup && sa > 0) {
-            // alpha_slot = sum_k B[i][k] * sa * y_k  ->  P[slot][k]; slots past count stay 0
-            double P[16 * 16];
-            std::fill(P, P + 256, 0.0);
-            for (int i = 0; i < (int)B.slot.size(); ++i)
-                for (int k = 0; k < B.m; ++k) P[B.slot[i] * 16 + k] = B.B[(size_t)i * B.m + k] * sa;
-            mlp_forward_coeffs(g.net, x, P, g.d_alpha);
-            have = true;
+        // The network predicts the change of the solution from F_{j-1} within
+        // span(V), c ~ V^T (F_j - F_{j-1}), from the direction of the state
+        // (V^T F_{j-1}) and of the change of the RHS (V^T (r_j - r_{j-1})).
+        // Inputs are unit vectors; the output is scaled by sigma |V^T dr|,
+        // sigma = |V^T F| / |V^T r| fixed at the first pair, so that targets
+        // are O(1); the start vector is x0 = F_{j-1} + V c.
+        const std::vector<double> bp = project(B, rprev);  // V^T r_{j-1}
+        std::vector<double> d(B.m);
+        for (int k = 0; k < B.m; ++k) d[k] = bh[k] - bp[k];
+        const double sa = norm(a), sd = norm(d);
+        if (g.sol_scale == 0.0 && sa > 0 && norm(bp) > 0) g.sol_scale = sa / norm(bp);
+        const double scale = g.sol_scale * sd;
+        if (sa > 0 && scale > 0 && std::isfinite(scale)) {
+            float x[32];
+            for (int k = 0; k < 16; ++k) {
+                x[k] = k < B.m ? (float)(a[k] / sa) : 0.0f;
+                x[16 + k] = k < B.m ? (float)(d[k] / sd) : 0.0f;
+            }
+            std::memcpy(g.pend_x, x, sizeof x);
+            g.pend_scale = scale;
+            for (int k = 0; k < 16; ++k) g.pend_a[k] = k < B.m ? a[k] : 0.0;
+            g.pend_slot = B.slot;
+            g.pend_B = B.B;
+            g.pend_m = B.m;
+            g.have_pending = true;
+            if (g.rcount >= g.p.warmup) {
+                // alpha_slot = [slot == e] + sum_k B[i][k] * scale * y_k; slots past count stay 0
+                double P[16 * 16], bias[16];
+                std::fill(P, P + 256, 0.0);
+                std::fill(bias, bias + 16, 0.0);
+                bias[e] = 1.0;
+                for (int i = 0; i < (int)B.slot.size(); ++i)
+                    for (int k = 0; k < B.m; ++k) P[B.slot[i] * 16 + k] = B.B[(size_t)i * B.m + k] * scale;
+                mlp_forward_coeffs(g.net, x, P, bias, g.d_alpha);
+                have = true;
+            }
         }
     }
 

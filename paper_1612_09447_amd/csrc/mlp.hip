@@ -193,6 +193,7 @@ __global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ x, const 
 struct MlpIn {
     float x[kIn];
     double P[kOut * kOut];
+    double bias[kOut];
 };
 
 template <bool BF16>
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(64) void k_mlp_alpha(MlpIn in, const float* __restr
     }
     __syncthreads();
     if (tid < kOut) {
-        double acc = 0.0;
+        double acc = in.bias[tid];
         for (int k = 0; k < kOut; ++k) acc += in.P[tid * kOut + k] * (double)yv[k];
         alpha[tid] = acc;
     }
@@ -314,10 +315,11 @@ void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B) {
 
 void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B) { mlp_launch(n, true, x, t, nullptr, B); }
 
-void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, double* alpha) {
+void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, const double* bias, double* alpha) {
     MlpIn in;
     std::memcpy(in.x, x, sizeof in.x);
     std::memcpy(in.P, P, sizeof in.P);
+    std::memcpy(in.bias, bias, sizeof in.bias);
     if (n->bf16)
         hipLaunchKernelGGL(k_mlp_alpha<true>, dim3(1), dim3(64), 0, n->stream, in, n->master, n->wq, alpha);
     else
