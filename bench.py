@@ -80,6 +80,38 @@ def copy_probe(mib=512, reps=20):
             "GB/s": round(nbytes / times[len(times) // 2] / 1e9, 1)}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_hbm_traffic.txt")
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1612_09447_amd", "csrc", f) for f in ("kernels.hip", "sell.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_class):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary, or None when there is none or the kernel sources have changed
+    since the counters were taken."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    sha, val = None, None
+    for ln in lines:
+        f = ln.split()
+        if len(f) >= 2 and f[0] == "source_sha256":
+            sha = f[1]
+        if len(f) >= 3 and f[0] == "traffic" and f[1] == kernel_class:
+            val = int(f[2])
+    return val if sha == kernel_source_hash() else None
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -147,6 +179,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         n += 1
     elapsed, iters, used, fallbacks = timed_steps(ctx, x, n, steps, tau, s, rtol, f"{precision}/{guess}")
     n += steps
+    x_timed = x.cpu().numpy()  # state after warmup + timed steps (compared across precisions)
     prof, prof_elapsed = {}, 0.0
     if prof_steps > 0:
         ctx.profile_enable(ALL_CLASSES)
@@ -179,10 +212,9 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         learned["window"] = {"first_step": n + learned_warmup, "steps": learned_steps,
                              "warmup_steps": learned_warmup}
         ctx.set_guess("previous")
-    xn = x.cpu().numpy()
     ctx.close()
     return dict(elapsed=elapsed, stages=steps * s, iters=iters, info=info, prof=prof, prof_elapsed=prof_elapsed,
-                prof_stages=prof_steps * s, setup_s=setup_s, x=xn, used=used, fallbacks=fallbacks, learned=learned)
+                prof_stages=prof_steps * s, setup_s=setup_s, x=x_timed, used=used, fallbacks=fallbacks, learned=learned)
 
 
 def run_batched(steps, warmup):
@@ -253,7 +285,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
     ap.add_argument("--n", type=int, default=None, help="override the mesh resolution (testing)")
-    ap.add_argument("--plain-steps", type=int, default=10, help="timed steps of the plain FP64 path (0: skip)")
+    ap.add_argument("--plain-steps", type=int, default=-1,
+                    help="timed steps of the plain FP64 path over the same steps (-1: as --steps, 0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prof-steps", type=int, default=3, help="instrumented steps after the timed ones")
     ap.add_argument("--guess", default="previous", choices=["previous", "zero", "galerkin", "mlp"])
@@ -300,21 +333,36 @@ def main():
         achieved = per_class_bytes[dominant] / avg_s / 1e9
         roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dominant],
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dominant),
                     "frac_of_copy": round(achieved / copy["GB/s"], 4),
                     "bytes_per_launch": per_class_bytes[dominant], "avg_launch_us": round(avg_s * 1e6, 2),
-                    "timing": f"HIP events around every launch on the context stream, {args.prof_steps} "
-                              f"instrumented steps following the timed ones"}
+                    "timing": f"start/stop events of every launch (hipExtLaunchKernelGGL) on the context stream, "
+                              f"{args.prof_steps} instrumented steps following the timed ones"}
+        rooflines = {}
+        for k, nbytes in per_class_bytes.items():
+            a = nbytes / (prof[k]["avg_ms"] * 1e-3) / 1e9
+            rooflines[k] = {"kernel": KERNEL_NAMES[k], "achieved": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4),
+                            "avg_launch_us": round(prof[k]["avg_ms"] * 1e3, 2), "bytes_per_launch": nbytes,
+                            "traffic": measured_traffic(k)}
+        roofline["per_kernel"] = rooflines
         breakdown = {k: {"launches": v["launches"], "avg_us": round(v["avg_ms"] * 1e3, 2),
                          "share_of_instrumented": round(v["total_ms"] * 1e-3 / r["prof_elapsed"], 4)}
                      for k, v in prof.items()}
 
     plain = None
-    if args.plain_steps > 0 and main_prec != EQS_PREC_FP64:
-        p = run_gpu(case, EQS_PREC_FP64, args.plain_steps, args.warmup, case.rtol)
+    plain_steps = args.steps if args.plain_steps < 0 else args.plain_steps
+    if plain_steps > 0 and main_prec != EQS_PREC_FP64:
+        p = run_gpu(case, EQS_PREC_FP64, plain_steps, args.warmup, case.rtol)
         plain = {"stages_per_s": round(p["stages"] / p["elapsed"], 2),
                  "mean_cg_iters_per_stage": round(sum(p["iters"]) / len(p["iters"]), 2),
-                 "steps": args.plain_steps}
+                 "steps": plain_steps,
+                 "rel_diff_of_final_state_vs_fp32_form": None}
+        if plain_steps == args.steps:
+            import numpy as np
+
+            d = np.linalg.norm(r["x"] - p["x"]) / max(np.linalg.norm(p["x"]), 1e-300)
+            plain["rel_diff_of_final_state_vs_fp32_form"] = float(f"{d:.3e}")
+            plain["fp32_form_speedup"] = round(stages_per_s / plain["stages_per_s"], 3)
 
     batched = run_batched(args.c3_steps, 1) if args.c3_steps > 0 else None
 

@@ -245,11 +245,12 @@ int eqs_batch_instance_stats(const eqs_batch *b, int64_t *iters, double *relres)
  *                       solutions: V (V^T M V)^{-1} V^T r (the reduced matrix
  *                       comes for free because M s_k = r_k for every stored
  *                       solution s_k)
- *   EQS_GUESS_MLP       the coefficients on the same basis come from the
- *                       start-vector network (eqs_mlp below), fed with the
- *                       POD coefficients of the latest solution and of the
- *                       stage right-hand side; the network is trained online
- *                       on the GPU from (features, V^T F_j) pairs of the run.
+ *   EQS_GUESS_MLP       F_{j-1} + V c, where the start-vector network
+ *                       (eqs_mlp below) predicts the change c of the stage
+ *                       solution on the same basis from the directions of
+ *                       V^T F_{j-1} and of V^T (r_j - r_{j-1}); it is trained
+ *                       online on the GPU from the run's own pairs, with
+ *                       target V^T (F_j - F_{j-1}) once F_j is known.
  * For GALERKIN and MLP a guard compares |r - M x0| of the candidate with that
  * of the previous solution and keeps the better one; CG to rtol always follows,
  * so the start vector never changes the result beyond the solve tolerance. */

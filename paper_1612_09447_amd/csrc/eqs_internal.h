@@ -63,7 +63,7 @@ struct Sell {
     int64_t stored = 0;         // padded entries
     int32_t* sptr = nullptr;    // [n_slices + 1]
     int32_t* col = nullptr;     // [stored] absolute column ids, or
-    int16_t* d16 = nullptr;     // [stored] column - row (when every entry is within 32767 rows)
+    int16_t* d16 = nullptr;     // [stored] column - offset_base(row) when every entry allows
     T* val = nullptr;           // [stored]
 };
 
@@ -72,6 +72,13 @@ struct Sell {
 // `lanes` lanes per row (a power of two <= 64) whose partial sums are combined
 // by cross-lane shuffles, for long rows (coarse AMG operators).
 enum { FMT_SELL = 0, FMT_CSR = 1 };
+// Column ids stored as 16-bit offsets are relative to this base: the row
+// itself for a square operator, row * n_cols / n_rows for a rectangular one
+// (transfer operators between AMG levels, whose columns follow the rows).
+__host__ __device__ inline int32_t offset_base(int32_t row, int32_t n_rows, int32_t n_cols) {
+    return n_rows == n_cols ? row : (int32_t)(((int64_t)row * n_cols) / n_rows);
+}
+
 template <typename T>
 struct SpMat {
     int fmt = FMT_SELL;
@@ -79,7 +86,8 @@ struct SpMat {
     Sell<T> sell;
     int32_t n_rows = 0, n_cols = 0;
     int32_t* rowptr = nullptr;  // CSR
-    int32_t* col = nullptr;
+    int32_t* col = nullptr;     // absolute column ids, or
+    int16_t* d16 = nullptr;     // offsets from offset_base(row) when every entry allows
     T* val = nullptr;
     int64_t nnz = 0;
 };
@@ -133,7 +141,8 @@ struct Level {
     int32_t n = 0;
     SpMat<T> A, P, R;  // P, R unused on the coarsest level
     T* dinv = nullptr;
-    double omega = 0;  // damped Jacobi weight
+    T* sval = nullptr;  // values of A omega D^{-1} in A's storage order (pre-smoothing); not on the coarsest level
+    double omega = 0;   // damped Jacobi weight
     T *b = nullptr, *x = nullptr, *xs = nullptr, *res = nullptr;
     T* dense_inv = nullptr;  // coarsest level only: n x n, column-major
 };
@@ -310,10 +319,11 @@ void launch_finish_state(eqs_ctx* c, const double* yfree, double t, double* x_us
 void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out);
 double time_kx(eqs_ctx* c, const double* yfree, double* out, int reps);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);
-void launch_rkc_first(hipStream_t s, double* out, const double* Y0, const double* F0, double a, int64_t n);
-void launch_rkc_combine(hipStream_t s, double* out, const double* Y0, const double* Yjm1, const double* Yjm2,
-                        const double* Fjm1, const double* F0, double c0, double c1, double c2, double c3,
-                        double c4, int64_t n);
+void launch_rkc_first(eqs_ctx* c, hipStream_t s, double* out, const double* Y0, const double* F0, double a,
+                      int64_t n);
+void launch_rkc_combine(eqs_ctx* c, hipStream_t s, double* out, const double* Y0, const double* Yjm1,
+                        const double* Yjm2, const double* Fjm1, const double* F0, double c0, double c1, double c2,
+                        double c3, double c4, int64_t n);
 void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double* y);
 
 // PCG pieces (all scalar state on the device, one PcgScalars per instance)
@@ -350,6 +360,8 @@ double guess_last_loss(eqs_ctx* c);
 // per-kernel timing (profile.cpp)
 void prof_begin(eqs_ctx* c, int cls, hipStream_t s);
 void prof_end(eqs_ctx* c, int cls, hipStream_t s);
+// next start/stop pair of a profiled single-kernel class (false: not profiled)
+bool prof_pair(eqs_ctx* c, int cls, hipEvent_t* e0, hipEvent_t* e1);
 void prof_release(eqs_ctx* c);
 
 // drivers (solver.cpp)

@@ -10,11 +10,12 @@
 // Per stage j (after the element pass wrote r_j) one fused pass reads the
 // window S (before F_{j-1} joins it), u = F_{j-1}, v = r_j and w = r_{j-1}
 // and returns S^T u, S^T v, u.u, u.v, u.w. The host then
-//   * completes the training pair of stage j-1 (target V_{j-1}^T F_{j-1}),
+//   * completes the training pair of stage j-1 (target V_{j-1}^T (F_{j-1} - F_{j-2})),
 //   * moves F_{j-1} into the window (G and H gain a row),
-//   * forms V from G's eigenvectors, the features (V^T F_{j-1}, V^T r_j),
-//     and the coefficients of the start vector: by eq. (5) (GALERKIN) or by
-//     the network (MLP, inference on the GPU), x0 = S alpha (one pass),
+//   * forms V from G's eigenvectors and the coefficients of the start vector:
+//     by eq. (5) (GALERKIN), or F_{j-1} plus the change the network predicts
+//     from the directions of V^T F_{j-1} and V^T (r_j - r_{j-1}) (MLP,
+//     inference on the GPU); x0 = S alpha (one pass),
 //   * lets a guard compare |r_j - M x0| with |r_j - M F_{j-1}|.
 // The network then takes one Adam step on a minibatch of stored pairs.
 #include <algorithm>

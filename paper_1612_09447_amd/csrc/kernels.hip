@@ -13,10 +13,24 @@
 //  * RKC stage combination (the paper's ref. [9]).
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "eqs_internal.h"
 #include "sell.h"
 
 namespace eqs {
+
+// Launch `kernel`; when kernel class `cls` is being profiled the launch carries
+// its own start/stop events, so the class time is the kernel's execution.
+#define EQS_LAUNCH_TIMED(ctx, cls, kernel, grid, block, shmem, stream, ...)                                    \
+    do {                                                                                                      \
+        hipEvent_t e0_, e1_;                                                                                  \
+        if (prof_pair((ctx), (cls), &e0_, &e1_))                                                              \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, e0_, e1_, 0, __VA_ARGS__);              \
+        else                                                                                                  \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                              \
+    } while (0)
+
 
 // ----------------------------------------------------------- reductions
 // Sum over a 256-thread block in a fixed order (wavefront tree, then the four
@@ -303,6 +317,9 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, int64_t n_bloc
         R[k] = rate;
         Acc[k] = 0.0;
     }
+    // node lists are sorted and Dirichlet nodes come last in the internal
+    // order, so the block touches one iff its last node is one
+    const bool has_dir = RHS && nn > 0 && bnodes[off + nn - 1] >= n_free;
     __syncthreads();
 
 #pragma unroll
@@ -337,7 +354,7 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, int64_t n_bloc
         wx *= kappa;
         wy *= kappa;
         wz *= kappa;
-        if (RHS) {
+        if (RHS && has_dir) {
             const double r0 = R[l[0]], r1 = R[l[1]], r2 = R[l[2]], r3 = R[l[3]];
             if (r0 != 0.0 || r1 != 0.0 || r2 != 0.0 || r3 != 0.0) {
                 const double q1 = r1 - r0, q2 = r2 - r0, q3 = r3 - r0;
@@ -365,12 +382,13 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, int64_t n_bloc
 }
 
 template <bool RHS>
-static void launch_kx_t(hipStream_t s, const eqs_ctx* c, const double* yfree, double t, double* out) {
+static void launch_kx_t(hipStream_t s, eqs_ctx* c, const double* yfree, double t, double* out) {
     dim3 g((unsigned)c->n_blocks), b(kTetBlock);
     const size_t lds = sizeof(double) * 6 * (size_t)c->max_block_nodes;
-#define EQS_KX(TPT_)                                                                                                  \
-    hipLaunchKernelGGL((k_kx<RHS, TPT_>), g, b, lds, s, c->n_tets, c->n_blocks, c->d_tpack, c->d_boff, c->d_bnodes, \
-                       c->d_cx, c->d_cy, c->d_cz, c->d_mats, yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out)
+#define EQS_KX(TPT_)                                                                                            \
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx<RHS, TPT_>), g, b, lds, s, c->n_tets, c->n_blocks, c->d_tpack, \
+                     c->d_boff, c->d_bnodes, c->d_cx, c->d_cy, c->d_cz, c->d_mats, yfree, (int32_t)c->n_free,   \
+                     c->d_ddrive, c->d_drives, t, out)
     switch (c->tet_tpt) {
         case 1: EQS_KX(1); break;
         case 2: EQS_KX(2); break;
@@ -385,10 +403,8 @@ void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, do
     const int64_t nout = rhs_mode ? c->n_free : c->n_nodes;
     launch_fill(s, out, 0.0, nout);
     if (c->n_tets == 0) return;
-    prof_begin(c, EQS_KCLASS_ELEMENT, s);
     if (rhs_mode) launch_kx_t<true>(s, c, yfree, t, out);
     else launch_kx_t<false>(s, c, yfree, t, out);
-    prof_end(c, EQS_KCLASS_ELEMENT, s);
 }
 
 double time_kx(eqs_ctx* c, const double* yfree, double* out, int reps) {
@@ -442,19 +458,21 @@ void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double
 
 // ------------------------------------------------------------ V-cycle
 // Pre-smoothing from a zero guess fused with the residual:
-//   x = omega D^{-1} b,   res = b - A x = b - A (omega D^{-1} b).
+//   x = omega D^{-1} b,   res = b - A x = b - (A omega D^{-1}) b,
+// the last product with the stored pre-smoothing values a_ij omega / a_jj,
+// so rows gather b only.
 template <typename T, typename TB>
-__global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> A, const T* __restrict__ dinv, T omega,
+__global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> As, const T* __restrict__ dinv, T omega,
                                                         const TB* __restrict__ b, T* __restrict__ x,
                                                         T* __restrict__ res, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= A.n_slices * 64) return;
-    const T acc = sell_accum(A, row, [&](int32_t j) { return dinv[j] * (T)b[j]; });
-    if (row < A.n_rows) {
+    if (row >= As.n_slices * 64) return;
+    const T acc = sell_row(As, row, b);
+    if (row < As.n_rows) {
         const T bi = (T)b[row];
         x[row] = omega * dinv[row] * bi;
-        res[row] = bi - omega * acc;
+        res[row] = bi - acc;
     }
 }
 
@@ -497,12 +515,27 @@ template <typename T>
 struct CsrView {
     const int32_t* __restrict__ rp;
     const int32_t* __restrict__ col;
+    const int16_t* __restrict__ d16;  // offsets from offset_base(row) instead of col when set
     const T* __restrict__ val;
-    int32_t n_rows;
+    int32_t n_rows, n_cols;
 };
 template <typename T>
 static CsrView<T> cview(const SpMat<T>& A) {
-    return CsrView<T>{A.rowptr, A.col, A.val, A.n_rows};
+    return CsrView<T>{A.rowptr, A.col, A.d16, A.val, A.n_rows, A.n_cols};
+}
+
+// Views of a level's operator with the pre-smoothing values a_ij omega / a_jj.
+template <typename T>
+static SellView<T> sview(const Level<T>& lv) {
+    SellView<T> v = view(lv.A.sell);
+    v.val = lv.sval;
+    return v;
+}
+template <typename T>
+static CsrView<T> scview(const Level<T>& lv) {
+    CsrView<T> v = cview(lv.A);
+    v.val = lv.sval;
+    return v;
 }
 
 template <int L, typename T>
@@ -520,12 +553,14 @@ __device__ __forceinline__ T csr_row(const CsrView<T>& A, int32_t row, int lane,
     // select, so the loads carry no branch; the lane's sum runs in entry order
     T acc = T(0);
     const int32_t end = A.rp[row + 1];
+    const int32_t base = offset_base(row, A.n_rows, A.n_cols);
     for (int32_t k = A.rp[row] + lane; k < end; k += 4 * L) {
         T t[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int32_t kk = min(k + u * L, end - 1);
-            t[u] = A.val[kk] * f(A.col[kk]);
+            const int32_t j = A.d16 ? base + (int32_t)A.d16[kk] : A.col[kk];
+            t[u] = A.val[kk] * f(j);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc += (k + u * L < end) ? t[u] : T(0);
@@ -546,19 +581,19 @@ __global__ __launch_bounds__(256) void k_csr_mv(CsrView<T> A, const T* __restric
 }
 
 template <int L, typename T, typename TB>
-__global__ __launch_bounds__(256) void k_csr_presmooth_res(CsrView<T> A, const T* __restrict__ dinv, T omega,
+__global__ __launch_bounds__(256) void k_csr_presmooth_res(CsrView<T> As, const T* __restrict__ dinv, T omega,
                                                             const TB* __restrict__ b, T* __restrict__ x,
                                                             T* __restrict__ res, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
-    if (row >= A.n_rows) return;
-    const T acc = csr_row<L>(A, row, lane, [&](int32_t j) { return dinv[j] * (T)b[j]; });
+    if (row >= As.n_rows) return;
+    const T acc = csr_row<L>(As, row, lane, [&](int32_t j) { return (T)b[j]; });
     if (lane == 0) {
         const T bi = (T)b[row];
         x[row] = omega * dinv[row] * bi;
-        res[row] = bi - omega * acc;
+        res[row] = bi - acc;
     }
 }
 
@@ -603,11 +638,11 @@ static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int ac
 template <typename T, typename TB>
 static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, const int32_t* stop) {
     if (lv.A.fmt == FMT_SELL) {
-        hipLaunchKernelGGL((k_presmooth_res<T, TB>), dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s, view(lv.A.sell),
+        hipLaunchKernelGGL((k_presmooth_res<T, TB>), dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s, sview(lv),
                            (const T*)lv.dinv, (T)lv.omega, b, lv.x, lv.res, stop);
     } else {
         EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_presmooth_res<L_, T, TB>), dim3(csr_grid(lv.A)),
-                                                        dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
+                                                        dim3(kBlock), 0, s, scview(lv), (const T*)lv.dinv,
                                                         (T)lv.omega, b, lv.x, lv.res, stop));
     }
 }
@@ -717,9 +752,9 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
     for (int l = 0; l < L - 1; ++l) {
         Level<T>& lv = h.lv[l];
         if (l == 0) {
-            prof_begin(c, EQS_KCLASS_PRESMOOTH0, s);
-            launch_presmooth<T, double>(s, lv, r, stop);
-            prof_end(c, EQS_KCLASS_PRESMOOTH0, s);
+            // the finest operator is always SELL-64 (see tuned_spmat)
+            EQS_LAUNCH_TIMED(c, EQS_KCLASS_PRESMOOTH0, (k_presmooth_res<T, double>), dim3(sell_grid(lv.A.sell)), b, 0,
+                             s, sview(lv), (const T*)lv.dinv, (T)lv.omega, r, lv.x, lv.res, stop);
         } else {
             launch_presmooth<T, T>(s, lv, (const T*)lv.b, stop);
         }
@@ -739,16 +774,14 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
             launch_postsmooth<T>(s, lv, (const T*)lv.b, (const T*)lv.x, lv.xs, stop);
         } else {
             // the finest operator is always SELL-64 (see tuned_spmat)
-            prof_begin(c, EQS_KCLASS_POSTSMOOTH0, s);
             if (part_rz)
-                hipLaunchKernelGGL((k_postsmooth<T, double, double, true>), dim3(sell_grid(lv.A.sell)), b, 0, s,
-                                   view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, r, (const T*)lv.x, z, inst_map(c),
-                                   part_rz, part_rzold, stop);
+                EQS_LAUNCH_TIMED(c, EQS_KCLASS_POSTSMOOTH0, (k_postsmooth<T, double, double, true>),
+                                 dim3(sell_grid(lv.A.sell)), b, 0, s, view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega,
+                                 r, (const T*)lv.x, z, inst_map(c), part_rz, part_rzold, stop);
             else
-                hipLaunchKernelGGL((k_postsmooth<T, double, double, false>), dim3(sell_grid(lv.A.sell)), b, 0, s,
-                                   view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, r, (const T*)lv.x, z, InstMap{},
-                                   nullptr, nullptr, stop);
-            prof_end(c, EQS_KCLASS_POSTSMOOTH0, s);
+                EQS_LAUNCH_TIMED(c, EQS_KCLASS_POSTSMOOTH0, (k_postsmooth<T, double, double, false>),
+                                 dim3(sell_grid(lv.A.sell)), b, 0, s, view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega,
+                                 r, (const T*)lv.x, z, InstMap{}, nullptr, nullptr, stop);
         }
     }
 }
@@ -1036,15 +1069,11 @@ void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int 
     else vcycle<double>(s, c, c->h64, c->d_r, c->d_z, part(c, 0), part(c, 1), stop);
     prof_end(c, EQS_KCLASS_VCYCLE, s);
     hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), stop);
-    prof_begin(c, EQS_KCLASS_SPMV_M, s);
-    hipLaunchKernelGGL(k_pcg_spmv, dim3(nbM), dim3(kBlock), 0, s, view(c->M), inst_map(c), c->d_z, c->d_p, c->d_q,
-                       part(c, 2), c->d_scal, stop);
-    prof_end(c, EQS_KCLASS_SPMV_M, s);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_SPMV_M, k_pcg_spmv, dim3(nbM), dim3(kBlock), 0, s, view(c->M), inst_map(c),
+                     c->d_z, c->d_p, c->d_q, part(c, 2), c->d_scal, stop);
     hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 2), stop);
-    prof_begin(c, EQS_KCLASS_CG_UPDATE, s);
-    hipLaunchKernelGGL(k_pcg_update, dim3(nbV), dim3(kBlock), 0, s, inst_map(c), x, c->d_r, c->d_p, c->d_q,
-                       c->n_free, part(c, 3), c->d_scal, stop);
-    prof_end(c, EQS_KCLASS_CG_UPDATE, s);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_CG_UPDATE, k_pcg_update, dim3(nbV), dim3(kBlock), 0, s, inst_map(c), x, c->d_r,
+                     c->d_p, c->d_q, c->n_free, part(c, 3), c->d_scal, stop);
     hipLaunchKernelGGL(k_fin_conv, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 3), c->d_sum,
                        c->d_hsum, c->d_hscal);
 }
@@ -1064,15 +1093,17 @@ __global__ void k_rkc_combine(double* out, const double* __restrict__ Y0, const 
     if (i < n) out[i] = c0 * Y0[i] + c1 * Yjm1[i] + c2 * Yjm2[i] + c3 * Fjm1[i] + c4 * F0[i];
 }
 
-void launch_rkc_first(hipStream_t s, double* out, const double* Y0, const double* F0, double a, int64_t n) {
-    hipLaunchKernelGGL(k_rkc_first, dim3(grid_for(n)), dim3(kBlock), 0, s, out, Y0, F0, a, n);
+void launch_rkc_first(eqs_ctx* c, hipStream_t s, double* out, const double* Y0, const double* F0, double a,
+                      int64_t n) {
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_RKC_COMBINE, k_rkc_first, dim3(grid_for(n)), dim3(kBlock), 0, s, out, Y0, F0, a,
+                     n);
 }
 
-void launch_rkc_combine(hipStream_t s, double* out, const double* Y0, const double* Yjm1, const double* Yjm2,
-                        const double* Fjm1, const double* F0, double c0, double c1, double c2, double c3,
-                        double c4, int64_t n) {
-    hipLaunchKernelGGL(k_rkc_combine, dim3(grid_for(n)), dim3(kBlock), 0, s, out, Y0, Yjm1, Yjm2, Fjm1, F0, c0, c1,
-                       c2, c3, c4, n);
+void launch_rkc_combine(eqs_ctx* c, hipStream_t s, double* out, const double* Y0, const double* Yjm1,
+                        const double* Yjm2, const double* Fjm1, const double* F0, double c0, double c1, double c2,
+                        double c3, double c4, int64_t n) {
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_RKC_COMBINE, k_rkc_combine, dim3(grid_for(n)), dim3(kBlock), 0, s, out, Y0, Yjm1,
+                     Yjm2, Fjm1, F0, c0, c1, c2, c3, c4, n);
 }
 
 }  // namespace eqs

@@ -1,4 +1,7 @@
-// Per-kernel-class timing with HIP events recorded on the launching stream.
+// Per-kernel-class timing with HIP events. Classes of one kernel take the
+// start/stop events of the launch itself (hipExtLaunchKernelGGL: the
+// kernel's own execution, as a kernel trace reports it); the V-cycle class
+// brackets its launches with events recorded on the stream.
 #include "eqs_internal.h"
 
 namespace eqs {
@@ -13,6 +16,21 @@ void prof_begin(eqs_ctx* c, int cls, hipStream_t s) {
         ev.push_back(e);
     }
     EQS_HIP(hipEventRecord(ev[2 * c->prof_used[cls]], s));
+}
+
+bool prof_pair(eqs_ctx* c, int cls, hipEvent_t* e0, hipEvent_t* e1) {
+    if (!(c->prof_mask & (1u << cls))) return false;
+    std::vector<hipEvent_t>& ev = c->prof_ev[cls];
+    const size_t need = 2 * (size_t)(c->prof_used[cls] + 1);
+    while (ev.size() < need) {
+        hipEvent_t e;
+        EQS_HIP(hipEventCreate(&e));
+        ev.push_back(e);
+    }
+    *e0 = ev[2 * c->prof_used[cls]];
+    *e1 = ev[2 * c->prof_used[cls] + 1];
+    c->prof_used[cls]++;
+    return true;
 }
 
 void prof_end(eqs_ctx* c, int cls, hipStream_t s) {

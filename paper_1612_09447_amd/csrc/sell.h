@@ -2,8 +2,8 @@
 // column-major with the slice's longest row, so lane l of a wavefront reads
 // entry k of row 64 s + l at sptr[s] + 64 k + l (unit stride across lanes).
 // Column ids are either absolute (col, 32-bit) or, when every stored entry
-// lies within 32767 rows of the diagonal, 16-bit offsets from the row (d16):
-// 6 instead of 8 bytes per FP32 entry, 10 instead of 12 per FP64 entry.
+// lies within 32767 of offset_base(row), 16-bit offsets from it (d16): 6
+// instead of 8 bytes per FP32 entry, 10 instead of 12 per FP64 entry.
 // Padding entries carry value 0 and an in-range column.
 #pragma once
 
@@ -19,12 +19,12 @@ struct SellView {
     const int32_t* __restrict__ col;
     const int16_t* __restrict__ d16;
     const T* __restrict__ val;
-    int32_t n_rows, n_slices;
+    int32_t n_rows, n_slices, n_cols;
 };
 
 template <typename T>
 static inline SellView<T> view(const Sell<T>& A) {
-    return SellView<T>{A.sptr, A.col, A.d16, A.val, A.n_rows, A.n_slices};
+    return SellView<T>{A.sptr, A.col, A.d16, A.val, A.n_rows, A.n_slices, A.n_cols};
 }
 
 // sum_k a_{row,k} f(col_k) over the stored entries of `row` (rows past n_rows
@@ -44,11 +44,12 @@ __device__ __forceinline__ T sell_accum(const SellView<T>& A, int32_t row, F f) 
         int32_t j[8];
         if (A.d16) {
             const int16_t* dp = A.d16 + beg + l;
+            const int32_t base = offset_base(row, A.n_rows, A.n_cols);
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int64_t kk = (int64_t)min(k0 + u, w - 1) * 64;
                 v[u] = vp[kk];
-                j[u] = row + (int32_t)dp[kk];
+                j[u] = base + (int32_t)dp[kk];
             }
         } else {
             const int32_t* cp = A.col + beg + l;

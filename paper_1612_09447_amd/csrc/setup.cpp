@@ -543,44 +543,62 @@ Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A) {
             for (int32_t k = len; k < w; ++k) col[sptr[s] + (int64_t)k * kSlice + l] = pad_col;
         }
     }
-    // 16-bit offsets for square operators whose stored columns all lie within
-    // 32767 rows of their row (padding of rows past n_rows points at the last
-    // row, a valid column of a square matrix)
-    bool fits = c->index16 && A.n_rows == A.n_cols;
-    for (int32_t s = 0; s < S.n_slices && fits; ++s) {
-        const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
-        for (int32_t l = 0; l < kSlice && fits; ++l) {
-            const int32_t r = s * kSlice + l;
-            if (r >= A.n_rows) continue;
-            for (int32_t k = 0; k < w; ++k) {
-                const int64_t d = (int64_t)col[sptr[s] + (int64_t)k * kSlice + l] - r;
-                if (d < -32767 || d > 32767) { fits = false; break; }
+    // 16-bit offsets from offset_base(row) when every stored column allows
+    // (padding of rows past n_rows points at the last column)
+    bool fits = c->index16 && A.n_cols > 0;
+    std::vector<int16_t> d16;
+    if (fits) {
+        d16.assign(S.stored, 0);
+        for (int32_t s = 0; s < S.n_slices && fits; ++s) {
+            const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
+            for (int32_t l = 0; l < kSlice && fits; ++l) {
+                const int32_t r = s * kSlice + l;
+                const int64_t base = offset_base(r, A.n_rows, A.n_cols);
+                for (int32_t k = 0; k < w; ++k) {
+                    const int64_t at = sptr[s] + (int64_t)k * kSlice + l;
+                    const int64_t d = (r < A.n_rows ? (int64_t)col[at] : (int64_t)A.n_cols - 1) - base;
+                    if (d < -32767 || d > 32767) {
+                        fits = false;
+                        break;
+                    }
+                    d16[at] = (int16_t)d;
+                }
             }
         }
     }
     S.sptr = upload_vec(c, sptr);
-    if (fits) {
-        std::vector<int16_t> d16(S.stored, 0);
-        for (int32_t s = 0; s < S.n_slices; ++s) {
-            const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
-            for (int32_t l = 0; l < kSlice; ++l) {
-                const int32_t r = s * kSlice + l;
-                for (int32_t k = 0; k < w; ++k) {
-                    const int64_t at = sptr[s] + (int64_t)k * kSlice + l;
-                    d16[at] = (int16_t)(r < A.n_rows ? col[at] - r : (A.n_rows - 1) - r);
-                }
-            }
-        }
-        S.d16 = upload_vec(c, d16);
-    } else {
-        S.col = upload_vec(c, col);
-    }
+    if (fits) S.d16 = upload_vec(c, d16);
+    else S.col = upload_vec(c, col);
     S.val = upload_vec(c, val);
     return S;
 }
 
 template Sell<double> to_sell<double>(eqs_ctx*, const Csr<double>&);
 template Sell<float> to_sell<float>(eqs_ctx*, const Csr<double>&);
+
+// CSR column ids: 16-bit offsets from offset_base(row) when every entry
+// allows, else absolute.
+template <typename T>
+static void upload_csr_cols(eqs_ctx* c, SpMat<T>& S, const Csr<double>& A) {
+    bool fits = c->index16 && A.n_cols > 0;
+    std::vector<int16_t> d16;
+    if (fits) {
+        d16.resize(A.col.size());
+        for (int32_t r = 0; r < A.n_rows && fits; ++r) {
+            const int64_t base = offset_base(r, A.n_rows, A.n_cols);
+            for (int32_t k = A.ptr[r]; k < A.ptr[r + 1]; ++k) {
+                const int64_t d = (int64_t)A.col[k] - base;
+                if (d < -32767 || d > 32767) {
+                    fits = false;
+                    break;
+                }
+                d16[k] = (int16_t)d;
+            }
+        }
+    }
+    if (fits) S.d16 = upload_vec(c, d16);
+    else S.col = upload_vec(c, A.col);
+}
 
 // Layout choice: rows of up to 16 entries go one lane per row (SELL-64);
 // longer rows get L = 2^ceil(log2(mean/2)) lanes (2 <= L <= 64), so each lane
@@ -604,7 +622,7 @@ SpMat<T> to_spmat(eqs_ctx* c, const Csr<double>& A) {
     std::vector<T> v(A.val.size());
     for (size_t k = 0; k < v.size(); ++k) v[k] = (T)A.val[k];
     S.rowptr = upload_vec(c, A.ptr);
-    S.col = upload_vec(c, A.col);
+    upload_csr_cols(c, S, A);
     S.val = upload_vec(c, v);
     return S;
 }
@@ -619,6 +637,7 @@ static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
     dev_free(c, S.sell.val);
     dev_free(c, S.rowptr);
     dev_free(c, S.col);
+    dev_free(c, S.d16);
     dev_free(c, S.val);
     S = SpMat<T>{};
 }
@@ -665,7 +684,7 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
         S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
         S.fmt = FMT_SELL;
         S.sell = to_sell<T>(c, A);
-        consider(S, "sell64");
+        consider(S, S.sell.d16 ? "sell64/i16" : "sell64");
     }
     for (int L = 2; L <= 64; L *= 2) {
         if (L > 2 && L / 2 > 2.0 * mean) break;
@@ -676,9 +695,9 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
         std::vector<T> v(A.val.size());
         for (size_t k = 0; k < v.size(); ++k) v[k] = (T)A.val[k];
         S.rowptr = upload_vec(c, A.ptr);
-        S.col = upload_vec(c, A.col);
+        upload_csr_cols(c, S, A);
         S.val = upload_vec(c, v);
-        consider(S, "csr" + std::to_string(L));
+        consider(S, std::string("csr") + std::to_string(L) + (S.d16 ? "/i16" : ""));
     }
     dev_free(c, x);
     dev_free(c, y);
@@ -687,6 +706,25 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
                   best_name.c_str(), best_ms * 1e3);
     c->tune_log += line;
     return best;
+}
+
+// Values a_ij omega / a_jj of A omega D^{-1} in the storage order of the
+// uploaded layout S of A (same structure, so the same positions).
+template <typename T>
+static T* scaled_values(eqs_ctx* c, const SpMat<T>& S, const Csr<double>& A, const std::vector<double>& d,
+                        double omega) {
+    Csr<double> As = A;
+    for (size_t k = 0; k < As.val.size(); ++k) As.val[k] = A.val[k] * omega / d[A.col[k]];
+    if (S.fmt == FMT_SELL) {
+        Sell<T> t = to_sell<T>(c, As);
+        dev_free(c, t.sptr);
+        dev_free(c, t.col);
+        dev_free(c, t.d16);
+        return t.val;
+    }
+    std::vector<T> v(As.val.size());
+    for (size_t k = 0; k < v.size(); ++k) v[k] = (T)As.val[k];
+    return upload_vec(c, v);
 }
 
 template <typename T>
@@ -708,6 +746,7 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
         lv.xs = (T*)dev_alloc(c, sizeof(T) * lv.n);
         lv.res = (T*)dev_alloc(c, sizeof(T) * lv.n);
         if (l + 1 < L) {
+            lv.sval = scaled_values<T>(c, lv.A, ah.A[l], d, lv.omega);
             lv.P = tuned_spmat<T>(c, ah.P[l], ("P" + std::to_string(l)).c_str());
             lv.R = tuned_spmat<T>(c, ah.R[l], ("R" + std::to_string(l)).c_str());
         } else {

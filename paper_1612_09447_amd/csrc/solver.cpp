@@ -74,12 +74,17 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
     hipStream_t s = c->stream;
     const int prec = c->amg.precision;
     pcg_init(s, c, rhs, y, maxit, rtol, c->amg.flexible);
+    pcg_zero_rhs_rows(s, c, y);  // instances with rhs = 0 get y = 0 (others untouched)
     check_launch();
-    EQS_HIP(hipStreamSynchronize(s));
-    PcgSummary v = read_summary(c);
-    if (v.n_zero_rhs > 0) pcg_zero_rhs_rows(s, c, y);
+    // Iterations are enqueued without waiting for the start's result: an
+    // instance that is already done leaves its rows alone, and once all are
+    // done every kernel returns at entry.
+    PcgSummary v{};
     int restarts = 0;
-    while (!v.all_done) {
+    int32_t it_before = 0;
+    for (;;) {
+        int64_t used0[EQS_KCLASS_COUNT];
+        for (int k = 0; k < EQS_KCLASS_COUNT; ++k) used0[k] = c->prof_used[k];
         for (int64_t k = 0;; ++k) {
             run_iteration(c, y, prec);
             EQS_HIP(hipEventRecord(c->ev[k & 1], s));
@@ -91,13 +96,23 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
         }
         check_launch();
         EQS_HIP(hipStreamSynchronize(s));
+        if (c->prof_mask) {
+            // the launched iterations past the last one with work returned at
+            // entry: their launches are not counted in the kernel-class times
+            const int32_t it_now = read_summary(c).max_it;
+            const int64_t worked = std::max<int64_t>(0, it_now - it_before);
+            for (int k : {EQS_KCLASS_SPMV_M, EQS_KCLASS_PRESMOOTH0, EQS_KCLASS_POSTSMOOTH0, EQS_KCLASS_VCYCLE,
+                          EQS_KCLASS_CG_UPDATE})
+                c->prof_used[k] = std::min(c->prof_used[k], used0[k] + worked);
+            it_before = it_now;
+        }
         // every instance is done on its recursive residual (or out of iterations,
         // or broken down): check the true residuals; disagreeing ones restart
         pcg_true_residual(s, c, rhs, y);
         check_launch();
         EQS_HIP(hipStreamSynchronize(s));
         v = read_summary(c);
-        if (++restarts > 4) break;
+        if (v.all_done || ++restarts > 4) break;
     }
     int status = EQS_OK;
     if (v.n_notconv > 0 || !v.all_done) status = EQS_ERR_NOT_CONVERGED;
@@ -167,17 +182,15 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
         }
         if (j == 0) launch_copy(q, c->d_F0, c->d_F, NF);
         double* out;
-        prof_begin(c, EQS_KCLASS_RKC_COMBINE, q);
         if (j == 0) {
             out = c->d_Ya;
-            launch_rkc_first(q, out, c->d_Y0, c->d_F0, mut[1] * dt, NF);
+            launch_rkc_first(c, q, out, c->d_Y0, c->d_F0, mut[1] * dt, NF);
         } else {
             out = (Ycur == c->d_Ya) ? c->d_Yb : c->d_Ya;  // for j >= 2 this buffer holds Y_{j-1}
             const int k = j + 1;
-            launch_rkc_combine(q, out, c->d_Y0, Ycur, Yprev, c->d_F, c->d_F0, 1.0 - mu[k] - nu[k], mu[k], nu[k],
+            launch_rkc_combine(c, q, out, c->d_Y0, Ycur, Yprev, c->d_F, c->d_F0, 1.0 - mu[k] - nu[k], mu[k], nu[k],
                                mut[k] * dt, gmt[k] * dt, NF);
         }
-        prof_end(c, EQS_KCLASS_RKC_COMBINE, q);
         check_launch();
         Yprev = Ycur;
         Ycur = out;

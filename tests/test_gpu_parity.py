@@ -267,3 +267,25 @@ def test_rkc_single_level_hierarchy():
     case = eqsgen.case_c0(4)  # 75 free nodes: the dense coarse solve is the preconditioner
     err, it = trajectory_error(case, 5, 1e-12)
     assert err <= 1e-9 and it <= 2
+
+
+def test_profile_counts_launches_that_worked():
+    """Kernel-class timing: one element pass and one combination per stage,
+    one launch of each CG-iteration class per iteration that did work (the
+    launches enqueued after convergence return at entry and are not counted)."""
+    case = inclusion_case(14, 4)
+    classes = ("element", "spmv_M", "presmooth0", "postsmooth0", "vcycle", "cg_update", "rkc_combine")
+    with ctx_for(case, precision=EQS_PREC_FP32) as c:
+        x = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+        c.rkc_step(0.0, case.tau, case.s, x, rtol=1e-10)
+        c.profile_enable(classes)
+        st = c.rkc_step(case.tau, case.tau, case.s, x, rtol=1e-10)
+        prof = {k: c.profile_read(k) for k in classes}
+        c.profile_enable(())
+    print(f"[profile] {st['total_iters']} iterations: " +
+          ", ".join(f"{k} {v['launches']}x{1e3 * v['avg_ms']:.1f}us" for k, v in prof.items()), flush=True)
+    assert prof["element"]["launches"] == case.s and prof["rkc_combine"]["launches"] == case.s
+    for k in ("spmv_M", "presmooth0", "postsmooth0", "vcycle", "cg_update"):
+        assert prof[k]["launches"] == st["total_iters"], (k, prof[k], st)
+    for k in classes:
+        assert prof[k]["total_ms"] > 0.0, k
