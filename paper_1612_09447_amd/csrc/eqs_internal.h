@@ -160,9 +160,8 @@ struct GuessState {
     eqs_guess_params p{};
     std::vector<float> init;          // network initial parameters
     // window of stage solutions (device) and its Gram / energy matrices (host)
-    double* d_S = nullptr;            // [16][n_free]
+    double* d_S = nullptr;            // [16][n_free] window of stage solutions
     double* d_rprev = nullptr;        // r_{j-1}
-    double* d_x0 = nullptr;
     double* d_alpha = nullptr;        // [16]
     double* d_dots = nullptr;
     double* d_part = nullptr;

@@ -2,21 +2,26 @@
 //
 // The solutions F_j of successive stages solve M F_j = r_j with the same M, so
 // a window S of the last W stage solutions spans good start vectors. Sec. IV
-// builds them by a reduced solve on an orthonormal or POD basis V of S
-// (eq. (5): x0 = V (V^T M V)^{-1} V^T r). Here the POD basis comes from the
-// W x W Gram matrix G = S^T S, and V^T M V needs no extra products because
-// M s_k = r_k for every stored solution: H = S^T M S has entries r_a . s_b.
+// builds them by a reduced solve on a basis of S (eq. (5): x0 = V (V^T M V)^{-1}
+// V^T r). The reduced matrix needs no extra products because M s_k = r_k for
+// every stored solution: H = S^T M S has entries r_a . s_b. The window stays in
+// FP64: successive solutions differ by little, and the projection resolves
+// exactly those differences (FP32 snapshots cost 1.5-2x the CG iterations).
 //
 // Per stage j (after the element pass wrote r_j) one fused pass reads the
-// window S (before F_{j-1} joins it), u = F_{j-1}, v = r_j and w = r_{j-1}
-// and returns S^T u, S^T v, u.u, u.v, u.w. The host then
+// window S, u = F_{j-1}, v = r_j and w = r_{j-1}, returns S^T u, S^T v, u.u,
+// u.v, u.w, v.v, v.w, w.w and stores F_{j-1} in its slot. The host then
 //   * completes the training pair of stage j-1 (target V_{j-1}^T (F_{j-1} - F_{j-2})),
-//   * moves F_{j-1} into the window (G and H gain a row),
-//   * forms V from G's eigenvectors and the coefficients of the start vector:
-//     by eq. (5) (GALERKIN), or F_{j-1} plus the change the network predicts
-//     from the directions of V^T F_{j-1} and V^T (r_j - r_{j-1}) (MLP,
-//     inference on the GPU); x0 = S alpha (one pass),
-//   * lets a guard compare |r_j - M x0| with |r_j - M F_{j-1}|.
+//   * updates G = S^T S and H with the new solution's row,
+//   * forms the POD basis V = S B from G's eigenvectors (directions with
+//     singular values below 1e-7 of the largest are dropped) and then
+//     GALERKIN: solves eq. (5), (B^T H B) c = V^T r_j;
+//     MLP: lets the network
+//     predict the change from F_{j-1} from the directions of V^T F_{j-1} and
+//     V^T (r_j - r_{j-1}) (inference on the GPU);
+//   * x0 = S alpha in one pass, written over F_{j-1} (which stays in S);
+//   * MLP: a guard compares |r_j - M x0| with |r_j - M F_{j-1}|, the latter
+//     from the dots (|r_j - r_{j-1}|, since F_{j-1} solved M F = r_{j-1}).
 // The network then takes one Adam step on a minibatch of stored pairs.
 #include <algorithm>
 #include <cmath>
@@ -28,7 +33,7 @@
 namespace eqs {
 
 constexpr int kMaxWin = 16;
-constexpr int kNDots = 2 * kMaxWin + 3;
+constexpr int kNDots = 2 * kMaxWin + 6;
 constexpr int kDotGrid = 1024;
 
 // ------------------------------------------------------------- kernels
@@ -46,8 +51,10 @@ __device__ __forceinline__ void block_sums_store(double (&v)[NQ], double* __rest
     for (int q = threadIdx.x; q < NQ; q += blockDim.x) part[q * stride + blockIdx.x] = ((sh[q][0] + sh[q][1]) + sh[q][2]) + sh[q][3];
 }
 
-// S^T u, S^T v for the first nslot slots, and u.u, u.v, u.w.
-__global__ __launch_bounds__(256) void k_window_dots(const double* __restrict__ S, int64_t ld, int nslot,
+// S^T u, S^T v for the first nslot slots, and u.u, u.v, u.w, v.v, v.w, w.w;
+// slot `ins` then receives u (each element is read before it is replaced, so
+// the dots see the old window).
+__global__ __launch_bounds__(256) void k_window_dots(double* __restrict__ S, int64_t ld, int nslot, int ins,
                                                       const double* __restrict__ u, const double* __restrict__ v,
                                                       const double* __restrict__ w, int64_t n,
                                                       double* __restrict__ part) {
@@ -55,18 +62,23 @@ __global__ __launch_bounds__(256) void k_window_dots(const double* __restrict__ 
 #pragma unroll
     for (int q = 0; q < kNDots; ++q) acc[q] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double ui = u[i], vi = v[i];
+        const double ui = u[i], vi = v[i], wi = w[i];
+        double sk[kMaxWin];
+#pragma unroll
+        for (int k = 0; k < kMaxWin; ++k) sk[k] = S[(int64_t)min(k, max(nslot - 1, 0)) * ld + i];
 #pragma unroll
         for (int k = 0; k < kMaxWin; ++k) {
-            if (k < nslot) {
-                const double sk = S[k * ld + i];
-                acc[2 * k] += sk * ui;
-                acc[2 * k + 1] += sk * vi;
-            }
+            const double d = k < nslot ? sk[k] : 0.0;
+            acc[2 * k] += d * ui;
+            acc[2 * k + 1] += d * vi;
         }
         acc[2 * kMaxWin] += ui * ui;
         acc[2 * kMaxWin + 1] += ui * vi;
-        acc[2 * kMaxWin + 2] += ui * w[i];
+        acc[2 * kMaxWin + 2] += ui * wi;
+        acc[2 * kMaxWin + 3] += vi * vi;
+        acc[2 * kMaxWin + 4] += vi * wi;
+        acc[2 * kMaxWin + 5] += wi * wi;
+        S[(int64_t)ins * ld + i] = ui;
     }
     block_sums_store<kNDots>(acc, part, kDotGrid);
 }
@@ -82,32 +94,35 @@ __global__ void k_sum_rows(const double* __restrict__ part, int64_t stride, int 
     if (threadIdx.x == 0) out[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-// x0 = sum_k alpha_k S_k
-__global__ __launch_bounds__(256) void k_window_prolong(const double* __restrict__ S, int64_t ld, int nslot,
-                                                         const double* __restrict__ alpha, double* __restrict__ x0,
+struct Coef16 {
+    double v[kMaxWin];
+};
+
+// x0 = sum_k alpha_k S_k, alpha from the device (ad) or passed by value
+__global__ __launch_bounds__(256) void k_window_prolong(const double* __restrict__ S, int64_t ld, int nslot, Coef16 ah,
+                                                         const double* __restrict__ ad, double* __restrict__ x0,
                                                          int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double acc = 0.0;
-    for (int k = 0; k < nslot; ++k) acc += alpha[k] * S[k * ld + i];
+    for (int k = 0; k < nslot; ++k) acc += (ad ? ad[k] : ah.v[k]) * S[k * ld + i];
     x0[i] = acc;
 }
 
-// |r - M a|^2 and |r - M b|^2 (partials), M in SELL-64.
-__global__ __launch_bounds__(256) void k_two_residuals(SellView<double> M, const double* __restrict__ r,
-                                                        const double* __restrict__ a, const double* __restrict__ b,
-                                                        double* __restrict__ part, int64_t stride) {
-    double acc[2] = {0.0, 0.0};
+// |r - M a|^2 (block partials), M in SELL-64.
+__global__ __launch_bounds__(256) void k_residual_norm(SellView<double> M, const double* __restrict__ r,
+                                                        const double* __restrict__ a, double* __restrict__ part,
+                                                        int64_t stride) {
+    double acc[1] = {0.0};
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row < M.n_slices * 64) {
-        const double ma = sell_row(M, row, a), mb = sell_row(M, row, b);
+        const double ma = sell_row(M, row, a);
         if (row < M.n_rows) {
-            const double da = r[row] - ma, db = r[row] - mb;
+            const double da = r[row] - ma;
             acc[0] = da * da;
-            acc[1] = db * db;
         }
     }
-    block_sums_store<2>(acc, part, stride);
+    block_sums_store<1>(acc, part, stride);
 }
 
 // ---------------------------------------------------------- host algebra
@@ -175,6 +190,7 @@ static bool dense_solve(int n, std::vector<double> K, std::vector<double>& b) {
     return true;
 }
 
+
 // SplitMix64 (Steele, Lea, Flood 2014): minibatch indices from a counter.
 static uint64_t splitmix64(uint64_t x) {
     x += 0x9E3779B97F4A7C15ull;
@@ -227,7 +243,6 @@ void guess_alloc_device(eqs_ctx* c) {
     const int64_t NF = c->n_free;
     g.d_S = (double*)dev_alloc(c, sizeof(double) * (size_t)kMaxWin * NF);
     g.d_rprev = (double*)dev_alloc(c, sizeof(double) * NF);
-    g.d_x0 = (double*)dev_alloc(c, sizeof(double) * NF);
     g.d_alpha = (double*)dev_alloc(c, sizeof(double) * kMaxWin);
     g.d_dots = (double*)dev_alloc(c, sizeof(double) * 64);
     g.d_part = (double*)dev_alloc(c, sizeof(double) * kNDots * kDotGrid);
@@ -299,10 +314,14 @@ int guess_stage(eqs_ctx* c) {
     int used = 0;
     if (!g.have_prev) return 0;  // nothing known yet: d_F (zero or last run's) stays
 
-    // fused pass over the window (F_{j-1} still pending) with u = F_{j-1}, v = r_j, w = r_{j-1}
+    // the slot F_{j-1} will take (the oldest one once the window is full)
+    const int W = g.p.window;  // physical slots 0..W-1 fill in order, then rotate
     const int n_old = g.count;
+    const int e = (g.count < W) ? (g.oldest + g.count) % W : g.oldest;
+    // fused pass over the window with u = F_{j-1}, v = r_j, w = r_{j-1}; it
+    // also stores F_{j-1} in slot e
     const unsigned grid = (unsigned)std::min<int64_t>(kDotGrid, (NF + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_window_dots, dim3(grid), dim3(kBlock), 0, s, g.d_S, NF, n_old, c->d_F, c->d_rhs,
+    hipLaunchKernelGGL(k_window_dots, dim3(grid), dim3(kBlock), 0, s, g.d_S, NF, n_old, e, c->d_F, c->d_rhs,
                        g.d_rprev, NF, g.d_part);
     hipLaunchKernelGGL(k_sum_rows, dim3(kNDots), dim3(kBlock), 0, s, g.d_part, (int64_t)kDotGrid, (int)grid,
                        g.d_dots);
@@ -315,6 +334,8 @@ int guess_stage(eqs_ctx* c) {
         Sv[k] = k < n_old ? dots[2 * k + 1] : 0.0;
     }
     const double uu = dots[2 * kMaxWin], uv = dots[2 * kMaxWin + 1], uw = dots[2 * kMaxWin + 2];
+    // |r_j - M F_{j-1}|^2 = |r_j - r_{j-1}|^2 up to F_{j-1}'s own solve residual
+    const double prev_rr = dots[2 * kMaxWin + 3] - 2.0 * dots[2 * kMaxWin + 4] + dots[2 * kMaxWin + 5];
 
     // (1) training pair of the previous stage: target V_{j-1}^T (F_{j-1} - F_{j-2})
     if (g.have_pending && g.p.kind == EQS_GUESS_MLP) {
@@ -332,16 +353,9 @@ int guess_stage(eqs_ctx* c) {
     }
     g.have_pending = false;
 
-    // (2) F_{j-1} joins the window (evicting the oldest when full)
-    const int W = g.p.window;  // physical slots 0..W-1 fill in order, then rotate
-    int e;
-    if (g.count < W) {
-        e = (g.oldest + g.count) % W;
-        g.count++;
-    } else {
-        e = g.oldest;
-        g.oldest = (g.oldest + 1) % W;
-    }
+    // (2) F_{j-1} has joined the window in slot e (evicting the oldest when full)
+    if (g.count < W) g.count++;
+    else g.oldest = (g.oldest + 1) % W;
     // slots 0..n_old-1 are the physical slots in use before the insertion
     for (int b = 0; b < n_old; ++b) {
         if (b == e) continue;
@@ -350,7 +364,6 @@ int guess_stage(eqs_ctx* c) {
     }
     g.G[e * kMaxWin + e] = uu;
     g.H[e * kMaxWin + e] = uw;
-    launch_copy(s, g.d_S + (int64_t)e * NF, c->d_F, NF);
     // r_{j-1} against the new window (for the change of the RHS) and r_j,
     // kept for the next insertion
     double rprev[kMaxWin];
@@ -359,39 +372,40 @@ int guess_stage(eqs_ctx* c) {
 
     if (g.count < 2) return 0;
 
-    // (3) basis, features and coefficients
-    Basis B = window_basis(g);
-    std::vector<double> a = project(B, &g.G[e * kMaxWin]);  // V^T F_{j-1}
-    std::vector<double> bh = project(B, g.rdots.data());     // V^T r_j
-    std::vector<double> coef;                                // on V
+    // (3) coefficients of the start vector on the window
     bool have = false;
+    Coef16 coef{};
     if (g.p.kind == EQS_GUESS_GALERKIN) {
-        // (V^T M V) c = V^T r with V^T M V = B^T H B
+        // eq. (5) on the POD basis V = S B of the window: (V^T M V) c = V^T r_j,
+        // V^T M V = B^T H B (H = S^T M S has entries r_a . s_b), alpha = B c
+        const Basis B = window_basis(g);
         const int n = (int)B.slot.size(), m = B.m;
-        std::vector<double> K((size_t)m * m, 0.0);
-        for (int p = 0; p < m; ++p)
-            for (int q = 0; q < m; ++q) {
-                double acc = 0.0;
-                for (int i = 0; i < n; ++i)
-                    for (int k = 0; k < n; ++k)
-                        acc += B.B[(size_t)i * m + p] * g.H[B.slot[i] * kMaxWin + B.slot[k]] * B.B[(size_t)k * m + q];
-                K[(size_t)p * m + q] = acc;
+        std::vector<double> HB((size_t)n * m, 0.0), K((size_t)m * m, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                const double h = g.H[B.slot[i] * kMaxWin + B.slot[k]];
+                for (int q = 0; q < m; ++q) HB[(size_t)i * m + q] += h * B.B[(size_t)k * m + q];
+            }
+        for (int i = 0; i < n; ++i)
+            for (int p = 0; p < m; ++p) {
+                const double bip = B.B[(size_t)i * m + p];
+                for (int q = 0; q < m; ++q) K[(size_t)p * m + q] += bip * HB[(size_t)i * m + q];
             }
         for (int p = 0; p < m; ++p)
-            for (int q = p + 1; q < m; ++q) K[(size_t)p * m + q] = K[(size_t)q * m + p] = 0.5 * (K[(size_t)p * m + q] + K[(size_t)q * m + p]);
-        coef = bh;
-        have = dense_solve(m, K, coef);
-        if (have) {
-            std::vector<double> alpha(kMaxWin, 0.0);
+            for (int q = p + 1; q < m; ++q)
+                K[(size_t)p * m + q] = K[(size_t)q * m + p] = 0.5 * (K[(size_t)p * m + q] + K[(size_t)q * m + p]);
+        std::vector<double> cvec = project(B, g.rdots.data());  // V^T r_j
+        have = m > 0 && dense_solve(m, K, cvec);
+        if (have)
             for (int i = 0; i < n; ++i) {
                 double acc = 0.0;
-                for (int k = 0; k < m; ++k) acc += B.B[(size_t)i * m + k] * coef[k];
-                alpha[B.slot[i]] = acc;
+                for (int k = 0; k < m; ++k) acc += B.B[(size_t)i * m + k] * cvec[k];
+                coef.v[B.slot[i]] = acc;
             }
-            EQS_HIP(hipMemcpyAsync(g.d_alpha, alpha.data(), sizeof(double) * kMaxWin, hipMemcpyHostToDevice, s));
-            EQS_HIP(hipStreamSynchronize(s));
-        }
     } else if (g.p.kind == EQS_GUESS_MLP) {
+        const Basis B = window_basis(g);
+        const std::vector<double> a = project(B, &g.G[e * kMaxWin]);  // V^T F_{j-1}
+        const std::vector<double> bh = project(B, g.rdots.data());     // V^T r_j
         // The network predicts the change of the solution from F_{j-1} within
         // span(V), c ~ V^T (F_j - F_{j-1}), from the direction of the state
         // (V^T F_{j-1}) and of the change of the RHS (V^T (r_j - r_{j-1})).
@@ -432,24 +446,29 @@ int guess_stage(eqs_ctx* c) {
     }
 
     if (have) {
+        // x0 = S alpha goes straight into d_F; F_{j-1} stays in slot e
+        const bool mlp = g.p.kind == EQS_GUESS_MLP;
         hipLaunchKernelGGL(k_window_prolong, dim3((unsigned)((NF + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g.d_S,
-                           NF, g.count, g.d_alpha, g.d_x0, NF);
+                           NF, g.count, coef, mlp ? (const double*)g.d_alpha : nullptr, c->d_F, NF);
+        // The Galerkin vector minimises the M-norm of the error over the span
+        // of the window, which holds F_{j-1}: it cannot be worse than F_{j-1}
+        // in the norm CG reduces, so only the network's vector is guarded.
         bool take = true;
-        if (g.p.guard) {
+        if (g.p.guard && mlp) {
             const int64_t nb = (c->M.n_slices * 64 + kBlock - 1) / kBlock;
-            hipLaunchKernelGGL(k_two_residuals, dim3((unsigned)nb), dim3(kBlock), 0, s, view(c->M), c->d_rhs, g.d_x0,
-                               c->d_F, c->d_partials, c->max_blocks);
-            hipLaunchKernelGGL(k_sum_rows, dim3(2), dim3(kBlock), 0, s, c->d_partials, c->max_blocks, (int)nb,
+            hipLaunchKernelGGL(k_residual_norm, dim3((unsigned)nb), dim3(kBlock), 0, s, view(c->M), c->d_rhs, c->d_F,
+                               c->d_partials, c->max_blocks);
+            hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kBlock), 0, s, c->d_partials, c->max_blocks, (int)nb,
                                g.d_dots);
-            double rr[2];
-            EQS_HIP(hipMemcpyAsync(rr, g.d_dots, sizeof rr, hipMemcpyDeviceToHost, s));
+            double rr;
+            EQS_HIP(hipMemcpyAsync(&rr, g.d_dots, sizeof rr, hipMemcpyDeviceToHost, s));
             EQS_HIP(hipStreamSynchronize(s));
-            take = std::isfinite(rr[0]) && rr[0] <= rr[1];
+            take = std::isfinite(rr) && rr <= prev_rr;
         }
         if (take) {
-            launch_copy(s, c->d_F, g.d_x0, NF);
             used = 1;
         } else {
+            launch_copy(s, c->d_F, g.d_S + (int64_t)e * NF, NF);
             used = -1;
         }
     }

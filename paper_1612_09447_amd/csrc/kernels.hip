@@ -257,9 +257,10 @@ __device__ __forceinline__ double ipow(double x, int n) {
 }
 
 // Fused element pass over blocks of kTetBlock * TPT tets (one workgroup of
-// kTetBlock threads each; thread i handles tets i, i + kTetBlock, ...).
+// kTetBlock threads each).
 // 0. The block's packed tet records are loaded first (they do not depend on
-//    the node staging, so their latency overlaps it).
+//    the node staging, so their latency overlaps it); thread t takes TPT
+//    consecutive tets.
 // 1. The block's distinct nodes are staged in LDS: coordinates, potential
 //    (free: y[id]; Dirichlet: g(t) of its drive) and drive rate g'(t).
 // 2. Per tet: with edges e_k = p_k - p_0 and cofactor rows
@@ -278,59 +279,97 @@ __device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t nb) {
     return x * q + (x < r ? x : r) + (i >> 3);
 }
 
-template <bool RHS, int TPT>
-__global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, int64_t n_blocks, const uint64_t* __restrict__ tpack,
-                                                   const int32_t* __restrict__ boff,
-                                                   const int32_t* __restrict__ bnodes, const double* __restrict__ X,
-                                                   const double* __restrict__ Y, const double* __restrict__ Z,
-                                                   const MatDev* __restrict__ mats,
-                                                   const double* __restrict__ yfree, int32_t n_free,
-                                                   const int32_t* __restrict__ ddrive,
-                                                   const DriveDev* __restrict__ drives, double t,
-                                                   double* __restrict__ out) {
-    extern __shared__ double lds[];
-    const int64_t b = xcd_block(blockIdx.x, n_blocks);
-    uint64_t rec[TPT];
-#pragma unroll
-    for (int i = 0; i < TPT; ++i) {
-        const int64_t e = b * (kTetBlock * TPT) + i * kTetBlock + threadIdx.x;
-        rec[i] = e < n_tets ? tpack[e] : ~0ull;
-    }
-    const int32_t off = boff[b];
-    const int32_t nn = boff[b + 1] - off;
-    double4* P = reinterpret_cast<double4*>(lds);  // x, y, z, potential
-    double* R = lds + 4 * (size_t)nn;              // drive rate (0 for free nodes)
+// Stage a block's nodes in LDS (one array per quantity: 8-byte stride, so
+// gathers spread over the banks). Returns whether the block touches a
+// Dirichlet node (node lists are sorted and Dirichlet nodes come last in the
+// internal order, so iff its last node is one).
+
+struct KxArgs {
+    int64_t n_tets, n_blocks;
+    const uint64_t* __restrict__ tpack;
+    const int32_t* __restrict__ boff;
+    const int32_t* __restrict__ bnodes;
+    const double* __restrict__ X;
+    const double* __restrict__ Y;
+    const double* __restrict__ Z;
+    const MatDev* __restrict__ mats;
+    const double* __restrict__ yfree;
+    int32_t n_free;
+    const int32_t* __restrict__ ddrive;
+    const DriveDev* __restrict__ drives;
+    double t;
+    double* __restrict__ out;
+};
+
+template <bool RHS>
+__device__ __forceinline__ bool kx_stage(const KxArgs& A, double* lds, int32_t off, int32_t nn) {
+    double* PX = lds;
+    double* PY = PX + nn;
+    double* PZ = PY + nn;
+    double* PU = PZ + nn;
+    double* R = PU + nn;
     double* Acc = R + nn;
     for (int k = threadIdx.x; k < nn; k += kTetBlock) {
-        const int32_t id = bnodes[off + k];
-        double4 p = make_double4(X[id], Y[id], Z[id], 0.0);
-        double rate = 0.0;
-        if (id < n_free) {
-            p.w = yfree[id];
+        const int32_t id = A.bnodes[off + k];
+        double u, rate = 0.0;
+        if (id < A.n_free) {
+            u = A.yfree[id];
         } else {
-            const DriveDev d = drives[ddrive[id - n_free]];
-            const double ph = d.w * t + d.phase;
-            p.w = d.amp * sin(ph);
+            const DriveDev d = A.drives[A.ddrive[id - A.n_free]];
+            const double ph = d.w * A.t + d.phase;
+            u = d.amp * sin(ph);
             rate = d.w * d.amp * cos(ph);
         }
-        P[k] = p;
+        PX[k] = A.X[id];
+        PY[k] = A.Y[id];
+        PZ[k] = A.Z[id];
+        PU[k] = u;
         R[k] = rate;
         Acc[k] = 0.0;
     }
-    // node lists are sorted and Dirichlet nodes come last in the internal
-    // order, so the block touches one iff its last node is one
-    const bool has_dir = RHS && nn > 0 && bnodes[off + nn - 1] >= n_free;
-    __syncthreads();
+    return RHS && nn > 0 && A.bnodes[off + nn - 1] >= A.n_free;
+}
 
+// The thread's TPT consecutive tets of block b: records with 16-byte loads
+// (the record array is padded to whole blocks; padding records are ~0).
+template <int TPT>
+__device__ __forceinline__ void kx_records(const KxArgs& A, int64_t b, uint64_t (&rec)[TPT]) {
+    const uint64_t* rp = A.tpack + b * (kTetBlock * TPT) + (int64_t)threadIdx.x * TPT;
+    if (TPT == 1) {
+        rec[0] = rp[0];
+    } else {
+#pragma unroll
+        for (int q = 0; q < TPT / 2; ++q) {
+            const ulonglong2 v = reinterpret_cast<const ulonglong2*>(rp)[q];
+            rec[2 * q] = v.x;
+            rec[2 * q + 1] = v.y;
+        }
+    }
+}
+
+// Element matrices of the thread's tets times the staged potentials, added
+// into the LDS accumulator (see the kernel comment for the algebra).
+template <bool RHS, int TPT>
+__device__ __forceinline__ void kx_tets(const KxArgs& A, const double* lds, int32_t nn, bool has_dir,
+                                        const uint64_t (&rec)[TPT]) {
+    const double* PX = lds;
+    const double* PY = PX + nn;
+    const double* PZ = PY + nn;
+    const double* PU = PZ + nn;
+    const double* R = PU + nn;
+    double* Acc = const_cast<double*>(R + nn);
 #pragma unroll
     for (int i = 0; i < TPT; ++i) {
         const uint64_t w = rec[i];
         if (w == ~0ull) continue;
-        const MatDev m = mats[(uint32_t)(w & 0xffffu)];
+        const MatDev m = A.mats[(uint32_t)(w & 0xffffu)];
         int l[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) l[a] = (int)((w >> (16 + 12 * a)) & 0xfffu);
-        const double4 p0 = P[l[0]], p1 = P[l[1]], p2 = P[l[2]], p3 = P[l[3]];
+        const double4 p0 = make_double4(PX[l[0]], PY[l[0]], PZ[l[0]], PU[l[0]]);
+        const double4 p1 = make_double4(PX[l[1]], PY[l[1]], PZ[l[1]], PU[l[1]]);
+        const double4 p2 = make_double4(PX[l[2]], PY[l[2]], PZ[l[2]], PU[l[2]]);
+        const double4 p3 = make_double4(PX[l[3]], PY[l[3]], PZ[l[3]], PU[l[3]]);
         const double e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
         const double e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
         const double e3x = p3.x - p0.x, e3y = p3.y - p0.y, e3z = p3.z - p0.z;
@@ -373,22 +412,43 @@ __global__ __launch_bounds__(kTetBlock) void k_kx(int64_t n_tets, int64_t n_bloc
         unsafeAtomicAdd(&Acc[l[2]], y2);
         unsafeAtomicAdd(&Acc[l[3]], y3);
     }
-    __syncthreads();
+}
+
+// One global atomic per block node (RHS mode: free nodes only; the element
+// signs already give -K(x)x + b).
+template <bool RHS>
+__device__ __forceinline__ void kx_scatter(const KxArgs& A, const double* lds, int32_t off, int32_t nn) {
+    const double* Acc = lds + 5 * (size_t)nn;
     for (int k = threadIdx.x; k < nn; k += kTetBlock) {
-        const int32_t id = bnodes[off + k];
-        if (RHS && id >= n_free) continue;
-        unsafeAtomicAdd(&out[id], Acc[k]);
+        const int32_t id = A.bnodes[off + k];
+        if (RHS && id >= A.n_free) continue;
+        unsafeAtomicAdd(&A.out[id], Acc[k]);
     }
+}
+
+// One element block per workgroup (blocks in XCD-contiguous order).
+template <bool RHS, int TPT>
+__global__ __launch_bounds__(kTetBlock, 6) void k_kx(KxArgs A) {
+    extern __shared__ double lds[];
+    const int64_t b = xcd_block(blockIdx.x, A.n_blocks);
+    uint64_t rec[TPT];
+    kx_records<TPT>(A, b, rec);  // issued first: its latency overlaps the staging
+    const int32_t off = A.boff[b];
+    const int32_t nn = A.boff[b + 1] - off;
+    const bool has_dir = kx_stage<RHS>(A, lds, off, nn);
+    __syncthreads();
+    kx_tets<RHS, TPT>(A, lds, nn, has_dir, rec);
+    __syncthreads();
+    kx_scatter<RHS>(A, lds, off, nn);
 }
 
 template <bool RHS>
 static void launch_kx_t(hipStream_t s, eqs_ctx* c, const double* yfree, double t, double* out) {
-    dim3 g((unsigned)c->n_blocks), b(kTetBlock);
+    const KxArgs A{c->n_tets, c->n_blocks, c->d_tpack, c->d_boff, c->d_bnodes, c->d_cx, c->d_cy, c->d_cz, c->d_mats,
+                   yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out};
     const size_t lds = sizeof(double) * 6 * (size_t)c->max_block_nodes;
-#define EQS_KX(TPT_)                                                                                            \
-    EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx<RHS, TPT_>), g, b, lds, s, c->n_tets, c->n_blocks, c->d_tpack, \
-                     c->d_boff, c->d_bnodes, c->d_cx, c->d_cy, c->d_cz, c->d_mats, yfree, (int32_t)c->n_free,   \
-                     c->d_ddrive, c->d_drives, t, out)
+    const dim3 b(kTetBlock), g((unsigned)c->n_blocks);
+#define EQS_KX(TPT_) EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx<RHS, TPT_>), g, b, lds, s, A)
     switch (c->tet_tpt) {
         case 1: EQS_KX(1); break;
         case 2: EQS_KX(2); break;

@@ -817,7 +817,7 @@ static ElementBlocks element_blocks(const eqs_ctx* c, const std::vector<int32_t>
     const int64_t T = c->n_tets, per = (int64_t)kTetBlock * tpt;
     const int64_t nb = (T + per - 1) / per;
     ElementBlocks eb;
-    eb.pack.resize(T);
+    eb.pack.assign((size_t)(nb * per), ~0ull);  // whole blocks; padding records are skipped
     eb.boff.assign(nb + 1, 0);
     eb.bnodes.reserve((size_t)T);
     std::vector<int32_t> ids;
@@ -862,8 +862,8 @@ static void install_blocks(eqs_ctx* c, const ElementBlocks& eb, int tpt) {
 
 // Blocks of 256 tets per workgroup trade LDS reuse (each block re-reads the
 // nodes it shares with its neighbours) against parallelism; with autotuning
-// on, every block size that fits the 12-bit local ids is timed on the RHS
-// pass and the fastest kept (else 4 tets per thread).
+// on, every block size that fits the local ids is timed on the RHS pass and
+// the fastest kept (else 4 tets per thread).
 void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const double* yfree, double* out) {
     const std::vector<int32_t> order = morton_tet_order(c);
     const int fixed = 4;
@@ -890,7 +890,10 @@ void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const dou
         char buf[64];
         std::snprintf(buf, sizeof buf, " %d:%.1fus", kTetBlock * tpt, 1e3 * ms);
         line += buf;
-        if (ms < best) { best = ms; best_tpt = tpt; }
+        if (ms < best) {
+            best = ms;
+            best_tpt = tpt;
+        }
     }
     if (best_tpt == 0)
         fail(EQS_ERR_INVALID_ARG, "element block of 256 tets with more than " + std::to_string(kMaxBlockNodes) +
@@ -1004,7 +1007,7 @@ void free_device(eqs_ctx* c) {
     c->built = false;
     c->have_Flast = false;
     c->guess.dev_ready = false;
-    c->guess.d_S = c->guess.d_rprev = c->guess.d_x0 = c->guess.d_alpha = c->guess.d_dots = c->guess.d_part = nullptr;
+    c->guess.d_S = c->guess.d_rprev = c->guess.d_alpha = c->guess.d_dots = c->guess.d_part = nullptr;
     c->guess.d_bx = c->guess.d_bt = nullptr;
     if (!c->guess.G.empty()) guess_reset(c);
 }

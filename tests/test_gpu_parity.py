@@ -72,6 +72,24 @@ def test_apply_K_matches_oracle(maker):
             assert relinf(N(y), ref) <= 1e-12, (seed, relinf(N(y), ref))
 
 
+def test_element_pass_on_many_blocks_matches_oracle():
+    """The element pass on a mesh of 2.6 M tets (2,573 blocks of 1,024), whose
+    blocks include nodes shared between many blocks, against the oracle."""
+    case = inclusion_case(76, 2)
+    o = EqsOracle(case)
+    with ctx_for(case) as c:
+        print("[element] " + c.describe().splitlines()[1], flush=True)
+        x = eqsgen.random_state(case.n_nodes, 5, 1.5)
+        t = 0.0023
+        y = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+        c.apply_K(t, T(x), y)
+        ref = fem.apply_K(case, o.embed(x[o.free], t))
+        assert relinf(N(y), ref) <= 1e-12
+        r = torch.zeros(o.n_free, dtype=torch.float64, device=DEV)
+        c.stage_rhs(t, T(x[o.free]), r)
+        assert relinf(N(r), o.stage_rhs(t, x[o.free])) <= 1e-12
+
+
 def test_apply_K_relies_on_connectivity_only():
     case = inclusion_case(9, 5)
     x = eqsgen.random_state(case.n_nodes, 7, 2.0)
