@@ -251,11 +251,11 @@ int eqs_batch_instance_stats(const eqs_batch *b, int64_t *iters, double *relres)
  *                       V^T F_{j-1} and of V^T (r_j - r_{j-1}); it is trained
  *                       online on the GPU from the run's own pairs, with
  *                       target V^T (F_j - F_{j-1}) once F_j is known.
- * For MLP a guard compares |r - M x0| of the candidate with that of the
- * previous solution and keeps the better one (the Galerkin vector minimises the
- * M-norm of the error over a span that holds the previous solution, so it needs
- * none); CG to rtol always follows, so the start vector never changes the
- * result beyond the solve tolerance. */
+ * For MLP a guard keeps the network's correction only if it lowers the M-norm
+ * of the error of the start vector, which the reduced system gives without a
+ * product with M (the Galerkin vector minimises that norm over a span holding
+ * the previous solution, so it needs none); CG to rtol always follows, so the
+ * start vector never changes the result beyond the solve tolerance. */
 enum { EQS_GUESS_PREVIOUS = 0, EQS_GUESS_ZERO = 1, EQS_GUESS_GALERKIN = 2, EQS_GUESS_MLP = 3 };
 
 #define EQS_MLP_NPARAM 7312 /* W1[64][32] b1[64] W2[64][64] b2[64] W3[16][64] b3[16], float */
@@ -267,7 +267,7 @@ typedef struct eqs_guess_params {
     int32_t warmup;    /* pairs collected before the network's vector is used [256] */
     int32_t batch;     /* minibatch per stage, 1..64 [64] */
     int32_t bf16;      /* 1: BF16 matmul operands, FP32 accumulation; 0: FP32 [1] */
-    int32_t guard;     /* 1: residual guard of the network's vector against the previous solution [1] */
+    int32_t guard;     /* 1: keep the network's correction only where it lowers the error's M-norm [1] */
     int32_t reserved;
     double lr;         /* Adam learning rate [1e-3] */
     uint64_t seed;     /* minibatch sampling: SplitMix64 stream from this seed */

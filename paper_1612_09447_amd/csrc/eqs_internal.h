@@ -163,6 +163,9 @@ struct GuessState {
     double* d_S = nullptr;            // [16][n_free] window of stage solutions
     double* d_rprev = nullptr;        // r_{j-1}
     double* d_alpha = nullptr;        // [16]
+    double* d_guard = nullptr;        // [16 x 16 + 16 + 1] reduced matrix, RHS change, scale (network guard)
+    double* h_guard = nullptr;        // pinned staging of d_guard
+    int32_t* d_gstat = nullptr;       // [2] network corrections kept / dropped on the device
     double* d_dots = nullptr;
     double* d_part = nullptr;
     float *d_bx = nullptr, *d_bt = nullptr;  // minibatch staging
@@ -346,7 +349,8 @@ void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B);
 void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B);
 float mlp_last_loss(eqs_mlp* n);
 void mlp_get(eqs_mlp* n, float* params, float* grad);
-void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, const double* bias, double* alpha);
+void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, const double* bias, double* alpha,
+                        const double* guard, int32_t* stat);
 
 // start vectors (guess.hip)
 void guess_configure(eqs_ctx* c, const eqs_guess_params& p);
@@ -355,6 +359,7 @@ void guess_reset(eqs_ctx* c);
 int guess_stage(eqs_ctx* c);
 void guess_after_solve(eqs_ctx* c);
 double guess_last_loss(eqs_ctx* c);
+void guess_device_stats(eqs_ctx* c, int32_t* kept, int32_t* dropped);
 
 // per-kernel timing (profile.cpp)
 void prof_begin(eqs_ctx* c, int cls, hipStream_t s);

@@ -10,18 +10,17 @@
 //
 // Per stage j (after the element pass wrote r_j) one fused pass reads the
 // window S, u = F_{j-1}, v = r_j and w = r_{j-1}, returns S^T u, S^T v, u.u,
-// u.v, u.w, v.v, v.w, w.w and stores F_{j-1} in its slot. The host then
+// u.v, u.w and stores F_{j-1} in its slot. The host then
 //   * completes the training pair of stage j-1 (target V_{j-1}^T (F_{j-1} - F_{j-2})),
 //   * updates G = S^T S and H with the new solution's row,
 //   * forms the POD basis V = S B from G's eigenvectors (directions with
 //     singular values below 1e-7 of the largest are dropped) and then
 //     GALERKIN: solves eq. (5), (B^T H B) c = V^T r_j;
-//     MLP: lets the network
-//     predict the change from F_{j-1} from the directions of V^T F_{j-1} and
-//     V^T (r_j - r_{j-1}) (inference on the GPU);
-//   * x0 = S alpha in one pass, written over F_{j-1} (which stays in S);
-//   * MLP: a guard compares |r_j - M x0| with |r_j - M F_{j-1}|, the latter
-//     from the dots (|r_j - r_{j-1}|, since F_{j-1} solved M F = r_{j-1}).
+//     MLP: lets the network predict the change from F_{j-1} from the
+//     directions of V^T F_{j-1} and V^T (r_j - r_{j-1}) (inference on the
+//     GPU, which also keeps the change only if it lowers the M-norm of the
+//     error, judged in the reduced space);
+//   * x0 = S alpha in one pass, written over F_{j-1} (which stays in S).
 // The network then takes one Adam step on a minibatch of stored pairs.
 #include <algorithm>
 #include <cmath>
@@ -33,8 +32,9 @@
 namespace eqs {
 
 constexpr int kMaxWin = 16;
-constexpr int kNDots = 2 * kMaxWin + 6;
+constexpr int kNDots = 2 * kMaxWin + 3;
 constexpr int kDotGrid = 1024;
+constexpr int kGuardLen = 16 * 16 + 16 + 1;
 
 // ------------------------------------------------------------- kernels
 template <int NQ>
@@ -51,7 +51,7 @@ __device__ __forceinline__ void block_sums_store(double (&v)[NQ], double* __rest
     for (int q = threadIdx.x; q < NQ; q += blockDim.x) part[q * stride + blockIdx.x] = ((sh[q][0] + sh[q][1]) + sh[q][2]) + sh[q][3];
 }
 
-// S^T u, S^T v for the first nslot slots, and u.u, u.v, u.w, v.v, v.w, w.w;
+// S^T u, S^T v for the first nslot slots, and u.u, u.v, u.w;
 // slot `ins` then receives u (each element is read before it is replaced, so
 // the dots see the old window).
 __global__ __launch_bounds__(256) void k_window_dots(double* __restrict__ S, int64_t ld, int nslot, int ins,
@@ -75,9 +75,6 @@ __global__ __launch_bounds__(256) void k_window_dots(double* __restrict__ S, int
         acc[2 * kMaxWin] += ui * ui;
         acc[2 * kMaxWin + 1] += ui * vi;
         acc[2 * kMaxWin + 2] += ui * wi;
-        acc[2 * kMaxWin + 3] += vi * vi;
-        acc[2 * kMaxWin + 4] += vi * wi;
-        acc[2 * kMaxWin + 5] += wi * wi;
         S[(int64_t)ins * ld + i] = ui;
     }
     block_sums_store<kNDots>(acc, part, kDotGrid);
@@ -107,22 +104,6 @@ __global__ __launch_bounds__(256) void k_window_prolong(const double* __restrict
     double acc = 0.0;
     for (int k = 0; k < nslot; ++k) acc += (ad ? ad[k] : ah.v[k]) * S[k * ld + i];
     x0[i] = acc;
-}
-
-// |r - M a|^2 (block partials), M in SELL-64.
-__global__ __launch_bounds__(256) void k_residual_norm(SellView<double> M, const double* __restrict__ r,
-                                                        const double* __restrict__ a, double* __restrict__ part,
-                                                        int64_t stride) {
-    double acc[1] = {0.0};
-    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row < M.n_slices * 64) {
-        const double ma = sell_row(M, row, a);
-        if (row < M.n_rows) {
-            const double da = r[row] - ma;
-            acc[0] = da * da;
-        }
-    }
-    block_sums_store<1>(acc, part, stride);
 }
 
 // ---------------------------------------------------------- host algebra
@@ -206,6 +187,8 @@ void guess_release(eqs_ctx* c) {
     g.net = nullptr;
     if (g.h_stage) (void)hipHostFree(g.h_stage);
     g.h_stage = nullptr;
+    if (g.h_guard) (void)hipHostFree(g.h_guard);
+    g.h_guard = nullptr;
     g.dev_ready = false;
 }
 
@@ -236,6 +219,7 @@ void guess_configure(eqs_ctx* c, const eqs_guess_params& p) {
     guess_reset(c);
     if (p.kind == EQS_GUESS_MLP) g.net = mlp_create(c->device, c->stream, g.init.data(), p.bf16, p.lr);
     EQS_HIP(hipHostMalloc((void**)&g.h_stage, sizeof(float) * 64 * 48 + sizeof(double) * 64, hipHostMallocDefault));
+    EQS_HIP(hipHostMalloc((void**)&g.h_guard, sizeof(double) * kGuardLen, hipHostMallocDefault));
 }
 
 void guess_alloc_device(eqs_ctx* c) {
@@ -246,6 +230,9 @@ void guess_alloc_device(eqs_ctx* c) {
     g.d_alpha = (double*)dev_alloc(c, sizeof(double) * kMaxWin);
     g.d_dots = (double*)dev_alloc(c, sizeof(double) * 64);
     g.d_part = (double*)dev_alloc(c, sizeof(double) * kNDots * kDotGrid);
+    g.d_guard = (double*)dev_alloc(c, sizeof(double) * kGuardLen);
+    g.d_gstat = (int32_t*)dev_alloc(c, sizeof(int32_t) * 2);
+    EQS_HIP(hipMemset(g.d_gstat, 0, sizeof(int32_t) * 2));
     g.d_bx = (float*)dev_alloc(c, sizeof(float) * 64 * 32);
     g.d_bt = (float*)dev_alloc(c, sizeof(float) * 64 * 16);
     g.dev_ready = true;
@@ -296,6 +283,26 @@ static std::vector<double> project(const Basis& b, const double* dslot) {
     return out;
 }
 
+// V^T M V = B^T H B for V = S B (m x m, symmetrised).
+static std::vector<double> reduced_matrix(const GuessState& g, const Basis& B) {
+    const int n = (int)B.slot.size(), m = B.m;
+    std::vector<double> HB((size_t)n * m, 0.0), K((size_t)m * m, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
+            const double h = g.H[B.slot[i] * kMaxWin + B.slot[k]];
+            for (int q = 0; q < m; ++q) HB[(size_t)i * m + q] += h * B.B[(size_t)k * m + q];
+        }
+    for (int i = 0; i < n; ++i)
+        for (int p = 0; p < m; ++p) {
+            const double bip = B.B[(size_t)i * m + p];
+            for (int q = 0; q < m; ++q) K[(size_t)p * m + q] += bip * HB[(size_t)i * m + q];
+        }
+    for (int p = 0; p < m; ++p)
+        for (int q = p + 1; q < m; ++q)
+            K[(size_t)p * m + q] = K[(size_t)q * m + p] = 0.5 * (K[(size_t)p * m + q] + K[(size_t)q * m + p]);
+    return K;
+}
+
 static double norm(const std::vector<double>& v) {
     double s = 0.0;
     for (double x : v) s += x * x;
@@ -305,7 +312,8 @@ static double norm(const std::vector<double>& v) {
 // One stage's start vector. Called after the element pass wrote r_j into
 // c->d_rhs and before the solve; d_F holds F_{j-1} (if have_prev). On return
 // d_F holds the chosen start vector. Returns 1 if the estimator's vector was
-// used, -1 if the guard kept F_{j-1}, 0 if no estimate was available.
+// used, 2 if the network's vector went to the device guard (its decision is
+// counted there, see guess_device_stats), 0 if no estimate was available.
 int guess_stage(eqs_ctx* c) {
     GuessState& g = c->guess;
     hipStream_t s = c->stream;
@@ -334,8 +342,6 @@ int guess_stage(eqs_ctx* c) {
         Sv[k] = k < n_old ? dots[2 * k + 1] : 0.0;
     }
     const double uu = dots[2 * kMaxWin], uv = dots[2 * kMaxWin + 1], uw = dots[2 * kMaxWin + 2];
-    // |r_j - M F_{j-1}|^2 = |r_j - r_{j-1}|^2 up to F_{j-1}'s own solve residual
-    const double prev_rr = dots[2 * kMaxWin + 3] - 2.0 * dots[2 * kMaxWin + 4] + dots[2 * kMaxWin + 5];
 
     // (1) training pair of the previous stage: target V_{j-1}^T (F_{j-1} - F_{j-2})
     if (g.have_pending && g.p.kind == EQS_GUESS_MLP) {
@@ -380,20 +386,7 @@ int guess_stage(eqs_ctx* c) {
         // V^T M V = B^T H B (H = S^T M S has entries r_a . s_b), alpha = B c
         const Basis B = window_basis(g);
         const int n = (int)B.slot.size(), m = B.m;
-        std::vector<double> HB((size_t)n * m, 0.0), K((size_t)m * m, 0.0);
-        for (int i = 0; i < n; ++i)
-            for (int k = 0; k < n; ++k) {
-                const double h = g.H[B.slot[i] * kMaxWin + B.slot[k]];
-                for (int q = 0; q < m; ++q) HB[(size_t)i * m + q] += h * B.B[(size_t)k * m + q];
-            }
-        for (int i = 0; i < n; ++i)
-            for (int p = 0; p < m; ++p) {
-                const double bip = B.B[(size_t)i * m + p];
-                for (int q = 0; q < m; ++q) K[(size_t)p * m + q] += bip * HB[(size_t)i * m + q];
-            }
-        for (int p = 0; p < m; ++p)
-            for (int q = p + 1; q < m; ++q)
-                K[(size_t)p * m + q] = K[(size_t)q * m + p] = 0.5 * (K[(size_t)p * m + q] + K[(size_t)q * m + p]);
+        std::vector<double> K = reduced_matrix(g, B);
         std::vector<double> cvec = project(B, g.rdots.data());  // V^T r_j
         have = m > 0 && dense_solve(m, K, cvec);
         if (have)
@@ -439,7 +432,20 @@ int guess_stage(eqs_ctx* c) {
                 bias[e] = 1.0;
                 for (int i = 0; i < (int)B.slot.size(); ++i)
                     for (int k = 0; k < B.m; ++k) P[B.slot[i] * 16 + k] = B.B[(size_t)i * B.m + k] * scale;
-                mlp_forward_coeffs(g.net, x, P, bias, g.d_alpha);
+                const double* guard = nullptr;
+                if (g.p.guard) {
+                    // the device keeps the correction only if it lowers the M-norm of the error
+                    const std::vector<double> K = reduced_matrix(g, B);
+                    std::fill(g.h_guard, g.h_guard + kGuardLen, 0.0);
+                    for (int p = 0; p < B.m; ++p) {
+                        for (int q = 0; q < B.m; ++q) g.h_guard[p * 16 + q] = K[(size_t)p * B.m + q];
+                        g.h_guard[256 + p] = d[p];
+                    }
+                    g.h_guard[272] = scale;
+                    EQS_HIP(hipMemcpyAsync(g.d_guard, g.h_guard, sizeof(double) * kGuardLen, hipMemcpyHostToDevice, s));
+                    guard = g.d_guard;
+                }
+                mlp_forward_coeffs(g.net, x, P, bias, g.d_alpha, guard, g.d_gstat);
                 have = true;
             }
         }
@@ -452,25 +458,9 @@ int guess_stage(eqs_ctx* c) {
                            NF, g.count, coef, mlp ? (const double*)g.d_alpha : nullptr, c->d_F, NF);
         // The Galerkin vector minimises the M-norm of the error over the span
         // of the window, which holds F_{j-1}: it cannot be worse than F_{j-1}
-        // in the norm CG reduces, so only the network's vector is guarded.
-        bool take = true;
-        if (g.p.guard && mlp) {
-            const int64_t nb = (c->M.n_slices * 64 + kBlock - 1) / kBlock;
-            hipLaunchKernelGGL(k_residual_norm, dim3((unsigned)nb), dim3(kBlock), 0, s, view(c->M), c->d_rhs, c->d_F,
-                               c->d_partials, c->max_blocks);
-            hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kBlock), 0, s, c->d_partials, c->max_blocks, (int)nb,
-                               g.d_dots);
-            double rr;
-            EQS_HIP(hipMemcpyAsync(&rr, g.d_dots, sizeof rr, hipMemcpyDeviceToHost, s));
-            EQS_HIP(hipStreamSynchronize(s));
-            take = std::isfinite(rr) && rr <= prev_rr;
-        }
-        if (take) {
-            used = 1;
-        } else {
-            launch_copy(s, c->d_F, g.d_S + (int64_t)e * NF, NF);
-            used = -1;
-        }
+        // in the norm CG reduces. The network's correction is checked on the
+        // device in the same norm (k_mlp_alpha), its decision counted there.
+        used = mlp ? 2 : 1;
     }
     return used;
 }
@@ -494,6 +484,19 @@ void guess_after_solve(eqs_ctx* c) {
     EQS_HIP(hipMemcpyAsync(g.d_bt, ht, sizeof(float) * B * 16, hipMemcpyHostToDevice, c->stream));
     mlp_train(g.net, g.d_bx, g.d_bt, B);
     g.trained = true;
+}
+
+// Network corrections kept / dropped by the device guard since the last call
+// (the stream must be idle); the counters restart at zero.
+void guess_device_stats(eqs_ctx* c, int32_t* kept, int32_t* dropped) {
+    GuessState& g = c->guess;
+    *kept = *dropped = 0;
+    if (!g.dev_ready || !g.d_gstat) return;
+    int32_t h[2];
+    EQS_HIP(hipMemcpy(h, g.d_gstat, sizeof h, hipMemcpyDeviceToHost));
+    EQS_HIP(hipMemset(g.d_gstat, 0, sizeof h));
+    *kept = h[0];
+    *dropped = h[1];
 }
 
 double guess_last_loss(eqs_ctx* c) {

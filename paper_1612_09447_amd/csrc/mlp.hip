@@ -189,7 +189,12 @@ __global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ x, const 
 
 // Inference for one feature vector, followed by the map from the network's
 // 16 outputs to the 16 snapshot coefficients of the start vector:
-// alpha = P y (P carries the POD basis change and the output scale).
+// alpha = bias + P y (P carries the POD basis change and the output scale).
+// With a guard block g (K = V^T M V [16 x 16], d = V^T (r_j - r_{j-1}) [16],
+// scale s) the correction c = s y is kept only if it lowers the M-norm of the
+// error of the start vector: |x* - x0 - V c|_M^2 = |x* - x0|_M^2 - (2 c.d -
+// c.K c) when M x0 = r_{j-1}, so the test needs no product with M; otherwise
+// alpha = bias. stat[0] / stat[1] count kept / dropped corrections.
 struct MlpIn {
     float x[kIn];
     double P[kOut * kOut];
@@ -198,7 +203,8 @@ struct MlpIn {
 
 template <bool BF16>
 __global__ __launch_bounds__(64) void k_mlp_alpha(MlpIn in, const float* __restrict__ master,
-                                                   const float* __restrict__ wq, double* __restrict__ alpha) {
+                                                   const float* __restrict__ wq, double* __restrict__ alpha,
+                                                   const double* __restrict__ guard, int32_t* __restrict__ stat) {
     __shared__ float a1[kH], a2[kH], yv[kOut];
     const int tid = threadIdx.x;
     {
@@ -219,9 +225,28 @@ __global__ __launch_bounds__(64) void k_mlp_alpha(MlpIn in, const float* __restr
         yv[tid] = acc + master[oB3 + tid];
     }
     __syncthreads();
+    __shared__ int take;
+    if (tid == 0) {
+        take = 1;
+        if (guard) {
+            const double sc = guard[kOut * kOut + kOut];
+            double yd = 0.0, yky = 0.0;
+            for (int p = 0; p < kOut; ++p) {
+                yd += (double)yv[p] * guard[kOut * kOut + p];
+                double ky = 0.0;
+                for (int q = 0; q < kOut; ++q) ky += guard[p * kOut + q] * (double)yv[q];
+                yky += (double)yv[p] * ky;
+            }
+            const double gain = 2.0 * sc * yd - sc * sc * yky;
+            take = gain > 0.0 ? 1 : 0;
+            stat[take ? 0 : 1] += 1;
+        }
+    }
+    __syncthreads();
     if (tid < kOut) {
         double acc = in.bias[tid];
-        for (int k = 0; k < kOut; ++k) acc += in.P[tid * kOut + k] * (double)yv[k];
+        if (take)
+            for (int k = 0; k < kOut; ++k) acc += in.P[tid * kOut + k] * (double)yv[k];
         alpha[tid] = acc;
     }
 }
@@ -315,15 +340,18 @@ void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B) {
 
 void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B) { mlp_launch(n, true, x, t, nullptr, B); }
 
-void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, const double* bias, double* alpha) {
+void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, const double* bias, double* alpha,
+                        const double* guard, int32_t* stat) {
     MlpIn in;
     std::memcpy(in.x, x, sizeof in.x);
     std::memcpy(in.P, P, sizeof in.P);
     std::memcpy(in.bias, bias, sizeof in.bias);
     if (n->bf16)
-        hipLaunchKernelGGL(k_mlp_alpha<true>, dim3(1), dim3(64), 0, n->stream, in, n->master, n->wq, alpha);
+        hipLaunchKernelGGL(k_mlp_alpha<true>, dim3(1), dim3(64), 0, n->stream, in, n->master, n->wq, alpha, guard,
+                           stat);
     else
-        hipLaunchKernelGGL(k_mlp_alpha<false>, dim3(1), dim3(64), 0, n->stream, in, n->master, n->wq, alpha);
+        hipLaunchKernelGGL(k_mlp_alpha<false>, dim3(1), dim3(64), 0, n->stream, in, n->master, n->wq, alpha, guard,
+                           stat);
 }
 
 void mlp_get(eqs_mlp* n, float* params, float* grad) {

@@ -1008,6 +1008,8 @@ void free_device(eqs_ctx* c) {
     c->have_Flast = false;
     c->guess.dev_ready = false;
     c->guess.d_S = c->guess.d_rprev = c->guess.d_alpha = c->guess.d_dots = c->guess.d_part = nullptr;
+    c->guess.d_guard = nullptr;
+    c->guess.d_gstat = nullptr;
     c->guess.d_bx = c->guess.d_bt = nullptr;
     if (!c->guess.G.empty()) guess_reset(c);
 }

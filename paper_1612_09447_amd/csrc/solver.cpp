@@ -161,8 +161,7 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
             launch_fill(q, c->d_F, 0.0, NF);
         } else if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP) {
             const int u = guess_stage(c);
-            if (u > 0) S.guess_used++;
-            else if (u < 0) S.guess_fallbacks++;
+            if (u == 1) S.guess_used++;
         }
         // F_j = M^{-1} r_j
         eqs_solve_stats ss{};
@@ -200,7 +199,13 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
     EQS_HIP(hipStreamSynchronize(q));
     c->have_Flast = true;
     if (S.min_iters == INT32_MAX) S.min_iters = 0;
-    if (c->guess.p.kind == EQS_GUESS_MLP) S.train_loss = guess_last_loss(c);
+    if (c->guess.p.kind == EQS_GUESS_MLP) {
+        S.train_loss = guess_last_loss(c);
+        int32_t kept = 0, dropped = 0;
+        guess_device_stats(c, &kept, &dropped);
+        S.guess_used += kept;
+        S.guess_fallbacks += dropped;
+    }
     if (st) *st = S;
     return rc;
 }
