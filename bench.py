@@ -198,7 +198,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         # steps (filling the snapshot window and the replay buffer), then the
         # timed ones
         x0 = x.clone()
-        for kind in ("previous", "zero", "galerkin", "mlp"):
+        for kind in ("previous", "zero", "galerkin", "mor", "mlp"):
             x.copy_(x0)
             if kind == "mlp":
                 ctx.set_guess("mlp", init=eqsgen.mlp_init(4))
@@ -294,7 +294,7 @@ def main():
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     ap.add_argument("--c3-steps", type=int, default=0, help="also time the 64-instance batched workload")
     ap.add_argument("--learned-steps", type=int, default=0,
-                    help="also time this many steps with each start vector (zero, Galerkin, network)")
+                    help="also time this many steps with each start vector (zero, Galerkin, fixed POD, network)")
     args = ap.parse_args()
 
     os.environ["EQS_USE_GRAPHS"] = "1" if args.graphs else "0"

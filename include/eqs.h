@@ -245,6 +245,10 @@ int eqs_batch_instance_stats(const eqs_batch *b, int64_t *iters, double *relres)
  *                       solutions: V (V^T M V)^{-1} V^T r (the reduced matrix
  *                       comes for free because M s_k = r_k for every stored
  *                       solution s_k)
+ *   EQS_GUESS_MOR       eq. (5) on the POD basis of the first `window` stage
+ *                       solutions, which is then kept for the rest of the run
+ *                       (the reduced system is formed once; until the window
+ *                       is full it behaves as GALERKIN)
  *   EQS_GUESS_MLP       F_{j-1} + V c, where the start-vector network
  *                       (eqs_mlp below) predicts the change c of the stage
  *                       solution on the same basis from the directions of
@@ -256,7 +260,7 @@ int eqs_batch_instance_stats(const eqs_batch *b, int64_t *iters, double *relres)
  * product with M (the Galerkin vector minimises that norm over a span holding
  * the previous solution, so it needs none); CG to rtol always follows, so the
  * start vector never changes the result beyond the solve tolerance. */
-enum { EQS_GUESS_PREVIOUS = 0, EQS_GUESS_ZERO = 1, EQS_GUESS_GALERKIN = 2, EQS_GUESS_MLP = 3 };
+enum { EQS_GUESS_PREVIOUS = 0, EQS_GUESS_ZERO = 1, EQS_GUESS_GALERKIN = 2, EQS_GUESS_MLP = 3, EQS_GUESS_MOR = 4 };
 
 #define EQS_MLP_NPARAM 7312 /* W1[64][32] b1[64] W2[64][64] b2[64] W3[16][64] b3[16], float */
 
@@ -268,7 +272,8 @@ typedef struct eqs_guess_params {
     int32_t batch;     /* minibatch per stage, 1..64 [64] */
     int32_t bf16;      /* 1: BF16 matmul operands, FP32 accumulation; 0: FP32 [1] */
     int32_t guard;     /* 1: keep the network's correction only where it lowers the error's M-norm [1] */
-    int32_t reserved;
+    int32_t add_threshold; /* GALERKIN, MOR: a stage solution joins the window only if its solve took
+                              more than this many CG iterations (the first always joins) [0: every one] */
     double lr;         /* Adam learning rate [1e-3] */
     uint64_t seed;     /* minibatch sampling: SplitMix64 stream from this seed */
     const float *init; /* EQS_MLP_NPARAM initial parameters (host, copied); required for MLP */

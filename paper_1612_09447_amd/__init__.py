@@ -13,6 +13,7 @@ from .binding import (  # noqa: F401
     Mlp,
     EQS_GUESS_GALERKIN,
     EQS_GUESS_MLP,
+    EQS_GUESS_MOR,
     EQS_GUESS_PREVIOUS,
     EQS_GUESS_ZERO,
     EQS_MLP_NPARAM,

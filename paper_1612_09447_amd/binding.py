@@ -68,7 +68,7 @@ class eqs_step_stats(C.Structure):
 
 class eqs_guess_params(C.Structure):
     _fields_ = [("kind", C.c_int32), ("window", C.c_int32), ("capacity", C.c_int32), ("warmup", C.c_int32),
-                ("batch", C.c_int32), ("bf16", C.c_int32), ("guard", C.c_int32), ("reserved", C.c_int32),
+                ("batch", C.c_int32), ("bf16", C.c_int32), ("guard", C.c_int32), ("add_threshold", C.c_int32),
                 ("lr", C.c_double), ("seed", C.c_uint64), ("init", C.c_void_p)]
 
 
@@ -76,9 +76,10 @@ EQS_GUESS_PREVIOUS = 0
 EQS_GUESS_ZERO = 1
 EQS_GUESS_GALERKIN = 2
 EQS_GUESS_MLP = 3
+EQS_GUESS_MOR = 4
 EQS_MLP_NPARAM = 7312
 GUESS_KINDS = {"previous": EQS_GUESS_PREVIOUS, "zero": EQS_GUESS_ZERO, "galerkin": EQS_GUESS_GALERKIN,
-               "mlp": EQS_GUESS_MLP}
+               "mlp": EQS_GUESS_MLP, "mor": EQS_GUESS_MOR}
 
 
 class eqs_info(C.Structure):
@@ -338,7 +339,8 @@ class Context:
                     max_relres=st.max_relres, train_loss=st.train_loss, rc=rc)
 
     def set_guess(self, kind="previous", init=None, **kw):
-        """Select the stage start vector: previous, zero, galerkin (eq. (5)) or mlp."""
+        """Select the stage start vector: previous, zero, galerkin (eq. (5) on a sliding
+        window), mor (eq. (5) on a fixed basis) or mlp."""
         p = eqs_guess_params()
         p.kind = GUESS_KINDS[kind] if isinstance(kind, str) else int(kind)
         p.bf16 = 1

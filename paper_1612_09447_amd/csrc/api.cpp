@@ -357,7 +357,8 @@ int eqs_set_guess(eqs_ctx* c, const eqs_guess_params* p) {
     return guarded([&] {
         need(c != nullptr && p != nullptr, "NULL argument");
         eqs_guess_params a = *p;
-        need(a.kind >= EQS_GUESS_PREVIOUS && a.kind <= EQS_GUESS_MLP, "unknown guess kind");
+        need(a.kind >= EQS_GUESS_PREVIOUS && a.kind <= EQS_GUESS_MOR, "unknown guess kind");
+        need(a.add_threshold >= 0, "add_threshold must be >= 0");
         if (a.window == 0) a.window = 16;
         if (a.capacity == 0) a.capacity = 2000;
         if (a.batch == 0) a.batch = 64;

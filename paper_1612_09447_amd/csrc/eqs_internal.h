@@ -174,6 +174,11 @@ struct GuessState {
     int count = 0, oldest = 0;
     std::vector<double> G, H, rdots;  // 16 x 16, 16 x 16, 16
     bool have_prev = false;
+    int32_t last_iters = 0;           // CG iterations of the latest stage solve
+    bool frozen = false;              // MOR: the window is full and kept from now on
+    std::vector<int> mor_slot;        // MOR: basis and reduced matrix of the frozen window
+    std::vector<double> mor_B, mor_K;
+    int mor_m = 0;
     // pending training pair of the current stage
     bool have_pending = false;
     float pend_x[32];
@@ -188,6 +193,12 @@ struct GuessState {
     int rcount = 0, rhead = 0;
     uint64_t counter = 0;
     eqs_mlp* net = nullptr;
+    // the network trains on a stream of its own, overlapping the stage solve:
+    // training of stage j waits for that stage's inference (ev_inf), the
+    // inference of stage j+1 for that training (ev_train)
+    hipStream_t tstream = nullptr;
+    hipEvent_t ev_inf = nullptr, ev_train = nullptr;
+    bool inf_recorded = false, train_pending = false;
     bool trained = false;
     double last_loss = 0.0;
 };
@@ -349,15 +360,16 @@ void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B);
 void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B);
 float mlp_last_loss(eqs_mlp* n);
 void mlp_get(eqs_mlp* n, float* params, float* grad);
-void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, const double* bias, double* alpha,
-                        const double* guard, int32_t* stat);
+void mlp_forward_coeffs(eqs_mlp* n, hipStream_t s, const float* x, const double* P, const double* bias,
+                        double* alpha, const double* guard, int32_t* stat);
 
 // start vectors (guess.hip)
 void guess_configure(eqs_ctx* c, const eqs_guess_params& p);
 void guess_release(eqs_ctx* c);
 void guess_reset(eqs_ctx* c);
 int guess_stage(eqs_ctx* c);
-void guess_after_solve(eqs_ctx* c);
+void guess_after_solve(eqs_ctx* c, int32_t iters);
+void guess_train(eqs_ctx* c);
 double guess_last_loss(eqs_ctx* c);
 void guess_device_stats(eqs_ctx* c, int32_t* kept, int32_t* dropped);
 

@@ -21,7 +21,8 @@
 //     GPU, which also keeps the change only if it lowers the M-norm of the
 //     error, judged in the reduced space);
 //   * x0 = S alpha in one pass, written over F_{j-1} (which stays in S).
-// The network then takes one Adam step on a minibatch of stored pairs.
+// The network then takes one Adam step on a minibatch of stored pairs, on a
+// stream of its own while the stage's solve runs.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -52,8 +53,8 @@ __device__ __forceinline__ void block_sums_store(double (&v)[NQ], double* __rest
 }
 
 // S^T u, S^T v for the first nslot slots, and u.u, u.v, u.w;
-// slot `ins` then receives u (each element is read before it is replaced, so
-// the dots see the old window).
+// slot `ins` (if >= 0) then receives u (each element is read before it is
+// replaced, so the dots see the old window).
 __global__ __launch_bounds__(256) void k_window_dots(double* __restrict__ S, int64_t ld, int nslot, int ins,
                                                       const double* __restrict__ u, const double* __restrict__ v,
                                                       const double* __restrict__ w, int64_t n,
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(256) void k_window_dots(double* __restrict__ S, int
         acc[2 * kMaxWin] += ui * ui;
         acc[2 * kMaxWin + 1] += ui * vi;
         acc[2 * kMaxWin + 2] += ui * wi;
-        S[(int64_t)ins * ld + i] = ui;
+        if (ins >= 0) S[(int64_t)ins * ld + i] = ui;
     }
     block_sums_store<kNDots>(acc, part, kDotGrid);
 }
@@ -183,8 +184,15 @@ static uint64_t splitmix64(uint64_t x) {
 // ------------------------------------------------------------ guess state
 void guess_release(eqs_ctx* c) {
     GuessState& g = c->guess;
+    if (g.tstream) (void)hipStreamSynchronize(g.tstream);
     if (g.net) mlp_destroy(g.net);
     g.net = nullptr;
+    if (g.ev_inf) (void)hipEventDestroy(g.ev_inf);
+    if (g.ev_train) (void)hipEventDestroy(g.ev_train);
+    if (g.tstream) (void)hipStreamDestroy(g.tstream);
+    g.ev_inf = g.ev_train = nullptr;
+    g.tstream = nullptr;
+    g.inf_recorded = g.train_pending = false;
     if (g.h_stage) (void)hipHostFree(g.h_stage);
     g.h_stage = nullptr;
     if (g.h_guard) (void)hipHostFree(g.h_guard);
@@ -199,6 +207,12 @@ void guess_reset(eqs_ctx* c) {
     g.have_prev = false;
     g.have_pending = false;
     g.sol_scale = 0.0;
+    g.last_iters = 0;
+    g.frozen = false;
+    g.mor_slot.clear();
+    g.mor_B.clear();
+    g.mor_K.clear();
+    g.mor_m = 0;
     g.rcount = 0;
     g.rhead = 0;
     g.counter = 0;
@@ -217,7 +231,12 @@ void guess_configure(eqs_ctx* c, const eqs_guess_params& p) {
     g.rx.assign((size_t)p.capacity * 32, 0.0f);
     g.rt.assign((size_t)p.capacity * 16, 0.0f);
     guess_reset(c);
-    if (p.kind == EQS_GUESS_MLP) g.net = mlp_create(c->device, c->stream, g.init.data(), p.bf16, p.lr);
+    if (p.kind == EQS_GUESS_MLP) {
+        EQS_HIP(hipStreamCreateWithFlags(&g.tstream, hipStreamNonBlocking));  // default priority
+        EQS_HIP(hipEventCreateWithFlags(&g.ev_inf, hipEventDisableTiming));
+        EQS_HIP(hipEventCreateWithFlags(&g.ev_train, hipEventDisableTiming));
+        g.net = mlp_create(c->device, g.tstream, g.init.data(), p.bf16, p.lr);
+    }
     EQS_HIP(hipHostMalloc((void**)&g.h_stage, sizeof(float) * 64 * 48 + sizeof(double) * 64, hipHostMallocDefault));
     EQS_HIP(hipHostMalloc((void**)&g.h_guard, sizeof(double) * kGuardLen, hipHostMallocDefault));
 }
@@ -322,15 +341,20 @@ int guess_stage(eqs_ctx* c) {
     int used = 0;
     if (!g.have_prev) return 0;  // nothing known yet: d_F (zero or last run's) stays
 
-    // the slot F_{j-1} will take (the oldest one once the window is full)
+    // the slot F_{j-1} will take (the oldest one once the window is full). The
+    // network always adds it; GALERKIN and MOR only if its solve took more than
+    // add_threshold iterations (the first one always); a frozen MOR window
+    // takes no more.
     const int W = g.p.window;  // physical slots 0..W-1 fill in order, then rotate
     const int n_old = g.count;
     const int e = (g.count < W) ? (g.oldest + g.count) % W : g.oldest;
+    const bool insert = !g.frozen && (g.p.kind == EQS_GUESS_MLP || g.count == 0 || g.p.add_threshold == 0 ||
+                                      g.last_iters > g.p.add_threshold);
     // fused pass over the window with u = F_{j-1}, v = r_j, w = r_{j-1}; it
     // also stores F_{j-1} in slot e
     const unsigned grid = (unsigned)std::min<int64_t>(kDotGrid, (NF + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_window_dots, dim3(grid), dim3(kBlock), 0, s, g.d_S, NF, n_old, e, c->d_F, c->d_rhs,
-                       g.d_rprev, NF, g.d_part);
+    hipLaunchKernelGGL(k_window_dots, dim3(grid), dim3(kBlock), 0, s, g.d_S, NF, n_old, insert ? e : -1, c->d_F,
+                       c->d_rhs, g.d_rprev, NF, g.d_part);
     hipLaunchKernelGGL(k_sum_rows, dim3(kNDots), dim3(kBlock), 0, s, g.d_part, (int64_t)kDotGrid, (int)grid,
                        g.d_dots);
     double dots[kNDots];
@@ -360,33 +384,56 @@ int guess_stage(eqs_ctx* c) {
     g.have_pending = false;
 
     // (2) F_{j-1} has joined the window in slot e (evicting the oldest when full)
-    if (g.count < W) g.count++;
-    else g.oldest = (g.oldest + 1) % W;
-    // slots 0..n_old-1 are the physical slots in use before the insertion
-    for (int b = 0; b < n_old; ++b) {
-        if (b == e) continue;
-        g.G[e * kMaxWin + b] = g.G[b * kMaxWin + e] = Su[b];
-        g.H[e * kMaxWin + b] = g.H[b * kMaxWin + e] = g.rdots[b];  // r_{j-1} . s_b = s_b^T M F_{j-1}
+    double rprev[kMaxWin];  // r_{j-1} against the window (for the change of the RHS)
+    if (insert) {
+        if (g.count < W) g.count++;
+        else g.oldest = (g.oldest + 1) % W;
+        // slots 0..n_old-1 are the physical slots in use before the insertion
+        for (int b = 0; b < n_old; ++b) {
+            if (b == e) continue;
+            g.G[e * kMaxWin + b] = g.G[b * kMaxWin + e] = Su[b];
+            g.H[e * kMaxWin + b] = g.H[b * kMaxWin + e] = g.rdots[b];  // r_{j-1} . s_b = s_b^T M F_{j-1}
+        }
+        g.G[e * kMaxWin + e] = uu;
+        g.H[e * kMaxWin + e] = uw;
+        for (int b = 0; b < kMaxWin; ++b) rprev[b] = (b == e) ? uw : g.rdots[b];
+        // r_j against the new window, kept for the next insertion
+        for (int b = 0; b < kMaxWin; ++b) g.rdots[b] = (b == e) ? uv : (b < n_old ? Sv[b] : 0.0);
+        if (g.p.kind == EQS_GUESS_MOR && g.count == W) g.frozen = true;
+    } else {
+        for (int b = 0; b < kMaxWin; ++b) {
+            rprev[b] = g.rdots[b];
+            g.rdots[b] = b < n_old ? Sv[b] : 0.0;
+        }
     }
-    g.G[e * kMaxWin + e] = uu;
-    g.H[e * kMaxWin + e] = uw;
-    // r_{j-1} against the new window (for the change of the RHS) and r_j,
-    // kept for the next insertion
-    double rprev[kMaxWin];
-    for (int b = 0; b < kMaxWin; ++b) rprev[b] = (b == e) ? uw : g.rdots[b];
-    for (int b = 0; b < kMaxWin; ++b) g.rdots[b] = (b == e) ? uv : (b < n_old ? Sv[b] : 0.0);
 
     if (g.count < 2) return 0;
 
     // (3) coefficients of the start vector on the window
     bool have = false;
     Coef16 coef{};
-    if (g.p.kind == EQS_GUESS_GALERKIN) {
+    if (g.p.kind == EQS_GUESS_GALERKIN || g.p.kind == EQS_GUESS_MOR) {
         // eq. (5) on the POD basis V = S B of the window: (V^T M V) c = V^T r_j,
-        // V^T M V = B^T H B (H = S^T M S has entries r_a . s_b), alpha = B c
-        const Basis B = window_basis(g);
+        // V^T M V = B^T H B (H = S^T M S has entries r_a . s_b), alpha = B c.
+        // A frozen MOR window keeps its basis and reduced matrix.
+        Basis B;
+        std::vector<double> K;
+        if (g.frozen && !g.mor_slot.empty()) {
+            B.slot = g.mor_slot;
+            B.B = g.mor_B;
+            B.m = g.mor_m;
+            K = g.mor_K;
+        } else {
+            B = window_basis(g);
+            K = reduced_matrix(g, B);
+            if (g.frozen) {
+                g.mor_slot = B.slot;
+                g.mor_B = B.B;
+                g.mor_m = B.m;
+                g.mor_K = K;
+            }
+        }
         const int n = (int)B.slot.size(), m = B.m;
-        std::vector<double> K = reduced_matrix(g, B);
         std::vector<double> cvec = project(B, g.rdots.data());  // V^T r_j
         have = m > 0 && dense_solve(m, K, cvec);
         if (have)
@@ -445,7 +492,10 @@ int guess_stage(eqs_ctx* c) {
                     EQS_HIP(hipMemcpyAsync(g.d_guard, g.h_guard, sizeof(double) * kGuardLen, hipMemcpyHostToDevice, s));
                     guard = g.d_guard;
                 }
-                mlp_forward_coeffs(g.net, x, P, bias, g.d_alpha, guard, g.d_gstat);
+                if (g.train_pending) EQS_HIP(hipStreamWaitEvent(s, g.ev_train, 0));
+                mlp_forward_coeffs(g.net, s, x, P, bias, g.d_alpha, guard, g.d_gstat);
+                EQS_HIP(hipEventRecord(g.ev_inf, s));
+                g.inf_recorded = true;
                 have = true;
             }
         }
@@ -465,14 +515,23 @@ int guess_stage(eqs_ctx* c) {
     return used;
 }
 
-// After the solve of stage j: remember r_j (the next pass needs it), mark F_j
-// pending, and train the network on one minibatch.
-void guess_after_solve(eqs_ctx* c) {
+// After the solve of stage j: remember r_j (the next pass needs it) and mark
+// F_j pending.
+void guess_after_solve(eqs_ctx* c, int32_t iters) {
     GuessState& g = c->guess;
     std::swap(c->d_rhs, g.d_rprev);  // r_j is kept; the next element pass writes the other buffer
     g.have_prev = true;
+    g.last_iters = iters;
+}
+
+// One Adam step of the network on a minibatch of stored pairs, enqueued on the
+// training stream after this stage's inference has read the weights, so that
+// it runs while the stage's solve runs; the next inference waits for it.
+void guess_train(eqs_ctx* c) {
+    GuessState& g = c->guess;
     if (g.p.kind != EQS_GUESS_MLP || g.rcount == 0) return;
     const int B = std::min(g.p.batch, g.rcount);
+    if (g.train_pending) EQS_HIP(hipEventSynchronize(g.ev_train));  // the staging buffer is free again
     float* hx = g.h_stage;
     float* ht = g.h_stage + 64 * 32;
     for (int b = 0; b < B; ++b) {
@@ -480,9 +539,12 @@ void guess_after_solve(eqs_ctx* c) {
         std::memcpy(hx + b * 32, &g.rx[(size_t)idx * 32], 32 * sizeof(float));
         std::memcpy(ht + b * 16, &g.rt[(size_t)idx * 16], 16 * sizeof(float));
     }
-    EQS_HIP(hipMemcpyAsync(g.d_bx, hx, sizeof(float) * B * 32, hipMemcpyHostToDevice, c->stream));
-    EQS_HIP(hipMemcpyAsync(g.d_bt, ht, sizeof(float) * B * 16, hipMemcpyHostToDevice, c->stream));
+    if (g.inf_recorded) EQS_HIP(hipStreamWaitEvent(g.tstream, g.ev_inf, 0));  // weights read by this stage
+    EQS_HIP(hipMemcpyAsync(g.d_bx, hx, sizeof(float) * B * 32, hipMemcpyHostToDevice, g.tstream));
+    EQS_HIP(hipMemcpyAsync(g.d_bt, ht, sizeof(float) * B * 16, hipMemcpyHostToDevice, g.tstream));
     mlp_train(g.net, g.d_bx, g.d_bt, B);
+    EQS_HIP(hipEventRecord(g.ev_train, g.tstream));
+    g.train_pending = true;
     g.trained = true;
 }
 
@@ -499,10 +561,14 @@ void guess_device_stats(eqs_ctx* c, int32_t* kept, int32_t* dropped) {
     *dropped = h[1];
 }
 
+// Loss of the latest finished training step (a step still running on the
+// training stream is not waited for: its predecessor's loss is reported).
 double guess_last_loss(eqs_ctx* c) {
     GuessState& g = c->guess;
     if (!g.net || !g.trained) return 0.0;
-    return mlp_last_loss(g.net);
+    if (g.train_pending && hipEventQuery(g.ev_train) == hipErrorNotReady) return g.last_loss;
+    g.last_loss = mlp_last_loss(g.net);
+    return g.last_loss;
 }
 
 }  // namespace eqs

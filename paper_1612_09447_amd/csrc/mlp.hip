@@ -340,18 +340,16 @@ void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B) {
 
 void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B) { mlp_launch(n, true, x, t, nullptr, B); }
 
-void mlp_forward_coeffs(eqs_mlp* n, const float* x, const double* P, const double* bias, double* alpha,
-                        const double* guard, int32_t* stat) {
+void mlp_forward_coeffs(eqs_mlp* n, hipStream_t s, const float* x, const double* P, const double* bias,
+                        double* alpha, const double* guard, int32_t* stat) {
     MlpIn in;
     std::memcpy(in.x, x, sizeof in.x);
     std::memcpy(in.P, P, sizeof in.P);
     std::memcpy(in.bias, bias, sizeof in.bias);
     if (n->bf16)
-        hipLaunchKernelGGL(k_mlp_alpha<true>, dim3(1), dim3(64), 0, n->stream, in, n->master, n->wq, alpha, guard,
-                           stat);
+        hipLaunchKernelGGL(k_mlp_alpha<true>, dim3(1), dim3(64), 0, s, in, n->master, n->wq, alpha, guard, stat);
     else
-        hipLaunchKernelGGL(k_mlp_alpha<false>, dim3(1), dim3(64), 0, n->stream, in, n->master, n->wq, alpha, guard,
-                           stat);
+        hipLaunchKernelGGL(k_mlp_alpha<false>, dim3(1), dim3(64), 0, s, in, n->master, n->wq, alpha, guard, stat);
 }
 
 void mlp_get(eqs_mlp* n, float* params, float* grad) {

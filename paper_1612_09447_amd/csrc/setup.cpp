@@ -984,6 +984,7 @@ void upload(eqs_ctx* c) {
 }
 
 void free_device(eqs_ctx* c) {
+    if (c->guess.tstream) (void)hipStreamSynchronize(c->guess.tstream);
     release_graphs(c);
     for (auto& a : c->allocations) (void)hipFree(a.first);
     c->allocations.clear();

@@ -159,14 +159,15 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
         const int kind = c->guess.p.kind;
         if (kind == EQS_GUESS_ZERO) {
             launch_fill(q, c->d_F, 0.0, NF);
-        } else if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP) {
+        } else if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP || kind == EQS_GUESS_MOR) {
             const int u = guess_stage(c);
             if (u == 1) S.guess_used++;
+            guess_train(c);  // MLP: overlaps the solve below
         }
         // F_j = M^{-1} r_j
         eqs_solve_stats ss{};
         const int src = solve_M(c, c->d_rhs, c->d_F, rtol, maxit, &ss);
-        if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP) guess_after_solve(c);
+        if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP || kind == EQS_GUESS_MOR) guess_after_solve(c, ss.iters);
         S.total_iters += ss.iters;
         S.max_iters = std::max(S.max_iters, ss.iters);
         S.min_iters = std::min(S.min_iters, ss.iters);

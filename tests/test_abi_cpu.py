@@ -46,7 +46,7 @@ STRUCTS = {
     "eqs_solve_stats": ["iters", "status", "relres"],
     "eqs_step_stats": ["stages", "total_iters", "max_iters", "min_iters", "not_converged", "guess_used",
                        "guess_fallbacks", "reserved", "max_relres", "train_loss"],
-    "eqs_guess_params": ["kind", "window", "capacity", "warmup", "batch", "bf16", "guard", "reserved", "lr", "seed",
+    "eqs_guess_params": ["kind", "window", "capacity", "warmup", "batch", "bf16", "guard", "add_threshold", "lr", "seed",
                          "init"],
     "eqs_info": ["n_nodes", "n_tets", "n_free", "nnz_M", "n_levels", "precision", "level_rows", "level_nnz",
                  "device_bytes"],
