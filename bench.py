@@ -148,7 +148,7 @@ def timed_steps(ctx, x, n, steps, tau, s, rtol, label):
 
 
 def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous", flexible=0, learned_steps=0,
-            learned_warmup=20):
+            learned_warmup=20, mlp_batch=128):
     """Time `steps` RKC steps (uninstrumented), then `prof_steps` more with every
     kernel class timed by HIP events on the context's stream. With
     learned_steps > 0 the same context then switches to the Galerkin and the
@@ -201,7 +201,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         for kind in ("previous", "zero", "galerkin", "mor", "mlp"):
             x.copy_(x0)
             if kind == "mlp":
-                ctx.set_guess("mlp", init=eqsgen.mlp_init(4))
+                ctx.set_guess("mlp", init=eqsgen.mlp_init(4), batch=mlp_batch)
             else:
                 ctx.set_guess(kind)
             timed_steps(ctx, x, n, learned_warmup, tau, s, rtol, f"{kind} warm-up")
@@ -210,7 +210,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
                              "mean_cg_iters_per_stage": round(sum(it) / len(it), 2),
                              "guess_used": u, "guard_fallbacks": fb}
         learned["window"] = {"first_step": n + learned_warmup, "steps": learned_steps,
-                             "warmup_steps": learned_warmup}
+                             "warmup_steps": learned_warmup, "mlp_pairs_per_stage": mlp_batch}
         ctx.set_guess("previous")
     ctx.close()
     return dict(elapsed=elapsed, stages=steps * s, iters=iters, info=info, prof=prof, prof_elapsed=prof_elapsed,
@@ -293,6 +293,7 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     ap.add_argument("--c3-steps", type=int, default=0, help="also time the 64-instance batched workload")
+    ap.add_argument("--mlp-batch", type=int, default=128, help="network training pairs per stage (<= 256)")
     ap.add_argument("--learned-steps", type=int, default=0,
                     help="also time this many steps with each start vector (zero, Galerkin, fixed POD, network)")
     args = ap.parse_args()
@@ -316,7 +317,7 @@ def main():
     copy = copy_probe()
     log(f"[bench] copy probe: {copy}")
     r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess,
-                flexible=args.flexible, learned_steps=args.learned_steps)
+                flexible=args.flexible, learned_steps=args.learned_steps, mlp_batch=args.mlp_batch)
     stages_per_s = r["stages"] / r["elapsed"]
     info = r["info"]
     prof = r["prof"]

@@ -36,6 +36,7 @@ constexpr int kMaxWin = 16;
 constexpr int kNDots = 2 * kMaxWin + 3;
 constexpr int kDotGrid = 1024;
 constexpr int kGuardLen = 16 * 16 + 16 + 1;
+constexpr int kMaxPairsPerStage = 256;  // minibatches of up to 64 pairs, one Adam step each
 
 // ------------------------------------------------------------- kernels
 template <int NQ>
@@ -237,7 +238,7 @@ void guess_configure(eqs_ctx* c, const eqs_guess_params& p) {
         EQS_HIP(hipEventCreateWithFlags(&g.ev_train, hipEventDisableTiming));
         g.net = mlp_create(c->device, g.tstream, g.init.data(), p.bf16, p.lr);
     }
-    EQS_HIP(hipHostMalloc((void**)&g.h_stage, sizeof(float) * 64 * 48 + sizeof(double) * 64, hipHostMallocDefault));
+    EQS_HIP(hipHostMalloc((void**)&g.h_stage, sizeof(float) * kMaxPairsPerStage * 48, hipHostMallocDefault));
     EQS_HIP(hipHostMalloc((void**)&g.h_guard, sizeof(double) * kGuardLen, hipHostMallocDefault));
 }
 
@@ -252,8 +253,8 @@ void guess_alloc_device(eqs_ctx* c) {
     g.d_guard = (double*)dev_alloc(c, sizeof(double) * kGuardLen);
     g.d_gstat = (int32_t*)dev_alloc(c, sizeof(int32_t) * 2);
     EQS_HIP(hipMemset(g.d_gstat, 0, sizeof(int32_t) * 2));
-    g.d_bx = (float*)dev_alloc(c, sizeof(float) * 64 * 32);
-    g.d_bt = (float*)dev_alloc(c, sizeof(float) * 64 * 16);
+    g.d_bx = (float*)dev_alloc(c, sizeof(float) * kMaxPairsPerStage * 32);
+    g.d_bt = (float*)dev_alloc(c, sizeof(float) * kMaxPairsPerStage * 16);
     g.dev_ready = true;
 }
 
@@ -524,25 +525,27 @@ void guess_after_solve(eqs_ctx* c, int32_t iters) {
     g.last_iters = iters;
 }
 
-// One Adam step of the network on a minibatch of stored pairs, enqueued on the
-// training stream after this stage's inference has read the weights, so that
-// it runs while the stage's solve runs; the next inference waits for it.
+// Adam steps of the network on `batch` stored pairs (minibatches of up to 64,
+// one step each), enqueued on the training stream after this stage's
+// inference has read the weights, so that they run while the stage's solve
+// runs; the next inference waits for them.
 void guess_train(eqs_ctx* c) {
     GuessState& g = c->guess;
     if (g.p.kind != EQS_GUESS_MLP || g.rcount == 0) return;
-    const int B = std::min(g.p.batch, g.rcount);
+    const int total = std::min(g.p.batch, kMaxPairsPerStage);
     if (g.train_pending) EQS_HIP(hipEventSynchronize(g.ev_train));  // the staging buffer is free again
     float* hx = g.h_stage;
-    float* ht = g.h_stage + 64 * 32;
-    for (int b = 0; b < B; ++b) {
+    float* ht = g.h_stage + kMaxPairsPerStage * 32;
+    for (int b = 0; b < total; ++b) {
         const int idx = (int)(splitmix64(g.p.seed + g.counter++) % (uint64_t)g.rcount);
         std::memcpy(hx + b * 32, &g.rx[(size_t)idx * 32], 32 * sizeof(float));
         std::memcpy(ht + b * 16, &g.rt[(size_t)idx * 16], 16 * sizeof(float));
     }
     if (g.inf_recorded) EQS_HIP(hipStreamWaitEvent(g.tstream, g.ev_inf, 0));  // weights read by this stage
-    EQS_HIP(hipMemcpyAsync(g.d_bx, hx, sizeof(float) * B * 32, hipMemcpyHostToDevice, g.tstream));
-    EQS_HIP(hipMemcpyAsync(g.d_bt, ht, sizeof(float) * B * 16, hipMemcpyHostToDevice, g.tstream));
-    mlp_train(g.net, g.d_bx, g.d_bt, B);
+    EQS_HIP(hipMemcpyAsync(g.d_bx, hx, sizeof(float) * total * 32, hipMemcpyHostToDevice, g.tstream));
+    EQS_HIP(hipMemcpyAsync(g.d_bt, ht, sizeof(float) * total * 16, hipMemcpyHostToDevice, g.tstream));
+    for (int b0 = 0; b0 < total; b0 += 64)
+        mlp_train(g.net, g.d_bx + (size_t)b0 * 32, g.d_bt + (size_t)b0 * 16, std::min(64, total - b0));
     EQS_HIP(hipEventRecord(g.ev_train, g.tstream));
     g.train_pending = true;
     g.trained = true;

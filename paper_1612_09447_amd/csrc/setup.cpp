@@ -701,9 +701,10 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
     }
     dev_free(c, x);
     dev_free(c, y);
-    char line[160];
-    std::snprintf(line, sizeof line, "%s: %d x %d, %.1f nnz/row -> %s (%.1f us)\n", what, A.n_rows, A.n_cols, mean,
-                  best_name.c_str(), best_ms * 1e3);
+    char line[200];
+    const double fill = best.fmt == FMT_SELL && A.nnz() > 0 ? (double)best.sell.stored / (double)A.nnz() : 1.0;
+    std::snprintf(line, sizeof line, "%s: %d x %d, %.1f nnz/row -> %s (%.1f us, stored/nnz %.2f)\n", what, A.n_rows,
+                  A.n_cols, mean, best_name.c_str(), best_ms * 1e3, fill);
     c->tune_log += line;
     return best;
 }
