@@ -11,9 +11,12 @@ Each RKC(16) step runs 16 stages; a stage is one fused element pass
 (FP64 CG, FP32 AMG hierarchy and V-cycle), and one RKC combination.
 
 Prints ONE JSON line (rank 0). `value` = stages/s of the timed steps with all
-inputs resident in HBM. The plain FP64 path (FP64 hierarchy) is timed over a
-shorter window beside it, and the FP64 CPU oracle is timed on one stage of the
-same workload (cpu_baseline).
+inputs resident in HBM. Beside it: the plain FP64 path (FP64 hierarchy) over
+the same steps, the roofline of the dominant kernel from per-launch HIP events
+in an instrumented window that follows the timed steps, optionally
+(--learned-steps) every start vector over a common window and (--c3-steps) the
+64-instance batched workload, and the FP64 CPU oracle timed on one stage of the
+same workload (cpu_baseline). --gpus N > 1 exits: this build runs on one GPU.
 """
 
 from __future__ import annotations
@@ -110,6 +113,18 @@ def measured_traffic(kernel_class):
         if len(f) >= 3 and f[0] == "traffic" and f[1] == kernel_class:
             val = int(f[2])
     return val if sha == kernel_source_hash() else None
+
+
+def mixed_learned_vs_fp64(plain, learned):
+    """Stage rate of the mixed-precision form with the network start vector
+    relative to the plain FP64 path, as a product of same-window ratios: the
+    network vs the plain start vector (both mixed precision, same steps) times
+    the mixed-precision vs FP64 paths (plain start vector, same steps)."""
+    if not plain or "fp32_form_speedup" not in plain or not learned or "mlp" not in learned:
+        return None
+    net = learned["mlp"]["stages_per_s"] / learned["previous"]["stages_per_s"]
+    return {"value": round(net * plain["fp32_form_speedup"], 3), "network_vs_plain_start": round(net, 3),
+            "fp32_form_vs_fp64": plain["fp32_form_speedup"]}
 
 
 def cpu_model():
@@ -292,10 +307,11 @@ def main():
     ap.add_argument("--guess", default="previous", choices=["previous", "zero", "galerkin", "mlp"])
     ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
-    ap.add_argument("--c3-steps", type=int, default=0, help="also time the 64-instance batched workload")
+    ap.add_argument("--c3-steps", type=int, default=5, help="also time the 64-instance batched workload (0: skip)")
     ap.add_argument("--mlp-batch", type=int, default=128, help="network training pairs per stage (<= 256)")
-    ap.add_argument("--learned-steps", type=int, default=0,
-                    help="also time this many steps with each start vector (zero, Galerkin, fixed POD, network)")
+    ap.add_argument("--learned-steps", type=int, default=5,
+                    help="also time this many steps with each start vector (zero, Galerkin, fixed POD, network; "
+                         "0: skip)")
     args = ap.parse_args()
 
     os.environ["EQS_USE_GRAPHS"] = "1" if args.graphs else "0"
@@ -404,6 +420,7 @@ def main():
         "copy_probe": copy,
         "fp64_plain": plain,
         "start_vectors": r["learned"] or None,
+        "mixed_learned_vs_fp64": mixed_learned_vs_fp64(plain, r["learned"]),
         "batched": batched,
         "cpu_baseline": cpu,
     }
