@@ -92,8 +92,9 @@ typedef struct eqs_amg_params {
     int32_t coarse_max; /* coarsen until at most this many unknowns, <= 4096 [512] */
     int32_t max_levels; /* including the coarsest, 2..16 [12] */
     int32_t flexible;   /* CG beta: 1 Polak-Ribiere (flexible), 2 Fletcher-Reeves; 0 = PR with FP32, FR with FP64 */
-    double theta;       /* strength threshold |a_ij| >= theta sqrt(a_ii a_jj) [0.08] */
-    double jacobi_weight; /* damped-Jacobi weight times 1/rho(D^-1 A) [4/3] */
+    double theta;       /* strength threshold |a_ij| >= theta sqrt(a_ii a_jj) at the finest level,
+                           halved per level [0.02] */
+    double jacobi_weight; /* damped-Jacobi weight times 1/rho(D^-1 A) [3/2] */
     double smooth_weight; /* prolongator-smoothing weight times 1/rho(D^-1 A) [4/3] */
 } eqs_amg_params;
 

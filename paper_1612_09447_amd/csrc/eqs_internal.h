@@ -60,6 +60,7 @@ struct Csr {
 template <typename T>
 struct Sell {
     int32_t n_rows = 0, n_cols = 0, n_slices = 0;
+    int32_t lanes = 1;          // lanes per row (a slice holds 64 / lanes rows)
     int64_t stored = 0;         // padded entries
     int32_t* sptr = nullptr;    // [n_slices + 1]
     int32_t* col = nullptr;     // [stored] absolute column ids, or
@@ -67,10 +68,11 @@ struct Sell {
     T* val = nullptr;           // [stored]
 };
 
-// A hierarchy operator in one of two layouts, chosen per matrix from its
-// mean row length: SELL-64 (one lane per row) for short rows, or CSR with
-// `lanes` lanes per row (a power of two <= 64) whose partial sums are combined
-// by cross-lane shuffles, for long rows (coarse AMG operators).
+// A hierarchy operator in one of two layouts, chosen per matrix by timing
+// (or, without the autotuner, from its mean row length): SELL (1, 2, 4 or 8
+// lanes per row, sell.lanes), or CSR with `lanes` lanes per row (a power of
+// two <= 64) whose partial sums are combined by cross-lane shuffles, for the
+// long rows of coarse AMG operators.
 enum { FMT_SELL = 0, FMT_CSR = 1 };
 // Column ids stored as 16-bit offsets are relative to this base: the row
 // itself for a square operator, row * n_cols / n_rows for a rectangular one
@@ -279,6 +281,7 @@ struct eqs_ctx {
     std::vector<std::pair<void*, size_t>> allocations;
     bool index16 = true;   // 16-bit column offsets for SELL operators whose entries allow them
     bool autotune = true;  // time the candidate layouts of every AMG operator at build time
+    int force_layout = -1;  // >= 1: SELL with that many lanes per row, 0: CSR, for every coarse operator
     std::string tune_log;  // chosen layouts, one line per operator
 
     // start vectors
@@ -319,7 +322,7 @@ void upload(eqs_ctx* c);
 void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const double* yfree, double* out);
 void free_device(eqs_ctx* c);
 template <typename T>
-Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A);
+Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A, int lanes);
 template <typename T>
 SpMat<T> to_spmat(eqs_ctx* c, const Csr<double>& A);
 

@@ -106,22 +106,53 @@ __device__ __forceinline__ void inst_blocks(const InstMap& m, int32_t i, int32_t
     head = (r0 & 255) ? 1 : 0;
 }
 
-// Sum over blocks lo..hi (inclusive) of the first partial, by the 64 lanes of
-// one wavefront (the head block b0 is added by the caller); valid in all lanes.
-__device__ __forceinline__ double wave_range_sum(const double* __restrict__ part, int32_t lo, int32_t hi) {
+// Sums over blocks lo..hi (inclusive) of the first partial of NP arrays, by
+// the 64 lanes of one wavefront (the head block b0 is added by the caller);
+// valid in all lanes. Each lane issues 8 loads per array before it adds, so
+// a short range costs about one memory latency. The order of the additions
+// is fixed (it does not depend on timing).
+template <int NP>
+__device__ __forceinline__ void wave_range_sums(const double* const (&parts)[NP], int32_t lo, int32_t hi,
+                                                double (&out)[NP]) {
+    constexpr int U = 8;
     const int lane = threadIdx.x & 63;
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    double acc[NP][U];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[p][u] = 0.0;
     int32_t b = lo + lane;
-    for (; b + 192 <= hi; b += 256) {
-        v0 += part[2 * (int64_t)b];
-        v1 += part[2 * (int64_t)(b + 64)];
-        v2 += part[2 * (int64_t)(b + 128)];
-        v3 += part[2 * (int64_t)(b + 192)];
+    for (; b + 64 * (U - 1) <= hi; b += 64 * U) {
+        double t[NP][U];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int u = 0; u < U; ++u) t[p][u] = parts[p][2 * (int64_t)(b + 64 * u)];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[p][u] += t[p][u];
     }
-    for (; b <= hi; b += 64) v0 += part[2 * (int64_t)b];
-    double v = (v0 + v1) + (v2 + v3);
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    // tail: fewer than U blocks left for this lane; positions past hi re-read
+    // block hi and are dropped by a select
+    if (b <= hi) {
+#pragma unroll
+        for (int u = 0; u < U - 1; ++u) {
+            const int32_t bb = b + 64 * u;
+            const int32_t bc = min(bb, hi);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const double t = parts[p][2 * (int64_t)bc];
+                acc[p][u] += (bb <= hi) ? t : 0.0;
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        double v = ((acc[p][0] + acc[p][1]) + (acc[p][2] + acc[p][3])) + ((acc[p][4] + acc[p][5]) + (acc[p][6] + acc[p][7]));
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        out[p] = v;
+    }
 }
 
 constexpr int kFinWaves = kFin / 64;
@@ -148,11 +179,10 @@ __device__ __forceinline__ void for_each_instance_sum(const double* const (&part
                 const int32_t first = b0 + 1, n = b1 - b0;  // blocks first..b1 read their first partial
                 const int32_t lo = first + (int32_t)(((int64_t)n * sub) / wpi);
                 const int32_t hi = first + (int32_t)(((int64_t)n * (sub + 1)) / wpi) - 1;
+                wave_range_sums<NP>(parts, lo, hi, v);
+                if (sub == 0)
 #pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    v[p] = wave_range_sum(parts[p], lo, hi);
-                    if (sub == 0) v[p] += parts[p][2 * (int64_t)b0 + head];
-                }
+                    for (int p = 0; p < NP; ++p) v[p] += parts[p][2 * (int64_t)b0 + head];
             }
         }
         if (lane == 0)
@@ -176,9 +206,11 @@ __device__ __forceinline__ void for_each_instance_sum(const double* const (&part
             inst_blocks(m, i, b0, b1, head);
             double sums[NP];
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                sums[p] = 0.0;
-                if (b1 >= b0) sums[p] = wave_range_sum(parts[p], b0 + 1, b1) + parts[p][2 * (int64_t)b0 + head];
+            for (int p = 0; p < NP; ++p) sums[p] = 0.0;
+            if (b1 >= b0) {
+                wave_range_sums<NP>(parts, b0 + 1, b1, sums);
+#pragma unroll
+                for (int p = 0; p < NP; ++p) sums[p] += parts[p][2 * (int64_t)b0 + head];
             }
             if (lane == 0) body(i, sums);
         }
@@ -301,14 +333,20 @@ struct KxArgs {
     double* __restrict__ out;
 };
 
-template <bool RHS>
+// The six LDS arrays of a block (x, y, z, potential, rate, accumulator) are
+// S doubles apart: S = STRIDE when the kernel is built for a fixed stride
+// (covering every block, so each node needs one LDS address and the arrays are
+// reached by immediate offsets), else the block's node count. A fixed stride
+// is one more than a multiple of 64 doubles: the arrays of one node then sit
+// in different LDS banks (a multiple of 64 would put all six in one bank).
+template <int STRIDE>
+__device__ __forceinline__ int32_t kx_stride(int32_t nn) {
+    return STRIDE > 0 ? STRIDE : nn;
+}
+
+template <bool RHS, int STRIDE>
 __device__ __forceinline__ bool kx_stage(const KxArgs& A, double* lds, int32_t off, int32_t nn) {
-    double* PX = lds;
-    double* PY = PX + nn;
-    double* PZ = PY + nn;
-    double* PU = PZ + nn;
-    double* R = PU + nn;
-    double* Acc = R + nn;
+    const int32_t S = kx_stride<STRIDE>(nn);
     for (int k = threadIdx.x; k < nn; k += kTetBlock) {
         const int32_t id = A.bnodes[off + k];
         double u, rate = 0.0;
@@ -320,12 +358,13 @@ __device__ __forceinline__ bool kx_stage(const KxArgs& A, double* lds, int32_t o
             u = d.amp * sin(ph);
             rate = d.w * d.amp * cos(ph);
         }
-        PX[k] = A.X[id];
-        PY[k] = A.Y[id];
-        PZ[k] = A.Z[id];
-        PU[k] = u;
-        R[k] = rate;
-        Acc[k] = 0.0;
+        double* q = lds + k;
+        q[0] = A.X[id];
+        q[S] = A.Y[id];
+        q[2 * S] = A.Z[id];
+        q[3 * S] = u;
+        q[4 * S] = rate;
+        q[5 * S] = 0.0;
     }
     return RHS && nn > 0 && A.bnodes[off + nn - 1] >= A.n_free;
 }
@@ -349,15 +388,16 @@ __device__ __forceinline__ void kx_records(const KxArgs& A, int64_t b, uint64_t 
 
 // Element matrices of the thread's tets times the staged potentials, added
 // into the LDS accumulator (see the kernel comment for the algebra).
-template <bool RHS, int TPT>
-__device__ __forceinline__ void kx_tets(const KxArgs& A, const double* lds, int32_t nn, bool has_dir,
+template <bool RHS, int TPT, int STRIDE>
+__device__ __forceinline__ void kx_tets(const KxArgs& A, double* lds, int32_t nn, bool has_dir,
                                         const uint64_t (&rec)[TPT]) {
+    const int32_t S = kx_stride<STRIDE>(nn);
     const double* PX = lds;
-    const double* PY = PX + nn;
-    const double* PZ = PY + nn;
-    const double* PU = PZ + nn;
-    const double* R = PU + nn;
-    double* Acc = const_cast<double*>(R + nn);
+    const double* PY = PX + S;
+    const double* PZ = PY + S;
+    const double* PU = PZ + S;
+    const double* R = PU + S;
+    double* Acc = lds + 5 * S;
 #pragma unroll
     for (int i = 0; i < TPT; ++i) {
         const uint64_t w = rec[i];
@@ -377,35 +417,39 @@ __device__ __forceinline__ void kx_tets(const KxArgs& A, const double* lds, int3
         const double c2x = e3y * e1z - e3z * e1y, c2y = e3z * e1x - e3x * e1z, c2z = e3x * e1y - e3y * e1x;
         const double c3x = e1y * e2z - e1z * e2y, c3y = e1z * e2x - e1x * e2z, c3z = e1x * e2y - e1y * e2x;
         const double det = e1x * c1x + e1y * c1y + e1z * c1z;
-        const double adet = fabs(det);
+        const double inv = 1.0 / fabs(det);  // the one division per tet
 
         const double d1 = p1.w - p0.w, d2 = p2.w - p0.w, d3 = p3.w - p0.w;
         double wx = c1x * d1 + c2x * d2 + c3x * d3;
         double wy = c1y * d1 + c2y * d2 + c3y * d3;
         double wz = c1z * d1 + c2z * d2 + c3z * d3;
 
-        double kappa = m.kappa0;
+        // (A_e u)_a = c_a . w / (6 |det|): the factor sc goes into w
+        const double sc = (RHS ? -1.0 / 6.0 : 1.0 / 6.0) * inv;
+        double ks = m.kappa0 * sc;
         if (m.nonlinear) {
-            const double ratio = sqrt(wx * wx + wy * wy + wz * wz) / adet * m.inv_es;
-            const double pw = (m.ialpha >= 0) ? ipow(ratio, m.ialpha) : pow(ratio, m.alpha);
-            kappa *= 1.0 + pw;
+            const double ratio = sqrt(wx * wx + wy * wy + wz * wz) * inv * m.inv_es;
+            // r^alpha as exp(alpha ln r): relative error ~ ulp(alpha ln r), about
+            // 1e-14 for the exponents and fields here (r = 0 gives 0)
+            const double pw = (m.ialpha >= 0) ? ipow(ratio, m.ialpha) : exp(m.alpha * log(ratio));
+            ks *= 1.0 + pw;
         }
-        wx *= kappa;
-        wy *= kappa;
-        wz *= kappa;
+        wx *= ks;
+        wy *= ks;
+        wz *= ks;
         if (RHS && has_dir) {
             const double r0 = R[l[0]], r1 = R[l[1]], r2 = R[l[2]], r3 = R[l[3]];
             if (r0 != 0.0 || r1 != 0.0 || r2 != 0.0 || r3 != 0.0) {
                 const double q1 = r1 - r0, q2 = r2 - r0, q3 = r3 - r0;
-                wx += m.eps * (c1x * q1 + c2x * q2 + c3x * q3);
-                wy += m.eps * (c1y * q1 + c2y * q2 + c3y * q3);
-                wz += m.eps * (c1z * q1 + c2z * q2 + c3z * q3);
+                const double es = m.eps * sc;
+                wx += es * (c1x * q1 + c2x * q2 + c3x * q3);
+                wy += es * (c1y * q1 + c2y * q2 + c3y * q3);
+                wz += es * (c1z * q1 + c2z * q2 + c3z * q3);
             }
         }
-        const double sc = (RHS ? -1.0 : 1.0) / (6.0 * adet);
-        const double y1 = (c1x * wx + c1y * wy + c1z * wz) * sc;
-        const double y2 = (c2x * wx + c2y * wy + c2z * wz) * sc;
-        const double y3 = (c3x * wx + c3y * wy + c3z * wz) * sc;
+        const double y1 = c1x * wx + c1y * wy + c1z * wz;
+        const double y2 = c2x * wx + c2y * wy + c2z * wz;
+        const double y3 = c3x * wx + c3y * wy + c3z * wz;
         const double y0 = -(y1 + y2 + y3);
         unsafeAtomicAdd(&Acc[l[0]], y0);
         unsafeAtomicAdd(&Acc[l[1]], y1);
@@ -416,9 +460,9 @@ __device__ __forceinline__ void kx_tets(const KxArgs& A, const double* lds, int3
 
 // One global atomic per block node (RHS mode: free nodes only; the element
 // signs already give -K(x)x + b).
-template <bool RHS>
+template <bool RHS, int STRIDE>
 __device__ __forceinline__ void kx_scatter(const KxArgs& A, const double* lds, int32_t off, int32_t nn) {
-    const double* Acc = lds + 5 * (size_t)nn;
+    const double* Acc = lds + 5 * kx_stride<STRIDE>(nn);
     for (int k = threadIdx.x; k < nn; k += kTetBlock) {
         const int32_t id = A.bnodes[off + k];
         if (RHS && id >= A.n_free) continue;
@@ -427,7 +471,7 @@ __device__ __forceinline__ void kx_scatter(const KxArgs& A, const double* lds, i
 }
 
 // One element block per workgroup (blocks in XCD-contiguous order).
-template <bool RHS, int TPT>
+template <bool RHS, int TPT, int STRIDE>
 __global__ __launch_bounds__(kTetBlock, 6) void k_kx(KxArgs A) {
     extern __shared__ double lds[];
     const int64_t b = xcd_block(blockIdx.x, A.n_blocks);
@@ -435,21 +479,33 @@ __global__ __launch_bounds__(kTetBlock, 6) void k_kx(KxArgs A) {
     kx_records<TPT>(A, b, rec);  // issued first: its latency overlaps the staging
     const int32_t off = A.boff[b];
     const int32_t nn = A.boff[b + 1] - off;
-    const bool has_dir = kx_stage<RHS>(A, lds, off, nn);
+    const bool has_dir = kx_stage<RHS, STRIDE>(A, lds, off, nn);
     __syncthreads();
-    kx_tets<RHS, TPT>(A, lds, nn, has_dir, rec);
+    kx_tets<RHS, TPT, STRIDE>(A, lds, nn, has_dir, rec);
     __syncthreads();
-    kx_scatter<RHS>(A, lds, off, nn);
+    kx_scatter<RHS, STRIDE>(A, lds, off, nn);
 }
+
+// Fixed LDS stride for blocks of kTetBlock * TPT tets: above the node count of
+// such blocks on tetrahedral meshes of Kuhn or similar quality (about 0.33
+// nodes per tet for large blocks). Blocks with more nodes take the kernel with
+// the block's own node count as stride.
+constexpr int kx_fixed_stride(int tpt) { return tpt == 1 ? 129 : tpt == 2 ? 193 : tpt == 4 ? 385 : 705; }
 
 template <bool RHS>
 static void launch_kx_t(hipStream_t s, eqs_ctx* c, const double* yfree, double t, double* out) {
     const KxArgs A{c->n_tets, c->n_blocks, c->d_tpack, c->d_boff, c->d_bnodes, c->d_cx, c->d_cy, c->d_cz, c->d_mats,
                    yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out};
-    const size_t lds = sizeof(double) * 6 * (size_t)c->max_block_nodes;
     const dim3 b(kTetBlock), g((unsigned)c->n_blocks);
-#define EQS_KX(TPT_) EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx<RHS, TPT_>), g, b, lds, s, A)
-    switch (c->tet_tpt) {
+    const int tpt = c->tet_tpt;
+    const bool fixed = tpt >= 1 && c->max_block_nodes <= kx_fixed_stride(tpt);
+    const size_t lds = sizeof(double) * 6 * (size_t)(fixed ? kx_fixed_stride(tpt) : c->max_block_nodes);
+#define EQS_KX(TPT_)                                                                                           \
+    do {                                                                                                       \
+        if (fixed) EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx<RHS, TPT_, kx_fixed_stride(TPT_)>), g, b, lds, s, A); \
+        else EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx<RHS, TPT_, 0>), g, b, lds, s, A);                    \
+    } while (0)
+    switch (tpt) {
         case 1: EQS_KX(1); break;
         case 2: EQS_KX(2); break;
         case 4: EQS_KX(4); break;
@@ -493,15 +549,16 @@ static unsigned sell_grid(const Sell<T>& A) {
     return (unsigned)(((int64_t)A.n_slices * kSlice + kBlock - 1) / kBlock);
 }
 
-// y = A x  or  y += A x
-template <typename T>
+// y = A x  or  y += A x (L lanes per row)
+template <int L, typename T>
 __global__ __launch_bounds__(256) void k_sell_mv(SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
                                                   const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
-    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= A.n_slices * 64) return;
-    const T v = sell_row(A, row, x);
-    if (row < A.n_rows) y[row] = acc ? y[row] + v : v;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)A.n_slices * 64) return;  // whole wavefronts leave together
+    const int32_t row = sell_row_of<L>(g);
+    const T v = sell_row<L>(A, g, row, x);
+    if ((g & (L - 1)) == 0 && row < A.n_rows) y[row] = acc ? y[row] + v : v;
 }
 
 __global__ __launch_bounds__(256) void k_spmv64(SellView<double> A, const double* __restrict__ x,
@@ -521,15 +578,16 @@ void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double
 //   x = omega D^{-1} b,   res = b - A x = b - (A omega D^{-1}) b,
 // the last product with the stored pre-smoothing values a_ij omega / a_jj,
 // so rows gather b only.
-template <typename T, typename TB>
+template <int L, typename T, typename TB>
 __global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> As, const T* __restrict__ dinv, T omega,
                                                         const TB* __restrict__ b, T* __restrict__ x,
                                                         T* __restrict__ res, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
-    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= As.n_slices * 64) return;
-    const T acc = sell_row(As, row, b);
-    if (row < As.n_rows) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)As.n_slices * 64) return;
+    const int32_t row = sell_row_of<L>(g);
+    const T acc = sell_row<L>(As, g, row, b);
+    if ((g & (L - 1)) == 0 && row < As.n_rows) {
         const T bi = (T)b[row];
         x[row] = omega * dinv[row] * bi;
         res[row] = bi - acc;
@@ -540,19 +598,21 @@ __global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> As, const T* 
 // output is CG's z (FP64) and the block partials of r.z and r.z_old (the
 // Polak-Ribiere numerator) are produced per instance (pair layout, see
 // InstMap); z_old is read before it is overwritten.
-template <typename T, typename TB, typename TO, bool DOT>
+template <int L, typename T, typename TB, typename TO, bool DOT>
 __global__ __launch_bounds__(256) void k_postsmooth(SellView<T> A, const T* __restrict__ dinv, T omega,
                                                      const TB* __restrict__ b, const T* __restrict__ x,
                                                      TO* __restrict__ out, InstMap m, double* __restrict__ part_rz,
                                                      double* __restrict__ part_rzold,
                                                      const int32_t* __restrict__ stop) {
+    static_assert(!DOT || L == 1, "CG partials are produced by the one-lane-per-row finest level");
     __shared__ double sh[4];
     if (stop && *stop) return;
-    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t row = sell_row_of<L>(g);
     double rz = 0.0, rzo = 0.0;
-    if (row < A.n_slices * 64) {
-        const T ax = sell_row(A, row, x);
-        if (row < A.n_rows) {
+    if (g < (int64_t)A.n_slices * 64) {
+        const T ax = sell_row<L>(A, g, row, x);
+        if ((g & (L - 1)) == 0 && row < A.n_rows) {
             const T v = x[row] + omega * dinv[row] * ((T)b[row] - ax);
             if (DOT) {
                 const double ri = (double)b[row];
@@ -595,13 +655,6 @@ template <typename T>
 static CsrView<T> scview(const Level<T>& lv) {
     CsrView<T> v = cview(lv.A);
     v.val = lv.sval;
-    return v;
-}
-
-template <int L, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
     return v;
 }
 
@@ -675,6 +728,14 @@ static unsigned csr_grid(const SpMat<T>& A) {
     return (unsigned)(((int64_t)A.n_rows * A.lanes + kBlock - 1) / kBlock);
 }
 
+#define EQS_SELL_LANES_SWITCH(Lvar, CALL)                 \
+    switch (Lvar) {                                       \
+        case 2: { constexpr int L_ = 2; CALL; } break;    \
+        case 4: { constexpr int L_ = 4; CALL; } break;    \
+        case 8: { constexpr int L_ = 8; CALL; } break;    \
+        default: { constexpr int L_ = 1; CALL; } break;   \
+    }
+
 #define EQS_LANES_SWITCH(Lvar, CALL) \
     switch (Lvar) {                  \
         case 2: { constexpr int L_ = 2; CALL; } break;   \
@@ -688,7 +749,8 @@ static unsigned csr_grid(const SpMat<T>& A) {
 template <typename T>
 static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int acc, const int32_t* stop) {
     if (A.fmt == FMT_SELL) {
-        hipLaunchKernelGGL(k_sell_mv<T>, dim3(sell_grid(A.sell)), dim3(kBlock), 0, s, view(A.sell), x, y, acc, stop);
+        EQS_SELL_LANES_SWITCH(A.sell.lanes, hipLaunchKernelGGL((k_sell_mv<L_, T>), dim3(sell_grid(A.sell)),
+                                                               dim3(kBlock), 0, s, view(A.sell), x, y, acc, stop));
     } else {
         EQS_LANES_SWITCH(A.lanes, hipLaunchKernelGGL((k_csr_mv<L_, T>), dim3(csr_grid(A)), dim3(kBlock), 0, s,
                                                      cview(A), x, y, acc, stop));
@@ -698,8 +760,10 @@ static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int ac
 template <typename T, typename TB>
 static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, const int32_t* stop) {
     if (lv.A.fmt == FMT_SELL) {
-        hipLaunchKernelGGL((k_presmooth_res<T, TB>), dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s, sview(lv),
-                           (const T*)lv.dinv, (T)lv.omega, b, lv.x, lv.res, stop);
+        EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
+                              hipLaunchKernelGGL((k_presmooth_res<L_, T, TB>), dim3(sell_grid(lv.A.sell)),
+                                                 dim3(kBlock), 0, s, sview(lv), (const T*)lv.dinv, (T)lv.omega, b,
+                                                 lv.x, lv.res, stop));
     } else {
         EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_presmooth_res<L_, T, TB>), dim3(csr_grid(lv.A)),
                                                         dim3(kBlock), 0, s, scview(lv), (const T*)lv.dinv,
@@ -711,9 +775,10 @@ static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, con
 template <typename T>
 static void launch_postsmooth(hipStream_t s, const Level<T>& lv, const T* b, const T* x, T* out, const int32_t* stop) {
     if (lv.A.fmt == FMT_SELL) {
-        hipLaunchKernelGGL((k_postsmooth<T, T, T, false>), dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
-                           view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, b, x, out, InstMap{}, nullptr, nullptr,
-                           stop);
+        EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
+                              hipLaunchKernelGGL((k_postsmooth<L_, T, T, T, false>), dim3(sell_grid(lv.A.sell)),
+                                                 dim3(kBlock), 0, s, view(lv.A.sell), (const T*)lv.dinv,
+                                                 (T)lv.omega, b, x, out, InstMap{}, nullptr, nullptr, stop));
     } else {
         EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_postsmooth<L_, T, T, T>), dim3(csr_grid(lv.A)),
                                                         dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
@@ -813,7 +878,7 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         Level<T>& lv = h.lv[l];
         if (l == 0) {
             // the finest operator is always SELL-64 (see tuned_spmat)
-            EQS_LAUNCH_TIMED(c, EQS_KCLASS_PRESMOOTH0, (k_presmooth_res<T, double>), dim3(sell_grid(lv.A.sell)), b, 0,
+            EQS_LAUNCH_TIMED(c, EQS_KCLASS_PRESMOOTH0, (k_presmooth_res<1, T, double>), dim3(sell_grid(lv.A.sell)), b, 0,
                              s, sview(lv), (const T*)lv.dinv, (T)lv.omega, r, lv.x, lv.res, stop);
         } else {
             launch_presmooth<T, T>(s, lv, (const T*)lv.b, stop);
@@ -835,11 +900,11 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         } else {
             // the finest operator is always SELL-64 (see tuned_spmat)
             if (part_rz)
-                EQS_LAUNCH_TIMED(c, EQS_KCLASS_POSTSMOOTH0, (k_postsmooth<T, double, double, true>),
+                EQS_LAUNCH_TIMED(c, EQS_KCLASS_POSTSMOOTH0, (k_postsmooth<1, T, double, double, true>),
                                  dim3(sell_grid(lv.A.sell)), b, 0, s, view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega,
                                  r, (const T*)lv.x, z, inst_map(c), part_rz, part_rzold, stop);
             else
-                EQS_LAUNCH_TIMED(c, EQS_KCLASS_POSTSMOOTH0, (k_postsmooth<T, double, double, false>),
+                EQS_LAUNCH_TIMED(c, EQS_KCLASS_POSTSMOOTH0, (k_postsmooth<1, T, double, double, false>),
                                  dim3(sell_grid(lv.A.sell)), b, 0, s, view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega,
                                  r, (const T*)lv.x, z, InstMap{}, nullptr, nullptr, stop);
         }

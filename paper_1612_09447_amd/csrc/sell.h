@@ -1,6 +1,10 @@
-// SELL-64 rows on the device: slices of 64 rows (one wavefront), each stored
+// SELL rows on the device: slices of one wavefront (64 lanes) each, stored
 // column-major with the slice's longest row, so lane l of a wavefront reads
-// entry k of row 64 s + l at sptr[s] + 64 k + l (unit stride across lanes).
+// its entry k at sptr[s] + 64 k + l (unit stride across lanes). With L lanes
+// per row a slice holds 64 / L rows: lane l serves row 64 s / L + l / L and
+// takes the row's entries l % L, l % L + L, ... (long rows of coarse AMG
+// operators then need 1/L as many sequential loads); the L partial sums are
+// combined by cross-lane shuffles.
 // Column ids are either absolute (col, 32-bit) or, when every stored entry
 // lies within 32767 of offset_base(row), 16-bit offsets from it (d16): 6
 // instead of 8 bytes per FP32 entry, 10 instead of 12 per FP64 entry.
@@ -12,6 +16,20 @@
 #include "eqs_internal.h"
 
 namespace eqs {
+
+// Sum over the L lanes of an aligned lane group (result in every lane).
+template <int L, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
+    return v;
+}
+
+// The row served by global thread g of a SELL kernel with L lanes per row.
+template <int L>
+__device__ __forceinline__ int32_t sell_row_of(int64_t g) {
+    return (int32_t)((g >> 6) * (64 / L) + ((g & 63) / L));
+}
 
 template <typename T>
 struct SellView {
@@ -27,14 +45,16 @@ static inline SellView<T> view(const Sell<T>& A) {
     return SellView<T>{A.sptr, A.col, A.d16, A.val, A.n_rows, A.n_slices, A.n_cols};
 }
 
-// sum_k a_{row,k} f(col_k) over the stored entries of `row` (rows past n_rows
-// but inside the last slice see padding only). Entries are taken in groups of
-// 8 whose loads carry no branch: positions past the row's width re-read its
-// last entry (a cache hit) and their terms are dropped by a select, so all
-// loads and gathers of a group are in flight together. The sum runs in k order.
-template <typename T, typename F>
-__device__ __forceinline__ T sell_accum(const SellView<T>& A, int32_t row, F f) {
-    const int32_t s = row >> 6, l = row & 63;
+// sum_k a_{row,k} f(col_k) over the stored entries of `row` served by global
+// thread g (rows past n_rows but inside the last slice see padding only).
+// Entries are taken in groups of 8 whose loads carry no branch: positions
+// past the slice's width re-read its last entry (a cache hit) and their terms
+// are dropped by a select, so all loads and gathers of a group are in flight
+// together. Each lane sums in k order; with L > 1 the lane sums are then
+// combined by group_sum (every lane of the group gets the row's sum).
+template <int L, typename T, typename F>
+__device__ __forceinline__ T sell_accum(const SellView<T>& A, int64_t g, int32_t row, F f) {
+    const int32_t s = (int32_t)(g >> 6), l = (int32_t)(g & 63);
     const int32_t beg = A.sptr[s];
     const int32_t w = (A.sptr[s + 1] - beg) >> 6;  // uniform across the wavefront
     const T* vp = A.val + beg + l;
@@ -66,12 +86,18 @@ __device__ __forceinline__ T sell_accum(const SellView<T>& A, int32_t row, F f) 
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc += (k0 + u < w) ? t[u] : T(0);
     }
-    return acc;
+    return group_sum<L>(acc);
 }
 
+template <int L, typename T, typename TX>
+__device__ __forceinline__ T sell_row(const SellView<T>& A, int64_t g, int32_t row, const TX* __restrict__ x) {
+    return sell_accum<L>(A, g, row, [&](int32_t j) { return (T)x[j]; });
+}
+
+// One lane per row (thread index = row).
 template <typename T, typename TX>
 __device__ __forceinline__ T sell_row(const SellView<T>& A, int32_t row, const TX* __restrict__ x) {
-    return sell_accum(A, row, [&](int32_t j) { return (T)x[j]; });
+    return sell_row<1>(A, row, row, x);
 }
 
 }  // namespace eqs

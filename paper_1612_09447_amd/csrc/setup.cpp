@@ -509,38 +509,48 @@ static T* upload_vec(eqs_ctx* c, const std::vector<T>& v) {
 }
 
 template <typename T>
-Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A) {
+Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A, int lanes) {
+    if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) fail(EQS_ERR_STATE, "SELL lanes per row must be 1, 2, 4 or 8");
+    const int32_t rows_per = kSlice / lanes;  // rows of one slice
     Sell<T> S;
     S.n_rows = A.n_rows;
     S.n_cols = A.n_cols;
-    S.n_slices = (A.n_rows + kSlice - 1) / kSlice;
+    S.lanes = lanes;
+    S.n_slices = (A.n_rows + rows_per - 1) / rows_per;
     std::vector<int32_t> sptr(S.n_slices + 1, 0);
     for (int32_t s = 0; s < S.n_slices; ++s) {
-        int32_t w = 0;
-        for (int32_t r = s * kSlice; r < std::min(A.n_rows, (s + 1) * kSlice); ++r)
-            w = std::max(w, A.ptr[r + 1] - A.ptr[r]);
+        int32_t w = 0;  // entries per lane
+        for (int32_t r = s * rows_per; r < std::min(A.n_rows, (s + 1) * rows_per); ++r)
+            w = std::max(w, (A.ptr[r + 1] - A.ptr[r] + lanes - 1) / lanes);
         int64_t next = (int64_t)sptr[s] + (int64_t)w * kSlice;
         if (next > INT32_MAX) fail(EQS_ERR_INVALID_ARG, "matrix too large for SELL offsets");
         sptr[s + 1] = (int32_t)next;
     }
     S.stored = sptr[S.n_slices];
+    // lane l of slice s serves row s * rows_per + l / lanes and holds the
+    // row's entries l % lanes + lanes * k, k = 0 .. w-1
     std::vector<int32_t> col(S.stored, 0);
     std::vector<T> val(S.stored, T(0));
     for (int32_t s = 0; s < S.n_slices; ++s) {
         const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
         for (int32_t l = 0; l < kSlice; ++l) {
-            const int32_t r = s * kSlice + l;
+            const int32_t r = s * rows_per + l / lanes, part = l % lanes;
             int32_t pad_col = 0;
             int32_t len = 0;
             if (r < A.n_rows) {
                 len = A.ptr[r + 1] - A.ptr[r];
-                for (int32_t k = 0; k < len; ++k) {
-                    col[sptr[s] + (int64_t)k * kSlice + l] = A.col[A.ptr[r] + k];
-                    val[sptr[s] + (int64_t)k * kSlice + l] = (T)A.val[A.ptr[r] + k];
-                }
                 if (len > 0) pad_col = A.col[A.ptr[r] + len - 1];
             }
-            for (int32_t k = len; k < w; ++k) col[sptr[s] + (int64_t)k * kSlice + l] = pad_col;
+            for (int32_t k = 0; k < w; ++k) {
+                const int64_t at = sptr[s] + (int64_t)k * kSlice + l;
+                const int32_t e = k * lanes + part;
+                if (e < len) {
+                    col[at] = A.col[A.ptr[r] + e];
+                    val[at] = (T)A.val[A.ptr[r] + e];
+                } else {
+                    col[at] = pad_col;
+                }
+            }
         }
     }
     // 16-bit offsets from offset_base(row) when every stored column allows
@@ -552,7 +562,7 @@ Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A) {
         for (int32_t s = 0; s < S.n_slices && fits; ++s) {
             const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
             for (int32_t l = 0; l < kSlice && fits; ++l) {
-                const int32_t r = s * kSlice + l;
+                const int32_t r = s * rows_per + l / lanes;
                 const int64_t base = offset_base(r, A.n_rows, A.n_cols);
                 for (int32_t k = 0; k < w; ++k) {
                     const int64_t at = sptr[s] + (int64_t)k * kSlice + l;
@@ -573,8 +583,8 @@ Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A) {
     return S;
 }
 
-template Sell<double> to_sell<double>(eqs_ctx*, const Csr<double>&);
-template Sell<float> to_sell<float>(eqs_ctx*, const Csr<double>&);
+template Sell<double> to_sell<double>(eqs_ctx*, const Csr<double>&, int);
+template Sell<float> to_sell<float>(eqs_ctx*, const Csr<double>&, int);
 
 // CSR column ids: 16-bit offsets from offset_base(row) when every entry
 // allows, else absolute.
@@ -612,7 +622,7 @@ SpMat<T> to_spmat(eqs_ctx* c, const Csr<double>& A) {
     const double mean = A.n_rows ? (double)A.nnz() / A.n_rows : 0.0;
     if (mean <= 16.0) {
         S.fmt = FMT_SELL;
-        S.sell = to_sell<T>(c, A);
+        S.sell = to_sell<T>(c, A, 1);
         return S;
     }
     S.fmt = FMT_CSR;
@@ -642,8 +652,9 @@ static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
     S = SpMat<T>{};
 }
 
-// Autotuner: upload the operator in every candidate layout (SELL-64, CSR with
-// L = 2..64 lanes per row up to about twice the mean row length), time y = A x
+// Autotuner: upload the operator in every candidate layout (SELL with 1 lane
+// per row, and with 2, 4, 8 while each lane keeps about two entries or more;
+// CSR with L = 2..64 lanes per row up to about twice the mean row length), time y = A x
 // with HIP events on the context's stream (median of 5 after 2 warm-ups) and
 // keep the fastest.
 template <typename T>
@@ -652,9 +663,32 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
         SpMat<T> S;
         S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
         S.fmt = FMT_SELL;
-        S.sell = to_sell<T>(c, A);
+        S.sell = to_sell<T>(c, A, 1);
         c->tune_log += std::string(what) + ": sell64 (finest level), " +
                        (S.sell.d16 ? "16-bit column offsets\n" : "32-bit columns\n");
+        return S;
+    }
+    if (c->force_layout >= 0) {
+        SpMat<T> S;
+        if (c->force_layout == 0) {
+            S = to_spmat<T>(c, A);
+            if (S.fmt == FMT_SELL) {  // short rows: CSR with 2 lanes
+                free_spmat(c, S);
+                S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
+                S.fmt = FMT_CSR;
+                S.lanes = 2;
+                std::vector<T> v(A.val.size());
+                for (size_t k = 0; k < v.size(); ++k) v[k] = (T)A.val[k];
+                S.rowptr = upload_vec(c, A.ptr);
+                upload_csr_cols(c, S, A);
+                S.val = upload_vec(c, v);
+            }
+        } else {
+            S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
+            S.fmt = FMT_SELL;
+            S.sell = to_sell<T>(c, A, c->force_layout);
+        }
+        c->tune_log += std::string(what) + ": layout set by EQS_LAYOUT\n";
         return S;
     }
     if (!c->autotune || A.n_rows == 0) return to_spmat<T>(c, A);
@@ -679,12 +713,13 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
             free_spmat(c, cand);
         }
     };
-    {
+    for (int L = 1; L <= 8; L *= 2) {
+        if (L > 1 && mean < 2.0 * L) break;  // lanes with about one entry or less
         SpMat<T> S;
         S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
         S.fmt = FMT_SELL;
-        S.sell = to_sell<T>(c, A);
-        consider(S, S.sell.d16 ? "sell64/i16" : "sell64");
+        S.sell = to_sell<T>(c, A, L);
+        consider(S, std::string("sell64") + (L > 1 ? "x" + std::to_string(L) : "") + (S.sell.d16 ? "/i16" : ""));
     }
     for (int L = 2; L <= 64; L *= 2) {
         if (L > 2 && L / 2 > 2.0 * mean) break;
@@ -717,7 +752,7 @@ static T* scaled_values(eqs_ctx* c, const SpMat<T>& S, const Csr<double>& A, con
     Csr<double> As = A;
     for (size_t k = 0; k < As.val.size(); ++k) As.val[k] = A.val[k] * omega / d[A.col[k]];
     if (S.fmt == FMT_SELL) {
-        Sell<T> t = to_sell<T>(c, As);
+        Sell<T> t = to_sell<T>(c, As, S.sell.lanes);
         dev_free(c, t.sptr);
         dev_free(c, t.col);
         dev_free(c, t.d16);
@@ -947,7 +982,7 @@ void upload(eqs_ctx* c) {
     c->tune_log.clear();
     Csr<double> M = assemble_M_free(c);
     c->nnz_M = M.nnz();
-    c->M = to_sell<double>(c, M);
+    c->M = to_sell<double>(c, M, 1);
     c->tune_log += std::string("M: sell64, ") + (c->M.d16 ? "16-bit column offsets\n" : "32-bit columns\n");
     AmgHost ah = build_sa_amg(M, c->amg);
     if (c->amg.precision == EQS_PREC_FP32) upload_hierarchy<float>(c, ah, c->h32, nullptr);

@@ -165,6 +165,34 @@ def test_preconditioner_symmetric_positive(prec, tol):
             e = e_new
 
 
+@pytest.mark.parametrize("prec,tol", [(EQS_PREC_FP64, 1e-12), (EQS_PREC_FP32, 2e-5)])
+def test_preconditioner_same_in_every_layout(prec, tol, monkeypatch):
+    """Each storage layout of the coarse operators (SELL with 1, 2, 4, 8 lanes
+    per row, CSR with lanes) gives the same V-cycle up to summation order."""
+    case = inclusion_case(14, 4)
+    n = None
+    outs = {}
+    X = None
+    for lay in ("sell1", "sell2", "sell4", "sell8", "csr"):
+        monkeypatch.setenv("EQS_LAYOUT", lay)
+        with ctx_for(case, precision=prec, coarse_max=24) as c:
+            info = c.info()
+            assert info["n_levels"] >= 3, info  # coarse levels smooth in the forced layout
+            assert "layout set by EQS_LAYOUT" in c.describe()
+            if X is None:
+                n = info["n_free"]
+                X = np.random.default_rng(7).normal(size=n)
+            z = torch.zeros(n, dtype=torch.float64, device=DEV)
+            c.apply_preconditioner(T(X), z)
+            outs[lay] = N(z)
+            print(f"[layout] prec={prec} {lay} levels={info['n_levels']}", flush=True)
+    for lay, z in outs.items():
+        assert relinf(z, outs["sell1"]) <= tol, lay
+    monkeypatch.setenv("EQS_LAYOUT", "sell3")
+    with pytest.raises(EqsError):
+        Context(0, torch.cuda.current_stream(DEV))
+
+
 # ------------------------------------------------------------------ solve
 @pytest.mark.parametrize("prec", [EQS_PREC_FP64, EQS_PREC_FP32])
 def test_solve_M_matches_dense(prec):
