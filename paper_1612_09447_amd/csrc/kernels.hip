@@ -108,48 +108,35 @@ __device__ __forceinline__ void inst_blocks(const InstMap& m, int32_t i, int32_t
 
 // Sums over blocks lo..hi (inclusive) of the first partial of NP arrays, by
 // the 64 lanes of one wavefront (the head block b0 is added by the caller);
-// valid in all lanes. Each lane issues 8 loads per array before it adds, so
-// a short range costs about one memory latency. The order of the additions
-// is fixed (it does not depend on timing).
+// valid in all lanes. Lanes take blocks lo + lane, lo + lane + 64, ... in
+// chunks of U whose loads carry no branch (positions past hi re-read block hi
+// and are dropped by a select), so a range of up to 64 U blocks costs one
+// memory latency. The order of the additions is fixed (it does not depend on
+// timing).
 template <int NP>
 __device__ __forceinline__ void wave_range_sums(const double* const (&parts)[NP], int32_t lo, int32_t hi,
                                                 double (&out)[NP]) {
-    constexpr int U = 8;
+    constexpr int U = 16;
     const int lane = threadIdx.x & 63;
-    double acc[NP][U];
+    double acc[NP];
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[p][u] = 0.0;
-    int32_t b = lo + lane;
-    for (; b + 64 * (U - 1) <= hi; b += 64 * U) {
+    for (int p = 0; p < NP; ++p) acc[p] = 0.0;
+    for (int32_t b = lo + lane; b <= hi; b += 64 * U) {  // the lane's next chunk starts in range
         double t[NP][U];
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int u = 0; u < U; ++u) {
+            const int32_t bc = min(b + 64 * u, hi);
 #pragma unroll
-            for (int u = 0; u < U; ++u) t[p][u] = parts[p][2 * (int64_t)(b + 64 * u)];
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int u = 0; u < U; ++u) acc[p][u] += t[p][u];
-    }
-    // tail: fewer than U blocks left for this lane; positions past hi re-read
-    // block hi and are dropped by a select
-    if (b <= hi) {
-#pragma unroll
-        for (int u = 0; u < U - 1; ++u) {
-            const int32_t bb = b + 64 * u;
-            const int32_t bc = min(bb, hi);
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const double t = parts[p][2 * (int64_t)bc];
-                acc[p][u] += (bb <= hi) ? t : 0.0;
-            }
+            for (int p = 0; p < NP; ++p) t[p][u] = parts[p][2 * (int64_t)bc];
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) acc[p] += (b + 64 * u <= hi) ? t[p][u] : 0.0;
     }
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        double v = ((acc[p][0] + acc[p][1]) + (acc[p][2] + acc[p][3])) + ((acc[p][4] + acc[p][5]) + (acc[p][6] + acc[p][7]));
+        double v = acc[p];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         out[p] = v;
     }
@@ -738,6 +725,7 @@ static unsigned csr_grid(const SpMat<T>& A) {
 
 #define EQS_LANES_SWITCH(Lvar, CALL) \
     switch (Lvar) {                  \
+        case 1: { constexpr int L_ = 1; CALL; } break;   \
         case 2: { constexpr int L_ = 2; CALL; } break;   \
         case 4: { constexpr int L_ = 4; CALL; } break;   \
         case 8: { constexpr int L_ = 8; CALL; } break;   \

@@ -654,7 +654,8 @@ static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
 
 // Autotuner: upload the operator in every candidate layout (SELL with 1 lane
 // per row, and with 2, 4, 8 while each lane keeps about two entries or more;
-// CSR with L = 2..64 lanes per row up to about twice the mean row length), time y = A x
+// CSR with L = 2..64 lanes per row up to about twice the mean row length, and
+// with one lane per row for rows of up to 8 entries on average), time y = A x
 // with HIP events on the context's stream (median of 5 after 2 warm-ups) and
 // keep the fastest.
 template <typename T>
@@ -721,7 +722,7 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
         S.sell = to_sell<T>(c, A, L);
         consider(S, std::string("sell64") + (L > 1 ? "x" + std::to_string(L) : "") + (S.sell.d16 ? "/i16" : ""));
     }
-    for (int L = 2; L <= 64; L *= 2) {
+    for (int L = (mean <= 8.0 ? 1 : 2); L <= 64; L *= 2) {
         if (L > 2 && L / 2 > 2.0 * mean) break;
         SpMat<T> S;
         S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();

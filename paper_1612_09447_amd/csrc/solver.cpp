@@ -65,8 +65,8 @@ void release_graphs(eqs_ctx* c) {
 }
 
 // Solve M y = rhs for every instance to its own rel-res rtol. The host
-// enqueues iteration k+1 before it waits for iteration k and reads only the
-// "all done" flag of the pinned summary. When every instance has converged on
+// enqueues iteration k+1 before it waits for iteration k (unless k is expected
+// to converge) and reads only the pinned summary. When every instance has converged on
 // its recursive residual, the true residuals are checked; instances that
 // disagree restart from them. Aggregated stats: max iterations, worst status,
 // max relres; per-instance results are in c->inst_iters / c->inst_relres.
@@ -85,20 +85,38 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
     for (;;) {
         int64_t used0[EQS_KCLASS_COUNT];
         for (int k = 0; k < EQS_KCLASS_COUNT; ++k) used0[k] = c->prof_used[k];
+        // Iteration k+1 is enqueued before the host waits for iteration k, so
+        // the GPU does not wait for the host; only when iteration k is expected
+        // to converge (the last two residuals the host has seen, extrapolated
+        // geometrically, reach rtol) does the host wait for k first, so that
+        // no iteration is launched past convergence.
+        double rel_prev = -1.0, rel_last = -1.0;
+        run_iteration(c, y, prec);
+        EQS_HIP(hipEventRecord(c->ev[0], s));
         for (int64_t k = 0;; ++k) {
-            run_iteration(c, y, prec);
-            EQS_HIP(hipEventRecord(c->ev[k & 1], s));
-            if (k >= 1) {
-                EQS_HIP(hipEventSynchronize(c->ev[(k - 1) & 1]));
-                if (((volatile PcgSummary*)c->h_sum)->all_done) break;
+            const bool last = k + 1 > (int64_t)maxit + 2;  // the device stops itself at maxit
+            bool ahead = !last;
+            if (ahead && rel_last > 0.0 && rel_prev > rel_last && rel_last * (rel_last / rel_prev) <= rtol)
+                ahead = false;
+            if (ahead) {
+                run_iteration(c, y, prec);
+                EQS_HIP(hipEventRecord(c->ev[(k + 1) & 1], s));
             }
-            if (k > (int64_t)maxit + 2) break;  // the device stops itself at maxit
+            EQS_HIP(hipEventSynchronize(c->ev[k & 1]));
+            const volatile PcgSummary* hs = c->h_sum;
+            if (hs->all_done || last) break;
+            rel_prev = rel_last;
+            rel_last = hs->max_relres;
+            if (!ahead) {
+                run_iteration(c, y, prec);
+                EQS_HIP(hipEventRecord(c->ev[(k + 1) & 1], s));
+            }
         }
         check_launch();
-        EQS_HIP(hipStreamSynchronize(s));
         if (c->prof_mask) {
             // the launched iterations past the last one with work returned at
             // entry: their launches are not counted in the kernel-class times
+            EQS_HIP(hipStreamSynchronize(s));
             const int32_t it_now = read_summary(c).max_it;
             const int64_t worked = std::max<int64_t>(0, it_now - it_before);
             for (int k : {EQS_KCLASS_SPMV_M, EQS_KCLASS_PRESMOOTH0, EQS_KCLASS_POSTSMOOTH0, EQS_KCLASS_VCYCLE,
@@ -107,7 +125,8 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
             it_before = it_now;
         }
         // every instance is done on its recursive residual (or out of iterations,
-        // or broken down): check the true residuals; disagreeing ones restart
+        // or broken down): check the true residuals (queued behind any iteration
+        // still in flight); disagreeing ones restart
         pcg_true_residual(s, c, rhs, y);
         check_launch();
         EQS_HIP(hipStreamSynchronize(s));
