@@ -255,6 +255,8 @@ struct eqs_ctx {
 
     // device: work vectors (n_free doubles each)
     double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr;
+    double* d_mx = nullptr;  // M F of the stage solution in d_F when mx_of_F
+    bool mx_of_F = false;
     double *d_Y0 = nullptr, *d_Ya = nullptr, *d_Yb = nullptr, *d_F0 = nullptr, *d_F = nullptr;
     double *d_rhs = nullptr, *d_tmpN = nullptr, *d_tmpN2 = nullptr;  // tmpN*: n_nodes
     bool have_Flast = false;
@@ -343,10 +345,12 @@ void launch_rkc_combine(eqs_ctx* c, hipStream_t s, double* out, const double* Y0
 void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double* y);
 
 // PCG pieces (all scalar state on the device, one PcgScalars per instance)
+// mx (may be NULL): M x as stored by the residual check that ended a solve
+// from the same x; the start residual is then rhs - mx without a product.
 void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int32_t maxit, double rtol,
-              int flexible);
+              int flexible, const double* mx = nullptr);
 void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int precision);
-void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x);
+void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, double* mx_out = nullptr);
 void pcg_zero_rhs_rows(hipStream_t s, eqs_ctx* c, double* x);
 
 template <typename T>
@@ -384,7 +388,10 @@ bool prof_pair(eqs_ctx* c, int cls, hipEvent_t* e0, hipEvent_t* e1);
 void prof_release(eqs_ctx* c);
 
 // drivers (solver.cpp)
-int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st);
+// mx_in (may be NULL): M y for the incoming y (see pcg_init); mx_out (may be
+// NULL): receives M y for the returned y.
+int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st,
+            const double* mx_in = nullptr, double* mx_out = nullptr);
 int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double rtol, int32_t maxit,
              eqs_step_stats* st);
 void apply_preconditioner(eqs_ctx* c, const double* r, double* z);

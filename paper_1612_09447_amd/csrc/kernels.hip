@@ -909,10 +909,12 @@ template void vcycle<float>(hipStream_t, eqs_ctx*, Hierarchy<float>&, const doub
 // sparse products and the V-cycle act on all instances at once (block-diagonal
 // operators). Rows of an instance that is done are left untouched.
 
-// r = rhs - M x; pair partials of |r|^2 and |rhs|^2.
+// r = rhs - M x; pair partials of |r|^2 and |rhs|^2. With mx_out, M x is
+// also stored (the next solve that starts from this x then needs no product).
 __global__ __launch_bounds__(256) void k_pcg_residual(SellView<double> M, InstMap m, const double* __restrict__ rhs,
                                                        const double* __restrict__ x, double* __restrict__ r,
-                                                       double* __restrict__ part_rr, double* __restrict__ part_bb) {
+                                                       double* __restrict__ part_rr, double* __restrict__ part_bb,
+                                                       double* __restrict__ mx_out) {
     __shared__ double sh[4];
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     double rr = 0.0, bb = 0.0;
@@ -922,9 +924,33 @@ __global__ __launch_bounds__(256) void k_pcg_residual(SellView<double> M, InstMa
             const double bi = rhs[row];
             const double ri = bi - mx;
             r[row] = ri;
+            if (mx_out) mx_out[row] = mx;
             rr = ri * ri;
             bb = bi * bi;
         }
+    }
+    int32_t lo, bound;
+    block_instances(m, lo, bound);
+    store_pair(part_rr, rr, row >= bound, sh);
+    store_pair(part_bb, bb, row >= bound, sh);
+}
+
+// r = rhs - mx with mx = M x stored by the residual check that ended the
+// previous solve from the same x (the same products, so the same r); pair
+// partials as k_pcg_residual.
+__global__ __launch_bounds__(256) void k_pcg_residual_mx(InstMap m, const double* __restrict__ rhs,
+                                                          const double* __restrict__ mx, double* __restrict__ r,
+                                                          int64_t n, double* __restrict__ part_rr,
+                                                          double* __restrict__ part_bb) {
+    __shared__ double sh[4];
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0, bb = 0.0;
+    if (row < n) {
+        const double bi = rhs[row];
+        const double ri = bi - mx[row];
+        r[row] = ri;
+        rr = ri * ri;
+        bb = bi * bi;
     }
     int32_t lo, bound;
     block_instances(m, lo, bound);
@@ -1150,18 +1176,22 @@ __global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, I
 static double* part(eqs_ctx* c, int q) { return c->d_partials + (int64_t)q * 2 * c->max_blocks; }
 
 void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int32_t maxit, double rtol,
-              int flexible) {
+              int flexible, const double* mx) {
     const int64_t nb = sell_grid(c->M);
-    hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
-                       part(c, 0), part(c, 1));
+    if (mx)
+        hipLaunchKernelGGL(k_pcg_residual_mx, dim3(grid_for(c->n_free)), dim3(kBlock), 0, s, inst_map(c), rhs, mx,
+                           c->d_r, c->n_free, part(c, 0), part(c, 1));
+    else
+        hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
+                           part(c, 0), part(c, 1), (double*)nullptr);
     hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), rtol,
                        maxit, flexible, 0, c->d_sum, c->d_hsum, c->d_hscal);
 }
 
-void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x) {
+void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, double* mx_out) {
     const int64_t nb = sell_grid(c->M);
     hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
-                       part(c, 0), part(c, 1));
+                       part(c, 0), part(c, 1), mx_out);
     hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), 0.0, 0,
                        0, 1, c->d_sum, c->d_hsum, c->d_hscal);
 }

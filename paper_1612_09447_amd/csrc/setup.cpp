@@ -990,7 +990,8 @@ void upload(eqs_ctx* c) {
     else upload_hierarchy<double>(c, ah, c->h64, nullptr);
 
     auto vec = [&](int64_t n) { return (double*)dev_alloc(c, sizeof(double) * (size_t)n); };
-    c->d_r = vec(NF); c->d_z = vec(NF); c->d_p = vec(NF); c->d_q = vec(NF);
+    c->d_r = vec(NF); c->d_z = vec(NF); c->d_p = vec(NF); c->d_q = vec(NF); c->d_mx = vec(NF);
+    c->mx_of_F = false;
     c->d_Y0 = vec(NF); c->d_Ya = vec(NF); c->d_Yb = vec(NF); c->d_F0 = vec(NF); c->d_F = vec(NF);
     c->d_rhs = vec(NF); c->d_tmpN = vec(N); c->d_tmpN2 = vec(N);
     c->max_blocks = (std::max<int64_t>(N, T) + kBlock - 1) / kBlock + 1;
@@ -1037,7 +1038,8 @@ void free_device(eqs_ctx* c) {
     c->d_tpack = nullptr; c->d_bnodes = nullptr; c->d_boff = nullptr; c->n_blocks = 0; c->max_block_nodes = 0; c->n_block_nodes = 0;
     c->d_cx = c->d_cy = c->d_cz = nullptr; c->d_mats = nullptr; c->tet_tpt = 0;
     c->d_ddrive = nullptr; c->d_int_to_user = nullptr; c->d_drives = nullptr;
-    c->d_r = c->d_z = c->d_p = c->d_q = nullptr;
+    c->d_r = c->d_z = c->d_p = c->d_q = c->d_mx = nullptr;
+    c->mx_of_F = false;
     c->d_Y0 = c->d_Ya = c->d_Yb = c->d_F0 = c->d_F = nullptr;
     c->d_rhs = c->d_tmpN = c->d_tmpN2 = nullptr;
     c->d_partials = nullptr;

@@ -70,10 +70,11 @@ void release_graphs(eqs_ctx* c) {
 // its recursive residual, the true residuals are checked; instances that
 // disagree restart from them. Aggregated stats: max iterations, worst status,
 // max relres; per-instance results are in c->inst_iters / c->inst_relres.
-int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st) {
+int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st,
+            const double* mx_in, double* mx_out) {
     hipStream_t s = c->stream;
     const int prec = c->amg.precision;
-    pcg_init(s, c, rhs, y, maxit, rtol, c->amg.flexible);
+    pcg_init(s, c, rhs, y, maxit, rtol, c->amg.flexible, mx_in);
     pcg_zero_rhs_rows(s, c, y);  // instances with rhs = 0 get y = 0 (others untouched)
     check_launch();
     // Iterations are enqueued without waiting for the start's result: an
@@ -127,7 +128,7 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
         // every instance is done on its recursive residual (or out of iterations,
         // or broken down): check the true residuals (queued behind any iteration
         // still in flight); disagreeing ones restart
-        pcg_true_residual(s, c, rhs, y);
+        pcg_true_residual(s, c, rhs, y, mx_out);
         check_launch();
         EQS_HIP(hipStreamSynchronize(s));
         v = read_summary(c);
@@ -160,7 +161,10 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
     const int64_t NF = c->n_free;
 
     launch_gather(q, x_user, c->d_int_to_user, c->d_Y0, NF);
-    if (!c->have_Flast) launch_fill(q, c->d_F, 0.0, NF);
+    if (!c->have_Flast) {
+        launch_fill(q, c->d_F, 0.0, NF);
+        c->mx_of_F = false;
+    }
 
     std::fill(c->inst_iters.begin(), c->inst_iters.end(), 0);
     std::fill(c->inst_relres.begin(), c->inst_relres.end(), 0.0);
@@ -183,9 +187,13 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
             if (u == 1) S.guess_used++;
             guess_train(c);  // MLP: overlaps the solve below
         }
-        // F_j = M^{-1} r_j
+        // F_j = M^{-1} r_j. Started from F_{j-1} itself, the start residual
+        // reuses M F_{j-1} from the check that ended the previous solve.
         eqs_solve_stats ss{};
-        const int src = solve_M(c, c->d_rhs, c->d_F, rtol, maxit, &ss);
+        const bool reuse = kind == EQS_GUESS_PREVIOUS && c->mx_of_F;
+        c->mx_of_F = false;
+        const int src = solve_M(c, c->d_rhs, c->d_F, rtol, maxit, &ss, reuse ? c->d_mx : nullptr, c->d_mx);
+        c->mx_of_F = src == EQS_OK || src == EQS_ERR_NOT_CONVERGED;
         if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP || kind == EQS_GUESS_MOR) guess_after_solve(c, ss.iters);
         S.total_iters += ss.iters;
         S.max_iters = std::max(S.max_iters, ss.iters);
