@@ -83,6 +83,29 @@ def copy_probe(mib=512, reps=20):
             "GB/s": round(nbytes / times[len(times) // 2] / 1e9, 1)}
 
 
+def read_probe(mib=1024, reps=20):
+    """Bandwidth of a read-only pass (torch's sum) over `mib` MiB: the streaming
+    ceiling for kernels that mostly read, as the sparse products do."""
+    import torch
+
+    src = torch.empty(mib << 17, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for r in range(reps + 2):
+        ev[0].record()
+        src.sum()
+        ev[1].record()
+        ev[1].synchronize()
+        if r >= 2:
+            times.append(ev[0].elapsed_time(ev[1]) * 1e-3)
+    times.sort()
+    nbytes = src.numel() * 8
+    del src
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch": nbytes, "median_us": round(times[len(times) // 2] * 1e6, 2),
+            "GB/s": round(nbytes / times[len(times) // 2] / 1e9, 1)}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_hbm_traffic.txt")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1612_09447_amd", "csrc", f) for f in ("kernels.hip", "sell.h")]
 
@@ -331,7 +354,8 @@ def main():
 
     main_prec = EQS_PREC_FP32 if prec == "fp32" else EQS_PREC_FP64
     copy = copy_probe()
-    log(f"[bench] copy probe: {copy}")
+    rd = read_probe()
+    log(f"[bench] copy probe: {copy}; read probe: {rd}")
     r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess,
                 flexible=args.flexible, learned_steps=args.learned_steps, mlp_batch=args.mlp_batch)
     stages_per_s = r["stages"] / r["elapsed"]
@@ -352,6 +376,7 @@ def main():
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dominant),
                     "frac_of_copy": round(achieved / copy["GB/s"], 4),
+                    "frac_of_read": round(achieved / rd["GB/s"], 4),
                     "bytes_per_launch": per_class_bytes[dominant], "avg_launch_us": round(avg_s * 1e6, 2),
                     "timing": f"start/stop events of every launch (hipExtLaunchKernelGGL) on the context stream, "
                               f"{args.prof_steps} instrumented steps following the timed ones"}
@@ -418,6 +443,7 @@ def main():
         "roofline": roofline,
         "kernel_breakdown": breakdown,
         "copy_probe": copy,
+        "read_probe": rd,
         "fp64_plain": plain,
         "start_vectors": r["learned"] or None,
         "mixed_learned_vs_fp64": mixed_learned_vs_fp64(plain, r["learned"]),

@@ -50,7 +50,9 @@ static inline SellView<T> view(const Sell<T>& A) {
 // Entries are taken in groups of 8 whose loads carry no branch: positions
 // past the slice's width re-read its last entry (a cache hit) and their terms
 // are dropped by a select, so all loads and gathers of a group are in flight
-// together. Each lane sums in k order; with L > 1 the lane sums are then
+// together. The operator's values and column data are read once per product
+// and carry the nontemporal hint, which leaves the caches to the gathered
+// vector. Each lane sums in k order; with L > 1 the lane sums are then
 // combined by group_sum (every lane of the group gets the row's sum).
 template <int L, typename T, typename F>
 __device__ __forceinline__ T sell_accum(const SellView<T>& A, int64_t g, int32_t row, F f) {
@@ -68,16 +70,16 @@ __device__ __forceinline__ T sell_accum(const SellView<T>& A, int64_t g, int32_t
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int64_t kk = (int64_t)min(k0 + u, w - 1) * 64;
-                v[u] = vp[kk];
-                j[u] = base + (int32_t)dp[kk];
+                v[u] = __builtin_nontemporal_load(vp + kk);
+                j[u] = base + (int32_t)__builtin_nontemporal_load(dp + kk);
             }
         } else {
             const int32_t* cp = A.col + beg + l;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int64_t kk = (int64_t)min(k0 + u, w - 1) * 64;
-                v[u] = vp[kk];
-                j[u] = cp[kk];
+                v[u] = __builtin_nontemporal_load(vp + kk);
+                j[u] = __builtin_nontemporal_load(cp + kk);
             }
         }
         T t[8];
