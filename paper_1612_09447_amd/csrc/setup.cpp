@@ -653,7 +653,7 @@ static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
 }
 
 // Autotuner: upload the operator in every candidate layout (SELL with 1 lane
-// per row, and with 2, 4, 8 while each lane keeps about two entries or more;
+// per row, and with 2, 4, 8 while each lane keeps 1.5 entries or more;
 // CSR with L = 2..64 lanes per row up to about twice the mean row length, and
 // with one lane per row for rows of up to 8 entries on average), time y = A x
 // with HIP events on the context's stream (median of 5 after 2 warm-ups) and
@@ -715,7 +715,7 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
         }
     };
     for (int L = 1; L <= 8; L *= 2) {
-        if (L > 1 && mean < 2.0 * L) break;  // lanes with about one entry or less
+        if (L > 1 && mean < 1.5 * L) break;  // lanes with about one entry or less
         SpMat<T> S;
         S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
         S.fmt = FMT_SELL;
