@@ -73,9 +73,15 @@ struct InstMap {
     const int32_t* __restrict__ row_off;   // [n_inst + 1] first row of every instance
     const int32_t* __restrict__ blk_inst;  // [blocks] instance of each block's first row
     int32_t n_inst;
+    int32_t rows1;  // the row count when n_inst == 1 (no table lookups then), else -1
 };
 
 __device__ __forceinline__ void block_instances(const InstMap& m, int32_t& lo, int32_t& bound) {
+    if (m.rows1 >= 0) {
+        lo = 0;
+        bound = m.rows1;
+        return;
+    }
     lo = m.blk_inst[blockIdx.x];
     bound = m.row_off[lo + 1];
 }
@@ -94,7 +100,7 @@ __device__ __forceinline__ void store_pair(double* __restrict__ part, double v, 
 // inside instance i, so its first partial is i's; block b0 starts inside i
 // only when r0 is a multiple of 256, else i's share is its second partial.
 __device__ __forceinline__ void inst_blocks(const InstMap& m, int32_t i, int32_t& b0, int32_t& b1, int32_t& head) {
-    const int32_t r0 = m.row_off[i], r1 = m.row_off[i + 1];
+    const int32_t r0 = m.rows1 >= 0 ? 0 : m.row_off[i], r1 = m.rows1 >= 0 ? m.rows1 : m.row_off[i + 1];
     if (r1 <= r0) {
         b0 = 0;
         b1 = -1;
@@ -766,7 +772,7 @@ static void launch_postsmooth(hipStream_t s, const Level<T>& lv, const T* b, con
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
                               hipLaunchKernelGGL((k_postsmooth<L_, T, T, T, false>), dim3(sell_grid(lv.A.sell)),
                                                  dim3(kBlock), 0, s, view(lv.A.sell), (const T*)lv.dinv,
-                                                 (T)lv.omega, b, x, out, InstMap{}, nullptr, nullptr, stop));
+                                                 (T)lv.omega, b, x, out, InstMap{nullptr, nullptr, 0, -1}, nullptr, nullptr, stop));
     } else {
         EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_postsmooth<L_, T, T, T>), dim3(csr_grid(lv.A)),
                                                         dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
@@ -840,7 +846,9 @@ __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv
     }
 }
 
-static InstMap inst_map(const eqs_ctx* c) { return InstMap{c->d_inst_row, c->d_blk_inst, (int32_t)c->n_inst}; }
+static InstMap inst_map(const eqs_ctx* c) {
+    return InstMap{c->d_inst_row, c->d_blk_inst, (int32_t)c->n_inst, c->n_inst == 1 ? (int32_t)c->n_free : -1};
+}
 
 // V(1,1) cycle z = B r. r and z are FP64 (CG's vectors); the hierarchy is T.
 // With part_rz the finest post-smoothing also writes the r.z and r.z_old
@@ -894,7 +902,7 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
             else
                 EQS_LAUNCH_TIMED(c, EQS_KCLASS_POSTSMOOTH0, (k_postsmooth<1, T, double, double, false>),
                                  dim3(sell_grid(lv.A.sell)), b, 0, s, view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega,
-                                 r, (const T*)lv.x, z, InstMap{}, nullptr, nullptr, stop);
+                                 r, (const T*)lv.x, z, InstMap{nullptr, nullptr, 0, -1}, nullptr, nullptr, stop);
         }
     }
 }
@@ -1108,52 +1116,75 @@ __global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, 
     summarise(s, m.n_inst, sum, host_sum, host);
 }
 
+// The finalisers below issue their independent loads (the stop flag, the
+// instance's scalars, the partials) before any of them is waited for, and test
+// the flag only where it matters: a finaliser costs about one memory latency
+// plus the reduction, not one latency per dependent step.
+__device__ __forceinline__ PcgScalars prefetch_scalars(const PcgScalars* __restrict__ s, const InstMap& m) {
+    PcgScalars x{};
+    if ((int32_t)threadIdx.x < m.n_inst && m.n_inst <= kFinWaves) x = s[threadIdx.x];
+    return x;
+}
+// the prefetched copy serves thread i == threadIdx.x (every instance when n_inst <= kFinWaves)
+__device__ __forceinline__ PcgScalars scalars_of(const PcgScalars* __restrict__ s, const InstMap& m, int32_t i,
+                                                 const PcgScalars& pre) {
+    return (m.n_inst <= kFinWaves && i == (int32_t)threadIdx.x) ? pre : s[i];
+}
+
 // beta from r.z (Polak-Ribiere with r.z_old when flexible).
 __global__ __launch_bounds__(kFin) void k_fin_beta(PcgScalars* __restrict__ s, InstMap m,
                                                     const double* __restrict__ prz, const double* __restrict__ przold,
                                                     const int32_t* __restrict__ stop) {
-    if (*stop) return;
+    const int32_t stopped = *stop;
+    const PcgScalars pre = prefetch_scalars(s, m);
     const double* parts[2] = {prz, przold};
     for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
-        PcgScalars& x = s[i];
+        if (stopped) return;
+        PcgScalars x = scalars_of(s, m, i, pre);
         if (x.done) return;
         const double rz = v[0], rzo = v[1];
         if (!(rz > 0.0) || !isfinite(rz)) {
             x.done = 1;
             x.status = EQS_ERR_BREAKDOWN;
-            return;
+        } else {
+            if (x.fresh) x.beta = 0.0;
+            else x.beta = x.flexible ? (rz - rzo) / x.rho : rz / x.rho;
+            x.rho = rz;
         }
-        if (x.fresh) x.beta = 0.0;
-        else x.beta = x.flexible ? (rz - rzo) / x.rho : rz / x.rho;
-        x.rho = rz;
+        s[i] = x;
     });
 }
 
 __global__ __launch_bounds__(kFin) void k_fin_alpha(PcgScalars* __restrict__ s, InstMap m,
                                                      const double* __restrict__ ppq, const int32_t* __restrict__ stop) {
-    if (*stop) return;
+    const int32_t stopped = *stop;
+    const PcgScalars pre = prefetch_scalars(s, m);
     const double* parts[1] = {ppq};
     for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
-        PcgScalars& x = s[i];
+        if (stopped) return;
+        PcgScalars x = scalars_of(s, m, i, pre);
         if (x.done) return;
         const double pq = v[0];
         if (!(pq > 0.0) || !isfinite(pq)) {
             x.done = 1;
             x.status = EQS_ERR_BREAKDOWN;
-            return;
+        } else {
+            x.alpha = x.rho / pq;
+            x.fresh = 0;
         }
-        x.alpha = x.rho / pq;
-        x.fresh = 0;
+        s[i] = x;
     });
 }
 
 __global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, InstMap m,
                                                     const double* __restrict__ prr, PcgSummary* __restrict__ sum,
                                                     PcgSummary* __restrict__ host_sum, PcgScalars* __restrict__ host) {
-    if (sum->all_done) return;
+    const int32_t stopped = sum->all_done;
+    const PcgScalars pre = prefetch_scalars(s, m);
     const double* parts[1] = {prr};
     for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
-        PcgScalars& x = s[i];
+        if (stopped) return;
+        PcgScalars x = scalars_of(s, m, i, pre);
         if (x.done) return;
         const double rr = v[0];
         x.rr = rr;
@@ -1168,7 +1199,9 @@ __global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, I
             x.done = 1;
             x.status = EQS_ERR_NOT_CONVERGED;
         }
+        s[i] = x;
     });
+    if (stopped) return;  // uniform: the summary already says all done
     __syncthreads();
     summarise(s, m.n_inst, sum, host_sum, host);
 }
