@@ -33,35 +33,8 @@ namespace eqs {
 
 
 // ----------------------------------------------------------- reductions
-// Sum over a 256-thread block in a fixed order (wavefront tree, then the four
-// wavefront sums in index order); the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
-    return r;
-}
-
-// Sum of partials[0..n) by one block of kFin threads, in a fixed order; valid
-// in thread 0. sh must hold kFin / 64 doubles.
+// Threads of a finaliser block (one block per finaliser launch).
 constexpr int kFin = 1024;
-__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int64_t n, double* sh) {
-    double v = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kFin) v += part[i];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kFin / 64; ++w) r += sh[w];
-    return r;
-}
 
 // ---------------------------------------------------- instances (batches)
 // Independent instances occupy contiguous ranges of free rows. Every
@@ -86,13 +59,60 @@ __device__ __forceinline__ void block_instances(const InstMap& m, int32_t& lo, i
     bound = m.row_off[lo + 1];
 }
 
-// Thread 0 stores the block's pair of sums of v (split by `second`).
-__device__ __forceinline__ void store_pair(double* __restrict__ part, double v, bool second, double* sh) {
-    const double a = block_sum(second ? 0.0 : v, sh);
-    const double b = block_sum(second ? v : 0.0, sh);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = a;
-        part[2 * blockIdx.x + 1] = b;
+// Sums over the 256-thread block of K values per thread, each in a fixed order
+// (wavefront tree, then the four wavefront sums in index order), with one
+// barrier for all K; valid in thread 0. sh holds 4 K doubles and is used once
+// per kernel.
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* sh) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[4 * k + wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = ((sh[4 * k] + sh[4 * k + 1]) + sh[4 * k + 2]) + sh[4 * k + 3];
+}
+
+// Thread 0 stores the block's pair of sums of each v[p] into part[p] (split by
+// `second`, i.e. row >= bound). A block whose rows all lie before bound (the
+// common case: the block lies inside one instance) has a zero second sum and
+// needs only one reduction.
+constexpr int kPairSh = 16;  // doubles of shared memory store_pairs needs (NP <= 2)
+template <int NP>
+__device__ __forceinline__ void store_pairs(double* const (&part)[NP], const double (&v)[NP], bool second,
+                                            int32_t bound, double* sh) {
+    static_assert(NP >= 1 && NP <= 2, "at most two partial arrays");
+    const bool split = (int64_t)bound < (int64_t)(blockIdx.x + 1) * blockDim.x;  // uniform over the block
+    if (!split) {
+        double a[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) a[p] = v[p];
+        block_sums<NP>(a, sh);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                part[p][2 * blockIdx.x] = a[p];
+                part[p][2 * blockIdx.x + 1] = 0.0;
+            }
+    } else {
+        double a[2 * NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            a[2 * p] = second ? 0.0 : v[p];
+            a[2 * p + 1] = second ? v[p] : 0.0;
+        }
+        block_sums<2 * NP>(a, sh);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                part[p][2 * blockIdx.x] = a[2 * p];
+                part[p][2 * blockIdx.x + 1] = a[2 * p + 1];
+            }
     }
 }
 
@@ -598,7 +618,7 @@ __global__ __launch_bounds__(256) void k_postsmooth(SellView<T> A, const T* __re
                                                      double* __restrict__ part_rzold,
                                                      const int32_t* __restrict__ stop) {
     static_assert(!DOT || L == 1, "CG partials are produced by the one-lane-per-row finest level");
-    __shared__ double sh[4];
+    __shared__ double sh[kPairSh];
     if (stop && *stop) return;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t row = sell_row_of<L>(g);
@@ -618,8 +638,9 @@ __global__ __launch_bounds__(256) void k_postsmooth(SellView<T> A, const T* __re
     if (DOT) {
         int32_t lo, bound;
         block_instances(m, lo, bound);
-        store_pair(part_rz, rz, row >= bound, sh);
-        store_pair(part_rzold, rzo, row >= bound, sh);
+        double* const parts[2] = {part_rz, part_rzold};
+        const double vals[2] = {rz, rzo};
+        store_pairs<2>(parts, vals, row >= bound, bound, sh);
     }
 }
 
@@ -825,7 +846,7 @@ __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv
                                                         double* __restrict__ z, int32_t n, InstMap m,
                                                         double* __restrict__ part_rz, double* __restrict__ part_rzold,
                                                         const int32_t* __restrict__ stop) {
-    __shared__ double sh[4];
+    __shared__ double sh[kPairSh];
     if (stop && *stop) return;
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     double rz = 0.0, rzo = 0.0;
@@ -841,8 +862,9 @@ __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv
     if (DOT) {
         int32_t lo, bound;
         block_instances(m, lo, bound);
-        store_pair(part_rz, rz, i >= bound, sh);
-        store_pair(part_rzold, rzo, i >= bound, sh);
+        double* const parts[2] = {part_rz, part_rzold};
+        const double vals[2] = {rz, rzo};
+        store_pairs<2>(parts, vals, i >= bound, bound, sh);
     }
 }
 
@@ -923,7 +945,7 @@ __global__ __launch_bounds__(256) void k_pcg_residual(SellView<double> M, InstMa
                                                        const double* __restrict__ x, double* __restrict__ r,
                                                        double* __restrict__ part_rr, double* __restrict__ part_bb,
                                                        double* __restrict__ mx_out) {
-    __shared__ double sh[4];
+    __shared__ double sh[kPairSh];
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     double rr = 0.0, bb = 0.0;
     if (row < M.n_slices * 64) {
@@ -939,8 +961,9 @@ __global__ __launch_bounds__(256) void k_pcg_residual(SellView<double> M, InstMa
     }
     int32_t lo, bound;
     block_instances(m, lo, bound);
-    store_pair(part_rr, rr, row >= bound, sh);
-    store_pair(part_bb, bb, row >= bound, sh);
+    double* const parts[2] = {part_rr, part_bb};
+    const double vals[2] = {rr, bb};
+    store_pairs<2>(parts, vals, row >= bound, bound, sh);
 }
 
 // r = rhs - mx with mx = M x stored by the residual check that ended the
@@ -950,7 +973,7 @@ __global__ __launch_bounds__(256) void k_pcg_residual_mx(InstMap m, const double
                                                           const double* __restrict__ mx, double* __restrict__ r,
                                                           int64_t n, double* __restrict__ part_rr,
                                                           double* __restrict__ part_bb) {
-    __shared__ double sh[4];
+    __shared__ double sh[kPairSh];
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double rr = 0.0, bb = 0.0;
     if (row < n) {
@@ -962,8 +985,9 @@ __global__ __launch_bounds__(256) void k_pcg_residual_mx(InstMap m, const double
     }
     int32_t lo, bound;
     block_instances(m, lo, bound);
-    store_pair(part_rr, rr, row >= bound, sh);
-    store_pair(part_bb, bb, row >= bound, sh);
+    double* const parts[2] = {part_rr, part_bb};
+    const double vals[2] = {rr, bb};
+    store_pairs<2>(parts, vals, row >= bound, bound, sh);
 }
 
 // q = M z + beta q, p = z + beta p (so q = M p without a second pass); pair partials of p.q.
@@ -971,7 +995,7 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(SellView<double> M, InstMap m,
                                                    double* __restrict__ p, double* __restrict__ q,
                                                    double* __restrict__ part_pq, const PcgScalars* __restrict__ scal,
                                                    const int32_t* __restrict__ stop) {
-    __shared__ double sh[4];
+    __shared__ double sh[kPairSh];
     if (*stop) return;
     int32_t lo, bound;
     block_instances(m, lo, bound);
@@ -995,7 +1019,9 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(SellView<double> M, InstMap m,
             pq = pi * qi;
         }
     }
-    store_pair(part_pq, pq, second, sh);
+    double* const parts[1] = {part_pq};
+    const double vals[1] = {pq};
+    store_pairs<1>(parts, vals, second, bound, sh);
 }
 
 // x += alpha p, r -= alpha q; pair partials of |r|^2.
@@ -1004,7 +1030,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(InstMap m, double* __restric
                                                      int64_t n, double* __restrict__ part_rr,
                                                      const PcgScalars* __restrict__ scal,
                                                      const int32_t* __restrict__ stop) {
-    __shared__ double sh[4];
+    __shared__ double sh[kPairSh];
     if (*stop) return;
     int32_t lo, bound;
     block_instances(m, lo, bound);
@@ -1018,7 +1044,9 @@ __global__ __launch_bounds__(256) void k_pcg_update(InstMap m, double* __restric
         r[i] = ri;
         rr = ri * ri;
     }
-    store_pair(part_rr, rr, second, sh);
+    double* const parts[1] = {part_rr};
+    const double vals[1] = {rr};
+    store_pairs<1>(parts, vals, second, bound, sh);
 }
 
 // x = 0 on the rows of instances whose right-hand side is zero.
