@@ -30,7 +30,8 @@ namespace eqs {
 constexpr int kSlice = 64;   // SELL slice height = wavefront size
 constexpr int kTetBlock = 256;  // threads per element-pass workgroup
 constexpr int kMaxTetsPerThread = 8;  // element blocks hold kTetBlock * tpt tets, tpt in {1, 2, 4, 8}
-constexpr int kMaxBlockNodes = 1360;  // distinct nodes per element block: 48 B of LDS each (<= 64 KiB)
+constexpr int kMaxBlockNodes = 1360;
+constexpr int64_t kMaxCoarseR = 4 << 20;  // entries of the fused restriction + coarse solve matrix  // distinct nodes per element block: 48 B of LDS each (<= 64 KiB)
 constexpr int kBlock = 256;  // threads per block for streaming kernels
 
 // ---------------------------------------------------------------- errors
@@ -147,6 +148,10 @@ struct Level {
     double omega = 0;   // damped Jacobi weight
     T *b = nullptr, *x = nullptr, *xs = nullptr, *res = nullptr;
     T* dense_inv = nullptr;  // coarsest level only: n x n, column-major
+    // coarsest level only, when small enough: A^{-1} R of the level above
+    // (n x coarse_R_cols, row-major), so restriction and coarse solve are one product
+    T* coarse_R = nullptr;
+    int32_t coarse_R_cols = 0;
 };
 
 template <typename T>

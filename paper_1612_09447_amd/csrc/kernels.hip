@@ -840,6 +840,34 @@ __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const
     if (lane == 0) x[i] = acc;
 }
 
+// Coarsest level with the restriction folded in: x = (A^{-1} R) r, one
+// workgroup per coarse row of the dense row-major product matrix C. Each thread
+// sums its columns j = t, t + 256, ... eight at a time (loads in flight
+// together), then the block sums in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_restrict(const T* __restrict__ C, const T* __restrict__ r,
+                                                          T* __restrict__ x, int32_t n, int32_t nf,
+                                                          const int32_t* __restrict__ stop) {
+    __shared__ double sh[4];
+    if (stop && *stop) return;
+    const int32_t i = blockIdx.x;
+    const T* row = C + (int64_t)i * nf;
+    T acc = T(0);
+    for (int32_t j0 = threadIdx.x; j0 < nf; j0 += 8 * 256) {
+        T t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t j = min(j0 + u * 256, nf - 1);
+            t[u] = row[j] * r[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (j0 + u * 256 < nf) ? t[u] : T(0);
+    }
+    double v[1] = {(double)acc};
+    block_sums<1>(v, sh);
+    if (threadIdx.x == 0 && i < n) x[i] = (T)v[0];
+}
+
 // Single-level hierarchy: z = A^{-1} r with the same r.z partials as k_postsmooth.
 template <typename T, bool DOT>
 __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv, const double* __restrict__ r,
@@ -901,12 +929,17 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         } else {
             launch_presmooth<T, T>(s, lv, (const T*)lv.b, stop);
         }
-        launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, stop);
+        if (l + 1 < L - 1 || !h.lv[L - 1].coarse_R)
+            launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, stop);
     }
     {
         Level<T>& lc = h.lv[L - 1];
-        hipLaunchKernelGGL(k_coarse<T>, dim3(grid_for((int64_t)lc.n * 64)), b, 0, s, (const T*)lc.dense_inv,
-                           (const T*)lc.b, lc.x, lc.n, stop);
+        if (lc.coarse_R)  // restriction and coarse solve in one product
+            hipLaunchKernelGGL(k_coarse_restrict<T>, dim3((unsigned)lc.n), b, 0, s, (const T*)lc.coarse_R,
+                               (const T*)h.lv[L - 2].res, lc.x, lc.n, lc.coarse_R_cols, stop);
+        else
+            hipLaunchKernelGGL(k_coarse<T>, dim3(grid_for((int64_t)lc.n * 64)), b, 0, s, (const T*)lc.dense_inv,
+                               (const T*)lc.b, lc.x, lc.n, stop);
     }
     // ascend
     for (int l = L - 2; l >= 0; --l) {

@@ -790,6 +790,25 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
             std::vector<T> inv(ah.coarse_inv.size());
             for (size_t k = 0; k < inv.size(); ++k) inv[k] = (T)ah.coarse_inv[k];
             lv.dense_inv = upload_vec(c, inv);
+            // A^{-1} R of the level above, formed in FP64: the V-cycle then
+            // restricts and solves on the coarsest level in one dense product
+            if (l >= 1) {
+                const Csr<double>& R = ah.R[l - 1];
+                const int64_t n = lv.n, nf = R.n_cols;
+                if (n * nf <= kMaxCoarseR) {
+                    std::vector<double> C((size_t)(n * nf), 0.0);
+                    for (int32_t k = 0; k < R.n_rows; ++k)
+                        for (int32_t e = R.ptr[k]; e < R.ptr[k + 1]; ++e) {
+                            const double r = R.val[e];
+                            const int32_t j = R.col[e];
+                            for (int64_t i = 0; i < n; ++i) C[(size_t)(i * nf + j)] += ah.coarse_inv[(size_t)(k * n + i)] * r;
+                        }
+                    std::vector<T> Ct(C.size());
+                    for (size_t k = 0; k < C.size(); ++k) Ct[k] = (T)C[k];
+                    lv.coarse_R = upload_vec(c, Ct);
+                    lv.coarse_R_cols = (int32_t)nf;
+                }
+            }
         }
     }
 }
