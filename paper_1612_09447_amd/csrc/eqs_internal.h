@@ -148,10 +148,17 @@ struct Level {
     double omega = 0;   // damped Jacobi weight
     T *b = nullptr, *x = nullptr, *xs = nullptr, *res = nullptr;
     T* dense_inv = nullptr;  // coarsest level only: n x n, column-major
-    // coarsest level only, when small enough: A^{-1} R of the level above
-    // (n x coarse_R_cols, row-major), so restriction and coarse solve are one product
+    // coarsest level only, when small enough: the dense matrix that maps the
+    // level above to the coarse solution in one product (n x coarse_R_cols,
+    // row-major): A^{-1} R r of its residual, or, with `tail` set on the level
+    // above, A^{-1} R (I - A w D^{-1}) b of its right-hand side
     T* coarse_R = nullptr;
     int32_t coarse_R_cols = 0;
+    // level above the coarsest, when folded (`tail`): its V(1,1) visit is
+    // xs = [G Q] [b; x_coarse] after the coarse product (b and the coarsest x
+    // share one buffer)
+    bool tail = false;
+    SpMat<T> GQ;
 };
 
 template <typename T>

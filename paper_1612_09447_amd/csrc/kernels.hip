@@ -922,6 +922,7 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
     // descend
     for (int l = 0; l < L - 1; ++l) {
         Level<T>& lv = h.lv[l];
+        if (lv.tail) break;  // folded into the coarse product and [G Q] (the last level above the coarsest)
         if (l == 0) {
             // the finest operator is always SELL-64 (see tuned_spmat)
             EQS_LAUNCH_TIMED(c, EQS_KCLASS_PRESMOOTH0, (k_presmooth_res<1, T, double>), dim3(sell_grid(lv.A.sell)), b, 0,
@@ -934,9 +935,10 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
     }
     {
         Level<T>& lc = h.lv[L - 1];
-        if (lc.coarse_R)  // restriction and coarse solve in one product
+        const Level<T>& la = h.lv[L - 2];
+        if (lc.coarse_R)  // restriction (and, folded, the level above's pre-smoothing) and coarse solve in one product
             hipLaunchKernelGGL(k_coarse_restrict<T>, dim3((unsigned)lc.n), b, 0, s, (const T*)lc.coarse_R,
-                               (const T*)h.lv[L - 2].res, lc.x, lc.n, lc.coarse_R_cols, stop);
+                               (const T*)(la.tail ? la.b : la.res), lc.x, lc.n, lc.coarse_R_cols, stop);
         else
             hipLaunchKernelGGL(k_coarse<T>, dim3(grid_for((int64_t)lc.n * 64)), b, 0, s, (const T*)lc.dense_inv,
                                (const T*)lc.b, lc.x, lc.n, stop);
@@ -944,6 +946,10 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
     // ascend
     for (int l = L - 2; l >= 0; --l) {
         Level<T>& lv = h.lv[l];
+        if (lv.tail) {  // xs = G b + Q x_coarse on the stacked [b; x_coarse]
+            launch_mv<T>(s, lv.GQ, (const T*)lv.b, lv.xs, 0, stop);
+            continue;
+        }
         const T* xc = (l + 1 == L - 1) ? h.lv[l + 1].x : h.lv[l + 1].xs;
         launch_mv<T>(s, lv.P, xc, lv.x, 1, stop);
         if (l > 0) {

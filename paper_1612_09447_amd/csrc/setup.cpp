@@ -765,6 +765,9 @@ static T* scaled_values(eqs_ctx* c, const SpMat<T>& S, const Csr<double>& A, con
 }
 
 template <typename T>
+static void upload_coarse_tail(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h);
+
+template <typename T>
 static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, const double* level0_M_vals_hint) {
     (void)level0_M_vals_hint;
     const size_t L = ah.A.size();
@@ -790,27 +793,95 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
             std::vector<T> inv(ah.coarse_inv.size());
             for (size_t k = 0; k < inv.size(); ++k) inv[k] = (T)ah.coarse_inv[k];
             lv.dense_inv = upload_vec(c, inv);
-            // A^{-1} R of the level above, formed in FP64: the V-cycle then
-            // restricts and solves on the coarsest level in one dense product
-            if (l >= 1) {
-                const Csr<double>& R = ah.R[l - 1];
-                const int64_t n = lv.n, nf = R.n_cols;
-                if (n * nf <= kMaxCoarseR) {
-                    std::vector<double> C((size_t)(n * nf), 0.0);
-                    for (int32_t k = 0; k < R.n_rows; ++k)
-                        for (int32_t e = R.ptr[k]; e < R.ptr[k + 1]; ++e) {
-                            const double r = R.val[e];
-                            const int32_t j = R.col[e];
-                            for (int64_t i = 0; i < n; ++i) C[(size_t)(i * nf + j)] += ah.coarse_inv[(size_t)(k * n + i)] * r;
-                        }
-                    std::vector<T> Ct(C.size());
-                    for (size_t k = 0; k < C.size(); ++k) Ct[k] = (T)C[k];
-                    lv.coarse_R = upload_vec(c, Ct);
-                    lv.coarse_R_cols = (int32_t)nf;
-                }
-            }
         }
     }
+    upload_coarse_tail<T>(c, ah, h);
+}
+
+// The two lowest levels folded into two products (formed in FP64 here). With
+// t = L-2 (the level above the coarsest c = L-1), S = I - w D^-1 A_t and
+// T = I - A_t w D^-1, one V(1,1) visit of t with the exact coarse solve is
+//   x_c = C' b_t,            C' = A_c^-1 R_t T       (dense n_c x n_t)
+//   xs_t = G b_t + Q x_c,    G = (S + I) w D^-1 (A_t's pattern), Q = S P_t
+// so the pre-smoother, restriction, coarse solve, prolongation and
+// post-smoother of t become one dense and one sparse product, [G Q] acting on
+// the stacked vector [b_t; x_c]. Only when t is not the finest level (whose
+// post-smoother produces CG partials) and C' is small; with two levels only
+// the restriction is folded into the coarse solve (x_c = A_c^-1 R_0 r_0).
+template <typename T>
+static void upload_coarse_tail(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h) {
+    const int L = (int)h.lv.size();
+    if (L < 2) return;
+    Level<T>& lc = h.lv[L - 1];
+    const int t = L - 2;
+    const Csr<double>& R = ah.R[t];
+    const int64_t nc = lc.n, nt = R.n_cols;
+    if (nc * nt > kMaxCoarseR) return;
+    auto inv = [&](int64_t i, int64_t k) { return ah.coarse_inv[(size_t)(k * nc + i)]; };  // column-major
+    // C = A_c^-1 R_t (dense, row-major nc x nt)
+    std::vector<double> C((size_t)(nc * nt), 0.0);
+    for (int32_t k = 0; k < R.n_rows; ++k)
+        for (int32_t e = R.ptr[k]; e < R.ptr[k + 1]; ++e)
+            for (int64_t i = 0; i < nc; ++i) C[(size_t)(i * nt + R.col[e])] += inv(i, k) * R.val[e];
+    if (t == 0) {  // finest level above the coarsest: fold the restriction only
+        std::vector<T> Ct(C.size());
+        for (size_t k = 0; k < C.size(); ++k) Ct[k] = (T)C[k];
+        lc.coarse_R = upload_vec(c, Ct);
+        lc.coarse_R_cols = (int32_t)nt;
+        return;
+    }
+    Level<T>& lt = h.lv[t];
+    const Csr<double>& A = ah.A[t];
+    const Csr<double>& P = ah.P[t];
+    const std::vector<double> d = diagonal(A);
+    const double w = ah.omega[t];
+    // C' = C - w C A D^-1: row i of C A is sum_k C(i,k) A(k,:)
+    std::vector<double> Cp = C;
+    for (int32_t k = 0; k < A.n_rows; ++k)
+        for (int32_t e = A.ptr[k]; e < A.ptr[k + 1]; ++e) {
+            const int32_t j = A.col[e];
+            const double f = w * A.val[e] / d[j];
+            for (int64_t i = 0; i < nc; ++i) Cp[(size_t)(i * nt + j)] -= C[(size_t)(i * nt + k)] * f;
+        }
+    // [G Q]: row i holds G's entries (columns j < nt) then Q's nonzeros
+    // (columns nt + k), Q = P - w D^-1 A P
+    Csr<double> GQ;
+    GQ.n_rows = (int32_t)nt;
+    GQ.n_cols = (int32_t)(nt + nc);
+    GQ.ptr.assign((size_t)nt + 1, 0);
+    std::vector<double> q((size_t)nc);
+    for (int32_t i = 0; i < (int32_t)nt; ++i) {
+        for (int32_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+            const int32_t j = A.col[e];
+            const double g = (j == i ? 2.0 * w / d[i] : 0.0) - w * w * A.val[e] / (d[i] * d[j]);
+            GQ.col.push_back(j);
+            GQ.val.push_back(g);
+        }
+        std::fill(q.begin(), q.end(), 0.0);
+        for (int32_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) q[P.col[e]] += P.val[e];
+        for (int32_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+            const int32_t k = A.col[e];
+            const double f = w * A.val[e] / d[i];
+            for (int32_t u = P.ptr[k]; u < P.ptr[k + 1]; ++u) q[P.col[u]] -= f * P.val[u];
+        }
+        for (int64_t k = 0; k < nc; ++k)
+            if (q[(size_t)k] != 0.0) {
+                GQ.col.push_back((int32_t)(nt + k));
+                GQ.val.push_back(q[(size_t)k]);
+            }
+        GQ.ptr[(size_t)i + 1] = (int32_t)GQ.col.size();
+    }
+    std::vector<T> Ct(Cp.size());
+    for (size_t k = 0; k < Cp.size(); ++k) Ct[k] = (T)Cp[k];
+    lc.coarse_R = upload_vec(c, Ct);
+    lc.coarse_R_cols = (int32_t)nt;
+    lt.GQ = tuned_spmat<T>(c, GQ, ("[G Q]" + std::to_string(t)).c_str());
+    // b_t and x_c side by side: the restriction from above writes b_t, the
+    // dense product writes x_c, the sparse product reads both
+    T* bx = (T*)dev_alloc(c, sizeof(T) * (size_t)(nt + nc));
+    lt.b = bx;
+    lc.x = bx + nt;
+    lt.tail = true;
 }
 
 // Morton key of a point quantised to 21 bits per axis inside the box [lo, hi].
