@@ -80,6 +80,8 @@ int eqs_create(eqs_ctx** out, int device, void* hip_stream) {
         c->autotune = !(at && at[0] == '0');
         const char* i16 = std::getenv("EQS_INDEX16");
         c->index16 = !(i16 && i16[0] == '0');
+        const char* fo = std::getenv("EQS_FOLD");  // "0": the plain V-cycle (no folded operators)
+        c->fold = !(fo && fo[0] == '0');
         // "sell1", "sell2", "sell4", "sell8" or "csr": every AMG operator below
         // the finest level in that layout (tests compare the layouts)
         const char* lay = std::getenv("EQS_LAYOUT");

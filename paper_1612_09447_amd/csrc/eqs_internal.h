@@ -159,6 +159,10 @@ struct Level {
     // share one buffer)
     bool tail = false;
     SpMat<T> GQ;
+    // pre-smoother folded into the restriction: R holds R (I - A w D^-1), so
+    // the descent restricts b directly and the prolongation stores
+    // x = w D^-1 b + P x_coarse (levels other than the finest and the tail)
+    bool fold_pre = false;
 };
 
 template <typename T>
@@ -295,6 +299,7 @@ struct eqs_ctx {
     std::vector<std::pair<void*, size_t>> allocations;
     bool index16 = true;   // 16-bit column offsets for SELL operators whose entries allow them
     bool autotune = true;  // time the candidate layouts of every AMG operator at build time
+    bool fold = true;       // fold pre-smoothers into restrictions and the lowest two levels into two products
     int force_layout = -1;  // >= 1: SELL with that many lanes per row, 0: CSR, for every coarse operator
     std::string tune_log;  // chosen layouts, one line per operator
 

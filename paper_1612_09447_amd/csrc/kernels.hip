@@ -562,16 +562,32 @@ static unsigned sell_grid(const Sell<T>& A) {
     return (unsigned)(((int64_t)A.n_slices * kSlice + kBlock - 1) / kBlock);
 }
 
-// y = A x  or  y += A x (L lanes per row)
+// Epilogue of a product y = A x: acc 0 stores A x, 1 adds it to y, 2 stores
+// omega dinv[row] b[row] + A x (the pre-smoothed x = omega D^-1 b of a level
+// whose pre-smoother is folded into its restriction, plus the prolonged
+// correction).
+template <typename T>
+struct MvInit {
+    const T* __restrict__ dinv;
+    const T* __restrict__ b;
+    T omega;
+};
+template <typename T>
+__device__ __forceinline__ void mv_store(T* __restrict__ y, int32_t row, T v, int acc, const MvInit<T>& in) {
+    if (acc == 2) y[row] = in.omega * in.dinv[row] * in.b[row] + v;
+    else y[row] = acc ? y[row] + v : v;
+}
+
+// y = A x with the epilogue above (L lanes per row)
 template <int L, typename T>
 __global__ __launch_bounds__(256) void k_sell_mv(SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
-                                                  const int32_t* __restrict__ stop) {
+                                                  MvInit<T> in, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (int64_t)A.n_slices * 64) return;  // whole wavefronts leave together
     const int32_t row = sell_row_of<L>(g);
     const T v = sell_row<L>(A, g, row, x);
-    if ((g & (L - 1)) == 0 && row < A.n_rows) y[row] = acc ? y[row] + v : v;
+    if ((g & (L - 1)) == 0 && row < A.n_rows) mv_store(y, row, v, acc, in);
 }
 
 __global__ __launch_bounds__(256) void k_spmv64(SellView<double> A, const double* __restrict__ x,
@@ -697,14 +713,14 @@ __device__ __forceinline__ T csr_row(const CsrView<T>& A, int32_t row, int lane,
 
 template <int L, typename T>
 __global__ __launch_bounds__(256) void k_csr_mv(CsrView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
-                                                 const int32_t* __restrict__ stop) {
+                                                 MvInit<T> in, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
     if (row >= A.n_rows) return;  // whole groups leave together
     const T v = csr_row<L>(A, row, lane, [&](int32_t j) { return x[j]; });
-    if (lane == 0) y[row] = acc ? y[row] + v : v;
+    if (lane == 0) mv_store(y, row, v, acc, in);
 }
 
 template <int L, typename T, typename TB>
@@ -762,13 +778,14 @@ static unsigned csr_grid(const SpMat<T>& A) {
     }
 
 template <typename T>
-static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int acc, const int32_t* stop) {
+static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int acc, const int32_t* stop,
+                      MvInit<T> in = MvInit<T>{nullptr, nullptr, T(0)}) {
     if (A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(A.sell.lanes, hipLaunchKernelGGL((k_sell_mv<L_, T>), dim3(sell_grid(A.sell)),
-                                                               dim3(kBlock), 0, s, view(A.sell), x, y, acc, stop));
+                                                               dim3(kBlock), 0, s, view(A.sell), x, y, acc, in, stop));
     } else {
         EQS_LANES_SWITCH(A.lanes, hipLaunchKernelGGL((k_csr_mv<L_, T>), dim3(csr_grid(A)), dim3(kBlock), 0, s,
-                                                     cview(A), x, y, acc, stop));
+                                                     cview(A), x, y, acc, in, stop));
     }
 }
 
@@ -923,6 +940,10 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
     for (int l = 0; l < L - 1; ++l) {
         Level<T>& lv = h.lv[l];
         if (lv.tail) break;  // folded into the coarse product and [G Q] (the last level above the coarsest)
+        if (lv.fold_pre) {  // R holds R (I - A w D^-1): restrict b itself
+            launch_mv<T>(s, lv.R, (const T*)lv.b, h.lv[l + 1].b, 0, stop);
+            continue;
+        }
         if (l == 0) {
             // the finest operator is always SELL-64 (see tuned_spmat)
             EQS_LAUNCH_TIMED(c, EQS_KCLASS_PRESMOOTH0, (k_presmooth_res<1, T, double>), dim3(sell_grid(lv.A.sell)), b, 0,
@@ -951,7 +972,10 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
             continue;
         }
         const T* xc = (l + 1 == L - 1) ? h.lv[l + 1].x : h.lv[l + 1].xs;
-        launch_mv<T>(s, lv.P, xc, lv.x, 1, stop);
+        if (lv.fold_pre)  // x = w D^-1 b (the folded pre-smoother's result) + P xc
+            launch_mv<T>(s, lv.P, xc, lv.x, 2, stop, MvInit<T>{(const T*)lv.dinv, (const T*)lv.b, (T)lv.omega});
+        else
+            launch_mv<T>(s, lv.P, xc, lv.x, 1, stop);
         if (l > 0) {
             launch_postsmooth<T>(s, lv, (const T*)lv.b, (const T*)lv.x, lv.xs, stop);
         } else {

@@ -767,10 +767,61 @@ static T* scaled_values(eqs_ctx* c, const SpMat<T>& S, const Csr<double>& A, con
 template <typename T>
 static void upload_coarse_tail(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h);
 
+// Whether the level above the coarsest is folded with it (see upload_coarse_tail).
+static bool coarse_tail_applies(const eqs_ctx* c, const AmgHost& ah) {
+    const size_t L = ah.A.size();
+    return c->fold && L >= 3 && (int64_t)ah.A[L - 1].n_rows * ah.A[L - 2].n_rows <= kMaxCoarseR;
+}
+
+// R (I - A w D^-1) = R - w (R A) D^-1 (rows in column order): the restriction
+// of a level whose pre-smoother x = w D^-1 b, res = b - A x is folded into it.
+static Csr<double> fold_presmoother(const Csr<double>& R, const Csr<double>& A, const std::vector<double>& d,
+                                    double w) {
+    Csr<double> out;
+    out.n_rows = R.n_rows;
+    out.n_cols = R.n_cols;
+    out.ptr.assign((size_t)R.n_rows + 1, 0);
+    std::vector<double> acc((size_t)R.n_cols, 0.0);
+    std::vector<char> seen((size_t)R.n_cols, 0);
+    std::vector<int32_t> cols;
+    auto touch = [&](int32_t j) {
+        if (!seen[j]) {
+            seen[j] = 1;
+            cols.push_back(j);
+        }
+    };
+    for (int32_t i = 0; i < R.n_rows; ++i) {
+        cols.clear();
+        for (int32_t e = R.ptr[i]; e < R.ptr[i + 1]; ++e) {
+            touch(R.col[e]);
+            acc[R.col[e]] += R.val[e];
+        }
+        for (int32_t e = R.ptr[i]; e < R.ptr[i + 1]; ++e) {
+            const int32_t k = R.col[e];
+            const double rk = w * R.val[e];
+            for (int32_t f = A.ptr[k]; f < A.ptr[k + 1]; ++f) {
+                const int32_t j = A.col[f];
+                touch(j);
+                acc[j] -= rk * A.val[f] / d[j];
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        for (int32_t j : cols) {
+            out.col.push_back(j);
+            out.val.push_back(acc[j]);
+            acc[j] = 0.0;
+            seen[j] = 0;
+        }
+        out.ptr[(size_t)i + 1] = (int32_t)out.col.size();
+    }
+    return out;
+}
+
 template <typename T>
 static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, const double* level0_M_vals_hint) {
     (void)level0_M_vals_hint;
     const size_t L = ah.A.size();
+    const bool tail_ok = coarse_tail_applies(c, ah);
     h.lv.resize(L);
     for (size_t l = 0; l < L; ++l) {
         Level<T>& lv = h.lv[l];
@@ -786,9 +837,17 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
         lv.xs = (T*)dev_alloc(c, sizeof(T) * lv.n);
         lv.res = (T*)dev_alloc(c, sizeof(T) * lv.n);
         if (l + 1 < L) {
-            lv.sval = scaled_values<T>(c, lv.A, ah.A[l], d, lv.omega);
+            // levels other than the finest (whose smoothers feed CG) and the
+            // folded tail restrict b through R (I - A w D^-1)
+            const bool tail_level = tail_ok && l == (int)L - 2;
+            lv.fold_pre = c->fold && l >= 1 && !tail_level;
+            if (!lv.fold_pre) lv.sval = scaled_values<T>(c, lv.A, ah.A[l], d, lv.omega);
             lv.P = tuned_spmat<T>(c, ah.P[l], ("P" + std::to_string(l)).c_str());
-            lv.R = tuned_spmat<T>(c, ah.R[l], ("R" + std::to_string(l)).c_str());
+            if (lv.fold_pre)
+                lv.R = tuned_spmat<T>(c, fold_presmoother(ah.R[l], ah.A[l], d, lv.omega),
+                                      ("R" + std::to_string(l) + "(I-AwD^-1)").c_str());
+            else
+                lv.R = tuned_spmat<T>(c, ah.R[l], ("R" + std::to_string(l)).c_str());
         } else {
             std::vector<T> inv(ah.coarse_inv.size());
             for (size_t k = 0; k < inv.size(); ++k) inv[k] = (T)ah.coarse_inv[k];
@@ -811,7 +870,7 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
 template <typename T>
 static void upload_coarse_tail(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h) {
     const int L = (int)h.lv.size();
-    if (L < 2) return;
+    if (L < 2 || !c->fold) return;
     Level<T>& lc = h.lv[L - 1];
     const int t = L - 2;
     const Csr<double>& R = ah.R[t];

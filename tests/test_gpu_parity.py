@@ -193,6 +193,29 @@ def test_preconditioner_same_in_every_layout(prec, tol, monkeypatch):
         Context(0, torch.cuda.current_stream(DEV))
 
 
+@pytest.mark.parametrize("prec,tol", [(EQS_PREC_FP64, 1e-12), (EQS_PREC_FP32, 2e-5)])
+def test_folded_vcycle_matches_plain(prec, tol, monkeypatch):
+    """The folded operators (pre-smoothers inside the restrictions, the two
+    lowest levels as two products) give the plain V(1,1) cycle up to rounding."""
+    case = inclusion_case(14, 4)
+    outs = {}
+    X = None
+    for fold in ("0", "1"):
+        monkeypatch.setenv("EQS_FOLD", fold)
+        with ctx_for(case, precision=prec, coarse_max=8) as c:
+            info = c.info()
+            assert info["n_levels"] >= 4, info  # a folded restriction, the folded tail and the plain finest level
+            d = c.describe()
+            assert ("(I-AwD^-1)" in d and "[G Q]" in d) == (fold == "1"), d
+            if X is None:
+                X = np.random.default_rng(11).normal(size=info["n_free"])
+            z = torch.zeros(info["n_free"], dtype=torch.float64, device=DEV)
+            c.apply_preconditioner(T(X), z)
+            outs[fold] = N(z)
+            print(f"[fold] prec={prec} fold={fold} levels={info['level_rows']}", flush=True)
+    assert relinf(outs["1"], outs["0"]) <= tol
+
+
 # ------------------------------------------------------------------ solve
 @pytest.mark.parametrize("prec", [EQS_PREC_FP64, EQS_PREC_FP32])
 def test_solve_M_matches_dense(prec):
