@@ -193,20 +193,25 @@ def test_preconditioner_same_in_every_layout(prec, tol, monkeypatch):
         Context(0, torch.cuda.current_stream(DEV))
 
 
+@pytest.mark.parametrize("coarse_max,min_levels", [(8, 4), (512, 2)])
 @pytest.mark.parametrize("prec,tol", [(EQS_PREC_FP64, 1e-12), (EQS_PREC_FP32, 2e-5)])
-def test_folded_vcycle_matches_plain(prec, tol, monkeypatch):
+def test_folded_vcycle_matches_plain(prec, tol, coarse_max, min_levels, monkeypatch):
     """The folded operators (pre-smoothers inside the restrictions, the two
-    lowest levels as two products) give the plain V(1,1) cycle up to rounding."""
+    lowest levels as two products) give the plain V(1,1) cycle up to rounding,
+    on a deep hierarchy and on a two-level one."""
     case = inclusion_case(14, 4)
     outs = {}
     X = None
     for fold in ("0", "1"):
         monkeypatch.setenv("EQS_FOLD", fold)
-        with ctx_for(case, precision=prec, coarse_max=8) as c:
+        with ctx_for(case, precision=prec, coarse_max=coarse_max) as c:
             info = c.info()
-            assert info["n_levels"] >= 4, info  # a folded restriction, the folded tail and the plain finest level
+            assert info["n_levels"] >= min_levels, info
             d = c.describe()
-            assert ("(I-AwD^-1)" in d and "[G Q]" in d) == (fold == "1"), d
+            # folded: every level strictly between the finest and the tail
+            # restricts through R (I - A w D^-1); the tail needs three levels
+            assert ("(I-AwD^-1)" in d) == (fold == "1" and info["n_levels"] >= 4), d
+            assert ("[G Q]" in d) == (fold == "1" and info["n_levels"] >= 3), d
             if X is None:
                 X = np.random.default_rng(11).normal(size=info["n_free"])
             z = torch.zeros(info["n_free"], dtype=torch.float64, device=DEV)
