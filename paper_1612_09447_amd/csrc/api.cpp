@@ -80,21 +80,27 @@ int eqs_create(eqs_ctx** out, int device, void* hip_stream) {
         c->autotune = !(at && at[0] == '0');
         const char* i16 = std::getenv("EQS_INDEX16");
         c->index16 = !(i16 && i16[0] == '0');
+        const char* tv = std::getenv("EQS_TUNE_LOG");  // "all": list every layout candidate's time
+        c->tune_verbose = tv && std::string(tv) == "all";
         const char* fo = std::getenv("EQS_FOLD");  // "0": the plain V-cycle (no folded operators)
         c->fold = !(fo && fo[0] == '0');
         // "sell1", "sell2", "sell4", "sell8" or "csr": every AMG operator below
-        // the finest level in that layout (tests compare the layouts)
+        // the finest level in that layout; "sell1s" etc. also sort the rows of
+        // the operators used only in products (tests compare the layouts)
         const char* lay = std::getenv("EQS_LAYOUT");
         if (lay && lay[0]) {
             const std::string v(lay);
-            if (v == "sell1") c->force_layout = 1;
-            else if (v == "sell2") c->force_layout = 2;
-            else if (v == "sell4") c->force_layout = 4;
-            else if (v == "sell8") c->force_layout = 8;
+            const bool srt = v.size() == 6 && v.compare(0, 4, "sell") == 0 && v[5] == 's';
+            const std::string base = srt ? v.substr(0, 5) : v;
+            c->force_sorted = srt;
+            if (base == "sell1") c->force_layout = 1;
+            else if (base == "sell2") c->force_layout = 2;
+            else if (base == "sell4") c->force_layout = 4;
+            else if (base == "sell8") c->force_layout = 8;
             else if (v == "csr") c->force_layout = 0;
             else {
                 delete c;
-                need(false, "EQS_LAYOUT must be sell1, sell2, sell4, sell8 or csr");
+                need(false, "EQS_LAYOUT must be sell1, sell2, sell4, sell8 (optionally with s: rows sorted) or csr");
             }
         }
         *out = c;

@@ -67,6 +67,7 @@ struct Sell {
     int32_t* col = nullptr;     // [stored] absolute column ids, or
     int16_t* d16 = nullptr;     // [stored] column - offset_base(row) when every entry allows
     T* val = nullptr;           // [stored]
+    uint8_t* perm = nullptr;    // [n_slices * 64 / lanes] row order within 256-thread windows, or NULL
 };
 
 // A hierarchy operator in one of two layouts, chosen per matrix by timing
@@ -300,7 +301,9 @@ struct eqs_ctx {
     bool index16 = true;   // 16-bit column offsets for SELL operators whose entries allow them
     bool autotune = true;  // time the candidate layouts of every AMG operator at build time
     bool fold = true;       // fold pre-smoothers into restrictions and the lowest two levels into two products
-    int force_layout = -1;  // >= 1: SELL with that many lanes per row, 0: CSR, for every coarse operator
+    int force_layout = -1;
+    bool force_sorted = false;  // with force_layout >= 1: sorted rows where allowed
+    bool tune_verbose = false;  // the tuner log lists every candidate's time  // >= 1: SELL with that many lanes per row, 0: CSR, for every coarse operator
     std::string tune_log;  // chosen layouts, one line per operator
 
     // start vectors
@@ -341,7 +344,7 @@ void upload(eqs_ctx* c);
 void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const double* yfree, double* out);
 void free_device(eqs_ctx* c);
 template <typename T>
-Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A, int lanes);
+Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A, int lanes, bool sorted = false);
 template <typename T>
 SpMat<T> to_spmat(eqs_ctx* c, const Csr<double>& A);
 

@@ -557,6 +557,9 @@ double time_kx(eqs_ctx* c, const double* yfree, double* out, int reps) {
 }
 
 // ------------------------------------------------------------- SELL-64
+// Sparse products and smoothers are memory-latency bound: they are built for
+// 8 wavefronts per SIMD (at most 64 VGPRs), the most a SIMD holds.
+constexpr int kSparseWaves = 8;
 template <typename T>
 static unsigned sell_grid(const Sell<T>& A) {
     return (unsigned)(((int64_t)A.n_slices * kSlice + kBlock - 1) / kBlock);
@@ -580,17 +583,17 @@ __device__ __forceinline__ void mv_store(T* __restrict__ y, int32_t row, T v, in
 
 // y = A x with the epilogue above (L lanes per row)
 template <int L, typename T>
-__global__ __launch_bounds__(256) void k_sell_mv(SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
+__global__ __launch_bounds__(256, kSparseWaves) void k_sell_mv(SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
                                                   MvInit<T> in, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (int64_t)A.n_slices * 64) return;  // whole wavefronts leave together
-    const int32_t row = sell_row_of<L>(g);
+    const int32_t row = sell_perm_row<L>(A.perm, g);
     const T v = sell_row<L>(A, g, row, x);
     if ((g & (L - 1)) == 0 && row < A.n_rows) mv_store(y, row, v, acc, in);
 }
 
-__global__ __launch_bounds__(256) void k_spmv64(SellView<double> A, const double* __restrict__ x,
+__global__ __launch_bounds__(256, kSparseWaves) void k_spmv64(SellView<double> A, const double* __restrict__ x,
                                                  double* __restrict__ y) {
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= A.n_slices * 64) return;
@@ -608,7 +611,7 @@ void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double
 // the last product with the stored pre-smoothing values a_ij omega / a_jj,
 // so rows gather b only.
 template <int L, typename T, typename TB>
-__global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> As, const T* __restrict__ dinv, T omega,
+__global__ __launch_bounds__(256, kSparseWaves) void k_presmooth_res(SellView<T> As, const T* __restrict__ dinv, T omega,
                                                         const TB* __restrict__ b, T* __restrict__ x,
                                                         T* __restrict__ res, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
@@ -628,7 +631,7 @@ __global__ __launch_bounds__(256) void k_presmooth_res(SellView<T> As, const T* 
 // Polak-Ribiere numerator) are produced per instance (pair layout, see
 // InstMap); z_old is read before it is overwritten.
 template <int L, typename T, typename TB, typename TO, bool DOT>
-__global__ __launch_bounds__(256) void k_postsmooth(SellView<T> A, const T* __restrict__ dinv, T omega,
+__global__ __launch_bounds__(256, kSparseWaves) void k_postsmooth(SellView<T> A, const T* __restrict__ dinv, T omega,
                                                      const TB* __restrict__ b, const T* __restrict__ x,
                                                      TO* __restrict__ out, InstMap m, double* __restrict__ part_rz,
                                                      double* __restrict__ part_rzold,
@@ -712,7 +715,7 @@ __device__ __forceinline__ T csr_row(const CsrView<T>& A, int32_t row, int lane,
 }
 
 template <int L, typename T>
-__global__ __launch_bounds__(256) void k_csr_mv(CsrView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
+__global__ __launch_bounds__(256, kSparseWaves) void k_csr_mv(CsrView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
                                                  MvInit<T> in, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -724,7 +727,7 @@ __global__ __launch_bounds__(256) void k_csr_mv(CsrView<T> A, const T* __restric
 }
 
 template <int L, typename T, typename TB>
-__global__ __launch_bounds__(256) void k_csr_presmooth_res(CsrView<T> As, const T* __restrict__ dinv, T omega,
+__global__ __launch_bounds__(256, kSparseWaves) void k_csr_presmooth_res(CsrView<T> As, const T* __restrict__ dinv, T omega,
                                                             const TB* __restrict__ b, T* __restrict__ x,
                                                             T* __restrict__ res, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
@@ -741,7 +744,7 @@ __global__ __launch_bounds__(256) void k_csr_presmooth_res(CsrView<T> As, const 
 }
 
 template <int L, typename T, typename TB, typename TO>
-__global__ __launch_bounds__(256) void k_csr_postsmooth(CsrView<T> A, const T* __restrict__ dinv, T omega,
+__global__ __launch_bounds__(256, kSparseWaves) void k_csr_postsmooth(CsrView<T> A, const T* __restrict__ dinv, T omega,
                                                          const TB* __restrict__ b, const T* __restrict__ x,
                                                          TO* __restrict__ out, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
@@ -791,6 +794,7 @@ static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int ac
 
 template <typename T, typename TB>
 static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, const int32_t* stop) {
+    if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
     if (lv.A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
                               hipLaunchKernelGGL((k_presmooth_res<L_, T, TB>), dim3(sell_grid(lv.A.sell)),
@@ -806,6 +810,7 @@ static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, con
 // Post-smoothing of a coarse level (no dot products).
 template <typename T>
 static void launch_postsmooth(hipStream_t s, const Level<T>& lv, const T* b, const T* x, T* out, const int32_t* stop) {
+    if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
     if (lv.A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
                               hipLaunchKernelGGL((k_postsmooth<L_, T, T, T, false>), dim3(sell_grid(lv.A.sell)),
@@ -1004,7 +1009,7 @@ template void vcycle<float>(hipStream_t, eqs_ctx*, Hierarchy<float>&, const doub
 
 // r = rhs - M x; pair partials of |r|^2 and |rhs|^2. With mx_out, M x is
 // also stored (the next solve that starts from this x then needs no product).
-__global__ __launch_bounds__(256) void k_pcg_residual(SellView<double> M, InstMap m, const double* __restrict__ rhs,
+__global__ __launch_bounds__(256, kSparseWaves) void k_pcg_residual(SellView<double> M, InstMap m, const double* __restrict__ rhs,
                                                        const double* __restrict__ x, double* __restrict__ r,
                                                        double* __restrict__ part_rr, double* __restrict__ part_bb,
                                                        double* __restrict__ mx_out) {
@@ -1054,7 +1059,7 @@ __global__ __launch_bounds__(256) void k_pcg_residual_mx(InstMap m, const double
 }
 
 // q = M z + beta q, p = z + beta p (so q = M p without a second pass); pair partials of p.q.
-__global__ __launch_bounds__(256) void k_pcg_spmv(SellView<double> M, InstMap m, const double* __restrict__ z,
+__global__ __launch_bounds__(256, kSparseWaves) void k_pcg_spmv(SellView<double> M, InstMap m, const double* __restrict__ z,
                                                    double* __restrict__ p, double* __restrict__ q,
                                                    double* __restrict__ part_pq, const PcgScalars* __restrict__ scal,
                                                    const int32_t* __restrict__ stop) {

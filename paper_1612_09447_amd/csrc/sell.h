@@ -38,11 +38,24 @@ struct SellView {
     const int16_t* __restrict__ d16;
     const T* __restrict__ val;
     int32_t n_rows, n_slices, n_cols;
+    const uint8_t* __restrict__ perm;  // row order within each 256-thread window, or NULL (see sell_perm_row)
 };
 
 template <typename T>
 static inline SellView<T> view(const Sell<T>& A) {
-    return SellView<T>{A.sptr, A.col, A.d16, A.val, A.n_rows, A.n_slices, A.n_cols};
+    return SellView<T>{A.sptr, A.col, A.d16, A.val, A.n_rows, A.n_slices, A.n_cols, A.perm};
+}
+
+// With a row order (perm), the rows served by one 256-thread window (4
+// slices, 256 / L rows) are stored longest first, so the slices of the window
+// pad less; position k of the window serves row window_base + perm[k]. Only
+// products y = A x use it (they write y[row] of their own window only).
+template <int L>
+__device__ __forceinline__ int32_t sell_perm_row(const uint8_t* __restrict__ perm, int64_t g) {
+    const int32_t pos = sell_row_of<L>(g);
+    if (!perm) return pos;
+    const int32_t base = (int32_t)((g >> 8) * (256 / L));
+    return base + (int32_t)perm[pos];
 }
 
 // sum_k a_{row,k} f(col_k) over the stored entries of `row` served by global

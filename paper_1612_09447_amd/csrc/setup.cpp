@@ -509,42 +509,51 @@ static T* upload_vec(eqs_ctx* c, const std::vector<T>& v) {
 }
 
 template <typename T>
-Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A, int lanes) {
+Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A, int lanes, bool sorted) {
     if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) fail(EQS_ERR_STATE, "SELL lanes per row must be 1, 2, 4 or 8");
     const int32_t rows_per = kSlice / lanes;  // rows of one slice
+    const int32_t window = 4 * rows_per;      // rows of one 256-thread window
     Sell<T> S;
     S.n_rows = A.n_rows;
     S.n_cols = A.n_cols;
     S.lanes = lanes;
     S.n_slices = (A.n_rows + rows_per - 1) / rows_per;
+    // pos2row[k]: the row stored at position k (positions past n_rows are
+    // phantom rows >= n_rows); sorted: longest rows first within each window
+    const int32_t n_pos = S.n_slices * rows_per;
+    std::vector<int32_t> pos2row((size_t)n_pos);
+    for (int32_t k = 0; k < n_pos; ++k) pos2row[(size_t)k] = k;
+    auto len = [&](int32_t r) { return r < A.n_rows ? A.ptr[r + 1] - A.ptr[r] : 0; };
+    if (sorted)
+        for (int32_t w0 = 0; w0 < n_pos; w0 += window) {
+            const int32_t w1 = std::min(n_pos, w0 + window);
+            std::stable_sort(pos2row.begin() + w0, pos2row.begin() + w1,
+                             [&](int32_t a, int32_t b) { return len(a) > len(b); });
+        }
     std::vector<int32_t> sptr(S.n_slices + 1, 0);
     for (int32_t s = 0; s < S.n_slices; ++s) {
         int32_t w = 0;  // entries per lane
-        for (int32_t r = s * rows_per; r < std::min(A.n_rows, (s + 1) * rows_per); ++r)
-            w = std::max(w, (A.ptr[r + 1] - A.ptr[r] + lanes - 1) / lanes);
+        for (int32_t k = s * rows_per; k < (s + 1) * rows_per; ++k) w = std::max(w, (len(pos2row[k]) + lanes - 1) / lanes);
         int64_t next = (int64_t)sptr[s] + (int64_t)w * kSlice;
         if (next > INT32_MAX) fail(EQS_ERR_INVALID_ARG, "matrix too large for SELL offsets");
         sptr[s + 1] = (int32_t)next;
     }
     S.stored = sptr[S.n_slices];
-    // lane l of slice s serves row s * rows_per + l / lanes and holds the
-    // row's entries l % lanes + lanes * k, k = 0 .. w-1
+    // lane l of slice s serves the row at position s * rows_per + l / lanes and
+    // holds the row's entries l % lanes + lanes * k, k = 0 .. w-1
     std::vector<int32_t> col(S.stored, 0);
     std::vector<T> val(S.stored, T(0));
     for (int32_t s = 0; s < S.n_slices; ++s) {
         const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
         for (int32_t l = 0; l < kSlice; ++l) {
-            const int32_t r = s * rows_per + l / lanes, part = l % lanes;
+            const int32_t r = pos2row[(size_t)(s * rows_per + l / lanes)], part = l % lanes;
             int32_t pad_col = 0;
-            int32_t len = 0;
-            if (r < A.n_rows) {
-                len = A.ptr[r + 1] - A.ptr[r];
-                if (len > 0) pad_col = A.col[A.ptr[r] + len - 1];
-            }
+            const int32_t n = len(r);
+            if (n > 0) pad_col = A.col[A.ptr[r] + n - 1];
             for (int32_t k = 0; k < w; ++k) {
                 const int64_t at = sptr[s] + (int64_t)k * kSlice + l;
                 const int32_t e = k * lanes + part;
-                if (e < len) {
+                if (e < n) {
                     col[at] = A.col[A.ptr[r] + e];
                     val[at] = (T)A.val[A.ptr[r] + e];
                 } else {
@@ -562,7 +571,7 @@ Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A, int lanes) {
         for (int32_t s = 0; s < S.n_slices && fits; ++s) {
             const int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
             for (int32_t l = 0; l < kSlice && fits; ++l) {
-                const int32_t r = s * rows_per + l / lanes;
+                const int32_t r = pos2row[(size_t)(s * rows_per + l / lanes)];
                 const int64_t base = offset_base(r, A.n_rows, A.n_cols);
                 for (int32_t k = 0; k < w; ++k) {
                     const int64_t at = sptr[s] + (int64_t)k * kSlice + l;
@@ -580,11 +589,16 @@ Sell<T> to_sell(eqs_ctx* c, const Csr<double>& A, int lanes) {
     if (fits) S.d16 = upload_vec(c, d16);
     else S.col = upload_vec(c, col);
     S.val = upload_vec(c, val);
+    if (sorted) {
+        std::vector<uint8_t> perm((size_t)n_pos);
+        for (int32_t k = 0; k < n_pos; ++k) perm[(size_t)k] = (uint8_t)(pos2row[(size_t)k] - (k / window) * window);
+        S.perm = upload_vec(c, perm);
+    }
     return S;
 }
 
-template Sell<double> to_sell<double>(eqs_ctx*, const Csr<double>&, int);
-template Sell<float> to_sell<float>(eqs_ctx*, const Csr<double>&, int);
+template Sell<double> to_sell<double>(eqs_ctx*, const Csr<double>&, int, bool);
+template Sell<float> to_sell<float>(eqs_ctx*, const Csr<double>&, int, bool);
 
 // CSR column ids: 16-bit offsets from offset_base(row) when every entry
 // allows, else absolute.
@@ -645,6 +659,7 @@ static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
     dev_free(c, S.sell.col);
     dev_free(c, S.sell.d16);
     dev_free(c, S.sell.val);
+    dev_free(c, S.sell.perm);
     dev_free(c, S.rowptr);
     dev_free(c, S.col);
     dev_free(c, S.d16);
@@ -653,13 +668,16 @@ static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
 }
 
 // Autotuner: upload the operator in every candidate layout (SELL with 1 lane
-// per row, and with 2, 4, 8 while each lane keeps 1.5 entries or more;
+// per row, and with 2, 4, 8 while each lane keeps 1.5 entries or more, each
+// also with rows sorted by length within 256-thread windows when the operator
+// is only used in products y = A x;
 // CSR with L = 2..64 lanes per row up to about twice the mean row length, and
 // with one lane per row for rows of up to 8 entries on average), time y = A x
 // with HIP events on the context's stream (median of 5 after 2 warm-ups) and
 // keep the fastest.
 template <typename T>
-static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, bool sell_only = false) {
+static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, bool sell_only = false,
+                             bool allow_sorted = false) {
     if (sell_only) {  // the finest operator: its post-smoothing kernel writes per-block CG partials
         SpMat<T> S;
         S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
@@ -687,7 +705,7 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
         } else {
             S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
             S.fmt = FMT_SELL;
-            S.sell = to_sell<T>(c, A, c->force_layout);
+            S.sell = to_sell<T>(c, A, c->force_layout, c->force_sorted && allow_sorted);
         }
         c->tune_log += std::string(what) + ": layout set by EQS_LAYOUT\n";
         return S;
@@ -703,8 +721,14 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
     SpMat<T> best;
     double best_ms = 1e300;
     std::string best_name;
+    std::string tried;
     auto consider = [&](SpMat<T> cand, const std::string& name) {
         const double ms = time_mv<T>(c, cand, x, y, 5);
+        if (c->tune_verbose) {
+            char t[96];
+            std::snprintf(t, sizeof t, " %s %.1f", name.c_str(), ms * 1e3);
+            tried += t;
+        }
         if (ms < best_ms) {
             if (best.n_rows || best.nnz) free_spmat(c, best);
             best = cand;
@@ -716,11 +740,14 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
     };
     for (int L = 1; L <= 8; L *= 2) {
         if (L > 1 && mean < 1.5 * L) break;  // lanes with about one entry or less
-        SpMat<T> S;
-        S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
-        S.fmt = FMT_SELL;
-        S.sell = to_sell<T>(c, A, L);
-        consider(S, std::string("sell64") + (L > 1 ? "x" + std::to_string(L) : "") + (S.sell.d16 ? "/i16" : ""));
+        for (int sorted = 0; sorted <= (allow_sorted ? 1 : 0); ++sorted) {
+            SpMat<T> S;
+            S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
+            S.fmt = FMT_SELL;
+            S.sell = to_sell<T>(c, A, L, sorted != 0);
+            consider(S, std::string("sell64") + (L > 1 ? "x" + std::to_string(L) : "") + (sorted ? "s" : "") +
+                            (S.sell.d16 ? "/i16" : ""));
+        }
     }
     for (int L = (mean <= 8.0 ? 1 : 2); L <= 64; L *= 2) {
         if (L > 2 && L / 2 > 2.0 * mean) break;
@@ -742,6 +769,7 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
     std::snprintf(line, sizeof line, "%s: %d x %d, %.1f nnz/row -> %s (%.1f us, stored/nnz %.2f)\n", what, A.n_rows,
                   A.n_cols, mean, best_name.c_str(), best_ms * 1e3, fill);
     c->tune_log += line;
+    if (c->tune_verbose) c->tune_log += "  tried (us):" + tried + "\n";
     return best;
 }
 
@@ -842,12 +870,12 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
             const bool tail_level = tail_ok && l == (int)L - 2;
             lv.fold_pre = c->fold && l >= 1 && !tail_level;
             if (!lv.fold_pre) lv.sval = scaled_values<T>(c, lv.A, ah.A[l], d, lv.omega);
-            lv.P = tuned_spmat<T>(c, ah.P[l], ("P" + std::to_string(l)).c_str());
+            lv.P = tuned_spmat<T>(c, ah.P[l], ("P" + std::to_string(l)).c_str(), false, true);
             if (lv.fold_pre)
                 lv.R = tuned_spmat<T>(c, fold_presmoother(ah.R[l], ah.A[l], d, lv.omega),
-                                      ("R" + std::to_string(l) + "(I-AwD^-1)").c_str());
+                                      ("R" + std::to_string(l) + "(I-AwD^-1)").c_str(), false, true);
             else
-                lv.R = tuned_spmat<T>(c, ah.R[l], ("R" + std::to_string(l)).c_str());
+                lv.R = tuned_spmat<T>(c, ah.R[l], ("R" + std::to_string(l)).c_str(), false, true);
         } else {
             std::vector<T> inv(ah.coarse_inv.size());
             for (size_t k = 0; k < inv.size(); ++k) inv[k] = (T)ah.coarse_inv[k];
@@ -934,7 +962,7 @@ static void upload_coarse_tail(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h) {
     for (size_t k = 0; k < Cp.size(); ++k) Ct[k] = (T)Cp[k];
     lc.coarse_R = upload_vec(c, Ct);
     lc.coarse_R_cols = (int32_t)nt;
-    lt.GQ = tuned_spmat<T>(c, GQ, ("[G Q]" + std::to_string(t)).c_str());
+    lt.GQ = tuned_spmat<T>(c, GQ, ("[G Q]" + std::to_string(t)).c_str(), false, true);
     // b_t and x_c side by side: the restriction from above writes b_t, the
     // dense product writes x_c, the sparse product reads both
     T* bx = (T*)dev_alloc(c, sizeof(T) * (size_t)(nt + nc));

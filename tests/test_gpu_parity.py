@@ -168,12 +168,13 @@ def test_preconditioner_symmetric_positive(prec, tol):
 @pytest.mark.parametrize("prec,tol", [(EQS_PREC_FP64, 1e-12), (EQS_PREC_FP32, 2e-5)])
 def test_preconditioner_same_in_every_layout(prec, tol, monkeypatch):
     """Each storage layout of the coarse operators (SELL with 1, 2, 4, 8 lanes
-    per row, CSR with lanes) gives the same V-cycle up to summation order."""
+    per row, with and without rows sorted by length within windows, CSR with
+    lanes) gives the same V-cycle up to summation order."""
     case = inclusion_case(14, 4)
     n = None
     outs = {}
     X = None
-    for lay in ("sell1", "sell2", "sell4", "sell8", "csr"):
+    for lay in ("sell1", "sell2", "sell4", "sell8", "csr", "sell1s", "sell2s", "sell4s", "sell8s"):
         monkeypatch.setenv("EQS_LAYOUT", lay)
         with ctx_for(case, precision=prec, coarse_max=24) as c:
             info = c.info()
