@@ -5,9 +5,11 @@
 //    E = -grad(phi) gives kappa(|E|), and the element matrix times the local
 //    potentials is added straight into the output (K(x)x, or the stage
 //    right-hand side b(t) - K(x)x with b folded in element by element).
-//  * SELL-64 sparse products with fused epilogues for CG on M and for the
-//    smoothed-aggregation V-cycle (damped Jacobi, restriction, prolongation,
-//    dense coarsest solve).
+//  * SELL and CSR sparse products with fused epilogues for CG on M and for
+//    the smoothed-aggregation V-cycle (damped Jacobi, restriction,
+//    prolongation, dense coarsest solve), including the folded operators the
+//    host forms at set-up (a restriction with the pre-smoother inside, the two
+//    lowest levels as one dense and one sparse product).
 //  * CG vector updates with block partial sums; one-block finalisers turn the
 //    partials into the CG scalars, kept in device memory.
 //  * RKC stage combination (the paper's ref. [9]).
