@@ -354,14 +354,17 @@ void launch_fill(hipStream_t s, double* p, double v, int64_t n);
 void launch_gather(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n);
 void launch_scatter(hipStream_t s, const double* src, const int32_t* idx, double* dst, int64_t n);
 void launch_finish_state(eqs_ctx* c, const double* yfree, double t, double* x_user);
-void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out);
+// zeroed: `out` is already cleared (no fill launch)
+void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out,
+               bool zeroed = false);
 double time_kx(eqs_ctx* c, const double* yfree, double* out, int reps);
 void launch_copy(hipStream_t s, double* dst, const double* src, int64_t n);
+// zero (may be NULL): also cleared (the next stage's element-pass output)
 void launch_rkc_first(eqs_ctx* c, hipStream_t s, double* out, const double* Y0, const double* F0, double a,
-                      int64_t n);
+                      int64_t n, double* zero = nullptr);
 void launch_rkc_combine(eqs_ctx* c, hipStream_t s, double* out, const double* Y0, const double* Yjm1,
                         const double* Yjm2, const double* Fjm1, const double* F0, double c0, double c1, double c2,
-                        double c3, double c4, int64_t n);
+                        double c3, double c4, int64_t n, double* zero = nullptr);
 void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double* y);
 
 // PCG pieces (all scalar state on the device, one PcgScalars per instance)
@@ -370,7 +373,10 @@ void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double
 void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int32_t maxit, double rtol,
               int flexible, const double* mx = nullptr);
 void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int precision);
-void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, double* mx_out = nullptr);
+// only_if_done: queued before the host knows the outcome of the iteration in
+// flight; the kernels act only if that iteration completed every instance
+void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, double* mx_out = nullptr,
+                       bool only_if_done = false);
 void pcg_zero_rhs_rows(hipStream_t s, eqs_ctx* c, double* x);
 
 template <typename T>

@@ -530,9 +530,9 @@ static void launch_kx_t(hipStream_t s, eqs_ctx* c, const double* yfree, double t
 #undef EQS_KX
 }
 
-void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out) {
+void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out, bool zeroed) {
     const int64_t nout = rhs_mode ? c->n_free : c->n_nodes;
-    launch_fill(s, out, 0.0, nout);
+    if (!zeroed) launch_fill(s, out, 0.0, nout);
     if (c->n_tets == 0) return;
     if (rhs_mode) launch_kx_t<true>(s, c, yfree, t, out);
     else launch_kx_t<false>(s, c, yfree, t, out);
@@ -1014,8 +1014,9 @@ template void vcycle<float>(hipStream_t, eqs_ctx*, Hierarchy<float>&, const doub
 __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_residual(SellView<double> M, InstMap m, const double* __restrict__ rhs,
                                                        const double* __restrict__ x, double* __restrict__ r,
                                                        double* __restrict__ part_rr, double* __restrict__ part_bb,
-                                                       double* __restrict__ mx_out) {
+                                                       double* __restrict__ mx_out, const int32_t* __restrict__ when_done) {
     __shared__ double sh[kPairSh];
+    if (when_done && !*when_done) return;  // queued ahead of the host's decision: only once every instance is done
     const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     double rr = 0.0, bb = 0.0;
     if (row < M.n_slices * 64) {
@@ -1179,7 +1180,8 @@ __global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, 
                                                      const double* __restrict__ pbb, double rtol, int32_t maxit,
                                                      int32_t flexible, int32_t mode, PcgSummary* __restrict__ sum,
                                                      PcgSummary* __restrict__ host_sum,
-                                                     PcgScalars* __restrict__ host) {
+                                                     PcgScalars* __restrict__ host, int32_t when_done) {
+    if (when_done && !sum->all_done) return;  // pairs with k_pcg_residual's when_done
     const double* parts[2] = {prr, pbb};
     for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
         const double rr = v[0], bb = v[1];
@@ -1314,17 +1316,19 @@ void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int
                            c->d_r, c->n_free, part(c, 0), part(c, 1));
     else
         hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
-                           part(c, 0), part(c, 1), (double*)nullptr);
+                           part(c, 0), part(c, 1), (double*)nullptr, (const int32_t*)nullptr);
     hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), rtol,
-                       maxit, flexible, 0, c->d_sum, c->d_hsum, c->d_hscal);
+                       maxit, flexible, 0, c->d_sum, c->d_hsum, c->d_hscal, 0);
 }
 
-void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, double* mx_out) {
+void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, double* mx_out,
+                       bool only_if_done) {
     const int64_t nb = sell_grid(c->M);
+    const int32_t* done = only_if_done ? &c->d_sum->all_done : nullptr;
     hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
-                       part(c, 0), part(c, 1), mx_out);
+                       part(c, 0), part(c, 1), mx_out, done);
     hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), 0.0, 0,
-                       0, 1, c->d_sum, c->d_hsum, c->d_hscal);
+                       0, 1, c->d_sum, c->d_hsum, c->d_hscal, only_if_done ? 1 : 0);
 }
 
 void pcg_zero_rhs_rows(hipStream_t s, eqs_ctx* c, double* x) {
@@ -1353,31 +1357,40 @@ void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int 
 }
 
 // ------------------------------------------------------------------ RKC
+// With `zero` (may be NULL) the combination also clears that vector (the next
+// stage's element-pass output), saving a launch.
 __global__ void k_rkc_first(double* __restrict__ out, const double* __restrict__ Y0, const double* __restrict__ F0,
-                            double a, int64_t n) {
+                            double a, int64_t n, double* __restrict__ zero) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = Y0[i] + a * F0[i];
+    if (i < n) {
+        out[i] = Y0[i] + a * F0[i];
+        if (zero) zero[i] = 0.0;
+    }
 }
 
 // out may alias Yjm2 (each element is read before it is written).
 __global__ void k_rkc_combine(double* out, const double* __restrict__ Y0, const double* __restrict__ Yjm1,
                               const double* Yjm2, const double* __restrict__ Fjm1, const double* __restrict__ F0,
-                              double c0, double c1, double c2, double c3, double c4, int64_t n) {
+                              double c0, double c1, double c2, double c3, double c4, int64_t n,
+                              double* __restrict__ zero) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = c0 * Y0[i] + c1 * Yjm1[i] + c2 * Yjm2[i] + c3 * Fjm1[i] + c4 * F0[i];
+    if (i < n) {
+        out[i] = c0 * Y0[i] + c1 * Yjm1[i] + c2 * Yjm2[i] + c3 * Fjm1[i] + c4 * F0[i];
+        if (zero) zero[i] = 0.0;
+    }
 }
 
 void launch_rkc_first(eqs_ctx* c, hipStream_t s, double* out, const double* Y0, const double* F0, double a,
-                      int64_t n) {
+                      int64_t n, double* zero) {
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_RKC_COMBINE, k_rkc_first, dim3(grid_for(n)), dim3(kBlock), 0, s, out, Y0, F0, a,
-                     n);
+                     n, zero);
 }
 
 void launch_rkc_combine(eqs_ctx* c, hipStream_t s, double* out, const double* Y0, const double* Yjm1,
                         const double* Yjm2, const double* Fjm1, const double* F0, double c0, double c1, double c2,
-                        double c3, double c4, int64_t n) {
+                        double c3, double c4, int64_t n, double* zero) {
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_RKC_COMBINE, k_rkc_combine, dim3(grid_for(n)), dim3(kBlock), 0, s, out, Y0, Yjm1,
-                     Yjm2, Fjm1, F0, c0, c1, c2, c3, c4, n);
+                     Yjm2, Fjm1, F0, c0, c1, c2, c3, c4, n, zero);
 }
 
 }  // namespace eqs

@@ -91,7 +91,11 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
         // to converge (the last two residuals the host has seen, extrapolated
         // geometrically, reach rtol) does the host wait for k first, so that
         // no iteration is launched past convergence.
+        // When it waits, the host first queues the residual check, which acts
+        // only if iteration k completed the solve: the check then runs without
+        // a host round trip in between.
         double rel_prev = -1.0, rel_last = -1.0;
+        bool checked = false;
         run_iteration(c, y, prec);
         EQS_HIP(hipEventRecord(c->ev[0], s));
         for (int64_t k = 0;; ++k) {
@@ -99,9 +103,13 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
             bool ahead = !last;
             if (ahead && rel_last > 0.0 && rel_prev > rel_last && rel_last * (rel_last / rel_prev) <= rtol)
                 ahead = false;
+            checked = false;
             if (ahead) {
                 run_iteration(c, y, prec);
                 EQS_HIP(hipEventRecord(c->ev[(k + 1) & 1], s));
+            } else if (!last && !c->prof_mask) {
+                pcg_true_residual(s, c, rhs, y, mx_out, true);
+                checked = true;
             }
             EQS_HIP(hipEventSynchronize(c->ev[k & 1]));
             const volatile PcgSummary* hs = c->h_sum;
@@ -127,8 +135,8 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
         }
         // every instance is done on its recursive residual (or out of iterations,
         // or broken down): check the true residuals (queued behind any iteration
-        // still in flight); disagreeing ones restart
-        pcg_true_residual(s, c, rhs, y, mx_out);
+        // still in flight, unless already queued above); disagreeing ones restart
+        if (!checked) pcg_true_residual(s, c, rhs, y, mx_out);
         check_launch();
         EQS_HIP(hipStreamSynchronize(s));
         v = read_summary(c);
@@ -174,9 +182,10 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
     int rc = EQS_OK;
     const double* Ycur = c->d_Y0;
     const double* Yprev = c->d_Y0;
+    bool rhs_zeroed = false;  // the last combination cleared d_rhs for this stage's element pass
     for (int j = 0; j < s; ++j) {
         const double tj = t + cc[j] * dt;
-        launch_kx(q, true, c, Ycur, tj, c->d_rhs);
+        launch_kx(q, true, c, Ycur, tj, c->d_rhs, rhs_zeroed);
         check_launch();
         // start vector: F_{j-1} (held in d_F), zero, or an estimator's vector
         const int kind = c->guess.p.kind;
@@ -209,15 +218,19 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
         }
         if (j == 0) launch_copy(q, c->d_F0, c->d_F, NF);
         double* out;
+        // d_rhs (this stage's right-hand side) is no longer needed: the
+        // combination clears it for the next stage's element pass
+        double* zero = (j + 1 < s) ? c->d_rhs : nullptr;
         if (j == 0) {
             out = c->d_Ya;
-            launch_rkc_first(c, q, out, c->d_Y0, c->d_F0, mut[1] * dt, NF);
+            launch_rkc_first(c, q, out, c->d_Y0, c->d_F0, mut[1] * dt, NF, zero);
         } else {
             out = (Ycur == c->d_Ya) ? c->d_Yb : c->d_Ya;  // for j >= 2 this buffer holds Y_{j-1}
             const int k = j + 1;
             launch_rkc_combine(c, q, out, c->d_Y0, Ycur, Yprev, c->d_F, c->d_F0, 1.0 - mu[k] - nu[k], mu[k], nu[k],
-                               mut[k] * dt, gmt[k] * dt, NF);
+                               mut[k] * dt, gmt[k] * dt, NF, zero);
         }
+        rhs_zeroed = zero != nullptr;
         check_launch();
         Yprev = Ycur;
         Ycur = out;
