@@ -138,16 +138,23 @@ def measured_traffic(kernel_class):
     return val if sha == kernel_source_hash() else None
 
 
-def mixed_learned_vs_fp64(plain, learned):
+def mixed_learned_vs_fp64(plain, learned, full):
     """Stage rate of the mixed-precision form with the network start vector
-    relative to the plain FP64 path, as a product of same-window ratios: the
-    network vs the plain start vector (both mixed precision, same steps) times
-    the mixed-precision vs FP64 paths (plain start vector, same steps)."""
-    if not plain or "fp32_form_speedup" not in plain or not learned or "mlp" not in learned:
+    relative to the plain FP64 path. `value`: both run the same timed steps
+    from t = 0 (whole-run rates). Beside it, the product of same-window ratios
+    from the start-vector comparison: network vs plain start (both mixed
+    precision) times mixed precision vs FP64 (plain start)."""
+    if not plain or "fp32_form_speedup" not in plain:
         return None
-    net = learned["mlp"]["stages_per_s"] / learned["previous"]["stages_per_s"]
-    return {"value": round(net * plain["fp32_form_speedup"], 3), "network_vs_plain_start": round(net, 3),
-            "fp32_form_vs_fp64": plain["fp32_form_speedup"]}
+    out = {"fp32_form_vs_fp64": plain["fp32_form_speedup"]}
+    if full and "mlp" in full and plain.get("steps") == full["mlp"]["steps"]:
+        out["value"] = round(full["mlp"]["stages_per_s"] / plain["stages_per_s"], 3)
+        out["basis"] = f"whole runs of {plain['steps']} steps: FP32 form + network start vector vs plain FP64"
+    if learned and "mlp" in learned:
+        net = learned["mlp"]["stages_per_s"] / learned["previous"]["stages_per_s"]
+        out["window_product"] = round(net * plain["fp32_form_speedup"], 3)
+        out["network_vs_plain_start_in_window"] = round(net, 3)
+    return out if "value" in out or "window_product" in out else None
 
 
 def cpu_model():
@@ -204,7 +211,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
     ctx = Context(0, stream)
     info = ctx.setup_case(case, precision=precision, flexible=flexible)
     if guess == "mlp":
-        ctx.set_guess("mlp", init=eqsgen.mlp_init(4))
+        ctx.set_guess("mlp", init=eqsgen.mlp_init(4), batch=mlp_batch)
     elif guess != "previous":
         ctx.set_guess(guess)
     setup_s = time.perf_counter() - t0
@@ -319,7 +326,7 @@ def cpu_baseline(case):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40, help="timed RKC steps")
+    ap.add_argument("--steps", type=int, default=200, help="timed RKC steps (the workload's 200)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
     ap.add_argument("--n", type=int, default=None, help="override the mesh resolution (testing)")
@@ -332,6 +339,8 @@ def main():
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     ap.add_argument("--c3-steps", type=int, default=5, help="also time the 64-instance batched workload (0: skip)")
     ap.add_argument("--mlp-batch", type=int, default=128, help="network training pairs per stage (<= 256)")
+    ap.add_argument("--full-runs", default="mlp,galerkin",
+                    help="start vectors timed over the whole run beside the plain one (comma list; empty: none)")
     ap.add_argument("--learned-steps", type=int, default=5,
                     help="also time this many steps with each start vector (zero, Galerkin, fixed POD, network; "
                          "0: skip)")
@@ -406,6 +415,15 @@ def main():
             plain["rel_diff_of_final_state_vs_fp32_form"] = float(f"{d:.3e}")
             plain["fp32_form_speedup"] = round(stages_per_s / plain["stages_per_s"], 3)
 
+    # whole runs with the estimator start vectors, same steps as the main run
+    full = {}
+    for kind in [k for k in args.full_runs.split(",") if k]:
+        f = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, guess=kind, mlp_batch=args.mlp_batch)
+        full[kind] = {"stages_per_s": round(f["stages"] / f["elapsed"], 2),
+                      "mean_cg_iters_per_stage": round(sum(f["iters"]) / len(f["iters"]), 2),
+                      "steps": args.steps, "guess_used": f["used"], "guard_fallbacks": f["fallbacks"],
+                      "vs_plain_start": round(f["stages"] / f["elapsed"] / stages_per_s, 3)}
+
     batched = run_batched(args.c3_steps, 1) if args.c3_steps > 0 else None
 
     cpu = None
@@ -446,7 +464,8 @@ def main():
         "read_probe": rd,
         "fp64_plain": plain,
         "start_vectors": r["learned"] or None,
-        "mixed_learned_vs_fp64": mixed_learned_vs_fp64(plain, r["learned"]),
+        "start_vector_runs": full or None,
+        "mixed_learned_vs_fp64": mixed_learned_vs_fp64(plain, r["learned"], full),
         "batched": batched,
         "cpu_baseline": cpu,
     }
