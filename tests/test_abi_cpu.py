@@ -80,6 +80,23 @@ def test_constants_match_header():
         assert m and int(m.group(1)) == getattr(binding, name), name
 
 
+def test_enums_match_header():
+    """Precision, start-vector and kernel-class enums of the header against the
+    binding's constants and name maps."""
+    src = open(HEADER).read()
+    vals = {m.group(1): int(m.group(2)) for m in re.finditer(r"(EQS_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)}
+    for name in ["EQS_PREC_FP64", "EQS_PREC_FP32", "EQS_GUESS_PREVIOUS", "EQS_GUESS_ZERO", "EQS_GUESS_GALERKIN",
+                 "EQS_GUESS_MLP", "EQS_GUESS_MOR"]:
+        assert vals[name] == getattr(binding, name), name
+    kclass = {k: v for k, v in vals.items() if k.startswith("EQS_KCLASS_") and k != "EQS_KCLASS_COUNT"}
+    assert sorted(kclass.values()) == list(range(vals["EQS_KCLASS_COUNT"]))
+    assert sorted(binding.KCLASS.values()) == sorted(kclass.values())
+    for name, v in binding.KCLASS.items():
+        assert kclass["EQS_KCLASS_" + name.upper()] == v, name
+    for name, v in binding.GUESS_KINDS.items():
+        assert vals["EQS_GUESS_" + name.upper()] == v, name
+
+
 def _no_gpu():
     try:
         import torch
