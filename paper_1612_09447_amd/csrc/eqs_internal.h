@@ -21,6 +21,7 @@
 
 #include <cstdint>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "eqs.h"
@@ -274,8 +275,9 @@ struct eqs_ctx {
     double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr;
     double* d_mx = nullptr;  // M F of the stage solution in d_F when mx_of_F
     bool mx_of_F = false;
-    double *d_Y0 = nullptr, *d_Ya = nullptr, *d_Yb = nullptr, *d_F0 = nullptr, *d_F = nullptr;
-    double *d_rhs = nullptr, *d_tmpN = nullptr, *d_tmpN2 = nullptr;  // tmpN*: n_nodes
+    double *d_Y0 = nullptr, *d_Ya = nullptr, *d_Yb = nullptr, *d_Yc = nullptr, *d_F0 = nullptr, *d_F = nullptr;
+    double *d_rhs = nullptr, *d_rhs_alt = nullptr;  // the stage RHS, and the next stage's when it is formed early
+    double *d_tmpN = nullptr, *d_tmpN2 = nullptr;  // n_nodes
     bool have_Flast = false;
     double* d_partials = nullptr;  // 4 * max_blocks doubles
     int64_t max_blocks = 0;
@@ -416,8 +418,12 @@ void prof_release(eqs_ctx* c);
 // drivers (solver.cpp)
 // mx_in (may be NULL): M y for the incoming y (see pcg_init); mx_out (may be
 // NULL): receives M y for the returned y.
+// before_sync (may be NULL): queued work the caller wants behind the residual
+// check, called each time before the host waits for that check (again after a
+// restart, so it acts on the final solution).
 int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st,
-            const double* mx_in = nullptr, double* mx_out = nullptr);
+            const double* mx_in = nullptr, double* mx_out = nullptr,
+            const std::function<void()>* before_sync = nullptr);
 int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double rtol, int32_t maxit,
              eqs_step_stats* st);
 void apply_preconditioner(eqs_ctx* c, const double* r, double* z);

@@ -1169,8 +1169,8 @@ void upload(eqs_ctx* c) {
     auto vec = [&](int64_t n) { return (double*)dev_alloc(c, sizeof(double) * (size_t)n); };
     c->d_r = vec(NF); c->d_z = vec(NF); c->d_p = vec(NF); c->d_q = vec(NF); c->d_mx = vec(NF);
     c->mx_of_F = false;
-    c->d_Y0 = vec(NF); c->d_Ya = vec(NF); c->d_Yb = vec(NF); c->d_F0 = vec(NF); c->d_F = vec(NF);
-    c->d_rhs = vec(NF); c->d_tmpN = vec(N); c->d_tmpN2 = vec(N);
+    c->d_Y0 = vec(NF); c->d_Ya = vec(NF); c->d_Yb = vec(NF); c->d_Yc = vec(NF); c->d_F0 = vec(NF); c->d_F = vec(NF);
+    c->d_rhs = vec(NF); c->d_rhs_alt = vec(NF); c->d_tmpN = vec(N); c->d_tmpN2 = vec(N);
     c->max_blocks = (std::max<int64_t>(N, T) + kBlock - 1) / kBlock + 1;
     c->d_partials = vec(8 * c->max_blocks);
     c->d_scal = (PcgScalars*)dev_alloc(c, sizeof(PcgScalars) * (size_t)c->n_inst);
@@ -1217,8 +1217,8 @@ void free_device(eqs_ctx* c) {
     c->d_ddrive = nullptr; c->d_int_to_user = nullptr; c->d_drives = nullptr;
     c->d_r = c->d_z = c->d_p = c->d_q = c->d_mx = nullptr;
     c->mx_of_F = false;
-    c->d_Y0 = c->d_Ya = c->d_Yb = c->d_F0 = c->d_F = nullptr;
-    c->d_rhs = c->d_tmpN = c->d_tmpN2 = nullptr;
+    c->d_Y0 = c->d_Ya = c->d_Yb = c->d_Yc = c->d_F0 = c->d_F = nullptr;
+    c->d_rhs = c->d_rhs_alt = c->d_tmpN = c->d_tmpN2 = nullptr;
     c->d_partials = nullptr;
     c->d_scal = nullptr;
     c->built = false;

@@ -9,6 +9,7 @@
 // between iterations; once done, further kernels exit at entry.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 
 #include "eqs_internal.h"
 
@@ -71,7 +72,7 @@ void release_graphs(eqs_ctx* c) {
 // disagree restart from them. Aggregated stats: max iterations, worst status,
 // max relres; per-instance results are in c->inst_iters / c->inst_relres.
 int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st,
-            const double* mx_in, double* mx_out) {
+            const double* mx_in, double* mx_out, const std::function<void()>* before_sync) {
     hipStream_t s = c->stream;
     const int prec = c->amg.precision;
     pcg_init(s, c, rhs, y, maxit, rtol, c->amg.flexible, mx_in);
@@ -137,8 +138,17 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
         // or broken down): check the true residuals (queued behind any iteration
         // still in flight, unless already queued above); disagreeing ones restart
         if (!checked) pcg_true_residual(s, c, rhs, y, mx_out);
-        check_launch();
-        EQS_HIP(hipStreamSynchronize(s));
+        if (before_sync) {
+            // the host waits for the check only; the caller's work queued behind
+            // it keeps the GPU busy meanwhile
+            EQS_HIP(hipEventRecord(c->ev[0], s));
+            (*before_sync)();
+            check_launch();
+            EQS_HIP(hipEventSynchronize(c->ev[0]));
+        } else {
+            check_launch();
+            EQS_HIP(hipStreamSynchronize(s));
+        }
         v = read_summary(c);
         if (v.all_done || ++restarts > 4) break;
     }
@@ -183,9 +193,18 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
     const double* Ycur = c->d_Y0;
     const double* Yprev = c->d_Y0;
     bool rhs_zeroed = false;  // the last combination cleared d_rhs for this stage's element pass
+    bool rhs_ready = false;   // this stage's element pass already ran (queued behind the last solve)
+    // With the plain start vector the host queues the rest of the stage (F_0
+    // copy, combination) and the next stage's element pass behind the residual
+    // check that ends each solve, before it waits for that check: the GPU then
+    // works through the host's round trip. The combination writes a third
+    // buffer (no operand is overwritten) and the next element pass writes
+    // d_rhs_alt, so a restart of the solve only has to queue them again.
+    const bool early = c->guess.p.kind == EQS_GUESS_PREVIOUS;
+    double* const ybuf[3] = {c->d_Ya, c->d_Yb, c->d_Yc};
     for (int j = 0; j < s; ++j) {
         const double tj = t + cc[j] * dt;
-        launch_kx(q, true, c, Ycur, tj, c->d_rhs, rhs_zeroed);
+        if (!rhs_ready) launch_kx(q, true, c, Ycur, tj, c->d_rhs, rhs_zeroed);
         check_launch();
         // start vector: F_{j-1} (held in d_F), zero, or an estimator's vector
         const int kind = c->guess.p.kind;
@@ -196,12 +215,35 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
             if (u == 1) S.guess_used++;
             guess_train(c);  // MLP: overlaps the solve below
         }
+        double* out = ybuf[0];
+        for (double* b : ybuf)
+            if (b != Ycur && b != Yprev) {
+                out = b;
+                break;
+            }
+        const bool next = j + 1 < s;
+        // the rest of the stage: F_0, Y_{j+1} (clearing the next element pass's
+        // output), and with `early` that pass itself
+        auto rest = [&]() {
+            if (j == 0) launch_copy(q, c->d_F0, c->d_F, NF);
+            double* zero = next ? (early ? c->d_rhs_alt : c->d_rhs) : nullptr;
+            if (j == 0) {
+                launch_rkc_first(c, q, out, c->d_Y0, c->d_F0, mut[1] * dt, NF, zero);
+            } else {
+                const int k = j + 1;
+                launch_rkc_combine(c, q, out, c->d_Y0, Ycur, Yprev, c->d_F, c->d_F0, 1.0 - mu[k] - nu[k], mu[k],
+                                   nu[k], mut[k] * dt, gmt[k] * dt, NF, zero);
+            }
+            if (early && next) launch_kx(q, true, c, out, t + cc[j + 1] * dt, c->d_rhs_alt, true);
+        };
+        const std::function<void()> rest_fn = rest;
         // F_j = M^{-1} r_j. Started from F_{j-1} itself, the start residual
         // reuses M F_{j-1} from the check that ended the previous solve.
         eqs_solve_stats ss{};
         const bool reuse = kind == EQS_GUESS_PREVIOUS && c->mx_of_F;
         c->mx_of_F = false;
-        const int src = solve_M(c, c->d_rhs, c->d_F, rtol, maxit, &ss, reuse ? c->d_mx : nullptr, c->d_mx);
+        const int src = solve_M(c, c->d_rhs, c->d_F, rtol, maxit, &ss, reuse ? c->d_mx : nullptr, c->d_mx,
+                                early ? &rest_fn : nullptr);
         c->mx_of_F = src == EQS_OK || src == EQS_ERR_NOT_CONVERGED;
         if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP || kind == EQS_GUESS_MOR) guess_after_solve(c, ss.iters);
         S.total_iters += ss.iters;
@@ -216,22 +258,11 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
             c->have_Flast = false;
             return src;
         }
-        if (j == 0) launch_copy(q, c->d_F0, c->d_F, NF);
-        double* out;
-        // d_rhs (this stage's right-hand side) is no longer needed: the
-        // combination clears it for the next stage's element pass
-        double* zero = (j + 1 < s) ? c->d_rhs : nullptr;
-        if (j == 0) {
-            out = c->d_Ya;
-            launch_rkc_first(c, q, out, c->d_Y0, c->d_F0, mut[1] * dt, NF, zero);
-        } else {
-            out = (Ycur == c->d_Ya) ? c->d_Yb : c->d_Ya;  // for j >= 2 this buffer holds Y_{j-1}
-            const int k = j + 1;
-            launch_rkc_combine(c, q, out, c->d_Y0, Ycur, Yprev, c->d_F, c->d_F0, 1.0 - mu[k] - nu[k], mu[k], nu[k],
-                               mut[k] * dt, gmt[k] * dt, NF, zero);
-        }
-        rhs_zeroed = zero != nullptr;
+        if (!early) rest();
         check_launch();
+        if (early && next) std::swap(c->d_rhs, c->d_rhs_alt);  // the next stage's RHS is ready
+        rhs_ready = early && next;
+        rhs_zeroed = !early && next;
         Yprev = Ycur;
         Ycur = out;
     }
