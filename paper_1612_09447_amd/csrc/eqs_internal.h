@@ -303,9 +303,9 @@ struct eqs_ctx {
     bool index16 = true;   // 16-bit column offsets for SELL operators whose entries allow them
     bool autotune = true;  // time the candidate layouts of every AMG operator at build time
     bool fold = true;       // fold pre-smoothers into restrictions and the lowest two levels into two products
-    int force_layout = -1;
+    int force_layout = -1;      // >= 1: SELL with that many lanes per row, 0: CSR, for every coarse operator
     bool force_sorted = false;  // with force_layout >= 1: sorted rows where allowed
-    bool tune_verbose = false;  // the tuner log lists every candidate's time  // >= 1: SELL with that many lanes per row, 0: CSR, for every coarse operator
+    bool tune_verbose = false;  // the tuner log lists every candidate's time
     std::string tune_log;  // chosen layouts, one line per operator
 
     // start vectors
