@@ -16,7 +16,7 @@ the same steps, the roofline of the dominant kernel from per-launch HIP events
 in an instrumented window that follows the timed steps, optionally
 (--learned-steps) every start vector over a common window and (--c3-steps) the
 64-instance batched workload, and the FP64 CPU oracle timed on one stage of the
-same workload (cpu_baseline). --gpus N > 1 exits: this build runs on one GPU.
+same workload (cpu_baseline). --gpus N > 1 exits: the library runs on one GPU.
 """
 
 from __future__ import annotations
@@ -348,8 +348,8 @@ def main():
 
     os.environ["EQS_USE_GRAPHS"] = "1" if args.graphs else "0"
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design note, not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1 "
+                                   "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
 
     import eqsgen
