@@ -285,6 +285,23 @@ typedef struct eqs_guess_params {
  * snapshot window, the replay buffer and (for MLP) the network. */
 int eqs_set_guess(eqs_ctx *ctx, const eqs_guess_params *p);
 
+/* The Galerkin start vector of eq. (5) (Sec. IV) on a window the caller
+ * gives: x0 = V (V^T M V)^{-1} V^T r, V the POD basis of the k columns of S
+ * (directions with singular values below 1e-7 of the largest dropped) and
+ * V^T M V formed from R = M S (no product with M is taken here). The same
+ * basis, reduced matrix and coefficient solve as a stage's
+ * EQS_GUESS_GALERKIN start vector in eqs_rkc_step.
+ * S_dev, R_dev: device, k x n_free doubles (column a at offset a * n_free,
+ * oldest first), 1 <= k <= 16; r_dev, x0_dev: device, n_free doubles; x0
+ * may not overlap S, R or r. Device pointers are borrowed for the call.
+ * *m_out (host, may be NULL) receives the number of directions kept; with
+ * none kept or a singular reduced matrix x0 = 0 and *m_out = 0. Runs on
+ * the context's stream with its start-vector scratch and returns when x0
+ * is written. Errors: EQS_ERR_INVALID_ARG (NULL, k, overlap),
+ * EQS_ERR_STATE (before eqs_build_preconditioner). */
+int eqs_galerkin_start(eqs_ctx *ctx, int32_t k, const double *S_dev, const double *R_dev, const double *r_dev,
+                       double *x0_dev, int32_t *m_out);
+
 /* ---- the start-vector network on its own ------------------------------
  * Multilayer perceptron 32 -> 64 -> 64 -> 16, SiLU hidden activations,
  * linear output, mean-squared-error loss, Adam (beta1 0.9, beta2 0.999,

@@ -104,6 +104,7 @@ _SIGNATURES = {
     "eqs_solve_M": ([_P, _P, _P, C.c_double, C.c_int32, _P], C.c_int),
     "eqs_rkc_step": ([_P, C.c_double, C.c_double, C.c_int32, _P, C.c_double, C.c_int32, _P], C.c_int),
     "eqs_set_guess": ([_P, _P], C.c_int),
+    "eqs_galerkin_start": ([_P, C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_int32)], C.c_int),
     "eqs_set_instances": ([_P, C.c_int32, _P, _P], C.c_int),
     "eqs_instance_stats": ([_P, C.c_int32, _P, _P], C.c_int),
     "eqs_batch_create": ([C.POINTER(_P), C.c_int32, _P, C.c_int, _P, _P], C.c_int),
@@ -353,6 +354,17 @@ class Context:
             keep = _flat_params(init)
             p.init = keep.ctypes.data_as(_P)
         _check(lib().eqs_set_guess(self._h, C.byref(p)), "eqs_set_guess")
+
+    def galerkin_start(self, S, R, r, x0):
+        """Eq. (5) on the window S (k x n_free, oldest first) with R = M S; writes
+        x0 and returns the number of POD directions kept."""
+        nf = self.info()["n_free"]
+        if S.dim() != 2 or tuple(R.shape) != tuple(S.shape) or S.shape[1] != nf or r.numel() != nf or x0.numel() != nf:
+            raise ValueError(f"galerkin_start: S and R must be k x {nf}, r and x0 hold {nf} values")
+        m = C.c_int32(0)
+        _check(lib().eqs_galerkin_start(self._h, int(S.shape[0]), _dev(S), _dev(R), _dev(r), _dev(x0), C.byref(m)),
+               "eqs_galerkin_start")
+        return int(m.value)
 
 
 def _flat_params(params):

@@ -3,6 +3,7 @@
 // records a thread-local message on failure.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -405,6 +406,33 @@ int eqs_set_guess(eqs_ctx* c, const eqs_guess_params* p) {
         if (a.kind >= EQS_GUESS_GALERKIN && c->inst_node_off.size() > 2)
             fail(EQS_ERR_STATE, "Galerkin and network start vectors need a single instance");
         eqs::guess_configure(c, a);
+        return EQS_OK;
+    });
+}
+
+// [a, a + na) and [b, b + nb) share an element
+static bool overlaps(const double* a, int64_t na, const double* b, int64_t nb) {
+    const uintptr_t a0 = (uintptr_t)a, a1 = a0 + sizeof(double) * (uintptr_t)na;
+    const uintptr_t b0 = (uintptr_t)b, b1 = b0 + sizeof(double) * (uintptr_t)nb;
+    return a0 < b1 && b0 < a1;
+}
+
+int eqs_galerkin_start(eqs_ctx* c, int32_t k, const double* S_dev, const double* R_dev, const double* r_dev,
+                       double* x0_dev, int32_t* m_out) {
+    return guarded([&] {
+        need(c != nullptr && S_dev != nullptr && R_dev != nullptr && r_dev != nullptr && x0_dev != nullptr,
+             "NULL argument");
+        need(k >= 1 && k <= 16, "k must be in [1, 16]");
+        need_built(c);
+        const int64_t NF = c->n_free;
+        need(NF > 0, "no free nodes");
+        need(!overlaps(x0_dev, NF, S_dev, (int64_t)k * NF) && !overlaps(x0_dev, NF, R_dev, (int64_t)k * NF) &&
+                 !overlaps(x0_dev, NF, r_dev, NF),
+             "x0 must not overlap S, R or r");
+        bind_device(c);
+        const int m = eqs::guess_galerkin_explicit(c, k, S_dev, R_dev, r_dev, x0_dev);
+        EQS_HIP(hipStreamSynchronize(c->stream));
+        if (m_out) *m_out = m;
         return EQS_OK;
     });
 }

@@ -403,6 +403,7 @@ void guess_configure(eqs_ctx* c, const eqs_guess_params& p);
 void guess_release(eqs_ctx* c);
 void guess_reset(eqs_ctx* c);
 int guess_stage(eqs_ctx* c);
+int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R, const double* r, double* x0);
 void guess_after_solve(eqs_ctx* c, int32_t iters);
 void guess_train(eqs_ctx* c);
 double guess_last_loss(eqs_ctx* c);

@@ -245,6 +245,11 @@ void guess_configure(eqs_ctx* c, const eqs_guess_params& p) {
 void guess_alloc_device(eqs_ctx* c) {
     GuessState& g = c->guess;
     const int64_t NF = c->n_free;
+    // buffers of an earlier configuration of this context (eqs_set_guess again)
+    // go first; the training stream was drained when that one was released
+    for (void* p : {(void*)g.d_S, (void*)g.d_rprev, (void*)g.d_alpha, (void*)g.d_dots, (void*)g.d_part,
+                    (void*)g.d_guard, (void*)g.d_gstat, (void*)g.d_bx, (void*)g.d_bt})
+        dev_free(c, p);
     g.d_S = (double*)dev_alloc(c, sizeof(double) * (size_t)kMaxWin * NF);
     g.d_rprev = (double*)dev_alloc(c, sizeof(double) * NF);
     g.d_alpha = (double*)dev_alloc(c, sizeof(double) * kMaxWin);
@@ -327,6 +332,76 @@ static double norm(const std::vector<double>& v) {
     double s = 0.0;
     for (double x : v) s += x * x;
     return std::sqrt(s);
+}
+
+// Eq. (5) on the basis V = S B: solve (V^T M V) c = V^T r with V^T M V = K and
+// V^T r from r's dots with the window slots (rslot), then alpha = B c on the
+// slots. False (coef untouched) if no direction is kept or K is singular.
+static bool galerkin_coef(const Basis& B, const std::vector<double>& K, const double* rslot, Coef16& coef) {
+    const int n = (int)B.slot.size(), m = B.m;
+    std::vector<double> cvec = project(B, rslot);
+    if (m == 0 || !dense_solve(m, K, cvec)) return false;
+    for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < m; ++k) acc += B.B[(size_t)i * m + k] * cvec[k];
+        coef.v[B.slot[i]] = acc;
+    }
+    return true;
+}
+
+// Eq. (5) on a window given by the caller (k columns of S, oldest first, with
+// R = M S): G = S^T S and H = S^T R from k passes of the window-dots kernel,
+// S^T r from one more, then the basis, reduced matrix and coefficient solve of
+// a stage's GALERKIN start vector and x0 = S alpha. Returns the number of
+// directions kept (0: x0 = 0). Uses the start-vector scratch on c->stream.
+int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R, const double* r, double* x0) {
+    GuessState& gs = c->guess;
+    if (!gs.dev_ready) guess_alloc_device(c);
+    hipStream_t s = c->stream;
+    const int64_t NF = c->n_free;
+    GuessState g;  // window bookkeeping only: slots 0..k-1, slot 0 the oldest
+    g.p.window = k;
+    g.count = k;
+    g.oldest = 0;
+    g.G.assign(kMaxWin * kMaxWin, 0.0);
+    g.H.assign(kMaxWin * kMaxWin, 0.0);
+    std::vector<double> rs(kMaxWin, 0.0);
+    const unsigned grid = (unsigned)std::min<int64_t>(kDotGrid, (NF + kBlock - 1) / kBlock);
+    double dots[kNDots];
+    for (int a = 0; a <= k; ++a) {
+        // u = s_a, v = r_a (column a of G and H); the last pass u = v = r
+        const double* u = a < k ? S + (int64_t)a * NF : r;
+        const double* v = a < k ? R + (int64_t)a * NF : r;
+        hipLaunchKernelGGL(k_window_dots, dim3(grid), dim3(kBlock), 0, s, const_cast<double*>(S), NF, k, -1, u, v, v,
+                           NF, gs.d_part);
+        hipLaunchKernelGGL(k_sum_rows, dim3(kNDots), dim3(kBlock), 0, s, gs.d_part, (int64_t)kDotGrid, (int)grid,
+                           gs.d_dots);
+        EQS_HIP(hipMemcpyAsync(dots, gs.d_dots, sizeof dots, hipMemcpyDeviceToHost, s));
+        EQS_HIP(hipStreamSynchronize(s));
+        for (int b = 0; b < k; ++b) {
+            if (a < k) {
+                g.G[b * kMaxWin + a] = dots[2 * b];      // s_b . s_a
+                g.H[b * kMaxWin + a] = dots[2 * b + 1];  // s_b . M s_a
+            } else {
+                rs[b] = dots[2 * b];  // s_b . r
+            }
+        }
+    }
+    for (int a = 0; a < k; ++a)  // both are symmetric; each pair was summed twice
+        for (int b = a + 1; b < k; ++b) {
+            const double gv = 0.5 * (g.G[a * kMaxWin + b] + g.G[b * kMaxWin + a]);
+            const double hv = 0.5 * (g.H[a * kMaxWin + b] + g.H[b * kMaxWin + a]);
+            g.G[a * kMaxWin + b] = g.G[b * kMaxWin + a] = gv;
+            g.H[a * kMaxWin + b] = g.H[b * kMaxWin + a] = hv;
+        }
+    const Basis B = window_basis(g);
+    const std::vector<double> K = reduced_matrix(g, B);
+    Coef16 coef{};
+    const bool ok = galerkin_coef(B, K, rs.data(), coef);
+    const unsigned pg = (unsigned)((NF + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_window_prolong, dim3(pg), dim3(kBlock), 0, s, S, NF, k, coef, nullptr, x0, NF);
+    EQS_HIP(hipGetLastError());
+    return ok ? B.m : 0;
 }
 
 // One stage's start vector. Called after the element pass wrote r_j into
@@ -434,15 +509,7 @@ int guess_stage(eqs_ctx* c) {
                 g.mor_K = K;
             }
         }
-        const int n = (int)B.slot.size(), m = B.m;
-        std::vector<double> cvec = project(B, g.rdots.data());  // V^T r_j
-        have = m > 0 && dense_solve(m, K, cvec);
-        if (have)
-            for (int i = 0; i < n; ++i) {
-                double acc = 0.0;
-                for (int k = 0; k < m; ++k) acc += B.B[(size_t)i * m + k] * cvec[k];
-                coef.v[B.slot[i]] = acc;
-            }
+        have = galerkin_coef(B, K, g.rdots.data(), coef);  // r_j's dots with the slots give V^T r_j
     } else if (g.p.kind == EQS_GUESS_MLP) {
         const Basis B = window_basis(g);
         const std::vector<double> a = project(B, &g.G[e * kMaxWin]);  // V^T F_{j-1}

@@ -136,3 +136,70 @@ def test_start_vector_kinds_keep_the_result_and_galerkin_beats_previous():
     assert iters["galerkin"] < iters["previous"] < iters["zero"]
     assert iters["mlp"] < iters["previous"]  # what the trained network gains over the plain method
     assert iters["mor"] < iters["zero"] and iters["mor2"] < iters["zero"]
+
+
+def test_galerkin_start_vector_matches_oracle():
+    """Eq. (5) through eqs_galerkin_start (the coefficient solve of a stage's
+    Galerkin start vector) against the oracle's POD basis and reduced solve, on
+    windows of seeded vectors: full rank (every direction kept), one exactly
+    dependent column (one direction dropped) and a single column (closed form
+    s (s^T r) / (s^T M s)); Galerkin orthogonality S^T (r - M x0) = 0 holds."""
+    from oracle.guess import galerkin_start, pod_from_gram
+
+    from paper_1612_09447_amd import EqsError
+
+    case = eqsgen.case_c1(n=12, seed=1)
+    o = EqsOracle(case)
+    nf = o.n_free
+    rng = np.random.default_rng(11)
+    base = rng.standard_normal((nf, 6))
+    windows = {
+        "full": base,
+        "dependent": np.column_stack([base[:, :4], base[:, 0] + 2.0 * base[:, 2], base[:, 4]]),
+        "single": base[:, :1],
+    }
+    r = rng.standard_normal(nf)
+    with Context(0, torch.cuda.current_stream(DEV)) as c:
+        c.setup_case(case, precision=EQS_PREC_FP64)
+        rd = torch.from_numpy(r).to(DEV)
+        for label, S in windows.items():
+            k = S.shape[1]
+            R = o.M_II @ S
+            Sd = torch.from_numpy(np.ascontiguousarray(S.T)).to(DEV)
+            Rd = torch.from_numpy(np.ascontiguousarray(R.T)).to(DEV)
+            x0 = torch.full((nf,), float("nan"), dtype=torch.float64, device=DEV)
+            m = c.galerkin_start(Sd, Rd, rd, x0)
+            got = x0.cpu().numpy()
+            V, sig, _ = pod_from_gram(S, 16)
+            want = galerkin_start(V, o.M_II, r)
+            err = np.linalg.norm(got - want) / np.linalg.norm(want)
+            orth = np.linalg.norm(S.T @ (r - o.M_II @ got)) / (np.linalg.norm(S, axis=0).max() * np.linalg.norm(r))
+            print(f"[galerkin] {label}: k {k}, kept {m} (oracle {V.shape[1]}), rel err {err:.2e}, "
+                  f"orthogonality {orth:.2e}", flush=True)
+            assert m == V.shape[1] == {"full": 6, "dependent": 5, "single": 1}[label]
+            assert err <= 1e-10, (label, err)
+            assert orth <= 1e-11, (label, orth)
+            if label == "single":
+                s = S[:, 0]
+                closed = s * (s @ r) / (s @ (o.M_II @ s))
+                assert np.linalg.norm(got - closed) <= 1e-12 * np.linalg.norm(closed)
+        # x0 over its own window is refused before any launch
+        with pytest.raises(EqsError):
+            c.galerkin_start(Sd, Rd, rd, Sd[0])
+
+
+def test_setting_the_start_vector_again_keeps_device_memory():
+    """eqs_set_guess on a context that already ran guessed stages replaces the
+    window buffers instead of adding new ones (device_bytes stays put)."""
+    case = eqsgen.case_c1(n=10, seed=1)
+    case.s = 8
+    with Context(0, torch.cuda.current_stream(DEV)) as c:
+        c.setup_case(case, precision=EQS_PREC_FP64)
+        x = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+        sizes = []
+        for n, kind in enumerate(["galerkin", "mor", "galerkin"]):
+            c.set_guess(kind)
+            c.rkc_step(n * case.tau, case.tau, case.s, x, rtol=1e-10, maxit=500)
+            sizes.append(c.info()["device_bytes"])
+        print(f"[guess] device bytes after each setting: {sizes}", flush=True)
+        assert sizes[0] == sizes[1] == sizes[2]
