@@ -116,6 +116,10 @@ def test_error_paths_without_device():
     assert b"NULL" in L.eqs_last_error()
     assert L.eqs_destroy(None) == binding.EQS_OK
     assert L.eqs_last_error() == b""
+    # a NULL context is refused before any device work
+    assert L.eqs_apply_M(None, None, None) == binding.EQS_ERR_INVALID_ARG
+    assert L.eqs_galerkin_start(None, 1, None, None, None, None, None) == binding.EQS_ERR_INVALID_ARG
+    assert b"NULL" in L.eqs_last_error()
     with pytest.raises(pkg.EqsError) as ei:
         pkg.Context(0)
     assert ei.value.code == binding.EQS_ERR_HIP
