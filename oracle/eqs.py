@@ -39,7 +39,19 @@ def drive_rates(amp, freq, phase, t):
 class EqsOracle:
     """FP64 reference for one EQS instance (a ``eqsgen.Case``)."""
 
-    def __init__(self, case, solve_rtol: float = 1e-13, dense_limit: int = DENSE_LIMIT):
+    def __init__(self, case, solve_rtol: float = 1e-13, dense_limit: int = DENSE_LIMIT, solver: str = "sgs",
+                 warm: bool = False, threads=None):
+        """solver: "sgs" (serial symmetric Gauss-Seidel PCG) or "jacobi"
+        (Jacobi PCG on OpenMP threads) for systems above dense_limit.
+        warm: start every stage solve from the previous one's solution (the
+        plain start vector of Sec. IV's multiple right-hand-side setting); the
+        result still meets solve_rtol, so only the iteration count changes."""
+        if solver not in ("sgs", "jacobi"):
+            raise ValueError("solver must be 'sgs' or 'jacobi'")
+        self.solver = solver
+        self.warm = warm
+        self.threads = threads
+        self._prev = None
         self.case = case
         n = case.n_nodes
         is_dir = np.zeros(n, dtype=bool)
@@ -96,18 +108,26 @@ class EqsOracle:
         return self.b(t) - kx
 
     def solve(self, r, x0=None):
-        """y = M_II^{-1} r (dense Cholesky, or SGS-PCG to solve_rtol)."""
+        """y = M_II^{-1} r (dense Cholesky, or PCG to solve_rtol from x0)."""
         if self.dense:
             self.last_iters = 0
             return sla.cho_solve(self._chol, r)
-        res = fem.pcg_sgs(self.M_II, r, x0=x0, rtol=self.solve_rtol)
+        if self.solver == "jacobi":
+            res = fem.pcg_jacobi(self.M_II, r, x0=x0, rtol=self.solve_rtol, threads=self.threads)
+        else:
+            res = fem.pcg_sgs(self.M_II, r, x0=x0, rtol=self.solve_rtol)
         if res.status != 0:
             raise RuntimeError("oracle PCG failed: status %d relres %g" % (res.status, res.relres))
         self.last_iters = res.iters
         return res.x
 
     def F(self, t, Y):
-        return self.solve(self.stage_rhs(t, Y))
+        """F(t, Y) = M_II^{-1}(b(t) - [K(x_bar)x_bar]_I); with ``warm`` the
+        solve starts from the previous evaluation's result."""
+        y = self.solve(self.stage_rhs(t, Y), x0=self._prev if self.warm else None)
+        if self.warm:
+            self._prev = y
+        return y
 
     # -- integrators -------------------------------------------------------
     def euler_step(self, t, Y, tau):

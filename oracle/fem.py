@@ -42,6 +42,8 @@ def lib():
         L.orc_csr_matvec.restype = None
         L.orc_pcg_sgs.argtypes = [i64, P, P, P, P, P, C.c_double, C.c_int32, P, P]
         L.orc_pcg_sgs.restype = C.c_int
+        L.orc_pcg_jacobi.argtypes = [i64, P, P, P, P, P, C.c_double, C.c_int32, C.c_int32, P, P]
+        L.orc_pcg_jacobi.restype = C.c_int
         _lib = L
     return _lib
 
@@ -165,4 +167,30 @@ def pcg_sgs(A: sp.csr_matrix, rhs, x0=None, rtol=1e-13, maxit=100000) -> PcgResu
     it = np.zeros(1, dtype=np.int32)
     rr = np.zeros(1)
     st = lib().orc_pcg_sgs(n, _p(rowptr), _p(col), _p(val), _p(rhs), _p(x), rtol, maxit, _p(it), _p(rr))
+    return PcgResult(x, int(it[0]), float(rr[0]), int(st))
+
+
+def default_threads() -> int:
+    """Threads for the Jacobi-PCG reference solver: OMP_NUM_THREADS if set,
+    else the CPUs this process may run on."""
+    v = os.environ.get("OMP_NUM_THREADS", "")
+    if v.isdigit() and int(v) > 0:
+        return int(v)
+    return max(1, len(os.sched_getaffinity(0)))
+
+
+def pcg_jacobi(A: sp.csr_matrix, rhs, x0=None, rtol=1e-13, maxit=1000000, threads=None) -> PcgResult:
+    """Jacobi-preconditioned CG to a true relative residual rtol (same CG loop
+    as pcg_sgs; row loops on ``threads`` OpenMP threads)."""
+    A = A.tocsr()
+    n = A.shape[0]
+    rowptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+    col = _i32(A.indices)
+    val = _f64(A.data)
+    rhs = _f64(rhs)
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    it = np.zeros(1, dtype=np.int32)
+    rr = np.zeros(1)
+    nt = default_threads() if threads is None else int(threads)
+    st = lib().orc_pcg_jacobi(n, _p(rowptr), _p(col), _p(val), _p(rhs), _p(x), rtol, maxit, nt, _p(it), _p(rr))
     return PcgResult(x, int(it[0]), float(rr[0]), int(st))

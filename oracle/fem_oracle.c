@@ -8,6 +8,9 @@
  * or calls this file; only the tests, the smoke check and the CPU-baseline
  * leg of the benchmark load it. It is written for reading, not for speed:
  * single-threaded element loops, one tet at a time, no blocking or fusion.
+ * Only the Jacobi-preconditioned CG may spread its row loops over OpenMP
+ * threads, so that reference trajectories on the 2.1M-unknown mesh finish
+ * in minutes.
  *
  * Model (eq. (1)): div(kappa grad phi) + div(eps grad d(phi)/dt) = 0 with
  * P1 (linear) tetrahedral elements. On element e with vertices p0..p3 the
@@ -286,9 +289,15 @@ int orc_element_kappa(const double *xyz, int64_t n_tets, const int32_t *tets, co
 
 /* ------------------------------------------------------------- CSR algebra */
 
-void orc_csr_matvec(int64_t n_rows, const int64_t *rowptr, const int32_t *col, const double *val,
-                    const double *x, double *y)
+/* The CSR products, dot products and vector updates below run their loops
+ * over rows with OpenMP when nthreads > 1 (each row or entry computed
+ * exactly as in the serial loop; only the summation order of a dot product
+ * changes). nthreads <= 1 keeps them serial. */
+
+static void csr_matvec_t(int64_t n_rows, const int64_t *rowptr, const int32_t *col, const double *val,
+                         const double *x, double *y, int nthreads)
 {
+#pragma omp parallel for schedule(static) num_threads(nthreads) if (nthreads > 1)
     for (int64_t i = 0; i < n_rows; ++i) {
         double s = 0.0;
         for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
@@ -297,9 +306,16 @@ void orc_csr_matvec(int64_t n_rows, const int64_t *rowptr, const int32_t *col, c
     }
 }
 
-static double dot(int64_t n, const double *a, const double *b)
+void orc_csr_matvec(int64_t n_rows, const int64_t *rowptr, const int32_t *col, const double *val,
+                    const double *x, double *y)
+{
+    csr_matvec_t(n_rows, rowptr, col, val, x, y, 1);
+}
+
+static double dot(int64_t n, const double *a, const double *b, int nthreads)
 {
     double s = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : s) num_threads(nthreads) if (nthreads > 1)
     for (int64_t i = 0; i < n; ++i)
         s += a[i] * b[i];
     return s;
@@ -307,7 +323,7 @@ static double dot(int64_t n, const double *a, const double *b)
 
 /* z = SGS(r): symmetric Gauss-Seidel, a forward sweep from z = 0 and a
  * backward sweep; z = (D+U)^{-1} D (D+L)^{-1} r, symmetric positive definite
- * for an SPD matrix. */
+ * for an SPD matrix. Serial by nature. */
 static void sgs_apply(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                       const double *diag, const double *r, double *z)
 {
@@ -327,16 +343,26 @@ static void sgs_apply(int64_t n, const int64_t *rowptr, const int32_t *col, cons
     }
 }
 
+/* z = D^{-1} r (Jacobi). */
+static void jacobi_apply(int64_t n, const double *diag, const double *r, double *z, int nthreads)
+{
+#pragma omp parallel for schedule(static) num_threads(nthreads) if (nthreads > 1)
+    for (int64_t i = 0; i < n; ++i)
+        z[i] = r[i] / diag[i];
+}
+
+enum { PREC_SGS = 0, PREC_JACOBI = 1 };
+
 /* Preconditioned CG (Saad, Iterative Methods for Sparse Linear Systems,
- * Alg. 9.1) with the symmetric Gauss-Seidel preconditioner. x holds the start
- * vector on entry and the solution on exit. Stops when the true relative
- * residual |rhs - A x| / |rhs| <= rtol (the recursive residual triggers the
- * check; if the true one disagrees the recurrence restarts from it).
- * |rhs| = 0 gives x = 0 with no iterations. Returns 0 when converged, 1 when
- * maxit was reached, -1 on breakdown (p.Ap <= 0), -2 on allocation failure. */
-int orc_pcg_sgs(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
-                const double *rhs, double *x, double rtol, int32_t maxit, int32_t *iters_out,
-                double *relres_out)
+ * Alg. 9.1) with the symmetric Gauss-Seidel or the Jacobi preconditioner.
+ * x holds the start vector on entry and the solution on exit. Stops when the
+ * true relative residual |rhs - A x| / |rhs| <= rtol (the recursive residual
+ * triggers the check; if the true one disagrees the recurrence restarts from
+ * it). |rhs| = 0 gives x = 0 with no iterations. Returns 0 when converged,
+ * 1 when maxit was reached, -1 on breakdown (p.Ap <= 0), -2 on allocation
+ * failure, -3 for a non-positive diagonal entry. */
+static int pcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, const double *rhs,
+               double *x, double rtol, int32_t maxit, int prec, int nt, int32_t *iters_out, double *relres_out)
 {
     double *diag = malloc((size_t)n * sizeof(double));
     double *r = malloc((size_t)n * sizeof(double));
@@ -347,24 +373,28 @@ int orc_pcg_sgs(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
         free(diag); free(r); free(z); free(p); free(q);
         return -2;
     }
+    int status = 0;
     for (int64_t i = 0; i < n; ++i) {
         diag[i] = 0.0;
         for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
             if (col[k] == i)
                 diag[i] = val[k];
+        if (!(diag[i] > 0.0))
+            status = -3;
     }
-    int status = 0;
     int32_t it = 0;
     double relres = 0.0;
-    double bnorm = sqrt(dot(n, rhs, rhs));
-    if (bnorm == 0.0) {
+    double bnorm = sqrt(dot(n, rhs, rhs, nt));
+    if (status != 0) {
+        /* not SPD: nothing to iterate */
+    } else if (bnorm == 0.0) {
         for (int64_t i = 0; i < n; ++i)
             x[i] = 0.0;
     } else {
-        orc_csr_matvec(n, rowptr, col, val, x, q);
+        csr_matvec_t(n, rowptr, col, val, x, q, nt);
         for (int64_t i = 0; i < n; ++i)
             r[i] = rhs[i] - q[i];
-        relres = sqrt(dot(n, r, r)) / bnorm;
+        relres = sqrt(dot(n, r, r, nt)) / bnorm;
         double rho_prev = 0.0;
         int restart = 1;
         while (relres > rtol) {
@@ -372,35 +402,40 @@ int orc_pcg_sgs(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
                 status = 1;
                 break;
             }
-            sgs_apply(n, rowptr, col, val, diag, r, z);
-            double rho = dot(n, r, z);
+            if (prec == PREC_SGS)
+                sgs_apply(n, rowptr, col, val, diag, r, z);
+            else
+                jacobi_apply(n, diag, r, z, nt);
+            double rho = dot(n, r, z, nt);
             if (restart) {
                 memcpy(p, z, (size_t)n * sizeof(double));
             } else {
                 double beta = rho / rho_prev;
+#pragma omp parallel for schedule(static) num_threads(nt) if (nt > 1)
                 for (int64_t i = 0; i < n; ++i)
                     p[i] = z[i] + beta * p[i];
             }
             restart = 0;
-            orc_csr_matvec(n, rowptr, col, val, p, q);
-            double pq = dot(n, p, q);
+            csr_matvec_t(n, rowptr, col, val, p, q, nt);
+            double pq = dot(n, p, q, nt);
             if (!(pq > 0.0)) {
                 status = -1;
                 break;
             }
             double alpha = rho / pq;
+#pragma omp parallel for schedule(static) num_threads(nt) if (nt > 1)
             for (int64_t i = 0; i < n; ++i) {
                 x[i] += alpha * p[i];
                 r[i] -= alpha * q[i];
             }
             rho_prev = rho;
             ++it;
-            relres = sqrt(dot(n, r, r)) / bnorm;
+            relres = sqrt(dot(n, r, r, nt)) / bnorm;
             if (relres <= rtol) {
-                orc_csr_matvec(n, rowptr, col, val, x, q);
+                csr_matvec_t(n, rowptr, col, val, x, q, nt);
                 for (int64_t i = 0; i < n; ++i)
                     r[i] = rhs[i] - q[i];
-                relres = sqrt(dot(n, r, r)) / bnorm;
+                relres = sqrt(dot(n, r, r, nt)) / bnorm;
                 restart = 1;
             }
         }
@@ -411,4 +446,23 @@ int orc_pcg_sgs(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
         *relres_out = relres;
     free(diag); free(r); free(z); free(p); free(q);
     return status;
+}
+
+/* CG with symmetric Gauss-Seidel preconditioning, single-threaded. */
+int orc_pcg_sgs(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                const double *rhs, double *x, double rtol, int32_t maxit, int32_t *iters_out,
+                double *relres_out)
+{
+    return pcg(n, rowptr, col, val, rhs, x, rtol, maxit, PREC_SGS, 1, iters_out, relres_out);
+}
+
+/* CG with Jacobi preconditioning; products, dots and updates on nthreads
+ * OpenMP threads (the reference solver for the large meshes, where the
+ * serial SGS sweeps would take minutes per solve). */
+int orc_pcg_jacobi(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                   const double *rhs, double *x, double rtol, int32_t maxit, int32_t nthreads,
+                   int32_t *iters_out, double *relres_out)
+{
+    return pcg(n, rowptr, col, val, rhs, x, rtol, maxit, PREC_JACOBI, nthreads < 1 ? 1 : nthreads, iters_out,
+               relres_out);
 }

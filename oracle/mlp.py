@@ -32,36 +32,49 @@ def silu_grad(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(p, x):
-    """Returns the output [B,16] and the cache of pre-activations."""
-    h1 = x @ p["W1"].T + p["b1"]
+def _q(a, bf16):
+    """A matmul operand: rounded to bfloat16 in the BF16 form, else as is."""
+    return round_bf16(a) if bf16 else a
+
+
+def forward(p, x, bf16=False):
+    """Returns the output [B,16] and the cache of pre-activations.
+
+    bf16: the BF16 form of the network (BF16 weights with FP32 accumulation):
+    both operands of every matrix product, the weights and the layer inputs,
+    are rounded to bfloat16 first; biases and the sums are not."""
+    h1 = _q(x, bf16) @ _q(p["W1"], bf16).T + p["b1"]
     a1 = silu(h1)
-    h2 = a1 @ p["W2"].T + p["b2"]
+    h2 = _q(a1, bf16) @ _q(p["W2"], bf16).T + p["b2"]
     a2 = silu(h2)
-    y = a2 @ p["W3"].T + p["b3"]
+    y = _q(a2, bf16) @ _q(p["W3"], bf16).T + p["b3"]
     return y, (x, h1, a1, h2, a2)
 
 
-def loss(p, x, t):
-    y, _ = forward(p, x)
+def loss(p, x, t, bf16=False):
+    y, _ = forward(p, x, bf16)
     return float(np.mean((y - t) ** 2))
 
 
-def backward(p, x, t):
-    """Loss and gradients of L = mean((y - t)^2) over batch and outputs."""
-    y, (x, h1, a1, h2, a2) = forward(p, x)
+def backward(p, x, t, bf16=False):
+    """Loss and gradients of L = mean((y - t)^2) over batch and outputs.
+
+    bf16: as in forward, every operand of the backward matrix products (the
+    output error, the layer errors, the activations, the inputs and the
+    weights) is rounded to bfloat16; the bias gradients sum unrounded errors."""
+    y, (x, h1, a1, h2, a2) = forward(p, x, bf16)
     B, K = y.shape
     dy = 2.0 * (y - t) / (B * K)
     g = {}
-    g["W3"] = dy.T @ a2
+    g["W3"] = _q(dy, bf16).T @ _q(a2, bf16)
     g["b3"] = dy.sum(axis=0)
-    da2 = dy @ p["W3"]
+    da2 = _q(dy, bf16) @ _q(p["W3"], bf16)
     dh2 = da2 * silu_grad(h2)
-    g["W2"] = dh2.T @ a1
+    g["W2"] = _q(dh2, bf16).T @ _q(a1, bf16)
     g["b2"] = dh2.sum(axis=0)
-    da1 = dh2 @ p["W2"]
+    da1 = _q(dh2, bf16) @ _q(p["W2"], bf16)
     dh1 = da1 * silu_grad(h1)
-    g["W1"] = dh1.T @ x
+    g["W1"] = _q(dh1, bf16).T @ _q(x, bf16)
     g["b1"] = dh1.sum(axis=0)
     return float(np.mean((y - t) ** 2)), g
 

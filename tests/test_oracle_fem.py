@@ -175,6 +175,42 @@ def test_pcg_sgs_matches_dense_solve():
     assert bad.status == 1 and bad.iters == 1
 
 
+@pytest.mark.parametrize("threads", [1, 4])
+def test_pcg_jacobi_matches_dense_solve(threads):
+    """The Jacobi-preconditioned CG (the reference solver for the large meshes,
+    row loops on OpenMP threads) against numpy's dense solve, on one thread
+    and on several."""
+    case = _perturbed(eqsgen.case_c1(n=6, seed=3), seed=4)
+    o = EqsOracle(case, dense_limit=0, solver="jacobi", threads=threads)
+    rng = np.random.default_rng(1)
+    r = rng.normal(size=o.n_free)
+    ref = np.linalg.solve(o.M_II.toarray(), r)
+    res = fem.pcg_jacobi(o.M_II, r, rtol=1e-13, threads=threads)
+    assert res.status == 0 and res.relres <= 1e-13
+    assert np.linalg.norm(res.x - ref) <= 1e-10 * np.linalg.norm(ref)
+    np.testing.assert_allclose(o.solve(r), ref, rtol=0, atol=1e-10 * abs(ref).max())
+    # a start vector is honoured: the exact solution needs no iteration
+    ex = fem.pcg_jacobi(o.M_II, r, x0=res.x, rtol=1e-12, threads=threads)
+    assert ex.iters == 0 and np.array_equal(ex.x, res.x)
+    z = fem.pcg_jacobi(o.M_II, np.zeros(o.n_free), x0=np.ones(o.n_free), threads=threads)
+    assert z.iters == 0 and not z.x.any()
+    bad = fem.pcg_jacobi(o.M_II, r, rtol=1e-15, maxit=1, threads=threads)
+    assert bad.status == 1 and bad.iters == 1
+
+
+def test_warm_started_trajectory_equals_cold_sgs():
+    """Warm starts (each stage solve from the previous solution) and the Jacobi
+    solver change only iteration counts: the RKC trajectory equals the one with
+    cold-started SGS solves to well below the parity bars."""
+    case = eqsgen.case_c1(n=12, seed=1)
+    a = EqsOracle(case, dense_limit=0)
+    b = EqsOracle(case, dense_limit=0, solver="jacobi", warm=True, threads=2)
+    ya = a.rkc_trajectory(np.zeros(a.n_free), 0.0, case.tau, case.s, 3)
+    yb = b.rkc_trajectory(np.zeros(b.n_free), 0.0, case.tau, case.s, 3)
+    scale = max(np.linalg.norm(y) for y in ya)
+    assert max(np.linalg.norm(p - q) for p, q in zip(ya, yb)) <= 1e-12 * scale
+
+
 def test_dirichlet_rhs_is_capacitive_coupling():
     """b(t) = -M_ID g'(t): with uniform eps the discrete harmonic extension of
     the top drive is exactly z on the free nodes (linear functions are in the

@@ -131,3 +131,88 @@ def test_round_bf16_matches_torch():
                         np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -(1.0 + 2 ** -8), 0.0, -0.0])])
     ref = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(mlp.round_bf16(a), ref)
+
+
+def _torch_net(p, bf16):
+    """The network written out in torch float64 (an implementation independent
+    of the oracle's): torch's SiLU, explicit products, torch's bfloat16
+    conversion for the BF16 form's operands."""
+    torch = pytest.importorskip("torch")
+    P = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in p.items()}
+
+    def q(a):
+        return a.to(torch.float32).to(torch.bfloat16).to(torch.float64) if bf16 else a
+
+    def fwd(x):
+        a1 = torch.nn.functional.silu(torch.mm(q(x), q(P["W1"]).t()) + P["b1"])
+        a2 = torch.nn.functional.silu(torch.mm(q(a1), q(P["W2"]).t()) + P["b2"])
+        return torch.mm(q(a2), q(P["W3"]).t()) + P["b3"]
+
+    return P, fwd
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_mlp_forward_matches_torch_float64(bf16):
+    """The oracle's forward (both forms) equals the network written in torch."""
+    torch = pytest.importorskip("torch")
+    p = _params(11)
+    rng = np.random.default_rng(12)
+    x = rng.normal(size=(40, 32)) * 2.0
+    _, fwd = _torch_net(p, bf16)
+    ref = fwd(torch.tensor(x)).detach().numpy()
+    y, _ = mlp.forward(p, x, bf16=bf16)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    if bf16:
+        # the rounding matters: the BF16 form differs from the FP64 network
+        y64, _ = mlp.forward(p, x)
+        assert np.abs(y - y64).max() > 1e-4 * np.abs(y64).max()
+
+
+def test_mlp_gradients_match_torch_autograd():
+    """The oracle's backward equals torch's automatic differentiation of the
+    mean-squared error of the same network, in float64."""
+    torch = pytest.importorskip("torch")
+    p = _params(13)
+    rng = np.random.default_rng(14)
+    x, t = rng.normal(size=(24, 32)), rng.normal(size=(24, 16))
+    P, fwd = _torch_net(p, False)
+    L = torch.mean((fwd(torch.tensor(x)) - torch.tensor(t)) ** 2)
+    L.backward()
+    Lo, g = mlp.backward(p, x, t)
+    assert Lo == pytest.approx(L.item(), rel=1e-14)
+    for k in mlp.NAMES:
+        ref = P[k].grad.numpy()
+        np.testing.assert_allclose(g[k], ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_mlp_bf16_gradients_near_exact_ones():
+    """The BF16 form's gradients (products of rounded operands) stay within a
+    few bfloat16 unit roundoffs (2^-8) of the exact gradients."""
+    p = _params(15)
+    rng = np.random.default_rng(16)
+    x, t = rng.normal(size=(64, 32)), rng.normal(size=(64, 16))
+    _, g = mlp.backward(p, x, t)
+    _, gb = mlp.backward(p, x, t, bf16=True)
+    for k in mlp.NAMES:
+        r = np.linalg.norm(gb[k] - g[k]) / np.linalg.norm(g[k])
+        assert 1e-5 < r < 4 * 2.0 ** -8, (k, r)
+
+
+def test_adam_matches_torch_optimizer():
+    """Five Adam steps of the oracle equal torch.optim.Adam in float64 with the
+    same gradients (lr 1e-3, betas 0.9 / 0.999, eps 1e-8)."""
+    torch = pytest.importorskip("torch")
+    p = _params(17)
+    rng = np.random.default_rng(18)
+    P = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in p.items()}
+    opt = torch.optim.Adam([P[k] for k in mlp.NAMES], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    q = {k: v.copy() for k, v in p.items()}
+    st = mlp.adam_state(q)
+    for _ in range(5):
+        g = {k: rng.normal(size=v.shape) * 10.0 ** rng.uniform(-6, 0) for k, v in p.items()}
+        for k in mlp.NAMES:
+            P[k].grad = torch.tensor(g[k])
+        opt.step()
+        mlp.adam_step(q, g, st, lr=1e-3)
+    for k in mlp.NAMES:
+        np.testing.assert_allclose(q[k], P[k].detach().numpy(), rtol=0, atol=1e-14)
