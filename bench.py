@@ -150,6 +150,8 @@ def mixed_learned_vs_fp64(plain, learned, full):
     if full and "mlp" in full and plain.get("steps") == full["mlp"]["steps"]:
         out["value"] = round(full["mlp"]["stages_per_s"] / plain["stages_per_s"], 3)
         out["basis"] = f"whole runs of {plain['steps']} steps: FP32 form + network start vector vs plain FP64"
+        if "error_vs_fp64" in full["mlp"]:
+            out["error_vs_fp64"] = full["mlp"]["error_vs_fp64"]
     if learned and "mlp" in learned:
         net = learned["mlp"]["stages_per_s"] / learned["previous"]["stages_per_s"]
         out["window_product"] = round(net * plain["fp32_form_speedup"], 3)
@@ -167,15 +169,53 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-SINGLE_KERNEL_CLASSES = ("element", "spmv_M", "presmooth0", "postsmooth0", "cg_update", "rkc_combine")
-ALL_CLASSES = SINGLE_KERNEL_CLASSES + ("vcycle",)
-KERNEL_NAMES = {"element": "k_kx<true>", "spmv_M": "k_pcg_spmv", "presmooth0": "k_presmooth_res (finest)",
-                "postsmooth0": "k_postsmooth (finest)", "cg_update": "k_pcg_update", "rkc_combine": "k_rkc_combine"}
+# kernel classes timed one launch at a time (each launch is one kernel)
+SINGLE_KERNEL_CLASSES = ("element", "spmv_M", "presmooth0", "postsmooth0", "restrict0", "prolong0", "cg_update",
+                         "rkc_combine")
+# classes spanning several kernels (bracketed by events on the stream)
+MULTI_KERNEL_CLASSES = ("vcycle", "vcoarse", "finalise")
+ALL_CLASSES = SINGLE_KERNEL_CLASSES + MULTI_KERNEL_CLASSES
+KERNEL_NAMES = {"element": "k_kx<true> (element pass)", "spmv_M": "k_pcg_spmv", "presmooth0": "k_presmooth_res (finest)",
+                "postsmooth0": "k_postsmooth (finest)", "restrict0": "k_sell_mv (finest restriction R0)",
+                "prolong0": "k_sell_mv (finest prolongation P0)", "cg_update": "k_pcg_update",
+                "rkc_combine": "k_rkc_first / k_rkc_combine"}
 
 
-def timed_steps(ctx, x, n, steps, tau, s, rtol, label):
+def class_bytes(info, s_stages):
+    """Algorithmic bytes per launch of every single-kernel class: each array
+    the kernel must touch, once, at its own width (4 B per index; hierarchy
+    values 4 B in the FP32 form, 8 B in FP64; CG vectors 8 B)."""
+    n = info["n_free"]
+    w = 4 if info["precision"] == 1 else 8
+    rows, nnz = info["level_rows"], info["level_nnz"]
+    pn, rn = info["level_p_nnz"], info["level_r_nnz"]
+    n0 = rows[0]
+    out = {
+        "element": element_bytes(info),
+        "spmv_M": spmv_bytes(info, info["nnz_M"]),
+        "cg_update": 48 * n,  # x, r read and written; p, q read
+        # Y_j from Y_0, Y_{j-1}, Y_{j-2}, F_{j-1}, F_0 (the first stage: Y_0, F_0),
+        # the next stage's element-pass output cleared (not after the last)
+        "rkc_combine": (32 + 56 * (s_stages - 2) + 48) * n // s_stages,
+        # x = w D^-1 r, res = r - A w D^-1 r: operator, r (FP64), dinv, x, res
+        "presmooth0": (w + 4) * nnz[0] + 4 * (n0 // 64 + 1) + n0 * (8 + 3 * w),
+        # z = x + w D^-1 (r - A x) with r.z and r.z_old: operator, x gathered,
+        # dinv, r (FP64), z_old read, z written
+        "postsmooth0": (w + 4) * nnz[0] + 4 * (n0 // 64 + 1) + n0 * (2 * w + 24),
+    }
+    if len(rows) > 1:
+        n1 = rows[1]
+        out["restrict0"] = (w + 4) * rn[0] + 4 * (n1 + 1) + w * n0 + w * n1  # R0, res read, b_1 written
+        out["prolong0"] = (w + 4) * pn[0] + 4 * (n0 + 1) + w * n1 + 2 * w * n0  # P0, x_1 read, x_0 updated
+    return out
+
+
+def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None):
     """Run `steps` RKC steps from step index n; returns (elapsed s, per-step
-    mean CG iterations per stage, guesses used, guard fallbacks)."""
+    mean CG iterations per stage, guesses used, guard fallbacks). With `hist`
+    (a device tensor [steps, n_nodes]) every step-end state is copied into it
+    on the same stream (a device copy of one vector per step, inside the timed
+    loop)."""
     import torch
 
     torch.cuda.synchronize()
@@ -183,6 +223,8 @@ def timed_steps(ctx, x, n, steps, tau, s, rtol, label):
     iters, used, fallbacks = [], 0, 0
     for k in range(steps):
         st = ctx.rkc_step((n + k) * tau, tau, s, x, rtol=rtol, maxit=500)
+        if hist is not None:
+            hist[k].copy_(x)
         iters.append(st["total_iters"] / st["stages"])
         used += st["guess_used"]
         fallbacks += st["guess_fallbacks"]
@@ -193,7 +235,7 @@ def timed_steps(ctx, x, n, steps, tau, s, rtol, label):
 
 
 def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous", flexible=0, learned_steps=0,
-            learned_warmup=20, mlp_batch=128):
+            learned_warmup=20, mlp_batch=128, keep_states=False):
     """Time `steps` RKC steps (uninstrumented), then `prof_steps` more with every
     kernel class timed by HIP events on the context's stream. With
     learned_steps > 0 the same context then switches to the Galerkin and the
@@ -222,7 +264,8 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
     for _ in range(warmup):
         ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
         n += 1
-    elapsed, iters, used, fallbacks = timed_steps(ctx, x, n, steps, tau, s, rtol, f"{precision}/{guess}")
+    hist = torch.empty((steps, case.n_nodes), dtype=torch.float64, device=dev) if keep_states else None
+    elapsed, iters, used, fallbacks = timed_steps(ctx, x, n, steps, tau, s, rtol, f"{precision}/{guess}", hist)
     n += steps
     x_timed = x.cpu().numpy()  # state after warmup + timed steps (compared across precisions)
     prof, prof_elapsed = {}, 0.0
@@ -259,7 +302,21 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         ctx.set_guess("previous")
     ctx.close()
     return dict(elapsed=elapsed, stages=steps * s, iters=iters, info=info, prof=prof, prof_elapsed=prof_elapsed,
-                prof_stages=prof_steps * s, setup_s=setup_s, x=x_timed, used=used, fallbacks=fallbacks, learned=learned)
+                prof_stages=prof_steps * s, setup_s=setup_s, x=x_timed, used=used, fallbacks=fallbacks, learned=learned,
+                hist=hist)
+
+
+def state_errors(hist, ref, free):
+    """Error of every step-end state against the FP64 path's state at the same
+    step, over the free nodes: the trajectory norm max_n |x_n - x_n^ref| /
+    max_n |x_n^ref|, and the largest per-step ratio |x_n - x_n^ref| / |x_n^ref|."""
+    import torch
+
+    d = torch.linalg.vector_norm((hist - ref)[:, free], dim=1)
+    r = torch.linalg.vector_norm(ref[:, free], dim=1)
+    return {"traj_rel_err": float(f"{float(d.max() / r.max()):.3e}"),
+            "max_step_rel_err": float(f"{float((d / r.clamp_min(1e-300)).max()):.3e}"),
+            "steps_compared": int(hist.shape[0])}
 
 
 def run_batched(steps, warmup):
@@ -303,24 +360,24 @@ def run_batched(steps, warmup):
             "precision": "FP64 CG + K(x)x, FP32 AMG", "setup_s": round(setup_s, 1)}
 
 
-def cpu_baseline(case):
-    """The oracle, as it stands, on one stage of the workload (single thread)."""
-    import numpy as np
-
+def cpu_baseline(case, x_user, step):
+    """The oracle, as it stands, on one stage of the workload (single thread):
+    F(t_n, Y_n) at the state the GPU run reached after `step` steps."""
     from oracle.eqs import EqsOracle
 
     t0 = time.perf_counter()
     orc = EqsOracle(case, solve_rtol=case.rtol)
     log(f"[bench] oracle setup {time.perf_counter() - t0:.1f}s")
+    t = step * case.tau
     t1 = time.perf_counter()
-    orc.F(0.0, np.zeros(orc.n_free))  # one stage: K(x)x over all tets + one SGS-PCG solve of M
+    orc.F(t, x_user[orc.free])  # one stage: K(x)x over all tets + one SGS-PCG solve of M
     dt = time.perf_counter() - t1
     log(f"[bench] oracle stage {dt:.1f}s ({orc.last_iters} SGS-PCG iterations)")
     return dict(value=1.0 / dt, unit="stages/s", cores=1, kind="oracle",
-                sample=f"stage 0 of step 0 (t=0, phi=0): one element pass over {case.n_tets} tets + one "
-                       f"SGS-PCG solve of M to rel-res {case.rtol:g} from a zero start "
-                       f"({orc.last_iters} iterations), {dt:.1f} s on 1 of {os.cpu_count()} cores "
-                       f"({cpu_model()})")
+                sample=f"stage 0 of step {step} (t={t:g} s, from the state the GPU run reached there): one "
+                       f"element pass over {case.n_tets} tets + one SGS-PCG solve of M to rel-res {case.rtol:g} "
+                       f"from a zero start ({orc.last_iters} iterations), {dt:.1f} s on 1 of {os.cpu_count()} "
+                       f"cores ({cpu_model()})")
 
 
 def main():
@@ -366,69 +423,79 @@ def main():
     rd = read_probe()
     log(f"[bench] copy probe: {copy}; read probe: {rd}")
     r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess,
-                flexible=args.flexible, learned_steps=args.learned_steps, mlp_batch=args.mlp_batch)
+                flexible=args.flexible, learned_steps=args.learned_steps, mlp_batch=args.mlp_batch,
+                keep_states=True)
     stages_per_s = r["stages"] / r["elapsed"]
     info = r["info"]
     prof = r["prof"]
 
-    # roofline of the dominant single kernel (largest summed time in the instrumented window)
-    per_class_bytes = {
-        "element": element_bytes(info),
-        "spmv_M": spmv_bytes(info, info["nnz_M"]),
-    }
+    # roofline of the dominant single kernel: the class with the largest summed
+    # time in the instrumented window
+    per_class_bytes = class_bytes(info, case.s)
     roofline, breakdown = None, None
     if prof:
-        dominant = max(per_class_bytes, key=lambda k: prof[k]["total_ms"])
-        avg_s = prof[dominant]["avg_ms"] * 1e-3
-        achieved = per_class_bytes[dominant] / avg_s / 1e9
-        roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dominant],
-                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dominant),
-                    "frac_of_copy": round(achieved / copy["GB/s"], 4),
-                    "frac_of_read": round(achieved / rd["GB/s"], 4),
-                    "bytes_per_launch": per_class_bytes[dominant], "avg_launch_us": round(avg_s * 1e6, 2),
-                    "timing": f"start/stop events of every launch (hipExtLaunchKernelGGL) on the context stream, "
-                              f"{args.prof_steps} instrumented steps following the timed ones"}
         rooflines = {}
         for k, nbytes in per_class_bytes.items():
+            if not prof[k]["launches"]:
+                continue
             a = nbytes / (prof[k]["avg_ms"] * 1e-3) / 1e9
             rooflines[k] = {"kernel": KERNEL_NAMES[k], "achieved": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4),
                             "avg_launch_us": round(prof[k]["avg_ms"] * 1e3, 2), "bytes_per_launch": nbytes,
+                            "launches": prof[k]["launches"], "total_ms": round(prof[k]["total_ms"], 3),
                             "traffic": measured_traffic(k)}
-        roofline["per_kernel"] = rooflines
+        dominant = max(rooflines, key=lambda k: prof[k]["total_ms"])
+        d = rooflines[dominant]
+        roofline = {"bound": "hbm", "kernel": d["kernel"], "class": dominant,
+                    "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": d["frac"], "traffic": d["traffic"],
+                    "frac_of_copy": round(d["achieved"] / copy["GB/s"], 4),
+                    "frac_of_read": round(d["achieved"] / rd["GB/s"], 4),
+                    "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_launch_us"],
+                    "timing": f"start/stop events of every launch (hipExtLaunchKernelGGL) on the context stream, "
+                              f"{args.prof_steps} instrumented steps following the timed ones",
+                    "per_kernel": rooflines}
         breakdown = {k: {"launches": v["launches"], "avg_us": round(v["avg_ms"] * 1e3, 2),
                          "share_of_instrumented": round(v["total_ms"] * 1e-3 / r["prof_elapsed"], 4)}
                      for k, v in prof.items()}
 
+    import torch
+
+    free = torch.ones(case.n_nodes, dtype=torch.bool, device="cuda:0")
+    free[torch.as_tensor(case.dir_nodes, dtype=torch.int64, device="cuda:0")] = False
     plain = None
     plain_steps = args.steps if args.plain_steps < 0 else args.plain_steps
+    ref_hist = None
     if plain_steps > 0 and main_prec != EQS_PREC_FP64:
-        p = run_gpu(case, EQS_PREC_FP64, plain_steps, args.warmup, case.rtol)
+        p = run_gpu(case, EQS_PREC_FP64, plain_steps, args.warmup, case.rtol, keep_states=plain_steps == args.steps)
         plain = {"stages_per_s": round(p["stages"] / p["elapsed"], 2),
                  "mean_cg_iters_per_stage": round(sum(p["iters"]) / len(p["iters"]), 2),
-                 "steps": plain_steps,
-                 "rel_diff_of_final_state_vs_fp32_form": None}
+                 "steps": plain_steps}
         if plain_steps == args.steps:
-            import numpy as np
-
-            d = np.linalg.norm(r["x"] - p["x"]) / max(np.linalg.norm(p["x"]), 1e-300)
-            plain["rel_diff_of_final_state_vs_fp32_form"] = float(f"{d:.3e}")
+            ref_hist = p["hist"]
             plain["fp32_form_speedup"] = round(stages_per_s / plain["stages_per_s"], 3)
+            plain["fp32_form_error_vs_fp64"] = state_errors(r["hist"], ref_hist, free)
+    r["hist"] = None
 
     # whole runs with the estimator start vectors, same steps as the main run
     full = {}
     for kind in [k for k in args.full_runs.split(",") if k]:
-        f = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, guess=kind, mlp_batch=args.mlp_batch)
+        f = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, guess=kind, mlp_batch=args.mlp_batch,
+                    keep_states=ref_hist is not None)
         full[kind] = {"stages_per_s": round(f["stages"] / f["elapsed"], 2),
                       "mean_cg_iters_per_stage": round(sum(f["iters"]) / len(f["iters"]), 2),
                       "steps": args.steps, "guess_used": f["used"], "guard_fallbacks": f["fallbacks"],
                       "vs_plain_start": round(f["stages"] / f["elapsed"] / stages_per_s, 3)}
+        if ref_hist is not None:
+            full[kind]["error_vs_fp64"] = state_errors(f["hist"], ref_hist, free)
+        f["hist"] = None
+    ref_hist = None
+    torch.cuda.empty_cache()
 
     batched = run_batched(args.c3_steps, 1) if args.c3_steps > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(case)
+        cpu = cpu_baseline(case, r["x"], args.warmup + args.steps)
         cpu["value"] = round(cpu["value"], 6)
 
     out = {

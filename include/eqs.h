@@ -125,7 +125,10 @@ typedef struct eqs_info {
     int32_t n_levels;     /* AMG levels including the coarsest (0 before build) */
     int32_t precision;
     int64_t level_rows[16];
-    int64_t level_nnz[16];
+    int64_t level_nnz[16];   /* nonzeros of the level operator A_l */
+    int64_t level_p_nnz[16]; /* nonzeros of the prolongation P_l (level l+1 -> l; 0 on the coarsest) */
+    int64_t level_r_nnz[16]; /* nonzeros of the restriction applied at level l (R_l = P_l^T, or
+                                R_l (I - A_l w D_l^-1) where the pre-smoother is folded in) */
     int64_t device_bytes; /* device memory held by the context */
 } eqs_info;
 
@@ -331,7 +334,11 @@ enum {
     EQS_KCLASS_VCYCLE = 4,      /* one whole V-cycle */
     EQS_KCLASS_CG_UPDATE = 5,   /* x += alpha p, r -= alpha q (+ |r|^2) */
     EQS_KCLASS_RKC_COMBINE = 6, /* RKC stage combination */
-    EQS_KCLASS_COUNT = 7
+    EQS_KCLASS_RESTRICT0 = 7,   /* finest restriction b_1 = R_0 res (one product) */
+    EQS_KCLASS_PROLONG0 = 8,    /* finest prolongation x_0 += P_0 x_1 (one product) */
+    EQS_KCLASS_VCOARSE = 9,     /* all V-cycle work below the finest level (several kernels) */
+    EQS_KCLASS_FINALISE = 10,   /* the one-block CG finalisers (three launches per iteration) */
+    EQS_KCLASS_COUNT = 11
 };
 
 /* Enable timing of the classes whose bits are set in class_mask (bit k =

@@ -85,7 +85,8 @@ GUESS_KINDS = {"previous": EQS_GUESS_PREVIOUS, "zero": EQS_GUESS_ZERO, "galerkin
 class eqs_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("n_free", C.c_int64), ("nnz_M", C.c_int64),
                 ("n_levels", C.c_int32), ("precision", C.c_int32), ("level_rows", C.c_int64 * 16),
-                ("level_nnz", C.c_int64 * 16), ("device_bytes", C.c_int64)]
+                ("level_nnz", C.c_int64 * 16), ("level_p_nnz", C.c_int64 * 16), ("level_r_nnz", C.c_int64 * 16),
+                ("device_bytes", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -131,6 +132,10 @@ KCLASS = {
     "vcycle": 4,
     "cg_update": 5,
     "rkc_combine": 6,
+    "restrict0": 7,
+    "prolong0": 8,
+    "vcoarse": 9,
+    "finalise": 10,
 }
 
 _lib = None
@@ -287,6 +292,7 @@ class Context:
         L = o.n_levels
         return dict(n_nodes=o.n_nodes, n_tets=o.n_tets, n_free=o.n_free, nnz_M=o.nnz_M, n_levels=L,
                     precision=o.precision, level_rows=list(o.level_rows[:L]), level_nnz=list(o.level_nnz[:L]),
+                    level_p_nnz=list(o.level_p_nnz[:L]), level_r_nnz=list(o.level_r_nnz[:L]),
                     device_bytes=o.device_bytes)
 
     def describe(self) -> str:

@@ -85,6 +85,12 @@ int eqs_create(eqs_ctx** out, int device, void* hip_stream) {
         c->tune_verbose = tv && std::string(tv) == "all";
         const char* fo = std::getenv("EQS_FOLD");  // "0": the plain V-cycle (no folded operators)
         c->fold = !(fo && fo[0] == '0');
+        // test knobs: "1" runs the element pass with each block's own LDS stride;
+        // "1" rejects the first true-residual check of every solve (restart path)
+        const char* kg = std::getenv("EQS_KX_GENERIC");
+        c->kx_generic = kg && kg[0] == '1';
+        const char* rj = std::getenv("EQS_TEST_REJECT_CHECK");
+        c->test_reject_first = rj && rj[0] == '1';
         // "sell1", "sell2", "sell4", "sell8" or "csr": every AMG operator below
         // the finest level in that layout; "sell1s" etc. also sort the rows of
         // the operators used only in products (tests compare the layouts)
@@ -243,20 +249,18 @@ int eqs_query(const eqs_ctx* c, eqs_info* info) {
         o.n_free = c->built ? c->n_free : 0;
         o.nnz_M = c->nnz_M;
         o.precision = c->amg.precision;
-        if (c->built) {
-            if (c->amg.precision == EQS_PREC_FP32) {
-                o.n_levels = (int32_t)c->h32.lv.size();
-                for (size_t l = 0; l < c->h32.lv.size() && l < 16; ++l) {
-                    o.level_rows[l] = c->h32.lv[l].n;
-                    o.level_nnz[l] = c->h32.lv[l].A.nnz;
-                }
-            } else {
-                o.n_levels = (int32_t)c->h64.lv.size();
-                for (size_t l = 0; l < c->h64.lv.size() && l < 16; ++l) {
-                    o.level_rows[l] = c->h64.lv[l].n;
-                    o.level_nnz[l] = c->h64.lv[l].A.nnz;
-                }
+        auto levels = [&](const auto& h) {
+            o.n_levels = (int32_t)h.lv.size();
+            for (size_t l = 0; l < h.lv.size() && l < 16; ++l) {
+                o.level_rows[l] = h.lv[l].n;
+                o.level_nnz[l] = h.lv[l].A.nnz;
+                o.level_p_nnz[l] = h.lv[l].P.nnz;
+                o.level_r_nnz[l] = h.lv[l].R.nnz;
             }
+        };
+        if (c->built) {
+            if (c->amg.precision == EQS_PREC_FP32) levels(c->h32);
+            else levels(c->h64);
         }
         o.device_bytes = c->device_bytes;
         *info = o;
@@ -500,9 +504,10 @@ int eqs_describe(const eqs_ctx* c, char* buf, int64_t cap, int64_t* needed) {
                       c->amg.precision == EQS_PREC_FP32 ? "fp32" : "fp64", (int)c->built);
         d += line;
         std::snprintf(line, sizeof line,
-                      "element blocks %lld of %d tets, block nodes %lld (max %d), graphs %d, autotune %d\n",
+                      "element blocks %lld of %d tets, block nodes %lld (max %d), graphs %d, autotune %d%s\n",
                       (long long)c->n_blocks, eqs::kTetBlock * c->tet_tpt, (long long)c->n_block_nodes,
-                      c->max_block_nodes, (int)c->use_graphs, (int)c->autotune);
+                      c->max_block_nodes, (int)c->use_graphs, (int)c->autotune,
+                      c->kx_generic ? ", per-block LDS stride" : "");
         d += line;
         d += c->tune_log;
         if (needed) *needed = (int64_t)d.size() + 1;

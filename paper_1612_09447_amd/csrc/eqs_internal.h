@@ -306,6 +306,12 @@ struct eqs_ctx {
     int force_layout = -1;      // >= 1: SELL with that many lanes per row, 0: CSR, for every coarse operator
     bool force_sorted = false;  // with force_layout >= 1: sorted rows where allowed
     bool tune_verbose = false;  // the tuner log lists every candidate's time
+    // test knobs: the element pass with each block's own LDS stride (the path
+    // for blocks with more nodes than the fixed stride), and a forced restart
+    // at the first true-residual check of every solve
+    bool kx_generic = false;
+    bool test_reject_first = false;
+    int32_t* d_force = nullptr;
     std::string tune_log;  // chosen layouts, one line per operator
 
     // start vectors

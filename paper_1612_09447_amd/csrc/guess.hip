@@ -356,7 +356,9 @@ static bool galerkin_coef(const Basis& B, const std::vector<double>& K, const do
 // directions kept (0: x0 = 0). Uses the start-vector scratch on c->stream.
 int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R, const double* r, double* x0) {
     GuessState& gs = c->guess;
-    if (!gs.dev_ready) guess_alloc_device(c);
+    // only the dot-product scratch is needed here (not the stage window)
+    if (!gs.d_part) gs.d_part = (double*)dev_alloc(c, sizeof(double) * kNDots * kDotGrid);
+    if (!gs.d_dots) gs.d_dots = (double*)dev_alloc(c, sizeof(double) * 64);
     hipStream_t s = c->stream;
     const int64_t NF = c->n_free;
     GuessState g;  // window bookkeeping only: slots 0..k-1, slot 0 the oldest
@@ -398,10 +400,15 @@ int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R,
     const std::vector<double> K = reduced_matrix(g, B);
     Coef16 coef{};
     const bool ok = galerkin_coef(B, K, rs.data(), coef);
+    if (!ok) {  // no direction kept or a singular reduced matrix: x0 = 0 (not 0 * S, which keeps NaN)
+        launch_fill(s, x0, 0.0, NF);
+        EQS_HIP(hipGetLastError());
+        return 0;
+    }
     const unsigned pg = (unsigned)((NF + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_window_prolong, dim3(pg), dim3(kBlock), 0, s, S, NF, k, coef, nullptr, x0, NF);
     EQS_HIP(hipGetLastError());
-    return ok ? B.m : 0;
+    return B.m;
 }
 
 // One stage's start vector. Called after the element pass wrote r_j into

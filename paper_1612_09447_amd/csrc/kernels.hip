@@ -513,7 +513,7 @@ static void launch_kx_t(hipStream_t s, eqs_ctx* c, const double* yfree, double t
                    yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out};
     const dim3 b(kTetBlock), g((unsigned)c->n_blocks);
     const int tpt = c->tet_tpt;
-    const bool fixed = tpt >= 1 && c->max_block_nodes <= kx_fixed_stride(tpt);
+    const bool fixed = tpt >= 1 && c->max_block_nodes <= kx_fixed_stride(tpt) && !c->kx_generic;
     const size_t lds = sizeof(double) * 6 * (size_t)(fixed ? kx_fixed_stride(tpt) : c->max_block_nodes);
 #define EQS_KX(TPT_)                                                                                           \
     do {                                                                                                       \
@@ -794,6 +794,20 @@ static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int ac
     }
 }
 
+// launch_mv with the launch's own events when kernel class `cls` is profiled
+template <typename T>
+static void launch_mv_timed(hipStream_t s, eqs_ctx* c, int cls, const SpMat<T>& A, const T* x, T* y, int acc,
+                            const int32_t* stop) {
+    const MvInit<T> in{nullptr, nullptr, T(0)};
+    if (A.fmt == FMT_SELL) {
+        EQS_SELL_LANES_SWITCH(A.sell.lanes, EQS_LAUNCH_TIMED(c, cls, (k_sell_mv<L_, T>), dim3(sell_grid(A.sell)),
+                                                             dim3(kBlock), 0, s, view(A.sell), x, y, acc, in, stop));
+    } else {
+        EQS_LANES_SWITCH(A.lanes, EQS_LAUNCH_TIMED(c, cls, (k_csr_mv<L_, T>), dim3(csr_grid(A)), dim3(kBlock), 0, s,
+                                                   cview(A), x, y, acc, in, stop));
+    }
+}
+
 template <typename T, typename TB>
 static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, const int32_t* stop) {
     if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
@@ -958,8 +972,11 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         } else {
             launch_presmooth<T, T>(s, lv, (const T*)lv.b, stop);
         }
-        if (l + 1 < L - 1 || !h.lv[L - 1].coarse_R)
-            launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, stop);
+        if (l + 1 < L - 1 || !h.lv[L - 1].coarse_R) {
+            if (l == 0) launch_mv_timed<T>(s, c, EQS_KCLASS_RESTRICT0, lv.R, (const T*)lv.res, h.lv[1].b, 0, stop);
+            else launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, stop);
+        }
+        if (l == 0) prof_begin(c, EQS_KCLASS_VCOARSE, s);
     }
     {
         Level<T>& lc = h.lv[L - 1];
@@ -979,8 +996,11 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
             continue;
         }
         const T* xc = (l + 1 == L - 1) ? h.lv[l + 1].x : h.lv[l + 1].xs;
+        if (l == 0) prof_end(c, EQS_KCLASS_VCOARSE, s);
         if (lv.fold_pre)  // x = w D^-1 b (the folded pre-smoother's result) + P xc
             launch_mv<T>(s, lv.P, xc, lv.x, 2, stop, MvInit<T>{(const T*)lv.dinv, (const T*)lv.b, (T)lv.omega});
+        else if (l == 0)
+            launch_mv_timed<T>(s, c, EQS_KCLASS_PROLONG0, lv.P, xc, lv.x, 1, stop);
         else
             launch_mv<T>(s, lv.P, xc, lv.x, 1, stop);
         if (l > 0) {
@@ -1176,12 +1196,19 @@ __device__ void summarise(const PcgScalars* __restrict__ s, int32_t n, PcgSummar
 // mode 0: start of a solve (it = 0); mode 1: restart from the true residual
 // (iteration count kept; broken-down instances stay so). An instance is done
 // when |r| <= rtol |rhs|, rhs = 0, or its iteration budget is spent.
+// force (may be NULL): a one-shot flag for tests of the restart path; when
+// set, this check treats every instance as not yet converged (it then
+// continues from its true residual) and clears the flag.
 __global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, InstMap m, const double* __restrict__ prr,
                                                      const double* __restrict__ pbb, double rtol, int32_t maxit,
                                                      int32_t flexible, int32_t mode, PcgSummary* __restrict__ sum,
                                                      PcgSummary* __restrict__ host_sum,
-                                                     PcgScalars* __restrict__ host, int32_t when_done) {
+                                                     PcgScalars* __restrict__ host, int32_t when_done,
+                                                     int32_t* __restrict__ force) {
     if (when_done && !sum->all_done) return;  // pairs with k_pcg_residual's when_done
+    const int32_t forced = (mode == 1 && force) ? *force : 0;
+    __syncthreads();
+    if (forced && threadIdx.x == 0) *force = 0;
     const double* parts[2] = {prr, pbb};
     for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
         const double rr = v[0], bb = v[1];
@@ -1201,7 +1228,7 @@ __global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, 
         x.beta = 0.0;
         x.status = EQS_OK;
         x.done = 0;
-        if (bb == 0.0 || rr <= x.tol2) {
+        if (bb == 0.0 || (rr <= x.tol2 && !forced)) {
             x.done = 1;
         } else if (!isfinite(rr) || !isfinite(bb)) {
             x.done = 1;
@@ -1306,6 +1333,8 @@ __global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, I
     summarise(s, m.n_inst, sum, host_sum, host);
 }
 
+__global__ void k_set_flag(int32_t* __restrict__ p, int32_t v) { *p = v; }
+
 static double* part(eqs_ctx* c, int q) { return c->d_partials + (int64_t)q * 2 * c->max_blocks; }
 
 void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int32_t maxit, double rtol,
@@ -1318,7 +1347,8 @@ void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int
         hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
                            part(c, 0), part(c, 1), (double*)nullptr, (const int32_t*)nullptr);
     hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), rtol,
-                       maxit, flexible, 0, c->d_sum, c->d_hsum, c->d_hscal, 0);
+                       maxit, flexible, 0, c->d_sum, c->d_hsum, c->d_hscal, 0, (int32_t*)nullptr);
+    if (c->test_reject_first) hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, c->d_force, 1);
 }
 
 void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, double* mx_out,
@@ -1328,7 +1358,8 @@ void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const doubl
     hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
                        part(c, 0), part(c, 1), mx_out, done);
     hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), 0.0, 0,
-                       0, 1, c->d_sum, c->d_hsum, c->d_hscal, only_if_done ? 1 : 0);
+                       0, 1, c->d_sum, c->d_hsum, c->d_hscal, only_if_done ? 1 : 0,
+                       c->test_reject_first ? c->d_force : (int32_t*)nullptr);
 }
 
 void pcg_zero_rhs_rows(hipStream_t s, eqs_ctx* c, double* x) {
@@ -1346,14 +1377,16 @@ void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int 
     if (precision == EQS_PREC_FP32) vcycle<float>(s, c, c->h32, c->d_r, c->d_z, part(c, 0), part(c, 1), stop);
     else vcycle<double>(s, c, c->h64, c->d_r, c->d_z, part(c, 0), part(c, 1), stop);
     prof_end(c, EQS_KCLASS_VCYCLE, s);
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), stop);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, k_fin_beta, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c),
+                     part(c, 0), part(c, 1), stop);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_SPMV_M, k_pcg_spmv, dim3(nbM), dim3(kBlock), 0, s, view(c->M), inst_map(c),
                      c->d_z, c->d_p, c->d_q, part(c, 2), c->d_scal, stop);
-    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 2), stop);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, k_fin_alpha, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c),
+                     part(c, 2), stop);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_CG_UPDATE, k_pcg_update, dim3(nbV), dim3(kBlock), 0, s, inst_map(c), x, c->d_r,
                      c->d_p, c->d_q, c->n_free, part(c, 3), c->d_scal, stop);
-    hipLaunchKernelGGL(k_fin_conv, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 3), c->d_sum,
-                       c->d_hsum, c->d_hscal);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, k_fin_conv, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c),
+                     part(c, 3), c->d_sum, c->d_hsum, c->d_hscal);
 }
 
 // ------------------------------------------------------------------ RKC

@@ -1176,6 +1176,8 @@ void upload(eqs_ctx* c) {
     c->d_scal = (PcgScalars*)dev_alloc(c, sizeof(PcgScalars) * (size_t)c->n_inst);
     c->d_sum = (PcgSummary*)dev_alloc(c, sizeof(PcgSummary));
     EQS_HIP(hipMemset(c->d_sum, 0, sizeof(PcgSummary)));
+    c->d_force = (int32_t*)dev_alloc(c, sizeof(int32_t));
+    EQS_HIP(hipMemset(c->d_force, 0, sizeof(int32_t)));
     EQS_HIP(hipHostMalloc((void**)&c->h_scal, sizeof(PcgScalars) * (size_t)c->n_inst, hipHostMallocMapped));
     EQS_HIP(hipHostGetDevicePointer((void**)&c->d_hscal, c->h_scal, 0));
     EQS_HIP(hipHostMalloc((void**)&c->h_sum, sizeof(PcgSummary), hipHostMallocMapped));
@@ -1206,7 +1208,7 @@ void free_device(eqs_ctx* c) {
     c->device_bytes = 0;
     if (c->h_scal) { (void)hipHostFree(c->h_scal); c->h_scal = nullptr; c->d_hscal = nullptr; }
     if (c->h_sum) { (void)hipHostFree(c->h_sum); c->h_sum = nullptr; c->d_hsum = nullptr; }
-    c->d_sum = nullptr; c->d_inst_row = nullptr; c->d_blk_inst = nullptr;
+    c->d_sum = nullptr; c->d_inst_row = nullptr; c->d_blk_inst = nullptr; c->d_force = nullptr;
     for (auto& e : c->ev)
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
     c->M = Sell<double>{};

@@ -35,7 +35,9 @@ static void check_launch() {
 static void run_iteration(eqs_ctx* c, double* x, int prec) {
     const uint32_t iter_classes = (1u << EQS_KCLASS_SPMV_M) | (1u << EQS_KCLASS_PRESMOOTH0) |
                                   (1u << EQS_KCLASS_POSTSMOOTH0) | (1u << EQS_KCLASS_VCYCLE) |
-                                  (1u << EQS_KCLASS_CG_UPDATE);
+                                  (1u << EQS_KCLASS_CG_UPDATE) | (1u << EQS_KCLASS_RESTRICT0) |
+                                  (1u << EQS_KCLASS_PROLONG0) | (1u << EQS_KCLASS_VCOARSE) |
+                                  (1u << EQS_KCLASS_FINALISE);
     if (!c->use_graphs || c->stream == nullptr || (c->prof_mask & iter_classes)) {
         pcg_iteration(c->stream, c, nullptr, x, prec);
         return;
@@ -130,8 +132,11 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
             const int32_t it_now = read_summary(c).max_it;
             const int64_t worked = std::max<int64_t>(0, it_now - it_before);
             for (int k : {EQS_KCLASS_SPMV_M, EQS_KCLASS_PRESMOOTH0, EQS_KCLASS_POSTSMOOTH0, EQS_KCLASS_VCYCLE,
-                          EQS_KCLASS_CG_UPDATE})
+                          EQS_KCLASS_CG_UPDATE, EQS_KCLASS_RESTRICT0, EQS_KCLASS_PROLONG0, EQS_KCLASS_VCOARSE})
                 c->prof_used[k] = std::min(c->prof_used[k], used0[k] + worked);
+            // three finalisers per iteration
+            c->prof_used[EQS_KCLASS_FINALISE] =
+                std::min(c->prof_used[EQS_KCLASS_FINALISE], used0[EQS_KCLASS_FINALISE] + 3 * worked);
             it_before = it_now;
         }
         // every instance is done on its recursive residual (or out of iterations,

@@ -1,0 +1,117 @@
+"""RKC trajectories of the benchmark workloads against the FP64 CPU oracle.
+
+The method's result is the RKC trajectory of eq. (2) (Sec. II, its ref. [9])
+with every M-solve exact; the oracle integrates it with every stage solve at
+rel-res 1e-13 (tests/oracle_refs.py, run in a child process while the tests
+before this file run). Error norm: max over step ends n of |x_n - x_n^ref|
+over max_n |x_n^ref| (free nodes).
+
+* c2 (128^3 cubes, 2,113,407 free DOF, RKC(16)): the first step, for the FP64
+  and the FP32 hierarchy with CG at rel-res 1e-12 (the kernels' own error,
+  bar 1e-9), the FP32 form at the workload's rel-res 1e-8 (bar 1e-8), and the
+  FP32 form with the Galerkin and the network start vectors (bars 1e-9 at
+  rel-res 1e-12, 1e-8 at 1e-8).
+* c1 (64^3 cubes, 266,175 free DOF, RKC(12)): the first 10 steps, FP64 and
+  FP32 hierarchies at rel-res 1e-12 (bar 1e-9) and FP64 at the workload's
+  rel-res 1e-8 (bar 1e-8).
+
+Error budget of the looser runs: a stage solved to rel-res d changes F by
+about d relative, and the step by tau |F| d ~ 0.03 d of |x| (2 pi 50 Hz x
+tau), so 1e-8 per solve stays well below 1e-8 over these few steps.
+"""
+
+import numpy as np
+import pytest
+
+import eqsgen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1612_09447_amd import EQS_PREC_FP32, EQS_PREC_FP64, Context  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def traj_err(states, ref):
+    scale = max(np.linalg.norm(r) for r in ref)
+    return max(np.linalg.norm(a - b) for a, b in zip(states, ref)) / scale
+
+
+def run_steps(ctx, case, steps, rtol, free):
+    """`steps` RKC steps from phi(0) = 0 at t = 0; step-end states on the free
+    nodes (x_0 first) and the CG iterations."""
+    x = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+    out = [np.zeros(free.size)]
+    its = 0
+    for n in range(steps):
+        st = ctx.rkc_step(n * case.tau, case.tau, case.s, x, rtol=rtol, maxit=800)
+        its += st["total_iters"]
+        out.append(x.cpu().numpy()[free])
+    dirv = x.cpu().numpy()[case.dir_nodes]
+    g = (case.amp * np.sin(2 * np.pi * case.freq * steps * case.tau + case.phase))[case.dir_drive]
+    assert np.abs(dirv - g).max() <= 1e-13
+    return out, its
+
+
+@pytest.fixture(scope="module")
+def c2():
+    print("[trajectory] generating the c2 workload", flush=True)
+    return eqsgen.make_case("c2")
+
+
+@pytest.mark.oracle_refs("c2_1")
+def test_c2_first_step_matches_oracle(c2, oracle_ref):
+    ref = oracle_ref("c2_1")
+    free = ref["free"]
+    states = list(ref["states"])
+    assert len(states) == 2
+    stream = torch.cuda.current_stream(DEV)
+    results = []
+    with Context(0, stream) as c:
+        c.setup_case(c2, precision=EQS_PREC_FP64)
+        got, its = run_steps(c, c2, 1, 1e-12, free)
+        results.append(("FP64 hierarchy, rel-res 1e-12", traj_err(got, states), its, 1e-9))
+    with Context(0, stream) as c:
+        c.setup_case(c2, precision=EQS_PREC_FP32)
+        for label, rtol, bar, guess in [("FP32 hierarchy, rel-res 1e-12", 1e-12, 1e-9, None),
+                                        ("FP32 hierarchy, rel-res 1e-8", 1e-8, 1e-8, None),
+                                        ("FP32 + Galerkin start, rel-res 1e-12", 1e-12, 1e-9, "galerkin"),
+                                        ("FP32 + network start, rel-res 1e-12", 1e-12, 1e-9, "mlp"),
+                                        ("FP32 + network start, rel-res 1e-8", 1e-8, 1e-8, "mlp")]:
+            if guess == "mlp":
+                c.set_guess("mlp", init=eqsgen.mlp_init(4), warmup=0)
+            elif guess:
+                c.set_guess(guess)
+            else:
+                c.set_guess("previous")
+            got, its = run_steps(c, c2, 1, rtol, free)
+            results.append((label, traj_err(got, states), its, bar))
+    for label, err, its, bar in results:
+        print(f"[trajectory] c2 first RKC(16) step, {label}: err {err:.2e} ({its} CG iterations), bar {bar:g}",
+              flush=True)
+    for label, err, its, bar in results:
+        assert err <= bar, (label, err)
+
+
+@pytest.mark.oracle_refs("c1_10")
+def test_c1_ten_steps_match_oracle(oracle_ref):
+    case = eqsgen.case_c1()
+    ref = oracle_ref("c1_10")
+    free = ref["free"]
+    states = list(ref["states"])
+    assert len(states) == 11
+    stream = torch.cuda.current_stream(DEV)
+    results = []
+    for label, prec, rtol, bar in [("FP64 hierarchy, rel-res 1e-12", EQS_PREC_FP64, 1e-12, 1e-9),
+                                   ("FP32 hierarchy, rel-res 1e-12", EQS_PREC_FP32, 1e-12, 1e-9),
+                                   ("FP64 hierarchy, rel-res 1e-8", EQS_PREC_FP64, 1e-8, 1e-8)]:
+        with Context(0, stream) as c:
+            c.setup_case(case, precision=prec)
+            got, its = run_steps(c, case, 10, rtol, free)
+        results.append((label, traj_err(got, states), its, bar))
+    for label, err, its, bar in results:
+        print(f"[trajectory] c1 first 10 RKC(12) steps, {label}: err {err:.2e} ({its} CG iterations), bar {bar:g}",
+              flush=True)
+    for label, err, its, bar in results:
+        assert err <= bar, (label, err)
