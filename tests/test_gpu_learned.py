@@ -45,19 +45,23 @@ def abs_forward(p, x, bf16):
 
 
 def elementwise(got, ref, scale, tol, what):
-    """max_i |got_i - ref_i| / scale_i <= tol, reported."""
+    """Every |got_i - ref_i| / scale_i <= tol, and all but 1 % of them within
+    1e-5 (FP32 rounding of the sums); reported."""
     r = np.abs(np.asarray(got, np.float64) - ref) / np.maximum(scale, 1e-300)
-    print(f"[learned] {what}: worst element error {r.max():.2e} of its scale (bar {tol:g})", flush=True)
+    print(f"[learned] {what}: worst element error {r.max():.2e} of its scale (bar {tol:g}), "
+          f"{(r > 1e-5).mean() * 100:.2f} % above 1e-5", flush=True)
     assert r.max() <= tol, (what, r.max(), np.unravel_index(r.argmax(), r.shape))
+    assert (r > 1e-5).mean() <= 0.01, what
 
 
 # Element-wise bars against the oracle in the same operand precision (BF16:
 # operands rounded to bfloat16 on both sides): FP32 accumulation of up to 64
-# terms through three layers stays within 1e-5 of each output's scale; in BF16
+# terms through three layers stays within 2e-6 of each output's scale (measured
+# worst 2e-7); in BF16
 # an operand may round to the neighbouring bfloat16 value on one side only
 # (the GPU rounds an FP32 value, the oracle the FP64 one), which moves one term
 # by 2^-8 of its size, so the bar is 2^-8 of the scale.
-TOL = {False: 1e-5, True: 2.0 ** -8}
+TOL = {False: 2e-6, True: 2.0 ** -8}
 
 
 @pytest.mark.parametrize("bf16", [False, True])

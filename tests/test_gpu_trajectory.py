@@ -8,16 +8,20 @@ over max_n |x_n^ref| (free nodes).
 
 * c2 (128^3 cubes, 2,113,407 free DOF, RKC(16)): the first step, for the FP64
   and the FP32 hierarchy with CG at rel-res 1e-12 (the kernels' own error,
-  bar 1e-9), the FP32 form at the workload's rel-res 1e-8 (bar 1e-8), and the
-  FP32 form with the Galerkin and the network start vectors (bars 1e-9 at
-  rel-res 1e-12, 1e-8 at 1e-8).
+  bar 1e-9), the FP32 form at the workload's rel-res 1e-8, and the FP32 form
+  with the Galerkin and the network start vectors.
 * c1 (64^3 cubes, 266,175 free DOF, RKC(12)): the first 10 steps, FP64 and
   FP32 hierarchies at rel-res 1e-12 (bar 1e-9) and FP64 at the workload's
-  rel-res 1e-8 (bar 1e-8).
+  rel-res 1e-8.
 
-Error budget of the looser runs: a stage solved to rel-res d changes F by
-about d relative, and the step by tau |F| d ~ 0.03 d of |x| (2 pi 50 Hz x
-tau), so 1e-8 per solve stays well below 1e-8 over these few steps.
+Runs at the workload's rel-res 1e-8 are held to what a correct solver at that
+tolerance reaches: the oracle's own trajectory with its stage solves stopped
+at 1e-8 differs from the exact one by `floor`; the GPU run may differ by at
+most 3 floor (another solver stops at another point of its iteration, with the
+same residual bound). On the first step the floor is the solve tolerance
+itself (x_1 is a sum of tau F_j, so a relative error d in F is a relative
+error d in x_1); it shrinks relative to the trajectory's scale as the
+potential builds up over later steps.
 """
 
 import numpy as np
@@ -60,12 +64,19 @@ def c2():
     return eqsgen.make_case("c2")
 
 
-@pytest.mark.oracle_refs("c2_1")
+def loose_bar(floor):
+    return max(1e-9, 3.0 * floor)
+
+
+@pytest.mark.oracle_refs("c2_1", "c2_1_rtol8")
 def test_c2_first_step_matches_oracle(c2, oracle_ref):
     ref = oracle_ref("c2_1")
     free = ref["free"]
     states = list(ref["states"])
     assert len(states) == 2
+    floor = traj_err(list(oracle_ref("c2_1_rtol8")["states"]), states)
+    print(f"[trajectory] c2 first step: the oracle at rel-res 1e-8 differs from the exact trajectory by {floor:.2e}",
+          flush=True)
     stream = torch.cuda.current_stream(DEV)
     results = []
     with Context(0, stream) as c:
@@ -75,10 +86,11 @@ def test_c2_first_step_matches_oracle(c2, oracle_ref):
     with Context(0, stream) as c:
         c.setup_case(c2, precision=EQS_PREC_FP32)
         for label, rtol, bar, guess in [("FP32 hierarchy, rel-res 1e-12", 1e-12, 1e-9, None),
-                                        ("FP32 hierarchy, rel-res 1e-8", 1e-8, 1e-8, None),
+                                        ("FP32 hierarchy, rel-res 1e-8", 1e-8, loose_bar(floor), None),
                                         ("FP32 + Galerkin start, rel-res 1e-12", 1e-12, 1e-9, "galerkin"),
+                                        ("FP32 + Galerkin start, rel-res 1e-8", 1e-8, loose_bar(floor), "galerkin"),
                                         ("FP32 + network start, rel-res 1e-12", 1e-12, 1e-9, "mlp"),
-                                        ("FP32 + network start, rel-res 1e-8", 1e-8, 1e-8, "mlp")]:
+                                        ("FP32 + network start, rel-res 1e-8", 1e-8, loose_bar(floor), "mlp")]:
             if guess == "mlp":
                 c.set_guess("mlp", init=eqsgen.mlp_init(4), warmup=0)
             elif guess:
@@ -94,18 +106,21 @@ def test_c2_first_step_matches_oracle(c2, oracle_ref):
         assert err <= bar, (label, err)
 
 
-@pytest.mark.oracle_refs("c1_10")
+@pytest.mark.oracle_refs("c1_10", "c1_10_rtol8")
 def test_c1_ten_steps_match_oracle(oracle_ref):
     case = eqsgen.case_c1()
     ref = oracle_ref("c1_10")
     free = ref["free"]
     states = list(ref["states"])
     assert len(states) == 11
+    floor = traj_err(list(oracle_ref("c1_10_rtol8")["states"]), states)
+    print(f"[trajectory] c1 10 steps: the oracle at rel-res 1e-8 differs from the exact trajectory by {floor:.2e}",
+          flush=True)
     stream = torch.cuda.current_stream(DEV)
     results = []
     for label, prec, rtol, bar in [("FP64 hierarchy, rel-res 1e-12", EQS_PREC_FP64, 1e-12, 1e-9),
                                    ("FP32 hierarchy, rel-res 1e-12", EQS_PREC_FP32, 1e-12, 1e-9),
-                                   ("FP64 hierarchy, rel-res 1e-8", EQS_PREC_FP64, 1e-8, 1e-8)]:
+                                   ("FP64 hierarchy, rel-res 1e-8", EQS_PREC_FP64, 1e-8, loose_bar(floor))]:
         with Context(0, stream) as c:
             c.setup_case(case, precision=prec)
             got, its = run_steps(c, case, 10, rtol, free)
