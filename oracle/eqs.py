@@ -147,6 +147,20 @@ class EqsOracle:
                 % (tau * self.max_rate, coef.s, coef.beta)
             )
 
+    def spectral_bound(self, t, Y):
+        """max_e sigma_e / eps_e at the state (t, Y): an upper bound of the
+        spectral radius of M^{-1} times the Jacobian of K(x)x (element-wise
+        Rayleigh quotients, pin P5), the rho of the adaptive stage choice."""
+        _, rate = self.Kx(t, Y)
+        return rate
+
+    def rkc_adaptive(self, Y0, t0, t_end, tau0, atol, rtol, s_max=250, tau_max=None):
+        """Error-controlled RKC from t0 to t_end (ref. [9]'s estimate and step
+        control, stages from spectral_bound); returns the accepted step-end
+        states [(t_n, Y_n)] and the record of every attempted step."""
+        return rkc.adaptive(self.F, self.spectral_bound, t0, Y0, t_end, tau0, atol, rtol, s_max=s_max,
+                            tau_max=tau_max)
+
     def rkc_trajectory(self, Y0, t0, tau, s, steps, stages=None, callback=None):
         """Integrate `steps` RKC(s) steps; returns the list of step-end states Y_n.
 

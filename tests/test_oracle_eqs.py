@@ -214,3 +214,30 @@ def test_stability_bound_is_enforced():
     o = EqsOracle(case)
     with pytest.raises(RuntimeError, match="stability"):
         o.rkc_trajectory(np.zeros(o.n_free), 0.0, 1e-4, 4, 1)
+
+
+def test_P1b_adaptive_steps_equal_scalar_run():
+    """Adaptive RKC (ref. [9]'s estimate and controller) on P1b: with
+    kappa/eps = c everywhere and g = 0, every stage is a polynomial in -c tau
+    times x0, and with atol = 0 every component's weighted error equals the
+    scalar problem's, so the FE run attempts, accepts and rejects exactly the
+    steps (tau, s) of adaptive RKC on y' = -c y, and x_n = y_n x0."""
+    case = eqsgen.case_c1(n=5, seed=2)
+    c = 4.0e3
+    case.kappa0 = c * case.eps_r * EPS0
+    case.nonlinear[:] = 0
+    case.amp[:] = 0.0
+    o = EqsOracle(case)
+    x0 = eqsgen.random_state(case.n_nodes, seed=9)[o.free]
+    t_end, tau0, rtol = 3e-3, 2e-3, 1e-4
+    out, rec = o.rkc_adaptive(x0, 0.0, t_end, tau0, 0.0, rtol)
+    sout, srec = rkc.adaptive(lambda t, y: -c * y, lambda t, y: c, 0.0, np.array([1.0]), t_end, tau0, 0.0, rtol)
+    assert [(r.accepted, r.s) for r in rec] == [(r.accepted, r.s) for r in srec]
+    # err comes from differences of nearby states, so tau agrees to ~1e-10 (rounding)
+    np.testing.assert_allclose([r.tau for r in rec], [r.tau for r in srec], rtol=1e-9)
+    assert any(not r.accepted for r in rec) and max(r.s for r in rec) > 2
+    for (t, x), (ts, y) in zip(out, sout):
+        assert t == pytest.approx(ts, rel=1e-12)
+        np.testing.assert_allclose(x, y[0] * x0, rtol=0, atol=1e-11 * abs(x0).max())
+    # and the scalar run tracks the exact decay
+    assert abs(sout[-1][1][0] - np.exp(-c * t_end)) <= 50 * rtol
