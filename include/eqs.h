@@ -305,6 +305,19 @@ int eqs_set_guess(eqs_ctx *ctx, const eqs_guess_params *p);
 int eqs_galerkin_start(eqs_ctx *ctx, int32_t k, const double *S_dev, const double *R_dev, const double *r_dev,
                        double *x0_dev, int32_t *m_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as eqs_galerkin_start, with the same arguments and errors, but its
+ * dot-product scratch is a static device array of the library (287,232 bytes
+ * per GPU, held until the process ends) instead of context memory allocated
+ * on first use; the call allocates nothing. k is limited to 16 (the scratch
+ * holds the dots of 16 columns); a larger k gives EQS_ERR_INVALID_ARG. All
+ * calls on one GPU share that array: calls that overlap in time on the same
+ * GPU (other threads, other contexts' streams) race and must be serialised
+ * by the caller. */
+int eqs_galerkin_start_noalloc(eqs_ctx *ctx, int32_t k, const double *S_dev, const double *R_dev,
+                               const double *r_dev, double *x0_dev, int32_t *m_out);
+
 /* ---- the start-vector network on its own ------------------------------
  * Multilayer perceptron 32 -> 64 -> 64 -> 16, SiLU hidden activations,
  * linear output, mean-squared-error loss, Adam (beta1 0.9, beta2 0.999,

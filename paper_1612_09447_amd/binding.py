@@ -106,6 +106,7 @@ _SIGNATURES = {
     "eqs_rkc_step": ([_P, C.c_double, C.c_double, C.c_int32, _P, C.c_double, C.c_int32, _P], C.c_int),
     "eqs_set_guess": ([_P, _P], C.c_int),
     "eqs_galerkin_start": ([_P, C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_int32)], C.c_int),
+    "eqs_galerkin_start_noalloc": ([_P, C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_int32)], C.c_int),
     "eqs_set_instances": ([_P, C.c_int32, _P, _P], C.c_int),
     "eqs_instance_stats": ([_P, C.c_int32, _P, _P], C.c_int),
     "eqs_batch_create": ([C.POINTER(_P), C.c_int32, _P, C.c_int, _P, _P], C.c_int),
@@ -370,6 +371,18 @@ class Context:
         m = C.c_int32(0)
         _check(lib().eqs_galerkin_start(self._h, int(S.shape[0]), _dev(S), _dev(R), _dev(r), _dev(x0), C.byref(m)),
                "eqs_galerkin_start")
+        return int(m.value)
+
+
+    def galerkin_start_noalloc(self, S, R, r, x0):
+        """As galerkin_start, through eqs_galerkin_start_noalloc (no device
+        allocation: the library's static scratch)."""
+        nf = self.info()["n_free"]
+        if S.dim() != 2 or tuple(R.shape) != tuple(S.shape) or S.shape[1] != nf or r.numel() != nf or x0.numel() != nf:
+            raise ValueError(f"galerkin_start_noalloc: S and R must be k x {nf}, r and x0 hold {nf} values")
+        m = C.c_int32(0)
+        _check(lib().eqs_galerkin_start_noalloc(self._h, int(S.shape[0]), _dev(S), _dev(R), _dev(r), _dev(x0),
+                                                C.byref(m)), "eqs_galerkin_start_noalloc")
         return int(m.value)
 
 

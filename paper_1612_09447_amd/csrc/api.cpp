@@ -72,6 +72,7 @@ int eqs_create(eqs_ctx** out, int device, void* hip_stream) {
         EQS_HIP(hipGetDeviceCount(&n));
         need(device >= 0 && device < n, "device id out of range");
         EQS_HIP(hipSetDevice(device));
+        eqs::noalloc_scratch_init(device);  // once per device: the static scratch's address
         eqs_ctx* c = new eqs_ctx();
         c->device = device;
         c->stream = (hipStream_t)hip_stream;
@@ -435,6 +436,28 @@ int eqs_galerkin_start(eqs_ctx* c, int32_t k, const double* S_dev, const double*
              "x0 must not overlap S, R or r");
         bind_device(c);
         const int m = eqs::guess_galerkin_explicit(c, k, S_dev, R_dev, r_dev, x0_dev);
+        EQS_HIP(hipStreamSynchronize(c->stream));
+        if (m_out) *m_out = m;
+        return EQS_OK;
+    });
+}
+
+int eqs_galerkin_start_noalloc(eqs_ctx* c, int32_t k, const double* S_dev, const double* R_dev,
+                               const double* r_dev, double* x0_dev, int32_t* m_out) {
+    return guarded([&] {
+        need(c != nullptr && S_dev != nullptr && R_dev != nullptr && r_dev != nullptr && x0_dev != nullptr,
+             "NULL argument");
+        need(k >= 1 && k <= 16, "k must be in [1, 16]: the static scratch holds the dots of at most 16 columns");
+        need_built(c);
+        const int64_t NF = c->n_free;
+        need(NF > 0, "no free nodes");
+        need(!overlaps(x0_dev, NF, S_dev, (int64_t)k * NF) && !overlaps(x0_dev, NF, R_dev, (int64_t)k * NF) &&
+                 !overlaps(x0_dev, NF, r_dev, NF),
+             "x0 must not overlap S, R or r");
+        bind_device(c);
+        double* base = eqs::noalloc_scratch(c->device);
+        const int m = eqs::guess_galerkin_explicit(c, k, S_dev, R_dev, r_dev, x0_dev, base,
+                                                   base + eqs::kNoAllocPartDoubles);
         EQS_HIP(hipStreamSynchronize(c->stream));
         if (m_out) *m_out = m;
         return EQS_OK;

@@ -409,7 +409,13 @@ void guess_configure(eqs_ctx* c, const eqs_guess_params& p);
 void guess_release(eqs_ctx* c);
 void guess_reset(eqs_ctx* c);
 int guess_stage(eqs_ctx* c);
-int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R, const double* r, double* x0);
+int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R, const double* r, double* x0,
+                            double* part = nullptr, double* dots_dev = nullptr);
+// static device scratch of eqs_galerkin_start_noalloc: set up once per device
+// (with that device current), then its address on a device
+void noalloc_scratch_init(int device);
+double* noalloc_scratch(int device);
+constexpr int64_t kNoAllocPartDoubles = (2 * 16 + 3) * 1024;  // dot partials ahead of the 64 summed dots
 void guess_after_solve(eqs_ctx* c, int32_t iters);
 void guess_train(eqs_ctx* c);
 double guess_last_loss(eqs_ctx* c);

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "eqs_internal.h"
 #include "sell.h"
@@ -37,6 +38,8 @@ constexpr int kNDots = 2 * kMaxWin + 3;
 constexpr int kDotGrid = 1024;
 constexpr int kGuardLen = 16 * 16 + 16 + 1;
 constexpr int kMaxPairsPerStage = 256;  // minibatches of up to 64 pairs, one Adam step each
+constexpr int kNoAllocScratch = kNDots * kDotGrid + 64;  // doubles of the static scratch
+static_assert(kNoAllocPartDoubles == (int64_t)kNDots * kDotGrid, "static scratch layout");
 
 // ------------------------------------------------------------- kernels
 template <int NQ>
@@ -349,16 +352,52 @@ static bool galerkin_coef(const Basis& B, const std::vector<double>& K, const do
     return true;
 }
 
+// ------------------------------------------- scratch that needs no allocation
+// The dot-product partials of eqs_galerkin_start_noalloc live in this array,
+// one copy per GPU for the life of the process: kNDots x kDotGrid block
+// partials, then 64 summed dots (287,232 bytes). Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kNoAllocScratch];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;  // per device, from hipGetSymbolAddress
+}  // namespace
+
+void noalloc_scratch_init(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (g_scratch_ptr[device]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the device is current (eqs_create)
+    if (e != hipSuccess) fail(EQS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = (double*)p;
+}
+
+double* noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= (int)g_scratch_ptr.size() || !g_scratch_ptr[device])
+        fail(EQS_ERR_STATE, "the static scratch of this device was not set up");
+    return g_scratch_ptr[device];
+}
+
 // Eq. (5) on a window given by the caller (k columns of S, oldest first, with
 // R = M S): G = S^T S and H = S^T R from k passes of the window-dots kernel,
 // S^T r from one more, then the basis, reduced matrix and coefficient solve of
 // a stage's GALERKIN start vector and x0 = S alpha. Returns the number of
-// directions kept (0: x0 = 0). Uses the start-vector scratch on c->stream.
-int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R, const double* r, double* x0) {
+// directions kept (0: x0 = 0). The dot partials go to `part` (kNDots x
+// kDotGrid doubles) and `dots` (64 doubles), or, when part is NULL, to the
+// context's start-vector scratch (allocated on first use). Runs on c->stream.
+int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R, const double* r, double* x0,
+                            double* part, double* dots_dev) {
     GuessState& gs = c->guess;
-    // only the dot-product scratch is needed here (not the stage window)
-    if (!gs.d_part) gs.d_part = (double*)dev_alloc(c, sizeof(double) * kNDots * kDotGrid);
-    if (!gs.d_dots) gs.d_dots = (double*)dev_alloc(c, sizeof(double) * 64);
+    if (!part) {
+        // only the dot-product scratch is needed here (not the stage window)
+        if (!gs.d_part) gs.d_part = (double*)dev_alloc(c, sizeof(double) * kNDots * kDotGrid);
+        if (!gs.d_dots) gs.d_dots = (double*)dev_alloc(c, sizeof(double) * 64);
+        part = gs.d_part;
+        dots_dev = gs.d_dots;
+    }
     hipStream_t s = c->stream;
     const int64_t NF = c->n_free;
     GuessState g;  // window bookkeeping only: slots 0..k-1, slot 0 the oldest
@@ -375,10 +414,10 @@ int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R,
         const double* u = a < k ? S + (int64_t)a * NF : r;
         const double* v = a < k ? R + (int64_t)a * NF : r;
         hipLaunchKernelGGL(k_window_dots, dim3(grid), dim3(kBlock), 0, s, const_cast<double*>(S), NF, k, -1, u, v, v,
-                           NF, gs.d_part);
-        hipLaunchKernelGGL(k_sum_rows, dim3(kNDots), dim3(kBlock), 0, s, gs.d_part, (int64_t)kDotGrid, (int)grid,
-                           gs.d_dots);
-        EQS_HIP(hipMemcpyAsync(dots, gs.d_dots, sizeof dots, hipMemcpyDeviceToHost, s));
+                           NF, part);
+        hipLaunchKernelGGL(k_sum_rows, dim3(kNDots), dim3(kBlock), 0, s, part, (int64_t)kDotGrid, (int)grid,
+                           dots_dev);
+        EQS_HIP(hipMemcpyAsync(dots, dots_dev, sizeof dots, hipMemcpyDeviceToHost, s));
         EQS_HIP(hipStreamSynchronize(s));
         for (int b = 0; b < k; ++b) {
             if (a < k) {
