@@ -252,10 +252,17 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
     t0 = time.perf_counter()
     ctx = Context(0, stream)
     info = ctx.setup_case(case, precision=precision, flexible=flexible)
-    if guess == "mlp":
+    # PyTorch owns the device memory: the context moves into a torch workspace
+    # sized for its largest start-vector setting of this run
+    if guess == "mlp" or learned_steps > 0:
         ctx.set_guess("mlp", init=eqsgen.mlp_init(4), batch=mlp_batch)
     elif guess != "previous":
         ctx.set_guess(guess)
+    ws = ctx.use_torch_workspace()
+    if guess != "mlp":
+        ctx.set_guess(guess)
+    info = ctx.info()
+    assert info["device_bytes"] == 0
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup precision={precision} guess={guess}: {setup_s:.1f}s\n" + ctx.describe())
     x = torch.zeros(case.n_nodes, dtype=torch.float64, device=dev)
@@ -301,6 +308,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
                              "warmup_steps": learned_warmup, "mlp_pairs_per_stage": mlp_batch}
         ctx.set_guess("previous")
     ctx.close()
+    del ws
     return dict(elapsed=elapsed, stages=steps * s, iters=iters, info=info, prof=prof, prof_elapsed=prof_elapsed,
                 prof_stages=prof_steps * s, setup_s=setup_s, x=x_timed, used=used, fallbacks=fallbacks, learned=learned,
                 hist=hist)
@@ -522,6 +530,8 @@ def main():
             "graphs": bool(args.graphs),
             "mean_cg_iters_per_stage": round(sum(r["iters"]) / len(r["iters"]), 2),
             "amg_levels": info["level_rows"],
+            "device_memory": f"torch workspace of {info['workspace_bytes']} bytes (eqs_set_workspace); "
+                             f"library-allocated: {info['device_bytes']}",
             "nnz_M": info["nnz_M"],
             "setup_s": round(r["setup_s"], 1),
         },

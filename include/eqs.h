@@ -129,7 +129,9 @@ typedef struct eqs_info {
     int64_t level_p_nnz[16]; /* nonzeros of the prolongation P_l (level l+1 -> l; 0 on the coarsest) */
     int64_t level_r_nnz[16]; /* nonzeros of the restriction applied at level l (R_l = P_l^T, or
                                 R_l (I - A_l w D_l^-1) where the pre-smoother is folded in) */
-    int64_t device_bytes; /* device memory held by the context */
+    int64_t device_bytes;    /* device memory the library allocated itself for the context */
+    int64_t workspace_bytes; /* size of the caller's workspace (0: none attached) */
+    int64_t workspace_used;  /* bytes of it the context's buffers occupy */
 } eqs_info;
 
 /* Create a context on HIP device `device` whose work goes to `hip_stream`
@@ -166,7 +168,37 @@ int eqs_set_dirichlet(eqs_ctx *ctx, int64_t n_d, const int32_t *nodes, const int
 int eqs_build_preconditioner(eqs_ctx *ctx, const eqs_amg_params *p);
 
 /* Sizes and hierarchy statistics. */
-int eqs_query(const eqs_ctx *ctx, eqs_info *info);
+int eqs_get_info(const eqs_ctx *ctx, eqs_info *info);
+
+/* ---- device memory from the caller ------------------------------------
+ * Every device buffer of a context (mesh, M, the AMG hierarchy, the CG and
+ * RKC vectors, the start-vector window and network) is one of a set of
+ * 256-byte-aligned blocks; the library allocates them itself unless the
+ * caller supplies one workspace that holds them all, so that a framework's
+ * allocator (PyTorch's) can own all device memory.
+ *
+ * eqs_query: after eqs_build_preconditioner, *n_free (may be NULL) receives
+ * the number of free nodes and *ws_bytes (may be NULL) the workspace size the
+ * context needs for its present configuration: its buffers plus those the
+ * start-vector settings of eqs_set_guess will allocate on their first stage
+ * (query after eqs_set_guess to include them). EQS_ERR_STATE before the build.
+ *
+ * eqs_set_workspace: dev (device memory on the context's device, 256-byte
+ * aligned, `bytes` long, not freed by the caller while attached) becomes the
+ * context's device memory: a built context's buffers move into it (device
+ * copies, on the context's stream) and the memory the library had allocated
+ * is released, so eqs_get_info then reports device_bytes = 0; buffers the
+ * context allocates later (the start-vector window on its first stage, a
+ * rebuild) come from the workspace's free space, and EQS_ERR_ALLOC reports
+ * a workspace that cannot hold them (a rebuild also needs room for the
+ * trial layouts the set-up times). bytes below eqs_query's size gives
+ * EQS_ERR_INVALID_ARG and leaves the context as it was. dev = NULL moves the
+ * buffers back into memory the library allocates and detaches the workspace.
+ * The workspace stays attached until eqs_destroy, another eqs_set_workspace,
+ * or eqs_set_workspace(ctx, NULL, 0). Calling eqs_set_workspace before the
+ * build makes the build itself allocate from it. */
+int eqs_query(const eqs_ctx *ctx, int64_t *n_free, int64_t *ws_bytes);
+int eqs_set_workspace(eqs_ctx *ctx, void *dev, int64_t bytes);
 
 /* y = K(x_bar) x_bar on all nodes (Sec. III, element-by-element product),
  * where x_bar equals x_dev on free nodes and g(t) on Dirichlet nodes

@@ -86,7 +86,7 @@ class eqs_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("n_free", C.c_int64), ("nnz_M", C.c_int64),
                 ("n_levels", C.c_int32), ("precision", C.c_int32), ("level_rows", C.c_int64 * 16),
                 ("level_nnz", C.c_int64 * 16), ("level_p_nnz", C.c_int64 * 16), ("level_r_nnz", C.c_int64 * 16),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("workspace_bytes", C.c_int64), ("workspace_used", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -97,7 +97,9 @@ _SIGNATURES = {
     "eqs_set_materials": ([_P, C.c_int32, _P, _P], C.c_int),
     "eqs_set_dirichlet": ([_P, C.c_int64, _P, _P, C.c_int32, _P], C.c_int),
     "eqs_build_preconditioner": ([_P, _P], C.c_int),
-    "eqs_query": ([_P, _P], C.c_int),
+    "eqs_get_info": ([_P, _P], C.c_int),
+    "eqs_query": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
+    "eqs_set_workspace": ([_P, _P, C.c_int64], C.c_int),
     "eqs_apply_K": ([_P, C.c_double, _P, _P], C.c_int),
     "eqs_stage_rhs": ([_P, C.c_double, _P, _P], C.c_int),
     "eqs_apply_M": ([_P, _P, _P], C.c_int),
@@ -213,6 +215,7 @@ class Context:
         if self._h:
             lib().eqs_destroy(self._h)
             self._h = _P()
+        self._ws = None
 
     def __del__(self):
         try:
@@ -289,12 +292,42 @@ class Context:
 
     def info(self) -> dict:
         o = eqs_info()
-        _check(lib().eqs_query(self._h, C.byref(o)), "eqs_query")
+        _check(lib().eqs_get_info(self._h, C.byref(o)), "eqs_get_info")
         L = o.n_levels
         return dict(n_nodes=o.n_nodes, n_tets=o.n_tets, n_free=o.n_free, nnz_M=o.nnz_M, n_levels=L,
                     precision=o.precision, level_rows=list(o.level_rows[:L]), level_nnz=list(o.level_nnz[:L]),
                     level_p_nnz=list(o.level_p_nnz[:L]), level_r_nnz=list(o.level_r_nnz[:L]),
-                    device_bytes=o.device_bytes)
+                    device_bytes=o.device_bytes, workspace_bytes=o.workspace_bytes,
+                    workspace_used=o.workspace_used)
+
+    def query(self):
+        """(n_free, ws_bytes): free nodes and the workspace size the context needs now."""
+        nf, ws = C.c_int64(), C.c_int64()
+        _check(lib().eqs_query(self._h, C.byref(nf), C.byref(ws)), "eqs_query")
+        return nf.value, ws.value
+
+    def set_workspace(self, ws=None):
+        """Hand the context its device memory: a torch uint8 tensor on the
+        context's device (kept referenced here while attached), or None to
+        return to memory the library allocates."""
+        if ws is None:
+            _check(lib().eqs_set_workspace(self._h, None, 0), "eqs_set_workspace")
+        else:
+            if ws.device.type != "cuda" or not ws.is_contiguous():
+                raise ValueError("the workspace must be a contiguous tensor on the GPU")
+            _check(lib().eqs_set_workspace(self._h, _P(ws.data_ptr()), ws.numel() * ws.element_size()),
+                   "eqs_set_workspace")
+        self._ws = ws
+
+    def use_torch_workspace(self, extra=0):
+        """Allocate the workspace eqs_query asks for (plus `extra` bytes) with
+        torch and attach it; returns the tensor."""
+        import torch
+
+        _, need = self.query()
+        ws = torch.empty(need + extra, dtype=torch.uint8, device=torch.device("cuda", self.device))
+        self.set_workspace(ws)
+        return ws
 
     def describe(self) -> str:
         need = C.c_int64()

@@ -241,7 +241,7 @@ int eqs_build_preconditioner(eqs_ctx* c, const eqs_amg_params* p) {
     });
 }
 
-int eqs_query(const eqs_ctx* c, eqs_info* info) {
+int eqs_get_info(const eqs_ctx* c, eqs_info* info) {
     return guarded([&] {
         need(c != nullptr && info != nullptr, "NULL argument");
         eqs_info o{};
@@ -264,7 +264,40 @@ int eqs_query(const eqs_ctx* c, eqs_info* info) {
             else levels(c->h64);
         }
         o.device_bytes = c->device_bytes;
+        o.workspace_bytes = c->ws_base ? c->ws_size : 0;
+        o.workspace_used = c->ws_used;
         *info = o;
+        return EQS_OK;
+    });
+}
+
+int eqs_query(const eqs_ctx* c, int64_t* n_free, int64_t* ws_bytes) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        need_built(c);
+        if (n_free) *n_free = c->n_free;
+        if (ws_bytes) *ws_bytes = eqs::workspace_need(c);
+        return EQS_OK;
+    });
+}
+
+int eqs_set_workspace(eqs_ctx* c, void* dev, int64_t bytes) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        if (dev) {
+            need(bytes > 0, "bytes must be > 0 with a workspace");
+            need(((uintptr_t)dev & 255u) == 0, "the workspace must be 256-byte aligned");
+        } else {
+            need(bytes == 0, "bytes must be 0 without a workspace");
+        }
+        bind_device(c);
+        if (dev) {
+            hipPointerAttribute_t attr{};
+            EQS_HIP(hipPointerGetAttributes(&attr, dev));
+            need(attr.type == hipMemoryTypeDevice && attr.device == c->device,
+                 "the workspace must be device memory on the context's device");
+        }
+        eqs::set_workspace(c, dev, bytes);
         return EQS_OK;
     });
 }

@@ -22,6 +22,7 @@
 #include <cstdint>
 #include <string>
 #include <functional>
+#include <map>
 #include <vector>
 
 #include "eqs.h"
@@ -298,8 +299,16 @@ struct eqs_ctx {
     eqs::PcgSummary* d_hsum = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
 
+    // Device memory: every buffer of the context comes from dev_alloc, either
+    // allocated by the library (device_bytes counts it) or carved from the
+    // caller's workspace [ws_base, ws_base + ws_size) (ws_used counts it);
+    // allocations lists both, with lengths rounded to 256 bytes.
     int64_t device_bytes = 0;
     std::vector<std::pair<void*, size_t>> allocations;
+    char* ws_base = nullptr;
+    int64_t ws_size = 0;
+    int64_t ws_used = 0;
+    std::map<int64_t, int64_t> ws_free;  // free ranges of the workspace: offset -> length
     bool index16 = true;   // 16-bit column offsets for SELL operators whose entries allow them
     bool autotune = true;  // time the candidate layouts of every AMG operator at build time
     bool fold = true;       // fold pre-smoothers into restrictions and the lowest two levels into two products
@@ -346,6 +355,19 @@ void rkc_coefficients(int s, std::vector<double>& mu, std::vector<double>& nu, s
 // device upload
 void* dev_alloc(eqs_ctx* c, size_t bytes);
 void dev_free(eqs_ctx* c, void* p);
+// Device bytes the context needs for its present configuration: its buffers
+// plus those the start-vector settings will allocate on first use.
+int64_t workspace_need(const eqs_ctx* c);
+// Move every device buffer of the context into [dev, dev + bytes) (dev NULL:
+// into memory the library allocates) and release the old memory.
+void set_workspace(eqs_ctx* c, void* dev, int64_t bytes);
+// Calls f on the address of every device-pointer field of the context (the
+// visitor of set_workspace).
+void visit_device_ptrs(eqs_ctx* c, const std::function<void(void**)>& f);
+int64_t guess_pending_bytes(const eqs_ctx* c);
+void guess_alloc_scratch(eqs_ctx* c);
+void mlp_visit(eqs_mlp* n, const std::function<void(void**)>& f);
+int64_t mlp_device_bytes();  // device bytes of one network (rounded as dev_alloc rounds)
 template <typename T>
 double time_mv(eqs_ctx* c, const SpMat<T>& A, const T* x, T* y, int reps);
 void upload(eqs_ctx* c);
@@ -395,7 +417,10 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
 }  // namespace eqs
 struct eqs_mlp;
 namespace eqs {
-eqs_mlp* mlp_create(int device, hipStream_t stream, const float* params, int bf16, double lr);
+// owner (may be NULL): the context whose device memory (dev_alloc) holds the
+// network's buffers; NULL: the network allocates its own
+eqs_mlp* mlp_create(int device, hipStream_t stream, const float* params, int bf16, double lr,
+                    eqs_ctx* owner = nullptr);
 void mlp_destroy(eqs_mlp* n);
 void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B);
 void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B);

@@ -239,7 +239,7 @@ void guess_configure(eqs_ctx* c, const eqs_guess_params& p) {
         EQS_HIP(hipStreamCreateWithFlags(&g.tstream, hipStreamNonBlocking));  // default priority
         EQS_HIP(hipEventCreateWithFlags(&g.ev_inf, hipEventDisableTiming));
         EQS_HIP(hipEventCreateWithFlags(&g.ev_train, hipEventDisableTiming));
-        g.net = mlp_create(c->device, g.tstream, g.init.data(), p.bf16, p.lr);
+        g.net = mlp_create(c->device, g.tstream, g.init.data(), p.bf16, p.lr, c);
     }
     EQS_HIP(hipHostMalloc((void**)&g.h_stage, sizeof(float) * kMaxPairsPerStage * 48, hipHostMallocDefault));
     EQS_HIP(hipHostMalloc((void**)&g.h_guard, sizeof(double) * kGuardLen, hipHostMallocDefault));
@@ -249,21 +249,51 @@ void guess_alloc_device(eqs_ctx* c) {
     GuessState& g = c->guess;
     const int64_t NF = c->n_free;
     // buffers of an earlier configuration of this context (eqs_set_guess again)
-    // go first; the training stream was drained when that one was released
-    for (void* p : {(void*)g.d_S, (void*)g.d_rprev, (void*)g.d_alpha, (void*)g.d_dots, (void*)g.d_part,
-                    (void*)g.d_guard, (void*)g.d_gstat, (void*)g.d_bx, (void*)g.d_bt})
+    // go first, and the same sizes come back in the same order (so a workspace
+    // reuses the same ranges); the training stream was drained when that one
+    // was released. The dot scratch was allocated with the context and stays.
+    for (void* p : {(void*)g.d_S, (void*)g.d_rprev, (void*)g.d_alpha, (void*)g.d_guard, (void*)g.d_gstat,
+                    (void*)g.d_bx, (void*)g.d_bt})
         dev_free(c, p);
+    guess_alloc_scratch(c);
     g.d_S = (double*)dev_alloc(c, sizeof(double) * (size_t)kMaxWin * NF);
     g.d_rprev = (double*)dev_alloc(c, sizeof(double) * NF);
     g.d_alpha = (double*)dev_alloc(c, sizeof(double) * kMaxWin);
-    g.d_dots = (double*)dev_alloc(c, sizeof(double) * 64);
-    g.d_part = (double*)dev_alloc(c, sizeof(double) * kNDots * kDotGrid);
     g.d_guard = (double*)dev_alloc(c, sizeof(double) * kGuardLen);
     g.d_gstat = (int32_t*)dev_alloc(c, sizeof(int32_t) * 2);
     EQS_HIP(hipMemset(g.d_gstat, 0, sizeof(int32_t) * 2));
     g.d_bx = (float*)dev_alloc(c, sizeof(float) * kMaxPairsPerStage * 32);
     g.d_bt = (float*)dev_alloc(c, sizeof(float) * kMaxPairsPerStage * 16);
+    // the network's buffers are context memory too: a rebuild released them
+    if (g.p.kind == EQS_GUESS_MLP && !g.net) g.net = mlp_create(c->device, g.tstream, g.init.data(), g.p.bf16, g.p.lr, c);
     g.dev_ready = true;
+}
+
+// Bytes (rounded as dev_alloc rounds) that guess_alloc_device and the explicit
+// Galerkin call still have to allocate for the present settings.
+static int64_t rounded(int64_t b) { return (b + 255) / 256 * 256; }
+int64_t guess_pending_bytes(const eqs_ctx* c) {
+    const GuessState& g = c->guess;
+    const int64_t NF = c->n_free;
+    const int64_t scratch = rounded(sizeof(double) * kNDots * kDotGrid) + rounded(sizeof(double) * 64);
+    const int64_t have = (g.d_part ? rounded(sizeof(double) * kNDots * kDotGrid) : 0) +
+                         (g.d_dots ? rounded(sizeof(double) * 64) : 0);
+    if (g.p.kind >= EQS_GUESS_GALERKIN && !g.dev_ready) {
+        const int64_t full = rounded(sizeof(double) * (int64_t)kMaxWin * NF) + rounded(sizeof(double) * NF) +
+                             rounded(sizeof(double) * kMaxWin) + scratch + rounded(sizeof(double) * kGuardLen) +
+                             rounded(sizeof(int32_t) * 2) + rounded(sizeof(float) * kMaxPairsPerStage * 32) +
+                             rounded(sizeof(float) * kMaxPairsPerStage * 16);
+        const int64_t net = (g.p.kind == EQS_GUESS_MLP && !g.net) ? mlp_device_bytes() : 0;
+        return full - have + net;
+    }
+    return scratch - have;  // the dot scratch is allocated at upload, so normally 0
+}
+
+// The dot scratch of eqs_galerkin_start, allocated with the context's other buffers.
+void guess_alloc_scratch(eqs_ctx* c) {
+    GuessState& g = c->guess;
+    if (!g.d_part) g.d_part = (double*)dev_alloc(c, sizeof(double) * kNDots * kDotGrid);
+    if (!g.d_dots) g.d_dots = (double*)dev_alloc(c, sizeof(double) * 64);
 }
 
 // Basis from the Gram matrix of the current window (slots in age order).
@@ -393,8 +423,7 @@ int guess_galerkin_explicit(eqs_ctx* c, int k, const double* S, const double* R,
     GuessState& gs = c->guess;
     if (!part) {
         // only the dot-product scratch is needed here (not the stage window)
-        if (!gs.d_part) gs.d_part = (double*)dev_alloc(c, sizeof(double) * kNDots * kDotGrid);
-        if (!gs.d_dots) gs.d_dots = (double*)dev_alloc(c, sizeof(double) * 64);
+        guess_alloc_scratch(c);
         part = gs.d_part;
         dots_dev = gs.d_dots;
     }

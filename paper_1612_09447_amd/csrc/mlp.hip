@@ -256,6 +256,7 @@ __global__ __launch_bounds__(64) void k_mlp_alpha(MlpIn in, const float* __restr
 struct eqs_mlp {
     int device = 0;
     hipStream_t stream = nullptr;
+    eqs_ctx* owner = nullptr;  // context whose device memory holds the buffers, or NULL
     int bf16 = 1;
     float *master = nullptr, *wq = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
     eqs::MlpState* st = nullptr;
@@ -292,20 +293,24 @@ static float host_bf16(float x) {
     return r;
 }
 
-eqs_mlp* mlp_create(int device, hipStream_t stream, const float* params, int bf16, double lr) {
+eqs_mlp* mlp_create(int device, hipStream_t stream, const float* params, int bf16, double lr, eqs_ctx* owner) {
     eqs_mlp* n = new eqs_mlp();
     n->device = device;
     n->stream = stream;
+    n->owner = owner;
     n->bf16 = bf16 ? 1 : 0;
     const size_t bytes = sizeof(float) * kNParam;
-    auto alloc = [&](float** p) { EQS_HIP(hipMalloc((void**)p, bytes)); };
+    auto alloc = [&](void** p, size_t nb) {
+        if (owner) *p = dev_alloc(owner, nb);
+        else EQS_HIP(hipMalloc(p, nb));
+    };
     try {
-        alloc(&n->master);
-        alloc(&n->wq);
-        alloc(&n->grad);
-        alloc(&n->m1);
-        alloc(&n->m2);
-        EQS_HIP(hipMalloc((void**)&n->st, sizeof(MlpState)));
+        alloc((void**)&n->master, bytes);
+        alloc((void**)&n->wq, bytes);
+        alloc((void**)&n->grad, bytes);
+        alloc((void**)&n->m1, bytes);
+        alloc((void**)&n->m2, bytes);
+        alloc((void**)&n->st, sizeof(MlpState));
         std::vector<float> w(params, params + kNParam), wq(kNParam);
         for (int i = 0; i < kNParam; ++i) wq[i] = n->bf16 ? host_bf16(w[i]) : w[i];
         std::vector<float> zero(kNParam, 0.0f);
@@ -325,10 +330,27 @@ eqs_mlp* mlp_create(int device, hipStream_t stream, const float* params, int bf1
 
 void mlp_destroy(eqs_mlp* n) {
     if (!n) return;
-    for (float* p : {n->master, n->wq, n->grad, n->m1, n->m2})
-        if (p) (void)hipFree(p);
-    if (n->st) (void)hipFree(n->st);
+    for (void* p : {(void*)n->master, (void*)n->wq, (void*)n->grad, (void*)n->m1, (void*)n->m2, (void*)n->st}) {
+        if (!p) continue;
+        if (n->owner) dev_free(n->owner, p);
+        else (void)hipFree(p);
+    }
     delete n;
+}
+
+int64_t mlp_device_bytes() {
+    auto r = [](int64_t b) { return (b + 255) / 256 * 256; };
+    return 5 * r((int64_t)sizeof(float) * kNParam) + r((int64_t)sizeof(MlpState));
+}
+
+void mlp_visit(eqs_mlp* n, const std::function<void(void**)>& f) {
+    if (!n) return;
+    f((void**)&n->master);
+    f((void**)&n->wq);
+    f((void**)&n->grad);
+    f((void**)&n->m1);
+    f((void**)&n->m2);
+    f((void**)&n->st);
 }
 
 void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B) {

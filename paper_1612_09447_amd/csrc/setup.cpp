@@ -10,6 +10,9 @@
 #include <cstring>
 #include <numeric>
 
+#include <functional>
+#include <iterator>
+
 #include "eqs_internal.h"
 
 namespace eqs {
@@ -480,13 +483,44 @@ void rkc_coefficients(int s, std::vector<double>& mu, std::vector<double>& nu, s
 }
 
 // ------------------------------------------------------------------ upload
+// Every device buffer of a context goes through dev_alloc: 256-byte granules,
+// from hipMalloc or, when the caller gave a workspace, first fit from its free
+// ranges.
+static constexpr int64_t kGranule = 256;
+static int64_t granules(size_t bytes) { return ((int64_t)std::max<size_t>(bytes, 1) + kGranule - 1) / kGranule * kGranule; }
+
+static bool in_workspace(const eqs_ctx* c, const void* p) {
+    return c->ws_base && (const char*)p >= c->ws_base && (const char*)p < c->ws_base + c->ws_size;
+}
+
+static void ws_reset(eqs_ctx* c) {
+    c->ws_free.clear();
+    c->ws_used = 0;
+    if (c->ws_base && c->ws_size > 0) c->ws_free[0] = c->ws_size;
+}
+
 void* dev_alloc(eqs_ctx* c, size_t bytes) {
+    const int64_t len = granules(bytes);
     void* p = nullptr;
-    if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) fail(EQS_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
-    c->allocations.push_back({p, bytes});
-    c->device_bytes += (int64_t)bytes;
+    if (c->ws_base) {
+        for (auto it = c->ws_free.begin(); it != c->ws_free.end(); ++it)
+            if (it->second >= len) {
+                const int64_t off = it->first, rest = it->second - len;
+                c->ws_free.erase(it);
+                if (rest > 0) c->ws_free[off + len] = rest;
+                p = c->ws_base + off;
+                break;
+            }
+        if (!p)
+            fail(EQS_ERR_ALLOC, "workspace too small: " + std::to_string(len) + " more bytes needed with " +
+                                    std::to_string(c->ws_size - c->ws_used) + " free (eqs_query gives the size)");
+        c->ws_used += len;
+    } else {
+        hipError_t e = hipMalloc(&p, (size_t)len);
+        if (e != hipSuccess) fail(EQS_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+        c->device_bytes += len;
+    }
+    c->allocations.push_back({p, (size_t)len});
     return p;
 }
 
@@ -494,11 +528,168 @@ void dev_free(eqs_ctx* c, void* p) {
     if (!p) return;
     for (size_t k = 0; k < c->allocations.size(); ++k)
         if (c->allocations[k].first == p) {
-            (void)hipFree(p);
-            c->device_bytes -= (int64_t)c->allocations[k].second;
+            const int64_t len = (int64_t)c->allocations[k].second;
+            if (in_workspace(c, p)) {
+                // back to the free ranges, merged with its neighbours
+                int64_t off = (char*)p - c->ws_base, n = len;
+                auto nx = c->ws_free.lower_bound(off);
+                if (nx != c->ws_free.end() && nx->first == off + n) {
+                    n += nx->second;
+                    nx = c->ws_free.erase(nx);
+                }
+                if (nx != c->ws_free.begin()) {
+                    auto pv = std::prev(nx);
+                    if (pv->first + pv->second == off) {
+                        off = pv->first;
+                        n += pv->second;
+                        c->ws_free.erase(pv);
+                    }
+                }
+                c->ws_free[off] = n;
+                c->ws_used -= len;
+            } else {
+                (void)hipFree(p);
+                c->device_bytes -= len;
+            }
             c->allocations.erase(c->allocations.begin() + k);
             return;
         }
+}
+
+int64_t workspace_need(const eqs_ctx* c) {
+    int64_t n = 0;
+    for (const auto& a : c->allocations) n += (int64_t)a.second;
+    return n + guess_pending_bytes(c);
+}
+
+template <typename T>
+static void visit_sell(Sell<T>& S, const std::function<void(void**)>& f) {
+    f((void**)&S.sptr);
+    f((void**)&S.col);
+    f((void**)&S.d16);
+    f((void**)&S.val);
+    f((void**)&S.perm);
+}
+template <typename T>
+static void visit_spmat(SpMat<T>& A, const std::function<void(void**)>& f) {
+    visit_sell(A.sell, f);
+    f((void**)&A.rowptr);
+    f((void**)&A.col);
+    f((void**)&A.d16);
+    f((void**)&A.val);
+}
+template <typename T>
+static void visit_hierarchy(Hierarchy<T>& h, const std::function<void(void**)>& f) {
+    for (Level<T>& lv : h.lv) {
+        visit_spmat(lv.A, f);
+        visit_spmat(lv.P, f);
+        visit_spmat(lv.R, f);
+        visit_spmat(lv.GQ, f);
+        for (T** q : {&lv.dinv, &lv.sval, &lv.b, &lv.x, &lv.xs, &lv.res, &lv.dense_inv, &lv.coarse_R}) f((void**)q);
+    }
+}
+
+void visit_device_ptrs(eqs_ctx* c, const std::function<void(void**)>& f) {
+    f((void**)&c->d_tpack);
+    f((void**)&c->d_bnodes);
+    f((void**)&c->d_boff);
+    f((void**)&c->d_cx);
+    f((void**)&c->d_cy);
+    f((void**)&c->d_cz);
+    f((void**)&c->d_mats);
+    f((void**)&c->d_ddrive);
+    f((void**)&c->d_drives);
+    f((void**)&c->d_int_to_user);
+    visit_sell(c->M, f);
+    visit_hierarchy(c->h64, f);
+    visit_hierarchy(c->h32, f);
+    for (double** q : {&c->d_r, &c->d_z, &c->d_p, &c->d_q, &c->d_mx, &c->d_Y0, &c->d_Ya, &c->d_Yb, &c->d_Yc, &c->d_F0,
+                       &c->d_F, &c->d_rhs, &c->d_rhs_alt, &c->d_tmpN, &c->d_tmpN2, &c->d_partials})
+        f((void**)q);
+    f((void**)&c->d_inst_row);
+    f((void**)&c->d_blk_inst);
+    f((void**)&c->d_scal);
+    f((void**)&c->d_sum);
+    f((void**)&c->d_force);
+    GuessState& g = c->guess;
+    for (double** q : {&g.d_S, &g.d_rprev, &g.d_alpha, &g.d_guard, &g.d_dots, &g.d_part}) f((void**)q);
+    f((void**)&g.d_gstat);
+    f((void**)&g.d_bx);
+    f((void**)&g.d_bt);
+    mlp_visit(g.net, f);
+}
+
+// Move every device buffer into [dev, dev + bytes) (dev NULL: into buffers
+// the library allocates), packed in allocation order, and remap every pointer
+// that points into an old buffer (interior pointers keep their offset). A
+// buffer that no visited pointer reaches stops the move before anything
+// changes.
+void set_workspace(eqs_ctx* c, void* dev, int64_t bytes) {
+    EQS_HIP(hipStreamSynchronize(c->stream));
+    if (c->guess.tstream) EQS_HIP(hipStreamSynchronize(c->guess.tstream));
+    const std::vector<std::pair<void*, size_t>> old = c->allocations;
+    auto owner = [&](const void* p) -> int {
+        for (size_t k = 0; k < old.size(); ++k)
+            if ((const char*)p >= (const char*)old[k].first && (const char*)p < (const char*)old[k].first + old[k].second)
+                return (int)k;
+        return -1;
+    };
+    std::vector<int> hits(old.size(), 0);
+    visit_device_ptrs(c, [&](void** pp) {
+        if (*pp) {
+            const int k = owner(*pp);
+            if (k >= 0) hits[k]++;
+        }
+    });
+    for (size_t k = 0; k < old.size(); ++k)
+        if (!hits[k]) fail(EQS_ERR_STATE, "internal: a device buffer of the context is not reachable for the move");
+    int64_t total = 0;
+    for (const auto& a : old) total += (int64_t)a.second;
+    if (dev) {
+        if (bytes < total)
+            fail(EQS_ERR_INVALID_ARG, "workspace too small: " + std::to_string(total) + " bytes needed, " +
+                                          std::to_string(bytes) + " given");
+        for (const auto& a : old)
+            if ((const char*)a.first < (const char*)dev + bytes && (const char*)dev < (const char*)a.first + a.second)
+                fail(EQS_ERR_INVALID_ARG, "workspace overlaps the context's own device memory");
+    }
+    std::vector<void*> fresh(old.size(), nullptr);
+    int64_t off = 0;
+    try {
+        for (size_t k = 0; k < old.size(); ++k) {
+            if (dev) {
+                fresh[k] = (char*)dev + off;
+                off += (int64_t)old[k].second;
+            } else {
+                hipError_t e = hipMalloc(&fresh[k], old[k].second);
+                if (e != hipSuccess) fail(EQS_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+            }
+        }
+        for (size_t k = 0; k < old.size(); ++k)
+            EQS_HIP(hipMemcpyAsync(fresh[k], old[k].first, old[k].second, hipMemcpyDeviceToDevice, c->stream));
+        EQS_HIP(hipStreamSynchronize(c->stream));
+    } catch (...) {
+        if (!dev)
+            for (void* p : fresh)
+                if (p) (void)hipFree(p);
+        throw;
+    }
+    release_graphs(c);  // captured iterations hold the old addresses
+    visit_device_ptrs(c, [&](void** pp) {
+        if (!*pp) return;
+        const int k = owner(*pp);
+        if (k >= 0) *pp = (char*)fresh[k] + ((char*)*pp - (char*)old[k].first);
+    });
+    for (size_t k = 0; k < old.size(); ++k)
+        if (!in_workspace(c, old[k].first)) (void)hipFree(old[k].first);
+    c->allocations.clear();
+    for (size_t k = 0; k < old.size(); ++k) c->allocations.push_back({fresh[k], old[k].second});
+    c->ws_base = (char*)dev;
+    c->ws_size = dev ? bytes : 0;
+    c->ws_free.clear();
+    c->ws_used = dev ? total : 0;
+    if (dev && bytes > total) c->ws_free[total] = bytes - total;
+    c->device_bytes = dev ? 0 : total;
 }
 
 template <typename T>
@@ -966,6 +1157,8 @@ static void upload_coarse_tail(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h) {
     // b_t and x_c side by side: the restriction from above writes b_t, the
     // dense product writes x_c, the sparse product reads both
     T* bx = (T*)dev_alloc(c, sizeof(T) * (size_t)(nt + nc));
+    dev_free(c, lt.b);  // the separate vectors they replace
+    dev_free(c, lc.x);
     lt.b = bx;
     lc.x = bx + nt;
     lt.tail = true;
@@ -1193,6 +1386,7 @@ void upload(eqs_ctx* c) {
         }
         c->d_blk_inst = upload_vec(c, bi);
     }
+    guess_alloc_scratch(c);  // eqs_galerkin_start's dot scratch
     launch_fill(c->stream, c->d_Y0, 0.0, NF);
     build_element_blocks(c, u2i, c->d_Y0, c->d_rhs);
     EQS_HIP(hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming));
@@ -1203,9 +1397,16 @@ void upload(eqs_ctx* c) {
 void free_device(eqs_ctx* c) {
     if (c->guess.tstream) (void)hipStreamSynchronize(c->guess.tstream);
     release_graphs(c);
-    for (auto& a : c->allocations) (void)hipFree(a.first);
+    // the network's buffers belong to this memory too
+    if (c->guess.net) {
+        mlp_destroy(c->guess.net);
+        c->guess.net = nullptr;
+    }
+    for (auto& a : c->allocations)
+        if (!in_workspace(c, a.first)) (void)hipFree(a.first);
     c->allocations.clear();
     c->device_bytes = 0;
+    ws_reset(c);  // a workspace stays attached, empty
     if (c->h_scal) { (void)hipHostFree(c->h_scal); c->h_scal = nullptr; c->d_hscal = nullptr; }
     if (c->h_sum) { (void)hipHostFree(c->h_sum); c->h_sum = nullptr; c->d_hsum = nullptr; }
     c->d_sum = nullptr; c->d_inst_row = nullptr; c->d_blk_inst = nullptr; c->d_force = nullptr;

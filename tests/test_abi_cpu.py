@@ -49,7 +49,7 @@ STRUCTS = {
     "eqs_guess_params": ["kind", "window", "capacity", "warmup", "batch", "bf16", "guard", "add_threshold", "lr", "seed",
                          "init"],
     "eqs_info": ["n_nodes", "n_tets", "n_free", "nnz_M", "n_levels", "precision", "level_rows", "level_nnz",
-                 "device_bytes"],
+                 "level_p_nnz", "level_r_nnz", "device_bytes", "workspace_bytes", "workspace_used"],
 }
 
 
@@ -119,6 +119,12 @@ def test_error_paths_without_device():
     # a NULL context is refused before any device work
     assert L.eqs_apply_M(None, None, None) == binding.EQS_ERR_INVALID_ARG
     assert L.eqs_galerkin_start(None, 1, None, None, None, None, None) == binding.EQS_ERR_INVALID_ARG
+    assert b"NULL" in L.eqs_last_error()
+    assert L.eqs_galerkin_start_noalloc(None, 1, None, None, None, None, None) == binding.EQS_ERR_INVALID_ARG
+    # the workspace calls
+    nf, ws = C.c_int64(), C.c_int64()
+    assert L.eqs_query(None, C.byref(nf), C.byref(ws)) == binding.EQS_ERR_INVALID_ARG
+    assert L.eqs_set_workspace(None, None, 0) == binding.EQS_ERR_INVALID_ARG
     assert b"NULL" in L.eqs_last_error()
     with pytest.raises(pkg.EqsError) as ei:
         pkg.Context(0)

@@ -85,6 +85,9 @@ def test_c2_first_step_matches_oracle(c2, oracle_ref):
         results.append(("FP64 hierarchy, rel-res 1e-12", traj_err(got, states), its, 1e-9))
     with Context(0, stream) as c:
         c.setup_case(c2, precision=EQS_PREC_FP32)
+        c.set_guess("mlp", init=eqsgen.mlp_init(4), warmup=0)
+        c.use_torch_workspace()  # every device buffer of these runs in torch memory
+        assert c.info()["device_bytes"] == 0
         for label, rtol, bar, guess in [("FP32 hierarchy, rel-res 1e-12", 1e-12, 1e-9, None),
                                         ("FP32 hierarchy, rel-res 1e-8", 1e-8, loose_bar(floor), None),
                                         ("FP32 + Galerkin start, rel-res 1e-12", 1e-12, 1e-9, "galerkin"),
