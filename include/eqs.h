@@ -238,6 +238,64 @@ int eqs_solve_M(eqs_ctx *ctx, const double *rhs_dev, double *y_dev, double rtol,
 int eqs_rkc_step(eqs_ctx *ctx, double t, double dt, int32_t s, double *x_dev, double rtol, int32_t maxit,
                  eqs_step_stats *st);
 
+/* ---- error-controlled stepping -----------------------------------------
+ * RKC with the step size and stage count chosen per step, as the paper runs
+ * it (Sec. V: local time-integration error below a tolerance; the controller
+ * is its ref. [9]'s). After a step of size tau from (t, y_n) to y_{n+1} the
+ * local error is estimated as
+ *   est = (12 (y_n - y_{n+1}) + 6 tau (F(t, y_n) + F(t + tau, y_{n+1}))) / 15
+ * and measured as err = sqrt(mean_i (est_i / (atol + rtol max(|y_n,i|,
+ * |y_{n+1},i|)))^2) over the free nodes; the step is accepted if err <= 1
+ * (F(t + tau, y_{n+1}) is then the next step's first stage). The next size is
+ * 0.8 tau err^(-1/3) after a rejection, tau max(0.1, min(10, 0.8 err^(-1/3)))
+ * after the first accepted step and tau max(0.1, min(10, 0.8 (tau/tau_prev)
+ * err_prev^(1/3) err^(-2/3))) after later ones, capped by tau_max and the end
+ * of the interval. Each step takes the smallest s >= 2 whose stability
+ * boundary covers it, beta(s) >= tau rho with rho = max over elements of
+ * sigma_e / eps_e (sigma = kappa0 (1 + (alpha + 1)(|E|/e_s)^alpha), the
+ * differential conductivity) at the step's start, an upper bound of the
+ * spectral radius of M^-1 times the Jacobian of K(x)x; beyond s_max the step
+ * is shortened to beta(s_max) / rho. */
+typedef struct eqs_adapt_params {
+    double atol;          /* absolute error weight (volts), > 0 */
+    double rtol;          /* relative error weight, >= 0 */
+    double tau0;          /* size of the first attempted step, > 0 */
+    double tau_min;       /* smallest step allowed, >= 0 (a smaller one fails with EQS_ERR_STATE) */
+    double tau_max;       /* largest step (0: t_end - t0) */
+    int32_t s_max;        /* 2..256 [0: 256] */
+    int32_t max_attempts; /* attempted steps before EQS_ERR_STATE [0: 100000] */
+} eqs_adapt_params;
+
+typedef struct eqs_adapt_record {
+    double t;     /* start of the attempted step */
+    double tau;   /* its size */
+    double err;   /* its error norm */
+    int32_t s;    /* its stages */
+    int32_t accepted;
+} eqs_adapt_record;
+
+typedef struct eqs_adapt_stats {
+    int32_t accepted;
+    int32_t rejected;
+    int32_t max_s;
+    int32_t not_converged; /* stage solves that hit maxit */
+    int64_t stages;        /* M-solves (one per stage, plus one per step for its end slope) */
+    int64_t cg_iters;
+    double last_tau;       /* the controller's next step size at t_end */
+} eqs_adapt_stats;
+
+/* Integrate from t0 to t_end with error-controlled RKC steps. x_dev (n_nodes
+ * doubles) holds x(t0) on entry (Dirichlet entries ignored) and x(t_end) on
+ * exit. Every M-solve runs CG to rtol from the previous solve's solution.
+ * rec (host, may be NULL) receives the first cap attempted steps and *n_rec
+ * (may be NULL) their total number; st may be NULL. Needs the plain or zero
+ * start vector (EQS_ERR_STATE otherwise) and a single instance. Returns
+ * EQS_ERR_NOT_CONVERGED if any solve hit maxit (the run still ends at
+ * t_end). */
+int eqs_rkc_adaptive(eqs_ctx *ctx, double t0, double t_end, double *x_dev, double rtol, int32_t maxit,
+                     const eqs_adapt_params *p, eqs_adapt_record *rec, int32_t cap, int32_t *n_rec,
+                     eqs_adapt_stats *st);
+
 /* ---- batches of independent instances ---------------------------------
  * A context can hold several independent EQS problems at once (the batched
  * form): their meshes are concatenated (node ids of instance i in

@@ -82,6 +82,21 @@ GUESS_KINDS = {"previous": EQS_GUESS_PREVIOUS, "zero": EQS_GUESS_ZERO, "galerkin
                "mlp": EQS_GUESS_MLP, "mor": EQS_GUESS_MOR}
 
 
+class eqs_adapt_params(C.Structure):
+    _fields_ = [("atol", C.c_double), ("rtol", C.c_double), ("tau0", C.c_double), ("tau_min", C.c_double),
+                ("tau_max", C.c_double), ("s_max", C.c_int32), ("max_attempts", C.c_int32)]
+
+
+class eqs_adapt_record(C.Structure):
+    _fields_ = [("t", C.c_double), ("tau", C.c_double), ("err", C.c_double), ("s", C.c_int32),
+                ("accepted", C.c_int32)]
+
+
+class eqs_adapt_stats(C.Structure):
+    _fields_ = [("accepted", C.c_int32), ("rejected", C.c_int32), ("max_s", C.c_int32), ("not_converged", C.c_int32),
+                ("stages", C.c_int64), ("cg_iters", C.c_int64), ("last_tau", C.c_double)]
+
+
 class eqs_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("n_free", C.c_int64), ("nnz_M", C.c_int64),
                 ("n_levels", C.c_int32), ("precision", C.c_int32), ("level_rows", C.c_int64 * 16),
@@ -106,6 +121,8 @@ _SIGNATURES = {
     "eqs_apply_preconditioner": ([_P, _P, _P], C.c_int),
     "eqs_solve_M": ([_P, _P, _P, C.c_double, C.c_int32, _P], C.c_int),
     "eqs_rkc_step": ([_P, C.c_double, C.c_double, C.c_int32, _P, C.c_double, C.c_int32, _P], C.c_int),
+    "eqs_rkc_adaptive": ([_P, C.c_double, C.c_double, _P, C.c_double, C.c_int32, _P, _P, C.c_int32,
+                          C.POINTER(C.c_int32), _P], C.c_int),
     "eqs_set_guess": ([_P, _P], C.c_int),
     "eqs_galerkin_start": ([_P, C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_int32)], C.c_int),
     "eqs_galerkin_start_noalloc": ([_P, C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_int32)], C.c_int),
@@ -378,6 +395,24 @@ class Context:
         return dict(stages=st.stages, total_iters=st.total_iters, max_iters=st.max_iters, min_iters=st.min_iters,
                     not_converged=st.not_converged, guess_used=st.guess_used, guess_fallbacks=st.guess_fallbacks,
                     max_relres=st.max_relres, train_loss=st.train_loss, rc=rc)
+
+    def rkc_adaptive(self, t0, t_end, x, rtol, atol_err, rtol_err, tau0, maxit=1000, s_max=0, tau_min=0.0,
+                     tau_max=0.0, max_attempts=0, cap=100000, allow_not_converged=False):
+        """Error-controlled RKC from t0 to t_end (eqs_rkc_adaptive); returns the
+        stats and the list of attempted steps (t, tau, s, err, accepted)."""
+        p = eqs_adapt_params(float(atol_err), float(rtol_err), float(tau0), float(tau_min), float(tau_max),
+                             int(s_max), int(max_attempts))
+        recs = (eqs_adapt_record * cap)()
+        n = C.c_int32(0)
+        st = eqs_adapt_stats()
+        ok = (EQS_OK, EQS_ERR_NOT_CONVERGED) if allow_not_converged else (EQS_OK,)
+        rc = lib().eqs_rkc_adaptive(self._h, float(t0), float(t_end), _dev(x), float(rtol), int(maxit), C.byref(p),
+                                    C.cast(recs, _P), cap, C.byref(n), C.byref(st))
+        _check(rc, "eqs_rkc_adaptive", ok)
+        steps = [dict(t=recs[k].t, tau=recs[k].tau, s=recs[k].s, err=recs[k].err, accepted=bool(recs[k].accepted))
+                 for k in range(min(n.value, cap))]
+        return dict(accepted=st.accepted, rejected=st.rejected, max_s=st.max_s, not_converged=st.not_converged,
+                    stages=st.stages, cg_iters=st.cg_iters, last_tau=st.last_tau, rc=rc), steps
 
     def set_guess(self, kind="previous", init=None, **kw):
         """Select the stage start vector: previous, zero, galerkin (eq. (5) on a sliding

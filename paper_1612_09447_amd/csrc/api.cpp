@@ -385,6 +385,32 @@ int eqs_rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_dev, doub
     });
 }
 
+int eqs_rkc_adaptive(eqs_ctx* c, double t0, double t_end, double* x_dev, double rtol, int32_t maxit,
+                     const eqs_adapt_params* p, eqs_adapt_record* rec, int32_t cap, int32_t* n_rec,
+                     eqs_adapt_stats* st) {
+    return guarded([&] {
+        need(c != nullptr && x_dev != nullptr && p != nullptr, "NULL argument");
+        need(std::isfinite(t0) && std::isfinite(t_end) && t_end > t0, "need finite t0 < t_end");
+        need(std::isfinite(rtol) && rtol >= 0, "rtol must be finite and >= 0");
+        need(maxit >= 0, "maxit must be >= 0");
+        need(std::isfinite(p->atol) && p->atol > 0, "atol must be > 0");
+        need(std::isfinite(p->rtol) && p->rtol >= 0, "the error weight rtol must be >= 0");
+        need(std::isfinite(p->tau0) && p->tau0 > 0, "tau0 must be > 0");
+        need(std::isfinite(p->tau_min) && p->tau_min >= 0, "tau_min must be >= 0");
+        need(std::isfinite(p->tau_max) && p->tau_max >= 0, "tau_max must be >= 0");
+        need(p->s_max == 0 || (p->s_max >= 2 && p->s_max <= 256), "s_max must be 0 or in [2, 256]");
+        need(p->max_attempts >= 0, "max_attempts must be >= 0");
+        need(cap >= 0 && (cap == 0 || rec != nullptr), "rec must hold cap records");
+        need_built(c);
+        if (c->n_inst != 1) fail(EQS_ERR_STATE, "adaptive stepping needs a single instance");
+        if (c->guess.p.kind != EQS_GUESS_PREVIOUS && c->guess.p.kind != EQS_GUESS_ZERO)
+            fail(EQS_ERR_STATE, "adaptive stepping runs with the plain or the zero start vector");
+        bind_device(c);
+        return result_code(eqs::rkc_adaptive(c, t0, t_end, x_dev, rtol, maxit, *p, rec, cap, n_rec, st),
+                           "eqs_rkc_adaptive");
+    });
+}
+
 int eqs_set_instances(eqs_ctx* c, int32_t n_inst, const int64_t* node_off, const int64_t* tet_off) {
     return guarded([&] {
         need(c != nullptr && node_off != nullptr && tet_off != nullptr, "NULL argument");

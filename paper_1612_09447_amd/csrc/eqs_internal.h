@@ -351,6 +351,12 @@ struct AmgHost {
 AmgHost build_sa_amg(const Csr<double>& M, const eqs_amg_params& p);
 void rkc_coefficients(int s, std::vector<double>& mu, std::vector<double>& nu, std::vector<double>& mut,
                       std::vector<double>& gmt, std::vector<double>& c);
+double rkc_beta(int s);
+// adaptive stepping: max over elements of sigma_e / eps_e at (t, yfree), and
+// ref. [9]'s weighted RMS error norm of one step (both synchronise)
+double max_rate(eqs_ctx* c, const double* yfree, double t);
+double error_norm(eqs_ctx* c, const double* y0, const double* y1, const double* f0, const double* f1, double tau,
+                  double atol, double rtol);
 
 // device upload
 void* dev_alloc(eqs_ctx* c, size_t bytes);
@@ -465,6 +471,8 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
 int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double rtol, int32_t maxit,
              eqs_step_stats* st);
 void apply_preconditioner(eqs_ctx* c, const double* r, double* z);
+int rkc_adaptive(eqs_ctx* c, double t0, double t_end, double* x_user, double rtol, int32_t maxit,
+                 const eqs_adapt_params& p, eqs_adapt_record* rec, int32_t cap, int32_t* n_rec, eqs_adapt_stats* st);
 void release_graphs(eqs_ctx* c);
 
 }  // namespace eqs

@@ -14,6 +14,8 @@
 //    partials into the CG scalars, kept in device memory.
 //  * RKC stage combination (the paper's ref. [9]).
 #include <algorithm>
+#include <cmath>
+#include <vector>
 
 #include <hip/hip_ext.h>
 
@@ -501,6 +503,65 @@ __global__ __launch_bounds__(kTetBlock, 6) void k_kx(KxArgs A) {
     kx_scatter<RHS, STRIDE>(A, lds, off, nn);
 }
 
+// Spectral bound of one element block for the adaptive stage choice: the
+// largest sigma_e / eps_e over the block's tets, with sigma = kappa0 (1 +
+// (alpha + 1)(|E|/e_s)^alpha) the differential conductivity at the element's
+// field (|E| = |w| / |det| as in kx_tets); folded into *out with an atomic
+// maximum on the bits of non-negative doubles (whose order is the integers').
+template <int TPT, int STRIDE>
+__global__ __launch_bounds__(kTetBlock, 6) void k_kx_rate(KxArgs A) {
+    extern __shared__ double lds[];
+    __shared__ double wmax[kTetBlock / 64];
+    const int64_t b = xcd_block(blockIdx.x, A.n_blocks);
+    uint64_t rec[TPT];
+    kx_records<TPT>(A, b, rec);
+    const int32_t off = A.boff[b];
+    const int32_t nn = A.boff[b + 1] - off;
+    kx_stage<false, STRIDE>(A, lds, off, nn);
+    __syncthreads();
+    const int32_t S = kx_stride<STRIDE>(nn);
+    const double* PX = lds;
+    const double* PY = PX + S;
+    const double* PZ = PY + S;
+    const double* PU = PZ + S;
+    double best = 0.0;
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+        const uint64_t w = rec[i];
+        if (w == ~0ull) continue;
+        const MatDev m = A.mats[(uint32_t)(w & 0xffffu)];
+        int l[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) l[a] = (int)((w >> (16 + 12 * a)) & 0xfffu);
+        const double e1x = PX[l[1]] - PX[l[0]], e1y = PY[l[1]] - PY[l[0]], e1z = PZ[l[1]] - PZ[l[0]];
+        const double e2x = PX[l[2]] - PX[l[0]], e2y = PY[l[2]] - PY[l[0]], e2z = PZ[l[2]] - PZ[l[0]];
+        const double e3x = PX[l[3]] - PX[l[0]], e3y = PY[l[3]] - PY[l[0]], e3z = PZ[l[3]] - PZ[l[0]];
+        const double c1x = e2y * e3z - e2z * e3y, c1y = e2z * e3x - e2x * e3z, c1z = e2x * e3y - e2y * e3x;
+        const double c2x = e3y * e1z - e3z * e1y, c2y = e3z * e1x - e3x * e1z, c2z = e3x * e1y - e3y * e1x;
+        const double c3x = e1y * e2z - e1z * e2y, c3y = e1z * e2x - e1x * e2z, c3z = e1x * e2y - e1y * e2x;
+        const double det = e1x * c1x + e1y * c1y + e1z * c1z;
+        const double d1 = PU[l[1]] - PU[l[0]], d2 = PU[l[2]] - PU[l[0]], d3 = PU[l[3]] - PU[l[0]];
+        const double wx = c1x * d1 + c2x * d2 + c3x * d3;
+        const double wy = c1y * d1 + c2y * d2 + c3y * d3;
+        const double wz = c1z * d1 + c2z * d2 + c3z * d3;
+        double sig = m.kappa0;
+        if (m.nonlinear) {
+            const double ratio = sqrt(wx * wx + wy * wy + wz * wz) / fabs(det) * m.inv_es;
+            const double pw = (m.ialpha >= 0) ? ipow(ratio, m.ialpha) : exp(m.alpha * log(ratio));
+            sig *= 1.0 + (m.alpha + 1.0) * pw;
+        }
+        best = fmax(best, sig / m.eps);
+    }
+    for (int o = 32; o > 0; o >>= 1) best = fmax(best, __shfl_xor(best, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = wmax[0];
+        for (int k = 1; k < kTetBlock / 64; ++k) v = fmax(v, wmax[k]);
+        atomicMax((unsigned long long*)A.out, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
 // Fixed LDS stride for blocks of kTetBlock * TPT tets: above the node count of
 // such blocks on tetrahedral meshes of Kuhn or similar quality (about 0.33
 // nodes per tet for large blocks). Blocks with more nodes take the kernel with
@@ -528,6 +589,69 @@ static void launch_kx_t(hipStream_t s, eqs_ctx* c, const double* yfree, double t
         default: fail(EQS_ERR_STATE, "element blocks not built");
     }
 #undef EQS_KX
+}
+
+double max_rate(eqs_ctx* c, const double* yfree, double t) {
+    hipStream_t s = c->stream;
+    double* slot = c->d_partials;  // free between CG solves
+    launch_fill(s, slot, 0.0, 1);
+    const KxArgs A{c->n_tets, c->n_blocks, c->d_tpack, c->d_boff, c->d_bnodes, c->d_cx, c->d_cy, c->d_cz, c->d_mats,
+                   yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, slot};
+    const dim3 b(kTetBlock), g((unsigned)c->n_blocks);
+    const int tpt = c->tet_tpt;
+    const bool fixed = tpt >= 1 && c->max_block_nodes <= kx_fixed_stride(tpt) && !c->kx_generic;
+    const size_t lds = sizeof(double) * 6 * (size_t)(fixed ? kx_fixed_stride(tpt) : c->max_block_nodes);
+#define EQS_KR(TPT_)                                                                                     \
+    do {                                                                                                 \
+        if (fixed) hipLaunchKernelGGL((k_kx_rate<TPT_, kx_fixed_stride(TPT_)>), g, b, lds, s, A);        \
+        else hipLaunchKernelGGL((k_kx_rate<TPT_, 0>), g, b, lds, s, A);                                  \
+    } while (0)
+    switch (tpt) {
+        case 1: EQS_KR(1); break;
+        case 2: EQS_KR(2); break;
+        case 4: EQS_KR(4); break;
+        case 8: EQS_KR(8); break;
+        default: fail(EQS_ERR_STATE, "element blocks not built");
+    }
+#undef EQS_KR
+    double v = 0.0;
+    EQS_HIP(hipMemcpyAsync(&v, slot, sizeof v, hipMemcpyDeviceToHost, s));
+    EQS_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+// Ref. [9]'s local error estimate est = (12 (y0 - y1) + 6 tau (f0 + f1)) / 15
+// in the weighted RMS norm: per-block sums of (est_i / w_i)^2 with
+// w_i = atol + rtol max(|y0_i|, |y1_i|), in a fixed order.
+__global__ __launch_bounds__(256) void k_err_sq(const double* __restrict__ y0, const double* __restrict__ y1,
+                                                 const double* __restrict__ f0, const double* __restrict__ f1,
+                                                 double tau, double atol, double rtol, int64_t n,
+                                                 double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[1] = {0.0};
+    if (i < n) {
+        const double a = y0[i], b = y1[i];
+        const double est = (12.0 * (a - b) + 6.0 * tau * (f0[i] + f1[i])) / 15.0;
+        const double q = est / (atol + rtol * fmax(fabs(a), fabs(b)));
+        v[0] = q * q;
+    }
+    block_sums<1>(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+double error_norm(eqs_ctx* c, const double* y0, const double* y1, const double* f0, const double* f1, double tau,
+                  double atol, double rtol) {
+    hipStream_t s = c->stream;
+    const int64_t n = c->n_free;
+    const unsigned nb = grid_for(n);
+    hipLaunchKernelGGL(k_err_sq, dim3(nb), dim3(kBlock), 0, s, y0, y1, f0, f1, tau, atol, rtol, n, c->d_partials);
+    std::vector<double> part(nb);
+    EQS_HIP(hipMemcpyAsync(part.data(), c->d_partials, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    EQS_HIP(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (double x : part) sum += x;
+    return std::sqrt(sum / (double)n);
 }
 
 void launch_kx(hipStream_t s, bool rhs_mode, eqs_ctx* c, const double* yfree, double t, double* out, bool zeroed) {

@@ -451,6 +451,17 @@ AmgHost build_sa_amg(const Csr<double>& M, const eqs_amg_params& p) {
 }
 
 // ---------------------------------------------------------------- RKC(s)
+// Stability boundary beta(s) = (1 + w0) / w1 of RKC(s) (ref. [9]), damping 2/13.
+double rkc_beta(int s) {
+    const double w0 = 1.0 + (2.0 / 13.0) / ((double)s * s);
+    double T0 = 1.0, T = w0, d0 = 0.0, d = 1.0, dd0 = 0.0, dd = 0.0;  // T_j, T_j', T_j'' at w0 (j = 1)
+    for (int j = 2; j <= s; ++j) {
+        const double Tn = 2.0 * w0 * T - T0, dn = 2.0 * T + 2.0 * w0 * d - d0, ddn = 4.0 * d + 2.0 * w0 * dd - dd0;
+        T0 = T; T = Tn; d0 = d; d = dn; dd0 = dd; dd = ddn;
+    }
+    return (1.0 + w0) / (d / dd);
+}
+
 // Coefficients of the s-stage second-order RKC method (ref. [9]: Sommeijer,
 // Shampine, Verwer), damping 2/13. Index j = 0..s; mu, nu, mut (mu~), gmt
 // (gamma~) are used for j >= 2 (mut also for j = 1); c are the stage times.

@@ -287,4 +287,152 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
     return rc;
 }
 
+// ------------------------------------------------------------- adaptive
+// One RKC(s) attempt from Y_0 = d_Y0 with F_0 = d_F0 already known: stages
+// 1..s-1 (element pass + solve each), combinations into the three Y buffers.
+// Returns the buffer holding Y_s; solve statistics go to S.
+static const double* rkc_attempt(eqs_ctx* c, double t, double dt, int s, double rtol, int32_t maxit,
+                                 eqs_step_stats& S, int& rc) {
+    std::vector<double> mu, nu, mut, gmt, cc;
+    rkc_coefficients(s, mu, nu, mut, gmt, cc);
+    hipStream_t q = c->stream;
+    const int64_t NF = c->n_free;
+    if (c->guess.p.kind == EQS_GUESS_ZERO) launch_fill(q, c->d_F, 0.0, NF);
+    else launch_copy(q, c->d_F, c->d_F0, NF);  // the first solve starts from F_0
+    c->mx_of_F = false;
+    double* const ybuf[3] = {c->d_Ya, c->d_Yb, c->d_Yc};
+    const double* Yprev = c->d_Y0;
+    double* Ycur = ybuf[0];
+    launch_rkc_first(c, q, Ycur, c->d_Y0, c->d_F0, mut[1] * dt, NF, c->d_rhs);  // also clears the next RHS
+    for (int j = 1; j < s; ++j) {
+        launch_kx(q, true, c, Ycur, t + cc[j] * dt, c->d_rhs, true);
+        if (c->guess.p.kind == EQS_GUESS_ZERO) launch_fill(q, c->d_F, 0.0, NF);
+        eqs_solve_stats ss{};
+        const int src = solve_M(c, c->d_rhs, c->d_F, rtol, maxit, &ss);
+        S.total_iters += ss.iters;
+        S.max_relres = std::max(S.max_relres, ss.relres);
+        if (src == EQS_ERR_NOT_CONVERGED) {
+            S.not_converged++;
+            rc = EQS_ERR_NOT_CONVERGED;
+        } else if (src != EQS_OK) {
+            rc = src;
+            return nullptr;
+        }
+        double* out = ybuf[0];
+        for (double* b : ybuf)
+            if (b != Ycur && b != Yprev) {
+                out = b;
+                break;
+            }
+        const int k = j + 1;
+        launch_rkc_combine(c, q, out, c->d_Y0, Ycur, Yprev, c->d_F, c->d_F0, 1.0 - mu[k] - nu[k], mu[k], nu[k],
+                           mut[k] * dt, gmt[k] * dt, NF, k < s ? c->d_rhs : nullptr);
+        check_launch();
+        Yprev = Ycur;
+        Ycur = out;
+    }
+    return Ycur;
+}
+
+// F = M^{-1}(b(t) - K(x_bar)x_bar) at (t, y) into d_F (CG from d_F's content).
+static int stage_solve(eqs_ctx* c, const double* y, double t, double rtol, int32_t maxit, eqs_adapt_stats& A) {
+    launch_kx(c->stream, true, c, y, t, c->d_rhs);
+    if (c->guess.p.kind == EQS_GUESS_ZERO) launch_fill(c->stream, c->d_F, 0.0, c->n_free);
+    eqs_solve_stats ss{};
+    const int rc = solve_M(c, c->d_rhs, c->d_F, rtol, maxit, &ss);
+    c->mx_of_F = false;
+    A.stages++;
+    A.cg_iters += ss.iters;
+    if (rc == EQS_ERR_NOT_CONVERGED) A.not_converged++;
+    return rc;
+}
+
+int rkc_adaptive(eqs_ctx* c, double t0, double t_end, double* x_user, double rtol, int32_t maxit,
+                 const eqs_adapt_params& p, eqs_adapt_record* rec, int32_t cap, int32_t* n_rec, eqs_adapt_stats* st) {
+    hipStream_t q = c->stream;
+    const int64_t NF = c->n_free;
+    const double tau_max = p.tau_max > 0 ? p.tau_max : t_end - t0;
+    const int s_max = p.s_max > 0 ? p.s_max : 256;
+    const int max_att = p.max_attempts > 0 ? p.max_attempts : 100000;
+    eqs_adapt_stats A{};
+    int rc = EQS_OK;
+    int32_t n = 0;
+    auto finish = [&](int code) {
+        if (n_rec) *n_rec = n;
+        if (st) *st = A;
+        return code;
+    };
+    launch_gather(q, x_user, c->d_int_to_user, c->d_Y0, NF);
+    if (!c->have_Flast) launch_fill(q, c->d_F, 0.0, NF);
+    c->have_Flast = false;
+    // F_0 of the first step
+    int src = stage_solve(c, c->d_Y0, t0, rtol, maxit, A);
+    if (src != EQS_OK && src != EQS_ERR_NOT_CONVERGED) return finish(src);
+    if (src == EQS_ERR_NOT_CONVERGED) rc = src;
+    launch_copy(q, c->d_F0, c->d_F, NF);
+    double t = t0, tau = std::min(p.tau0, tau_max), tau_prev = -1.0, err_prev = -1.0;
+    while (t < t_end) {
+        if (n >= max_att) {
+            set_error("eqs_rkc_adaptive: too many attempted steps");
+            return finish(EQS_ERR_STATE);
+        }
+        bool last = tau >= t_end - t;
+        if (last) tau = t_end - t;
+        // stages: the smallest s >= 2 with beta(s) >= tau rho (s_max and a
+        // shorter step when even that does not cover it)
+        const double rho = max_rate(c, c->d_Y0, t);
+        int s = 2;
+        if (rho > 0.0) {
+            while (s < s_max && rkc_beta(s) < tau * rho) ++s;
+            if (rkc_beta(s) < tau * rho) {
+                tau = rkc_beta(s) / rho;
+                last = false;
+            }
+        }
+        eqs_step_stats S{};
+        const double* Ys = rkc_attempt(c, t, tau, s, rtol, maxit, S, rc);
+        A.stages += s - 1;
+        A.cg_iters += S.total_iters;
+        A.not_converged += S.not_converged;
+        if (!Ys) return finish(rc);
+        const double t1 = last ? t_end : t + tau;
+        src = stage_solve(c, Ys, t1, rtol, maxit, A);  // F(t + tau, y_{n+1}), from F_{s-1}
+        if (src != EQS_OK && src != EQS_ERR_NOT_CONVERGED) return finish(src);
+        if (src == EQS_ERR_NOT_CONVERGED) rc = src;
+        const double err = error_norm(c, c->d_Y0, Ys, c->d_F0, c->d_F, tau, p.atol, p.rtol);
+        const bool ok = err <= 1.0;
+        if (rec && n < cap) rec[n] = eqs_adapt_record{t, tau, err, s, ok ? 1 : 0};
+        ++n;
+        A.max_s = std::max(A.max_s, s);
+        double next;
+        if (ok) {
+            A.accepted++;
+            launch_copy(q, c->d_Y0, Ys, NF);
+            launch_copy(q, c->d_F0, c->d_F, NF);
+            t = t1;
+            if (err == 0.0) next = 10.0 * tau;
+            else if (tau_prev < 0.0) next = tau * std::max(0.1, std::min(10.0, 0.8 / std::cbrt(err)));
+            else
+                next = tau * std::max(0.1, std::min(10.0, 0.8 * (tau / tau_prev) * std::cbrt(err_prev) /
+                                                              std::pow(err, 2.0 / 3.0)));
+            tau_prev = tau;
+            err_prev = err;
+        } else {
+            A.rejected++;
+            next = 0.8 * tau / std::cbrt(err);
+        }
+        if (!(next >= p.tau_min) || !std::isfinite(next)) {
+            set_error("eqs_rkc_adaptive: step size below tau_min");
+            return finish(EQS_ERR_STATE);
+        }
+        tau = std::min(next, tau_max);
+    }
+    A.last_tau = tau;
+    launch_finish_state(c, c->d_Y0, t_end, x_user);
+    check_launch();
+    EQS_HIP(hipStreamSynchronize(q));
+    c->have_Flast = true;  // d_F holds F(t_end, x(t_end)): the next stage solve starts there
+    return finish(rc);
+}
+
 }  // namespace eqs

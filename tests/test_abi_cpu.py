@@ -48,6 +48,9 @@ STRUCTS = {
                        "guess_fallbacks", "reserved", "max_relres", "train_loss"],
     "eqs_guess_params": ["kind", "window", "capacity", "warmup", "batch", "bf16", "guard", "add_threshold", "lr", "seed",
                          "init"],
+    "eqs_adapt_params": ["atol", "rtol", "tau0", "tau_min", "tau_max", "s_max", "max_attempts"],
+    "eqs_adapt_record": ["t", "tau", "err", "s", "accepted"],
+    "eqs_adapt_stats": ["accepted", "rejected", "max_s", "not_converged", "stages", "cg_iters", "last_tau"],
     "eqs_info": ["n_nodes", "n_tets", "n_free", "nnz_M", "n_levels", "precision", "level_rows", "level_nnz",
                  "level_p_nnz", "level_r_nnz", "device_bytes", "workspace_bytes", "workspace_used"],
 }
