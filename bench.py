@@ -327,6 +327,39 @@ def state_errors(hist, ref, free):
             "steps_compared": int(hist.shape[0])}
 
 
+def run_adaptive(case, precision, t_end, tol):
+    """Error-controlled RKC over [0, t_end] (local error `tol` relative to the
+    drive amplitude and relative to the potential, as Sec. V runs it), on a
+    torch workspace; the fixed-step workload needs t_end / tau steps of s
+    stages for the same interval."""
+    import torch
+
+    from paper_1612_09447_amd import Context
+
+    dev = torch.device("cuda:0")
+    ctx = Context(0, torch.cuda.current_stream(dev))
+    ctx.setup_case(case, precision=precision)
+    ws = ctx.use_torch_workspace()
+    x = torch.zeros(case.n_nodes, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st, steps = ctx.rkc_adaptive(0.0, t_end, x, case.rtol, tol * float(max(case.amp)), tol, case.tau, s_max=256)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    ctx.close()
+    del ws
+    fixed_stages = round(t_end / case.tau) * case.s
+    acc = [d for d in steps if d["accepted"]]
+    log(f"[bench] adaptive: {st['accepted']} accepted, {st['rejected']} rejected, {st['stages']} solves in {el:.2f}s")
+    return {"t_end_s": t_end, "local_error_tol": tol, "accepted_steps": st["accepted"], "rejected_steps": st["rejected"],
+            "max_stages": st["max_s"], "solves": st["stages"], "cg_iters": st["cg_iters"],
+            "mean_cg_iters_per_solve": round(st["cg_iters"] / max(1, st["stages"]), 2), "wall_s": round(el, 3),
+            "solves_per_s": round(st["stages"] / el, 1),
+            "step_sizes_s": {"min": min(d["tau"] for d in acc), "max": max(d["tau"] for d in acc)},
+            "fixed_step_solves_same_interval": fixed_stages,
+            "solve_ratio_fixed_over_adaptive": round(fixed_stages / max(1, st["stages"]), 2)}
+
+
 def run_batched(steps, warmup):
     """The batched workload: 64 independent instances (n in {16..48}^3) packed
     into one context, RKC(8) steps of all of them together."""
@@ -404,6 +437,8 @@ def main():
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     ap.add_argument("--c3-steps", type=int, default=5, help="also time the 64-instance batched workload (0: skip)")
     ap.add_argument("--mlp-batch", type=int, default=128, help="network training pairs per stage (<= 256)")
+    ap.add_argument("--adaptive-ms", type=float, default=20.0,
+                    help="also run error-controlled RKC (local error 1e-2) over this many ms (0: skip)")
     ap.add_argument("--full-runs", default="mlp,galerkin",
                     help="start vectors timed over the whole run beside the plain one (comma list; empty: none)")
     ap.add_argument("--learned-steps", type=int, default=5,
@@ -500,6 +535,7 @@ def main():
     torch.cuda.empty_cache()
 
     batched = run_batched(args.c3_steps, 1) if args.c3_steps > 0 else None
+    adaptive = run_adaptive(case, main_prec, args.adaptive_ms * 1e-3, 1e-2) if args.adaptive_ms > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -544,6 +580,7 @@ def main():
         "start_vector_runs": full or None,
         "mixed_learned_vs_fp64": mixed_learned_vs_fp64(plain, r["learned"], full),
         "batched": batched,
+        "adaptive": adaptive,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -53,13 +53,14 @@ struct InstMap {
     int32_t rows1;  // the row count when n_inst == 1 (no table lookups then), else -1
 };
 
-__device__ __forceinline__ void block_instances(const InstMap& m, int32_t& lo, int32_t& bound) {
+// B: the block's row-block index (its logical block, see row_block)
+__device__ __forceinline__ void block_instances(const InstMap& m, int32_t& lo, int32_t& bound, int64_t B) {
     if (m.rows1 >= 0) {
         lo = 0;
         bound = m.rows1;
         return;
     }
-    lo = m.blk_inst[blockIdx.x];
+    lo = m.blk_inst[B];
     bound = m.row_off[lo + 1];
 }
 
@@ -89,9 +90,9 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double* sh) {
 constexpr int kPairSh = 16;  // doubles of shared memory store_pairs needs (NP <= 2)
 template <int NP>
 __device__ __forceinline__ void store_pairs(double* const (&part)[NP], const double (&v)[NP], bool second,
-                                            int32_t bound, double* sh) {
+                                            int32_t bound, double* sh, int64_t B) {
     static_assert(NP >= 1 && NP <= 2, "at most two partial arrays");
-    const bool split = (int64_t)bound < (int64_t)(blockIdx.x + 1) * blockDim.x;  // uniform over the block
+    const bool split = (int64_t)bound < (B + 1) * (int64_t)blockDim.x;  // uniform over the block
     if (!split) {
         double a[NP];
 #pragma unroll
@@ -100,8 +101,8 @@ __device__ __forceinline__ void store_pairs(double* const (&part)[NP], const dou
         if (threadIdx.x == 0)
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                part[p][2 * blockIdx.x] = a[p];
-                part[p][2 * blockIdx.x + 1] = 0.0;
+                part[p][2 * B] = a[p];
+                part[p][2 * B + 1] = 0.0;
             }
     } else {
         double a[2 * NP];
@@ -114,8 +115,8 @@ __device__ __forceinline__ void store_pairs(double* const (&part)[NP], const dou
         if (threadIdx.x == 0)
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                part[p][2 * blockIdx.x] = a[2 * p];
-                part[p][2 * blockIdx.x + 1] = a[2 * p + 1];
+                part[p][2 * B] = a[2 * p];
+                part[p][2 * B + 1] = a[2 * p + 1];
             }
     }
 }
@@ -323,10 +324,6 @@ __device__ __forceinline__ double ipow(double x, int n) {
 // Workgroups are mapped so that each XCD (workgroups are dealt to the 8 XCDs
 // round-robin) walks a contiguous range of Morton-ordered blocks: nodes
 // shared by neighbouring blocks then meet in the same L2.
-__device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t nb) {
-    const int64_t q = nb >> 3, r = nb & 7, x = i & 7;
-    return x * q + (x < r ? x : r) + (i >> 3);
-}
 
 // Stage a block's nodes in LDS (one array per quantity: 8-byte stride, so
 // gathers spread over the banks). Returns whether the block touches a
@@ -712,7 +709,7 @@ template <int L, typename T>
 __global__ __launch_bounds__(256, kSparseWaves) void k_sell_mv(SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
                                                   MvInit<T> in, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = row_block() * blockDim.x + threadIdx.x;
     if (g >= (int64_t)A.n_slices * 64) return;  // whole wavefronts leave together
     const int32_t row = sell_perm_row<L>(A.perm, g);
     const T v = sell_row<L>(A, g, row, x);
@@ -721,7 +718,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_sell_mv(SellView<T> A, co
 
 __global__ __launch_bounds__(256, kSparseWaves) void k_spmv64(SellView<double> A, const double* __restrict__ x,
                                                  double* __restrict__ y) {
-    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t row = (int32_t)(row_block() * blockDim.x + threadIdx.x);
     if (row >= A.n_slices * 64) return;
     const double v = sell_row(A, row, x);
     if (row < A.n_rows) y[row] = v;
@@ -741,7 +738,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_presmooth_res(SellView<T>
                                                         const TB* __restrict__ b, T* __restrict__ x,
                                                         T* __restrict__ res, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = row_block() * blockDim.x + threadIdx.x;
     if (g >= (int64_t)As.n_slices * 64) return;
     const int32_t row = sell_row_of<L>(g);
     const T acc = sell_row<L>(As, g, row, b);
@@ -765,7 +762,8 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_postsmooth(SellView<T> A,
     static_assert(!DOT || L == 1, "CG partials are produced by the one-lane-per-row finest level");
     __shared__ double sh[kPairSh];
     if (stop && *stop) return;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t B = row_block();
+    const int64_t g = B * blockDim.x + threadIdx.x;
     const int32_t row = sell_row_of<L>(g);
     double rz = 0.0, rzo = 0.0;
     if (g < (int64_t)A.n_slices * 64) {
@@ -782,10 +780,10 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_postsmooth(SellView<T> A,
     }
     if (DOT) {
         int32_t lo, bound;
-        block_instances(m, lo, bound);
+        block_instances(m, lo, bound, B);
         double* const parts[2] = {part_rz, part_rzold};
         const double vals[2] = {rz, rzo};
-        store_pairs<2>(parts, vals, row >= bound, bound, sh);
+        store_pairs<2>(parts, vals, row >= bound, bound, sh, B);
     }
 }
 
@@ -844,7 +842,7 @@ template <int L, typename T>
 __global__ __launch_bounds__(256, kSparseWaves) void k_csr_mv(CsrView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
                                                  MvInit<T> in, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = row_block() * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
     if (row >= A.n_rows) return;  // whole groups leave together
@@ -857,7 +855,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_csr_presmooth_res(CsrView
                                                             const TB* __restrict__ b, T* __restrict__ x,
                                                             T* __restrict__ res, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = row_block() * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
     if (row >= As.n_rows) return;
@@ -874,7 +872,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_csr_postsmooth(CsrView<T>
                                                          const TB* __restrict__ b, const T* __restrict__ x,
                                                          TO* __restrict__ out, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = row_block() * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
     if (row >= A.n_rows) return;
@@ -1038,6 +1036,7 @@ __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv
                                                         const int32_t* __restrict__ stop) {
     __shared__ double sh[kPairSh];
     if (stop && *stop) return;
+    const int64_t B = blockIdx.x;
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     double rz = 0.0, rzo = 0.0;
     if (i < n) {
@@ -1051,10 +1050,10 @@ __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv
     }
     if (DOT) {
         int32_t lo, bound;
-        block_instances(m, lo, bound);
+        block_instances(m, lo, bound, B);
         double* const parts[2] = {part_rz, part_rzold};
         const double vals[2] = {rz, rzo};
-        store_pairs<2>(parts, vals, i >= bound, bound, sh);
+        store_pairs<2>(parts, vals, i >= bound, bound, sh, B);
     }
 }
 
@@ -1161,7 +1160,8 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_residual(SellView<dou
                                                        double* __restrict__ mx_out, const int32_t* __restrict__ when_done) {
     __shared__ double sh[kPairSh];
     if (when_done && !*when_done) return;  // queued ahead of the host's decision: only once every instance is done
-    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t B = row_block();
+    const int32_t row = (int32_t)(B * blockDim.x + threadIdx.x);
     double rr = 0.0, bb = 0.0;
     if (row < M.n_slices * 64) {
         const double mx = sell_row(M, row, x);
@@ -1175,10 +1175,10 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_residual(SellView<dou
         }
     }
     int32_t lo, bound;
-    block_instances(m, lo, bound);
+    block_instances(m, lo, bound, B);
     double* const parts[2] = {part_rr, part_bb};
     const double vals[2] = {rr, bb};
-    store_pairs<2>(parts, vals, row >= bound, bound, sh);
+    store_pairs<2>(parts, vals, row >= bound, bound, sh, B);
 }
 
 // r = rhs - mx with mx = M x stored by the residual check that ended the
@@ -1199,10 +1199,10 @@ __global__ __launch_bounds__(256) void k_pcg_residual_mx(InstMap m, const double
         bb = bi * bi;
     }
     int32_t lo, bound;
-    block_instances(m, lo, bound);
+    block_instances(m, lo, bound, blockIdx.x);
     double* const parts[2] = {part_rr, part_bb};
     const double vals[2] = {rr, bb};
-    store_pairs<2>(parts, vals, row >= bound, bound, sh);
+    store_pairs<2>(parts, vals, row >= bound, bound, sh, blockIdx.x);
 }
 
 // q = M z + beta q, p = z + beta p (so q = M p without a second pass); pair partials of p.q.
@@ -1212,9 +1212,10 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_spmv(SellView<double>
                                                    const int32_t* __restrict__ stop) {
     __shared__ double sh[kPairSh];
     if (*stop) return;
+    const int64_t B = row_block();
     int32_t lo, bound;
-    block_instances(m, lo, bound);
-    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    block_instances(m, lo, bound, B);
+    const int32_t row = (int32_t)(B * blockDim.x + threadIdx.x);
     const bool second = row >= bound;
     const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
     double pq = 0.0;
@@ -1236,7 +1237,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_spmv(SellView<double>
     }
     double* const parts[1] = {part_pq};
     const double vals[1] = {pq};
-    store_pairs<1>(parts, vals, second, bound, sh);
+    store_pairs<1>(parts, vals, second, bound, sh, B);
 }
 
 // x += alpha p, r -= alpha q; pair partials of |r|^2.
@@ -1248,7 +1249,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(InstMap m, double* __restric
     __shared__ double sh[kPairSh];
     if (*stop) return;
     int32_t lo, bound;
-    block_instances(m, lo, bound);
+    block_instances(m, lo, bound, blockIdx.x);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool second = i >= bound;
     const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
@@ -1261,13 +1262,13 @@ __global__ __launch_bounds__(256) void k_pcg_update(InstMap m, double* __restric
     }
     double* const parts[1] = {part_rr};
     const double vals[1] = {rr};
-    store_pairs<1>(parts, vals, second, bound, sh);
+    store_pairs<1>(parts, vals, second, bound, sh, blockIdx.x);
 }
 
 // x = 0 on the rows of instances whose right-hand side is zero.
 __global__ void k_zero_rhs_rows(InstMap m, double* __restrict__ x, int64_t n, const PcgScalars* __restrict__ scal) {
     int32_t lo, bound;
-    block_instances(m, lo, bound);
+    block_instances(m, lo, bound, blockIdx.x);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && scal[min(i >= bound ? lo + 1 : lo, m.n_inst - 1)].bb == 0.0) x[i] = 0.0;
 }
