@@ -11,7 +11,7 @@ coating with field-dependent conductivity inside a polymer insulator) on cube
 meshes, because the paper's insulator model is not available.
 """
 
-from .mesh import kuhn_cube_mesh, permute_nodes, shuffle_tets
+from .mesh import kuhn_cube_mesh, kuhn_cube_mesh_p2, permute_nodes, shuffle_tets
 from .cases import (
     Case,
     make_case,
@@ -20,6 +20,8 @@ from .cases import (
     case_c1,
     case_c2,
     case_batch,
+    case_p2,
+    case_c0_p2,
     random_state,
     mlp_init,
     CASE_NAMES,
@@ -28,6 +30,9 @@ from .cases import (
 __all__ = [
     "Case",
     "kuhn_cube_mesh",
+    "kuhn_cube_mesh_p2",
+    "case_p2",
+    "case_c0_p2",
     "permute_nodes",
     "shuffle_tets",
     "make_case",

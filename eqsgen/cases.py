@@ -32,9 +32,9 @@ from typing import List, Optional
 
 import numpy as np
 
-from .mesh import kuhn_cube_mesh
+from .mesh import kuhn_cube_mesh, kuhn_cube_mesh_p2
 
-CASE_NAMES = ("c0", "c1", "c2", "c3", "c4")
+CASE_NAMES = ("c0", "c1", "c2", "c3", "c4", "p2")
 
 HOST = dict(eps_r=4.0, kappa0=1e-12, e_s=1.0, alpha=0.0, nonlinear=0)
 VARISTOR_KAPPA0 = 1e-10
@@ -84,7 +84,7 @@ class Case:
 
 
 def _centroids(xyz, tets):
-    return xyz[tets].mean(axis=1)
+    return xyz[tets[:, :4]].mean(axis=1)  # the vertices (10-node tets list them first)
 
 
 def _dirichlet_top_bottom(xyz, amp=1.0, freq=50.0, phase=0.0):
@@ -161,8 +161,8 @@ def case_c0(n: int = 8) -> Case:
                 s=8, steps=200, tau=1e-4, rtol=1e-10, precision="fp64")
 
 
-def _inclusion_case(name, n, seed, eps_range, alpha_range, amp=1.0, freq=50.0) -> Case:
-    xyz, tets = kuhn_cube_mesh(n)
+def _inclusion_case(name, n, seed, eps_range, alpha_range, amp=1.0, freq=50.0, order=1) -> Case:
+    xyz, tets = kuhn_cube_mesh(n) if order == 1 else kuhn_cube_mesh_p2(n)
     spheres = draw_spheres(seed, eps_range, alpha_range)
     tet_mat = _assign_spheres(_centroids(xyz, tets), spheres)
     rows = [HOST] + [
@@ -185,6 +185,26 @@ def case_c1(n: int = 64, seed: int = 1) -> Case:
 def case_c2(n: int = 128, seed: int = 1) -> Case:
     c = _inclusion_case("c2", n, seed, (8.0, 15.0), (8.0, 14.0))
     c.s, c.steps, c.tau, c.rtol, c.precision = 16, 200, 1e-4, 1e-8, "fp32"
+    return c
+
+
+def case_p2(n: int = 64, seed: int = 1) -> Case:
+    """Second-order (10-node) tets on the n^3 Kuhn mesh: (2n+1)^3 nodes, the
+    inclusion layout of c1/c2 (same seed), RKC s = 16, FP32 AMG under FP64 CG,
+    rel-res 1e-8. n = 64 has the 2.1M free DOF of c2; n = 128 the 17M of the
+    paper's second-order model."""
+    c = _inclusion_case("p2", n, seed, (8.0, 15.0), (8.0, 14.0), order=2)
+    c.s, c.steps, c.tau, c.rtol, c.precision = 16, 200, 1e-4, 1e-8, "fp32"
+    return c
+
+
+def case_c0_p2(n: int = 8) -> Case:
+    """The c0 slab problem on second-order (10-node) tets."""
+    c = case_c0(n)
+    xyz, tets = kuhn_cube_mesh_p2(n)
+    c.xyz, c.tets = xyz, tets
+    c.dir_nodes, c.dir_drive, c.amp, c.freq, c.phase = _dirichlet_top_bottom(xyz)
+    c.name = "c0p2"
     return c
 
 
@@ -230,6 +250,8 @@ def make_case(name: str, n: Optional[int] = None, seed: Optional[int] = None):
         return c
     if name == "c3":
         return case_batch()
+    if name == "p2":
+        return case_p2(n or 64, 1 if seed is None else seed)
     raise ValueError(f"unknown case {name!r}")
 
 

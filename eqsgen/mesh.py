@@ -9,6 +9,13 @@ has 14 neighbours.
 
 Numbering: node (i, j, k) -> i + (n+1) * (j + (n+1) * k), x fastest; tets are
 ordered by sub-cube (x fastest) and then by the axis ordering below.
+
+Second-order (10-node) tets add the midpoint of every edge. On the Kuhn split
+every point of the half-step lattice is the midpoint of exactly one edge (an
+axis edge, the one diagonal of a face, or the body diagonal of a sub-cube), so
+the nodes are the (2n+1)^3 lattice points with spacing 1/(2n), numbered the
+same way; a tet lists its 4 vertices and then the midpoints of its edges
+(0,1), (0,2), (0,3), (1,2), (1,3), (2,3).
 """
 
 from __future__ import annotations
@@ -90,3 +97,29 @@ def shuffle_tets(tets, tet_mat, seed: int, flip_orientation: bool = True):
             sel = rot == r
             t2[sel] = np.roll(t2[sel], r, axis=1)
     return t2, m2, order
+
+
+P2_EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+
+
+def kuhn_cube_mesh_p2(n: int):
+    """Return (xyz [(2n+1)^3, 3], tets [6 n^3, 10] int32) for the n^3 Kuhn cube
+    mesh with second-order (10-node) tets."""
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    m = 2 * n + 1
+    if m ** 3 >= 2 ** 31:
+        raise ValueError("mesh too large for int32 node ids")
+    g = np.arange(m, dtype=np.float64) / (2 * n)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    xyz = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    c = np.arange(n, dtype=np.int64)
+    ck, cj, ci = np.meshgrid(c, c, c, indexing="ij")
+    corner = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)  # (n^3, 3) lowest corner
+    offs = _kuhn_offsets()  # (6, 4, 3) vertex offsets in sub-cube units
+    # lattice coordinates (spacing 1/(2n)) of the 4 vertices and 6 midpoints
+    pts = [2 * offs[:, a, :] for a in range(4)] + [offs[:, a, :] + offs[:, b, :] for a, b in P2_EDGES]
+    loc = np.stack(pts, axis=1)  # (6, 10, 3)
+    lat = 2 * corner[:, None, None, :] + loc[None, :, :, :]  # (n^3, 6, 10, 3)
+    ids = lat[..., 0] + m * (lat[..., 1] + m * lat[..., 2])
+    return xyz, ids.reshape(-1, 10).astype(np.int32)

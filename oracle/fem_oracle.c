@@ -287,6 +287,207 @@ int orc_element_kappa(const double *xyz, int64_t n_tets, const int32_t *tets, co
     return 0;
 }
 
+/* ---------------------------------------------------- second-order tets */
+
+/* Second-order (10-node) Lagrange tetrahedra, the paper's P2 elements (Sec. III
+ * and Sec. V). Local nodes: 0..3 the vertices, 4..9 the midpoints of the edges
+ * (0,1), (0,2), (0,3), (1,2), (1,3), (2,3). In barycentric coordinates the
+ * basis is N_a = lambda_a (2 lambda_a - 1) at vertex a and N_ab = 4 lambda_a
+ * lambda_b at the midpoint of edge (a,b), with gradients
+ *     grad N_a  = (4 lambda_a - 1) grad(lambda_a),
+ *     grad N_ab = 4 (lambda_b grad(lambda_a) + lambda_a grad(lambda_b)),
+ * linear on a straight-sided element. Element integrals use the symmetric
+ * 4-point rule of degree 2: barycentric points (a, b, b, b) and permutations,
+ * a = (5 + 3 sqrt 5) / 20, b = (5 - sqrt 5) / 20, weight |T| / 4 each. It is
+ * exact for the product of two such gradients, so M is integrated exactly; in
+ * K(x)x the field E = -grad(phi) is linear on the element and kappa(|E|) is
+ * taken at the four points (this project's reading of the quadrature). */
+
+static const int P2_EDGE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+static void p2_point(int q, double lam[4])
+{
+    const double a = (5.0 + 3.0 * sqrt(5.0)) / 20.0, b = (5.0 - sqrt(5.0)) / 20.0;
+    for (int k = 0; k < 4; ++k)
+        lam[k] = (k == q) ? a : b;
+}
+
+/* gradients of the 10 basis functions at barycentric point lam */
+static void p2_gradients(const double g[4][3], const double lam[4], double G[10][3])
+{
+    for (int a = 0; a < 4; ++a)
+        for (int d = 0; d < 3; ++d)
+            G[a][d] = (4.0 * lam[a] - 1.0) * g[a][d];
+    for (int e = 0; e < 6; ++e) {
+        int a = P2_EDGE[e][0], b = P2_EDGE[e][1];
+        for (int d = 0; d < 3; ++d)
+            G[4 + e][d] = 4.0 * (lam[b] * g[a][d] + lam[a] * g[b][d]);
+    }
+}
+
+/* the 4 vertices of 10-node tet e */
+static void load_tet10(const double *xyz, const int32_t *tet, double p[4][3])
+{
+    for (int a = 0; a < 4; ++a)
+        for (int d = 0; d < 3; ++d)
+            p[a][d] = xyz[3 * (int64_t)tet[a] + d];
+}
+
+/* Unit-coefficient P2 element matrix A[i*10+j] = int grad N_i . grad N_j. */
+int orc_p2_element_matrix(const double *p12, double *A100, double *vol_out)
+{
+    double p[4][3], g[4][3], vol;
+    for (int a = 0; a < 4; ++a)
+        for (int d = 0; d < 3; ++d)
+            p[a][d] = p12[3 * a + d];
+    if (tet_gradients(p, g, &vol))
+        return -1;
+    for (int k = 0; k < 100; ++k)
+        A100[k] = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        double lam[4], G[10][3];
+        p2_point(q, lam);
+        p2_gradients(g, lam, G);
+        for (int i = 0; i < 10; ++i)
+            for (int j = 0; j < 10; ++j)
+                A100[10 * i + j] += 0.25 * vol * (G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2]);
+    }
+    if (vol_out)
+        *vol_out = vol;
+    return 0;
+}
+
+/* Full nodal matrix sum_e sum_q w[e*4+q] (|T_e|/4) grad N_i . grad N_j at the
+ * quadrature points (w = eps_e at every point for M, kappa at the point for a
+ * frozen K(x)), CSR with sorted columns; the two-call protocol of
+ * orc_assemble. */
+int64_t orc_p2_assemble(int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tets,
+                        const double *w_q, int64_t nnz_cap, int64_t *rowptr, int32_t *col, double *val)
+{
+    int64_t *start = calloc((size_t)n_nodes + 1, sizeof(int64_t));
+    if (!start)
+        return -2;
+    for (int64_t e = 0; e < n_tets; ++e)
+        for (int a = 0; a < 10; ++a)
+            start[tets[10 * e + a] + 1] += 10;
+    for (int64_t i = 0; i < n_nodes; ++i)
+        start[i + 1] += start[i];
+    entry_t *ent = malloc((size_t)start[n_nodes] * sizeof(entry_t));
+    int64_t *fill = malloc((size_t)n_nodes * sizeof(int64_t));
+    if (!ent || !fill) {
+        free(start); free(ent); free(fill);
+        return -2;
+    }
+    memcpy(fill, start, (size_t)n_nodes * sizeof(int64_t));
+    for (int64_t e = 0; e < n_tets; ++e) {
+        const int32_t *v = tets + 10 * e;
+        double p[4][3], g[4][3], vol, A[10][10];
+        load_tet10(xyz, v, p);
+        if (tet_gradients(p, g, &vol)) {
+            free(start); free(ent); free(fill);
+            return -1;
+        }
+        for (int i = 0; i < 10; ++i)
+            for (int j = 0; j < 10; ++j)
+                A[i][j] = 0.0;
+        for (int q = 0; q < 4; ++q) {
+            double lam[4], G[10][3];
+            p2_point(q, lam);
+            p2_gradients(g, lam, G);
+            double wq = w_q[4 * e + q] * 0.25 * vol;
+            for (int i = 0; i < 10; ++i)
+                for (int j = 0; j < 10; ++j)
+                    A[i][j] += wq * (G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2]);
+        }
+        for (int i = 0; i < 10; ++i)
+            for (int j = 0; j < 10; ++j) {
+                entry_t *en = &ent[fill[v[i]]++];
+                en->col = v[j];
+                en->val = A[i][j];
+            }
+    }
+    int fill_mode = nnz_cap > 0;
+    int64_t nnz = 0;
+    int overflow = 0;
+    if (fill_mode)
+        rowptr[0] = 0;
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        int64_t lo = start[i], hi = start[i + 1];
+        qsort(ent + lo, (size_t)(hi - lo), sizeof(entry_t), cmp_entry);
+        for (int64_t k = lo; k < hi; ++k) {
+            int same = (k > lo && ent[k].col == ent[k - 1].col);
+            if (!same)
+                ++nnz;
+            if (!fill_mode)
+                continue;
+            if (nnz > nnz_cap) {
+                overflow = 1;
+                continue;
+            }
+            if (same) {
+                val[nnz - 1] += ent[k].val;
+            } else {
+                col[nnz - 1] = ent[k].col;
+                val[nnz - 1] = ent[k].val;
+            }
+        }
+        if (fill_mode)
+            rowptr[i + 1] = nnz;
+    }
+    free(start); free(ent); free(fill);
+    return overflow ? -3 : nnz;
+}
+
+/* y = K(x)x on 10-node tets: per element and quadrature point the field
+ * E_q = -sum_j x_j grad N_j(q), kappa_q = kappa(|E_q|), and
+ * y_i += (|T|/4) kappa_q grad N_i(q) . (-E_q). kappa_q (n_tets x 4, may be
+ * NULL) receives the point conductivities; max_rate (may be NULL) the largest
+ * sigma/eps over all points (sigma the differential conductivity). */
+int orc_p2_apply_K(int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tets,
+                   const int32_t *tet_mat, const double *mat_eps_r, const double *mat_kappa0,
+                   const double *mat_e_s, const double *mat_alpha, const int32_t *mat_nonlinear,
+                   const double *x, double *y, double *kappa_q, double *max_rate)
+{
+    if (y)
+        for (int64_t i = 0; i < n_nodes; ++i)
+            y[i] = 0.0;
+    double rate = 0.0;
+    for (int64_t e = 0; e < n_tets; ++e) {
+        const int32_t *v = tets + 10 * e;
+        double p[4][3], g[4][3], vol;
+        load_tet10(xyz, v, p);
+        if (tet_gradients(p, g, &vol))
+            return -1;
+        int m = tet_mat[e];
+        for (int q = 0; q < 4; ++q) {
+            double lam[4], G[10][3];
+            p2_point(q, lam);
+            p2_gradients(g, lam, G);
+            double gphi[3] = {0.0, 0.0, 0.0}; /* grad(phi) = -E at the point */
+            for (int j = 0; j < 10; ++j)
+                for (int d = 0; d < 3; ++d)
+                    gphi[d] += x[v[j]] * G[j][d];
+            double emag = sqrt(gphi[0] * gphi[0] + gphi[1] * gphi[1] + gphi[2] * gphi[2]);
+            double kap = conductivity(emag, mat_kappa0[m], mat_e_s[m], mat_alpha[m], mat_nonlinear[m]);
+            if (kappa_q)
+                kappa_q[4 * e + q] = kap;
+            if (max_rate) {
+                double sig = differential_conductivity(emag, mat_kappa0[m], mat_e_s[m], mat_alpha[m],
+                                                       mat_nonlinear[m]);
+                double r = sig / (ORC_EPS0 * mat_eps_r[m]);
+                if (r > rate)
+                    rate = r;
+            }
+            if (y)
+                for (int i = 0; i < 10; ++i)
+                    y[v[i]] += 0.25 * vol * kap * (G[i][0] * gphi[0] + G[i][1] * gphi[1] + G[i][2] * gphi[2]);
+        }
+    }
+    if (max_rate)
+        *max_rate = rate;
+    return 0;
+}
+
 /* ------------------------------------------------------------- CSR algebra */
 
 /* The CSR products, dot products and vector updates below run their loops
