@@ -360,6 +360,35 @@ def run_adaptive(case, precision, t_end, tol):
             "solve_ratio_fixed_over_adaptive": round(fixed_stages / max(1, st["stages"]), 2)}
 
 
+def run_p2(n, steps, warmup, prof_steps=1):
+    """The second-order workload: 10-node tets on the n^3 Kuhn mesh (n = 64:
+    2.1M free DOF), the c2 inclusion layout, RKC(16), FP32 AMG under FP64 CG,
+    rel-res 1e-8; stages/s and the element pass against its bytes."""
+    import eqsgen
+    from paper_1612_09447_amd import EQS_PREC_FP32
+
+    case = eqsgen.case_p2(n)
+    r = run_gpu(case, EQS_PREC_FP32, steps, warmup, case.rtol, prof_steps=prof_steps)
+    info = r["info"]
+    out = {"workload": f"second-order (10-node) tets on {n}^3 cubes: {case.n_tets} tets, {info['n_free']} free DOF, "
+                       f"nnz(M) {info['nnz_M']}, RKC s={case.s}, CG rel-res {case.rtol:g}, FP32 AMG",
+           "steps": steps, "stages_per_s": round(r["stages"] / r["elapsed"], 2),
+           "mean_cg_iters_per_stage": round(sum(r["iters"]) / len(r["iters"]), 2), "amg_levels": info["level_rows"]}
+    if r["prof"]:
+        el = r["prof"]["element"]
+        # per tet its ten node ids (40 B) and material (4 B); per node 24 B
+        # coordinates, 8 B potential, 8 B result
+        nbytes = info["n_tets"] * 44 + info["n_nodes"] * 40
+        a = nbytes / (el["avg_ms"] * 1e-3) / 1e9
+        out["element_pass"] = {"avg_launch_us": round(el["avg_ms"] * 1e3, 2), "bytes_per_launch": nbytes,
+                               "achieved_GBs": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4)}
+        sp = r["prof"]["spmv_M"]
+        sbytes = spmv_bytes(info, info["nnz_M"])
+        out["spmv_M"] = {"avg_launch_us": round(sp["avg_ms"] * 1e3, 2), "bytes_per_launch": sbytes,
+                         "frac": round(sbytes / (sp["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def run_batched(steps, warmup):
     """The batched workload: 64 independent instances (n in {16..48}^3) packed
     into one context, RKC(8) steps of all of them together."""
@@ -437,6 +466,8 @@ def main():
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     ap.add_argument("--c3-steps", type=int, default=5, help="also time the 64-instance batched workload (0: skip)")
     ap.add_argument("--mlp-batch", type=int, default=128, help="network training pairs per stage (<= 256)")
+    ap.add_argument("--p2-steps", type=int, default=5, help="also time the second-order workload (0: skip)")
+    ap.add_argument("--p2-n", type=int, default=64, help="cubes per edge of the second-order workload")
     ap.add_argument("--adaptive-ms", type=float, default=20.0,
                     help="also run error-controlled RKC (local error 1e-2) over this many ms (0: skip)")
     ap.add_argument("--full-runs", default="mlp,galerkin",
@@ -536,6 +567,7 @@ def main():
 
     batched = run_batched(args.c3_steps, 1) if args.c3_steps > 0 else None
     adaptive = run_adaptive(case, main_prec, args.adaptive_ms * 1e-3, 1e-2) if args.adaptive_ms > 0 else None
+    p2 = run_p2(args.p2_n, args.p2_steps, 1) if args.p2_steps > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -581,6 +613,7 @@ def main():
         "mixed_learned_vs_fp64": mixed_learned_vs_fp64(plain, r["learned"], full),
         "batched": batched,
         "adaptive": adaptive,
+        "second_order": p2,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -147,6 +147,15 @@ int eqs_destroy(eqs_ctx *ctx);
  * EQS_ERR_INVALID_ARG. Resets materials, Dirichlet data and the preconditioner. */
 int eqs_set_mesh(eqs_ctx *ctx, int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tets);
 
+/* The same with second-order (10-node) tetrahedra (Sec. III's P2 elements;
+ * Sec. V's second-order model): tets is n_tets x 10, the four vertices, then
+ * the midpoints of the edges (0,1), (0,2), (0,3), (1,2), (1,3), (2,3). Elements
+ * are straight-sided: only the vertex coordinates enter the geometry. M is
+ * integrated exactly (4-point rule of degree 2) and K(x)x takes kappa(|E|) at
+ * those four points, where the field is linear on the element.
+ * eqs_rkc_adaptive and batches are built for 4-node tets only. */
+int eqs_set_mesh_p2(eqs_ctx *ctx, int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tets);
+
 /* Material table (n_mat entries) and the material id of every tet
  * (tet_mat[n_tets], 0 <= id < n_mat <= 65535): the "nonlinear material
  * parameters" of Sec. III. Invalidates the preconditioner. */

@@ -109,6 +109,7 @@ _SIGNATURES = {
     "eqs_create": ([C.POINTER(_P), C.c_int, _P], C.c_int),
     "eqs_destroy": ([_P], C.c_int),
     "eqs_set_mesh": ([_P, C.c_int64, _P, C.c_int64, _P], C.c_int),
+    "eqs_set_mesh_p2": ([_P, C.c_int64, _P, C.c_int64, _P], C.c_int),
     "eqs_set_materials": ([_P, C.c_int32, _P, _P], C.c_int),
     "eqs_set_dirichlet": ([_P, C.c_int64, _P, _P, C.c_int32, _P], C.c_int),
     "eqs_build_preconditioner": ([_P, _P], C.c_int),
@@ -248,9 +249,14 @@ class Context:
 
     # ---- set-up ----------------------------------------------------------
     def set_mesh(self, xyz, tets):
+        """4-node tets (n_tets x 4) or second-order 10-node tets (n_tets x 10)."""
         xyz, pxyz = _host(xyz, np.float64)
         tets, ptets = _host(tets, np.int32)
-        _check(lib().eqs_set_mesh(self._h, xyz.shape[0], pxyz, tets.shape[0], ptets), "eqs_set_mesh")
+        if tets.ndim != 2 or tets.shape[1] not in (4, 10):
+            raise ValueError("tets must be n_tets x 4 or n_tets x 10")
+        fn, name = (lib().eqs_set_mesh_p2, "eqs_set_mesh_p2") if tets.shape[1] == 10 else (lib().eqs_set_mesh,
+                                                                                           "eqs_set_mesh")
+        _check(fn(self._h, xyz.shape[0], pxyz, tets.shape[0], ptets), name)
 
     def set_materials(self, eps_r, kappa0, e_s, alpha, nonlinear, tet_mat):
         n = len(eps_r)

@@ -130,20 +130,21 @@ int eqs_destroy(eqs_ctx* ctx) {
     });
 }
 
-int eqs_set_mesh(eqs_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets) {
+static int set_mesh(eqs_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets, int npe) {
     return guarded([&] {
         need(c != nullptr, "ctx is NULL");
         need(n_nodes >= 4 && n_nodes < INT32_MAX, "n_nodes must be in [4, 2^31)");
         need(n_tets >= 1 && n_tets < INT32_MAX, "n_tets must be in [1, 2^31)");
         need(xyz != nullptr && tets != nullptr, "xyz or tets is NULL");
+        for (int64_t k = 0; k < npe * n_tets; ++k)
+            need(tets[k] >= 0 && tets[k] < n_nodes, "tet node id out of range");
         bind_device(c);
         eqs::free_device(c);
         c->n_nodes = n_nodes;
         c->n_tets = n_tets;
+        c->npe = npe;
         c->xyz.assign(xyz, xyz + 3 * n_nodes);
-        c->tets.assign(tets, tets + 4 * n_tets);
-        for (int64_t k = 0; k < 4 * n_tets; ++k)
-            need(tets[k] >= 0 && tets[k] < n_nodes, "tet node id out of range");
+        c->tets.assign(tets, tets + npe * n_tets);
         c->have_mesh = true;
         c->inst_node_off.clear();
         c->inst_tet_off.clear();
@@ -155,6 +156,14 @@ int eqs_set_mesh(eqs_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets,
         c->drives.clear();
         return EQS_OK;
     });
+}
+
+int eqs_set_mesh(eqs_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets) {
+    return set_mesh(c, n_nodes, xyz, n_tets, tets, 4);
+}
+
+int eqs_set_mesh_p2(eqs_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets) {
+    return set_mesh(c, n_nodes, xyz, n_tets, tets, 10);
 }
 
 int eqs_set_materials(eqs_ctx* c, int32_t n_mat, const eqs_material* mats, const int32_t* tet_mat) {
@@ -403,6 +412,7 @@ int eqs_rkc_adaptive(eqs_ctx* c, double t0, double t_end, double* x_dev, double 
         need(cap >= 0 && (cap == 0 || rec != nullptr), "rec must hold cap records");
         need_built(c);
         if (c->n_inst != 1) fail(EQS_ERR_STATE, "adaptive stepping needs a single instance");
+        if (c->npe != 4) fail(EQS_ERR_STATE, "adaptive stepping is built for first-order tets");
         if (c->guess.p.kind != EQS_GUESS_PREVIOUS && c->guess.p.kind != EQS_GUESS_ZERO)
             fail(EQS_ERR_STATE, "adaptive stepping runs with the plain or the zero start vector");
         bind_device(c);
@@ -581,8 +591,8 @@ int eqs_describe(const eqs_ctx* c, char* buf, int64_t cap, int64_t* needed) {
         need(c != nullptr, "ctx is NULL");
         std::string d;
         char line[200];
-        std::snprintf(line, sizeof line, "nodes %lld tets %lld free %lld nnz(M) %lld precision %s built %d\n",
-                      (long long)c->n_nodes, (long long)c->n_tets, (long long)c->n_free, (long long)c->nnz_M,
+        std::snprintf(line, sizeof line, "nodes %lld tets %lld (%d nodes each) free %lld nnz(M) %lld precision %s built %d\n",
+                      (long long)c->n_nodes, (long long)c->n_tets, c->npe, (long long)c->n_free, (long long)c->nnz_M,
                       c->amg.precision == EQS_PREC_FP32 ? "fp32" : "fp64", (int)c->built);
         d += line;
         std::snprintf(line, sizeof line,

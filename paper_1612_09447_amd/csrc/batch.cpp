@@ -35,6 +35,10 @@ int eqs_batch_create(eqs_batch** out, int32_t n, eqs_ctx* const* ctxs, int devic
             eqs::set_error("eqs_batch_create: instance " + std::to_string(i) + " lacks mesh, materials or Dirichlet data");
             return EQS_ERR_STATE;
         }
+        if (c->npe != 4) {
+            eqs::set_error("eqs_batch_create: batches hold first-order (4-node) meshes");
+            return EQS_ERR_INVALID_ARG;
+        }
         const int32_t nbase = (int32_t)noff.back();
         const int32_t mbase = (int32_t)mats.size();
         const int32_t dbase = (int32_t)drives.size();

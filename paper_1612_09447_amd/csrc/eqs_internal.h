@@ -32,8 +32,8 @@ namespace eqs {
 constexpr int kSlice = 64;   // SELL slice height = wavefront size
 constexpr int kTetBlock = 256;  // threads per element-pass workgroup
 constexpr int kMaxTetsPerThread = 8;  // element blocks hold kTetBlock * tpt tets, tpt in {1, 2, 4, 8}
-constexpr int kMaxBlockNodes = 1360;
-constexpr int64_t kMaxCoarseR = 4 << 20;  // entries of the fused restriction + coarse solve matrix  // distinct nodes per element block: 48 B of LDS each (<= 64 KiB)
+constexpr int kMaxBlockNodes = 1360;  // distinct nodes per element block: 48 B of LDS each (<= 64 KiB)
+constexpr int64_t kMaxCoarseR = 4 << 20;  // entries of the fused restriction + coarse solve matrix
 constexpr int kBlock = 256;  // threads per block for streaming kernels
 
 // ---------------------------------------------------------------- errors
@@ -233,8 +233,9 @@ struct eqs_ctx {
 
     // inputs (host copies)
     int64_t n_nodes = 0, n_tets = 0;
+    int npe = 4;  // nodes per tet: 4 (P1) or 10 (second order: vertices, then edge midpoints)
     std::vector<double> xyz;
-    std::vector<int32_t> tets;
+    std::vector<int32_t> tets;  // n_tets x npe
     std::vector<eqs_material> mats;
     std::vector<int32_t> tet_mat;
     std::vector<int32_t> dir_nodes, dir_drive;

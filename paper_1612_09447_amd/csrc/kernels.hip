@@ -20,6 +20,7 @@
 #include <hip/hip_ext.h>
 
 #include "eqs_internal.h"
+#include "p2.h"
 #include "sell.h"
 
 namespace eqs {
@@ -500,6 +501,156 @@ __global__ __launch_bounds__(kTetBlock, 6) void k_kx(KxArgs A) {
     kx_scatter<RHS, STRIDE>(A, lds, off, nn);
 }
 
+// ------------------------------------------------ second-order tets (P2)
+// The same block structure with ten nodes per tet (p2.h): each record is two
+// 64-bit words (material, then ten 11-bit block-local ids). Per tet the four
+// vertex coordinates give the cofactors c_a and det; at each of the four
+// quadrature points q the scaled field w_q = sum_a s_a c_a with
+//   s_a = (4 lambda_a - 1) u_a + 4 sum_{b != a} lambda_b u_ab
+// (det times grad phi), |E_q| = |w_q| / |det|, kappa_q = kappa(|E_q|), and with
+// d_a = c_a . (kappa_q w_q) the nodes receive
+//   vertex a: (4 lambda_a - 1) d_a,   edge ab: 4 (lambda_b d_a + lambda_a d_b),
+// summed over q and scaled by +-1 / (24 |det|) (RHS mode: negative, and the
+// Dirichlet term eps A_e g' adds eps times the same field of the drive rates).
+__device__ __forceinline__ int p2_local(uint64_t lo, uint64_t hi, int k) {
+    const int pos = 16 + 11 * k;
+    uint64_t v;
+    if (pos >= 64) v = hi >> (pos - 64);
+    else if (pos + 11 > 64) v = (lo >> pos) | (hi << (64 - pos));
+    else v = lo >> pos;
+    return (int)(v & 0x7ffu);
+}
+
+// s_a of one quadrature point from the ten nodal values v[]
+__device__ __forceinline__ void p2_svals(const double (&v)[kP2Nodes], int q, double (&sv)[4]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) sv[a] = (4.0 * p2_lambda(q, a) - 1.0) * v[a];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int a = p2_edge_a(k), b = p2_edge_b(k);
+        sv[a] += 4.0 * p2_lambda(q, b) * v[4 + k];
+        sv[b] += 4.0 * p2_lambda(q, a) * v[4 + k];
+    }
+}
+
+template <bool RHS, int TPT, int STRIDE>
+__device__ __forceinline__ void kx_p2_tets(const KxArgs& A, double* lds, int32_t nn, bool has_dir,
+                                           const uint64_t (&rec)[2 * TPT]) {
+    const int32_t S = kx_stride<STRIDE>(nn);
+    const double* PX = lds;
+    const double* PY = PX + S;
+    const double* PZ = PY + S;
+    const double* PU = PZ + S;
+    const double* R = PU + S;
+    double* Acc = lds + 5 * S;
+#pragma unroll 1
+    for (int i = 0; i < TPT; ++i) {
+        const uint64_t lo = rec[2 * i], hi = rec[2 * i + 1];
+        if (lo == ~0ull) continue;
+        const MatDev m = A.mats[(uint32_t)(lo & 0xffffu)];
+        int l[kP2Nodes];
+#pragma unroll
+        for (int k = 0; k < kP2Nodes; ++k) l[k] = p2_local(lo, hi, k);
+        double u[kP2Nodes];
+#pragma unroll
+        for (int k = 0; k < kP2Nodes; ++k) u[k] = PU[l[k]];
+        double cf[4][3];
+        {
+            const double x0 = PX[l[0]], y0 = PY[l[0]], z0 = PZ[l[0]];
+            const double e1x = PX[l[1]] - x0, e1y = PY[l[1]] - y0, e1z = PZ[l[1]] - z0;
+            const double e2x = PX[l[2]] - x0, e2y = PY[l[2]] - y0, e2z = PZ[l[2]] - z0;
+            const double e3x = PX[l[3]] - x0, e3y = PY[l[3]] - y0, e3z = PZ[l[3]] - z0;
+            cf[1][0] = e2y * e3z - e2z * e3y; cf[1][1] = e2z * e3x - e2x * e3z; cf[1][2] = e2x * e3y - e2y * e3x;
+            cf[2][0] = e3y * e1z - e3z * e1y; cf[2][1] = e3z * e1x - e3x * e1z; cf[2][2] = e3x * e1y - e3y * e1x;
+            cf[3][0] = e1y * e2z - e1z * e2y; cf[3][1] = e1z * e2x - e1x * e2z; cf[3][2] = e1x * e2y - e1y * e2x;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cf[0][d] = -(cf[1][d] + cf[2][d] + cf[3][d]);
+        }
+        const double det = (PX[l[1]] - PX[l[0]]) * cf[1][0] + (PY[l[1]] - PY[l[0]]) * cf[1][1] +
+                           (PZ[l[1]] - PZ[l[0]]) * cf[1][2];
+        const double inv = 1.0 / fabs(det);
+        double rate[kP2Nodes];
+        bool drive = false;
+        if (RHS && has_dir) {
+#pragma unroll
+            for (int k = 0; k < kP2Nodes; ++k) {
+                rate[k] = R[l[k]];
+                drive = drive || rate[k] != 0.0;
+            }
+        }
+        double acc[kP2Nodes];
+#pragma unroll
+        for (int k = 0; k < kP2Nodes; ++k) acc[k] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double sv[4];
+            p2_svals(u, q, sv);
+            double wx = 0.0, wy = 0.0, wz = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                wx += sv[a] * cf[a][0];
+                wy += sv[a] * cf[a][1];
+                wz += sv[a] * cf[a][2];
+            }
+            double ks = m.kappa0;
+            if (m.nonlinear) {
+                const double ratio = sqrt(wx * wx + wy * wy + wz * wz) * inv * m.inv_es;
+                const double pw = (m.ialpha >= 0) ? ipow(ratio, m.ialpha) : exp(m.alpha * log(ratio));
+                ks *= 1.0 + pw;
+            }
+            wx *= ks;
+            wy *= ks;
+            wz *= ks;
+            if (RHS && has_dir && drive) {
+                double sr[4];
+                p2_svals(rate, q, sr);
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    wx += m.eps * sr[a] * cf[a][0];
+                    wy += m.eps * sr[a] * cf[a][1];
+                    wz += m.eps * sr[a] * cf[a][2];
+                }
+            }
+            double dd[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) dd[a] = cf[a][0] * wx + cf[a][1] * wy + cf[a][2] * wz;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a] += (4.0 * p2_lambda(q, a) - 1.0) * dd[a];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int a = p2_edge_a(k), b = p2_edge_b(k);
+                acc[4 + k] += 4.0 * (p2_lambda(q, b) * dd[a] + p2_lambda(q, a) * dd[b]);
+            }
+        }
+        const double sc = (RHS ? -1.0 / 24.0 : 1.0 / 24.0) * inv;
+#pragma unroll
+        for (int k = 0; k < kP2Nodes; ++k) unsafeAtomicAdd(&Acc[l[k]], sc * acc[k]);
+    }
+}
+
+template <bool RHS, int TPT, int STRIDE>
+__global__ __launch_bounds__(kTetBlock) void k_kx_p2(KxArgs A) {
+    extern __shared__ double lds[];
+    const int64_t b = xcd_block(blockIdx.x, A.n_blocks);
+    uint64_t rec[2 * TPT];
+    {
+        const uint64_t* rp = A.tpack + 2 * (b * (kTetBlock * TPT) + (int64_t)threadIdx.x * TPT);
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+            const ulonglong2 v = reinterpret_cast<const ulonglong2*>(rp)[q];
+            rec[2 * q] = v.x;
+            rec[2 * q + 1] = v.y;
+        }
+    }
+    const int32_t off = A.boff[b];
+    const int32_t nn = A.boff[b + 1] - off;
+    const bool has_dir = kx_stage<RHS, STRIDE>(A, lds, off, nn);
+    __syncthreads();
+    kx_p2_tets<RHS, TPT, STRIDE>(A, lds, nn, has_dir, rec);
+    __syncthreads();
+    kx_scatter<RHS, STRIDE>(A, lds, off, nn);
+}
+
 // Spectral bound of one element block for the adaptive stage choice: the
 // largest sigma_e / eps_e over the block's tets, with sigma = kappa0 (1 +
 // (alpha + 1)(|E|/e_s)^alpha) the differential conductivity at the element's
@@ -565,12 +716,29 @@ __global__ __launch_bounds__(kTetBlock, 6) void k_kx_rate(KxArgs A) {
 // the block's own node count as stride.
 constexpr int kx_fixed_stride(int tpt) { return tpt == 1 ? 129 : tpt == 2 ? 193 : tpt == 4 ? 385 : 705; }
 
+// fixed LDS strides of second-order blocks (256 and 512 tets)
+constexpr int kx_p2_fixed_stride(int tpt) { return tpt == 1 ? 705 : 1217; }
+
 template <bool RHS>
 static void launch_kx_t(hipStream_t s, eqs_ctx* c, const double* yfree, double t, double* out) {
     const KxArgs A{c->n_tets, c->n_blocks, c->d_tpack, c->d_boff, c->d_bnodes, c->d_cx, c->d_cy, c->d_cz, c->d_mats,
                    yfree, (int32_t)c->n_free, c->d_ddrive, c->d_drives, t, out};
     const dim3 b(kTetBlock), g((unsigned)c->n_blocks);
     const int tpt = c->tet_tpt;
+    if (c->npe == kP2Nodes) {
+        const bool fixed2 = (tpt == 1 || tpt == 2) && c->max_block_nodes <= kx_p2_fixed_stride(tpt) && !c->kx_generic;
+        const size_t lds2 = sizeof(double) * 6 * (size_t)(fixed2 ? kx_p2_fixed_stride(tpt) : c->max_block_nodes);
+        if (tpt == 1) {
+            if (fixed2) EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx_p2<RHS, 1, kx_p2_fixed_stride(1)>), g, b, lds2, s, A);
+            else EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx_p2<RHS, 1, 0>), g, b, lds2, s, A);
+        } else if (tpt == 2) {
+            if (fixed2) EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx_p2<RHS, 2, kx_p2_fixed_stride(2)>), g, b, lds2, s, A);
+            else EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx_p2<RHS, 2, 0>), g, b, lds2, s, A);
+        } else {
+            fail(EQS_ERR_STATE, "second-order element blocks hold 256 or 512 tets");
+        }
+        return;
+    }
     const bool fixed = tpt >= 1 && c->max_block_nodes <= kx_fixed_stride(tpt) && !c->kx_generic;
     const size_t lds = sizeof(double) * 6 * (size_t)(fixed ? kx_fixed_stride(tpt) : c->max_block_nodes);
 #define EQS_KX(TPT_)                                                                                           \
@@ -589,6 +757,7 @@ static void launch_kx_t(hipStream_t s, eqs_ctx* c, const double* yfree, double t
 }
 
 double max_rate(eqs_ctx* c, const double* yfree, double t) {
+    if (c->npe != 4) fail(EQS_ERR_STATE, "the spectral bound is built for first-order tets");
     hipStream_t s = c->stream;
     double* slot = c->d_partials;  // free between CG solves
     launch_fill(s, slot, 0.0, 1);

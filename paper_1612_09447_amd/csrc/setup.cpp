@@ -14,6 +14,7 @@
 #include <iterator>
 
 #include "eqs_internal.h"
+#include "p2.h"
 
 namespace eqs {
 
@@ -48,9 +49,10 @@ void validate_and_order(eqs_ctx* c) {
     const int64_t N = c->n_nodes;
     for (int64_t i = 0; i < 3 * N; ++i)
         if (!std::isfinite(c->xyz[i])) fail(EQS_ERR_NONFINITE, "non-finite node coordinate");
+    const int npe = c->npe;
     for (int64_t e = 0; e < c->n_tets; ++e) {
-        const int32_t* v = &c->tets[4 * e];
-        for (int a = 0; a < 4; ++a)
+        const int32_t* v = &c->tets[npe * e];
+        for (int a = 0; a < npe; ++a)
             if (v[a] < 0 || v[a] >= N) fail(EQS_ERR_INVALID_ARG, "tet " + std::to_string(e) + " has a node id out of range");
         double cf[4][3];
         double det = tet_cofactors(&c->xyz[3 * (int64_t)v[0]], &c->xyz[3 * (int64_t)v[1]], &c->xyz[3 * (int64_t)v[2]],
@@ -87,8 +89,8 @@ void validate_and_order(eqs_ctx* c) {
     }
     for (int64_t i = 0; i < c->n_inst; ++i)
         for (int64_t e = c->inst_tet_off[i]; e < c->inst_tet_off[i + 1]; ++e)
-            for (int a = 0; a < 4; ++a) {
-                const int32_t v = c->tets[4 * e + a];
+            for (int a = 0; a < npe; ++a) {
+                const int32_t v = c->tets[npe * e + a];
                 if (v < c->inst_node_off[i] || v >= c->inst_node_off[i + 1])
                     fail(EQS_ERR_INVALID_ARG, "tet " + std::to_string(e) + " uses a node of another instance");
             }
@@ -129,15 +131,16 @@ Csr<double> assemble_M_free(const eqs_ctx* c) {
     std::vector<int32_t> u2i(N);
     for (int64_t i = 0; i < N; ++i) u2i[c->int_to_user[i]] = (int32_t)i;
 
+    const int npe = c->npe;
     // node -> incident tets
     std::vector<int64_t> nt_ptr(N + 1, 0);
-    for (int64_t e = 0; e < 4 * T; ++e) nt_ptr[u2i[c->tets[e]] + 1]++;
+    for (int64_t e = 0; e < npe * T; ++e) nt_ptr[u2i[c->tets[e]] + 1]++;
     for (int64_t i = 0; i < N; ++i) nt_ptr[i + 1] += nt_ptr[i];
     std::vector<int32_t> nt(nt_ptr[N]);
     {
         std::vector<int64_t> fill(nt_ptr.begin(), nt_ptr.end() - 1);
         for (int64_t e = 0; e < T; ++e)
-            for (int a = 0; a < 4; ++a) nt[fill[u2i[c->tets[4 * e + a]]]++] = (int32_t)e;
+            for (int a = 0; a < npe; ++a) nt[fill[u2i[c->tets[npe * e + a]]]++] = (int32_t)e;
     }
 
     // row patterns: free neighbours through incident tets
@@ -150,8 +153,8 @@ Csr<double> assemble_M_free(const eqs_ctx* c) {
         for (int64_t i = 0; i < NF; ++i) {
             buf.clear();
             for (int64_t k = nt_ptr[i]; k < nt_ptr[i + 1]; ++k) {
-                const int32_t* v = &c->tets[4 * (int64_t)nt[k]];
-                for (int a = 0; a < 4; ++a) {
+                const int32_t* v = &c->tets[npe * (int64_t)nt[k]];
+                for (int a = 0; a < npe; ++a) {
                     int32_t j = u2i[v[a]];
                     if (j < NF) buf.push_back(j);
                 }
@@ -172,23 +175,45 @@ Csr<double> assemble_M_free(const eqs_ctx* c) {
         }
     }
 
-    // values: element matrices eps_e |T| g_a . g_b = eps_e c_a . c_b / (6 |det|)
+    // values: P1 element matrices eps_e |T| g_a . g_b = eps_e c_a . c_b / (6 |det|);
+    // second order: eps_e sum_q G_a(q) . G_b(q) / (24 |det|) (see p2.h)
+    double A[kP2Nodes][kP2Nodes];
     for (int64_t e = 0; e < T; ++e) {
-        const int32_t* vu = &c->tets[4 * e];
-        int32_t v[4];
-        for (int a = 0; a < 4; ++a) v[a] = u2i[vu[a]];
+        const int32_t* vu = &c->tets[npe * e];
+        int32_t v[kP2Nodes];
+        for (int a = 0; a < npe; ++a) v[a] = u2i[vu[a]];
         double cf[4][3];
         double det = tet_cofactors(&c->xyz[3 * (int64_t)vu[0]], &c->xyz[3 * (int64_t)vu[1]], &c->xyz[3 * (int64_t)vu[2]],
                                    &c->xyz[3 * (int64_t)vu[3]], cf);
-        const double w = kEps0 * c->mats[c->tet_mat[e]].eps_r / (6.0 * std::fabs(det));
-        for (int a = 0; a < 4; ++a) {
+        const double eps = kEps0 * c->mats[c->tet_mat[e]].eps_r;
+        if (npe == 4) {
+            const double w = eps / (6.0 * std::fabs(det));
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) A[a][b] = w * (cf[a][0] * cf[b][0] + cf[a][1] * cf[b][1] + cf[a][2] * cf[b][2]);
+        } else {
+            for (int a = 0; a < kP2Nodes; ++a)
+                for (int b = 0; b < kP2Nodes; ++b) A[a][b] = 0.0;
+            const double w = eps / (24.0 * std::fabs(det));
+            for (int q = 0; q < 4; ++q) {
+                double G[kP2Nodes][3];
+                for (int a = 0; a < 4; ++a)
+                    for (int d = 0; d < 3; ++d) G[a][d] = (4.0 * p2_lambda(q, a) - 1.0) * cf[a][d];
+                for (int k = 0; k < 6; ++k) {
+                    const int a = p2_edge_a(k), b = p2_edge_b(k);
+                    for (int d = 0; d < 3; ++d) G[4 + k][d] = 4.0 * (p2_lambda(q, b) * cf[a][d] + p2_lambda(q, a) * cf[b][d]);
+                }
+                for (int a = 0; a < kP2Nodes; ++a)
+                    for (int b = 0; b < kP2Nodes; ++b) A[a][b] += w * (G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2]);
+            }
+        }
+        for (int a = 0; a < npe; ++a) {
             if (v[a] >= NF) continue;
             const int32_t* cb = &M.col[M.ptr[v[a]]];
             const int32_t* ce = &M.col[M.ptr[v[a] + 1]];
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < npe; ++b) {
                 if (v[b] >= NF) continue;
                 const int32_t* it = std::lower_bound(cb, ce, v[b]);
-                M.val[it - M.col.data()] += w * (cf[a][0] * cf[b][0] + cf[a][1] * cf[b][1] + cf[a][2] * cf[b][2]);
+                M.val[it - M.col.data()] += A[a][b];
             }
         }
     }
@@ -1216,7 +1241,7 @@ static std::vector<int32_t> morton_tet_order(const eqs_ctx* c) {
     for (int64_t e = 0; e < T; ++e) {
         double cen[3] = {0, 0, 0};
         for (int a = 0; a < 4; ++a)
-            for (int d = 0; d < 3; ++d) cen[d] += 0.25 * c->xyz[3 * (int64_t)c->tets[4 * e + a] + d];
+            for (int d = 0; d < 3; ++d) cen[d] += 0.25 * c->xyz[3 * (int64_t)c->tets[(int64_t)c->npe * e + a] + d];
         key[e] = {morton3(cen, lo, inv_ext), (int32_t)e};
     }
     // instance first (blocks then never mix instances, whose meshes may overlap in space)
@@ -1230,12 +1255,16 @@ static std::vector<int32_t> morton_tet_order(const eqs_ctx* c) {
     return order;
 }
 
+// Second-order tets take two 64-bit words per record: 16-bit material, then
+// the ten 11-bit block-local ids at bits 16 + 11 k of the 128-bit pair (low
+// word first).
 static ElementBlocks element_blocks(const eqs_ctx* c, const std::vector<int32_t>& u2i,
                                     const std::vector<int32_t>& order, int tpt) {
     const int64_t T = c->n_tets, per = (int64_t)kTetBlock * tpt;
     const int64_t nb = (T + per - 1) / per;
+    const int npe = c->npe, words = npe == 4 ? 1 : 2;
     ElementBlocks eb;
-    eb.pack.assign((size_t)(nb * per), ~0ull);  // whole blocks; padding records are skipped
+    eb.pack.assign((size_t)(nb * per * words), ~0ull);  // whole blocks; padding records are skipped
     eb.boff.assign(nb + 1, 0);
     eb.bnodes.reserve((size_t)T);
     std::vector<int32_t> ids;
@@ -1243,7 +1272,7 @@ static ElementBlocks element_blocks(const eqs_ctx* c, const std::vector<int32_t>
         const int64_t e0 = b * per, e1 = std::min<int64_t>(T, e0 + per);
         ids.clear();
         for (int64_t k = e0; k < e1; ++k)
-            for (int a = 0; a < 4; ++a) ids.push_back(u2i[c->tets[4 * (int64_t)order[k] + a]]);
+            for (int a = 0; a < npe; ++a) ids.push_back(u2i[c->tets[npe * (int64_t)order[k] + a]]);
         std::sort(ids.begin(), ids.end());
         ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
         if (ids.size() > (size_t)kMaxBlockNodes) {  // local ids / LDS: the caller tries a smaller block
@@ -1253,12 +1282,20 @@ static ElementBlocks element_blocks(const eqs_ctx* c, const std::vector<int32_t>
         eb.max_nodes = std::max<int32_t>(eb.max_nodes, (int32_t)ids.size());
         for (int64_t k = e0; k < e1; ++k) {
             const int32_t e = order[k];
-            uint64_t w = (uint64_t)(uint16_t)c->tet_mat[e];
-            for (int a = 0; a < 4; ++a) {
-                const int32_t loc = (int32_t)(std::lower_bound(ids.begin(), ids.end(), u2i[c->tets[4 * (int64_t)e + a]]) - ids.begin());
-                w |= (uint64_t)loc << (16 + 12 * a);
+            uint64_t w = (uint64_t)(uint16_t)c->tet_mat[e], w2 = 0;
+            for (int a = 0; a < npe; ++a) {
+                const uint64_t loc =
+                    (uint64_t)(std::lower_bound(ids.begin(), ids.end(), u2i[c->tets[npe * (int64_t)e + a]]) - ids.begin());
+                if (npe == 4) {
+                    w |= loc << (16 + 12 * a);
+                } else {
+                    const int pos = 16 + 11 * a;
+                    if (pos < 64) w |= loc << pos;
+                    if (pos + 11 > 64) w2 |= pos >= 64 ? loc << (pos - 64) : loc >> (64 - pos);
+                }
             }
-            eb.pack[k] = w;
+            eb.pack[k * words] = w;
+            if (words == 2) eb.pack[k * words + 1] = w2;
         }
         eb.bnodes.insert(eb.bnodes.end(), ids.begin(), ids.end());
         if (eb.bnodes.size() > (size_t)INT32_MAX) fail(EQS_ERR_INVALID_ARG, "too many block nodes");
@@ -1284,7 +1321,7 @@ static void install_blocks(eqs_ctx* c, const ElementBlocks& eb, int tpt) {
 // the fastest kept (else 4 tets per thread).
 void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const double* yfree, double* out) {
     const std::vector<int32_t> order = morton_tet_order(c);
-    const int fixed = 4;
+    const int fixed = c->npe == 4 ? 4 : 1;
     if (!c->autotune || c->n_tets < 16 * (int64_t)kTetBlock * kMaxTetsPerThread) {
         for (int tpt = fixed; tpt >= 1; tpt /= 2) {
             ElementBlocks eb = element_blocks(c, u2i, order, tpt);
@@ -1300,7 +1337,8 @@ void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const dou
     int best_tpt = 0;
     double best = 1e300;
     std::string line = "element:";
-    for (int tpt = 1; tpt <= kMaxTetsPerThread; tpt *= 2) {
+    const int max_tpt = c->npe == 4 ? kMaxTetsPerThread : 2;  // second order: ~1.3 nodes per tet
+    for (int tpt = 1; tpt <= max_tpt; tpt *= 2) {
         ElementBlocks eb = element_blocks(c, u2i, order, tpt);
         if (eb.max_nodes > kMaxBlockNodes) break;
         install_blocks(c, eb, tpt);
