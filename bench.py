@@ -235,7 +235,7 @@ def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None):
 
 
 def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous", flexible=0, learned_steps=0,
-            learned_warmup=20, mlp_batch=128, keep_states=False):
+            learned_warmup=20, mlp_batch=256, keep_states=False, mlp_warmup=64):
     """Time `steps` RKC steps (uninstrumented), then `prof_steps` more with every
     kernel class timed by HIP events on the context's stream. With
     learned_steps > 0 the same context then switches to the Galerkin and the
@@ -255,7 +255,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
     # PyTorch owns the device memory: the context moves into a torch workspace
     # sized for its largest start-vector setting of this run
     if guess == "mlp" or learned_steps > 0:
-        ctx.set_guess("mlp", init=eqsgen.mlp_init(4), batch=mlp_batch)
+        ctx.set_guess("mlp", init=eqsgen.mlp_init(4), batch=mlp_batch, warmup=mlp_warmup)
     elif guess != "previous":
         ctx.set_guess(guess)
     ws = ctx.use_torch_workspace()
@@ -296,7 +296,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         for kind in ("previous", "zero", "galerkin", "mor", "mlp"):
             x.copy_(x0)
             if kind == "mlp":
-                ctx.set_guess("mlp", init=eqsgen.mlp_init(4), batch=mlp_batch)
+                ctx.set_guess("mlp", init=eqsgen.mlp_init(4), batch=mlp_batch, warmup=mlp_warmup)
             else:
                 ctx.set_guess(kind)
             timed_steps(ctx, x, n, learned_warmup, tau, s, rtol, f"{kind} warm-up")
@@ -465,7 +465,9 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     ap.add_argument("--c3-steps", type=int, default=5, help="also time the 64-instance batched workload (0: skip)")
-    ap.add_argument("--mlp-batch", type=int, default=128, help="network training pairs per stage (<= 256)")
+    ap.add_argument("--mlp-batch", type=int, default=256, help="network training pairs per stage (<= 256)")
+    ap.add_argument("--mlp-warmup", type=int, default=64,
+                    help="training pairs collected before the network's start vector is used")
     ap.add_argument("--p2-steps", type=int, default=5, help="also time the second-order workload (0: skip)")
     ap.add_argument("--p2-n", type=int, default=64, help="cubes per edge of the second-order workload")
     ap.add_argument("--adaptive-ms", type=float, default=20.0,
@@ -498,7 +500,7 @@ def main():
     log(f"[bench] copy probe: {copy}; read probe: {rd}")
     r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess,
                 flexible=args.flexible, learned_steps=args.learned_steps, mlp_batch=args.mlp_batch,
-                keep_states=True)
+                keep_states=True, mlp_warmup=args.mlp_warmup)
     stages_per_s = r["stages"] / r["elapsed"]
     info = r["info"]
     prof = r["prof"]
@@ -554,7 +556,7 @@ def main():
     full = {}
     for kind in [k for k in args.full_runs.split(",") if k]:
         f = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, guess=kind, mlp_batch=args.mlp_batch,
-                    keep_states=ref_hist is not None)
+                    keep_states=ref_hist is not None, mlp_warmup=args.mlp_warmup)
         full[kind] = {"stages_per_s": round(f["stages"] / f["elapsed"], 2),
                       "mean_cg_iters_per_stage": round(sum(f["iters"]) / len(f["iters"]), 2),
                       "steps": args.steps, "guess_used": f["used"], "guard_fallbacks": f["fallbacks"],

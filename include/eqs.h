@@ -371,9 +371,9 @@ typedef struct eqs_guess_params {
     int32_t kind;      /* EQS_GUESS_* */
     int32_t window;    /* window of stage solutions (and POD basis), 2..16 [16] */
     int32_t capacity;  /* replay-buffer pairs kept for training, <= 100000 [2000] */
-    int32_t warmup;    /* pairs collected before the network's vector is used [256] */
+    int32_t warmup;    /* pairs collected before the network's vector is used (0 = from the first pair) */
     int32_t batch;     /* training pairs drawn per stage, 1..256, in minibatches of up to 64 with one
-                          Adam step each [128] */
+                          Adam step each [256] */
     int32_t bf16;      /* 1: BF16 matmul operands, FP32 accumulation; 0: FP32 [1] */
     int32_t guard;     /* 1: keep the network's correction only where it lowers the error's M-norm [1] */
     int32_t add_threshold; /* GALERKIN, MOR: a stage solution joins the window only if its solve took

@@ -427,7 +427,7 @@ class Context:
         p.kind = GUESS_KINDS[kind] if isinstance(kind, str) else int(kind)
         p.bf16 = 1
         p.guard = 1
-        p.warmup = 256
+        p.warmup = 64
         for k, v in kw.items():
             setattr(p, k, v)
         keep = None

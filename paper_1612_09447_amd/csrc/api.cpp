@@ -461,7 +461,7 @@ int eqs_set_guess(eqs_ctx* c, const eqs_guess_params* p) {
         need(a.add_threshold >= 0, "add_threshold must be >= 0");
         if (a.window == 0) a.window = 16;
         if (a.capacity == 0) a.capacity = 2000;
-        if (a.batch == 0) a.batch = 128;
+        if (a.batch == 0) a.batch = 256;
         if (a.lr == 0) a.lr = 1e-3;
         need(a.window >= 2 && a.window <= 16, "window must be in [2, 16]");
         need(a.capacity >= 1 && a.capacity <= 100000, "capacity must be in [1, 100000]");
