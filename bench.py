@@ -176,8 +176,8 @@ SINGLE_KERNEL_CLASSES = ("element", "spmv_M", "presmooth0", "postsmooth0", "rest
 MULTI_KERNEL_CLASSES = ("vcycle", "vcoarse", "finalise")
 ALL_CLASSES = SINGLE_KERNEL_CLASSES + MULTI_KERNEL_CLASSES
 KERNEL_NAMES = {"element": "k_kx<true> (element pass)", "spmv_M": "k_pcg_spmv", "presmooth0": "k_presmooth_res (finest)",
-                "postsmooth0": "k_postsmooth (finest)", "restrict0": "k_sell_mv (finest restriction R0)",
-                "prolong0": "k_sell_mv (finest prolongation P0)", "cg_update": "k_pcg_update",
+                "postsmooth0": "k_postsmooth (finest)", "restrict0": "k_restrict (finest level, R0)",
+                "prolong0": "k_prolong (finest level, P0)", "cg_update": "k_pcg_update",
                 "rkc_combine": "k_rkc_first / k_rkc_combine"}
 
 

@@ -95,6 +95,19 @@ int eqs_create(eqs_ctx** out, int device, void* hip_stream) {
         // "sell1", "sell2", "sell4", "sell8" or "csr": every AMG operator below
         // the finest level in that layout; "sell1s" etc. also sort the rows of
         // the operators used only in products (tests compare the layouts)
+        // EQS_UNROLL (4, 8 or 16): with EQS_LAYOUT's SELL layouts, the group
+        // size of every operator below the finest level
+        const char* un = std::getenv("EQS_UNROLL");
+        if (un && un[0]) {
+            const std::string v(un);
+            if (v == "4") c->force_unroll = 4;
+            else if (v == "8") c->force_unroll = 8;
+            else if (v == "16") c->force_unroll = 16;
+            else {
+                delete c;
+                need(false, "EQS_UNROLL must be 4, 8 or 16");
+            }
+        }
         const char* lay = std::getenv("EQS_LAYOUT");
         if (lay && lay[0]) {
             const std::string v(lay);

@@ -64,6 +64,7 @@ template <typename T>
 struct Sell {
     int32_t n_rows = 0, n_cols = 0, n_slices = 0;
     int32_t lanes = 1;          // lanes per row (a slice holds 64 / lanes rows)
+    int32_t unroll = 8;         // entries per lane whose loads are in flight together (4, 8 or 16)
     int64_t stored = 0;         // padded entries
     int32_t* sptr = nullptr;    // [n_slices + 1]
     int32_t* col = nullptr;     // [stored] absolute column ids, or
@@ -315,6 +316,7 @@ struct eqs_ctx {
     bool fold = true;       // fold pre-smoothers into restrictions and the lowest two levels into two products
     int force_layout = -1;      // >= 1: SELL with that many lanes per row, 0: CSR, for every coarse operator
     bool force_sorted = false;  // with force_layout >= 1: sorted rows where allowed
+    int force_unroll = 8;       // with force_layout >= 1: group size of the coarse operators (see Sell::unroll)
     bool tune_verbose = false;  // the tuner log lists every candidate's time
     // test knobs: the element pass with each block's own LDS stride (the path
     // for blocks with more nodes than the fixed stride), and a forced restart

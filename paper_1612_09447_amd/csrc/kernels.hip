@@ -873,16 +873,60 @@ __device__ __forceinline__ void mv_store(T* __restrict__ y, int32_t row, T v, in
     else y[row] = acc ? y[row] + v : v;
 }
 
-// y = A x with the epilogue above (L lanes per row)
-template <int L, typename T>
-__global__ __launch_bounds__(256, kSparseWaves) void k_sell_mv(SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
-                                                  MvInit<T> in, const int32_t* __restrict__ stop) {
-    if (stop && *stop) return;
+// y = A x with the epilogue above (L lanes per row, groups of U entries). The
+// epilogue's own loads are issued before the row sum, so they wait together
+// with the operator's loads instead of after the gathers.
+template <int L, int U, typename T>
+__device__ __forceinline__ void sell_mv(const SellView<T>& A, const T* __restrict__ x, T* __restrict__ y, int acc,
+                                        const MvInit<T>& in) {
     const int64_t g = row_block() * blockDim.x + threadIdx.x;
     if (g >= (int64_t)A.n_slices * 64) return;  // whole wavefronts leave together
     const int32_t row = sell_perm_row<L>(A.perm, g);
-    const T v = sell_row<L>(A, g, row, x);
-    if ((g & (L - 1)) == 0 && row < A.n_rows) mv_store(y, row, v, acc, in);
+    const bool writer = (g & (L - 1)) == 0 && row < A.n_rows;
+    T y0 = T(0), d = T(0), bb = T(0);
+    if (writer) {
+        if (acc == 1) y0 = y[row];
+        else if (acc == 2) {
+            d = in.dinv[row];
+            bb = in.b[row];
+        }
+    }
+    const T v = sell_row<L, U>(A, g, row, x);
+    if (writer) {
+        if (acc == 2) y[row] = in.omega * d * bb + v;
+        else y[row] = acc ? y0 + v : v;
+    }
+}
+
+// The same product under three names, so that traces tell the V-cycle's
+// restrictions (k_restrict) and prolongations (k_prolong) from other SELL
+// products (k_sell_mv). Groups of 16 entries hold their loads in up to 128
+// registers (4 waves per SIMD instead of 8).
+#define EQS_SELL_MV_ARGS \
+    SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc, MvInit<T> in, const int32_t* __restrict__ stop
+template <int L, int U, typename T>
+__global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_sell_mv(EQS_SELL_MV_ARGS) {
+    if (stop && *stop) return;
+    sell_mv<L, U, T>(A, x, y, acc, in);
+}
+template <int L, int U, typename T>
+__global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_restrict(EQS_SELL_MV_ARGS) {
+    if (stop && *stop) return;
+    sell_mv<L, U, T>(A, x, y, acc, in);
+}
+template <int L, int U, typename T>
+__global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_prolong(EQS_SELL_MV_ARGS) {
+    if (stop && *stop) return;
+    sell_mv<L, U, T>(A, x, y, acc, in);
+}
+#undef EQS_SELL_MV_ARGS
+
+enum MvRole { MV_PLAIN = 0, MV_RESTRICT = 1, MV_PROLONG = 2 };
+template <int L, int U, typename T>
+using SellMvKernel = void (*)(SellView<T>, const T*, T*, int, MvInit<T>, const int32_t*);
+template <int L, int U, typename T>
+static SellMvKernel<L, U, T> sell_mv_kernel(int role) {
+    return role == MV_RESTRICT ? k_restrict<L, U, T> : role == MV_PROLONG ? k_prolong<L, U, T> : k_sell_mv<L, U, T>;
 }
 
 __global__ __launch_bounds__(256, kSparseWaves) void k_spmv64(SellView<double> A, const double* __restrict__ x,
@@ -902,15 +946,15 @@ void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double
 //   x = omega D^{-1} b,   res = b - A x = b - (A omega D^{-1}) b,
 // the last product with the stored pre-smoothing values a_ij omega / a_jj,
 // so rows gather b only.
-template <int L, typename T, typename TB>
-__global__ __launch_bounds__(256, kSparseWaves) void k_presmooth_res(SellView<T> As, const T* __restrict__ dinv, T omega,
+template <int L, typename T, typename TB, int U = 8>
+__global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_presmooth_res(SellView<T> As, const T* __restrict__ dinv, T omega,
                                                         const TB* __restrict__ b, T* __restrict__ x,
                                                         T* __restrict__ res, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
     const int64_t g = row_block() * blockDim.x + threadIdx.x;
     if (g >= (int64_t)As.n_slices * 64) return;
     const int32_t row = sell_row_of<L>(g);
-    const T acc = sell_row<L>(As, g, row, b);
+    const T acc = sell_row<L, U>(As, g, row, b);
     if ((g & (L - 1)) == 0 && row < As.n_rows) {
         const T bi = (T)b[row];
         x[row] = omega * dinv[row] * bi;
@@ -922,8 +966,8 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_presmooth_res(SellView<T>
 // output is CG's z (FP64) and the block partials of r.z and r.z_old (the
 // Polak-Ribiere numerator) are produced per instance (pair layout, see
 // InstMap); z_old is read before it is overwritten.
-template <int L, typename T, typename TB, typename TO, bool DOT>
-__global__ __launch_bounds__(256, kSparseWaves) void k_postsmooth(SellView<T> A, const T* __restrict__ dinv, T omega,
+template <int L, typename T, typename TB, typename TO, bool DOT, int U = 8>
+__global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_postsmooth(SellView<T> A, const T* __restrict__ dinv, T omega,
                                                      const TB* __restrict__ b, const T* __restrict__ x,
                                                      TO* __restrict__ out, InstMap m, double* __restrict__ part_rz,
                                                      double* __restrict__ part_rzold,
@@ -936,7 +980,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_postsmooth(SellView<T> A,
     const int32_t row = sell_row_of<L>(g);
     double rz = 0.0, rzo = 0.0;
     if (g < (int64_t)A.n_slices * 64) {
-        const T ax = sell_row<L>(A, g, row, x);
+        const T ax = sell_row<L, U>(A, g, row, x);
         if ((g & (L - 1)) == 0 && row < A.n_rows) {
             const T v = x[row] + omega * dinv[row] * ((T)b[row] - ax);
             if (DOT) {
@@ -1062,6 +1106,14 @@ static unsigned csr_grid(const SpMat<T>& A) {
         default: { constexpr int L_ = 1; CALL; } break;   \
     }
 
+// group sizes of k_sell_mv (entries per lane in flight), nested inside EQS_SELL_LANES_SWITCH
+#define EQS_UNROLL_SWITCH(Uvar, CALL)                     \
+    switch (Uvar) {                                       \
+        case 4: { constexpr int U_ = 4; CALL; } break;    \
+        case 16: { constexpr int U_ = 16; CALL; } break;  \
+        default: { constexpr int U_ = 8; CALL; } break;   \
+    }
+
 #define EQS_LANES_SWITCH(Lvar, CALL) \
     switch (Lvar) {                  \
         case 1: { constexpr int L_ = 1; CALL; } break;   \
@@ -1075,10 +1127,13 @@ static unsigned csr_grid(const SpMat<T>& A) {
 
 template <typename T>
 static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int acc, const int32_t* stop,
-                      MvInit<T> in = MvInit<T>{nullptr, nullptr, T(0)}) {
+                      MvInit<T> in = MvInit<T>{nullptr, nullptr, T(0)}, int role = MV_PLAIN) {
     if (A.fmt == FMT_SELL) {
-        EQS_SELL_LANES_SWITCH(A.sell.lanes, hipLaunchKernelGGL((k_sell_mv<L_, T>), dim3(sell_grid(A.sell)),
-                                                               dim3(kBlock), 0, s, view(A.sell), x, y, acc, in, stop));
+        EQS_SELL_LANES_SWITCH(A.sell.lanes,
+                              EQS_UNROLL_SWITCH(A.sell.unroll,
+                                                hipLaunchKernelGGL((sell_mv_kernel<L_, U_, T>(role)),
+                                                                   dim3(sell_grid(A.sell)), dim3(kBlock), 0, s,
+                                                                   view(A.sell), x, y, acc, in, stop)));
     } else {
         EQS_LANES_SWITCH(A.lanes, hipLaunchKernelGGL((k_csr_mv<L_, T>), dim3(csr_grid(A)), dim3(kBlock), 0, s,
                                                      cview(A), x, y, acc, in, stop));
@@ -1088,11 +1143,14 @@ static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int ac
 // launch_mv with the launch's own events when kernel class `cls` is profiled
 template <typename T>
 static void launch_mv_timed(hipStream_t s, eqs_ctx* c, int cls, const SpMat<T>& A, const T* x, T* y, int acc,
-                            const int32_t* stop) {
+                            const int32_t* stop, int role) {
     const MvInit<T> in{nullptr, nullptr, T(0)};
     if (A.fmt == FMT_SELL) {
-        EQS_SELL_LANES_SWITCH(A.sell.lanes, EQS_LAUNCH_TIMED(c, cls, (k_sell_mv<L_, T>), dim3(sell_grid(A.sell)),
-                                                             dim3(kBlock), 0, s, view(A.sell), x, y, acc, in, stop));
+        EQS_SELL_LANES_SWITCH(A.sell.lanes,
+                              EQS_UNROLL_SWITCH(A.sell.unroll,
+                                                EQS_LAUNCH_TIMED(c, cls, (sell_mv_kernel<L_, U_, T>(role)),
+                                                                 dim3(sell_grid(A.sell)), dim3(kBlock), 0, s,
+                                                                 view(A.sell), x, y, acc, in, stop)));
     } else {
         EQS_LANES_SWITCH(A.lanes, EQS_LAUNCH_TIMED(c, cls, (k_csr_mv<L_, T>), dim3(csr_grid(A)), dim3(kBlock), 0, s,
                                                    cview(A), x, y, acc, in, stop));
@@ -1104,9 +1162,11 @@ static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, con
     if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
     if (lv.A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
-                              hipLaunchKernelGGL((k_presmooth_res<L_, T, TB>), dim3(sell_grid(lv.A.sell)),
-                                                 dim3(kBlock), 0, s, sview(lv), (const T*)lv.dinv, (T)lv.omega, b,
-                                                 lv.x, lv.res, stop));
+                              EQS_UNROLL_SWITCH(lv.A.sell.unroll,
+                                                hipLaunchKernelGGL((k_presmooth_res<L_, T, TB, U_>),
+                                                                   dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
+                                                                   sview(lv), (const T*)lv.dinv, (T)lv.omega, b, lv.x,
+                                                                   lv.res, stop)));
     } else {
         EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_presmooth_res<L_, T, TB>), dim3(csr_grid(lv.A)),
                                                         dim3(kBlock), 0, s, scview(lv), (const T*)lv.dinv,
@@ -1120,9 +1180,12 @@ static void launch_postsmooth(hipStream_t s, const Level<T>& lv, const T* b, con
     if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
     if (lv.A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
-                              hipLaunchKernelGGL((k_postsmooth<L_, T, T, T, false>), dim3(sell_grid(lv.A.sell)),
-                                                 dim3(kBlock), 0, s, view(lv.A.sell), (const T*)lv.dinv,
-                                                 (T)lv.omega, b, x, out, InstMap{nullptr, nullptr, 0, -1}, nullptr, nullptr, stop));
+                              EQS_UNROLL_SWITCH(lv.A.sell.unroll,
+                                                hipLaunchKernelGGL((k_postsmooth<L_, T, T, T, false, U_>),
+                                                                   dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
+                                                                   view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, b,
+                                                                   x, out, InstMap{nullptr, nullptr, 0, -1}, nullptr,
+                                                                   nullptr, stop)));
     } else {
         EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_postsmooth<L_, T, T, T>), dim3(csr_grid(lv.A)),
                                                         dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
@@ -1254,7 +1317,8 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         Level<T>& lv = h.lv[l];
         if (lv.tail) break;  // folded into the coarse product and [G Q] (the last level above the coarsest)
         if (lv.fold_pre) {  // R holds R (I - A w D^-1): restrict b itself
-            launch_mv<T>(s, lv.R, (const T*)lv.b, h.lv[l + 1].b, 0, stop);
+            launch_mv<T>(s, lv.R, (const T*)lv.b, h.lv[l + 1].b, 0, stop, MvInit<T>{nullptr, nullptr, T(0)},
+                         MV_RESTRICT);
             continue;
         }
         if (l == 0) {
@@ -1265,8 +1329,12 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
             launch_presmooth<T, T>(s, lv, (const T*)lv.b, stop);
         }
         if (l + 1 < L - 1 || !h.lv[L - 1].coarse_R) {
-            if (l == 0) launch_mv_timed<T>(s, c, EQS_KCLASS_RESTRICT0, lv.R, (const T*)lv.res, h.lv[1].b, 0, stop);
-            else launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, stop);
+            if (l == 0)
+                launch_mv_timed<T>(s, c, EQS_KCLASS_RESTRICT0, lv.R, (const T*)lv.res, h.lv[1].b, 0, stop,
+                                   MV_RESTRICT);
+            else
+                launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, stop, MvInit<T>{nullptr, nullptr, T(0)},
+                             MV_RESTRICT);
         }
         if (l == 0) prof_begin(c, EQS_KCLASS_VCOARSE, s);
     }
@@ -1290,11 +1358,12 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         const T* xc = (l + 1 == L - 1) ? h.lv[l + 1].x : h.lv[l + 1].xs;
         if (l == 0) prof_end(c, EQS_KCLASS_VCOARSE, s);
         if (lv.fold_pre)  // x = w D^-1 b (the folded pre-smoother's result) + P xc
-            launch_mv<T>(s, lv.P, xc, lv.x, 2, stop, MvInit<T>{(const T*)lv.dinv, (const T*)lv.b, (T)lv.omega});
+            launch_mv<T>(s, lv.P, xc, lv.x, 2, stop, MvInit<T>{(const T*)lv.dinv, (const T*)lv.b, (T)lv.omega},
+                         MV_PROLONG);
         else if (l == 0)
-            launch_mv_timed<T>(s, c, EQS_KCLASS_PROLONG0, lv.P, xc, lv.x, 1, stop);
+            launch_mv_timed<T>(s, c, EQS_KCLASS_PROLONG0, lv.P, xc, lv.x, 1, stop, MV_PROLONG);
         else
-            launch_mv<T>(s, lv.P, xc, lv.x, 1, stop);
+            launch_mv<T>(s, lv.P, xc, lv.x, 1, stop, MvInit<T>{nullptr, nullptr, T(0)}, MV_PROLONG);
         if (l > 0) {
             launch_postsmooth<T>(s, lv, (const T*)lv.b, (const T*)lv.x, lv.xs, stop);
         } else {

@@ -79,28 +79,30 @@ __device__ __forceinline__ int32_t sell_perm_row(const uint8_t* __restrict__ per
 
 // sum_k a_{row,k} f(col_k) over the stored entries of `row` served by global
 // thread g (rows past n_rows but inside the last slice see padding only).
-// Entries are taken in groups of 8 whose loads carry no branch: positions
+// Entries are taken in groups of U whose loads carry no branch: positions
 // past the slice's width re-read its last entry (a cache hit) and their terms
 // are dropped by a select, so all loads and gathers of a group are in flight
-// together. The operator's values and column data are read once per product
-// and carry the nontemporal hint, which leaves the caches to the gathered
-// vector. Each lane sums in k order; with L > 1 the lane sums are then
-// combined by group_sum (every lane of the group gets the row's sum).
-template <int L, typename T, typename F>
+// together (a row of w stored entries costs ceil(w / U) dependent rounds of
+// loads, then gathers; short rows want a small U, long ones a large U). The
+// operator's values and column data are read once per product and carry the
+// nontemporal hint, which leaves the caches to the gathered vector. Each lane
+// sums in k order; with L > 1 the lane sums are then combined by group_sum
+// (every lane of the group gets the row's sum).
+template <int L, int U = 8, typename T, typename F>
 __device__ __forceinline__ T sell_accum(const SellView<T>& A, int64_t g, int32_t row, F f) {
     const int32_t s = (int32_t)(g >> 6), l = (int32_t)(g & 63);
     const int32_t beg = A.sptr[s];
     const int32_t w = (A.sptr[s + 1] - beg) >> 6;  // uniform across the wavefront
     const T* vp = A.val + beg + l;
     T acc = T(0);
-    for (int32_t k0 = 0; k0 < w; k0 += 8) {
-        T v[8];
-        int32_t j[8];
+    for (int32_t k0 = 0; k0 < w; k0 += U) {
+        T v[U];
+        int32_t j[U];
         if (A.d16) {
             const int16_t* dp = A.d16 + beg + l;
             const int32_t base = offset_base(row, A.n_rows, A.n_cols);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int64_t kk = (int64_t)min(k0 + u, w - 1) * 64;
                 v[u] = __builtin_nontemporal_load(vp + kk);
                 j[u] = base + (int32_t)__builtin_nontemporal_load(dp + kk);
@@ -108,24 +110,24 @@ __device__ __forceinline__ T sell_accum(const SellView<T>& A, int64_t g, int32_t
         } else {
             const int32_t* cp = A.col + beg + l;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int64_t kk = (int64_t)min(k0 + u, w - 1) * 64;
                 v[u] = __builtin_nontemporal_load(vp + kk);
                 j[u] = __builtin_nontemporal_load(cp + kk);
             }
         }
-        T t[8];
+        T t[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) t[u] = v[u] * f(j[u]);
+        for (int u = 0; u < U; ++u) t[u] = v[u] * f(j[u]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += (k0 + u < w) ? t[u] : T(0);
+        for (int u = 0; u < U; ++u) acc += (k0 + u < w) ? t[u] : T(0);
     }
     return group_sum<L>(acc);
 }
 
-template <int L, typename T, typename TX>
+template <int L, int U = 8, typename T, typename TX>
 __device__ __forceinline__ T sell_row(const SellView<T>& A, int64_t g, int32_t row, const TX* __restrict__ x) {
-    return sell_accum<L>(A, g, row, [&](int32_t j) { return (T)x[j]; });
+    return sell_accum<L, U>(A, g, row, [&](int32_t j) { return (T)x[j]; });
 }
 
 // One lane per row (thread index = row).

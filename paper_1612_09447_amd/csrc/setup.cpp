@@ -933,6 +933,7 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
             S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
             S.fmt = FMT_SELL;
             S.sell = to_sell<T>(c, A, c->force_layout, c->force_sorted && allow_sorted);
+            S.sell.unroll = c->force_unroll;
         }
         c->tune_log += std::string(what) + ": layout set by EQS_LAYOUT\n";
         return S;
@@ -972,8 +973,30 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
             S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
             S.fmt = FMT_SELL;
             S.sell = to_sell<T>(c, A, L, sorted != 0);
+            // the group size, timed on the product (the coarse smoothing kernels
+            // take the same; the finest level's keep 8)
+            {
+                const double per_lane = mean / L;
+                double best_u_ms = 1e300;
+                int best_u = 8;
+                for (int U : {4, 8, 16}) {
+                    if (U == 16 && per_lane < 6.0) continue;
+                    S.sell.unroll = U;
+                    const double ms = time_mv<T>(c, S, x, y, 5);
+                    if (c->tune_verbose) {
+                        char t[64];
+                        std::snprintf(t, sizeof t, " [u%d %.1f]", U, ms * 1e3);
+                        tried += t;
+                    }
+                    if (ms < best_u_ms) {
+                        best_u_ms = ms;
+                        best_u = U;
+                    }
+                }
+                S.sell.unroll = best_u;
+            }
             consider(S, std::string("sell64") + (L > 1 ? "x" + std::to_string(L) : "") + (sorted ? "s" : "") +
-                            (S.sell.d16 ? "/i16" : ""));
+                            (S.sell.d16 ? "/i16" : "") + (S.sell.unroll != 8 ? "/u" + std::to_string(S.sell.unroll) : ""));
         }
     }
     for (int L = (mean <= 8.0 ? 1 : 2); L <= 64; L *= 2) {

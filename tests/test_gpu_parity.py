@@ -168,14 +168,18 @@ def test_preconditioner_symmetric_positive(prec, tol):
 @pytest.mark.parametrize("prec,tol", [(EQS_PREC_FP64, 1e-12), (EQS_PREC_FP32, 2e-5)])
 def test_preconditioner_same_in_every_layout(prec, tol, monkeypatch):
     """Each storage layout of the coarse operators (SELL with 1, 2, 4, 8 lanes
-    per row, with and without rows sorted by length within windows, CSR with
-    lanes) gives the same V-cycle up to summation order."""
+    per row, with and without rows sorted by length within windows, with 4, 8
+    or 16 entries per lane in flight, CSR with lanes)
+    gives the same V-cycle up to summation order."""
     case = inclusion_case(14, 4)
     n = None
     outs = {}
     X = None
-    for lay in ("sell1", "sell2", "sell4", "sell8", "csr", "sell1s", "sell2s", "sell4s", "sell8s"):
+    layouts = [(lay, "8") for lay in ("sell1", "sell2", "sell4", "sell8", "csr", "sell1s", "sell2s", "sell4s", "sell8s")]
+    layouts += [("sell1", "4"), ("sell1s", "16"), ("sell2s", "4"), ("sell4", "16"), ("sell8s", "16")]
+    for lay, unroll in layouts:
         monkeypatch.setenv("EQS_LAYOUT", lay)
+        monkeypatch.setenv("EQS_UNROLL", unroll)
         with ctx_for(case, precision=prec, coarse_max=24) as c:
             info = c.info()
             assert info["n_levels"] >= 3, info  # coarse levels smooth in the forced layout
@@ -185,10 +189,14 @@ def test_preconditioner_same_in_every_layout(prec, tol, monkeypatch):
                 X = np.random.default_rng(7).normal(size=n)
             z = torch.zeros(n, dtype=torch.float64, device=DEV)
             c.apply_preconditioner(T(X), z)
-            outs[lay] = N(z)
-            print(f"[layout] prec={prec} {lay} levels={info['n_levels']}", flush=True)
-    for lay, z in outs.items():
-        assert relinf(z, outs["sell1"]) <= tol, lay
+            outs[lay, unroll] = N(z)
+            print(f"[layout] prec={prec} {lay} u{unroll} levels={info['n_levels']}", flush=True)
+    for key, z in outs.items():
+        assert relinf(z, outs["sell1", "8"]) <= tol, key
+    monkeypatch.setenv("EQS_UNROLL", "6")
+    with pytest.raises(EqsError):
+        Context(0, torch.cuda.current_stream(DEV))
+    monkeypatch.setenv("EQS_UNROLL", "8")
     monkeypatch.setenv("EQS_LAYOUT", "sell3")
     with pytest.raises(EqsError):
         Context(0, torch.cuda.current_stream(DEV))
