@@ -235,7 +235,7 @@ def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None):
 
 
 def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous", flexible=0, learned_steps=0,
-            learned_warmup=20, mlp_batch=256, keep_states=False, mlp_warmup=64):
+            learned_warmup=20, mlp_batch=256, keep_states=False, mlp_warmup=64, graph_iters=1):
     """Time `steps` RKC steps (uninstrumented), then `prof_steps` more with every
     kernel class timed by HIP events on the context's stream. With
     learned_steps > 0 the same context then switches to the Galerkin and the
@@ -251,6 +251,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
     stream = torch.cuda.current_stream(dev)
     t0 = time.perf_counter()
     ctx = Context(0, stream)
+    ctx.set_graph_iters(graph_iters)
     info = ctx.setup_case(case, precision=precision, flexible=flexible)
     # PyTorch owns the device memory: the context moves into a torch workspace
     # sized for its largest start-vector setting of this run
@@ -389,9 +390,12 @@ def run_p2(n, steps, warmup, prof_steps=1):
     return out
 
 
-def run_batched(steps, warmup):
+def run_batched(steps, warmup, graph_iters=(1, 64)):
     """The batched workload: 64 independent instances (n in {16..48}^3) packed
-    into one context, RKC(8) steps of all of them together."""
+    into one context, RKC(8) steps of all of them together, timed once per
+    launch granularity in `graph_iters` (CG iterations per captured graph: 1,
+    and one that spans a whole stage solve), each from rest over the same
+    steps."""
     import torch
 
     import eqsgen
@@ -412,22 +416,35 @@ def run_batched(steps, warmup):
     dof = sum((c.n + 1) ** 2 * (c.n - 1) for c in cases)
     log(f"[bench] batched: {len(cases)} instances, {dof} free DOF, {sum(c.n_tets for c in cases)} tets, "
         f"setup {setup_s:.1f}s")
-    xs = [torch.zeros(c.n_nodes, dtype=torch.float64, device="cuda:0") for c in cases]
     tau, s, rtol = cases[0].tau, cases[0].s, cases[0].rtol
-    if warmup:
-        b.rkc_steps(warmup, 0.0, tau, s, xs, rtol)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    res = b.rkc_steps(steps, warmup * tau, tau, s, xs, rtol)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
+    runs, finals = {}, {}
+    for g in graph_iters:
+        b.set_graph_iters(g)
+        xs = [torch.zeros(c.n_nodes, dtype=torch.float64, device="cuda:0") for c in cases]
+        if warmup:
+            b.rkc_steps(warmup, 0.0, tau, s, xs, rtol)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = b.rkc_steps(steps, warmup * tau, tau, s, xs, rtol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        stages = steps * s * len(cases)
+        runs[g] = {"stages_per_s_aggregate": round(stages / el, 1), "dof_stages_per_s": round(dof * steps * s / el, 1),
+                   "cg_iters_per_instance_stage": {"min": round(float(res["iters"].min()) / (steps * s), 2),
+                                                   "max": round(float(res["iters"].max()) / (steps * s), 2)}}
+        finals[g] = torch.cat(xs)
+        log(f"[bench] batched, {g} CG iterations per graph: {runs[g]['stages_per_s_aggregate']} instance-stages/s")
     b.close()
-    stages = steps * s * len(cases)
-    return {"instances": len(cases), "free_dof": dof, "steps": steps, "s": s,
-            "stages_per_s_aggregate": round(stages / el, 1), "dof_stages_per_s": round(dof * steps * s / el, 1),
-            "cg_iters_per_instance_stage": {"min": round(float(res["iters"].min()) / (steps * s), 2),
-                                            "max": round(float(res["iters"].max()) / (steps * s), 2)},
-            "precision": "FP64 CG + K(x)x, FP32 AMG", "setup_s": round(setup_s, 1)}
+    g0 = graph_iters[0]
+    best = max(runs, key=lambda g: runs[g]["stages_per_s_aggregate"])
+    out = {"instances": len(cases), "free_dof": dof, "steps": steps, "s": s, **runs[best],
+           "graph_iters": best, "by_graph_iters": {str(g): r for g, r in runs.items()},
+           "precision": "FP64 CG + K(x)x, FP32 AMG", "setup_s": round(setup_s, 1)}
+    if len(runs) > 1:
+        # the launch granularity changes no arithmetic: the final states agree up to the solve tolerance
+        ref = finals[g0]
+        out["max_rel_state_diff_across_graph_forms"] = float(f"{max(float(torch.linalg.vector_norm(v - ref) / torch.linalg.vector_norm(ref)) for v in finals.values()):.3e}")
+    return out
 
 
 def cpu_baseline(case, x_user, step):
@@ -464,7 +481,10 @@ def main():
     ap.add_argument("--guess", default="previous", choices=["previous", "zero", "galerkin", "mlp"])
     ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
+    ap.add_argument("--graph-iters", type=int, default=1, help="CG iterations per captured graph launch")
     ap.add_argument("--c3-steps", type=int, default=5, help="also time the 64-instance batched workload (0: skip)")
+    ap.add_argument("--c3-graph-iters", default="1,64",
+                    help="CG iterations per graph launch for the batched workload, one timed run each (comma list)")
     ap.add_argument("--mlp-batch", type=int, default=256, help="network training pairs per stage (<= 256)")
     ap.add_argument("--mlp-warmup", type=int, default=64,
                     help="training pairs collected before the network's start vector is used")
@@ -500,7 +520,7 @@ def main():
     log(f"[bench] copy probe: {copy}; read probe: {rd}")
     r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess,
                 flexible=args.flexible, learned_steps=args.learned_steps, mlp_batch=args.mlp_batch,
-                keep_states=True, mlp_warmup=args.mlp_warmup)
+                keep_states=True, mlp_warmup=args.mlp_warmup, graph_iters=args.graph_iters)
     stages_per_s = r["stages"] / r["elapsed"]
     info = r["info"]
     prof = r["prof"]
@@ -542,7 +562,8 @@ def main():
     plain_steps = args.steps if args.plain_steps < 0 else args.plain_steps
     ref_hist = None
     if plain_steps > 0 and main_prec != EQS_PREC_FP64:
-        p = run_gpu(case, EQS_PREC_FP64, plain_steps, args.warmup, case.rtol, keep_states=plain_steps == args.steps)
+        p = run_gpu(case, EQS_PREC_FP64, plain_steps, args.warmup, case.rtol, keep_states=plain_steps == args.steps,
+                    graph_iters=args.graph_iters)
         plain = {"stages_per_s": round(p["stages"] / p["elapsed"], 2),
                  "mean_cg_iters_per_stage": round(sum(p["iters"]) / len(p["iters"]), 2),
                  "steps": plain_steps}
@@ -556,7 +577,7 @@ def main():
     full = {}
     for kind in [k for k in args.full_runs.split(",") if k]:
         f = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, guess=kind, mlp_batch=args.mlp_batch,
-                    keep_states=ref_hist is not None, mlp_warmup=args.mlp_warmup)
+                    keep_states=ref_hist is not None, mlp_warmup=args.mlp_warmup, graph_iters=args.graph_iters)
         full[kind] = {"stages_per_s": round(f["stages"] / f["elapsed"], 2),
                       "mean_cg_iters_per_stage": round(sum(f["iters"]) / len(f["iters"]), 2),
                       "steps": args.steps, "guess_used": f["used"], "guard_fallbacks": f["fallbacks"],
@@ -567,7 +588,8 @@ def main():
     ref_hist = None
     torch.cuda.empty_cache()
 
-    batched = run_batched(args.c3_steps, 1) if args.c3_steps > 0 else None
+    c3_g = tuple(int(g) for g in args.c3_graph_iters.split(",") if g)
+    batched = run_batched(args.c3_steps, 1, c3_g) if args.c3_steps > 0 else None
     adaptive = run_adaptive(case, main_prec, args.adaptive_ms * 1e-3, 1e-2) if args.adaptive_ms > 0 else None
     p2 = run_p2(args.p2_n, args.p2_steps, 1) if args.p2_steps > 0 else None
 
@@ -598,6 +620,7 @@ def main():
             "guess_used": r["used"],
             "guess_fallbacks": r["fallbacks"],
             "graphs": bool(args.graphs),
+            "cg_iters_per_graph_launch": args.graph_iters,
             "mean_cg_iters_per_stage": round(sum(r["iters"]) / len(r["iters"]), 2),
             "amg_levels": info["level_rows"],
             "device_memory": f"torch workspace of {info['workspace_bytes']} bytes (eqs_set_workspace); "

@@ -169,6 +169,16 @@ int eqs_set_materials(eqs_ctx *ctx, int32_t n_mat, const eqs_material *mats, con
 int eqs_set_dirichlet(eqs_ctx *ctx, int64_t n_d, const int32_t *nodes, const int32_t *drive_id,
                       int32_t n_drive, const eqs_drive *drives);
 
+/* Launch granularity of the CG solves (the solve is Sec. II's M-solve; the
+ * grouping is this library's choice): every launch replays one captured HIP
+ * graph of `iters` CG iterations, 1..EQS_MAX_GRAPH_ITERS [1]. Iterations that
+ * a launch holds past convergence return at entry (a few microseconds each),
+ * so a large value gives a graph spanning the whole solve, a small one lets
+ * the host stop closer to convergence. Results do not depend on it. Takes
+ * effect at the next solve; EQS_ERR_INVALID_ARG outside the range. */
+#define EQS_MAX_GRAPH_ITERS 256
+int eqs_set_graph_iters(eqs_ctx *ctx, int32_t iters);
+
 /* Assemble M on the free nodes (eq. (2)), build the AMG hierarchy once for
  * all stages and steps (Sec. II: the constant M makes the solves a multiple
  * right-hand-side problem), and upload mesh, materials and hierarchy to the
@@ -331,6 +341,8 @@ typedef struct eqs_batch eqs_batch;
 int eqs_batch_create(eqs_batch **out, int32_t n, eqs_ctx *const *ctxs, int device, void *hip_stream,
                      const eqs_amg_params *p);
 int eqs_batch_destroy(eqs_batch *b);
+/* eqs_set_graph_iters for the batch's packed context. */
+int eqs_batch_set_graph_iters(eqs_batch *b, int32_t iters);
 /* nsteps RKC(s) steps of every instance from t0 with step dt; x_dev[i] holds
  * instance i's n_nodes potentials (in/out, as eqs_rkc_step). st (may be NULL)
  * receives the batch's aggregated stats of the last step; per-instance

@@ -26,6 +26,7 @@ EQS_ERR_BREAKDOWN = -5
 EQS_ERR_NONFINITE = -6
 EQS_ERR_ALLOC = -7
 EQS_MAX_DRIVES = 65536
+EQS_MAX_GRAPH_ITERS = 256
 EQS_PREC_FP64 = 0
 EQS_PREC_FP32 = 1
 
@@ -113,6 +114,7 @@ _SIGNATURES = {
     "eqs_set_materials": ([_P, C.c_int32, _P, _P], C.c_int),
     "eqs_set_dirichlet": ([_P, C.c_int64, _P, _P, C.c_int32, _P], C.c_int),
     "eqs_build_preconditioner": ([_P, _P], C.c_int),
+    "eqs_set_graph_iters": ([_P, C.c_int32], C.c_int),
     "eqs_get_info": ([_P, _P], C.c_int),
     "eqs_query": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "eqs_set_workspace": ([_P, _P, C.c_int64], C.c_int),
@@ -131,6 +133,7 @@ _SIGNATURES = {
     "eqs_instance_stats": ([_P, C.c_int32, _P, _P], C.c_int),
     "eqs_batch_create": ([C.POINTER(_P), C.c_int32, _P, C.c_int, _P, _P], C.c_int),
     "eqs_batch_destroy": ([_P], C.c_int),
+    "eqs_batch_set_graph_iters": ([_P, C.c_int32], C.c_int),
     "eqs_batch_rkc_steps": ([_P, C.c_int32, C.c_double, C.c_double, C.c_int32, _P, C.c_double, C.c_int32, _P],
                             C.c_int),
     "eqs_batch_instance_stats": ([_P, _P, _P], C.c_int),
@@ -283,6 +286,10 @@ class Context:
         for k, v in kw.items():
             setattr(p, k, v)
         _check(lib().eqs_build_preconditioner(self._h, C.byref(p)), "eqs_build_preconditioner")
+
+    def set_graph_iters(self, iters):
+        """CG iterations replayed per captured graph launch (1 .. EQS_MAX_GRAPH_ITERS)."""
+        _check(lib().eqs_set_graph_iters(self._h, int(iters)), "eqs_set_graph_iters")
 
     def setup_case(self, case, precision=None, **amg):
         """Hand a ``eqsgen.Case`` to the library (mesh, materials, Dirichlet, AMG)."""
@@ -542,6 +549,10 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def set_graph_iters(self, iters):
+        """CG iterations replayed per captured graph launch (1 .. EQS_MAX_GRAPH_ITERS)."""
+        _check(lib().eqs_batch_set_graph_iters(self._h, int(iters)), "eqs_batch_set_graph_iters")
 
     def rkc_steps(self, nsteps, t0, dt, s, xs, rtol, maxit=1000):
         ptrs = (_P * self.n)(*[_dev(x) for x in xs])

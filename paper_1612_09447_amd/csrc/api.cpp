@@ -229,6 +229,15 @@ int eqs_set_dirichlet(eqs_ctx* c, int64_t n_d, const int32_t* nodes, const int32
     });
 }
 
+int eqs_set_graph_iters(eqs_ctx* c, int32_t iters) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        need(iters >= 1 && iters <= EQS_MAX_GRAPH_ITERS, "iterations per graph must be in [1, EQS_MAX_GRAPH_ITERS]");
+        c->graph_iters = iters;
+        return EQS_OK;
+    });
+}
+
 int eqs_build_preconditioner(eqs_ctx* c, const eqs_amg_params* p) {
     return guarded([&] {
         need(c != nullptr, "ctx is NULL");

@@ -85,6 +85,14 @@ int eqs_batch_create(eqs_batch** out, int32_t n, eqs_ctx* const* ctxs, int devic
     return EQS_OK;
 }
 
+int eqs_batch_set_graph_iters(eqs_batch* b, int32_t iters) {
+    if (!b) {
+        eqs::set_error("eqs_batch_set_graph_iters: NULL batch");
+        return EQS_ERR_INVALID_ARG;
+    }
+    return eqs_set_graph_iters(b->packed, iters);
+}
+
 int eqs_batch_destroy(eqs_batch* b) {
     if (!b) return EQS_OK;
     eqs_destroy(b->packed);

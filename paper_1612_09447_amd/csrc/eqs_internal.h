@@ -331,9 +331,11 @@ struct eqs_ctx {
 
     // the CG iteration body captured once as a HIP graph (x is baked in)
     bool use_graphs = true;
+    int32_t graph_iters = 1;  // CG iterations per captured graph (eqs_set_graph_iters)
     hipGraphExec_t iter_exec = nullptr;
     const double* iter_x = nullptr;
     int iter_prec = -1;
+    int iter_g = 0;
 
     // per-kernel-class timing (HIP event pairs around launches)
     uint32_t prof_mask = 0;

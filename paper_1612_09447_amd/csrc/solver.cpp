@@ -30,32 +30,36 @@ static void check_launch() {
 
 // The kernels of one CG iteration take every scalar from device memory, so a
 // single captured graph replays any iteration of any solve into the same x.
-// Graphs are skipped on the null stream and while kernels of the iteration
-// are being timed individually.
+// One graph holds c->graph_iters iterations (a launch runs that many; those
+// past convergence return at entry). Graphs are skipped on the null stream
+// and while kernels of the iteration are being timed individually (then the
+// iterations are launched one by one).
 static void run_iteration(eqs_ctx* c, double* x, int prec) {
     const uint32_t iter_classes = (1u << EQS_KCLASS_SPMV_M) | (1u << EQS_KCLASS_PRESMOOTH0) |
                                   (1u << EQS_KCLASS_POSTSMOOTH0) | (1u << EQS_KCLASS_VCYCLE) |
                                   (1u << EQS_KCLASS_CG_UPDATE) | (1u << EQS_KCLASS_RESTRICT0) |
                                   (1u << EQS_KCLASS_PROLONG0) | (1u << EQS_KCLASS_VCOARSE) |
                                   (1u << EQS_KCLASS_FINALISE);
+    const int G = c->graph_iters;
     if (!c->use_graphs || c->stream == nullptr || (c->prof_mask & iter_classes)) {
-        pcg_iteration(c->stream, c, nullptr, x, prec);
+        for (int k = 0; k < G; ++k) pcg_iteration(c->stream, c, nullptr, x, prec);
         return;
     }
-    if (c->iter_exec == nullptr || c->iter_x != x || c->iter_prec != prec) {
+    if (c->iter_exec == nullptr || c->iter_x != x || c->iter_prec != prec || c->iter_g != G) {
         if (c->iter_exec) {
             (void)hipGraphExecDestroy(c->iter_exec);
             c->iter_exec = nullptr;
         }
         hipGraph_t g = nullptr;
         EQS_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        pcg_iteration(c->stream, c, nullptr, x, prec);
+        for (int k = 0; k < G; ++k) pcg_iteration(c->stream, c, nullptr, x, prec);
         EQS_HIP(hipStreamEndCapture(c->stream, &g));
         hipError_t e = hipGraphInstantiate(&c->iter_exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) fail(EQS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         c->iter_x = x;
         c->iter_prec = prec;
+        c->iter_g = G;
     }
     EQS_HIP(hipGraphLaunch(c->iter_exec, c->stream));
 }
@@ -89,20 +93,21 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
     for (;;) {
         int64_t used0[EQS_KCLASS_COUNT];
         for (int k = 0; k < EQS_KCLASS_COUNT; ++k) used0[k] = c->prof_used[k];
-        // Iteration k+1 is enqueued before the host waits for iteration k, so
-        // the GPU does not wait for the host; only when iteration k is expected
-        // to converge (the last two residuals the host has seen, extrapolated
-        // geometrically, reach rtol) does the host wait for k first, so that
-        // no iteration is launched past convergence.
+        // Launch k+1 (of graph_iters iterations each) is enqueued before the
+        // host waits for launch k, so the GPU does not wait for the host; only
+        // when launch k is expected to converge (the last two residuals the
+        // host has seen, extrapolated geometrically, reach rtol) does the host
+        // wait for k first, so that no launch is queued past convergence.
         // When it waits, the host first queues the residual check, which acts
-        // only if iteration k completed the solve: the check then runs without
-        // a host round trip in between.
+        // only if launch k completed the solve: the check then runs without a
+        // host round trip in between.
+        const int64_t G = c->graph_iters;
         double rel_prev = -1.0, rel_last = -1.0;
         bool checked = false;
         run_iteration(c, y, prec);
         EQS_HIP(hipEventRecord(c->ev[0], s));
         for (int64_t k = 0;; ++k) {
-            const bool last = k + 1 > (int64_t)maxit + 2;  // the device stops itself at maxit
+            const bool last = (k + 1) * G > (int64_t)maxit + 2;  // the device stops itself at maxit
             bool ahead = !last;
             if (ahead && rel_last > 0.0 && rel_prev > rel_last && rel_last * (rel_last / rel_prev) <= rtol)
                 ahead = false;

@@ -78,7 +78,8 @@ def test_struct_layouts_match_header(tmp_path):
 def test_constants_match_header():
     src = open(HEADER).read()
     for name in ["EQS_OK", "EQS_ERR_INVALID_ARG", "EQS_ERR_STATE", "EQS_ERR_HIP", "EQS_ERR_NOT_CONVERGED",
-                 "EQS_ERR_BREAKDOWN", "EQS_ERR_NONFINITE", "EQS_ERR_ALLOC", "EQS_MAX_DRIVES", "EQS_MLP_NPARAM"]:
+                 "EQS_ERR_BREAKDOWN", "EQS_ERR_NONFINITE", "EQS_ERR_ALLOC", "EQS_MAX_DRIVES", "EQS_MLP_NPARAM",
+                 "EQS_MAX_GRAPH_ITERS"]:
         m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, src)
         assert m and int(m.group(1)) == getattr(binding, name), name
 
@@ -129,6 +130,8 @@ def test_error_paths_without_device():
     assert L.eqs_query(None, C.byref(nf), C.byref(ws)) == binding.EQS_ERR_INVALID_ARG
     assert L.eqs_set_workspace(None, None, 0) == binding.EQS_ERR_INVALID_ARG
     assert b"NULL" in L.eqs_last_error()
+    assert L.eqs_set_graph_iters(None, 4) == binding.EQS_ERR_INVALID_ARG
+    assert L.eqs_batch_set_graph_iters(None, 4) == binding.EQS_ERR_INVALID_ARG
     with pytest.raises(pkg.EqsError) as ei:
         pkg.Context(0)
     assert ei.value.code == binding.EQS_ERR_HIP
