@@ -78,6 +78,20 @@ int eqs_create(eqs_ctx** out, int device, void* hip_stream) {
         c->stream = (hipStream_t)hip_stream;
         const char* g = std::getenv("EQS_USE_GRAPHS");  // "0" replays CG iterations as plain launches
         c->use_graphs = !(g && g[0] == '0');
+        const char* tf = std::getenv("EQS_TUNE_FILE");  // tuning record: replayed if present, else written
+        if (tf && tf[0]) {
+            c->tune_file = tf;
+            if (FILE* f = std::fopen(tf, "r")) {
+                char buf[512];
+                while (std::fgets(buf, sizeof buf, f)) {
+                    std::string ln(buf);
+                    while (!ln.empty() && (ln.back() == '\n' || ln.back() == '\r')) ln.pop_back();
+                    const size_t tab = ln.find('\t');
+                    if (tab != std::string::npos) c->tune_replay[ln.substr(0, tab)] = ln.substr(tab + 1);
+                }
+                std::fclose(f);
+            }
+        }
         const char* at = std::getenv("EQS_AUTOTUNE");  // "0" keeps the rule-based operator layouts
         c->autotune = !(at && at[0] == '0');
         const char* i16 = std::getenv("EQS_INDEX16");

@@ -325,6 +325,12 @@ struct eqs_ctx {
     bool test_reject_first = false;
     int32_t* d_force = nullptr;
     std::string tune_log;  // chosen layouts, one line per operator
+    // Tuning record (EQS_TUNE_FILE): choices read from an existing file are
+    // replayed instead of timed; otherwise the timed choices are written there
+    // at the end of the build. Keys name the operator and its size.
+    std::string tune_file;
+    std::map<std::string, std::string> tune_replay;
+    std::vector<std::string> tune_record;
 
     // start vectors
     eqs::GuessState guess;

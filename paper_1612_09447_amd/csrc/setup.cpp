@@ -940,6 +940,42 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
     }
     if (!c->autotune || A.n_rows == 0) return to_spmat<T>(c, A);
     const double mean = (double)A.nnz() / A.n_rows;
+    auto make_csr = [&](int L) {
+        SpMat<T> S;
+        S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
+        S.fmt = FMT_CSR;
+        S.lanes = L;
+        std::vector<T> v(A.val.size());
+        for (size_t k = 0; k < v.size(); ++k) v[k] = (T)A.val[k];
+        S.rowptr = upload_vec(c, A.ptr);
+        upload_csr_cols(c, S, A);
+        S.val = upload_vec(c, v);
+        return S;
+    };
+    const std::string key = std::string(what) + " " + std::to_string(A.n_rows) + "x" + std::to_string(A.n_cols) + " " +
+                            std::to_string(A.nnz());
+    {
+        auto it = c->tune_replay.find(key);
+        if (it != c->tune_replay.end()) {  // a recorded choice: rebuild it without timing
+            char kind[8] = {0};
+            int L = 0, sorted = 0, U = 8;
+            const int n = std::sscanf(it->second.c_str(), "%7s %d %d %d", kind, &L, &sorted, &U);
+            SpMat<T> S;
+            if (n >= 2 && std::string(kind) == "csr" && L >= 1 && L <= 64 && (L & (L - 1)) == 0) {
+                S = make_csr(L);
+            } else if (n == 4 && std::string(kind) == "sell" && (L == 1 || L == 2 || L == 4 || L == 8) &&
+                       (U == 4 || U == 8 || U == 16)) {
+                S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
+                S.fmt = FMT_SELL;
+                S.sell = to_sell<T>(c, A, L, sorted != 0 && allow_sorted);
+                S.sell.unroll = U;
+            } else {
+                fail(EQS_ERR_INVALID_ARG, "tuning record: bad entry for " + key + ": " + it->second);
+            }
+            c->tune_log += key + " -> " + it->second + " (tuning record)\n";
+            return S;
+        }
+    }
     T* x = (T*)dev_alloc(c, sizeof(T) * std::max<int32_t>(A.n_cols, 1));
     T* y = (T*)dev_alloc(c, sizeof(T) * std::max<int32_t>(A.n_rows, 1));
     {
@@ -1014,6 +1050,11 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
     }
     dev_free(c, x);
     dev_free(c, y);
+    if (best.fmt == FMT_CSR)
+        c->tune_record.push_back(key + "\tcsr " + std::to_string(best.lanes));
+    else
+        c->tune_record.push_back(key + "\tsell " + std::to_string(best.sell.lanes) + " " +
+                                 std::to_string(best.sell.perm ? 1 : 0) + " " + std::to_string(best.sell.unroll));
     char line[200];
     const double fill = best.fmt == FMT_SELL && A.nnz() > 0 ? (double)best.sell.stored / (double)A.nnz() : 1.0;
     std::snprintf(line, sizeof line, "%s: %d x %d, %.1f nnz/row -> %s (%.1f us, stored/nnz %.2f)\n", what, A.n_rows,
@@ -1357,6 +1398,20 @@ void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const dou
         fail(EQS_ERR_INVALID_ARG, "element block of 256 tets with more than " + std::to_string(kMaxBlockNodes) +
                                       " distinct nodes");
     }
+    const std::string key = "element " + std::to_string(c->n_tets) + " " + std::to_string(c->npe);
+    {
+        auto it = c->tune_replay.find(key);
+        if (it != c->tune_replay.end()) {  // a recorded block size
+            const int tpt = std::atoi(it->second.c_str());
+            if (tpt < 1 || tpt > kMaxTetsPerThread || (tpt & (tpt - 1)))
+                fail(EQS_ERR_INVALID_ARG, "tuning record: bad entry for " + key + ": " + it->second);
+            ElementBlocks eb = element_blocks(c, u2i, order, tpt);
+            if (eb.max_nodes > kMaxBlockNodes) fail(EQS_ERR_INVALID_ARG, "tuning record: " + key + " does not fit");
+            install_blocks(c, eb, tpt);
+            c->tune_log += "element: " + std::to_string(kTetBlock * tpt) + " tets per block (tuning record)\n";
+            return;
+        }
+    }
     int best_tpt = 0;
     double best = 1e300;
     std::string line = "element:";
@@ -1379,6 +1434,7 @@ void build_element_blocks(eqs_ctx* c, const std::vector<int32_t>& u2i, const dou
                                       " distinct nodes");
     if (best_tpt != c->tet_tpt) install_blocks(c, element_blocks(c, u2i, order, best_tpt), best_tpt);
     c->tune_log += line + " -> " + std::to_string(kTetBlock * best_tpt) + " tets per block\n";
+    c->tune_record.push_back(key + "\t" + std::to_string(best_tpt));
 }
 
 void upload(eqs_ctx* c) {
@@ -1461,6 +1517,13 @@ void upload(eqs_ctx* c) {
     guess_alloc_scratch(c);  // eqs_galerkin_start's dot scratch
     launch_fill(c->stream, c->d_Y0, 0.0, NF);
     build_element_blocks(c, u2i, c->d_Y0, c->d_rhs);
+    if (!c->tune_file.empty() && c->tune_replay.empty() && !c->tune_record.empty()) {
+        FILE* f = std::fopen(c->tune_file.c_str(), "w");
+        if (!f) fail(EQS_ERR_INVALID_ARG, "tuning record: cannot write " + c->tune_file);
+        for (const std::string& ln : c->tune_record) std::fprintf(f, "%s\n", ln.c_str());
+        std::fclose(f);
+    }
+    c->tune_record.clear();
     EQS_HIP(hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming));
     EQS_HIP(hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming));
     c->have_Flast = false;

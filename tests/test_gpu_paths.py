@@ -5,6 +5,9 @@ the FP64 oracle:
 * EQS_KX_GENERIC=1: the element pass with each block's own LDS stride, the
   path taken by element blocks with more distinct nodes than the fixed stride
   (Sec. III's fused K(x)x); element by element to 1e-12.
+* EQS_TUNE_FILE: the layout and block-size choices of one build are recorded
+  and a second build replays them without timing, giving the same
+  preconditioner; a malformed record is refused.
 * EQS_TEST_REJECT_CHECK=1: the true-residual check that ends every CG solve
   reports "not converged" once per solve, so each solve restarts from its true
   residual; with the plain start vector the rest of the stage and the next
@@ -22,7 +25,7 @@ from oracle.eqs import EqsOracle
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-from paper_1612_09447_amd import EQS_PREC_FP32, EQS_PREC_FP64, Context  # noqa: E402
+from paper_1612_09447_amd import EQS_PREC_FP32, EQS_PREC_FP64, Context, EqsError  # noqa: E402
 
 DEV = torch.device("cuda:0")
 
@@ -59,6 +62,31 @@ def test_element_pass_per_block_stride_matches_oracle(maker, monkeypatch):
             r = torch.zeros(o.n_free, dtype=torch.float64, device=DEV)
             c.stage_rhs(t, T(x[o.free]), r)
             assert relinf(r.cpu().numpy(), o.stage_rhs(t, x[o.free])) <= 1e-12
+
+
+def test_tuning_record_replays_the_same_layouts(tmp_path, monkeypatch):
+    case = eqsgen.case_c1(n=20, seed=3)
+    rec = tmp_path / "tune.txt"
+    monkeypatch.setenv("EQS_TUNE_FILE", str(rec))
+    x = eqsgen.random_state(case.n_nodes, 9, 1.0)
+    outs = []
+    for k in range(2):
+        with make_ctx(case, EQS_PREC_FP32) as c:
+            desc = c.describe()
+            n = c.info()["n_free"]
+            r = T(np.random.default_rng(4).normal(size=n))
+            z = torch.zeros(n, dtype=torch.float64, device=DEV)
+            c.apply_preconditioner(r, z)
+            outs.append((desc, z.cpu().numpy()))
+        if k == 0:
+            lines = rec.read_text().splitlines()
+            print(f"[paths] tuning record: {len(lines)} entries, e.g. {lines[:2]}", flush=True)
+            assert any(l.startswith("element ") for l in lines) and any("\tsell " in l or "\tcsr " in l for l in lines)
+    assert "(tuning record)" not in outs[0][0] and outs[1][0].count("(tuning record)") == len(lines)
+    assert np.array_equal(outs[0][1], outs[1][1])  # same layouts, same summation order
+    rec.write_text(lines[0].split("\t")[0] + "\tsell 3 0 8\n")
+    with pytest.raises(EqsError):
+        make_ctx(case, EQS_PREC_FP32)
 
 
 def run(case, steps, rtol, precision):
