@@ -210,7 +210,7 @@ def class_bytes(info, s_stages):
     return out
 
 
-def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None):
+def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None, steplog=None):
     """Run `steps` RKC steps from step index n; returns (elapsed s, per-step
     mean CG iterations per stage, guesses used, guard fallbacks). With `hist`
     (a device tensor [steps, n_nodes]) every step-end state is copied into it
@@ -222,7 +222,10 @@ def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None):
     t1 = time.perf_counter()
     iters, used, fallbacks = [], 0, 0
     for k in range(steps):
-        st = ctx.rkc_step((n + k) * tau, tau, s, x, rtol=rtol, maxit=500)
+        if steplog is not None:
+            st = steplog.step(ctx, n + k, (n + k) * tau, tau, s, x, rtol, maxit=500)
+        else:
+            st = ctx.rkc_step((n + k) * tau, tau, s, x, rtol=rtol, maxit=500)
         if hist is not None:
             hist[k].copy_(x)
         iters.append(st["total_iters"] / st["stages"])
@@ -235,7 +238,7 @@ def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None):
 
 
 def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous", flexible=0, learned_steps=0,
-            learned_warmup=20, mlp_batch=256, keep_states=False, mlp_warmup=64, graph_iters=1):
+            learned_warmup=20, mlp_batch=256, keep_states=False, mlp_warmup=64, graph_iters=1, steplog=None):
     """Time `steps` RKC steps (uninstrumented), then `prof_steps` more with every
     kernel class timed by HIP events on the context's stream. With
     learned_steps > 0 the same context then switches to the Galerkin and the
@@ -273,7 +276,8 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
         n += 1
     hist = torch.empty((steps, case.n_nodes), dtype=torch.float64, device=dev) if keep_states else None
-    elapsed, iters, used, fallbacks = timed_steps(ctx, x, n, steps, tau, s, rtol, f"{precision}/{guess}", hist)
+    elapsed, iters, used, fallbacks = timed_steps(ctx, x, n, steps, tau, s, rtol, f"{precision}/{guess}", hist,
+                                                  steplog)
     n += steps
     x_timed = x.cpu().numpy()  # state after warmup + timed steps (compared across precisions)
     prof, prof_elapsed = {}, 0.0
@@ -482,6 +486,8 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     ap.add_argument("--graph-iters", type=int, default=1, help="CG iterations per captured graph launch")
+    ap.add_argument("--metrics-jsonl", default="",
+                    help="append one JSON line per timed step of the main run to this file")
     ap.add_argument("--c3-steps", type=int, default=5, help="also time the 64-instance batched workload (0: skip)")
     ap.add_argument("--c3-graph-iters", default="1,64",
                     help="CG iterations per graph launch for the batched workload, one timed run each (comma list)")
@@ -518,9 +524,16 @@ def main():
     copy = copy_probe()
     rd = read_probe()
     log(f"[bench] copy probe: {copy}; read probe: {rd}")
+    steplog = None
+    if args.metrics_jsonl:
+        from paper_1612_09447_amd.steplog import StepLog
+
+        steplog = StepLog(args.metrics_jsonl, run=f"{args.workload} main", precision=prec, guess=args.guess)
     r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess,
                 flexible=args.flexible, learned_steps=args.learned_steps, mlp_batch=args.mlp_batch,
-                keep_states=True, mlp_warmup=args.mlp_warmup, graph_iters=args.graph_iters)
+                keep_states=True, mlp_warmup=args.mlp_warmup, graph_iters=args.graph_iters, steplog=steplog)
+    if steplog is not None:
+        steplog.close()
     stages_per_s = r["stages"] / r["elapsed"]
     info = r["info"]
     prof = r["prof"]

@@ -169,6 +169,18 @@ int eqs_set_materials(eqs_ctx *ctx, int32_t n_mat, const eqs_material *mats, con
 int eqs_set_dirichlet(eqs_ctx *ctx, int64_t n_d, const int32_t *nodes, const int32_t *drive_id,
                       int32_t n_drive, const eqs_drive *drives);
 
+/* Deterministic element pass (the fused K(x)x of Sec. III): with on = 1 the
+ * element contributions are summed in an order fixed at set-up (each tet
+ * writes its four values to slots of its block; every block node sums its
+ * slots in order; every node sums its blocks' partials in block order)
+ * instead of by floating-point atomics, so K(x)x, the stage right-hand side
+ * and therefore whole RKC trajectories are the same bit for bit from run to
+ * run. It costs about 160 MB of lists and partials at 12.6 M tets and extra
+ * memory traffic per pass. First-order tets only. Must be set before
+ * eqs_build_preconditioner (EQS_ERR_STATE afterwards if it would change);
+ * [0]. */
+int eqs_set_deterministic(eqs_ctx *ctx, int32_t on);
+
 /* Launch granularity of the CG solves (the solve is Sec. II's M-solve; the
  * grouping is this library's choice): every launch replays one captured HIP
  * graph of `iters` CG iterations, 1..EQS_MAX_GRAPH_ITERS [1]. Iterations that

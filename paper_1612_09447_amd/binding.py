@@ -115,6 +115,7 @@ _SIGNATURES = {
     "eqs_set_dirichlet": ([_P, C.c_int64, _P, _P, C.c_int32, _P], C.c_int),
     "eqs_build_preconditioner": ([_P, _P], C.c_int),
     "eqs_set_graph_iters": ([_P, C.c_int32], C.c_int),
+    "eqs_set_deterministic": ([_P, C.c_int32], C.c_int),
     "eqs_get_info": ([_P, _P], C.c_int),
     "eqs_query": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "eqs_set_workspace": ([_P, _P, C.c_int64], C.c_int),
@@ -291,8 +292,14 @@ class Context:
         """CG iterations replayed per captured graph launch (1 .. EQS_MAX_GRAPH_ITERS)."""
         _check(lib().eqs_set_graph_iters(self._h, int(iters)), "eqs_set_graph_iters")
 
-    def setup_case(self, case, precision=None, **amg):
+    def set_deterministic(self, on=True):
+        """Element pass summed in a fixed order (bitwise reproducible); before the build."""
+        _check(lib().eqs_set_deterministic(self._h, 1 if on else 0), "eqs_set_deterministic")
+
+    def setup_case(self, case, precision=None, deterministic=None, **amg):
         """Hand a ``eqsgen.Case`` to the library (mesh, materials, Dirichlet, AMG)."""
+        if deterministic is not None:
+            self.set_deterministic(deterministic)
         self.set_mesh(case.xyz, case.tets)
         self.set_materials(case.eps_r, case.kappa0, case.e_s, case.alpha, case.nonlinear, case.tet_mat)
         self.set_dirichlet(case.dir_nodes, case.dir_drive, case.amp, case.freq, case.phase)

@@ -243,6 +243,17 @@ int eqs_set_dirichlet(eqs_ctx* c, int64_t n_d, const int32_t* nodes, const int32
     });
 }
 
+int eqs_set_deterministic(eqs_ctx* c, int32_t on) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        need(on == 0 || on == 1, "on must be 0 or 1");
+        if (c->built && c->deterministic != (on != 0))
+            fail(EQS_ERR_STATE, "set the deterministic element pass before eqs_build_preconditioner");
+        c->deterministic = on != 0;
+        return EQS_OK;
+    });
+}
+
 int eqs_set_graph_iters(eqs_ctx* c, int32_t iters) {
     return guarded([&] {
         need(c != nullptr, "ctx is NULL");
@@ -635,7 +646,7 @@ int eqs_describe(const eqs_ctx* c, char* buf, int64_t cap, int64_t* needed) {
                       "element blocks %lld of %d tets, block nodes %lld (max %d), graphs %d, autotune %d%s\n",
                       (long long)c->n_blocks, eqs::kTetBlock * c->tet_tpt, (long long)c->n_block_nodes,
                       c->max_block_nodes, (int)c->use_graphs, (int)c->autotune,
-                      c->kx_generic ? ", per-block LDS stride" : "");
+                      c->kx_generic ? ", per-block LDS stride" : c->deterministic ? ", deterministic sums" : "");
         d += line;
         d += c->tune_log;
         if (needed) *needed = (int64_t)d.size() + 1;

@@ -260,6 +260,16 @@ struct eqs_ctx {
     int64_t n_blocks = 0;
     int32_t max_block_nodes = 0;
     int32_t tet_tpt = 0;        // tets per thread of the element pass
+    // deterministic element pass (eqs_set_deterministic; see k_kx_det): per
+    // block the slots of every node in slot order, the end of every block
+    // node's list, every node's block-node positions in block order, and the
+    // block partials
+    bool deterministic = false;
+    uint16_t* d_kslots = nullptr;
+    uint16_t* d_kend = nullptr;
+    int32_t* d_occ_off = nullptr;
+    int32_t* d_occ = nullptr;
+    double* d_kx_part = nullptr;
     int64_t n_block_nodes = 0;  // entries of d_bnodes (nodes shared by blocks count once per block)
     double* d_cx = nullptr;
     double* d_cy = nullptr;

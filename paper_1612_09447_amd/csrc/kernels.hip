@@ -402,10 +402,12 @@ __device__ __forceinline__ void kx_records(const KxArgs& A, int64_t b, uint64_t 
 }
 
 // Element matrices of the thread's tets times the staged potentials, added
-// into the LDS accumulator (see the kernel comment for the algebra).
+// into the LDS accumulator (see the kernel comment for the algebra). With
+// contrib (the deterministic pass) the four values of the thread's tet i go
+// to contrib[4 (threadIdx.x TPT + i) + a] instead, each written once.
 template <bool RHS, int TPT, int STRIDE>
 __device__ __forceinline__ void kx_tets(const KxArgs& A, double* lds, int32_t nn, bool has_dir,
-                                        const uint64_t (&rec)[TPT]) {
+                                        const uint64_t (&rec)[TPT], double* contrib = nullptr) {
     const int32_t S = kx_stride<STRIDE>(nn);
     const double* PX = lds;
     const double* PY = PX + S;
@@ -466,10 +468,18 @@ __device__ __forceinline__ void kx_tets(const KxArgs& A, double* lds, int32_t nn
         const double y2 = c2x * wx + c2y * wy + c2z * wz;
         const double y3 = c3x * wx + c3y * wy + c3z * wz;
         const double y0 = -(y1 + y2 + y3);
-        unsafeAtomicAdd(&Acc[l[0]], y0);
-        unsafeAtomicAdd(&Acc[l[1]], y1);
-        unsafeAtomicAdd(&Acc[l[2]], y2);
-        unsafeAtomicAdd(&Acc[l[3]], y3);
+        if (contrib) {
+            double* q = contrib + 4 * ((int64_t)threadIdx.x * TPT + i);
+            q[0] = y0;
+            q[1] = y1;
+            q[2] = y2;
+            q[3] = y3;
+        } else {
+            unsafeAtomicAdd(&Acc[l[0]], y0);
+            unsafeAtomicAdd(&Acc[l[1]], y1);
+            unsafeAtomicAdd(&Acc[l[2]], y2);
+            unsafeAtomicAdd(&Acc[l[3]], y3);
+        }
     }
 }
 
@@ -499,6 +509,50 @@ __global__ __launch_bounds__(kTetBlock, 6) void k_kx(KxArgs A) {
     kx_tets<RHS, TPT, STRIDE>(A, lds, nn, has_dir, rec);
     __syncthreads();
     kx_scatter<RHS, STRIDE>(A, lds, off, nn);
+}
+
+// Deterministic element pass (eqs_set_deterministic): the same arithmetic,
+// summed in an order fixed at set-up instead of the order in which atomics
+// land. Each tet writes its four contributions to its own LDS slots
+// (4 t + a for block-local tet t, vertex a); each block node then sums its
+// slots in increasing slot order (lists built on the host: d_kslots holds,
+// block after block in the record layout, the slots of node 0, node 1, ...;
+// d_kend[boff[b] + k] ends node k's list) and stores the block's partial
+// without atomics; k_kx_gather sums every node's partials in block order. Run
+// to run the result is the same bit for bit.
+template <bool RHS, int TPT, int STRIDE>
+__global__ __launch_bounds__(kTetBlock) void k_kx_det(KxArgs A, const uint16_t* __restrict__ kslots,
+                                                      const uint16_t* __restrict__ kend,
+                                                      double* __restrict__ part) {
+    extern __shared__ double lds[];
+    const int64_t b = xcd_block(blockIdx.x, A.n_blocks);
+    uint64_t rec[TPT];
+    kx_records<TPT>(A, b, rec);
+    const int32_t off = A.boff[b];
+    const int32_t nn = A.boff[b + 1] - off;
+    const bool has_dir = kx_stage<RHS, STRIDE>(A, lds, off, nn);
+    double* contrib = lds + 6 * kx_stride<STRIDE>(nn);
+    __syncthreads();
+    kx_tets<RHS, TPT, STRIDE>(A, lds, nn, has_dir, rec, contrib);
+    __syncthreads();
+    const uint16_t* sl = kslots + b * (int64_t)(4 * kTetBlock * TPT);
+    for (int k = threadIdx.x; k < nn; k += kTetBlock) {
+        const int32_t beg = k ? (int32_t)kend[off + k - 1] : 0, end = kend[off + k];
+        double v = 0.0;
+        for (int32_t j = beg; j < end; ++j) v += contrib[sl[j]];
+        part[off + k] = v;
+    }
+}
+
+// out[i] = sum of node i's block partials in block order (occ lists, built at
+// set-up); RHS mode covers the free nodes only.
+__global__ void k_kx_gather(const int32_t* __restrict__ occ_off, const int32_t* __restrict__ occ,
+                            const double* __restrict__ part, double* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = 0.0;
+    for (int32_t j = occ_off[i]; j < occ_off[i + 1]; ++j) v += part[occ[j]];
+    out[i] = v;
 }
 
 // ------------------------------------------------ second-order tets (P2)
@@ -741,6 +795,31 @@ static void launch_kx_t(hipStream_t s, eqs_ctx* c, const double* yfree, double t
     }
     const bool fixed = tpt >= 1 && c->max_block_nodes <= kx_fixed_stride(tpt) && !c->kx_generic;
     const size_t lds = sizeof(double) * 6 * (size_t)(fixed ? kx_fixed_stride(tpt) : c->max_block_nodes);
+    if (c->deterministic) {
+        if (!c->d_kslots) fail(EQS_ERR_STATE, "deterministic element pass without its lists");
+        const size_t ldsd = lds + sizeof(double) * 4 * (size_t)(kTetBlock * tpt);
+#define EQS_KXD(TPT_)                                                                                            \
+    do {                                                                                                         \
+        if (fixed)                                                                                               \
+            EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx_det<RHS, TPT_, kx_fixed_stride(TPT_)>), g, b, ldsd, s, A, \
+                             c->d_kslots, c->d_kend, c->d_kx_part);                                              \
+        else                                                                                                     \
+            EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx_det<RHS, TPT_, 0>), g, b, ldsd, s, A, c->d_kslots,     \
+                             c->d_kend, c->d_kx_part);                                                           \
+    } while (0)
+        switch (tpt) {
+            case 1: EQS_KXD(1); break;
+            case 2: EQS_KXD(2); break;
+            case 4: EQS_KXD(4); break;
+            case 8: EQS_KXD(8); break;
+            default: fail(EQS_ERR_STATE, "element blocks not built");
+        }
+#undef EQS_KXD
+        const int64_t nout = RHS ? c->n_free : c->n_nodes;
+        hipLaunchKernelGGL(k_kx_gather, dim3(grid_for(nout)), dim3(kBlock), 0, s, c->d_occ_off, c->d_occ,
+                           (const double*)c->d_kx_part, out, nout);
+        return;
+    }
 #define EQS_KX(TPT_)                                                                                           \
     do {                                                                                                       \
         if (fixed) EQS_LAUNCH_TIMED(c, EQS_KCLASS_ELEMENT, (k_kx<RHS, TPT_, kx_fixed_stride(TPT_)>), g, b, lds, s, A); \

@@ -627,6 +627,11 @@ static void visit_hierarchy(Hierarchy<T>& h, const std::function<void(void**)>& 
 
 void visit_device_ptrs(eqs_ctx* c, const std::function<void(void**)>& f) {
     f((void**)&c->d_tpack);
+    f((void**)&c->d_kslots);
+    f((void**)&c->d_kend);
+    f((void**)&c->d_occ_off);
+    f((void**)&c->d_occ);
+    f((void**)&c->d_kx_part);
     f((void**)&c->d_bnodes);
     f((void**)&c->d_boff);
     f((void**)&c->d_cx);
@@ -1368,8 +1373,51 @@ static ElementBlocks element_blocks(const eqs_ctx* c, const std::vector<int32_t>
     return eb;
 }
 
+// Lists of the deterministic element pass (k_kx_det, k_kx_gather) from the
+// blocks: slot 4 t + a is vertex a of the block's record t; a node's slots and
+// a node's block occurrences are listed in increasing order (counting sorts).
+static void install_det_lists(eqs_ctx* c, const ElementBlocks& eb, int tpt) {
+    const int64_t nb = c->n_blocks, per = (int64_t)kTetBlock * tpt, NB = (int64_t)eb.bnodes.size();
+    std::vector<uint16_t> kslots((size_t)(nb * per * 4), 0), kend((size_t)NB, 0);
+    std::vector<int32_t> pos;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int32_t off = eb.boff[b], nn = eb.boff[b + 1] - off;
+        pos.assign((size_t)nn + 1, 0);
+        for (int64_t t = 0; t < per; ++t) {
+            const uint64_t w = eb.pack[(size_t)(b * per + t)];
+            if (w == ~0ull) continue;
+            for (int a = 0; a < 4; ++a) pos[((w >> (16 + 12 * a)) & 0xfffu) + 1]++;
+        }
+        for (int32_t k = 0; k < nn; ++k) {
+            pos[k + 1] += pos[k];
+            kend[(size_t)(off + k)] = (uint16_t)pos[k + 1];
+        }
+        uint16_t* sl = kslots.data() + b * per * 4;
+        for (int64_t t = 0; t < per; ++t) {
+            const uint64_t w = eb.pack[(size_t)(b * per + t)];
+            if (w == ~0ull) continue;
+            for (int a = 0; a < 4; ++a) sl[pos[(w >> (16 + 12 * a)) & 0xfffu]++] = (uint16_t)(4 * t + a);
+        }
+    }
+    std::vector<int32_t> occ_off((size_t)c->n_nodes + 1, 0), occ((size_t)NB);
+    for (int64_t p = 0; p < NB; ++p) occ_off[(size_t)eb.bnodes[p] + 1]++;
+    for (int64_t i = 0; i < c->n_nodes; ++i) occ_off[i + 1] += occ_off[i];
+    std::vector<int32_t> fill(occ_off.begin(), occ_off.end() - 1);
+    for (int64_t p = 0; p < NB; ++p) occ[(size_t)fill[eb.bnodes[p]]++] = (int32_t)p;
+    c->d_kslots = upload_vec(c, kslots);
+    c->d_kend = upload_vec(c, kend);
+    c->d_occ_off = upload_vec(c, occ_off);
+    c->d_occ = upload_vec(c, occ);
+    c->d_kx_part = (double*)dev_alloc(c, sizeof(double) * (size_t)std::max<int64_t>(NB, 1));
+}
+
 static void install_blocks(eqs_ctx* c, const ElementBlocks& eb, int tpt) {
     if (c->d_tpack) { dev_free(c, c->d_tpack); dev_free(c, c->d_bnodes); dev_free(c, c->d_boff); }
+    if (c->d_kslots) {
+        for (void* q : {(void*)c->d_kslots, (void*)c->d_kend, (void*)c->d_occ_off, (void*)c->d_occ, (void*)c->d_kx_part})
+            dev_free(c, q);
+        c->d_kslots = nullptr; c->d_kend = nullptr; c->d_occ_off = nullptr; c->d_occ = nullptr; c->d_kx_part = nullptr;
+    }
     c->n_blocks = (int64_t)eb.boff.size() - 1;
     c->max_block_nodes = eb.max_nodes;
     c->n_block_nodes = (int64_t)eb.bnodes.size();
@@ -1377,6 +1425,10 @@ static void install_blocks(eqs_ctx* c, const ElementBlocks& eb, int tpt) {
     c->d_tpack = upload_vec(c, eb.pack);
     c->d_bnodes = upload_vec(c, eb.bnodes);
     c->d_boff = upload_vec(c, eb.boff);
+    if (c->deterministic) {
+        if (c->npe != 4) fail(EQS_ERR_INVALID_ARG, "the deterministic element pass is built for first-order tets");
+        install_det_lists(c, eb, tpt);
+    }
 }
 
 // Blocks of 256 tets per workgroup trade LDS reuse (each block re-reads the
@@ -1551,6 +1603,7 @@ void free_device(eqs_ctx* c) {
     c->h64.lv.clear();
     c->h32.lv.clear();
     c->d_tpack = nullptr; c->d_bnodes = nullptr; c->d_boff = nullptr; c->n_blocks = 0; c->max_block_nodes = 0; c->n_block_nodes = 0;
+    c->d_kslots = nullptr; c->d_kend = nullptr; c->d_occ_off = nullptr; c->d_occ = nullptr; c->d_kx_part = nullptr;
     c->d_cx = c->d_cy = c->d_cz = nullptr; c->d_mats = nullptr; c->tet_tpt = 0;
     c->d_ddrive = nullptr; c->d_int_to_user = nullptr; c->d_drives = nullptr;
     c->d_r = c->d_z = c->d_p = c->d_q = c->d_mx = nullptr;

@@ -11,9 +11,21 @@
 #include <cmath>
 #include <functional>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "eqs_internal.h"
 
 namespace eqs {
+
+// Host-side ranges for tracing tools (rocprofv3 --marker-trace): an RKC step,
+// each stage, each CG solve, each adaptive attempt. Without a tool attached
+// a push or pop is a cheap call.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 static PcgSummary read_summary(eqs_ctx* c) {
     const volatile PcgSummary* h = c->h_sum;
@@ -79,6 +91,7 @@ void release_graphs(eqs_ctx* c) {
 // max relres; per-instance results are in c->inst_iters / c->inst_relres.
 int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit, eqs_solve_stats* st,
             const double* mx_in, double* mx_out, const std::function<void()>* before_sync) {
+    const Range range("eqs: CG solve of M");
     hipStream_t s = c->stream;
     const int prec = c->amg.precision;
     pcg_init(s, c, rhs, y, maxit, rtol, c->amg.flexible, mx_in);
@@ -183,6 +196,7 @@ void apply_preconditioner(eqs_ctx* c, const double* r, double* z) {
 
 int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double rtol, int32_t maxit,
              eqs_step_stats* st) {
+    const Range range("eqs: RKC step");
     std::vector<double> mu, nu, mut, gmt, cc;
     rkc_coefficients(s, mu, nu, mut, gmt, cc);
     hipStream_t q = c->stream;
@@ -213,6 +227,7 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
     const bool early = c->guess.p.kind == EQS_GUESS_PREVIOUS;
     double* const ybuf[3] = {c->d_Ya, c->d_Yb, c->d_Yc};
     for (int j = 0; j < s; ++j) {
+        const Range stage("eqs: RKC stage");
         const double tj = t + cc[j] * dt;
         if (!rhs_ready) launch_kx(q, true, c, Ycur, tj, c->d_rhs, rhs_zeroed);
         check_launch();
@@ -298,6 +313,7 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
 // Returns the buffer holding Y_s; solve statistics go to S.
 static const double* rkc_attempt(eqs_ctx* c, double t, double dt, int s, double rtol, int32_t maxit,
                                  eqs_step_stats& S, int& rc) {
+    const Range range("eqs: adaptive RKC attempt");
     std::vector<double> mu, nu, mut, gmt, cc;
     rkc_coefficients(s, mu, nu, mut, gmt, cc);
     hipStream_t q = c->stream;

@@ -132,6 +132,7 @@ def test_error_paths_without_device():
     assert b"NULL" in L.eqs_last_error()
     assert L.eqs_set_graph_iters(None, 4) == binding.EQS_ERR_INVALID_ARG
     assert L.eqs_batch_set_graph_iters(None, 4) == binding.EQS_ERR_INVALID_ARG
+    assert L.eqs_set_deterministic(None, 1) == binding.EQS_ERR_INVALID_ARG
     with pytest.raises(pkg.EqsError) as ei:
         pkg.Context(0)
     assert ei.value.code == binding.EQS_ERR_HIP
