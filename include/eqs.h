@@ -169,6 +169,27 @@ int eqs_set_materials(eqs_ctx *ctx, int32_t n_mat, const eqs_material *mats, con
 int eqs_set_dirichlet(eqs_ctx *ctx, int64_t n_d, const int32_t *nodes, const int32_t *drive_id,
                       int32_t n_drive, const eqs_drive *drives);
 
+/* Checkpoint and resume of a run (the state the RKC steps of Sec. II carry
+ * from one step to the next inside the context). Between steps, the state of
+ * a built context - the last stage solution F (the next step's first start
+ * vector, Sec. IV) and its M-product, the start-vector window with its
+ * reduced matrices, the network's weights and Adam moments, its replay buffer
+ * and sampling counter - is written to a host buffer the caller owns;
+ * eqs_state_load restores it into a context built from the same mesh,
+ * materials, Dirichlet data, instances and precision and given the same
+ * eqs_set_guess settings, so that the run continues as if it had not stopped
+ * (bit for bit with eqs_set_deterministic). The potentials themselves are the
+ * caller's (x of eqs_rkc_step). eqs_state_size gives the bytes a save needs
+ * (at 2.1 M free DOF: 34 MB, plus 16 window vectors of 17 MB each with an
+ * estimator start vector); save fails with EQS_ERR_INVALID_ARG if `bytes` is
+ * smaller; load fails with EQS_ERR_INVALID_ARG if the buffer is not a
+ * checkpoint of such a context (after a failed load the run state may be
+ * partly overwritten: load a valid checkpoint, or call eqs_set_guess, before
+ * the next step). All three synchronise the context's streams. */
+int eqs_state_size(eqs_ctx *ctx, int64_t *bytes);
+int eqs_state_save(eqs_ctx *ctx, void *host_buf, int64_t bytes);
+int eqs_state_load(eqs_ctx *ctx, const void *host_buf, int64_t bytes);
+
 /* Deterministic element pass (the fused K(x)x of Sec. III): with on = 1 the
  * element contributions are summed in an order fixed at set-up (each tet
  * writes its four values to slots of its block; every block node sums its

@@ -116,6 +116,9 @@ _SIGNATURES = {
     "eqs_build_preconditioner": ([_P, _P], C.c_int),
     "eqs_set_graph_iters": ([_P, C.c_int32], C.c_int),
     "eqs_set_deterministic": ([_P, C.c_int32], C.c_int),
+    "eqs_state_size": ([_P, C.POINTER(C.c_int64)], C.c_int),
+    "eqs_state_save": ([_P, _P, C.c_int64], C.c_int),
+    "eqs_state_load": ([_P, _P, C.c_int64], C.c_int),
     "eqs_get_info": ([_P, _P], C.c_int),
     "eqs_query": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "eqs_set_workspace": ([_P, _P, C.c_int64], C.c_int),
@@ -291,6 +294,19 @@ class Context:
     def set_graph_iters(self, iters):
         """CG iterations replayed per captured graph launch (1 .. EQS_MAX_GRAPH_ITERS)."""
         _check(lib().eqs_set_graph_iters(self._h, int(iters)), "eqs_set_graph_iters")
+
+    def state_save(self) -> bytes:
+        """Checkpoint of the context's run state (eqs_state_save) as bytes."""
+        n = C.c_int64(0)
+        _check(lib().eqs_state_size(self._h, C.byref(n)), "eqs_state_size")
+        buf = (C.c_char * max(1, n.value))()
+        _check(lib().eqs_state_save(self._h, C.cast(buf, _P), n.value), "eqs_state_save")
+        return bytes(buf[: n.value])
+
+    def state_load(self, data: bytes):
+        """Restore a checkpoint written by state_save (eqs_state_load)."""
+        buf = C.create_string_buffer(bytes(data), max(1, len(data)))
+        _check(lib().eqs_state_load(self._h, C.cast(buf, _P), len(data)), "eqs_state_load")
 
     def set_deterministic(self, on=True):
         """Element pass summed in a fixed order (bitwise reproducible); before the build."""

@@ -243,6 +243,86 @@ int eqs_set_dirichlet(eqs_ctx* c, int64_t n_d, const int32_t* nodes, const int32
     });
 }
 
+}  // extern "C"
+
+namespace {
+// Checkpoint layout: magic, version, the set-up's fingerprint, the step-level
+// state (the last stage solution and its M-product), the start-vector state.
+constexpr uint64_t kStateMagic = 0x3154504b43535145ull;  // "EQSCKPT1"
+constexpr int32_t kStateVersion = 1;
+
+void state_stream(eqs_ctx* c, eqs::StateWriter& w) {
+    EQS_HIP(hipStreamSynchronize(c->stream));
+    w.s = c->stream;
+    const eqs_guess_params& g = c->guess.p;
+    w.val(kStateMagic);
+    w.val(kStateVersion);
+    for (int64_t v : {c->n_nodes, c->n_tets, c->n_free, (int64_t)c->npe, c->nnz_M, (int64_t)c->amg.precision,
+                      c->n_inst, (int64_t)g.kind, (int64_t)g.window, (int64_t)g.capacity, (int64_t)g.bf16})
+        w.val(v);
+    w.val((int32_t)c->have_Flast);
+    w.val((int32_t)c->mx_of_F);
+    w.dev(c->d_F, c->have_Flast ? (int64_t)sizeof(double) * c->n_free : 0);
+    w.dev(c->d_mx, c->mx_of_F ? (int64_t)sizeof(double) * c->n_free : 0);
+    eqs::guess_save_state(c, w);
+}
+}  // namespace
+
+extern "C" {
+
+int eqs_state_size(eqs_ctx* c, int64_t* bytes) {
+    return guarded([&] {
+        need(c != nullptr && bytes != nullptr, "NULL argument");
+        need_built(c);
+        bind_device(c);
+        eqs::StateWriter w;  // counting only
+        state_stream(c, w);
+        *bytes = w.n;
+        return EQS_OK;
+    });
+}
+
+int eqs_state_save(eqs_ctx* c, void* buf, int64_t bytes) {
+    return guarded([&] {
+        need(c != nullptr && buf != nullptr, "NULL argument");
+        need_built(c);
+        bind_device(c);
+        eqs::StateWriter w;
+        w.buf = static_cast<char*>(buf);
+        w.cap = bytes;
+        state_stream(c, w);
+        return EQS_OK;
+    });
+}
+
+int eqs_state_load(eqs_ctx* c, const void* buf, int64_t bytes) {
+    return guarded([&] {
+        need(c != nullptr && buf != nullptr, "NULL argument");
+        need_built(c);
+        bind_device(c);
+        EQS_HIP(hipStreamSynchronize(c->stream));
+        eqs::StateReader r;
+        r.buf = static_cast<const char*>(buf);
+        r.cap = bytes;
+        r.s = c->stream;
+        const eqs_guess_params& g = c->guess.p;
+        if (r.val<uint64_t>() != kStateMagic || r.val<int32_t>() != kStateVersion)
+            eqs::fail(EQS_ERR_INVALID_ARG, "not a checkpoint of this library version");
+        for (int64_t v : {c->n_nodes, c->n_tets, c->n_free, (int64_t)c->npe, c->nnz_M, (int64_t)c->amg.precision,
+                          c->n_inst, (int64_t)g.kind, (int64_t)g.window, (int64_t)g.capacity, (int64_t)g.bf16})
+            if (r.val<int64_t>() != v)
+                eqs::fail(EQS_ERR_INVALID_ARG, "checkpoint of another set-up or start-vector setting");
+        const bool have_F = r.val<int32_t>() != 0, have_mx = r.val<int32_t>() != 0;
+        r.dev(c->d_F, have_F ? (int64_t)sizeof(double) * c->n_free : 0);
+        r.dev(c->d_mx, have_mx ? (int64_t)sizeof(double) * c->n_free : 0);
+        eqs::guess_load_state(c, r);
+        if (r.n != bytes) eqs::fail(EQS_ERR_INVALID_ARG, "state buffer longer than its checkpoint");
+        c->have_Flast = have_F;
+        c->mx_of_F = have_mx;
+        return EQS_OK;
+    });
+}
+
 int eqs_set_deterministic(eqs_ctx* c, int32_t on) {
     return guarded([&] {
         need(c != nullptr, "ctx is NULL");

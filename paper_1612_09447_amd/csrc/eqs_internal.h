@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <functional>
 #include <map>
@@ -453,6 +454,9 @@ void mlp_forward(eqs_mlp* n, const float* x, float* y, int32_t B);
 void mlp_train(eqs_mlp* n, const float* x, const float* t, int32_t B);
 float mlp_last_loss(eqs_mlp* n);
 void mlp_get(eqs_mlp* n, float* params, float* grad);
+int64_t mlp_state_bytes();
+void mlp_save_state(eqs_mlp* n, void* host);
+void mlp_load_state(eqs_mlp* n, const void* host);
 void mlp_forward_coeffs(eqs_mlp* n, hipStream_t s, const float* x, const double* P, const double* bias,
                         double* alpha, const double* guard, int32_t* stat);
 
@@ -472,6 +476,68 @@ void guess_after_solve(eqs_ctx* c, int32_t iters);
 void guess_train(eqs_ctx* c);
 double guess_last_loss(eqs_ctx* c);
 void guess_device_stats(eqs_ctx* c, int32_t* kept, int32_t* dropped);
+
+// Byte stream of a checkpoint (eqs_state_save / eqs_state_load). With a NULL
+// buffer it only counts; device ranges are copied on the context's stream.
+struct StateWriter {
+    char* buf = nullptr;
+    int64_t cap = 0, n = 0;
+    hipStream_t s = nullptr;
+    void raw(const void* src, int64_t b) {
+        if (buf) {
+            if (n + b > cap) fail(EQS_ERR_INVALID_ARG, "state buffer too small");
+            std::memcpy(buf + n, src, (size_t)b);
+        }
+        n += b;
+    }
+    template <typename T>
+    void val(const T& v) { raw(&v, sizeof v); }
+    template <typename T>
+    void vec(const std::vector<T>& v) {
+        val((int64_t)v.size());
+        raw(v.data(), (int64_t)(sizeof(T) * v.size()));
+    }
+    void dev(const void* d, int64_t b) {
+        if (buf && b > 0) {
+            if (n + b > cap) fail(EQS_ERR_INVALID_ARG, "state buffer too small");
+            EQS_HIP(hipMemcpyAsync(buf + n, d, (size_t)b, hipMemcpyDeviceToHost, s));
+            EQS_HIP(hipStreamSynchronize(s));
+        }
+        n += b;
+    }
+};
+struct StateReader {
+    const char* buf = nullptr;
+    int64_t cap = 0, n = 0;
+    hipStream_t s = nullptr;
+    void raw(void* dst, int64_t b) {
+        if (b < 0 || n + b > cap) fail(EQS_ERR_INVALID_ARG, "state buffer truncated or not a checkpoint of this set-up");
+        std::memcpy(dst, buf + n, (size_t)b);
+        n += b;
+    }
+    template <typename T>
+    T val() {
+        T v;
+        raw(&v, sizeof v);
+        return v;
+    }
+    template <typename T>
+    void vec(std::vector<T>& v, int64_t max_len) {
+        const int64_t k = val<int64_t>();
+        if (k < 0 || k > max_len) fail(EQS_ERR_INVALID_ARG, "state buffer: bad vector length");
+        v.resize((size_t)k);
+        raw(v.data(), (int64_t)(sizeof(T) * v.size()));
+    }
+    void dev(void* d, int64_t b) {
+        if (b <= 0) return;
+        if (n + b > cap) fail(EQS_ERR_INVALID_ARG, "state buffer truncated or not a checkpoint of this set-up");
+        EQS_HIP(hipMemcpyAsync(d, buf + n, (size_t)b, hipMemcpyHostToDevice, s));
+        EQS_HIP(hipStreamSynchronize(s));
+        n += b;
+    }
+};
+void guess_save_state(eqs_ctx* c, StateWriter& w);
+void guess_load_state(eqs_ctx* c, StateReader& r);
 
 // per-kernel timing (profile.cpp)
 void prof_begin(eqs_ctx* c, int cls, hipStream_t s);

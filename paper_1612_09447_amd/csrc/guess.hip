@@ -693,6 +693,100 @@ void guess_train(eqs_ctx* c) {
     g.trained = true;
 }
 
+// Checkpoint of the start-vector state (called between steps, both streams
+// idle): the window's host matrices and bookkeeping, the slots in use, r_{j-1},
+// the pending training pair, the replay buffer and its sampling counter, and
+// the network. Loading needs the same eqs_set_guess settings.
+void guess_save_state(eqs_ctx* c, StateWriter& w) {
+    GuessState& g = c->guess;
+    const int64_t NF = c->n_free;
+    if (g.tstream) EQS_HIP(hipStreamSynchronize(g.tstream));
+    w.val((int32_t)g.dev_ready);
+    if (!g.dev_ready) return;
+    for (int32_t v : {g.count, g.oldest, (int32_t)g.have_prev, g.last_iters, (int32_t)g.frozen, g.mor_m,
+                      (int32_t)g.have_pending, g.pend_m, g.rcount, g.rhead, (int32_t)g.trained})
+        w.val(v);
+    w.val(g.counter);
+    w.val(g.pend_scale);
+    w.val(g.sol_scale);
+    w.val(g.last_loss);
+    w.raw(g.pend_x, sizeof g.pend_x);
+    w.raw(g.pend_a, sizeof g.pend_a);
+    w.vec(g.G);
+    w.vec(g.H);
+    w.vec(g.rdots);
+    w.vec(g.mor_slot);
+    w.vec(g.mor_B);
+    w.vec(g.mor_K);
+    w.vec(g.pend_slot);
+    w.vec(g.pend_B);
+    w.vec(g.rx);
+    w.vec(g.rt);
+    const int used = std::min(g.count, g.p.window);  // physical slots 0..used-1
+    w.dev(g.d_S, (int64_t)sizeof(double) * used * NF);
+    w.dev(g.d_rprev, g.have_prev ? (int64_t)sizeof(double) * NF : 0);
+    const int32_t has_net = g.net ? 1 : 0;
+    w.val(has_net);
+    if (g.net) {
+        std::vector<char> tmp((size_t)mlp_state_bytes());
+        if (w.buf) mlp_save_state(g.net, tmp.data());
+        w.raw(tmp.data(), (int64_t)tmp.size());
+    }
+}
+
+void guess_load_state(eqs_ctx* c, StateReader& r) {
+    GuessState& g = c->guess;
+    const int64_t NF = c->n_free;
+    if (g.tstream) EQS_HIP(hipStreamSynchronize(g.tstream));
+    if (!r.val<int32_t>()) return;  // saved before the first estimator stage
+    if (!g.dev_ready) guess_alloc_device(c);
+    g.count = r.val<int32_t>();
+    g.oldest = r.val<int32_t>();
+    g.have_prev = r.val<int32_t>() != 0;
+    g.last_iters = r.val<int32_t>();
+    g.frozen = r.val<int32_t>() != 0;
+    g.mor_m = r.val<int32_t>();
+    g.have_pending = r.val<int32_t>() != 0;
+    g.pend_m = r.val<int32_t>();
+    g.rcount = r.val<int32_t>();
+    g.rhead = r.val<int32_t>();
+    g.trained = r.val<int32_t>() != 0;
+    g.counter = r.val<uint64_t>();
+    g.pend_scale = r.val<double>();
+    g.sol_scale = r.val<double>();
+    g.last_loss = r.val<double>();
+    r.raw(g.pend_x, sizeof g.pend_x);
+    r.raw(g.pend_a, sizeof g.pend_a);
+    r.vec(g.G, kMaxWin * kMaxWin);
+    r.vec(g.H, kMaxWin * kMaxWin);
+    r.vec(g.rdots, kMaxWin);
+    r.vec(g.mor_slot, kMaxWin);
+    r.vec(g.mor_B, kMaxWin * kMaxWin);
+    r.vec(g.mor_K, kMaxWin * kMaxWin);
+    r.vec(g.pend_slot, kMaxWin);
+    r.vec(g.pend_B, kMaxWin * kMaxWin);
+    r.vec(g.rx, (int64_t)g.p.capacity * 32);
+    r.vec(g.rt, (int64_t)g.p.capacity * 16);
+    if (g.count < 0 || g.count > g.p.window || g.oldest < 0 || g.oldest >= std::max(1, g.p.window) ||
+        g.G.size() != (size_t)kMaxWin * kMaxWin || g.H.size() != (size_t)kMaxWin * kMaxWin ||
+        g.rdots.size() != (size_t)kMaxWin || g.rx.size() != (size_t)g.p.capacity * 32 ||
+        g.rt.size() != (size_t)g.p.capacity * 16 || g.rcount < 0 || g.rcount > g.p.capacity || g.rhead < 0 ||
+        g.rhead >= std::max(1, g.p.capacity))
+        fail(EQS_ERR_INVALID_ARG, "state buffer: start-vector state does not match the context's settings");
+    const int used = std::min(g.count, g.p.window);
+    r.dev(g.d_S, (int64_t)sizeof(double) * used * NF);
+    r.dev(g.d_rprev, g.have_prev ? (int64_t)sizeof(double) * NF : 0);
+    const int32_t has_net = r.val<int32_t>();
+    if (has_net != (g.net ? 1 : 0)) fail(EQS_ERR_INVALID_ARG, "state buffer: network state does not match the settings");
+    if (g.net) {
+        std::vector<char> tmp((size_t)mlp_state_bytes());
+        r.raw(tmp.data(), (int64_t)tmp.size());
+        mlp_load_state(g.net, tmp.data());
+    }
+    g.inf_recorded = g.train_pending = false;
+    EQS_HIP(hipMemset(g.d_gstat, 0, sizeof(int32_t) * 2));
+}
+
 // Network corrections kept / dropped by the device guard since the last call
 // (the stream must be idle); the counters restart at zero.
 void guess_device_stats(eqs_ctx* c, int32_t* kept, int32_t* dropped) {

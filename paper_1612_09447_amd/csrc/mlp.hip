@@ -398,6 +398,30 @@ void mlp_get(eqs_mlp* n, float* params, float* grad) {
     EQS_HIP(hipStreamSynchronize(n->stream));
 }
 
+// Checkpoint of the network: master and matmul weights, Adam moments and
+// state (the gradient is rewritten by every step). Synchronises its stream.
+int64_t mlp_state_bytes() { return (int64_t)(sizeof(float) * 4 * kNParam + sizeof(MlpState)); }
+void mlp_save_state(eqs_mlp* n, void* host) {
+    char* p = static_cast<char*>(host);
+    const size_t b = sizeof(float) * kNParam;
+    for (float* src : {n->master, n->wq, n->m1, n->m2}) {
+        EQS_HIP(hipMemcpyAsync(p, src, b, hipMemcpyDeviceToHost, n->stream));
+        p += b;
+    }
+    EQS_HIP(hipMemcpyAsync(p, n->st, sizeof(MlpState), hipMemcpyDeviceToHost, n->stream));
+    EQS_HIP(hipStreamSynchronize(n->stream));
+}
+void mlp_load_state(eqs_mlp* n, const void* host) {
+    const char* p = static_cast<const char*>(host);
+    const size_t b = sizeof(float) * kNParam;
+    for (float* dst : {n->master, n->wq, n->m1, n->m2}) {
+        EQS_HIP(hipMemcpyAsync(dst, p, b, hipMemcpyHostToDevice, n->stream));
+        p += b;
+    }
+    EQS_HIP(hipMemcpyAsync(n->st, p, sizeof(MlpState), hipMemcpyHostToDevice, n->stream));
+    EQS_HIP(hipStreamSynchronize(n->stream));
+}
+
 float mlp_last_loss(eqs_mlp* n) {
     MlpState s;
     EQS_HIP(hipMemcpyAsync(&s, n->st, sizeof s, hipMemcpyDeviceToHost, n->stream));

@@ -133,6 +133,9 @@ def test_error_paths_without_device():
     assert L.eqs_set_graph_iters(None, 4) == binding.EQS_ERR_INVALID_ARG
     assert L.eqs_batch_set_graph_iters(None, 4) == binding.EQS_ERR_INVALID_ARG
     assert L.eqs_set_deterministic(None, 1) == binding.EQS_ERR_INVALID_ARG
+    assert L.eqs_state_size(None, C.byref(nf)) == binding.EQS_ERR_INVALID_ARG
+    assert L.eqs_state_save(None, None, 0) == binding.EQS_ERR_INVALID_ARG
+    assert L.eqs_state_load(None, None, 0) == binding.EQS_ERR_INVALID_ARG
     with pytest.raises(pkg.EqsError) as ei:
         pkg.Context(0)
     assert ei.value.code == binding.EQS_ERR_HIP
