@@ -196,7 +196,8 @@ int eqs_state_load(eqs_ctx *ctx, const void *host_buf, int64_t bytes);
  * slots in order; every node sums its blocks' partials in block order)
  * instead of by floating-point atomics, so K(x)x, the stage right-hand side
  * and therefore whole RKC trajectories are the same bit for bit from run to
- * run. It costs about 160 MB of lists and partials at 12.6 M tets and extra
+ * run (across separately built contexts when they use the same operator
+ * layouts: EQS_TUNE_FILE or EQS_AUTOTUNE=0 fix those). It costs about 160 MB of lists and partials at 12.6 M tets and extra
  * memory traffic per pass. First-order tets only. Must be set before
  * eqs_build_preconditioner (EQS_ERR_STATE afterwards if it would change);
  * [0]. */
