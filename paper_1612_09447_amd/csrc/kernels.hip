@@ -198,10 +198,14 @@ __device__ __forceinline__ void for_each_instance_sum(const double* const (&part
                 const int32_t first = b0 + 1, n = b1 - b0;  // blocks first..b1 read their first partial
                 const int32_t lo = first + (int32_t)(((int64_t)n * sub) / wpi);
                 const int32_t hi = first + (int32_t)(((int64_t)n * (sub + 1)) / wpi) - 1;
+                // the head block's partial is loaded with the range's, not after it
+                double hv[NP];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) hv[p] = sub == 0 ? parts[p][2 * (int64_t)b0 + head] : 0.0;
                 wave_range_sums<NP>(parts, lo, hi, v);
                 if (sub == 0)
 #pragma unroll
-                    for (int p = 0; p < NP; ++p) v[p] += parts[p][2 * (int64_t)b0 + head];
+                    for (int p = 0; p < NP; ++p) v[p] += hv[p];
             }
         }
         if (lane == 0)
@@ -227,9 +231,12 @@ __device__ __forceinline__ void for_each_instance_sum(const double* const (&part
 #pragma unroll
             for (int p = 0; p < NP; ++p) sums[p] = 0.0;
             if (b1 >= b0) {
+                double hv[NP];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) hv[p] = parts[p][2 * (int64_t)b0 + head];
                 wave_range_sums<NP>(parts, b0 + 1, b1, sums);
 #pragma unroll
-                for (int p = 0; p < NP; ++p) sums[p] += parts[p][2 * (int64_t)b0 + head];
+                for (int p = 0; p < NP; ++p) sums[p] += hv[p];
             }
             if (lane == 0) body(i, sums);
         }
