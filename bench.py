@@ -170,14 +170,15 @@ def cpu_model():
 
 
 # kernel classes timed one launch at a time (each launch is one kernel)
-SINGLE_KERNEL_CLASSES = ("element", "spmv_M", "presmooth0", "postsmooth0", "restrict0", "prolong0", "cg_update",
-                         "rkc_combine")
+SINGLE_KERNEL_CLASSES = ("element", "spmv_M", "presmooth0", "postsmooth0", "restrict0", "prolong0", "postsmooth1",
+                         "cg_update", "rkc_combine")
 # classes spanning several kernels (bracketed by events on the stream)
 MULTI_KERNEL_CLASSES = ("vcycle", "vcoarse", "finalise")
 ALL_CLASSES = SINGLE_KERNEL_CLASSES + MULTI_KERNEL_CLASSES
 KERNEL_NAMES = {"element": "k_kx<true> (element pass)", "spmv_M": "k_pcg_spmv", "presmooth0": "k_presmooth_res (finest)",
                 "postsmooth0": "k_postsmooth (finest)", "restrict0": "k_restrict (finest level, R0)",
-                "prolong0": "k_prolong (finest level, P0)", "cg_update": "k_pcg_update",
+                "prolong0": "k_prolong (finest level, P0)", "postsmooth1": "k_postsmooth (level 1)",
+                "cg_update": "k_pcg_update",
                 "rkc_combine": "k_rkc_first / k_rkc_combine"}
 
 
@@ -207,6 +208,10 @@ def class_bytes(info, s_stages):
         n1 = rows[1]
         out["restrict0"] = (w + 4) * rn[0] + 4 * (n1 + 1) + w * n0 + w * n1  # R0, res read, b_1 written
         out["prolong0"] = (w + 4) * pn[0] + 4 * (n0 + 1) + w * n1 + 2 * w * n0  # P0, x_1 read, x_0 updated
+    if len(rows) > 2:
+        n1 = rows[1]
+        # level 1: out = x + w D^-1 (b - A x): operator, x gathered, dinv, b, out (hierarchy precision)
+        out["postsmooth1"] = (w + 4) * nnz[1] + 4 * (n1 // 64 + 1) + n1 * 4 * w
     return out
 
 

@@ -496,7 +496,8 @@ enum {
     EQS_KCLASS_PROLONG0 = 8,    /* finest prolongation x_0 += P_0 x_1 (one product) */
     EQS_KCLASS_VCOARSE = 9,     /* all V-cycle work below the finest level (several kernels) */
     EQS_KCLASS_FINALISE = 10,   /* the one-block CG finalisers (three launches per iteration) */
-    EQS_KCLASS_COUNT = 11
+    EQS_KCLASS_POSTSMOOTH1 = 11, /* level-1 Jacobi post-smoothing (when level 1 is not folded) */
+    EQS_KCLASS_COUNT = 12
 };
 
 /* Enable timing of the classes whose bits are set in class_mask (bit k =

@@ -164,6 +164,7 @@ KCLASS = {
     "prolong0": 8,
     "vcoarse": 9,
     "finalise": 10,
+    "postsmooth1": 11,
 }
 
 _lib = None

@@ -1260,22 +1260,24 @@ static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, con
     }
 }
 
-// Post-smoothing of a coarse level (no dot products).
+// Post-smoothing of a coarse level (no dot products), timed as kernel class
+// `cls` when that class is profiled.
 template <typename T>
-static void launch_postsmooth(hipStream_t s, const Level<T>& lv, const T* b, const T* x, T* out, const int32_t* stop) {
+static void launch_postsmooth(hipStream_t s, eqs_ctx* c, int cls, const Level<T>& lv, const T* b, const T* x, T* out,
+                              const int32_t* stop) {
     if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
     if (lv.A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
                               EQS_UNROLL_SWITCH(lv.A.sell.unroll,
-                                                hipLaunchKernelGGL((k_postsmooth<L_, T, T, T, false, U_>),
-                                                                   dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
-                                                                   view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, b,
-                                                                   x, out, InstMap{nullptr, nullptr, 0, -1}, nullptr,
-                                                                   nullptr, stop)));
+                                                EQS_LAUNCH_TIMED(c, cls, (k_postsmooth<L_, T, T, T, false, U_>),
+                                                                 dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
+                                                                 view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, b,
+                                                                 x, out, InstMap{nullptr, nullptr, 0, -1}, nullptr,
+                                                                 nullptr, stop)));
     } else {
-        EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_postsmooth<L_, T, T, T>), dim3(csr_grid(lv.A)),
-                                                        dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
-                                                        (T)lv.omega, b, x, out, stop));
+        EQS_LANES_SWITCH(lv.A.lanes, EQS_LAUNCH_TIMED(c, cls, (k_csr_postsmooth<L_, T, T, T>), dim3(csr_grid(lv.A)),
+                                                      dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
+                                                      (T)lv.omega, b, x, out, stop));
     }
 }
 
@@ -1451,7 +1453,8 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         else
             launch_mv<T>(s, lv.P, xc, lv.x, 1, stop, MvInit<T>{nullptr, nullptr, T(0)}, MV_PROLONG);
         if (l > 0) {
-            launch_postsmooth<T>(s, lv, (const T*)lv.b, (const T*)lv.x, lv.xs, stop);
+            launch_postsmooth<T>(s, c, l == 1 ? EQS_KCLASS_POSTSMOOTH1 : -1, lv, (const T*)lv.b, (const T*)lv.x,
+                                 lv.xs, stop);
         } else {
             // the finest operator is always SELL-64 (see tuned_spmat)
             if (part_rz)

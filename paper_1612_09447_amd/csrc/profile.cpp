@@ -19,7 +19,7 @@ void prof_begin(eqs_ctx* c, int cls, hipStream_t s) {
 }
 
 bool prof_pair(eqs_ctx* c, int cls, hipEvent_t* e0, hipEvent_t* e1) {
-    if (!(c->prof_mask & (1u << cls))) return false;
+    if (cls < 0 || !(c->prof_mask & (1u << cls))) return false;  // cls < 0: a launch that is never timed
     std::vector<hipEvent_t>& ev = c->prof_ev[cls];
     const size_t need = 2 * (size_t)(c->prof_used[cls] + 1);
     while (ev.size() < need) {

@@ -51,6 +51,7 @@ static void run_iteration(eqs_ctx* c, double* x, int prec) {
                                   (1u << EQS_KCLASS_POSTSMOOTH0) | (1u << EQS_KCLASS_VCYCLE) |
                                   (1u << EQS_KCLASS_CG_UPDATE) | (1u << EQS_KCLASS_RESTRICT0) |
                                   (1u << EQS_KCLASS_PROLONG0) | (1u << EQS_KCLASS_VCOARSE) |
+                                  (1u << EQS_KCLASS_POSTSMOOTH1) |
                                   (1u << EQS_KCLASS_FINALISE);
     const int G = c->graph_iters;
     if (!c->use_graphs || c->stream == nullptr || (c->prof_mask & iter_classes)) {
@@ -150,7 +151,8 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
             const int32_t it_now = read_summary(c).max_it;
             const int64_t worked = std::max<int64_t>(0, it_now - it_before);
             for (int k : {EQS_KCLASS_SPMV_M, EQS_KCLASS_PRESMOOTH0, EQS_KCLASS_POSTSMOOTH0, EQS_KCLASS_VCYCLE,
-                          EQS_KCLASS_CG_UPDATE, EQS_KCLASS_RESTRICT0, EQS_KCLASS_PROLONG0, EQS_KCLASS_VCOARSE})
+                          EQS_KCLASS_CG_UPDATE, EQS_KCLASS_RESTRICT0, EQS_KCLASS_PROLONG0, EQS_KCLASS_VCOARSE,
+                          EQS_KCLASS_POSTSMOOTH1})
                 c->prof_used[k] = std::min(c->prof_used[k], used0[k] + worked);
             // three finalisers per iteration
             c->prof_used[EQS_KCLASS_FINALISE] =

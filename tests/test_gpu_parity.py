@@ -356,10 +356,12 @@ def test_profile_counts_launches_that_worked():
     """Kernel-class timing: one element pass and one combination per stage,
     one launch of each CG-iteration class per iteration that did work (the
     launches enqueued after convergence return at entry and are not counted)."""
-    case = inclusion_case(24, 4)  # three levels: the finest restriction is a product of its own
+    # four levels or more: the finest restriction is a product of its own and
+    # level 1 smooths on its own (not folded into the coarse tail)
+    case = inclusion_case(24, 4)
     classes = ("element", "spmv_M", "presmooth0", "postsmooth0", "vcycle", "cg_update", "rkc_combine",
-               "restrict0", "prolong0", "vcoarse", "finalise")
-    with ctx_for(case, precision=EQS_PREC_FP32) as c:
+               "restrict0", "prolong0", "vcoarse", "finalise", "postsmooth1")
+    with ctx_for(case, precision=EQS_PREC_FP32, coarse_max=32) as c:
         x = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
         c.rkc_step(0.0, case.tau, case.s, x, rtol=1e-10)
         c.profile_enable(classes)
@@ -370,8 +372,9 @@ def test_profile_counts_launches_that_worked():
     print(f"[profile] {st['total_iters']} iterations: " +
           ", ".join(f"{k} {v['launches']}x{1e3 * v['avg_ms']:.1f}us" for k, v in prof.items()), flush=True)
     assert prof["element"]["launches"] == case.s and prof["rkc_combine"]["launches"] == case.s
-    assert n_levels >= 3
-    for k in ("spmv_M", "presmooth0", "postsmooth0", "vcycle", "cg_update", "restrict0", "prolong0", "vcoarse"):
+    assert n_levels >= 4
+    for k in ("spmv_M", "presmooth0", "postsmooth0", "vcycle", "cg_update", "restrict0", "prolong0", "vcoarse",
+              "postsmooth1"):
         assert prof[k]["launches"] == st["total_iters"], (k, prof[k], st)
     assert prof["finalise"]["launches"] == 3 * st["total_iters"]
     for k in classes:
