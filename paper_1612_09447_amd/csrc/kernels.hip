@@ -161,6 +161,9 @@ __device__ __forceinline__ void wave_range_sums(const double* const (&parts)[NP]
 #pragma unroll
             for (int p = 0; p < NP; ++p) t[p][u] = parts[p][2 * (int64_t)bc];
         }
+        // every load is issued before the first add (left alone, the scheduler starts adding after the
+        // first loads, and the wait for them holds back the rest)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -1698,91 +1701,248 @@ __global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, 
 // The finalisers below issue their independent loads (the stop flag, the
 // instance's scalars, the partials) before any of them is waited for, and test
 // the flag only where it matters: a finaliser costs about one memory latency
-// plus the reduction, not one latency per dependent step.
-__device__ __forceinline__ PcgScalars prefetch_scalars(const PcgScalars* __restrict__ s, const InstMap& m) {
-    PcgScalars x{};
-    if ((int32_t)threadIdx.x < m.n_inst && m.n_inst <= kFinWaves) x = s[threadIdx.x];
+// plus the reduction, not one latency per dependent step. Two things keep it
+// so. With one instance (the plain form) the flag and the scalars are read
+// with vector loads (vec_load): being uniform, plain loads would become scalar
+// loads, and the wait for the kernel argument the partials' addresses need
+// would then also wait for them. With several, each thread reads only the
+// scalar fields it uses and stores only those it changes (a copy of the whole
+// struct, read, modified and written back, would keep the untouched fields in
+// LDS, and the loads into it would be waited for before the partials' loads
+// are issued).
+template <typename T>
+__device__ __forceinline__ T vec_load(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+struct FinIn {
+    double rho, bb, tol2;
+    int32_t it, maxit, done, fresh, flexible;
+};
+__device__ __forceinline__ FinIn fin_fields(const PcgScalars* __restrict__ s, int32_t i) {
+    const PcgScalars* p = s + i;
+    return FinIn{p->rho, p->bb, p->tol2, p->it, p->maxit, p->done, p->fresh, p->flexible};
+}
+__device__ __forceinline__ FinIn prefetch_fields(const PcgScalars* __restrict__ s, const InstMap& m) {
+    FinIn x{};
+    if ((int32_t)threadIdx.x < m.n_inst && m.n_inst <= kFinWaves) x = fin_fields(s, threadIdx.x);
     return x;
 }
-// the prefetched copy serves thread i == threadIdx.x (every instance when n_inst <= kFinWaves)
-__device__ __forceinline__ PcgScalars scalars_of(const PcgScalars* __restrict__ s, const InstMap& m, int32_t i,
-                                                 const PcgScalars& pre) {
-    return (m.n_inst <= kFinWaves && i == (int32_t)threadIdx.x) ? pre : s[i];
+// the prefetched fields serve thread i == threadIdx.x (every instance when n_inst <= kFinWaves)
+__device__ __forceinline__ FinIn fields_of(const PcgScalars* __restrict__ s, const InstMap& m, int32_t i,
+                                           const FinIn& pre) {
+    FinIn x;
+    if (m.n_inst <= kFinWaves && i == (int32_t)threadIdx.x) x = pre;
+    else x = fin_fields(s, i);
+    return x;
 }
 
-// beta from r.z (Polak-Ribiere with r.z_old when flexible).
+// One instance: every wavefront sums an equal share of the blocks' first
+// partials (the second is 0 when there is one instance); thread 0 gets the
+// totals. The order of the additions is fixed.
+template <int NP>
+__device__ __forceinline__ void single_instance_sums(const double* const (&parts)[NP], int32_t rows,
+                                                     double (&out)[NP]) {
+    __shared__ double sh[NP][kFinWaves];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t nb = (rows + 255) >> 8;
+    const int32_t lo = (int32_t)(((int64_t)nb * wave) / kFinWaves);
+    const int32_t hi = (int32_t)(((int64_t)nb * (wave + 1)) / kFinWaves) - 1;
+    double v[NP];
+    wave_range_sums<NP>(parts, lo, hi, v);
+    if (lane == 0)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) sh[p][wave] = v[p];
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        double t = 0.0;
+        if (threadIdx.x == 0)
+            for (int w = 0; w < kFinWaves; ++w) t += sh[p][w];
+        out[p] = t;
+    }
+}
+
+// CG decisions from the reduced dot products; 0 = carry on.
+enum { FIN_GO = 0, FIN_CONVERGED = 1, FIN_BREAKDOWN = 2, FIN_OUT_OF_ITERS = 3 };
+__device__ __forceinline__ int fin_positive(double d) { return (!(d > 0.0) || !isfinite(d)) ? FIN_BREAKDOWN : FIN_GO; }
+__device__ __forceinline__ int fin_conv_decision(double rr, double tol2, int32_t it, int32_t maxit) {
+    if (rr <= tol2) return FIN_CONVERGED;
+    if (!isfinite(rr)) return FIN_BREAKDOWN;
+    if (it >= maxit) return FIN_OUT_OF_ITERS;
+    return FIN_GO;
+}
+__device__ __forceinline__ void set_breakdown(PcgScalars* __restrict__ p) {
+    p->done = 1;
+    p->status = EQS_ERR_BREAKDOWN;
+}
+__device__ __forceinline__ double fin_beta_of(const FinIn& x, double rz, double rzo) {
+    return x.fresh ? 0.0 : (x.flexible ? (rz - rzo) / x.rho : rz / x.rho);
+}
+
+// beta from r.z (Polak-Ribiere with r.z_old when flexible). ONE: a single
+// instance (InstMap::rows1 >= 0); the two forms are separate kernels so each
+// gets its own register allocation.
+template <bool ONE>
 __global__ __launch_bounds__(kFin) void k_fin_beta(PcgScalars* __restrict__ s, InstMap m,
                                                     const double* __restrict__ prz, const double* __restrict__ przold,
                                                     const int32_t* __restrict__ stop) {
-    const int32_t stopped = *stop;
-    const PcgScalars pre = prefetch_scalars(s, m);
+    const int32_t stopped = ONE ? vec_load(stop) : *stop;
     const double* parts[2] = {prz, przold};
-    for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
-        if (stopped) return;
-        PcgScalars x = scalars_of(s, m, i, pre);
-        if (x.done) return;
-        const double rz = v[0], rzo = v[1];
-        if (!(rz > 0.0) || !isfinite(rz)) {
-            x.done = 1;
-            x.status = EQS_ERR_BREAKDOWN;
-        } else {
-            if (x.fresh) x.beta = 0.0;
-            else x.beta = x.flexible ? (rz - rzo) / x.rho : rz / x.rho;
-            x.rho = rz;
+    if constexpr (ONE) {
+        // only the fields used: a vector load whose result is never read still holds its register
+        FinIn x{};
+        x.rho = vec_load(&s->rho);
+        x.done = vec_load(&s->done);
+        x.fresh = vec_load(&s->fresh);
+        x.flexible = vec_load(&s->flexible);
+        double v[2];
+        single_instance_sums<2>(parts, m.rows1, v);
+        if (threadIdx.x == 0 && !stopped && !x.done) {
+            if (fin_positive(v[0]) != FIN_GO) {
+                set_breakdown(s);
+            } else {
+                s->beta = fin_beta_of(x, v[0], v[1]);
+                s->rho = v[0];
+            }
         }
-        s[i] = x;
-    });
+    } else {
+        const FinIn pre = prefetch_fields(s, m);
+        for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
+            if (stopped) return;
+            const FinIn x = fields_of(s, m, i, pre);
+            if (x.done) return;
+            PcgScalars* p = s + i;
+            if (fin_positive(v[0]) != FIN_GO) {
+                set_breakdown(p);
+            } else {
+                p->beta = fin_beta_of(x, v[0], v[1]);
+                p->rho = v[0];
+            }
+        });
+    }
 }
 
+template <bool ONE>
 __global__ __launch_bounds__(kFin) void k_fin_alpha(PcgScalars* __restrict__ s, InstMap m,
                                                      const double* __restrict__ ppq, const int32_t* __restrict__ stop) {
-    const int32_t stopped = *stop;
-    const PcgScalars pre = prefetch_scalars(s, m);
+    const int32_t stopped = ONE ? vec_load(stop) : *stop;
     const double* parts[1] = {ppq};
-    for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
-        if (stopped) return;
-        PcgScalars x = scalars_of(s, m, i, pre);
-        if (x.done) return;
-        const double pq = v[0];
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            x.done = 1;
-            x.status = EQS_ERR_BREAKDOWN;
-        } else {
-            x.alpha = x.rho / pq;
-            x.fresh = 0;
+    if constexpr (ONE) {
+        const double rho = vec_load(&s->rho);
+        const int32_t done = vec_load(&s->done);
+        double v[1];
+        single_instance_sums<1>(parts, m.rows1, v);
+        if (threadIdx.x == 0 && !stopped && !done) {
+            if (fin_positive(v[0]) != FIN_GO) {
+                set_breakdown(s);
+            } else {
+                s->alpha = rho / v[0];
+                s->fresh = 0;
+            }
         }
-        s[i] = x;
-    });
+    } else {
+        const FinIn pre = prefetch_fields(s, m);
+        for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
+            if (stopped) return;
+            const FinIn x = fields_of(s, m, i, pre);
+            if (x.done) return;
+            PcgScalars* p = s + i;
+            if (fin_positive(v[0]) != FIN_GO) {
+                set_breakdown(p);
+            } else {
+                p->alpha = x.rho / v[0];
+                p->fresh = 0;
+            }
+        });
+    }
 }
 
+template <bool ONE>
 __global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, InstMap m,
                                                     const double* __restrict__ prr, PcgSummary* __restrict__ sum,
                                                     PcgSummary* __restrict__ host_sum, PcgScalars* __restrict__ host) {
-    const int32_t stopped = sum->all_done;
-    const PcgScalars pre = prefetch_scalars(s, m);
+    const int32_t stopped = ONE ? vec_load(&sum->all_done) : sum->all_done;
     const double* parts[1] = {prr};
-    for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
-        if (stopped) return;
-        PcgScalars x = scalars_of(s, m, i, pre);
-        if (x.done) return;
-        const double rr = v[0];
-        x.rr = rr;
-        x.relres = sqrt(rr / x.bb);
-        x.it += 1;
-        if (rr <= x.tol2) {
-            x.done = 1;
-        } else if (!isfinite(rr)) {
-            x.done = 1;
-            x.status = EQS_ERR_BREAKDOWN;
-        } else if (x.it >= x.maxit) {
-            x.done = 1;
-            x.status = EQS_ERR_NOT_CONVERGED;
+    if constexpr (ONE) {
+        // the instance's scalars and the summary as summarise() leaves them for one instance; the struct is
+        // handled field by field (a whole-struct copy would be kept in LDS)
+        const PcgScalars* p = s;
+        const double bb = vec_load(&p->bb), rho = vec_load(&p->rho), rho_old = vec_load(&p->rho_old);
+        const double beta = vec_load(&p->beta), alpha = vec_load(&p->alpha), tol2 = vec_load(&p->tol2);
+        const double rr0 = vec_load(&p->rr), relres0 = vec_load(&p->relres);
+        const int32_t it0 = vec_load(&p->it), maxit = vec_load(&p->maxit), done0 = vec_load(&p->done);
+        const int32_t status0 = vec_load(&p->status), fresh = vec_load(&p->fresh), flexible = vec_load(&p->flexible);
+        double v[1];
+        single_instance_sums<1>(parts, m.rows1, v);
+        if (threadIdx.x == 0 && !stopped) {
+            double rr = rr0, relres = relres0;
+            int32_t it = it0, done = done0, status = status0;
+            if (!done0) {
+                rr = v[0];
+                relres = sqrt(rr / bb);
+                it = it0 + 1;
+                const int d = fin_conv_decision(rr, tol2, it, maxit);
+                if (d != FIN_GO) done = 1;
+                if (d == FIN_BREAKDOWN) status = EQS_ERR_BREAKDOWN;
+                if (d == FIN_OUT_OF_ITERS) status = EQS_ERR_NOT_CONVERGED;
+                s->rr = rr;
+                s->relres = relres;
+                s->it = it;
+                s->done = done;
+                s->status = status;
+            }
+            PcgScalars h;
+            h.bb = bb;
+            h.rr = rr;
+            h.rho = rho;
+            h.rho_old = rho_old;
+            h.beta = beta;
+            h.alpha = alpha;
+            h.tol2 = tol2;
+            h.relres = relres;
+            h.it = it;
+            h.maxit = maxit;
+            h.done = done;
+            h.status = status;
+            h.fresh = fresh;
+            h.flexible = flexible;
+            *host = h;
+            PcgSummary v1;
+            v1.all_done = done ? 1 : 0;
+            v1.n_active = done ? 0 : 1;
+            v1.n_breakdown = status == EQS_ERR_BREAKDOWN;
+            v1.n_notconv = status == EQS_ERR_NOT_CONVERGED;
+            v1.n_zero_rhs = bb == 0.0;
+            v1.max_it = max(it, 0);
+            const double mr = isnan(relres) ? INFINITY : relres;
+            v1.max_relres = mr > 0.0 ? mr : 0.0;
+            *sum = v1;
+            *host_sum = v1;
         }
-        s[i] = x;
-    });
-    if (stopped) return;  // uniform: the summary already says all done
-    __syncthreads();
-    summarise(s, m.n_inst, sum, host_sum, host);
+    } else {
+        const FinIn pre = prefetch_fields(s, m);
+        for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
+            if (stopped) return;
+            const FinIn x = fields_of(s, m, i, pre);
+            if (x.done) return;
+            const double rr = v[0];
+            const int32_t it = x.it + 1;
+            PcgScalars* p = s + i;
+            p->rr = rr;
+            p->relres = sqrt(rr / x.bb);
+            p->it = it;
+            const int d = fin_conv_decision(rr, x.tol2, it, x.maxit);
+            if (d == FIN_CONVERGED) p->done = 1;
+            else if (d == FIN_BREAKDOWN) set_breakdown(p);
+            else if (d == FIN_OUT_OF_ITERS) {
+                p->done = 1;
+                p->status = EQS_ERR_NOT_CONVERGED;
+            }
+        });
+        if (stopped) return;  // uniform: the summary already says all done
+        __syncthreads();
+        summarise(s, m.n_inst, sum, host_sum, host);
+    }
 }
 
 __global__ void k_set_flag(int32_t* __restrict__ p, int32_t v) { *p = v; }
@@ -1829,16 +1989,18 @@ void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int 
     if (precision == EQS_PREC_FP32) vcycle<float>(s, c, c->h32, c->d_r, c->d_z, part(c, 0), part(c, 1), stop);
     else vcycle<double>(s, c, c->h64, c->d_r, c->d_z, part(c, 0), part(c, 1), stop);
     prof_end(c, EQS_KCLASS_VCYCLE, s);
-    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, k_fin_beta, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c),
-                     part(c, 0), part(c, 1), stop);
+    const InstMap im = inst_map(c);
+    const bool one = im.rows1 >= 0;
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_beta<true> : k_fin_beta<false>, dim3(1), dim3(kFin), 0, s,
+                     c->d_scal, im, part(c, 0), part(c, 1), stop);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_SPMV_M, k_pcg_spmv, dim3(nbM), dim3(kBlock), 0, s, view(c->M), inst_map(c),
                      c->d_z, c->d_p, c->d_q, part(c, 2), c->d_scal, stop);
-    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, k_fin_alpha, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c),
-                     part(c, 2), stop);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_alpha<true> : k_fin_alpha<false>, dim3(1), dim3(kFin), 0,
+                     s, c->d_scal, im, part(c, 2), stop);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_CG_UPDATE, k_pcg_update, dim3(nbV), dim3(kBlock), 0, s, inst_map(c), x, c->d_r,
                      c->d_p, c->d_q, c->n_free, part(c, 3), c->d_scal, stop);
-    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, k_fin_conv, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c),
-                     part(c, 3), c->d_sum, c->d_hsum, c->d_hscal);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_conv<true> : k_fin_conv<false>, dim3(1), dim3(kFin), 0, s,
+                     c->d_scal, im, part(c, 3), c->d_sum, c->d_hsum, c->d_hscal);
 }
 
 // ------------------------------------------------------------------ RKC
