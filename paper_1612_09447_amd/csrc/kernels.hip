@@ -1648,56 +1648,6 @@ __device__ void summarise(const PcgScalars* __restrict__ s, int32_t n, PcgSummar
     }
 }
 
-// mode 0: start of a solve (it = 0); mode 1: restart from the true residual
-// (iteration count kept; broken-down instances stay so). An instance is done
-// when |r| <= rtol |rhs|, rhs = 0, or its iteration budget is spent.
-// force (may be NULL): a one-shot flag for tests of the restart path; when
-// set, this check treats every instance as not yet converged (it then
-// continues from its true residual) and clears the flag.
-__global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, InstMap m, const double* __restrict__ prr,
-                                                     const double* __restrict__ pbb, double rtol, int32_t maxit,
-                                                     int32_t flexible, int32_t mode, PcgSummary* __restrict__ sum,
-                                                     PcgSummary* __restrict__ host_sum,
-                                                     PcgScalars* __restrict__ host, int32_t when_done,
-                                                     int32_t* __restrict__ force) {
-    if (when_done && !sum->all_done) return;  // pairs with k_pcg_residual's when_done
-    const int32_t forced = (mode == 1 && force) ? *force : 0;
-    __syncthreads();
-    if (forced && threadIdx.x == 0) *force = 0;
-    const double* parts[2] = {prr, pbb};
-    for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
-        const double rr = v[0], bb = v[1];
-        PcgScalars x = s[i];
-        if (mode == 0) {
-            x = PcgScalars{};
-            x.maxit = maxit;
-            x.flexible = flexible;
-            x.tol2 = rtol * rtol * bb;
-        } else if (x.status == EQS_ERR_BREAKDOWN) {
-            return;
-        }
-        x.bb = bb;
-        x.rr = rr;
-        x.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-        x.fresh = 1;
-        x.beta = 0.0;
-        x.status = EQS_OK;
-        x.done = 0;
-        if (bb == 0.0 || (rr <= x.tol2 && !forced)) {
-            x.done = 1;
-        } else if (!isfinite(rr) || !isfinite(bb)) {
-            x.done = 1;
-            x.status = EQS_ERR_BREAKDOWN;
-        } else if (x.it >= x.maxit) {
-            x.done = 1;
-            x.status = EQS_ERR_NOT_CONVERGED;
-        }
-        s[i] = x;
-    });
-    __syncthreads();
-    summarise(s, m.n_inst, sum, host_sum, host);
-}
-
 // The finalisers below issue their independent loads (the stop flag, the
 // instance's scalars, the partials) before any of them is waited for, and test
 // the flag only where it matters: a finaliser costs about one memory latency
@@ -1777,6 +1727,130 @@ __device__ __forceinline__ void set_breakdown(PcgScalars* __restrict__ p) {
 }
 __device__ __forceinline__ double fin_beta_of(const FinIn& x, double rz, double rzo) {
     return x.fresh ? 0.0 : (x.flexible ? (rz - rzo) / x.rho : rz / x.rho);
+}
+
+// mode 0: start of a solve (it = 0); mode 1: restart from the true residual
+// (iteration count kept; broken-down instances stay so). An instance is done
+// when |r| <= rtol |rhs|, rhs = 0, or its iteration budget is spent.
+// force (may be NULL): a one-shot flag for tests of the restart path; when
+// set, this check treats every instance as not yet converged (it then
+// continues from its true residual) and clears the flag. ONE: a single
+// instance (its scalars handled field by field, as in k_fin_conv).
+template <bool ONE>
+__global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, InstMap m, const double* __restrict__ prr,
+                                                     const double* __restrict__ pbb, double rtol, int32_t maxit,
+                                                     int32_t flexible, int32_t mode, PcgSummary* __restrict__ sum,
+                                                     PcgSummary* __restrict__ host_sum,
+                                                     PcgScalars* __restrict__ host, int32_t when_done,
+                                                     int32_t* __restrict__ force) {
+    const double* parts[2] = {prr, pbb};
+    if constexpr (ONE) {
+        // both flags are read unconditionally (a load under a branch is waited for at the branch's end)
+        const int32_t all_done = vec_load(&sum->all_done);
+        const int32_t force_raw = vec_load(force ? (const int32_t*)force : &sum->all_done);
+        const PcgScalars* p = s;
+        double rho = vec_load(&p->rho), rho_old = vec_load(&p->rho_old), alpha = vec_load(&p->alpha);
+        double tol2 = vec_load(&p->tol2), rr = vec_load(&p->rr), relres = vec_load(&p->relres);
+        double beta = vec_load(&p->beta), bb = vec_load(&p->bb);
+        int32_t it = vec_load(&p->it), mx = vec_load(&p->maxit), done = vec_load(&p->done);
+        int32_t status = vec_load(&p->status), fresh = vec_load(&p->fresh), flex = vec_load(&p->flexible);
+        double v[2];
+        single_instance_sums<2>(parts, m.rows1, v);
+        // the flags are tested only here, so that no wait for them precedes the partials' loads
+        const int32_t skip = when_done ? !all_done : 0;
+        const int32_t forced = (mode == 1 && force) ? force_raw : 0;
+        if (threadIdx.x != 0 || skip) return;  // skip pairs with k_pcg_residual's when_done
+        if (forced) *force = 0;
+        if (mode == 0) {
+            rho = rho_old = alpha = 0.0;
+            it = 0;
+            mx = maxit;
+            flex = flexible;
+            tol2 = rtol * rtol * v[1];
+        }
+        if (mode == 0 || status != EQS_ERR_BREAKDOWN) {
+            bb = v[1];
+            rr = v[0];
+            relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            fresh = 1;
+            beta = 0.0;
+            status = EQS_OK;
+            done = 0;
+            if (bb == 0.0 || (rr <= tol2 && !forced)) {
+                done = 1;
+            } else if (!isfinite(rr) || !isfinite(bb)) {
+                done = 1;
+                status = EQS_ERR_BREAKDOWN;
+            } else if (it >= mx) {
+                done = 1;
+                status = EQS_ERR_NOT_CONVERGED;
+            }
+        }
+        PcgScalars h;
+        h.bb = bb;
+        h.rr = rr;
+        h.rho = rho;
+        h.rho_old = rho_old;
+        h.beta = beta;
+        h.alpha = alpha;
+        h.tol2 = tol2;
+        h.relres = relres;
+        h.it = it;
+        h.maxit = mx;
+        h.done = done;
+        h.status = status;
+        h.fresh = fresh;
+        h.flexible = flex;
+        *s = h;
+        *host = h;
+        PcgSummary v1;
+        v1.all_done = done ? 1 : 0;
+        v1.n_active = done ? 0 : 1;
+        v1.n_breakdown = status == EQS_ERR_BREAKDOWN;
+        v1.n_notconv = status == EQS_ERR_NOT_CONVERGED;
+        v1.n_zero_rhs = bb == 0.0;
+        v1.max_it = max(it, 0);
+        const double mr = isnan(relres) ? INFINITY : relres;
+        v1.max_relres = mr > 0.0 ? mr : 0.0;
+        *sum = v1;
+        *host_sum = v1;
+    } else {
+        if (when_done && !sum->all_done) return;  // pairs with k_pcg_residual's when_done
+        const int32_t forced = (mode == 1 && force) ? *force : 0;
+        __syncthreads();
+        if (forced && threadIdx.x == 0) *force = 0;
+        for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
+            const double rr = v[0], bb = v[1];
+            PcgScalars x = s[i];
+            if (mode == 0) {
+                x = PcgScalars{};
+                x.maxit = maxit;
+                x.flexible = flexible;
+                x.tol2 = rtol * rtol * bb;
+            } else if (x.status == EQS_ERR_BREAKDOWN) {
+                return;
+            }
+            x.bb = bb;
+            x.rr = rr;
+            x.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            x.fresh = 1;
+            x.beta = 0.0;
+            x.status = EQS_OK;
+            x.done = 0;
+            if (bb == 0.0 || (rr <= x.tol2 && !forced)) {
+                x.done = 1;
+            } else if (!isfinite(rr) || !isfinite(bb)) {
+                x.done = 1;
+                x.status = EQS_ERR_BREAKDOWN;
+            } else if (x.it >= x.maxit) {
+                x.done = 1;
+                x.status = EQS_ERR_NOT_CONVERGED;
+            }
+            s[i] = x;
+        });
+        __syncthreads();
+        summarise(s, m.n_inst, sum, host_sum, host);
+    }
 }
 
 // beta from r.z (Polak-Ribiere with r.z_old when flexible). ONE: a single
@@ -1958,7 +2032,8 @@ void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int
     else
         hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
                            part(c, 0), part(c, 1), (double*)nullptr, (const int32_t*)nullptr);
-    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), rtol,
+    hipLaunchKernelGGL(inst_map(c).rows1 >= 0 ? k_fin_start<true> : k_fin_start<false>, dim3(1), dim3(kFin), 0, s,
+                       c->d_scal, inst_map(c), part(c, 0), part(c, 1), rtol,
                        maxit, flexible, 0, c->d_sum, c->d_hsum, c->d_hscal, 0, (int32_t*)nullptr);
     if (c->test_reject_first) hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, c->d_force, 1);
 }
@@ -1969,7 +2044,8 @@ void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const doubl
     const int32_t* done = only_if_done ? &c->d_sum->all_done : nullptr;
     hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
                        part(c, 0), part(c, 1), mx_out, done);
-    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), 0.0, 0,
+    hipLaunchKernelGGL(inst_map(c).rows1 >= 0 ? k_fin_start<true> : k_fin_start<false>, dim3(1), dim3(kFin), 0, s,
+                       c->d_scal, inst_map(c), part(c, 0), part(c, 1), 0.0, 0,
                        0, 1, c->d_sum, c->d_hsum, c->d_hscal, only_if_done ? 1 : 0,
                        c->test_reject_first ? c->d_force : (int32_t*)nullptr);
 }
