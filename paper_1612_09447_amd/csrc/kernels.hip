@@ -1284,20 +1284,27 @@ static void launch_postsmooth(hipStream_t s, eqs_ctx* c, int cls, const Level<T>
     }
 }
 
+// Time per product y = A x (ms) for the layout tuner: the median over `reps`
+// rounds (after one warm-up round) of kBatch back-to-back launches between two
+// events, divided by kBatch. A single launch between events carries the
+// events' own cost and jitter, which at 5-20 us per launch is as large as the
+// differences between layouts; back to back, the launches also run as they
+// do inside the V-cycle, one after another on the stream.
 template <typename T>
 double time_mv(eqs_ctx* c, const SpMat<T>& A, const T* x, T* y, int reps) {
+    constexpr int kBatch = 8;
     hipEvent_t e0, e1;
     EQS_HIP(hipEventCreate(&e0));
     EQS_HIP(hipEventCreate(&e1));
     std::vector<float> ms;
-    for (int r = 0; r < reps + 2; ++r) {
+    for (int r = 0; r < reps + 1; ++r) {
         EQS_HIP(hipEventRecord(e0, c->stream));
-        launch_mv<T>(c->stream, A, x, y, 0, nullptr);
+        for (int k = 0; k < kBatch; ++k) launch_mv<T>(c->stream, A, x, y, 0, nullptr);
         EQS_HIP(hipEventRecord(e1, c->stream));
         EQS_HIP(hipEventSynchronize(e1));
         float t = 0.0f;
         EQS_HIP(hipEventElapsedTime(&t, e0, e1));
-        if (r >= 2) ms.push_back(t);
+        if (r >= 1) ms.push_back(t / kBatch);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

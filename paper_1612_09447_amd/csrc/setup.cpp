@@ -905,7 +905,7 @@ static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
 // is only used in products y = A x;
 // CSR with L = 2..64 lanes per row up to about twice the mean row length, and
 // with one lane per row for rows of up to 8 entries on average), time y = A x
-// with HIP events on the context's stream (median of 5 after 2 warm-ups) and
+// with HIP events on the context's stream (median of 5 rounds of 8 back-to-back launches, after a warm-up round) and
 // keep the fastest.
 template <typename T>
 static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, bool sell_only = false,
