@@ -206,10 +206,13 @@ int eqs_set_deterministic(eqs_ctx *ctx, int32_t on);
 /* Launch granularity of the CG solves (the solve is Sec. II's M-solve; the
  * grouping is this library's choice): every launch replays one captured HIP
  * graph of `iters` CG iterations, 1..EQS_MAX_GRAPH_ITERS [1]. Iterations that
- * a launch holds past convergence return at entry (a few microseconds each),
- * so a large value gives a graph spanning the whole solve, a small one lets
- * the host stop closer to convergence. Results do not depend on it. Takes
- * effect at the next solve; EQS_ERR_INVALID_ARG outside the range. */
+ * a launch holds past convergence change nothing: their preconditioner cycle
+ * runs (its kernels do not test the stop flag, which would cost every one of
+ * them a wait), and their SpMV, update and scalar kernels return at entry.
+ * So a large value gives a graph spanning the whole solve at the price of
+ * those cycles, a small one lets the host stop at convergence. Results do not
+ * depend on it. Takes effect at the next solve; EQS_ERR_INVALID_ARG outside
+ * the range. */
 #define EQS_MAX_GRAPH_ITERS 256
 int eqs_set_graph_iters(eqs_ctx *ctx, int32_t iters);
 

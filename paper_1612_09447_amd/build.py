@@ -29,6 +29,9 @@ COMMON = [
     "-fPIC",
     f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep kernel-argument loads in the entry block: sunk into the branches that use them, they are issued and
+    # waited for one batch at a time before a kernel's first data load
+    "-mllvm", "-disable-machine-sink",
     "-Wall",
     "-Wno-unused-function",
     "-I", INCLUDE,

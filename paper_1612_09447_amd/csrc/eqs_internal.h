@@ -439,7 +439,7 @@ void pcg_zero_rhs_rows(hipStream_t s, eqs_ctx* c, double* x);
 
 template <typename T>
 void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double* z, double* part_rz,
-            double* part_rzold, const int32_t* stop);
+            double* part_rzold);
 
 // start-vector network (mlp.hip)
 }  // namespace eqs

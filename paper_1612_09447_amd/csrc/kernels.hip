@@ -41,6 +41,16 @@ namespace eqs {
 // Threads of a finaliser block (one block per finaliser launch).
 constexpr int kFin = 1024;
 
+// A relaxed load that stays a vector load even when its address is uniform. A
+// uniform plain load becomes a scalar load, and the wait for it is then shared
+// with the waits for kernel arguments that later data loads need (scalar loads
+// complete out of order, so the compiler waits for all of them at once);
+// vector loads complete in order, so issuing one early holds nothing back.
+template <typename T>
+__device__ __forceinline__ T vec_load(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------- instances (batches)
 // Independent instances occupy contiguous ranges of free rows. Every
 // 256-row block of the finest level holds rows of at most two instances (each
@@ -992,27 +1002,24 @@ __device__ __forceinline__ void sell_mv(const SellView<T>& A, const T* __restric
 // products (k_sell_mv). Groups of 16 entries hold their loads in up to 128
 // registers (4 waves per SIMD instead of 8).
 #define EQS_SELL_MV_ARGS \
-    SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc, MvInit<T> in, const int32_t* __restrict__ stop
+    SellView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc, MvInit<T> in
 template <int L, int U, typename T>
 __global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_sell_mv(EQS_SELL_MV_ARGS) {
-    if (stop && *stop) return;
     sell_mv<L, U, T>(A, x, y, acc, in);
 }
 template <int L, int U, typename T>
 __global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_restrict(EQS_SELL_MV_ARGS) {
-    if (stop && *stop) return;
     sell_mv<L, U, T>(A, x, y, acc, in);
 }
 template <int L, int U, typename T>
 __global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_prolong(EQS_SELL_MV_ARGS) {
-    if (stop && *stop) return;
     sell_mv<L, U, T>(A, x, y, acc, in);
 }
 #undef EQS_SELL_MV_ARGS
 
 enum MvRole { MV_PLAIN = 0, MV_RESTRICT = 1, MV_PROLONG = 2 };
 template <int L, int U, typename T>
-using SellMvKernel = void (*)(SellView<T>, const T*, T*, int, MvInit<T>, const int32_t*);
+using SellMvKernel = void (*)(SellView<T>, const T*, T*, int, MvInit<T>);
 template <int L, int U, typename T>
 static SellMvKernel<L, U, T> sell_mv_kernel(int role) {
     return role == MV_RESTRICT ? k_restrict<L, U, T> : role == MV_PROLONG ? k_prolong<L, U, T> : k_sell_mv<L, U, T>;
@@ -1038,8 +1045,7 @@ void launch_spmv64(hipStream_t s, const Sell<double>& A, const double* x, double
 template <int L, typename T, typename TB, int U = 8>
 __global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_presmooth_res(SellView<T> As, const T* __restrict__ dinv, T omega,
                                                         const TB* __restrict__ b, T* __restrict__ x,
-                                                        T* __restrict__ res, const int32_t* __restrict__ stop) {
-    if (stop && *stop) return;
+                                                        T* __restrict__ res) {
     const int64_t g = row_block() * blockDim.x + threadIdx.x;
     if (g >= (int64_t)As.n_slices * 64) return;
     const int32_t row = sell_row_of<L>(g);
@@ -1059,11 +1065,9 @@ template <int L, typename T, typename TB, typename TO, bool DOT, int U = 8>
 __global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_postsmooth(SellView<T> A, const T* __restrict__ dinv, T omega,
                                                      const TB* __restrict__ b, const T* __restrict__ x,
                                                      TO* __restrict__ out, InstMap m, double* __restrict__ part_rz,
-                                                     double* __restrict__ part_rzold,
-                                                     const int32_t* __restrict__ stop) {
+                                                     double* __restrict__ part_rzold) {
     static_assert(!DOT || L == 1, "CG partials are produced by the one-lane-per-row finest level");
     __shared__ double sh[kPairSh];
-    if (stop && *stop) return;
     const int64_t B = row_block();
     const int64_t g = B * blockDim.x + threadIdx.x;
     const int32_t row = sell_row_of<L>(g);
@@ -1142,8 +1146,7 @@ __device__ __forceinline__ T csr_row(const CsrView<T>& A, int32_t row, int lane,
 
 template <int L, typename T>
 __global__ __launch_bounds__(256, kSparseWaves) void k_csr_mv(CsrView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
-                                                 MvInit<T> in, const int32_t* __restrict__ stop) {
-    if (stop && *stop) return;
+                                                 MvInit<T> in) {
     const int64_t g = row_block() * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
@@ -1155,8 +1158,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_csr_mv(CsrView<T> A, cons
 template <int L, typename T, typename TB>
 __global__ __launch_bounds__(256, kSparseWaves) void k_csr_presmooth_res(CsrView<T> As, const T* __restrict__ dinv, T omega,
                                                             const TB* __restrict__ b, T* __restrict__ x,
-                                                            T* __restrict__ res, const int32_t* __restrict__ stop) {
-    if (stop && *stop) return;
+                                                            T* __restrict__ res) {
     const int64_t g = row_block() * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
@@ -1172,8 +1174,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_csr_presmooth_res(CsrView
 template <int L, typename T, typename TB, typename TO>
 __global__ __launch_bounds__(256, kSparseWaves) void k_csr_postsmooth(CsrView<T> A, const T* __restrict__ dinv, T omega,
                                                          const TB* __restrict__ b, const T* __restrict__ x,
-                                                         TO* __restrict__ out, const int32_t* __restrict__ stop) {
-    if (stop && *stop) return;
+                                                         TO* __restrict__ out) {
     const int64_t g = row_block() * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
@@ -1215,39 +1216,39 @@ static unsigned csr_grid(const SpMat<T>& A) {
     }
 
 template <typename T>
-static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int acc, const int32_t* stop,
+static void launch_mv(hipStream_t s, const SpMat<T>& A, const T* x, T* y, int acc,
                       MvInit<T> in = MvInit<T>{nullptr, nullptr, T(0)}, int role = MV_PLAIN) {
     if (A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(A.sell.lanes,
                               EQS_UNROLL_SWITCH(A.sell.unroll,
                                                 hipLaunchKernelGGL((sell_mv_kernel<L_, U_, T>(role)),
                                                                    dim3(sell_grid(A.sell)), dim3(kBlock), 0, s,
-                                                                   view(A.sell), x, y, acc, in, stop)));
+                                                                   view(A.sell), x, y, acc, in)));
     } else {
         EQS_LANES_SWITCH(A.lanes, hipLaunchKernelGGL((k_csr_mv<L_, T>), dim3(csr_grid(A)), dim3(kBlock), 0, s,
-                                                     cview(A), x, y, acc, in, stop));
+                                                     cview(A), x, y, acc, in));
     }
 }
 
 // launch_mv with the launch's own events when kernel class `cls` is profiled
 template <typename T>
 static void launch_mv_timed(hipStream_t s, eqs_ctx* c, int cls, const SpMat<T>& A, const T* x, T* y, int acc,
-                            const int32_t* stop, int role) {
+                            int role) {
     const MvInit<T> in{nullptr, nullptr, T(0)};
     if (A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(A.sell.lanes,
                               EQS_UNROLL_SWITCH(A.sell.unroll,
                                                 EQS_LAUNCH_TIMED(c, cls, (sell_mv_kernel<L_, U_, T>(role)),
                                                                  dim3(sell_grid(A.sell)), dim3(kBlock), 0, s,
-                                                                 view(A.sell), x, y, acc, in, stop)));
+                                                                 view(A.sell), x, y, acc, in)));
     } else {
         EQS_LANES_SWITCH(A.lanes, EQS_LAUNCH_TIMED(c, cls, (k_csr_mv<L_, T>), dim3(csr_grid(A)), dim3(kBlock), 0, s,
-                                                   cview(A), x, y, acc, in, stop));
+                                                   cview(A), x, y, acc, in));
     }
 }
 
 template <typename T, typename TB>
-static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, const int32_t* stop) {
+static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b) {
     if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
     if (lv.A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
@@ -1255,19 +1256,18 @@ static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b, con
                                                 hipLaunchKernelGGL((k_presmooth_res<L_, T, TB, U_>),
                                                                    dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
                                                                    sview(lv), (const T*)lv.dinv, (T)lv.omega, b, lv.x,
-                                                                   lv.res, stop)));
+                                                                   lv.res)));
     } else {
         EQS_LANES_SWITCH(lv.A.lanes, hipLaunchKernelGGL((k_csr_presmooth_res<L_, T, TB>), dim3(csr_grid(lv.A)),
                                                         dim3(kBlock), 0, s, scview(lv), (const T*)lv.dinv,
-                                                        (T)lv.omega, b, lv.x, lv.res, stop));
+                                                        (T)lv.omega, b, lv.x, lv.res));
     }
 }
 
 // Post-smoothing of a coarse level (no dot products), timed as kernel class
 // `cls` when that class is profiled.
 template <typename T>
-static void launch_postsmooth(hipStream_t s, eqs_ctx* c, int cls, const Level<T>& lv, const T* b, const T* x, T* out,
-                              const int32_t* stop) {
+static void launch_postsmooth(hipStream_t s, eqs_ctx* c, int cls, const Level<T>& lv, const T* b, const T* x, T* out) {
     if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
     if (lv.A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
@@ -1276,11 +1276,11 @@ static void launch_postsmooth(hipStream_t s, eqs_ctx* c, int cls, const Level<T>
                                                                  dim3(sell_grid(lv.A.sell)), dim3(kBlock), 0, s,
                                                                  view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega, b,
                                                                  x, out, InstMap{nullptr, nullptr, 0, -1}, nullptr,
-                                                                 nullptr, stop)));
+                                                                 nullptr)));
     } else {
         EQS_LANES_SWITCH(lv.A.lanes, EQS_LAUNCH_TIMED(c, cls, (k_csr_postsmooth<L_, T, T, T>), dim3(csr_grid(lv.A)),
                                                       dim3(kBlock), 0, s, cview(lv.A), (const T*)lv.dinv,
-                                                      (T)lv.omega, b, x, out, stop));
+                                                      (T)lv.omega, b, x, out));
     }
 }
 
@@ -1299,7 +1299,7 @@ double time_mv(eqs_ctx* c, const SpMat<T>& A, const T* x, T* y, int reps) {
     std::vector<float> ms;
     for (int r = 0; r < reps + 1; ++r) {
         EQS_HIP(hipEventRecord(e0, c->stream));
-        for (int k = 0; k < kBatch; ++k) launch_mv<T>(c->stream, A, x, y, 0, nullptr);
+        for (int k = 0; k < kBatch; ++k) launch_mv<T>(c->stream, A, x, y, 0);
         EQS_HIP(hipEventRecord(e1, c->stream));
         EQS_HIP(hipEventSynchronize(e1));
         float t = 0.0f;
@@ -1319,8 +1319,7 @@ template double time_mv<float>(eqs_ctx*, const SpMat<float>&, const float*, floa
 // splits the dot product over its 64 lanes.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const T* __restrict__ b,
-                                                 T* __restrict__ x, int32_t n, const int32_t* __restrict__ stop) {
-    if (stop && *stop) return;
+                                                 T* __restrict__ x, int32_t n) {
     const int32_t i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (i >= n) return;
@@ -1336,10 +1335,8 @@ __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const
 // together), then the block sums in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_restrict(const T* __restrict__ C, const T* __restrict__ r,
-                                                          T* __restrict__ x, int32_t n, int32_t nf,
-                                                          const int32_t* __restrict__ stop) {
+                                                          T* __restrict__ x, int32_t n, int32_t nf) {
     __shared__ double sh[4];
-    if (stop && *stop) return;
     const int32_t i = blockIdx.x;
     const T* row = C + (int64_t)i * nf;
     T acc = T(0);
@@ -1362,10 +1359,8 @@ __global__ __launch_bounds__(256) void k_coarse_restrict(const T* __restrict__ C
 template <typename T, bool DOT>
 __global__ __launch_bounds__(256) void k_dense_precond(const T* __restrict__ inv, const double* __restrict__ r,
                                                         double* __restrict__ z, int32_t n, InstMap m,
-                                                        double* __restrict__ part_rz, double* __restrict__ part_rzold,
-                                                        const int32_t* __restrict__ stop) {
+                                                        double* __restrict__ part_rz, double* __restrict__ part_rzold) {
     __shared__ double sh[kPairSh];
-    if (stop && *stop) return;
     const int64_t B = blockIdx.x;
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     double rz = 0.0, rzo = 0.0;
@@ -1393,10 +1388,16 @@ static InstMap inst_map(const eqs_ctx* c) {
 
 // V(1,1) cycle z = B r. r and z are FP64 (CG's vectors); the hierarchy is T.
 // With part_rz the finest post-smoothing also writes the r.z and r.z_old
-// partials (pair layout); `stop` (may be NULL) ends every kernel at entry.
+// partials (pair layout). Its kernels do not test CG's stop flag: a test on a
+// flag in memory makes every kernel wait for it, and for the kernel arguments
+// loaded after the branch, before its first data load (together about 3 of
+// 186 us per cycle at 2.1M DOF, nine kernels). A CG iteration launched
+// after convergence therefore runs its V-cycle on the unchanged residual; it
+// writes only the cycle's temporaries, z and the r.z partials, none of which a
+// finished solve or a restart (beta = 0) reads.
 template <typename T>
 void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double* z, double* part_rz,
-            double* part_rzold, const int32_t* stop) {
+            double* part_rzold) {
     const int L = (int)h.lv.size();
     dim3 b(kBlock);
     if (L == 1) {
@@ -1404,10 +1405,10 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         Level<T>& lv = h.lv[0];
         if (part_rz)
             hipLaunchKernelGGL((k_dense_precond<T, true>), dim3(grid_for(lv.n)), b, 0, s, (const T*)lv.dense_inv, r, z,
-                               lv.n, inst_map(c), part_rz, part_rzold, stop);
+                               lv.n, inst_map(c), part_rz, part_rzold);
         else
             hipLaunchKernelGGL((k_dense_precond<T, false>), dim3(grid_for(lv.n)), b, 0, s, (const T*)lv.dense_inv, r,
-                               z, lv.n, inst_map(c), part_rz, part_rzold, stop);
+                               z, lv.n, inst_map(c), part_rz, part_rzold);
         return;
     }
     // descend
@@ -1415,23 +1416,23 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         Level<T>& lv = h.lv[l];
         if (lv.tail) break;  // folded into the coarse product and [G Q] (the last level above the coarsest)
         if (lv.fold_pre) {  // R holds R (I - A w D^-1): restrict b itself
-            launch_mv<T>(s, lv.R, (const T*)lv.b, h.lv[l + 1].b, 0, stop, MvInit<T>{nullptr, nullptr, T(0)},
+            launch_mv<T>(s, lv.R, (const T*)lv.b, h.lv[l + 1].b, 0, MvInit<T>{nullptr, nullptr, T(0)},
                          MV_RESTRICT);
             continue;
         }
         if (l == 0) {
             // the finest operator is always SELL-64 (see tuned_spmat)
             EQS_LAUNCH_TIMED(c, EQS_KCLASS_PRESMOOTH0, (k_presmooth_res<1, T, double>), dim3(sell_grid(lv.A.sell)), b, 0,
-                             s, sview(lv), (const T*)lv.dinv, (T)lv.omega, r, lv.x, lv.res, stop);
+                             s, sview(lv), (const T*)lv.dinv, (T)lv.omega, r, lv.x, lv.res);
         } else {
-            launch_presmooth<T, T>(s, lv, (const T*)lv.b, stop);
+            launch_presmooth<T, T>(s, lv, (const T*)lv.b);
         }
         if (l + 1 < L - 1 || !h.lv[L - 1].coarse_R) {
             if (l == 0)
-                launch_mv_timed<T>(s, c, EQS_KCLASS_RESTRICT0, lv.R, (const T*)lv.res, h.lv[1].b, 0, stop,
+                launch_mv_timed<T>(s, c, EQS_KCLASS_RESTRICT0, lv.R, (const T*)lv.res, h.lv[1].b, 0,
                                    MV_RESTRICT);
             else
-                launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, stop, MvInit<T>{nullptr, nullptr, T(0)},
+                launch_mv<T>(s, lv.R, (const T*)lv.res, h.lv[l + 1].b, 0, MvInit<T>{nullptr, nullptr, T(0)},
                              MV_RESTRICT);
         }
         if (l == 0) prof_begin(c, EQS_KCLASS_VCOARSE, s);
@@ -1441,48 +1442,46 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         const Level<T>& la = h.lv[L - 2];
         if (lc.coarse_R)  // restriction (and, folded, the level above's pre-smoothing) and coarse solve in one product
             hipLaunchKernelGGL(k_coarse_restrict<T>, dim3((unsigned)lc.n), b, 0, s, (const T*)lc.coarse_R,
-                               (const T*)(la.tail ? la.b : la.res), lc.x, lc.n, lc.coarse_R_cols, stop);
+                               (const T*)(la.tail ? la.b : la.res), lc.x, lc.n, lc.coarse_R_cols);
         else
             hipLaunchKernelGGL(k_coarse<T>, dim3(grid_for((int64_t)lc.n * 64)), b, 0, s, (const T*)lc.dense_inv,
-                               (const T*)lc.b, lc.x, lc.n, stop);
+                               (const T*)lc.b, lc.x, lc.n);
     }
     // ascend
     for (int l = L - 2; l >= 0; --l) {
         Level<T>& lv = h.lv[l];
         if (lv.tail) {  // xs = G b + Q x_coarse on the stacked [b; x_coarse]
-            launch_mv<T>(s, lv.GQ, (const T*)lv.b, lv.xs, 0, stop);
+            launch_mv<T>(s, lv.GQ, (const T*)lv.b, lv.xs, 0);
             continue;
         }
         const T* xc = (l + 1 == L - 1) ? h.lv[l + 1].x : h.lv[l + 1].xs;
         if (l == 0) prof_end(c, EQS_KCLASS_VCOARSE, s);
         if (lv.fold_pre)  // x = w D^-1 b (the folded pre-smoother's result) + P xc
-            launch_mv<T>(s, lv.P, xc, lv.x, 2, stop, MvInit<T>{(const T*)lv.dinv, (const T*)lv.b, (T)lv.omega},
+            launch_mv<T>(s, lv.P, xc, lv.x, 2, MvInit<T>{(const T*)lv.dinv, (const T*)lv.b, (T)lv.omega},
                          MV_PROLONG);
         else if (l == 0)
-            launch_mv_timed<T>(s, c, EQS_KCLASS_PROLONG0, lv.P, xc, lv.x, 1, stop, MV_PROLONG);
+            launch_mv_timed<T>(s, c, EQS_KCLASS_PROLONG0, lv.P, xc, lv.x, 1, MV_PROLONG);
         else
-            launch_mv<T>(s, lv.P, xc, lv.x, 1, stop, MvInit<T>{nullptr, nullptr, T(0)}, MV_PROLONG);
+            launch_mv<T>(s, lv.P, xc, lv.x, 1, MvInit<T>{nullptr, nullptr, T(0)}, MV_PROLONG);
         if (l > 0) {
             launch_postsmooth<T>(s, c, l == 1 ? EQS_KCLASS_POSTSMOOTH1 : -1, lv, (const T*)lv.b, (const T*)lv.x,
-                                 lv.xs, stop);
+                                 lv.xs);
         } else {
             // the finest operator is always SELL-64 (see tuned_spmat)
             if (part_rz)
                 EQS_LAUNCH_TIMED(c, EQS_KCLASS_POSTSMOOTH0, (k_postsmooth<1, T, double, double, true>),
                                  dim3(sell_grid(lv.A.sell)), b, 0, s, view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega,
-                                 r, (const T*)lv.x, z, inst_map(c), part_rz, part_rzold, stop);
+                                 r, (const T*)lv.x, z, inst_map(c), part_rz, part_rzold);
             else
                 EQS_LAUNCH_TIMED(c, EQS_KCLASS_POSTSMOOTH0, (k_postsmooth<1, T, double, double, false>),
                                  dim3(sell_grid(lv.A.sell)), b, 0, s, view(lv.A.sell), (const T*)lv.dinv, (T)lv.omega,
-                                 r, (const T*)lv.x, z, InstMap{nullptr, nullptr, 0, -1}, nullptr, nullptr, stop);
+                                 r, (const T*)lv.x, z, InstMap{nullptr, nullptr, 0, -1}, nullptr, nullptr);
         }
     }
 }
 
-template void vcycle<double>(hipStream_t, eqs_ctx*, Hierarchy<double>&, const double*, double*, double*, double*,
-                             const int32_t*);
-template void vcycle<float>(hipStream_t, eqs_ctx*, Hierarchy<float>&, const double*, double*, double*, double*,
-                            const int32_t*);
+template void vcycle<double>(hipStream_t, eqs_ctx*, Hierarchy<double>&, const double*, double*, double*, double*);
+template void vcycle<float>(hipStream_t, eqs_ctx*, Hierarchy<float>&, const double*, double*, double*, double*);
 
 // ------------------------------------------------------------------ CG
 // Every instance runs its own CG (own scalars, own convergence test); the
@@ -1543,63 +1542,109 @@ __global__ __launch_bounds__(256) void k_pcg_residual_mx(InstMap m, const double
 }
 
 // q = M z + beta q, p = z + beta p (so q = M p without a second pass); pair partials of p.q.
+// stop (may be NULL) ends the launch at entry. ONE: a single instance; nothing in it waits for the scalars
+// before the row's loads are issued: they are read with vector loads issued first, and used by selects, not
+// branches (a branch on a loaded flag is waited for where the compiler places it, ahead of the loads). It
+// writes p and q even after the solve has converged: a finished solve, and a restart (beta = 0), read neither.
+template <bool ONE>
 __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_spmv(SellView<double> M, InstMap m, const double* __restrict__ z,
                                                    double* __restrict__ p, double* __restrict__ q,
                                                    double* __restrict__ part_pq, const PcgScalars* __restrict__ scal,
                                                    const int32_t* __restrict__ stop) {
     __shared__ double sh[kPairSh];
-    if (*stop) return;
+    if (stop && *stop) return;
     const int64_t B = row_block();
-    int32_t lo, bound;
-    block_instances(m, lo, bound, B);
     const int32_t row = (int32_t)(B * blockDim.x + threadIdx.x);
-    const bool second = row >= bound;
-    const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
     double pq = 0.0;
-    if (row < M.n_slices * 64) {
-        const double mz = sell_row(M, row, z);
-        if (row < M.n_rows && !S.done) {
-            double pi, qi;
-            if (S.fresh) {
-                pi = z[row];
-                qi = mz;
-            } else {
-                pi = z[row] + S.beta * p[row];
-                qi = mz + S.beta * q[row];
+    if constexpr (ONE) {
+        const double beta = vec_load(&scal->beta);
+        const int32_t fresh = vec_load(&scal->fresh);
+        const int32_t bound = m.rows1;
+        if (row < M.n_slices * 64) {
+            const double mz = sell_row(M, row, z);
+            if (row < M.n_rows) {
+                const double zi = z[row], po = p[row], qo = q[row];
+                const double pi = fresh ? zi : zi + beta * po;
+                const double qi = fresh ? mz : mz + beta * qo;
+                p[row] = pi;
+                q[row] = qi;
+                pq = pi * qi;
             }
-            p[row] = pi;
-            q[row] = qi;
-            pq = pi * qi;
         }
+        double* const parts[1] = {part_pq};
+        const double vals[1] = {pq};
+        store_pairs<1>(parts, vals, row >= bound, bound, sh, B);
+    } else {
+        int32_t lo, bound;
+        block_instances(m, lo, bound, B);
+        const bool second = row >= bound;
+        const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
+        if (row < M.n_slices * 64) {
+            const double mz = sell_row(M, row, z);
+            if (row < M.n_rows && !S.done) {
+                double pi, qi;
+                if (S.fresh) {
+                    pi = z[row];
+                    qi = mz;
+                } else {
+                    pi = z[row] + S.beta * p[row];
+                    qi = mz + S.beta * q[row];
+                }
+                p[row] = pi;
+                q[row] = qi;
+                pq = pi * qi;
+            }
+        }
+        double* const parts[1] = {part_pq};
+        const double vals[1] = {pq};
+        store_pairs<1>(parts, vals, second, bound, sh, B);
     }
-    double* const parts[1] = {part_pq};
-    const double vals[1] = {pq};
-    store_pairs<1>(parts, vals, second, bound, sh, B);
 }
-
-// x += alpha p, r -= alpha q; pair partials of |r|^2.
+// x += alpha p, r -= alpha q; pair partials of r.r. stop and ONE as for k_pcg_spmv: with one instance the done
+// flag selects the stored values (x and r written back unchanged once the solve has converged), so the four
+// streams' loads do not wait for it.
+template <bool ONE>
 __global__ __launch_bounds__(256) void k_pcg_update(InstMap m, double* __restrict__ x, double* __restrict__ r,
                                                      const double* __restrict__ p, const double* __restrict__ q,
                                                      int64_t n, double* __restrict__ part_rr,
                                                      const PcgScalars* __restrict__ scal,
                                                      const int32_t* __restrict__ stop) {
     __shared__ double sh[kPairSh];
-    if (*stop) return;
-    int32_t lo, bound;
-    block_instances(m, lo, bound, blockIdx.x);
+    if (stop && *stop) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool second = i >= bound;
-    const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
     double rr = 0.0;
-    if (i < n && !S.done) {
-        x[i] += S.alpha * p[i];
-        const double ri = r[i] - S.alpha * q[i];
-        r[i] = ri;
-        rr = ri * ri;
+    if constexpr (ONE) {
+        const double alpha = vec_load(&scal->alpha);
+        const int32_t done = vec_load(&scal->done);
+        const int32_t bound = m.rows1;
+        if (i < n) {
+            const double pi = p[i], qi = q[i], xi = x[i], ri0 = r[i];
+            __builtin_amdgcn_sched_barrier(0);  // the four loads are issued before anything waits
+            const double xn = xi + alpha * pi, rn = ri0 - alpha * qi;
+            x[i] = done ? xi : xn;
+            r[i] = done ? ri0 : rn;
+            rr = done ? 0.0 : rn * rn;
+        }
+        double* const parts[1] = {part_rr};
+        const double vals[1] = {rr};
+        store_pairs<1>(parts, vals, i >= bound, bound, sh, blockIdx.x);
+    } else {
+        int32_t lo, bound;
+        block_instances(m, lo, bound, blockIdx.x);
+        const bool second = i >= bound;
+        const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
+        if (i < n && !S.done) {
+            const double pi = p[i], qi = q[i], xi = x[i], ri0 = r[i];
+            __builtin_amdgcn_sched_barrier(0);  // the four loads are issued before anything waits
+            x[i] = xi + S.alpha * pi;
+            const double ri = ri0 - S.alpha * qi;
+            r[i] = ri;
+            rr = ri * ri;
+        }
+        double* const parts[1] = {part_rr};
+        const double vals[1] = {rr};
+        store_pairs<1>(parts, vals, second, bound, sh, blockIdx.x);
     }
-    double* const parts[1] = {part_rr};
-    const double vals[1] = {rr};
-    store_pairs<1>(parts, vals, second, bound, sh, blockIdx.x);
 }
 
 // x = 0 on the rows of instances whose right-hand side is zero.
@@ -1667,10 +1712,6 @@ __device__ void summarise(const PcgScalars* __restrict__ s, int32_t n, PcgSummar
 // struct, read, modified and written back, would keep the untouched fields in
 // LDS, and the loads into it would be waited for before the partials' loads
 // are issued).
-template <typename T>
-__device__ __forceinline__ T vec_load(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 struct FinIn {
     double rho, bb, tol2;
     int32_t it, maxit, done, fresh, flexible;
@@ -2067,21 +2108,26 @@ void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int 
     const int64_t nbM = sell_grid(c->M);
     const int64_t nbV = grid_for(c->n_free);
     const int32_t* stop = &c->d_sum->all_done;
+    // With one iteration per graph the CG SpMV and update do not test the flag either (the V-cycle never does;
+    // see vcycle): an iteration past convergence is rarely launched (the host waits once the residuals
+    // extrapolate to rtol), and it writes only partials and p and q, guarded for x and r by the instance's done
+    // flag. With several iterations per graph they test it, so that surplus iterations skip their SpMV and update.
+    const int32_t* vstop = c->graph_iters > 1 ? stop : nullptr;
     // z = B r, with pair partials of r.z (part 0) and r.z_old (part 1)
     prof_begin(c, EQS_KCLASS_VCYCLE, s);
-    if (precision == EQS_PREC_FP32) vcycle<float>(s, c, c->h32, c->d_r, c->d_z, part(c, 0), part(c, 1), stop);
-    else vcycle<double>(s, c, c->h64, c->d_r, c->d_z, part(c, 0), part(c, 1), stop);
+    if (precision == EQS_PREC_FP32) vcycle<float>(s, c, c->h32, c->d_r, c->d_z, part(c, 0), part(c, 1));
+    else vcycle<double>(s, c, c->h64, c->d_r, c->d_z, part(c, 0), part(c, 1));
     prof_end(c, EQS_KCLASS_VCYCLE, s);
     const InstMap im = inst_map(c);
     const bool one = im.rows1 >= 0;
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_beta<true> : k_fin_beta<false>, dim3(1), dim3(kFin), 0, s,
                      c->d_scal, im, part(c, 0), part(c, 1), stop);
-    EQS_LAUNCH_TIMED(c, EQS_KCLASS_SPMV_M, k_pcg_spmv, dim3(nbM), dim3(kBlock), 0, s, view(c->M), inst_map(c),
-                     c->d_z, c->d_p, c->d_q, part(c, 2), c->d_scal, stop);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_SPMV_M, one ? k_pcg_spmv<true> : k_pcg_spmv<false>, dim3(nbM), dim3(kBlock), 0,
+                     s, view(c->M), im, c->d_z, c->d_p, c->d_q, part(c, 2), c->d_scal, vstop);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_alpha<true> : k_fin_alpha<false>, dim3(1), dim3(kFin), 0,
                      s, c->d_scal, im, part(c, 2), stop);
-    EQS_LAUNCH_TIMED(c, EQS_KCLASS_CG_UPDATE, k_pcg_update, dim3(nbV), dim3(kBlock), 0, s, inst_map(c), x, c->d_r,
-                     c->d_p, c->d_q, c->n_free, part(c, 3), c->d_scal, stop);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_CG_UPDATE, one ? k_pcg_update<true> : k_pcg_update<false>, dim3(nbV),
+                     dim3(kBlock), 0, s, im, x, c->d_r, c->d_p, c->d_q, c->n_free, part(c, 3), c->d_scal, vstop);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_conv<true> : k_fin_conv<false>, dim3(1), dim3(kFin), 0, s,
                      c->d_scal, im, part(c, 3), c->d_sum, c->d_hsum, c->d_hscal);
 }

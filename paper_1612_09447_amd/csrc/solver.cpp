@@ -190,8 +190,8 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
 }
 
 void apply_preconditioner(eqs_ctx* c, const double* r, double* z) {
-    if (c->amg.precision == EQS_PREC_FP32) vcycle<float>(c->stream, c, c->h32, r, z, nullptr, nullptr, nullptr);
-    else vcycle<double>(c->stream, c, c->h64, r, z, nullptr, nullptr, nullptr);
+    if (c->amg.precision == EQS_PREC_FP32) vcycle<float>(c->stream, c, c->h32, r, z, nullptr, nullptr);
+    else vcycle<double>(c->stream, c, c->h64, r, z, nullptr, nullptr);
     check_launch();
     EQS_HIP(hipStreamSynchronize(c->stream));
 }
