@@ -627,7 +627,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32" if main_prec == EQS_PREC_FP32 else "f64",  # FP64 CG and element pass, FP32 V-cycle
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: unit cube, {case.n}^3 sub-cubes x 6 P1 tets ({case.n_tets} tets, "
