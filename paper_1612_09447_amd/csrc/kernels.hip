@@ -1121,25 +1121,33 @@ static CsrView<T> scview(const Level<T>& lv) {
     return v;
 }
 
+// Entries per lane in flight in a CSR row: with 64 lanes per row (the tuner
+// gives rows of hundreds of entries 64 lanes; the folded restriction of the
+// 2.1M-DOF hierarchy has 614 per row) 16 for FP32 values, one round of loads
+// instead of three, and 8 for FP64 (16 would spill at 8 waves per SIMD); else 4.
+template <int L, typename T>
+constexpr int csr_group() { return L >= 64 ? (sizeof(T) == 4 ? 16 : 8) : 4; }
+
 // Row sum of A (lanes of one group split the row), with x_j given by f(j).
 template <int L, typename T, typename F>
 __device__ __forceinline__ T csr_row(const CsrView<T>& A, int32_t row, int lane, F f) {
-    // each lane takes entries lane, lane + L, ... of the row, four at a time:
+    // each lane takes entries lane, lane + L, ... of the row, U at a time:
     // positions past the row's end re-read its last entry and are dropped by a
     // select, so the loads carry no branch; the lane's sum runs in entry order
+    constexpr int U = csr_group<L, T>();
     T acc = T(0);
     const int32_t end = A.rp[row + 1];
     const int32_t base = offset_base(row, A.n_rows, A.n_cols);
-    for (int32_t k = A.rp[row] + lane; k < end; k += 4 * L) {
-        T t[4];
+    for (int32_t k = A.rp[row] + lane; k < end; k += U * L) {
+        T t[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int32_t kk = min(k + u * L, end - 1);
             const int32_t j = A.d16 ? base + (int32_t)A.d16[kk] : A.col[kk];
             t[u] = A.val[kk] * f(j);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc += (k + u * L < end) ? t[u] : T(0);
+        for (int u = 0; u < U; ++u) acc += (k + u * L < end) ? t[u] : T(0);
     }
     return group_sum<L>(acc);
 }
@@ -1330,29 +1338,37 @@ __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const
 }
 
 // Coarsest level with the restriction folded in: x = (A^{-1} R) r, one
-// workgroup per coarse row of the dense row-major product matrix C. Each thread
-// sums its columns j = t, t + 256, ... eight at a time (loads in flight
-// together), then the block sums in a fixed order.
+// workgroup of kCoarseThreads threads per coarse row of the dense row-major
+// product matrix C. Each thread sums its columns j = t, t + kCoarseThreads, ...
+// eight at a time (loads in flight together: one round covers 8192 columns),
+// then the block sums in a fixed order.
+constexpr int kCoarseThreads = 1024;
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_restrict(const T* __restrict__ C, const T* __restrict__ r,
-                                                          T* __restrict__ x, int32_t n, int32_t nf) {
-    __shared__ double sh[4];
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_restrict(const T* __restrict__ C, const T* __restrict__ r,
+                                                                     T* __restrict__ x, int32_t n, int32_t nf) {
+    __shared__ double sh[kCoarseThreads / 64];
     const int32_t i = blockIdx.x;
     const T* row = C + (int64_t)i * nf;
     T acc = T(0);
-    for (int32_t j0 = threadIdx.x; j0 < nf; j0 += 8 * 256) {
+    for (int32_t j0 = threadIdx.x; j0 < nf; j0 += 8 * kCoarseThreads) {
         T t[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int32_t j = min(j0 + u * 256, nf - 1);
+            const int32_t j = min(j0 + u * kCoarseThreads, nf - 1);
             t[u] = row[j] * r[j];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += (j0 + u * 256 < nf) ? t[u] : T(0);
+        for (int u = 0; u < 8; ++u) acc += (j0 + u * kCoarseThreads < nf) ? t[u] : T(0);
     }
-    double v[1] = {(double)acc};
-    block_sums<1>(v, sh);
-    if (threadIdx.x == 0 && i < n) x[i] = (T)v[0];
+    double v = (double)acc;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0 && i < n) {
+        double t = 0.0;
+        for (int w = 0; w < kCoarseThreads / 64; ++w) t += sh[w];
+        x[i] = (T)t;
+    }
 }
 
 // Single-level hierarchy: z = A^{-1} r with the same r.z partials as k_postsmooth.
@@ -1441,8 +1457,9 @@ void vcycle(hipStream_t s, eqs_ctx* c, Hierarchy<T>& h, const double* r, double*
         Level<T>& lc = h.lv[L - 1];
         const Level<T>& la = h.lv[L - 2];
         if (lc.coarse_R)  // restriction (and, folded, the level above's pre-smoothing) and coarse solve in one product
-            hipLaunchKernelGGL(k_coarse_restrict<T>, dim3((unsigned)lc.n), b, 0, s, (const T*)lc.coarse_R,
-                               (const T*)(la.tail ? la.b : la.res), lc.x, lc.n, lc.coarse_R_cols);
+            hipLaunchKernelGGL(k_coarse_restrict<T>, dim3((unsigned)lc.n), dim3(kCoarseThreads), 0, s,
+                               (const T*)lc.coarse_R, (const T*)(la.tail ? la.b : la.res), lc.x, lc.n,
+                               lc.coarse_R_cols);
         else
             hipLaunchKernelGGL(k_coarse<T>, dim3(grid_for((int64_t)lc.n * 64)), b, 0, s, (const T*)lc.dense_inv,
                                (const T*)lc.b, lc.x, lc.n);
