@@ -72,6 +72,7 @@ struct Sell {
     int16_t* d16 = nullptr;     // [stored] column - offset_base(row) when every entry allows
     T* val = nullptr;           // [stored]
     uint8_t* perm = nullptr;    // [n_slices * 64 / lanes] row order within 256-thread windows, or NULL
+    int32_t xcd = 0;            // 1: products walk row blocks in the XCD order (row_block in sell.h)
 };
 
 // A hierarchy operator in one of two layouts, chosen per matrix by timing

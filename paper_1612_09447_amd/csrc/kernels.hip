@@ -978,7 +978,7 @@ __device__ __forceinline__ void mv_store(T* __restrict__ y, int32_t row, T v, in
 template <int L, int U, typename T>
 __device__ __forceinline__ void sell_mv(const SellView<T>& A, const T* __restrict__ x, T* __restrict__ y, int acc,
                                         const MvInit<T>& in) {
-    const int64_t g = row_block() * blockDim.x + threadIdx.x;
+    const int64_t g = row_block(A.xcd) * blockDim.x + threadIdx.x;
     if (g >= (int64_t)A.n_slices * 64) return;  // whole wavefronts leave together
     const int32_t row = sell_perm_row<L>(A.perm, g);
     const bool writer = (g & (L - 1)) == 0 && row < A.n_rows;
@@ -1027,7 +1027,7 @@ static SellMvKernel<L, U, T> sell_mv_kernel(int role) {
 
 __global__ __launch_bounds__(256, kSparseWaves) void k_spmv64(SellView<double> A, const double* __restrict__ x,
                                                  double* __restrict__ y) {
-    const int32_t row = (int32_t)(row_block() * blockDim.x + threadIdx.x);
+    const int32_t row = (int32_t)(row_block(A.xcd) * blockDim.x + threadIdx.x);
     if (row >= A.n_slices * 64) return;
     const double v = sell_row(A, row, x);
     if (row < A.n_rows) y[row] = v;
@@ -1046,7 +1046,7 @@ template <int L, typename T, typename TB, int U = 8>
 __global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_presmooth_res(SellView<T> As, const T* __restrict__ dinv, T omega,
                                                         const TB* __restrict__ b, T* __restrict__ x,
                                                         T* __restrict__ res) {
-    const int64_t g = row_block() * blockDim.x + threadIdx.x;
+    const int64_t g = row_block(As.xcd) * blockDim.x + threadIdx.x;
     if (g >= (int64_t)As.n_slices * 64) return;
     const int32_t row = sell_row_of<L>(g);
     const T acc = sell_row<L, U>(As, g, row, b);
@@ -1068,7 +1068,7 @@ __global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_postsmoot
                                                      double* __restrict__ part_rzold) {
     static_assert(!DOT || L == 1, "CG partials are produced by the one-lane-per-row finest level");
     __shared__ double sh[kPairSh];
-    const int64_t B = row_block();
+    const int64_t B = row_block(A.xcd);
     const int64_t g = B * blockDim.x + threadIdx.x;
     const int32_t row = sell_row_of<L>(g);
     double rz = 0.0, rzo = 0.0;
@@ -1155,7 +1155,7 @@ __device__ __forceinline__ T csr_row(const CsrView<T>& A, int32_t row, int lane,
 template <int L, typename T>
 __global__ __launch_bounds__(256, kSparseWaves) void k_csr_mv(CsrView<T> A, const T* __restrict__ x, T* __restrict__ y, int acc,
                                                  MvInit<T> in) {
-    const int64_t g = row_block() * blockDim.x + threadIdx.x;
+    const int64_t g = row_block(0) * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
     if (row >= A.n_rows) return;  // whole groups leave together
@@ -1167,7 +1167,7 @@ template <int L, typename T, typename TB>
 __global__ __launch_bounds__(256, kSparseWaves) void k_csr_presmooth_res(CsrView<T> As, const T* __restrict__ dinv, T omega,
                                                             const TB* __restrict__ b, T* __restrict__ x,
                                                             T* __restrict__ res) {
-    const int64_t g = row_block() * blockDim.x + threadIdx.x;
+    const int64_t g = row_block(0) * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
     if (row >= As.n_rows) return;
@@ -1183,7 +1183,7 @@ template <int L, typename T, typename TB, typename TO>
 __global__ __launch_bounds__(256, kSparseWaves) void k_csr_postsmooth(CsrView<T> A, const T* __restrict__ dinv, T omega,
                                                          const TB* __restrict__ b, const T* __restrict__ x,
                                                          TO* __restrict__ out) {
-    const int64_t g = row_block() * blockDim.x + threadIdx.x;
+    const int64_t g = row_block(0) * blockDim.x + threadIdx.x;
     const int32_t row = (int32_t)(g / L);
     const int lane = (int)(g % L);
     if (row >= A.n_rows) return;
@@ -1513,7 +1513,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_residual(SellView<dou
                                                        double* __restrict__ mx_out, const int32_t* __restrict__ when_done) {
     __shared__ double sh[kPairSh];
     if (when_done && !*when_done) return;  // queued ahead of the host's decision: only once every instance is done
-    const int64_t B = row_block();
+    const int64_t B = row_block(M.xcd);
     const int32_t row = (int32_t)(B * blockDim.x + threadIdx.x);
     double rr = 0.0, bb = 0.0;
     if (row < M.n_slices * 64) {
@@ -1570,7 +1570,7 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_spmv(SellView<double>
                                                    const int32_t* __restrict__ stop) {
     __shared__ double sh[kPairSh];
     if (stop && *stop) return;
-    const int64_t B = row_block();
+    const int64_t B = row_block(M.xcd);
     const int32_t row = (int32_t)(B * blockDim.x + threadIdx.x);
     double pq = 0.0;
     if constexpr (ONE) {
@@ -1619,16 +1619,18 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_spmv(SellView<double>
 }
 // x += alpha p, r -= alpha q; pair partials of r.r. stop and ONE as for k_pcg_spmv: with one instance the done
 // flag selects the stored values (x and r written back unchanged once the solve has converged), so the four
-// streams' loads do not wait for it.
+// streams' loads do not wait for it. xcd: M's block order, so that each workgroup reads the p and q rows the SpMV
+// wrote on the same XCD.
 template <bool ONE>
 __global__ __launch_bounds__(256) void k_pcg_update(InstMap m, double* __restrict__ x, double* __restrict__ r,
                                                      const double* __restrict__ p, const double* __restrict__ q,
                                                      int64_t n, double* __restrict__ part_rr,
                                                      const PcgScalars* __restrict__ scal,
-                                                     const int32_t* __restrict__ stop) {
+                                                     const int32_t* __restrict__ stop, int32_t xcd) {
     __shared__ double sh[kPairSh];
     if (stop && *stop) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t B = row_block(xcd);
+    const int64_t i = B * blockDim.x + threadIdx.x;
     double rr = 0.0;
     if constexpr (ONE) {
         const double alpha = vec_load(&scal->alpha);
@@ -1644,10 +1646,10 @@ __global__ __launch_bounds__(256) void k_pcg_update(InstMap m, double* __restric
         }
         double* const parts[1] = {part_rr};
         const double vals[1] = {rr};
-        store_pairs<1>(parts, vals, i >= bound, bound, sh, blockIdx.x);
+        store_pairs<1>(parts, vals, i >= bound, bound, sh, B);
     } else {
         int32_t lo, bound;
-        block_instances(m, lo, bound, blockIdx.x);
+        block_instances(m, lo, bound, B);
         const bool second = i >= bound;
         const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
         if (i < n && !S.done) {
@@ -1660,7 +1662,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(InstMap m, double* __restric
         }
         double* const parts[1] = {part_rr};
         const double vals[1] = {rr};
-        store_pairs<1>(parts, vals, second, bound, sh, blockIdx.x);
+        store_pairs<1>(parts, vals, second, bound, sh, B);
     }
 }
 
@@ -2144,7 +2146,8 @@ void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int 
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_alpha<true> : k_fin_alpha<false>, dim3(1), dim3(kFin), 0,
                      s, c->d_scal, im, part(c, 2), stop);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_CG_UPDATE, one ? k_pcg_update<true> : k_pcg_update<false>, dim3(nbV),
-                     dim3(kBlock), 0, s, im, x, c->d_r, c->d_p, c->d_q, c->n_free, part(c, 3), c->d_scal, vstop);
+                     dim3(kBlock), 0, s, im, x, c->d_r, c->d_p, c->d_q, c->n_free, part(c, 3), c->d_scal, vstop,
+                     c->M.xcd);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_conv<true> : k_fin_conv<false>, dim3(1), dim3(kFin), 0, s,
                      c->d_scal, im, part(c, 3), c->d_sum, c->d_hsum, c->d_hscal);
 }

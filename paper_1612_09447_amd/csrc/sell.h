@@ -26,22 +26,24 @@ __device__ __forceinline__ T group_sum(T v) {
 }
 
 // Row blocks of the sparse kernels. The hardware deals the workgroups of a
-// launch to its 8 XCDs round-robin (workgroup i to XCD i mod 8); with
-// EQS_BLOCK_ORDER_XCD set, workgroup i takes row block xcd_block(i, nb), so
-// each XCD walks one contiguous range of row blocks and the vector entries
-// its rows gather meet in that XCD's L2. Measured on the 2.1M-DOF workload it
-// changed no sparse kernel by more than run-to-run noise (the 256 MB
-// Infinity Cache serves the other XCDs' misses), so the natural order is the
-// default. Partial sums are indexed by row block either way.
-#ifndef EQS_BLOCK_ORDER_XCD
-#define EQS_BLOCK_ORDER_XCD 0
-#endif
+// launch to its 8 XCDs round-robin (workgroup i to XCD i mod 8). In the XCD
+// order (an operator's `xcd` flag) workgroup i takes row block
+// xcd_block(i, nb), so each XCD walks one contiguous range of row blocks and
+// the vector entries its rows gather meet in that XCD's L2 instead of being
+// fetched by several L2s. On the 2.1M-DOF workload this cut the counted
+// traffic of the finest level's kernels (CG SpMV 267 -> 232 MB per launch,
+// pre-smoother 168 -> 133 MB, post-smoother 177 -> 158 MB) and their times
+// (post-smoother 26.7 -> 25.1 us), while the transfer products between the
+// finest two levels and the level-1 smoother became slower (the restriction
+// 22.9 -> 24.3 us), so M and the finest level's operator take the XCD order
+// and the others the natural one. Partial sums are indexed by row block
+// either way.
 __device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t nb) {
     const int64_t q = nb >> 3, r = nb & 7, x = i & 7;
     return x * q + (x < r ? x : r) + (i >> 3);
 }
-__device__ __forceinline__ int64_t row_block() {
-    return EQS_BLOCK_ORDER_XCD ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+__device__ __forceinline__ int64_t row_block(int32_t xcd) {
+    return xcd ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
 }
 
 // The row served by global thread g of a SELL kernel with L lanes per row.
@@ -58,11 +60,12 @@ struct SellView {
     const T* __restrict__ val;
     int32_t n_rows, n_slices, n_cols;
     const uint8_t* __restrict__ perm;  // row order within each 256-thread window, or NULL (see sell_perm_row)
+    int32_t xcd;                       // block order of its products (see row_block)
 };
 
 template <typename T>
 static inline SellView<T> view(const Sell<T>& A) {
-    return SellView<T>{A.sptr, A.col, A.d16, A.val, A.n_rows, A.n_slices, A.n_cols, A.perm};
+    return SellView<T>{A.sptr, A.col, A.d16, A.val, A.n_rows, A.n_slices, A.n_cols, A.perm, A.xcd};
 }
 
 // With a row order (perm), the rows served by one 256-thread window (4

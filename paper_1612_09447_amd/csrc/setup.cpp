@@ -915,6 +915,7 @@ static SpMat<T> tuned_spmat(eqs_ctx* c, const Csr<double>& A, const char* what, 
         S.n_rows = A.n_rows; S.n_cols = A.n_cols; S.nnz = A.nnz();
         S.fmt = FMT_SELL;
         S.sell = to_sell<T>(c, A, 1);
+        S.sell.xcd = 1;  // the finest smoothers walk their row blocks in the XCD order (row_block in sell.h)
         c->tune_log += std::string(what) + ": sell64 (finest level), " +
                        (S.sell.d16 ? "16-bit column offsets\n" : "32-bit columns\n");
         return S;
@@ -1534,6 +1535,7 @@ void upload(eqs_ctx* c) {
     Csr<double> M = assemble_M_free(c);
     c->nnz_M = M.nnz();
     c->M = to_sell<double>(c, M, 1);
+    c->M.xcd = 1;  // the CG SpMV walks its row blocks in the XCD order (row_block in sell.h)
     c->tune_log += std::string("M: sell64, ") + (c->M.d16 ? "16-bit column offsets\n" : "32-bit columns\n");
     AmgHost ah = build_sa_amg(M, c->amg);
     if (c->amg.precision == EQS_PREC_FP32) upload_hierarchy<float>(c, ah, c->h32, nullptr);
