@@ -43,7 +43,7 @@ static void check_launch() {
 // The kernels of one CG iteration take every scalar from device memory, so a
 // single captured graph replays any iteration of any solve into the same x.
 // One graph holds c->graph_iters iterations (a launch runs that many; those
-// past convergence return at entry). Graphs are skipped on the null stream
+// past convergence change nothing, see pcg_iteration). Graphs are skipped on the null stream
 // and while kernels of the iteration are being timed individually (then the
 // iterations are launched one by one).
 static void run_iteration(eqs_ctx* c, double* x, int prec) {
@@ -100,7 +100,7 @@ int solve_M(eqs_ctx* c, const double* rhs, double* y, double rtol, int32_t maxit
     check_launch();
     // Iterations are enqueued without waiting for the start's result: an
     // instance that is already done leaves its rows alone, and once all are
-    // done every kernel returns at entry.
+    // done an iteration changes nothing (see pcg_iteration).
     PcgSummary v{};
     int restarts = 0;
     int32_t it_before = 0;
