@@ -1027,9 +1027,10 @@ static SellMvKernel<L, U, T> sell_mv_kernel(int role) {
 
 __global__ __launch_bounds__(256, kSparseWaves) void k_spmv64(SellView<double> A, const double* __restrict__ x,
                                                  double* __restrict__ y) {
-    const int32_t row = (int32_t)(row_block(A.xcd) * blockDim.x + threadIdx.x);
-    if (row >= A.n_slices * 64) return;
-    const double v = sell_row(A, row, x);
+    const int64_t g = row_block(A.xcd) * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)A.n_slices * 64) return;
+    const int32_t row = sell_perm_row<1>(A.perm, g);  // M may store its rows in a row order
+    const double v = sell_row<1>(A, g, row, x);
     if (row < A.n_rows) y[row] = v;
 }
 
@@ -1048,7 +1049,7 @@ __global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_presmooth
                                                         T* __restrict__ res) {
     const int64_t g = row_block(As.xcd) * blockDim.x + threadIdx.x;
     if (g >= (int64_t)As.n_slices * 64) return;
-    const int32_t row = sell_row_of<L>(g);
+    const int32_t row = sell_perm_row<L>(As.perm, g);  // the finest operator may store its rows in a row order
     const T acc = sell_row<L, U>(As, g, row, b);
     if ((g & (L - 1)) == 0 && row < As.n_rows) {
         const T bi = (T)b[row];
@@ -1070,7 +1071,7 @@ __global__ __launch_bounds__(256, (U >= 16 ? 4 : kSparseWaves)) void k_postsmoot
     __shared__ double sh[kPairSh];
     const int64_t B = row_block(A.xcd);
     const int64_t g = B * blockDim.x + threadIdx.x;
-    const int32_t row = sell_row_of<L>(g);
+    const int32_t row = sell_perm_row<L>(A.perm, g);  // the finest operator may store its rows in a row order
     double rz = 0.0, rzo = 0.0;
     if (g < (int64_t)A.n_slices * 64) {
         const T ax = sell_row<L, U>(A, g, row, x);
@@ -1510,10 +1511,11 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_residual(SellView<dou
     __shared__ double sh[kPairSh];
     if (when_done && !*when_done) return;  // queued ahead of the host's decision: only once every instance is done
     const int64_t B = row_block(M.xcd);
-    const int32_t row = (int32_t)(B * blockDim.x + threadIdx.x);
+    const int64_t g = B * blockDim.x + threadIdx.x;
+    const int32_t row = sell_perm_row<1>(M.perm, g);  // the row order, if any, stays inside the block's rows
     double rr = 0.0, bb = 0.0;
-    if (row < M.n_slices * 64) {
-        const double mx = sell_row(M, row, x);
+    if (g < (int64_t)M.n_slices * 64) {
+        const double mx = sell_row<1>(M, g, row, x);
         if (row < M.n_rows) {
             const double bi = rhs[row];
             const double ri = bi - mx;
@@ -1567,14 +1569,15 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_spmv(SellView<double>
     __shared__ double sh[kPairSh];
     if (stop && *stop) return;
     const int64_t B = row_block(M.xcd);
-    const int32_t row = (int32_t)(B * blockDim.x + threadIdx.x);
+    const int64_t g = B * blockDim.x + threadIdx.x;
+    const int32_t row = sell_perm_row<1>(M.perm, g);  // the row order, if any, stays inside the block's rows
     double pq = 0.0;
     if constexpr (ONE) {
         const double beta = vec_load(&scal->beta);
         const int32_t fresh = vec_load(&scal->fresh);
         const int32_t bound = m.rows1;
-        if (row < M.n_slices * 64) {
-            const double mz = sell_row(M, row, z);
+        if (g < (int64_t)M.n_slices * 64) {
+            const double mz = sell_row<1>(M, g, row, z);
             if (row < M.n_rows) {
                 const double zi = z[row], po = p[row], qo = q[row];
                 const double pi = fresh ? zi : zi + beta * po;
@@ -1592,8 +1595,8 @@ __global__ __launch_bounds__(256, kSparseWaves) void k_pcg_spmv(SellView<double>
         block_instances(m, lo, bound, B);
         const bool second = row >= bound;
         const PcgScalars& S = scal[min(second ? lo + 1 : lo, m.n_inst - 1)];
-        if (row < M.n_slices * 64) {
-            const double mz = sell_row(M, row, z);
+        if (g < (int64_t)M.n_slices * 64) {
+            const double mz = sell_row<1>(M, g, row, z);
             if (row < M.n_rows && !S.done) {
                 double pi, qi;
                 if (S.fresh) {

@@ -70,8 +70,10 @@ static inline SellView<T> view(const Sell<T>& A) {
 
 // With a row order (perm), the rows served by one 256-thread window (4
 // slices, 256 / L rows) are stored longest first, so the slices of the window
-// pad less; position k of the window serves row window_base + perm[k]. Only
-// products y = A x use it (they write y[row] of their own window only).
+// pad less; position k of the window serves row window_base + perm[k]. The
+// kernels that use it write only rows of their own window (products y = A x,
+// the CG SpMV and residual, the finest smoothers), so the rows of a workgroup,
+// and with them its partial sums, are the same with and without it.
 template <int L>
 __device__ __forceinline__ int32_t sell_perm_row(const uint8_t* __restrict__ perm, int64_t g) {
     const int32_t pos = sell_row_of<L>(g);
