@@ -1254,7 +1254,6 @@ static void launch_mv_timed(hipStream_t s, eqs_ctx* c, int cls, const SpMat<T>& 
 
 template <typename T, typename TB>
 static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b) {
-    if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
     if (lv.A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
                               EQS_UNROLL_SWITCH(lv.A.sell.unroll,
@@ -1273,7 +1272,6 @@ static void launch_presmooth(hipStream_t s, const Level<T>& lv, const TB* b) {
 // `cls` when that class is profiled.
 template <typename T>
 static void launch_postsmooth(hipStream_t s, eqs_ctx* c, int cls, const Level<T>& lv, const T* b, const T* x, T* out) {
-    if (lv.A.fmt == FMT_SELL && lv.A.sell.perm) fail(EQS_ERR_STATE, "smoother operator with a row order");
     if (lv.A.fmt == FMT_SELL) {
         EQS_SELL_LANES_SWITCH(lv.A.sell.lanes,
                               EQS_UNROLL_SWITCH(lv.A.sell.unroll,

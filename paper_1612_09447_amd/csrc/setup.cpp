@@ -926,8 +926,8 @@ static void free_spmat(eqs_ctx* c, SpMat<T>& S) {
 
 // Autotuner: upload the operator in every candidate layout (SELL with 1 lane
 // per row, and with 2, 4, 8 while each lane keeps 1.5 entries or more, each
-// also with rows sorted by length within 256-thread windows when the operator
-// is only used in products y = A x;
+// also with rows sorted by length within 256-thread windows (the products and
+// the smoothers write only rows of their own window);
 // CSR with L = 2..64 lanes per row up to about twice the mean row length, and
 // with one lane per row for rows of up to 8 entries on average), time y = A x
 // with HIP events on the context's stream (median of 5 rounds of 8 back-to-back launches, after a warm-up round) and
@@ -1177,7 +1177,8 @@ static void upload_hierarchy(eqs_ctx* c, const AmgHost& ah, Hierarchy<T>& h, con
     for (size_t l = 0; l < L; ++l) {
         Level<T>& lv = h.lv[l];
         lv.n = ah.A[l].n_rows;
-        lv.A = tuned_spmat<T>(c, ah.A[l], ("A" + std::to_string(l)).c_str(), l == 0);
+        // coarse operators may take a row order too: their smoothers write only rows of their own window
+        lv.A = tuned_spmat<T>(c, ah.A[l], ("A" + std::to_string(l)).c_str(), l == 0, l > 0);
         std::vector<double> d = diagonal(ah.A[l]);
         std::vector<T> dinv(lv.n);
         for (int32_t i = 0; i < lv.n; ++i) dinv[i] = (T)(1.0 / d[i]);
