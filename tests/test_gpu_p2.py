@@ -65,9 +65,14 @@ def test_p2_element_pass_and_rhs_match_oracle(maker, generic, monkeypatch):
 
 
 def test_p2_M_product_and_solve():
+    """The M product and an AMG-PCG solve; second-order M (vertex and edge rows of
+    different lengths alternating) is stored with its rows sorted by length
+    within 256-row windows, a path this test therefore covers."""
     case = eqsgen.case_p2(n=10, seed=3)
     o = EqsOracle(case, dense_limit=0)
     with ctx_for(case, EQS_PREC_FP32) as c:
+        d = c.describe()
+        assert "M: sell64s" in d and "A0: sell64s" in d, d
         info = c.info()
         assert info["n_free"] == o.n_free
         x = np.random.default_rng(5).normal(size=o.n_free)

@@ -130,6 +130,8 @@ def test_apply_M_matches_oracle():
         d = o.M_II.diagonal()
         keep = (A.row == A.col) | (np.abs(A.data) > 1e-14 * np.sqrt(np.abs(d[A.row] * d[A.col])))
         assert info["n_free"] == o.n_free and info["nnz_M"] == int(keep.sum())
+        # nearly uniform first-order rows keep the natural row order (second-order M sorts; tests/test_gpu_p2.py)
+        assert "M: sell64," in c.describe()
         x = np.random.default_rng(0).normal(size=o.n_free)
         y = torch.zeros(o.n_free, dtype=torch.float64, device=DEV)
         c.apply_M(T(x), y)
