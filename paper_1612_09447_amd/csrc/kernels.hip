@@ -190,69 +190,54 @@ __device__ __forceinline__ void wave_range_sums(const double* const (&parts)[NP]
 constexpr int kFinWaves = kFin / 64;
 
 // Per-instance sums of NP pair-partial arrays, in a fixed order (the result
-// does not depend on timing). With at most kFinWaves instances every instance
-// gets kFinWaves / n_inst wavefronts, each summing an equal share of its
-// blocks; otherwise wavefronts take whole instances in turn. body(i, sums)
-// runs once per instance, in one thread. Must be reached by the whole block.
+// does not depend on timing). A finaliser runs one workgroup per kFinWaves
+// instances (fin_grid): the instances i0 = kFinWaves * blockIdx.x onwards of
+// this workgroup each get kFinWaves / count wavefronts, each summing an equal
+// share of the instance's blocks, so every instance's sums are in flight at
+// once. body(i, sums) runs once per instance, in thread i - i0. Must be
+// reached by the whole block.
 template <int NP, typename F>
 __device__ __forceinline__ void for_each_instance_sum(const double* const (&parts)[NP], const InstMap& m, F body) {
     __shared__ double sh[NP][kFinWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (m.n_inst <= kFinWaves) {
-        const int wpi = kFinWaves / m.n_inst;
-        const int i = wave / wpi, sub = wave - i * wpi;
-        double v[NP];
+    const int32_t i0 = (int32_t)blockIdx.x * kFinWaves;
+    const int32_t cnt = max(1, min(kFinWaves, m.n_inst - i0));
+    const int wpi = kFinWaves / cnt;
+    const int li = wave / wpi, sub = wave - li * wpi;
+    double v[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) v[p] = 0.0;
-        if (i < m.n_inst) {
-            int32_t b0, b1, head;
-            inst_blocks(m, i, b0, b1, head);
-            if (b1 >= b0) {
-                const int32_t first = b0 + 1, n = b1 - b0;  // blocks first..b1 read their first partial
-                const int32_t lo = first + (int32_t)(((int64_t)n * sub) / wpi);
-                const int32_t hi = first + (int32_t)(((int64_t)n * (sub + 1)) / wpi) - 1;
-                // the head block's partial is loaded with the range's, not after it
-                double hv[NP];
+    for (int p = 0; p < NP; ++p) v[p] = 0.0;
+    if (li < cnt && i0 + li < m.n_inst) {
+        int32_t b0, b1, head;
+        inst_blocks(m, i0 + li, b0, b1, head);
+        if (b1 >= b0) {
+            const int32_t first = b0 + 1, n = b1 - b0;  // blocks first..b1 read their first partial
+            const int32_t lo = first + (int32_t)(((int64_t)n * sub) / wpi);
+            const int32_t hi = first + (int32_t)(((int64_t)n * (sub + 1)) / wpi) - 1;
+            // the head block's partial is loaded with the range's, not after it
+            double hv[NP];
 #pragma unroll
-                for (int p = 0; p < NP; ++p) hv[p] = sub == 0 ? parts[p][2 * (int64_t)b0 + head] : 0.0;
-                wave_range_sums<NP>(parts, lo, hi, v);
-                if (sub == 0)
+            for (int p = 0; p < NP; ++p) hv[p] = sub == 0 ? parts[p][2 * (int64_t)b0 + head] : 0.0;
+            wave_range_sums<NP>(parts, lo, hi, v);
+            if (sub == 0)
 #pragma unroll
-                    for (int p = 0; p < NP; ++p) v[p] += hv[p];
-            }
+                for (int p = 0; p < NP; ++p) v[p] += hv[p];
         }
-        if (lane == 0)
+    }
+    if (lane == 0)
 #pragma unroll
-            for (int p = 0; p < NP; ++p) sh[p][wave] = v[p];
-        __syncthreads();
-        if ((int32_t)threadIdx.x < m.n_inst) {
-            const int32_t k = threadIdx.x;
-            double sums[NP];
+        for (int p = 0; p < NP; ++p) sh[p][wave] = v[p];
+    __syncthreads();
+    if ((int32_t)threadIdx.x < cnt && i0 + (int32_t)threadIdx.x < m.n_inst) {
+        const int32_t k = threadIdx.x;
+        double sums[NP];
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                double t = 0.0;
-                for (int w = k * wpi; w < (k + 1) * wpi; ++w) t += sh[p][w];
-                sums[p] = t;
-            }
-            body(k, sums);
+        for (int p = 0; p < NP; ++p) {
+            double t = 0.0;
+            for (int w = k * wpi; w < (k + 1) * wpi; ++w) t += sh[p][w];
+            sums[p] = t;
         }
-    } else {
-        for (int32_t i = wave; i < m.n_inst; i += kFinWaves) {
-            int32_t b0, b1, head;
-            inst_blocks(m, i, b0, b1, head);
-            double sums[NP];
-#pragma unroll
-            for (int p = 0; p < NP; ++p) sums[p] = 0.0;
-            if (b1 >= b0) {
-                double hv[NP];
-#pragma unroll
-                for (int p = 0; p < NP; ++p) hv[p] = parts[p][2 * (int64_t)b0 + head];
-                wave_range_sums<NP>(parts, b0 + 1, b1, sums);
-#pragma unroll
-                for (int p = 0; p < NP; ++p) sums[p] += hv[p];
-            }
-            if (lane == 0) body(i, sums);
-        }
+        body(i0 + k, sums);
     }
 }
 
@@ -1736,17 +1721,12 @@ __device__ __forceinline__ FinIn fin_fields(const PcgScalars* __restrict__ s, in
     const PcgScalars* p = s + i;
     return FinIn{p->rho, p->bb, p->tol2, p->it, p->maxit, p->done, p->fresh, p->flexible};
 }
+// the fields of instance kFinWaves * blockIdx.x + threadIdx.x, the one this thread's body call serves
+// (for_each_instance_sum)
 __device__ __forceinline__ FinIn prefetch_fields(const PcgScalars* __restrict__ s, const InstMap& m) {
     FinIn x{};
-    if ((int32_t)threadIdx.x < m.n_inst && m.n_inst <= kFinWaves) x = fin_fields(s, threadIdx.x);
-    return x;
-}
-// the prefetched fields serve thread i == threadIdx.x (every instance when n_inst <= kFinWaves)
-__device__ __forceinline__ FinIn fields_of(const PcgScalars* __restrict__ s, const InstMap& m, int32_t i,
-                                           const FinIn& pre) {
-    FinIn x;
-    if (m.n_inst <= kFinWaves && i == (int32_t)threadIdx.x) x = pre;
-    else x = fin_fields(s, i);
+    const int32_t i = (int32_t)blockIdx.x * kFinWaves + (int32_t)threadIdx.x;
+    if ((int32_t)threadIdx.x < kFinWaves && i < m.n_inst) x = fin_fields(s, i);
     return x;
 }
 
@@ -1882,36 +1862,50 @@ __global__ __launch_bounds__(kFin) void k_fin_start(PcgScalars* __restrict__ s, 
         if (when_done && !sum->all_done) return;  // pairs with k_pcg_residual's when_done
         const int32_t forced = (mode == 1 && force) ? *force : 0;
         __syncthreads();
-        if (forced && threadIdx.x == 0) *force = 0;
+        // with several workgroups k_fin_summary clears the flag once every workgroup has read it
+        if (forced && threadIdx.x == 0 && gridDim.x == 1) *force = 0;
+        // field by field, as in the single-instance form (a copy of the whole struct would be kept in LDS)
         for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
             const double rr = v[0], bb = v[1];
-            PcgScalars x = s[i];
-            if (mode == 0) {
-                x = PcgScalars{};
-                x.maxit = maxit;
-                x.flexible = flexible;
-                x.tol2 = rtol * rtol * bb;
-            } else if (x.status == EQS_ERR_BREAKDOWN) {
-                return;
+            PcgScalars* p = s + i;
+            int32_t it, mx;
+            double tol2;
+            if (mode == 0) {  // a fresh solve: every field set, the others 0
+                it = 0;
+                mx = maxit;
+                tol2 = rtol * rtol * bb;
+                p->rho = 0.0;
+                p->rho_old = 0.0;
+                p->alpha = 0.0;
+                p->it = 0;
+                p->maxit = maxit;
+                p->flexible = flexible;
+                p->tol2 = tol2;
+            } else {
+                if (p->status == EQS_ERR_BREAKDOWN) return;
+                it = p->it;
+                mx = p->maxit;
+                tol2 = p->tol2;
             }
-            x.bb = bb;
-            x.rr = rr;
-            x.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-            x.fresh = 1;
-            x.beta = 0.0;
-            x.status = EQS_OK;
-            x.done = 0;
-            if (bb == 0.0 || (rr <= x.tol2 && !forced)) {
-                x.done = 1;
+            int32_t done = 0, status = EQS_OK;
+            if (bb == 0.0 || (rr <= tol2 && !forced)) {
+                done = 1;
             } else if (!isfinite(rr) || !isfinite(bb)) {
-                x.done = 1;
-                x.status = EQS_ERR_BREAKDOWN;
-            } else if (x.it >= x.maxit) {
-                x.done = 1;
-                x.status = EQS_ERR_NOT_CONVERGED;
+                done = 1;
+                status = EQS_ERR_BREAKDOWN;
+            } else if (it >= mx) {
+                done = 1;
+                status = EQS_ERR_NOT_CONVERGED;
             }
-            s[i] = x;
+            p->bb = bb;
+            p->rr = rr;
+            p->relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            p->fresh = 1;
+            p->beta = 0.0;
+            p->status = status;
+            p->done = done;
         });
+        if (gridDim.x > 1) return;  // k_fin_summary follows
         __syncthreads();
         summarise(s, m.n_inst, sum, host_sum, host);
     }
@@ -1947,7 +1941,7 @@ __global__ __launch_bounds__(kFin) void k_fin_beta(PcgScalars* __restrict__ s, I
         const FinIn pre = prefetch_fields(s, m);
         for_each_instance_sum<2>(parts, m, [&](int32_t i, const double* v) {
             if (stopped) return;
-            const FinIn x = fields_of(s, m, i, pre);
+            const FinIn& x = pre;
             if (x.done) return;
             PcgScalars* p = s + i;
             if (fin_positive(v[0]) != FIN_GO) {
@@ -1982,7 +1976,7 @@ __global__ __launch_bounds__(kFin) void k_fin_alpha(PcgScalars* __restrict__ s, 
         const FinIn pre = prefetch_fields(s, m);
         for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
             if (stopped) return;
-            const FinIn x = fields_of(s, m, i, pre);
+            const FinIn& x = pre;
             if (x.done) return;
             PcgScalars* p = s + i;
             if (fin_positive(v[0]) != FIN_GO) {
@@ -2061,7 +2055,7 @@ __global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, I
         const FinIn pre = prefetch_fields(s, m);
         for_each_instance_sum<1>(parts, m, [&](int32_t i, const double* v) {
             if (stopped) return;
-            const FinIn x = fields_of(s, m, i, pre);
+            const FinIn& x = pre;
             if (x.done) return;
             const double rr = v[0];
             const int32_t it = x.it + 1;
@@ -2077,15 +2071,37 @@ __global__ __launch_bounds__(kFin) void k_fin_conv(PcgScalars* __restrict__ s, I
                 p->status = EQS_ERR_NOT_CONVERGED;
             }
         });
-        if (stopped) return;  // uniform: the summary already says all done
+        if (stopped || gridDim.x > 1) return;  // the summary already says all done, or k_fin_summary follows
         __syncthreads();
         summarise(s, m.n_inst, sum, host_sum, host);
     }
 }
 
+// The summary of every instance's CG state after a finaliser of several
+// workgroups (more than kFinWaves instances), which cannot summarise itself:
+// what summarise() does at the end of a one-workgroup finaliser. gate 0:
+// always; 1: only while the summary does not yet say all done (after
+// k_fin_conv, which then acted); 2: only once it does (after a k_fin_start
+// queued with when_done). force (may be NULL): cleared here, after every
+// workgroup of the k_fin_start before has read it.
+__global__ __launch_bounds__(kFin) void k_fin_summary(const PcgScalars* __restrict__ s, int32_t n_inst,
+                                                       PcgSummary* __restrict__ sum,
+                                                       PcgSummary* __restrict__ host_sum,
+                                                       PcgScalars* __restrict__ host, int32_t gate,
+                                                       int32_t* __restrict__ force) {
+    const int32_t all_done = sum->all_done;
+    if ((gate == 1 && all_done) || (gate == 2 && !all_done)) return;
+    __syncthreads();  // every thread has read the old summary before summarise() writes the new one
+    if (force && threadIdx.x == 0) *force = 0;
+    summarise(s, n_inst, sum, host_sum, host);
+}
+
 __global__ void k_set_flag(int32_t* __restrict__ p, int32_t v) { *p = v; }
 
 static double* part(eqs_ctx* c, int q) { return c->d_partials + (int64_t)q * 2 * c->max_blocks; }
+
+// Workgroups of a finaliser: one per kFinWaves instances (one with a single instance).
+static unsigned fin_grid(const eqs_ctx* c) { return (unsigned)((c->n_inst + kFinWaves - 1) / kFinWaves); }
 
 void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int32_t maxit, double rtol,
               int flexible, const double* mx) {
@@ -2096,9 +2112,12 @@ void pcg_init(hipStream_t s, eqs_ctx* c, const double* rhs, const double* x, int
     else
         hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
                            part(c, 0), part(c, 1), (double*)nullptr, (const int32_t*)nullptr);
-    hipLaunchKernelGGL(inst_map(c).rows1 >= 0 ? k_fin_start<true> : k_fin_start<false>, dim3(1), dim3(kFin), 0, s,
-                       c->d_scal, inst_map(c), part(c, 0), part(c, 1), rtol,
-                       maxit, flexible, 0, c->d_sum, c->d_hsum, c->d_hscal, 0, (int32_t*)nullptr);
+    hipLaunchKernelGGL(inst_map(c).rows1 >= 0 ? k_fin_start<true> : k_fin_start<false>, dim3(fin_grid(c)),
+                       dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), rtol, maxit, flexible, 0,
+                       c->d_sum, c->d_hsum, c->d_hscal, 0, (int32_t*)nullptr);
+    if (fin_grid(c) > 1)
+        hipLaunchKernelGGL(k_fin_summary, dim3(1), dim3(kFin), 0, s, c->d_scal, (int32_t)c->n_inst, c->d_sum, c->d_hsum,
+                           c->d_hscal, 0, (int32_t*)nullptr);
     if (c->test_reject_first) hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, c->d_force, 1);
 }
 
@@ -2108,10 +2127,13 @@ void pcg_true_residual(hipStream_t s, eqs_ctx* c, const double* rhs, const doubl
     const int32_t* done = only_if_done ? &c->d_sum->all_done : nullptr;
     hipLaunchKernelGGL(k_pcg_residual, dim3(nb), dim3(kBlock), 0, s, view(c->M), inst_map(c), rhs, x, c->d_r,
                        part(c, 0), part(c, 1), mx_out, done);
-    hipLaunchKernelGGL(inst_map(c).rows1 >= 0 ? k_fin_start<true> : k_fin_start<false>, dim3(1), dim3(kFin), 0, s,
-                       c->d_scal, inst_map(c), part(c, 0), part(c, 1), 0.0, 0,
-                       0, 1, c->d_sum, c->d_hsum, c->d_hscal, only_if_done ? 1 : 0,
-                       c->test_reject_first ? c->d_force : (int32_t*)nullptr);
+    int32_t* force = c->test_reject_first ? c->d_force : (int32_t*)nullptr;
+    hipLaunchKernelGGL(inst_map(c).rows1 >= 0 ? k_fin_start<true> : k_fin_start<false>, dim3(fin_grid(c)),
+                       dim3(kFin), 0, s, c->d_scal, inst_map(c), part(c, 0), part(c, 1), 0.0, 0, 0, 1, c->d_sum,
+                       c->d_hsum, c->d_hscal, only_if_done ? 1 : 0, force);
+    if (fin_grid(c) > 1)
+        hipLaunchKernelGGL(k_fin_summary, dim3(1), dim3(kFin), 0, s, c->d_scal, (int32_t)c->n_inst, c->d_sum, c->d_hsum,
+                           c->d_hscal, only_if_done ? 2 : 0, force);
 }
 
 void pcg_zero_rhs_rows(hipStream_t s, eqs_ctx* c, double* x) {
@@ -2136,17 +2158,21 @@ void pcg_iteration(hipStream_t s, eqs_ctx* c, const double* rhs, double* x, int 
     prof_end(c, EQS_KCLASS_VCYCLE, s);
     const InstMap im = inst_map(c);
     const bool one = im.rows1 >= 0;
-    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_beta<true> : k_fin_beta<false>, dim3(1), dim3(kFin), 0, s,
+    const dim3 fg(fin_grid(c));
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_beta<true> : k_fin_beta<false>, fg, dim3(kFin), 0, s,
                      c->d_scal, im, part(c, 0), part(c, 1), stop);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_SPMV_M, one ? k_pcg_spmv<true> : k_pcg_spmv<false>, dim3(nbM), dim3(kBlock), 0,
                      s, view(c->M), im, c->d_z, c->d_p, c->d_q, part(c, 2), c->d_scal, vstop);
-    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_alpha<true> : k_fin_alpha<false>, dim3(1), dim3(kFin), 0,
-                     s, c->d_scal, im, part(c, 2), stop);
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_alpha<true> : k_fin_alpha<false>, fg, dim3(kFin), 0, s,
+                     c->d_scal, im, part(c, 2), stop);
     EQS_LAUNCH_TIMED(c, EQS_KCLASS_CG_UPDATE, one ? k_pcg_update<true> : k_pcg_update<false>, dim3(nbV),
                      dim3(kBlock), 0, s, im, x, c->d_r, c->d_p, c->d_q, c->n_free, part(c, 3), c->d_scal, vstop,
                      c->M.xcd);
-    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_conv<true> : k_fin_conv<false>, dim3(1), dim3(kFin), 0, s,
+    EQS_LAUNCH_TIMED(c, EQS_KCLASS_FINALISE, one ? k_fin_conv<true> : k_fin_conv<false>, fg, dim3(kFin), 0, s,
                      c->d_scal, im, part(c, 3), c->d_sum, c->d_hsum, c->d_hscal);
+    if (fg.x > 1)  // the summary of all instances (part of the finalise class's work, not timed on its own)
+        hipLaunchKernelGGL(k_fin_summary, dim3(1), dim3(kFin), 0, s, c->d_scal, (int32_t)c->n_inst, c->d_sum,
+                           c->d_hsum, c->d_hscal, 1, (int32_t*)nullptr);
 }
 
 // ------------------------------------------------------------------ RKC

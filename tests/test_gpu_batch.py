@@ -89,3 +89,40 @@ def test_instance_validation():
         with pytest.raises(EqsError) as e:
             ctx.build_preconditioner()
         assert e.value.code == EQS_ERR_INVALID_ARG and "another instance" in str(e.value)
+
+
+@pytest.mark.parametrize("reject", ["0", "1"])
+def test_batch_of_more_instances_than_one_finaliser_workgroup(reject, monkeypatch):
+    """20 instances: the CG finalisers run two workgroups (16 instances each)
+    and a separate summary kernel. Every instance follows its own trajectory as
+    in a batch of four; with EQS_TEST_REJECT_CHECK=1 every solve restarts once
+    from its true residual (the summary kernel clears the one-shot flag after
+    both workgroups have read it), with the same result."""
+    monkeypatch.setenv("EQS_TEST_REJECT_CHECK", reject)
+    cases = []
+    for k in range(20):
+        n, seed, amp, freq = SPECS[k % len(SPECS)]
+        c = _inclusion_case("c3", 7 + k % 2, seed + k, (2.0, 15.0), (6.0, 14.0), amp=amp * (1 + 0.05 * k),
+                            freq=freq)
+        c.s, c.tau = 8, 1e-4
+        cases.append(c)
+    steps, rtol = 2, 1e-12
+    stream = torch.cuda.current_stream(DEV)
+    inputs = []
+    for c in cases:
+        ctx = Context(0, stream)
+        ctx.set_inputs(c)
+        inputs.append(ctx)
+    b = Batch(inputs, precision=EQS_PREC_FP64, stream=stream)
+    for ctx in inputs:
+        ctx.close()
+    xs = [torch.zeros(c.n_nodes, dtype=torch.float64, device=DEV) for c in cases]
+    res = b.rkc_steps(steps, 0.0, cases[0].tau, cases[0].s, xs, rtol)
+    b.close()
+    print(f"[batch20] reject={reject} CG iterations {res['iters'].tolist()}", flush=True)
+    assert (res["relres"] <= rtol * 1.01).all()
+    for c, x in zip(cases, xs):
+        o = EqsOracle(c)
+        ref = o.rkc_trajectory(np.zeros(o.n_free), 0.0, c.tau, c.s, steps)
+        err = np.linalg.norm(x.cpu().numpy()[o.free] - ref[-1]) / max(np.linalg.norm(r) for r in ref)
+        assert err <= 1e-9, (c.n, err)
