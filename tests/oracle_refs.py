@@ -20,7 +20,8 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LOG_DIR = os.path.join(ROOT, "gpurun_out", "oracle_refs")
+# progress logs of the reference runs (EQS_TEST_LOG_DIR, else a folder under the ignored build directory)
+LOG_DIR = os.environ.get("EQS_TEST_LOG_DIR") or os.path.join(ROOT, "_build", "test_logs", "oracle_refs")
 
 # reference runs a test may ask for: name -> (case, steps, stage-solve rel-res).
 # The 1e-13 runs are the method's result; the 1e-8 runs are the oracle at the

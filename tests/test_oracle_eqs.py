@@ -1,6 +1,6 @@
 """Pins of the oracle's semi-discrete EQS system and RKC trajectories — CPU only.
 
-Closed forms used (derived in DESIGN.md, "Pins"):
+Closed forms used:
   P1  two-layer Maxwell-Wagner relaxation under a step drive: the P1 solution
       stays piecewise linear in z and the interface potential obeys one scalar
       linear ODE, so RKC gives phi_inf + (phi_0 - phi_inf) P_s(-tau/T)^n.
