@@ -2,6 +2,11 @@
 
 Every source under ``csrc/`` is compiled for gfx950 only; packed-FP32
 instruction selection is switched off for device code.
+
+``build_sanitized()`` builds the test driver ``tests/native/bin/abi_sanitize``:
+the same sources and the driver, with AddressSanitizer and
+UndefinedBehaviorSanitizer on the host code only (every sanitizer flag is
+passed through ``-Xarch_host``; the device code is built as above).
 """
 
 from __future__ import annotations
@@ -39,9 +44,20 @@ COMMON = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+SAN_OBJDIR = os.path.join(ROOT, "_build", "sanitize")
+SAN_DRIVER = os.path.join(ROOT, "tests", "native", "abi_sanitize.cpp")
+SAN_EXE = os.path.join(ROOT, "tests", "native", "bin", "abi_sanitize")
+# host code only: each flag reaches the host compilation and the link, not the device code
+# (_GLIBCXX_ASSERTIONS adds libstdc++'s bounds checks of vector and string indexing)
+SAN_FLAGS = [f for flag in ("-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=all",
+                            "-fno-omit-frame-pointer", "-g", "-D_GLIBCXX_ASSERTIONS")
+             for f in ("-Xarch_host", flag)]
+
+
+def _compile(src: str, objdir: str = OBJDIR, extra=()) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    path = src if os.path.isabs(src) else os.path.join(CSRC, src)
+    cmd = [HIPCC, *COMMON, *extra, "-x", "hip", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -63,5 +79,25 @@ def build(jobs: int = 4) -> str:
     return LIB
 
 
+def build_sanitized(jobs: int = 4) -> str:
+    """Compile the library's sources and the sanitizer driver with host-side
+    ASan/UBSan and link the driver executable; returns its path."""
+    os.makedirs(SAN_OBJDIR, exist_ok=True)
+    os.makedirs(os.path.dirname(SAN_EXE), exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda src: _compile(src, SAN_OBJDIR, SAN_FLAGS), [*SOURCES, SAN_DRIVER]))
+    tmp = SAN_EXE + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, f"--offload-arch={ARCH}", *SAN_FLAGS, "-o", tmp, *objs, "-L", ROCM_LIB,
+           "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SAN_EXE)
+    return SAN_EXE
+
+
 if __name__ == "__main__":
-    print(build(int(sys.argv[1]) if len(sys.argv) > 1 else 4))
+    jobs = int(sys.argv[1]) if len(sys.argv) > 1 else 4
+    print(build(jobs))
+    if "--sanitize" in sys.argv[2:]:
+        print(build_sanitized(jobs))

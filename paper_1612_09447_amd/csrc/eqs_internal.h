@@ -487,7 +487,7 @@ struct StateWriter {
     void raw(const void* src, int64_t b) {
         if (buf) {
             if (n + b > cap) fail(EQS_ERR_INVALID_ARG, "state buffer too small");
-            std::memcpy(buf + n, src, (size_t)b);
+            if (b > 0) std::memcpy(buf + n, src, (size_t)b);  // an empty vector's data() may be NULL
         }
         n += b;
     }
@@ -513,7 +513,7 @@ struct StateReader {
     hipStream_t s = nullptr;
     void raw(void* dst, int64_t b) {
         if (b < 0 || n + b > cap) fail(EQS_ERR_INVALID_ARG, "state buffer truncated or not a checkpoint of this set-up");
-        std::memcpy(dst, buf + n, (size_t)b);
+        if (b > 0) std::memcpy(dst, buf + n, (size_t)b);
         n += b;
     }
     template <typename T>

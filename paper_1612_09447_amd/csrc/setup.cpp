@@ -208,8 +208,8 @@ Csr<double> assemble_M_free(const eqs_ctx* c) {
         }
         for (int a = 0; a < npe; ++a) {
             if (v[a] >= NF) continue;
-            const int32_t* cb = &M.col[M.ptr[v[a]]];
-            const int32_t* ce = &M.col[M.ptr[v[a] + 1]];
+            const int32_t* cb = M.col.data() + M.ptr[v[a]];
+            const int32_t* ce = M.col.data() + M.ptr[v[a] + 1];
             for (int b = 0; b < npe; ++b) {
                 if (v[b] >= NF) continue;
                 const int32_t* it = std::lower_bound(cb, ce, v[b]);
