@@ -402,7 +402,12 @@ void run_abi() {
     double ms = 0;
     for (int k = 0; k < EQS_KCLASS_COUNT; ++k) OK(eqs_profile_read(c, k, &launches, &ms));
     OK(eqs_profile_read(c, EQS_KCLASS_ELEMENT, &launches, &ms));
-    CHECK(launches == s && ms > 0);
+    // one element pass per stage; with the plain start vector the next stage's
+    // pass is queued behind a solve's convergence check and queued again when
+    // the check sends the solve back (every solve, with EQS_TEST_REJECT_CHECK=1)
+    const char* rj = std::getenv("EQS_TEST_REJECT_CHECK");
+    if (rj && rj[0] == '1') CHECK(launches >= s && launches <= 2 * s && ms > 0);
+    else CHECK(launches == s && ms > 0);
     FAILS(eqs_profile_read(c, EQS_KCLASS_COUNT, &launches, &ms), EQS_ERR_INVALID_ARG);
     OK(eqs_profile_enable(c, 0));
 

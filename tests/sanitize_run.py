@@ -28,7 +28,7 @@ def stale():
     return any(os.path.getmtime(p) > t for p in sources())
 
 
-def run(mode, timeout):
+def run(mode, timeout, extra_env=None):
     from paper_1612_09447_amd import build as b
 
     env = dict(os.environ)
@@ -39,8 +39,10 @@ def run(mode, timeout):
     env["ASAN_OPTIONS"] = "halt_on_error=1:abort_on_error=0:handle_abort=1:detect_leaks=1:protect_shadow_gap=0:exitcode=99"
     env["LSAN_OPTIONS"] = f"suppressions={SUPP}:print_suppressions=0:exitcode=98"
     env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
-    for k in ("EQS_TUNE_FILE", "EQS_AUTOTUNE", "EQS_USE_GRAPHS", "EQS_KX_GENERIC", "EQS_INDEX16"):
-        env.pop(k, None)
+    for k in list(env):
+        if k.startswith("EQS_"):
+            del env[k]
+    env.update(extra_env or {})
     r = subprocess.run([b.SAN_EXE, mode], capture_output=True, text=True, timeout=timeout, env=env)
     out = r.stdout + r.stderr
     print(out[-6000:], flush=True)
