@@ -273,6 +273,62 @@ void run_host() {
         delete c;
     }
 
+    // instances side by side: their free rows are contiguous per instance, and
+    // a tet across two instances or a small instance is rejected
+    {
+        const Mesh A8 = kuhn_mesh(8, false), A7 = kuhn_mesh(7, false);
+        const Mesh B = concat(A8, A7);
+        const Inputs in = slab_inputs(B, 1.0);
+        auto fill = [&](eqs_ctx* c, const Mesh& m, int64_t split_node, int64_t split_tet) {
+            c->n_nodes = m.n_nodes;
+            c->n_tets = m.n_tets;
+            c->npe = 4;
+            c->xyz = m.xyz;
+            c->tets = m.tets;
+            c->mats = in.mats;
+            c->tet_mat.assign(m.n_tets, 0);
+            c->dir_nodes = in.dir_nodes;
+            c->dir_drive = in.dir_drive;
+            c->drives = in.drives;
+            c->inst_node_off = {0, split_node, m.n_nodes};
+            c->inst_tet_off = {0, split_tet, m.n_tets};
+            c->have_mesh = c->have_mat = c->have_dir = true;
+        };
+        auto code_of = [](eqs_ctx* c) {
+            try {
+                validate_and_order(c);
+            } catch (const Error& e) {
+                return e.code;
+            }
+            return 0;
+        };
+        eqs_ctx* c = new eqs_ctx();
+        fill(c, B, A8.n_nodes, A8.n_tets);
+        CHECK(code_of(c) == 0);
+        CHECK(c->n_inst == 2 && c->inst_row_off[2] == c->n_free);
+        const int64_t nd8 = 2 * 81;  // bottom and top faces of the 8^3 mesh
+        CHECK(c->inst_row_off[1] == A8.n_nodes - nd8);
+        for (int64_t k = 0; k < c->n_free; ++k) {
+            const int32_t u = c->int_to_user[k];
+            CHECK((k < c->inst_row_off[1]) == (u < A8.n_nodes));
+            if (k > 0) CHECK(u > c->int_to_user[k - 1]);
+        }
+        // the last tet of the first instance moved into the second one
+        fill(c, B, A8.n_nodes, A8.n_tets - 1);
+        CHECK(code_of(c) == EQS_ERR_INVALID_ARG);
+        delete c;
+        // fewer than 256 free nodes in an instance
+        const Mesh A4 = kuhn_mesh(4, false);
+        const Mesh S = concat(A8, A4);
+        c = new eqs_ctx();
+        fill(c, S, A8.n_nodes, A8.n_tets);
+        c->dir_nodes = slab_inputs(S, 1.0).dir_nodes;
+        c->dir_drive = slab_inputs(S, 1.0).dir_drive;
+        c->tet_mat.assign(S.n_tets, 0);
+        CHECK(code_of(c) == EQS_ERR_INVALID_ARG);
+        delete c;
+    }
+
     // RKC coefficients: the last stage ends at the step's end, and the
     // stability boundary grows with s
     double prev = 0;
