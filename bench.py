@@ -215,12 +215,12 @@ def class_bytes(info, s_stages):
     return out
 
 
-def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None, steplog=None):
+def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None, steplog=None, stage_iters=None):
     """Run `steps` RKC steps from step index n; returns (elapsed s, per-step
     mean CG iterations per stage, guesses used, guard fallbacks). With `hist`
     (a device tensor [steps, n_nodes]) every step-end state is copied into it
     on the same stream (a device copy of one vector per step, inside the timed
-    loop)."""
+    loop); a `stage_iters` list receives every stage's CG iterations."""
     import torch
 
     torch.cuda.synchronize()
@@ -234,6 +234,8 @@ def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None, steplog=None):
         if hist is not None:
             hist[k].copy_(x)
         iters.append(st["total_iters"] / st["stages"])
+        if stage_iters is not None:
+            stage_iters.extend(st["stage_iters"])
         used += st["guess_used"]
         fallbacks += st["guess_fallbacks"]
         if (k + 1) % max(1, steps // 5) == 0:
@@ -281,8 +283,9 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         ctx.rkc_step(n * tau, tau, s, x, rtol=rtol, maxit=500)
         n += 1
     hist = torch.empty((steps, case.n_nodes), dtype=torch.float64, device=dev) if keep_states else None
+    stage_its = []
     elapsed, iters, used, fallbacks = timed_steps(ctx, x, n, steps, tau, s, rtol, f"{precision}/{guess}", hist,
-                                                  steplog)
+                                                  steplog, stage_its)
     n += steps
     x_timed = x.cpu().numpy()  # state after warmup + timed steps (compared across precisions)
     prof, prof_elapsed = {}, 0.0
@@ -319,9 +322,21 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         ctx.set_guess("previous")
     ctx.close()
     del ws
-    return dict(elapsed=elapsed, stages=steps * s, iters=iters, info=info, prof=prof, prof_elapsed=prof_elapsed,
+    return dict(elapsed=elapsed, stages=steps * s, iters=iters, stage_iters=stage_its, info=info, prof=prof,
+                prof_elapsed=prof_elapsed,
                 prof_stages=prof_steps * s, setup_s=setup_s, x=x_timed, used=used, fallbacks=fallbacks, learned=learned,
                 hist=hist)
+
+
+def stage_iter_stats(its):
+    """Mean, median and extremes of the timed stages' CG iterations."""
+    if not its:
+        return None
+    import numpy as np
+
+    a = np.asarray(its)
+    return {"mean": round(float(a.mean()), 2), "p50": float(np.median(a)), "min": int(a.min()), "max": int(a.max()),
+            "stages": int(a.size)}
 
 
 def state_errors(hist, ref, free):
@@ -640,6 +655,7 @@ def main():
             "graphs": bool(args.graphs),
             "cg_iters_per_graph_launch": args.graph_iters,
             "mean_cg_iters_per_stage": round(sum(r["iters"]) / len(r["iters"]), 2),
+            "cg_iters_per_stage": stage_iter_stats(r["stage_iters"]),
             "amg_levels": info["level_rows"],
             "device_memory": f"torch workspace of {info['workspace_bytes']} bytes (eqs_set_workspace); "
                              f"library-allocated: {info['device_bytes']}",

@@ -294,6 +294,17 @@ int eqs_solve_M(eqs_ctx *ctx, const double *rhs_dev, double *y_dev, double rtol,
 int eqs_rkc_step(eqs_ctx *ctx, double t, double dt, int32_t s, double *x_dev, double rtol, int32_t maxit,
                  eqs_step_stats *st);
 
+/* CG iterations of every stage of the last eqs_rkc_step (Sec. II: one
+ * M-solve per stage), in stage order, for per-stage statistics (median,
+ * spread) that eqs_step_stats' sum, minimum and maximum do not give. iters
+ * (host) receives min(cap, n) entries and *n (may be NULL) the number of
+ * stages whose solve ran in that step: s after a completed step, fewer after
+ * a step that stopped on an error, 0 before the first step after a set-up
+ * call (a call that its argument checks reject changes nothing). In a context
+ * with several instances a stage's count is the largest over its instances.
+ * EQS_ERR_INVALID_ARG for a NULL ctx, cap < 0, or iters NULL with cap > 0. */
+int eqs_stage_iters(const eqs_ctx *ctx, int32_t *iters, int32_t cap, int32_t *n);
+
 /* ---- error-controlled stepping -----------------------------------------
  * RKC with the step size and stage count chosen per step, as the paper runs
  * it (Sec. V: local time-integration error below a tolerance; the controller

@@ -135,6 +135,7 @@ _SIGNATURES = {
     "eqs_galerkin_start_noalloc": ([_P, C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_int32)], C.c_int),
     "eqs_set_instances": ([_P, C.c_int32, _P, _P], C.c_int),
     "eqs_instance_stats": ([_P, C.c_int32, _P, _P], C.c_int),
+    "eqs_stage_iters": ([_P, _P, C.c_int32, _P], C.c_int),
     "eqs_batch_create": ([C.POINTER(_P), C.c_int32, _P, C.c_int, _P, _P], C.c_int),
     "eqs_batch_destroy": ([_P], C.c_int),
     "eqs_batch_set_graph_iters": ([_P, C.c_int32], C.c_int),
@@ -431,7 +432,14 @@ class Context:
         _check(rc, "eqs_rkc_step", ok)
         return dict(stages=st.stages, total_iters=st.total_iters, max_iters=st.max_iters, min_iters=st.min_iters,
                     not_converged=st.not_converged, guess_used=st.guess_used, guess_fallbacks=st.guess_fallbacks,
-                    max_relres=st.max_relres, train_loss=st.train_loss, rc=rc)
+                    max_relres=st.max_relres, train_loss=st.train_loss, stage_iters=self.stage_iters(), rc=rc)
+
+    def stage_iters(self):
+        """CG iterations of each stage of the last rkc_step (eqs_stage_iters)."""
+        buf = np.zeros(256, np.int32)
+        n = C.c_int32(0)
+        _check(lib().eqs_stage_iters(self._h, buf.ctypes.data_as(_P), buf.size, C.byref(n)), "eqs_stage_iters")
+        return buf[:min(n.value, buf.size)].tolist()
 
     def rkc_adaptive(self, t0, t_end, x, rtol, atol_err, rtol_err, tau0, maxit=1000, s_max=0, tau_min=0.0,
                      tau_max=0.0, max_attempts=0, cap=100000, allow_not_converged=False):

@@ -580,6 +580,18 @@ int eqs_instance_stats(const eqs_ctx* c, int32_t n_inst, int64_t* iters, double*
     });
 }
 
+int eqs_stage_iters(const eqs_ctx* c, int32_t* iters, int32_t cap, int32_t* n) {
+    return guarded([&] {
+        need(c != nullptr, "ctx is NULL");
+        need(cap >= 0, "cap must be >= 0");
+        need(iters != nullptr || cap == 0, "iters is NULL");
+        const int32_t m = (int32_t)c->stage_iters.size();
+        for (int32_t k = 0; k < std::min(cap, m); ++k) iters[k] = c->stage_iters[k];
+        if (n) *n = m;
+        return EQS_OK;
+    });
+}
+
 int eqs_set_guess(eqs_ctx* c, const eqs_guess_params* p) {
     return guarded([&] {
         need(c != nullptr && p != nullptr, "NULL argument");

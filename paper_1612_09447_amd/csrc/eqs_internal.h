@@ -302,6 +302,7 @@ struct eqs_ctx {
     std::vector<int32_t> inst_row_off;                  // free rows [n_inst + 1]
     int32_t* d_inst_row = nullptr;
     int32_t* d_blk_inst = nullptr;  // instance of the first row of every 256-row block
+    std::vector<int32_t> stage_iters; // CG iterations of each stage of the last rkc_step, in stage order
     std::vector<int64_t> inst_iters;  // CG iterations per instance over the last rkc_step / solve
     std::vector<double> inst_relres;  // largest final relative residual per instance over the same
 

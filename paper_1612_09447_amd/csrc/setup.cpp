@@ -1630,6 +1630,7 @@ void free_device(eqs_ctx* c) {
     for (auto& e : c->ev)
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
     c->M = Sell<double>{};
+    c->stage_iters.clear();
     c->h64.lv.clear();
     c->h32.lv.clear();
     c->d_tpack = nullptr; c->d_bnodes = nullptr; c->d_boff = nullptr; c->n_blocks = 0; c->max_block_nodes = 0; c->n_block_nodes = 0;

@@ -212,6 +212,7 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
 
     std::fill(c->inst_iters.begin(), c->inst_iters.end(), 0);
     std::fill(c->inst_relres.begin(), c->inst_relres.end(), 0.0);
+    c->stage_iters.clear();
     eqs_step_stats S{};
     S.stages = s;
     S.min_iters = INT32_MAX;
@@ -273,6 +274,7 @@ int rkc_step(eqs_ctx* c, double t, double dt, int32_t s, double* x_user, double 
                                 early ? &rest_fn : nullptr);
         c->mx_of_F = src == EQS_OK || src == EQS_ERR_NOT_CONVERGED;
         if (kind == EQS_GUESS_GALERKIN || kind == EQS_GUESS_MLP || kind == EQS_GUESS_MOR) guess_after_solve(c, ss.iters);
+        c->stage_iters.push_back(ss.iters);
         S.total_iters += ss.iters;
         S.max_iters = std::max(S.max_iters, ss.iters);
         S.min_iters = std::min(S.min_iters, ss.iters);

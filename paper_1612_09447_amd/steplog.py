@@ -1,7 +1,8 @@
 """Per-step records of a run as JSON lines.
 
 ``StepLog`` appends one JSON object per RKC step: the step index and time,
-the stage count, the CG iterations of the step (total, per stage, extremes),
+the stage count, the CG iterations of the step (total, mean per stage, extremes, and each
+stage's count),
 the largest final relative residual, the start-vector counters and the host
 wall time of the call (``eqs_rkc_step`` returns after the step's work has
 finished, so the wall time is the step's). It only formats what the library
@@ -34,6 +35,8 @@ class StepLog:
                "max_iters": st["max_iters"], "min_iters": st["min_iters"], "max_relres": st["max_relres"],
                "not_converged": st["not_converged"], "guess_used": st["guess_used"],
                "guess_fallbacks": st["guess_fallbacks"], "wall_ms": round(wall_s * 1e3, 3), **self._fields}
+        if st.get("stage_iters") is not None:
+            rec["stage_iters"] = list(st["stage_iters"])
         self._f.write(json.dumps(rec) + "\n")
 
     def close(self):

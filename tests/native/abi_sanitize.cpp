@@ -182,6 +182,7 @@ void run_host() {
     FAILS(eqs_solve_M(none, nullptr, nullptr, 1e-8, 10, nullptr), EQS_ERR_INVALID_ARG);
     FAILS(eqs_set_graph_iters(none, 1), EQS_ERR_INVALID_ARG);
     FAILS(eqs_describe(none, nullptr, 0, nullptr), EQS_ERR_INVALID_ARG);
+    FAILS(eqs_stage_iters(none, nullptr, 0, nullptr), EQS_ERR_INVALID_ARG);
     OK(eqs_batch_destroy(nullptr));
     FAILS(eqs_mlp_create(nullptr, 0, nullptr, nullptr, 1, 1e-3), EQS_ERR_INVALID_ARG);
 
@@ -374,6 +375,18 @@ void steps(eqs_ctx* c, double* x, int n, double t0, double tau, int s, double rt
         eqs_step_stats st{};
         OK(eqs_rkc_step(c, t0 + k * tau, tau, s, x, rtol, 500, &st));
         CHECK(st.stages == s && st.not_converged == 0 && st.max_relres <= 1.01 * rtol);
+        // the per-stage counts, read into a buffer shorter than s first
+        std::vector<int32_t> its(s, -1);
+        int32_t m = -1;
+        OK(eqs_stage_iters(c, its.data(), s - 1, &m));
+        CHECK(m == s && its[s - 1] == -1);
+        OK(eqs_stage_iters(c, its.data(), s, nullptr));
+        int32_t sum = 0, mx = 0;
+        for (int32_t v : its) {
+            sum += v;
+            mx = std::max(mx, v);
+        }
+        CHECK(sum == st.total_iters && mx == st.max_iters);
     }
 }
 
@@ -445,6 +458,13 @@ void run_abi() {
     FAILS(eqs_rkc_step(c, 0.0, tau, 1, x, rtol, 500, nullptr), EQS_ERR_INVALID_ARG);
     FAILS(eqs_rkc_step(c, 0.0, tau, 257, x, rtol, 500, nullptr), EQS_ERR_INVALID_ARG);
     FAILS(eqs_set_deterministic(c, 1), EQS_ERR_STATE);
+    {
+        int32_t m = -1, one = 0;
+        FAILS(eqs_stage_iters(c, nullptr, 4, &m), EQS_ERR_INVALID_ARG);
+        FAILS(eqs_stage_iters(c, &one, -1, &m), EQS_ERR_INVALID_ARG);
+        OK(eqs_stage_iters(c, nullptr, 0, &m));
+        CHECK(m == s);  // the last step's, untouched by the rejected step calls above
+    }
     int64_t its = 0;
     double rr = 0;
     OK(eqs_instance_stats(c, 1, &its, &rr));

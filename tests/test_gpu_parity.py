@@ -354,6 +354,29 @@ def test_rkc_single_level_hierarchy():
     assert err <= 1e-9 and it <= 2
 
 
+def test_stage_iterations_of_the_last_step():
+    """eqs_stage_iters: one count per stage of the last RKC step, in stage
+    order, adding up to the step's total with the step's extremes; a call
+    that its argument checks reject changes nothing, a new set-up clears it."""
+    case = eqsgen.case_c0(8)
+    case.amp[1] = 3.0
+    with ctx_for(case) as c:
+        assert c.stage_iters() == []
+        x = torch.zeros(case.n_nodes, dtype=torch.float64, device=DEV)
+        for n in range(3):
+            st = c.rkc_step(n * case.tau, case.tau, case.s, x, rtol=1e-10)
+            its = st["stage_iters"]
+            print(f"[stage_iters] step {n + 1}: {its}", flush=True)
+            assert len(its) == case.s == st["stages"] and sum(its) == st["total_iters"]
+            assert max(its) == st["max_iters"] and min(its) == st["min_iters"]
+        with pytest.raises(EqsError) as e:
+            c.rkc_step(0.0, case.tau, 1, x, rtol=1e-10)
+        assert e.value.code == EQS_ERR_INVALID_ARG
+        assert c.stage_iters() == its
+        c.setup_case(case)
+        assert c.stage_iters() == []
+
+
 def test_profile_counts_launches_that_worked():
     """Kernel-class timing: one element pass and one combination per stage,
     one launch of each CG-iteration class per iteration that did work (the
