@@ -245,7 +245,8 @@ def timed_steps(ctx, x, n, steps, tau, s, rtol, label, hist=None, steplog=None, 
 
 
 def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous", flexible=0, learned_steps=0,
-            learned_warmup=20, mlp_batch=256, keep_states=False, mlp_warmup=64, graph_iters=1, steplog=None):
+            learned_warmup=20, mlp_batch=256, keep_states=False, mlp_warmup=64, graph_iters=1, steplog=None,
+            mlp_seed=4):
     """Time `steps` RKC steps (uninstrumented), then `prof_steps` more with every
     kernel class timed by HIP events on the context's stream. With
     learned_steps > 0 the same context then switches to the Galerkin and the
@@ -266,7 +267,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
     # PyTorch owns the device memory: the context moves into a torch workspace
     # sized for its largest start-vector setting of this run
     if guess == "mlp" or learned_steps > 0:
-        ctx.set_guess("mlp", init=eqsgen.mlp_init(4), batch=mlp_batch, warmup=mlp_warmup)
+        ctx.set_guess("mlp", init=eqsgen.mlp_init(mlp_seed), batch=mlp_batch, warmup=mlp_warmup)
     elif guess != "previous":
         ctx.set_guess(guess)
     ws = ctx.use_torch_workspace()
@@ -309,7 +310,7 @@ def run_gpu(case, precision, steps, warmup, rtol, prof_steps=0, guess="previous"
         for kind in ("previous", "zero", "galerkin", "mor", "mlp"):
             x.copy_(x0)
             if kind == "mlp":
-                ctx.set_guess("mlp", init=eqsgen.mlp_init(4), batch=mlp_batch, warmup=mlp_warmup)
+                ctx.set_guess("mlp", init=eqsgen.mlp_init(mlp_seed), batch=mlp_batch, warmup=mlp_warmup)
             else:
                 ctx.set_guess(kind)
             timed_steps(ctx, x, n, learned_warmup, tau, s, rtol, f"{kind} warm-up")
@@ -497,12 +498,16 @@ def main():
     ap.add_argument("--steps", type=int, default=200, help="timed RKC steps (the workload's 200)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
+    ap.add_argument("--config", default="",
+                    help="workload configuration (a name under eqsgen/configs or a JSON path): its recipe, "
+                         "settings and start vector replace --workload and --guess")
     ap.add_argument("--n", type=int, default=None, help="override the mesh resolution (testing)")
     ap.add_argument("--plain-steps", type=int, default=-1,
                     help="timed steps of the plain FP64 path over the same steps (-1: as --steps, 0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prof-steps", type=int, default=3, help="instrumented steps after the timed ones")
-    ap.add_argument("--guess", default="previous", choices=["previous", "zero", "galerkin", "mlp"])
+    ap.add_argument("--guess", default="previous", choices=["previous", "zero", "galerkin", "mor", "mlp"])
+    ap.add_argument("--mlp-seed", type=int, default=4, help="seed of the start-vector network's initial weights")
     ap.add_argument("--graphs", type=int, default=1, help="replay CG iterations as a captured HIP graph")
     ap.add_argument("--flexible", type=int, default=0, help="CG beta: 0 default, 1 Polak-Ribiere, 2 Fletcher-Reeves")
     ap.add_argument("--graph-iters", type=int, default=1, help="CG iterations per captured graph launch")
@@ -534,7 +539,17 @@ def main():
     import eqsgen
 
     t0 = time.perf_counter()
-    case = eqsgen.make_case(args.workload, n=args.n)
+    if args.config:
+        cfg = eqsgen.load_config(args.config)
+        if cfg["recipe"] not in ("c0", "c1", "c2"):
+            print(json.dumps({"error": f"--config {args.config}: the timed run takes a single-context recipe "
+                                       "(c0, c1, c2); the batched and second-order workloads are legs of their own"}))
+            sys.exit(2)
+        case = eqsgen.cases_from_config(cfg, n=args.n)[0]
+        args.workload, args.guess = cfg["name"], cfg["guess"]
+        args.mlp_seed = cfg.get("mlp_init_seed", 4)
+    else:
+        case = eqsgen.make_case(args.workload, n=args.n)
     log(f"[bench] workload {args.workload}: n={case.n} nodes={case.n_nodes} tets={case.n_tets} "
         f"({time.perf_counter() - t0:.1f}s to generate)")
     prec = "fp32" if case.precision == "fp32" else "fp64"
@@ -551,7 +566,8 @@ def main():
         steplog = StepLog(args.metrics_jsonl, run=f"{args.workload} main", precision=prec, guess=args.guess)
     r = run_gpu(case, main_prec, args.steps, args.warmup, case.rtol, prof_steps=args.prof_steps, guess=args.guess,
                 flexible=args.flexible, learned_steps=args.learned_steps, mlp_batch=args.mlp_batch,
-                keep_states=True, mlp_warmup=args.mlp_warmup, graph_iters=args.graph_iters, steplog=steplog)
+                keep_states=True, mlp_warmup=args.mlp_warmup, graph_iters=args.graph_iters, steplog=steplog,
+                mlp_seed=args.mlp_seed)
     if steplog is not None:
         steplog.close()
     stages_per_s = r["stages"] / r["elapsed"]

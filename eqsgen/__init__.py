@@ -12,6 +12,7 @@ meshes, because the paper's insulator model is not available.
 """
 
 from .mesh import kuhn_cube_mesh, kuhn_cube_mesh_p2, permute_nodes, shuffle_tets
+from .config import CONFIG_DIR, cases_from_config, config_names, load_config
 from .cases import (
     Case,
     make_case,
@@ -44,4 +45,8 @@ __all__ = [
     "random_state",
     "mlp_init",
     "CASE_NAMES",
+    "CONFIG_DIR",
+    "config_names",
+    "load_config",
+    "cases_from_config",
 ]
