@@ -34,3 +34,21 @@ def test_one_record_per_step(tmp_path):
     with StepLog(path) as log:
         log.step(ctx, 3, 3e-4, 1e-4, 8, None, 1e-8)
     assert len(path.read_text().splitlines()) == 4
+
+
+def test_each_stage_count_is_recorded(tmp_path):
+    class StageCtx(FakeCtx):
+        def rkc_step(self, t, dt, s, x, rtol, maxit=1000):
+            st = super().rkc_step(t, dt, s, x, rtol, maxit)
+            st["stage_iters"] = [6 + (k % 4) for k in range(s)]
+            st["total_iters"] = sum(st["stage_iters"])
+            return st
+
+    path = tmp_path / "steps.jsonl"
+    with StepLog(path, run="c0") as log:
+        log.step(StageCtx(), 0, 0.0, 1e-4, 8, None, 1e-10)
+        log.step(FakeCtx(), 1, 1e-4, 1e-4, 8, None, 1e-10)  # stats without per-stage counts
+    with_counts, without = [json.loads(l) for l in path.read_text().splitlines()]
+    assert with_counts["stage_iters"] == [6, 7, 8, 9, 6, 7, 8, 9]
+    assert with_counts["cg_iters"] == sum(with_counts["stage_iters"])
+    assert "stage_iters" not in without
