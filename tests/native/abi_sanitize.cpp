@@ -314,6 +314,36 @@ void run_host() {
             CHECK((k < c->inst_row_off[1]) == (u < A8.n_nodes));
             if (k > 0) CHECK(u > c->int_to_user[k - 1]);
         }
+        // the hierarchy of the block-diagonal M keeps the instances apart: every
+        // prolongator column and every coarse row belongs to one instance
+        {
+            const Csr<double> A = assemble_M_free(c);
+            eqs_amg_params p{};
+            p.coarse_max = 32;
+            p.max_levels = 12;
+            p.theta = 0.02;
+            p.jacobi_weight = 1.5;
+            p.smooth_weight = 4.0 / 3.0;
+            const AmgHost h = build_sa_amg(A, p);
+            CHECK(h.A.size() >= 3);
+            std::vector<int> inst(A.n_rows);
+            for (int32_t i = 0; i < A.n_rows; ++i) inst[i] = i < c->inst_row_off[1] ? 0 : 1;
+            for (size_t l = 0; l + 1 < h.A.size(); ++l) {
+                const Csr<double>& P = h.P[l];
+                std::vector<int> next(P.n_cols, -1);
+                for (int32_t i = 0; i < P.n_rows; ++i)
+                    for (int32_t k = P.ptr[i]; k < P.ptr[i + 1]; ++k) {
+                        int& v = next[P.col[k]];
+                        CHECK(v < 0 || v == inst[i]);
+                        v = inst[i];
+                    }
+                for (int v : next) CHECK(v >= 0);
+                const Csr<double>& Ac = h.A[l + 1];
+                for (int32_t i = 0; i < Ac.n_rows; ++i)
+                    for (int32_t k = Ac.ptr[i]; k < Ac.ptr[i + 1]; ++k) CHECK(next[Ac.col[k]] == next[i]);
+                inst = next;
+            }
+        }
         // the last tet of the first instance moved into the second one
         fill(c, B, A8.n_nodes, A8.n_tets - 1);
         CHECK(code_of(c) == EQS_ERR_INVALID_ARG);
