@@ -8,11 +8,14 @@
 //   abi   every C ABI entry point end to end on device 0: first- and second-
 //         order meshes, both precisions, stepping with every start-vector kind
 //         (Sec. IV), adaptive stepping, checkpoints, workspaces, instances,
-//         batches, the network, timing, and the error paths.
+//         batches, the network, timing, and the error paths; the host arrays of
+//         the set-up calls are freed as soon as each call returns (the library
+//         keeps copies, never the caller's pointers).
 // Prints "SANITIZE OK <mode>" and exits 0 when every check held; a check that
 // fails exits 1, and a sanitizer finding aborts the process.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -144,12 +147,35 @@ Inputs slab_inputs(const Mesh& M, double amp) {
     return in;
 }
 
+// A heap copy of a host array, released as soon as the call that reads it
+// returns: the library copies host arrays, so a pointer it kept would be a
+// use after free that AddressSanitizer reports.
+template <typename T>
+struct Transient {
+    T* p;
+    explicit Transient(const std::vector<T>& v) : p(new T[std::max<size_t>(v.size(), 1)]) {
+        std::copy(v.begin(), v.end(), p);
+    }
+    ~Transient() { delete[] p; }
+    Transient(const Transient&) = delete;
+    Transient& operator=(const Transient&) = delete;
+};
+
 void set_inputs(eqs_ctx* c, const Mesh& M, const Inputs& in) {
-    OK(M.npe == 4 ? eqs_set_mesh(c, M.n_nodes, M.xyz.data(), M.n_tets, M.tets.data())
-                  : eqs_set_mesh_p2(c, M.n_nodes, M.xyz.data(), M.n_tets, M.tets.data()));
-    OK(eqs_set_materials(c, (int32_t)in.mats.size(), in.mats.data(), in.tet_mat.data()));
-    OK(eqs_set_dirichlet(c, (int64_t)in.dir_nodes.size(), in.dir_nodes.data(), in.dir_drive.data(),
-                         (int32_t)in.drives.size(), in.drives.data()));
+    {
+        Transient<double> xyz(M.xyz);
+        Transient<int32_t> tets(M.tets);
+        OK(M.npe == 4 ? eqs_set_mesh(c, M.n_nodes, xyz.p, M.n_tets, tets.p)
+                      : eqs_set_mesh_p2(c, M.n_nodes, xyz.p, M.n_tets, tets.p));
+    }
+    {
+        Transient<eqs_material> mats(in.mats);
+        Transient<int32_t> tet_mat(in.tet_mat);
+        OK(eqs_set_materials(c, (int32_t)in.mats.size(), mats.p, tet_mat.p));
+    }
+    Transient<int32_t> nodes(in.dir_nodes), drive(in.dir_drive);
+    Transient<eqs_drive> drives(in.drives);
+    OK(eqs_set_dirichlet(c, (int64_t)in.dir_nodes.size(), nodes.p, drive.p, (int32_t)in.drives.size(), drives.p));
 }
 
 // A fixed pseudo-random sequence (SplitMix64) for test vectors and weights.
@@ -547,8 +573,12 @@ void run_abi() {
     gp.capacity = 64;
     gp.batch = 32;
     gp.seed = 11;
-    gp.init = init.data();
-    OK(eqs_set_guess(c, &gp));
+    {
+        Transient<float> w(init);  // the initial weights are copied by the call
+        gp.init = w.p;
+        OK(eqs_set_guess(c, &gp));
+    }
+    gp.init = nullptr;
     steps(c, x, 3, 7 * tau, tau, s, rtol);
     OK(eqs_state_size(c, &bytes));
     ckpt.assign(bytes, 0);
@@ -670,7 +700,10 @@ void run_abi() {
         OK(eqs_create(&c, 0, stream));
         OK(eqs_set_mesh(c, B.n_nodes, B.xyz.data(), B.n_tets, B.tets.data()));
         const int64_t node_off[3] = {0, M8.n_nodes, B.n_nodes}, tet_off[3] = {0, M8.n_tets, B.n_tets};
-        OK(eqs_set_instances(c, 2, node_off, tet_off));
+        {
+            Transient<int64_t> no(std::vector<int64_t>(node_off, node_off + 3)), to(std::vector<int64_t>(tet_off, tet_off + 3));
+            OK(eqs_set_instances(c, 2, no.p, to.p));
+        }
         OK(eqs_set_materials(c, (int32_t)in.mats.size(), in.mats.data(), in.tet_mat.data()));
         OK(eqs_set_dirichlet(c, (int64_t)in.dir_nodes.size(), in.dir_nodes.data(), in.dir_drive.data(),
                              (int32_t)in.drives.size(), in.drives.data()));
